@@ -1,0 +1,80 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module only draws numbers; it holds none of the factorisation's
+arithmetic.  Every generator uses numpy's PCG64 (``default_rng(seed)``) and
+draws an (m, n) array in C order before it is copied to column-major, so the
+values do not depend on the storage layout.  The same host bytes feed the
+oracle and the GPU path.
+
+Workloads (the paper's QR runs use random dense matrices; its stability
+experiments draw entries with randn):
+
+* ``uniform``      entries i.i.d. uniform(-1, 1)            (square FP64 QR)
+* ``svd_matrix``   A = U diag(s) V^T with random orthogonal U, V and s
+                   log-spaced from 1 to 1/kappa              (least squares)
+* ``batch_sizes`` / ``batch_matrices``  m ~ U{32..768}, n ~ U{16..m},
+                   entries N(0, 1)                           (batched QR)
+"""
+import numpy as np
+
+
+def uniform(seed, m, n):
+    rng = np.random.default_rng(seed)
+    return np.asfortranarray(rng.uniform(-1.0, 1.0, (m, n)))
+
+
+def normal(seed, m, n):
+    rng = np.random.default_rng(seed)
+    return np.asfortranarray(rng.standard_normal((m, n)))
+
+
+def _orthonormal_columns(rng, m, n):
+    """Orthonormal m x n basis from the QR of a Gaussian matrix (input
+    construction only), column signs fixed so that diag(R) > 0."""
+    G = rng.standard_normal((m, n))
+    Q, R = np.linalg.qr(G)
+    d = np.sign(np.diag(R))
+    d[d == 0] = 1.0
+    return Q * d[None, :]
+
+
+def svd_matrix(seed, m, n, kappa, nrhs=1, noise=1e-6):
+    """(A, b, x_true): A = U diag(s) V^T, s = logspace(0, -log10(kappa), n),
+    x_true ~ N(0,1) (n x nrhs), b = A x_true + noise * N(0,1) (m x nrhs).
+    With nrhs == 1, x_true and b are vectors."""
+    rng = np.random.default_rng(seed)
+    U = _orthonormal_columns(rng, m, n)
+    V = _orthonormal_columns(rng, n, n)
+    s = np.logspace(0.0, -np.log10(kappa), n)
+    A = np.asfortranarray((U * s[None, :]) @ V.T)
+    x = rng.standard_normal((n, nrhs))
+    b = A @ x + noise * rng.standard_normal((m, nrhs))
+    if nrhs == 1:
+        return A, np.ascontiguousarray(b[:, 0]), np.ascontiguousarray(x[:, 0])
+    return A, np.asfortranarray(b), np.asfortranarray(x)
+
+
+def batch_sizes(seed, count=4000, m_lo=32, m_hi=768, n_lo=16):
+    """Sizes of the batched workload: m ~ U{m_lo..m_hi}, then n_i ~ U{n_lo..m_i}."""
+    rng = np.random.default_rng(seed)
+    m = rng.integers(m_lo, m_hi + 1, size=count)
+    n = np.array([rng.integers(n_lo, mi + 1) for mi in m])
+    return m.astype(np.int64), n.astype(np.int64), rng
+
+
+def batch_matrices(seed, count=4000, m_lo=32, m_hi=768, n_lo=16):
+    """List of column-major N(0,1) matrices with the sizes of ``batch_sizes``,
+    drawn in order from the same generator."""
+    m, n, rng = batch_sizes(seed, count, m_lo, m_hi, n_lo)
+    mats = [np.asfortranarray(rng.standard_normal((int(mi), int(ni)))) for mi, ni in zip(m, n)]
+    return m, n, mats
+
+
+def qr_flops(m, n):
+    """LAPACK operation count of a Householder QR, 2 m n^2 - 2 n^3 / 3 (m >= n);
+    for m < n the count of the m x m leading part plus the update of the rest."""
+    m = float(m)
+    n = float(n)
+    if m >= n:
+        return 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
+    return 2.0 * n * m * m - 2.0 * m ** 3 / 3.0
