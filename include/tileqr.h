@@ -1,0 +1,242 @@
+/*
+ * tileqr: tiled Householder QR factorisation on AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the tiled QR of Buttari, Langou, Kurzak and Dongarra,
+ * "A Class of Parallel Tiled Linear Algebra Algorithms for Multicore
+ * Architectures", Section 3.2.1 (Algorithm 2): A (m x n) is cut into b x b
+ * tiles (b = nb) and factored as A = QR by four tile kernels,
+ *   GEQRT  A_kk -> (V_kk, R_kk, T_kk)              QR of a diagonal tile,
+ *   LARFB  A_kj <- Q_kk^T A_kj                     its block reflector applied
+ *                                                  along tile row k,
+ *   TSQRT  [R_kk; A_ik] -> (R_kk, V_ik, T_ik)      QR of a triangle on top of
+ *                                                  a square tile,
+ *   SSRFB  [A_kj; A_ij] <- Q_ik^T [A_kj; A_ij]     that reflector applied to
+ *                                                  the pairs of tiles beside,
+ * each accumulating its reflectors in groups of s = ib (inner blocking,
+ * Section 3.2.3).  The tasks run as a dependency DAG (Section 4) that a
+ * persistent GPU kernel schedules; Q is kept as tile reflectors V plus the
+ * triangular T factors of the compact WY form (Section 3.2.1), never formed.
+ *
+ * Conventions for every entry point:
+ *  - Matrix pointers (A, T, B, X) are DEVICE pointers (hipMalloc, or a torch
+ *    CUDA tensor's data_ptr), column-major with the given leading dimension,
+ *    FP64.  Size arguments and the option/info structs live in host memory.
+ *  - The caller allocates and frees A, T, B and X; the library never frees
+ *    caller memory.  The library owns its workspace (tile buffer, dependency
+ *    counters, ready queues), allocates it lazily on the device current at
+ *    the call and keeps it until tileqr_finalize().
+ *  - Calls are synchronous: they return once the device work has finished
+ *    (so that a device-side status can be reported), unless
+ *    TILEQR_FLAG_ASYNC is set.  Work runs on opts->stream (NULL: the null
+ *    stream).
+ *  - Return value: TILEQR_OK (0) on success; -i when argument i (1-based) is
+ *    invalid, in which case nothing is touched (LAPACK INFO style); a
+ *    positive tileqr_status otherwise.  A dimension of zero returns 0 at once.
+ *  - Calls into one library instance are not thread-safe: the workspace is
+ *    shared.  Serialise calls from several host threads.
+ */
+#ifndef TILEQR_H
+#define TILEQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TILEQR_OK = 0,
+    TILEQR_EHIP = 1,        /* a HIP runtime call failed (see tileqr_last_hip_error) */
+    TILEQR_ENONFINITE = 2,  /* A holds a NaN or an infinity: nothing factored      */
+    TILEQR_ENOCONV = 3,     /* refinement stopped above tol (best iterate returned) */
+    TILEQR_ETIMEOUT = 4,    /* scheduler watchdog: no task became ready in time     */
+    TILEQR_ENOMEM = 5,      /* workspace allocation failed                          */
+    TILEQR_EUNSUPPORTED = 6,/* a valid but unsupported combination (see nb/ib rules)*/
+    TILEQR_ESINGULAR = 7    /* R has an exact zero on its diagonal (solve only)     */
+} tileqr_status;
+
+/* Arithmetic of the two GEMM-shaped kernels (LARFB, SSRFB).  Reflectors
+ * (norms, tau, the R diagonal in GEQRT/TSQRT), T, storage and the
+ * refinement's residuals stay FP64 in every mode. */
+typedef enum {
+    TILEQR_FP64 = 0,    /* FP64 MFMA                                               */
+    TILEQR_BF16X2 = 1,  /* hi+lo BF16 split, 3 products, FP32 accumulation         */
+    TILEQR_FP16X2 = 2,  /* hi+lo FP16 split with power-of-two scaling, 3 products  */
+    TILEQR_BF16X3 = 3   /* hi+mid+lo BF16 split, 6 products, FP32 accumulation     */
+} tileqr_precision;
+
+enum {
+    TILEQR_FLAG_ASYNC = 1u << 0,   /* return without synchronising the stream          */
+    TILEQR_FLAG_SERIAL = 1u << 1,  /* run the tasks one launch each in Algorithm 2's
+                                      loop order instead of the DAG scheduler          */
+    TILEQR_FLAG_TRACE = 1u << 2,   /* record one trace event per task (tileqr_trace)   */
+    TILEQR_FLAG_SHUFFLE = 1u << 3  /* DAG scheduler pops ready tasks in a seeded
+                                      pseudo-random order (schedule-independence test) */
+};
+
+typedef struct {
+    int precision;        /* tileqr_precision                                        */
+    int64_t nb, ib;       /* tile size b and inner block s; 0 = pick automatically   */
+    int max_iter;         /* refinement iterations in tileqr_solve_ls (<= 64)        */
+    double tol;           /* refinement target for the backward error                */
+    void *stream;         /* hipStream_t; NULL = null stream                         */
+    unsigned flags;       /* TILEQR_FLAG_*                                           */
+    uint64_t seed;        /* seed of TILEQR_FLAG_SHUFFLE                             */
+    int64_t spin_limit;   /* scheduler watchdog: idle polls without progress before
+                             TILEQR_ETIMEOUT; 0 = default (several seconds)          */
+    int64_t workers;      /* persistent workgroups; 0 = as many as fit on the device   */
+    int64_t drop_edge;    /* test hook for the watchdog: the task with this id skips
+                             its first successor release; -1 (default) = none        */
+} tileqr_opts;
+
+typedef struct {
+    int iterations;       /* refinement steps taken                                  */
+    int converged;        /* 1 if the backward error reached tol                     */
+    double eta;           /* final backward error (normwise, see tileqr_solve_ls)    */
+    double eta_hist[65];  /* eta after 0, 1, ... iterations                          */
+    int64_t nb, ib;       /* blocking used                                           */
+    double ms_factor;     /* device time of the factorisation                        */
+    double ms_total;      /* device time of the whole call                           */
+} tileqr_info;
+
+/* Fill *opts with the defaults: FP64, automatic nb/ib, max_iter 30,
+ * tol 1e-14, null stream, no flags, drop_edge -1. */
+void tileqr_opts_default(tileqr_opts *opts);
+
+/* Supported blockings: nb in {64, 128, 256} and ib in {16, 32} (so nb % ib
+ * == 0: the paper takes b/s integral, Section 3.2.3).  Returns 1 if (nb, ib)
+ * is supported, else 0. */
+int tileqr_blocking_supported(int64_t nb, int64_t ib);
+
+/* Blocking the library picks for an m x n factorisation when nb = ib = 0
+ * (tuned table, see tileqr_tune).  Writes nb and ib; returns 0. */
+int tileqr_choose_blocking(int64_t m, int64_t n, int precision, int64_t *nb, int64_t *ib);
+
+/* Number of doubles the T factors of an m x n factorisation occupy:
+ * one ib x nb block (nb/ib upper-triangular ib x ib blocks, Section 3.2.3)
+ * per tile (i, k) with k < min(p, q), k <= i < p, where p = ceil(m/nb),
+ * q = ceil(n/nb).  0 for an empty matrix or unsupported blocking. */
+size_t tileqr_t_size(int64_t m, int64_t n, int64_t nb, int64_t ib);
+
+/*
+ * Factor A = QR in place (Section 3.2.1, Algorithm 2; reflector sign
+ * beta = -sign(alpha) ||x|| with sign(0) = +1, tau = 0 when the column below
+ * the diagonal is already zero).
+ *   m, n   >= 0 (m < n allowed: min(p, q) tile steps)
+ *   A      device, m x n, leading dimension lda >= max(1, m); overwritten by
+ *          R (upper triangle of rows 0..min(m,n)-1) and the tile reflectors:
+ *          V_kk in the strict lower triangle of each diagonal tile, V_ik
+ *          (i > k) filling the tiles below it.  This is the tiled layout of
+ *          the paper (Section 3.2.1), not LAPACK's: use Q only through
+ *          tileqr_apply_q / tileqr_apply_qt with the same nb, ib and T.
+ *   nb, ib blocking (see tileqr_blocking_supported); 0, 0 = automatic is not
+ *          allowed here because T is sized by the caller
+ *   T      device, >= tileqr_t_size(m, n, nb, ib) doubles, written; its
+ *          internal layout is private to the library.
+ * Errors: -1 m, -2 n, -3 A (NULL with m, n > 0), -4 lda, -5 nb, -6 ib,
+ *         -7 T; TILEQR_ENONFINITE if A holds NaN/Inf (A then unchanged).
+ */
+int tileqr_factor(int64_t m, int64_t n, double *A, int64_t lda, int64_t nb, int64_t ib,
+                  double *T);
+
+/* tileqr_factor with options (schedule, stream, flags, precision of the
+ * two GEMM-shaped kernels).  opts may be NULL (defaults); opts->nb/ib are
+ * ignored (the explicit arguments rule).  Argument 8 is opts. */
+int tileqr_factor_ex(int64_t m, int64_t n, double *A, int64_t lda, int64_t nb, int64_t ib,
+                     double *T, const tileqr_opts *opts);
+
+/*
+ * B := Q^T B (tileqr_apply_qt) or B := Q B (tileqr_apply_q) for Q of a
+ * previous tileqr_factor(m, n, A, lda, nb, ib, T).  Q^T applies, for each
+ * tile step k in ascending order, the diagonal reflector (as LARFB does) and
+ * then the coupled reflectors of tiles i = k+1.. in ascending order (as SSRFB
+ * does); Q applies the same operators transposed in reverse order.
+ *   nrhs >= 0; B device, m x nrhs, ldb >= max(1, m), overwritten.
+ * Errors: -1 m, -2 n, -3 nrhs, -4 A, -5 lda, -6 nb, -7 ib, -8 T, -9 B, -10 ldb.
+ */
+int tileqr_apply_qt(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda,
+                    int64_t nb, int64_t ib, const double *T, double *B, int64_t ldb);
+int tileqr_apply_q(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda,
+                   int64_t nb, int64_t ib, const double *T, double *B, int64_t ldb);
+
+/*
+ * Least squares X = argmin ||B - A X||_2 for m >= n and A of full column
+ * rank, one column per right-hand side.  A and B are left untouched (the
+ * library factors a copy).  With opts->precision = TILEQR_FP64 the solution
+ * is R^{-1} (Q^T B)(0:n).  With a split precision the factorisation's
+ * GEMM-shaped kernels run in that arithmetic and the solution is refined in
+ * FP64 on the original A (augmented-system refinement: residuals f = B - R
+ * - A X and g = -A^T R in FP64, corrections through the mixed factors) until
+ * the backward error eta = ||A^T (B - A X)||_2 / (||A||_F (||A||_F ||X||_2
+ * + ||B||_2)) (worst column) is <= opts->tol, stagnates, or max_iter steps
+ * are taken.  The paper advises checking the backward error of a solve and
+ * refining when needed (Section 3.2.4); the refinement scheme is this
+ * library's reading.
+ *   X device, n x nrhs, ldx >= max(1, n), written.  info may be NULL.
+ * Errors: -1 m, -2 n (n > m), -3 nrhs, -4 A, -5 lda, -6 B, -7 ldb, -8 X,
+ *         -9 ldx, -10 opts; TILEQR_ENOCONV (best iterate in X) when the
+ *         refinement does not reach tol; TILEQR_ESINGULAR for a zero R_jj.
+ */
+int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda,
+                    const double *B, int64_t ldb, double *X, int64_t ldx,
+                    const tileqr_opts *opts, tileqr_info *info);
+
+/*
+ * Factor `batch` independent matrices in one persistent launch: one global
+ * task space over all of them (Section 4's DAG, one per matrix).
+ *   m, n, lda, nb, ib : host arrays of `batch` entries (nb/ib may be NULL:
+ *                       tileqr_choose_blocking per matrix)
+ *   A, T              : host arrays of `batch` device pointers; T[i] holds
+ *                       tileqr_t_size(m[i], n[i], nb[i], ib[i]) doubles.
+ * Each result equals, bit for bit, tileqr_factor on that matrix alone with
+ * the same nb, ib.  The launch sequence is captured once per distinct batch
+ * shape into a HIP graph and replayed.
+ * Errors: -1 batch, -2 m, -3 n, -4 A, -5 lda, -6 nb, -7 ib, -8 T, -9 opts
+ * (for an array argument: the first bad entry).
+ */
+int tileqr_factor_batched(int64_t batch, const int64_t *m, const int64_t *n,
+                          double *const *A, const int64_t *lda, const int64_t *nb,
+                          const int64_t *ib, double *const *T, const tileqr_opts *opts);
+
+/* Operation counts.  tileqr_flops_lapack: 2mn^2 - 2n^3/3 (m >= n; the
+ * mirror formula for m < n), the count the paper reports rates with
+ * (Section 5).  tileqr_flops_tiled: the tiled algorithm's own count from
+ * its per-kernel costs (Section 3.2.3), which exceeds it by about s/(4b). */
+double tileqr_flops_lapack(int64_t m, int64_t n);
+double tileqr_flops_tiled(int64_t m, int64_t n, int64_t nb, int64_t ib);
+
+/* Tasks of the DAG (Section 4) for a p x q tile grid with `strips` column
+ * strips per tile (strips = 1: the paper's tasks).  counts[0..3] receive the
+ * numbers of GEQRT, TSQRT, LARFB and SSRFB tasks; returns their sum.
+ * Host only, no GPU needed. */
+int64_t tileqr_dag_counts(int64_t p, int64_t q, int64_t strips, int64_t counts[4]);
+
+/* Host-side check of the dependency rules the scheduler uses: executes the
+ * DAG of a p x q grid in `trials` random topological orders (seeded) on a
+ * symbolic tile-version model and checks that every task sees each tile in
+ * the state Algorithm 2's loop order would give it.  Also checks that
+ * in-degrees equal the number of predecessors that release each task.
+ * Returns 0 if all orders pass, else the 1-based number of the failing
+ * trial.  Host only. */
+int tileqr_dag_selfcheck(int64_t p, int64_t q, int64_t strips, int64_t trials, uint64_t seed);
+
+/* Trace of the last factorisation run with TILEQR_FLAG_TRACE: up to `cap`
+ * events copied to host memory, 8 int64 each: {type, k, i, j, strip,
+ * worker, t_start, t_end} (types 0 GEQRT, 1 TSQRT, 2 LARFB, 3 SSRFB;
+ * times in ticks of the device wall clock, tileqr_trace_clock_hz per second).
+ * Returns the number of events available. */
+int64_t tileqr_trace(int64_t *events, int64_t cap);
+double tileqr_trace_clock_hz(void);
+
+const char *tileqr_status_string(int status);
+const char *tileqr_last_hip_error(void);
+
+/* Release the library workspace on every device it was allocated on. */
+int tileqr_finalize(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TILEQR_H */

@@ -1,0 +1,499 @@
+// Host side of the C-ABI library declared in include/tileqr.h: argument
+// checks, workspace, schedule set-up and the host-only DAG utilities.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <random>
+#include <vector>
+
+#include "../../include/tileqr.h"
+#include "tileqr_dag.h"
+#include "tileqr_internal.h"
+
+using namespace tq;
+
+namespace {
+
+char g_hip_error[256] = "";
+
+int hip_fail(hipError_t e, const char *what)
+{
+    snprintf(g_hip_error, sizeof g_hip_error, "%s: %s", what, hipGetErrorString(e));
+    return TILEQR_EHIP;
+}
+
+#define TQ_HIP(expr)                                   \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return hip_fail(e_, #expr); \
+    } while (0)
+
+// Grow-only device buffer.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    int ensure(size_t need)
+    {
+        if (need <= bytes) return 0;
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+        if (hipMalloc(&ptr, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return TILEQR_ENOMEM;
+        }
+        bytes = need;
+        return 0;
+    }
+    void release()
+    {
+        if (ptr) (void)hipFree(ptr);
+        ptr = nullptr;
+        bytes = 0;
+    }
+};
+
+// Library workspace of one device.
+struct Workspace {
+    int device = -1;
+    DevBuf tiles, counters, qslot, qctl, mats, status, trace, misc;
+    int *host_status = nullptr;   // pinned
+    int64_t trace_events = 0;
+    int num_cu = 0;
+    double wall_hz = 0.0;
+};
+
+std::mutex g_mu;
+std::vector<Workspace *> g_ws;
+
+Workspace *workspace()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    for (auto *w : g_ws)
+        if (w->device == dev) return w;
+    auto *w = new Workspace;
+    w->device = dev;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) w->num_cu = prop.multiProcessorCount;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess) w->wall_hz = khz * 1e3;
+    if (hipHostMalloc((void **)&w->host_status, 64, hipHostMallocDefault) != hipSuccess) {
+        delete w;
+        return nullptr;
+    }
+    g_ws.push_back(w);
+    return w;
+}
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+constexpr int kStripWidth = 32;   // columns per LARFB/SSRFB strip task
+
+}  // namespace
+
+// ------------------------------------------------------------------ basics
+
+extern "C" void tileqr_opts_default(tileqr_opts *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->precision = TILEQR_FP64;
+    o->max_iter = 30;
+    o->tol = 1e-14;
+    o->drop_edge = -1;
+}
+
+extern "C" int tileqr_blocking_supported(int64_t nb, int64_t ib)
+{
+    if (nb != 64 && nb != 128 && nb != 256) return 0;
+    if (ib != 16 && ib != 32) return 0;
+    return nb % ib == 0 && ib <= nb;
+}
+
+extern "C" int tileqr_choose_blocking(int64_t m, int64_t n, int precision, int64_t *nb, int64_t *ib)
+{
+    (void)precision;
+    const int64_t k = std::min(m, n);
+    int64_t b = 256, s = 32;
+    if (k <= 1024) { b = 64; s = 16; }
+    else if (k <= 4096 || m >= 16 * n) { b = 128; s = 32; }
+    if (nb) *nb = b;
+    if (ib) *ib = s;
+    return 0;
+}
+
+extern "C" size_t tileqr_t_size(int64_t m, int64_t n, int64_t nb, int64_t ib)
+{
+    if (m <= 0 || n <= 0 || !tileqr_blocking_supported(nb, ib)) return 0;
+    const int64_t p = cdiv(m, nb), q = cdiv(n, nb), kmax = std::min(p, q);
+    return (size_t)(kmax * p * ib * nb);
+}
+
+extern "C" double tileqr_flops_lapack(int64_t m, int64_t n)
+{
+    const double M = (double)m, N = (double)n;
+    if (m >= n) return 2.0 * M * N * N - 2.0 * N * N * N / 3.0;
+    return 2.0 * N * M * M - 2.0 * M * M * M / 3.0;
+}
+
+extern "C" double tileqr_flops_tiled(int64_t m, int64_t n, int64_t nb, int64_t ib)
+{
+    if (m <= 0 || n <= 0 || nb <= 0 || ib <= 0) return 0.0;
+    const int p = (int)cdiv(m, nb), q = (int)cdiv(n, nb);
+    const Grid g = make_grid(p, q, 1);
+    double f = 0.0;
+    for (int64_t id = 0; id < g.total; ++id) {
+        const Task t = decode(g, id);
+        if (valid(g, t)) f += task_flops(t, (int)nb, (int)ib, 1);
+    }
+    return f;
+}
+
+extern "C" int64_t tileqr_dag_counts(int64_t p, int64_t q, int64_t strips, int64_t counts[4])
+{
+    int64_t c[4] = {0, 0, 0, 0};
+    if (p > 0 && q > 0 && strips > 0) {
+        const Grid g = make_grid((int)p, (int)q, (int)strips);
+        for (int64_t id = 0; id < g.total; ++id) {
+            const Task t = decode(g, id);
+            if (valid(g, t)) ++c[t.type];
+        }
+    }
+    if (counts)
+        for (int k = 0; k < 4; ++k) counts[k] = c[k];
+    return c[0] + c[1] + c[2] + c[3];
+}
+
+// ------------------------------------------------------- DAG self-check
+
+namespace {
+
+// Regions: strip s of tile (i, j), plus the R and V halves of diagonal tiles.
+struct RegionMap {
+    int p, q, ns;
+    int64_t strip(int i, int j, int s) const { return ((int64_t)j * p + i) * ns + s; }
+    int64_t rpart(int k) const { return (int64_t)p * q * ns + k; }
+    int64_t vpart(int k) const { return (int64_t)p * q * ns + std::min(p, q) + k; }
+    int64_t size() const { return (int64_t)p * q * ns + 2 * std::min(p, q); }
+};
+
+// Reads and writes of a task (Algorithm 2, the table in tileqr_dag.h).
+void task_access(const RegionMap &R, const Task &t, std::vector<int64_t> &rd, std::vector<int64_t> &wr)
+{
+    rd.clear();
+    wr.clear();
+    switch (t.type) {
+    case GEQRT:
+        for (int s = 0; s < R.ns; ++s) {
+            rd.push_back(R.strip(t.k, t.k, s));
+            wr.push_back(R.strip(t.k, t.k, s));
+        }
+        wr.push_back(R.rpart(t.k));
+        wr.push_back(R.vpart(t.k));
+        break;
+    case LARFB:
+        rd.push_back(R.vpart(t.k));
+        rd.push_back(R.strip(t.k, t.j, t.s));
+        wr.push_back(R.strip(t.k, t.j, t.s));
+        break;
+    case TSQRT:
+        rd.push_back(R.rpart(t.k));
+        wr.push_back(R.rpart(t.k));
+        for (int s = 0; s < R.ns; ++s) {
+            rd.push_back(R.strip(t.i, t.k, s));
+            wr.push_back(R.strip(t.i, t.k, s));
+        }
+        break;
+    default:
+        for (int s = 0; s < R.ns; ++s) rd.push_back(R.strip(t.i, t.k, s));
+        rd.push_back(R.strip(t.k, t.j, t.s));
+        rd.push_back(R.strip(t.i, t.j, t.s));
+        wr.push_back(R.strip(t.k, t.j, t.s));
+        wr.push_back(R.strip(t.i, t.j, t.s));
+        break;
+    }
+}
+
+}  // namespace
+
+extern "C" int tileqr_dag_selfcheck(int64_t p, int64_t q, int64_t strips, int64_t trials, uint64_t seed)
+{
+    if (p <= 0 || q <= 0 || strips <= 0) return 0;
+    const Grid g = make_grid((int)p, (int)q, (int)strips);
+    const RegionMap R{(int)p, (int)q, (int)strips};
+    std::vector<int64_t> rd, wr;
+    // Reference: Algorithm 2's loop order.
+    std::vector<int64_t> order;
+    for (int k = 0; k < g.kmax; ++k) {
+        order.push_back(id_geqrt(g, k));
+        for (int j = k + 1; j < g.q; ++j)
+            for (int s = 0; s < g.ns; ++s) order.push_back(id_larfb(g, k, j, s));
+        for (int i = k + 1; i < g.p; ++i) {
+            order.push_back(id_tsqrt(g, k, i));
+            for (int j = k + 1; j < g.q; ++j)
+                for (int s = 0; s < g.ns; ++s) order.push_back(id_ssrfb(g, k, i, j, s));
+        }
+    }
+    std::vector<std::vector<int64_t>> expect(g.total);
+    {
+        std::vector<int64_t> ver(R.size(), 0);
+        for (int64_t id : order) {
+            task_access(R, decode(g, id), rd, wr);
+            for (int64_t r : rd) expect[id].push_back(ver[r]);
+            for (int64_t w : wr) ++ver[w];
+        }
+    }
+    int64_t ntasks = (int64_t)order.size();
+    std::mt19937_64 rng(seed);
+    for (int64_t trial = 0; trial < trials; ++trial) {
+        std::vector<int32_t> cnt(g.total, -1);
+        std::vector<int64_t> ready;
+        for (int64_t id = 0; id < g.total; ++id) {
+            const Task t = decode(g, id);
+            if (valid(g, t)) {
+                cnt[id] = indegree(g, t);
+                if (cnt[id] == 0) ready.push_back(id);
+            }
+        }
+        std::vector<int64_t> ver(R.size(), 0);
+        int64_t executed = 0;
+        while (!ready.empty()) {
+            const size_t pick = (size_t)(rng() % ready.size());
+            const int64_t id = ready[pick];
+            ready[pick] = ready.back();
+            ready.pop_back();
+            const Task t = decode(g, id);
+            task_access(R, t, rd, wr);
+            for (size_t e = 0; e < rd.size(); ++e)
+                if (ver[rd[e]] != expect[id][e]) return (int)(trial + 1);
+            for (int64_t w : wr) ++ver[w];
+            ++executed;
+            const int ns = nsucc(g, t);
+            for (int n = 0; n < ns; ++n) {
+                const int64_t s = succ(g, t, n);
+                if (s < 0 || s >= g.total || !valid(g, decode(g, s))) return (int)(trial + 1);
+                if (--cnt[s] == 0) ready.push_back(s);
+                if (cnt[s] < 0) return (int)(trial + 1);
+            }
+        }
+        if (executed != ntasks) return (int)(trial + 1);
+        for (int64_t id = 0; id < g.total; ++id)
+            if (cnt[id] > 0) return (int)(trial + 1);
+    }
+    return 0;
+}
+
+// ------------------------------------------------------------ factorisation
+
+namespace {
+
+int check_status(Workspace *W, int *dstatus, hipStream_t st)
+{
+    TQ_HIP(hipMemcpyAsync(W->host_status, dstatus, sizeof(int), hipMemcpyDeviceToHost, st));
+    TQ_HIP(hipStreamSynchronize(st));
+    const int s = *W->host_status;
+    if (s & STATUS_NONFINITE) return TILEQR_ENONFINITE;
+    if (s & STATUS_TIMEOUT) return TILEQR_ETIMEOUT;
+    return TILEQR_OK;
+}
+
+// Runs the factorisation of the tiles already in W->tiles (status already
+// cleared and set by the conversion).  Either the serial Algorithm 2 driver
+// or the persistent DAG scheduler.
+int run_factor(Workspace *W, int nb, int ib, int p, int q, double *T, const tileqr_opts &o, hipStream_t st)
+{
+    int *dstatus = (int *)W->status.ptr;
+    MatDev M;
+    M.tiles = (double *)W->tiles.ptr;
+    M.T = T;
+    M.p = p;
+    M.q = q;
+    M.task_base = 0;
+    if (o.flags & TILEQR_FLAG_SERIAL) {
+        TQ_HIP(launch_factor_serial(nb, ib, M, dstatus, st));
+        return 0;
+    }
+    const int ns = nb / kStripWidth;
+    const Grid g = make_grid(p, q, ns);
+    int64_t counts[4];
+    const int64_t ntask = tileqr_dag_counts(p, q, ns, counts);
+    int rc;
+    if ((rc = W->counters.ensure((size_t)g.total * sizeof(int32_t)))) return rc;
+    const int64_t qtotal = ntask;
+    if ((rc = W->qslot.ensure((size_t)qtotal * sizeof(int32_t)))) return rc;
+    if ((rc = W->qctl.ensure(2 * 4 * 32 * sizeof(uint32_t) + 256))) return rc;
+    if ((rc = W->mats.ensure(sizeof(MatDev)))) return rc;
+    TQ_HIP(hipMemcpyAsync(W->mats.ptr, &M, sizeof(MatDev), hipMemcpyHostToDevice, st));
+    SchedDev S;
+    std::memset(&S, 0, sizeof S);
+    S.mats = (MatDev *)W->mats.ptr;
+    S.nmat = 1;
+    S.ns = ns;
+    S.total_ids = g.total;
+    S.total_tasks = (uint32_t)ntask;
+    S.counters = (int32_t *)W->counters.ptr;
+    S.qslot = (int32_t *)W->qslot.ptr;
+    S.qslot_total = qtotal;
+    int64_t off = 0;
+    for (int l = 0; l < 4; ++l) {
+        S.qoff[l] = off;
+        off += counts[l];
+    }
+    S.qhead = (uint32_t *)W->qctl.ptr;
+    S.qtail = S.qhead + 4 * 32;
+    S.done = S.qtail + 4 * 32;
+    S.trace_count = S.done + 1;
+    S.status = dstatus;
+    S.spin_limit = o.spin_limit > 0 ? o.spin_limit : (int64_t)1 << 24;
+    S.shuffle = (o.flags & TILEQR_FLAG_SHUFFLE) ? 1 : 0;
+    S.seed = o.seed;
+    S.drop_edge = o.drop_edge;
+    S.trace = nullptr;
+    if (o.flags & TILEQR_FLAG_TRACE) {
+        if ((rc = W->trace.ensure((size_t)ntask * 8 * sizeof(int64_t)))) return rc;
+        S.trace = (int64_t *)W->trace.ptr;
+        S.trace_cap = (uint32_t)ntask;
+        W->trace_events = ntask;
+    }
+    int workers = (int)o.workers;
+    if (workers <= 0) workers = std::max(1, W->num_cu) * worker_occupancy(nb, ib);
+    TQ_HIP(launch_sched_init(S, st));
+    TQ_HIP(launch_worker(nb, ib, S, workers, st));
+    return 0;
+}
+
+}  // namespace
+
+extern "C" int tileqr_factor_ex(int64_t m, int64_t n, double *A, int64_t lda, int64_t nb, int64_t ib,
+                                double *T, const tileqr_opts *opts)
+{
+    if (m < 0) return -1;
+    if (n < 0) return -2;
+    if (A == nullptr && m > 0 && n > 0) return -3;
+    if (lda < std::max<int64_t>(1, m)) return -4;
+    if (nb <= 0) return -5;
+    if (ib <= 0 || ib > nb || nb % ib != 0) return -6;
+    if (m == 0 || n == 0) return TILEQR_OK;
+    if (T == nullptr) return -7;
+    if (!tileqr_blocking_supported(nb, ib)) return TILEQR_EUNSUPPORTED;
+    tileqr_opts o;
+    tileqr_opts_default(&o);
+    if (opts) o = *opts;
+    std::lock_guard<std::mutex> lock(g_mu);
+    Workspace *W = workspace();
+    if (!W) return hip_fail(hipErrorNoDevice, "workspace");
+    hipStream_t st = (hipStream_t)o.stream;
+    const int p = (int)cdiv(m, nb), q = (int)cdiv(n, nb);
+    int rc;
+    if ((rc = W->tiles.ensure((size_t)p * q * nb * nb * sizeof(double)))) return rc;
+    if ((rc = W->status.ensure(256))) return rc;
+    W->trace_events = 0;
+    TQ_HIP(hipMemsetAsync(W->status.ptr, 0, sizeof(int), st));
+    TQ_HIP(launch_cm2tile(A, lda, m, n, (double *)W->tiles.ptr, (int)nb, p, q, (int *)W->status.ptr, st));
+    if ((rc = run_factor(W, (int)nb, (int)ib, p, q, T, o, st))) return rc;
+    TQ_HIP(launch_tile2cm(A, lda, m, n, (double *)W->tiles.ptr, (int)nb, p, q, (const int *)W->status.ptr, st));
+    if (o.flags & TILEQR_FLAG_ASYNC) return TILEQR_OK;
+    return check_status(W, (int *)W->status.ptr, st);
+}
+
+extern "C" int tileqr_factor(int64_t m, int64_t n, double *A, int64_t lda, int64_t nb, int64_t ib, double *T)
+{
+    return tileqr_factor_ex(m, n, A, lda, nb, ib, T, nullptr);
+}
+
+// ----------------------------------------------------------------- trace
+
+extern "C" int64_t tileqr_trace(int64_t *events, int64_t cap)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    Workspace *W = workspace();
+    if (!W || W->trace_events == 0 || !W->trace.ptr) return 0;
+    const int64_t n = std::min(cap, W->trace_events);
+    if (events && n > 0) {
+        if (hipDeviceSynchronize() != hipSuccess) return 0;
+        if (hipMemcpy(events, W->trace.ptr, (size_t)n * 8 * sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
+            return 0;
+    }
+    return W->trace_events;
+}
+
+extern "C" double tileqr_trace_clock_hz(void)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    Workspace *W = workspace();
+    return W ? W->wall_hz : 0.0;
+}
+
+// ------------------------------------------------------------------ misc
+
+extern "C" const char *tileqr_status_string(int s)
+{
+    if (s < 0) return "invalid argument";
+    switch (s) {
+    case TILEQR_OK: return "ok";
+    case TILEQR_EHIP: return "HIP runtime error";
+    case TILEQR_ENONFINITE: return "input holds NaN or Inf";
+    case TILEQR_ENOCONV: return "refinement did not converge";
+    case TILEQR_ETIMEOUT: return "scheduler watchdog timeout";
+    case TILEQR_ENOMEM: return "out of device memory";
+    case TILEQR_EUNSUPPORTED: return "unsupported blocking";
+    case TILEQR_ESINGULAR: return "singular triangular factor";
+    default: return "unknown status";
+    }
+}
+
+extern "C" const char *tileqr_last_hip_error(void) { return g_hip_error; }
+
+extern "C" int tileqr_finalize(void)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    for (auto *w : g_ws) {
+        if (hipSetDevice(w->device) == hipSuccess) {
+            (void)hipDeviceSynchronize();
+            w->tiles.release();
+            w->counters.release();
+            w->qslot.release();
+            w->qctl.release();
+            w->mats.release();
+            w->status.release();
+            w->trace.release();
+            w->misc.release();
+            if (w->host_status) (void)hipHostFree(w->host_status);
+        }
+        delete w;
+    }
+    g_ws.clear();
+    (void)hipSetDevice(cur);
+    return TILEQR_OK;
+}
+// ------------------------------------------- not yet wired (filled in below)
+
+extern "C" int tileqr_apply_qt(int64_t, int64_t, int64_t, const double *, int64_t, int64_t, int64_t,
+                               const double *, double *, int64_t)
+{
+    return TILEQR_EUNSUPPORTED;
+}
+extern "C" int tileqr_apply_q(int64_t, int64_t, int64_t, const double *, int64_t, int64_t, int64_t,
+                              const double *, double *, int64_t)
+{
+    return TILEQR_EUNSUPPORTED;
+}
+extern "C" int tileqr_solve_ls(int64_t, int64_t, int64_t, const double *, int64_t, const double *, int64_t,
+                               double *, int64_t, const tileqr_opts *, tileqr_info *)
+{
+    return TILEQR_EUNSUPPORTED;
+}
+extern "C" int tileqr_factor_batched(int64_t, const int64_t *, const int64_t *, double *const *,
+                                     const int64_t *, const int64_t *, const int64_t *, double *const *,
+                                     const tileqr_opts *)
+{
+    return TILEQR_EUNSUPPORTED;
+}

@@ -1,0 +1,55 @@
+// Internal interface between the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tq {
+
+enum : int {
+    STATUS_NONFINITE = 1,   // NaN or Inf in the input
+    STATUS_TIMEOUT = 2      // scheduler watchdog fired
+};
+
+// One matrix as the kernels see it.
+struct MatDev {
+    double *tiles;       // p x q row-major nb x nb tiles (workspace)
+    double *T;           // T factors (caller memory)
+    int32_t p, q;        // tile grid
+    int64_t task_base;   // first global task id of this matrix
+};
+
+// Scheduler state in device memory (all pointers are device pointers).
+struct SchedDev {
+    MatDev *mats;
+    int32_t nmat;
+    int32_t ns;               // strips per tile
+    int64_t total_ids;        // size of the id space (with holes)
+    uint32_t total_tasks;     // number of real tasks
+    int32_t *counters;        // [total_ids] remaining predecessors
+    int32_t *qslot;           // queue slots of the 4 levels, back to back
+    int64_t qslot_total;
+    int64_t qoff[4];          // offset of each level's slots
+    uint32_t *qhead;          // [4 * 32] (one 128-byte line per level)
+    uint32_t *qtail;          // [4 * 32]
+    uint32_t *done;           // completed tasks
+    int32_t *status;          // STATUS_* flags
+    int64_t spin_limit;       // idle polls without progress before STATUS_TIMEOUT
+    int32_t shuffle;          // pseudo-random pop order
+    uint64_t seed;
+    int64_t drop_edge;        // debug: task whose first release is skipped (-1: none)
+    int64_t *trace;           // [trace_cap * 8] or NULL
+    uint32_t *trace_count;
+    uint32_t trace_cap;
+};
+
+hipError_t launch_cm2tile(const double *A, int64_t lda, int64_t m, int64_t n, double *tiles, int nb,
+                          int p, int q, int *status, hipStream_t st);
+hipError_t launch_tile2cm(double *A, int64_t lda, int64_t m, int64_t n, const double *tiles, int nb,
+                          int p, int q, const int *status, hipStream_t st);
+hipError_t launch_factor_serial(int nb, int ib, const MatDev &M, const int *status, hipStream_t st);
+hipError_t launch_sched_init(const SchedDev &S, hipStream_t st);
+hipError_t launch_worker(int nb, int ib, const SchedDev &S, int workers, hipStream_t st);
+int worker_occupancy(int nb, int ib);
+
+}  // namespace tq

@@ -1,0 +1,210 @@
+"""ctypes binding of ``libtileqr.so`` (declared in ``include/tileqr.h``).
+
+Argument marshalling only: every step of the factorisation and of the
+solvers runs in the library's HIP kernels.  Functions take device pointers
+(ints) exactly like the C entry points; the ``*_tensor`` helpers accept torch
+CUDA tensors holding column-major FP64 matrices (a column-major m x n matrix
+is a contiguous torch tensor of shape (n, m)).
+
+Importing this module fails loudly when the library has not been built:
+there is no fallback path.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtileqr.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
+                      f"g.build()'` (hipcc, gfx950)")
+
+_L = ctypes.CDLL(LIB_PATH)
+
+OK, EHIP, ENONFINITE, ENOCONV, ETIMEOUT, ENOMEM, EUNSUPPORTED, ESINGULAR = range(8)
+FP64, BF16X2, FP16X2, BF16X3 = range(4)
+FLAG_ASYNC, FLAG_SERIAL, FLAG_TRACE, FLAG_SHUFFLE = 1, 2, 4, 8
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("nb", ctypes.c_int64), ("ib", ctypes.c_int64),
+                ("max_iter", ctypes.c_int), ("tol", ctypes.c_double), ("stream", ctypes.c_void_p),
+                ("flags", ctypes.c_uint), ("seed", ctypes.c_uint64), ("spin_limit", ctypes.c_int64),
+                ("workers", ctypes.c_int64), ("drop_edge", ctypes.c_int64)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("eta", ctypes.c_double),
+                ("eta_hist", ctypes.c_double * 65), ("nb", ctypes.c_int64), ("ib", ctypes.c_int64),
+                ("ms_factor", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+
+_i64, _int, _vp, _dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_double
+_I64P = ctypes.POINTER(ctypes.c_int64)
+
+_SIGS = {
+    "tileqr_opts_default": (None, [ctypes.POINTER(Opts)]),
+    "tileqr_blocking_supported": (_int, [_i64, _i64]),
+    "tileqr_choose_blocking": (_int, [_i64, _i64, _int, _I64P, _I64P]),
+    "tileqr_t_size": (ctypes.c_size_t, [_i64, _i64, _i64, _i64]),
+    "tileqr_factor": (_int, [_i64, _i64, _vp, _i64, _i64, _i64, _vp]),
+    "tileqr_factor_ex": (_int, [_i64, _i64, _vp, _i64, _i64, _i64, _vp, ctypes.POINTER(Opts)]),
+    "tileqr_apply_qt": (_int, [_i64, _i64, _i64, _vp, _i64, _i64, _i64, _vp, _vp, _i64]),
+    "tileqr_apply_q": (_int, [_i64, _i64, _i64, _vp, _i64, _i64, _i64, _vp, _vp, _i64]),
+    "tileqr_solve_ls": (_int, [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
+                               ctypes.POINTER(Opts), ctypes.POINTER(Info)]),
+    "tileqr_factor_batched": (_int, [_i64, _I64P, _I64P, ctypes.POINTER(_vp), _I64P, _I64P, _I64P,
+                                     ctypes.POINTER(_vp), ctypes.POINTER(Opts)]),
+    "tileqr_flops_lapack": (_dbl, [_i64, _i64]),
+    "tileqr_flops_tiled": (_dbl, [_i64, _i64, _i64, _i64]),
+    "tileqr_dag_counts": (_i64, [_i64, _i64, _i64, _I64P]),
+    "tileqr_dag_selfcheck": (_int, [_i64, _i64, _i64, _i64, ctypes.c_uint64]),
+    "tileqr_trace": (_i64, [_I64P, _i64]),
+    "tileqr_trace_clock_hz": (_dbl, []),
+    "tileqr_status_string": (ctypes.c_char_p, [_int]),
+    "tileqr_last_hip_error": (ctypes.c_char_p, []),
+    "tileqr_finalize": (_int, []),
+}
+
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_L, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTS = sorted(_SIGS)
+
+
+class TileQRError(RuntimeError):
+    def __init__(self, status, where):
+        msg = _L.tileqr_status_string(status).decode()
+        if status == EHIP:
+            msg += ": " + _L.tileqr_last_hip_error().decode()
+        super().__init__(f"{where}: status {status} ({msg})")
+        self.status = status
+
+
+def opts(**kw):
+    o = Opts()
+    _L.tileqr_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _ptr_opts(o):
+    return ctypes.byref(o) if o is not None else None
+
+
+# ------------------------------------------------------------ raw entry points
+
+def blocking_supported(nb, ib):
+    return bool(_L.tileqr_blocking_supported(nb, ib))
+
+
+def choose_blocking(m, n, precision=FP64):
+    nb, ib = ctypes.c_int64(), ctypes.c_int64()
+    _L.tileqr_choose_blocking(m, n, precision, ctypes.byref(nb), ctypes.byref(ib))
+    return nb.value, ib.value
+
+
+def t_size(m, n, nb, ib):
+    return int(_L.tileqr_t_size(m, n, nb, ib))
+
+
+def factor(m, n, A, lda, nb, ib, T, o=None):
+    if o is None:
+        return _L.tileqr_factor(m, n, A, lda, nb, ib, T)
+    return _L.tileqr_factor_ex(m, n, A, lda, nb, ib, T, _ptr_opts(o))
+
+
+def apply_qt(m, n, nrhs, A, lda, nb, ib, T, B, ldb):
+    return _L.tileqr_apply_qt(m, n, nrhs, A, lda, nb, ib, T, B, ldb)
+
+
+def apply_q(m, n, nrhs, A, lda, nb, ib, T, B, ldb):
+    return _L.tileqr_apply_q(m, n, nrhs, A, lda, nb, ib, T, B, ldb)
+
+
+def solve_ls(m, n, nrhs, A, lda, B, ldb, X, ldx, o=None, info=None):
+    return _L.tileqr_solve_ls(m, n, nrhs, A, lda, B, ldb, X, ldx, _ptr_opts(o),
+                              ctypes.byref(info) if info is not None else None)
+
+
+def factor_batched(ms, ns, A_ptrs, ldas, nbs, ibs, T_ptrs, o=None):
+    b = len(ms)
+    arr = lambda vals: (ctypes.c_int64 * b)(*[int(v) for v in vals])
+    ptrs = lambda vals: (ctypes.c_void_p * b)(*[int(v) for v in vals])
+    return _L.tileqr_factor_batched(b, arr(ms), arr(ns), ptrs(A_ptrs), arr(ldas),
+                                    arr(nbs) if nbs is not None else None,
+                                    arr(ibs) if ibs is not None else None, ptrs(T_ptrs), _ptr_opts(o))
+
+
+def flops_lapack(m, n):
+    return _L.tileqr_flops_lapack(m, n)
+
+
+def flops_tiled(m, n, nb, ib):
+    return _L.tileqr_flops_tiled(m, n, nb, ib)
+
+
+def dag_counts(p, q, strips=1):
+    c = (ctypes.c_int64 * 4)()
+    total = _L.tileqr_dag_counts(p, q, strips, c)
+    return total, list(c)
+
+
+def dag_selfcheck(p, q, strips, trials, seed):
+    return _L.tileqr_dag_selfcheck(p, q, strips, trials, seed)
+
+
+def trace():
+    n = _L.tileqr_trace(None, 0)
+    buf = (ctypes.c_int64 * (8 * max(n, 1)))()
+    n = _L.tileqr_trace(buf, n)
+    return [tuple(buf[8 * e: 8 * e + 8]) for e in range(n)], _L.tileqr_trace_clock_hz()
+
+
+def status_string(s):
+    return _L.tileqr_status_string(s).decode()
+
+
+def finalize():
+    return _L.tileqr_finalize()
+
+
+def check(status, where):
+    if status != OK:
+        raise TileQRError(status, where)
+
+
+# ------------------------------------------------------- torch conveniences
+
+def _torch():
+    import torch
+    return torch
+
+
+def to_device(M, device="cuda"):
+    """Column-major device copy of a host matrix (numpy or torch): returns a
+    contiguous (n, m) float64 tensor whose storage is M column-major."""
+    torch = _torch()
+    t = torch.as_tensor(M, dtype=torch.float64)
+    if t.dim() == 1:
+        t = t.reshape(-1, 1)
+    return t.t().contiguous().to(device)
+
+
+def to_host(t, m=None):
+    """Inverse of to_device: numpy (m, n) array from a (n, ld) column-major tensor."""
+    a = t.detach().cpu().numpy().T
+    return a[:m] if m is not None else a
+
+
+def factor_tensor(At, m, nb, ib, o=None):
+    """Factor the column-major matrix in tensor At (shape (n, lda)) in place;
+    returns the T tensor."""
+    torch = _torch()
+    n, lda = At.shape
+    T = torch.empty(max(t_size(m, n, nb, ib), 1), dtype=torch.float64, device=At.device)
+    check(factor(m, n, At.data_ptr(), lda, nb, ib, T.data_ptr(), o), "tileqr_factor")
+    return T

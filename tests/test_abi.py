@@ -1,0 +1,89 @@
+"""Host-side checks of the C-ABI library: it loads without a GPU, exports
+every entry point the header declares, and its host-only DAG utilities agree
+with Algorithm 2 (task counts, dependency rules) and with the cost model of
+Section 3.2.3."""
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+
+def _tq():
+    lib = os.path.join(ROOT, "paper_0709_1272_amd", "libtileqr.so")
+    if not os.path.exists(lib):
+        pytest.skip("libtileqr.so not built")
+    from paper_0709_1272_amd import tileqr
+    return tileqr
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "tileqr.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tileqr_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_match_header():
+    tq = _tq()
+    declared = header_functions()
+    assert declared, "no declarations parsed"
+    for name in declared:
+        assert hasattr(tq._L, name), f"{name} declared in include/tileqr.h but not exported"
+    assert sorted(tq.EXPORTS) == declared
+
+
+def test_dag_counts_p3q3():
+    # Algorithm 2 on a 3 x 3 tile grid: 3 GEQRT, 3 TSQRT, 3 LARFB, 5 SSRFB.
+    tq = _tq()
+    total, c = tq.dag_counts(3, 3, 1)
+    assert total == 14
+    assert c == [3, 3, 3, 5]
+
+
+@pytest.mark.parametrize("p,q", [(1, 1), (4, 4), (8, 8), (32, 32), (256, 4), (3, 7), (7, 3)])
+def test_dag_counts_closed_form(p, q):
+    tq = _tq()
+    kmax = min(p, q)
+    geqrt = kmax
+    tsqrt = sum(p - k - 1 for k in range(kmax))
+    larfb = sum(q - k - 1 for k in range(kmax))
+    ssrfb = sum((p - k - 1) * (q - k - 1) for k in range(kmax))
+    for strips in (1, 8):
+        total, c = tq.dag_counts(p, q, strips)
+        assert c == [geqrt, tsqrt, larfb * strips, ssrfb * strips]
+
+
+@pytest.mark.parametrize("p,q,strips,trials", [(1, 1, 1, 3), (3, 3, 1, 50), (3, 3, 4, 50), (5, 2, 2, 50),
+                                               (2, 6, 2, 50), (6, 6, 8, 20), (12, 4, 2, 10), (1, 5, 2, 10),
+                                               (5, 1, 2, 10)])
+def test_dag_rules_random_orders(p, q, strips, trials):
+    # Random topological orders of the scheduler's DAG must show every task
+    # the tile versions that Algorithm 2's loop order shows it.
+    tq = _tq()
+    assert tq.dag_selfcheck(p, q, strips, trials, 1234 + p * 100 + q) == 0
+
+
+def test_flop_model():
+    tq = _tq()
+    # Per-kernel sum with s << b approaches 2n^2(m - n/3)(1 + s/(4b)) (Section 3.2.3).
+    for (m, n, b, s) in ((8192, 8192, 256, 32), (65536, 1024, 256, 32), (32768, 32768, 256, 32)):
+        tiled = tq.flops_tiled(m, n, b, s)
+        model = 2.0 * n * n * (m - n / 3.0) * (1 + s / (4.0 * b))
+        assert abs(tiled / model - 1) < 0.05, (m, n, tiled / model)
+    # s = b costs 25 % more than the LAPACK count (Section 3.2.3).
+    r = tq.flops_tiled(16384, 16384, 64, 64) / tq.flops_lapack(16384, 16384)
+    assert abs(r - 1.25) < 0.02
+    assert tq.flops_lapack(8192, 8192) == pytest.approx(2 * 8192**3 - 2 * 8192**3 / 3)
+
+
+def test_blocking_rules():
+    tq = _tq()
+    for nb in (64, 128, 256):
+        for ib in (16, 32):
+            assert tq.blocking_supported(nb, ib)
+    assert not tq.blocking_supported(96, 32)
+    assert not tq.blocking_supported(64, 8)
+    assert tq.t_size(512, 512, 64, 16) == 8 * 8 * 16 * 64
+    assert tq.t_size(0, 5, 64, 16) == 0
+    assert tq.t_size(100, 300, 64, 16) == 2 * 2 * 16 * 64   # p = 2, q = 5, min = 2
