@@ -71,8 +71,10 @@ enum {
     TILEQR_FLAG_SERIAL = 1u << 1,  /* run the tasks one launch each in Algorithm 2's
                                       loop order instead of the DAG scheduler          */
     TILEQR_FLAG_TRACE = 1u << 2,   /* record one trace event per task (tileqr_trace)   */
-    TILEQR_FLAG_SHUFFLE = 1u << 3  /* DAG scheduler pops ready tasks in a seeded
+    TILEQR_FLAG_SHUFFLE = 1u << 3, /* DAG scheduler pops ready tasks in a seeded
                                       pseudo-random order (schedule-independence test) */
+    TILEQR_FLAG_TIMING = 1u << 4   /* time each stage with HIP events on the call's
+                                      stream (tileqr_last_timing)                      */
 };
 
 typedef struct {
@@ -85,7 +87,8 @@ typedef struct {
     uint64_t seed;        /* seed of TILEQR_FLAG_SHUFFLE                             */
     int64_t spin_limit;   /* scheduler watchdog: idle polls without progress before
                              TILEQR_ETIMEOUT; 0 = default (several seconds)          */
-    int64_t workers;      /* persistent workgroups; 0 = as many as fit on the device   */
+    int64_t workers;      /* update-worker workgroups of the DAG scheduler; 0 = as many
+                             as fit beside the panel worker                          */
     int64_t drop_edge;    /* test hook for the watchdog: the task with this id skips
                              its first successor release; -1 (default) = none        */
 } tileqr_opts;
@@ -228,6 +231,13 @@ int tileqr_dag_selfcheck(int64_t p, int64_t q, int64_t strips, int64_t trials, u
  * Returns the number of events available. */
 int64_t tileqr_trace(int64_t *events, int64_t cap);
 double tileqr_trace_clock_hz(void);
+
+/* Device times in milliseconds of the stages of the last tileqr_factor_ex
+ * call made with TILEQR_FLAG_TIMING (synchronous): ms[0] layout conversion
+ * in, ms[1] scheduler set-up, ms[2] the factorisation kernel(s) (the
+ * persistent worker, or all launches of the serial driver), ms[3] layout
+ * conversion out.  Returns 0, or TILEQR_EUNSUPPORTED if no timed call ran. */
+int tileqr_last_timing(double ms[4]);
 
 const char *tileqr_status_string(int status);
 const char *tileqr_last_hip_error(void);

@@ -1,9 +1,11 @@
 """Compile the HIP library ``libtileqr.so`` in-tree for gfx950.
 
 Every source is built with ``-Xclang -target-feature -Xclang -packed-fp32-ops``
-(packed FP32 instructions disabled) and ``-ffp-contract=fast`` left at the
-compiler default for device code.  The host pass warns that it does not know
-that target feature; the warning is harmless.
+(packed FP32 instructions disabled; the host pass warns that it does not know
+that target feature, which is harmless) and ``-ffp-contract=on``: a multiply
+and an add are fused only inside one source expression, so every kernel that
+inlines the same tile routine performs the same roundings (the serial driver
+and the persistent scheduler then agree bit for bit).
 """
 import os
 import subprocess
@@ -28,7 +30,7 @@ def build(verbose=False, jobs=None):
     for src in sources():
         obj = os.path.join(CSRC, os.path.basename(src) + ".o")
         cmd = [hipcc, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
-               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=on",
                "-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
         if src.endswith(".cpp"):
             cmd[1:1] = ["-x", "hip"]

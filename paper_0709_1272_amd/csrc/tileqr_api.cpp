@@ -64,6 +64,9 @@ struct Workspace {
     DevBuf tiles, counters, qslot, qctl, mats, status, trace, misc;
     int *host_status = nullptr;   // pinned
     int64_t trace_events = 0;
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    double last_ms[4] = {0, 0, 0, 0};
+    bool have_timing = false;
     int num_cu = 0;
     double wall_hz = 0.0;
 };
@@ -306,7 +309,8 @@ int check_status(Workspace *W, int *dstatus, hipStream_t st)
 // Runs the factorisation of the tiles already in W->tiles (status already
 // cleared and set by the conversion).  Either the serial Algorithm 2 driver
 // or the persistent DAG scheduler.
-int run_factor(Workspace *W, int nb, int ib, int p, int q, double *T, const tileqr_opts &o, hipStream_t st)
+int run_factor(Workspace *W, int nb, int ib, int p, int q, double *T, const tileqr_opts &o, hipStream_t st,
+               hipEvent_t ev_setup_done)
 {
     int *dstatus = (int *)W->status.ptr;
     MatDev M;
@@ -316,18 +320,27 @@ int run_factor(Workspace *W, int nb, int ib, int p, int q, double *T, const tile
     M.q = q;
     M.task_base = 0;
     if (o.flags & TILEQR_FLAG_SERIAL) {
+        if (ev_setup_done) TQ_HIP(hipEventRecord(ev_setup_done, st));
         TQ_HIP(launch_factor_serial(nb, ib, M, dstatus, st));
         return 0;
     }
     const int ns = nb / kStripWidth;
     const Grid g = make_grid(p, q, ns);
-    int64_t counts[4];
-    const int64_t ntask = tileqr_dag_counts(p, q, ns, counts);
+    int64_t counts[NQUEUE] = {0};
+    int64_t ntask = 0;
+    for (int64_t id = 0; id < g.total; ++id) {
+        const Task t = decode(g, id);
+        if (valid(g, t)) {
+            ++counts[queue_of(t, ns, 0)];
+            ++ntask;
+        }
+    }
     int rc;
     if ((rc = W->counters.ensure((size_t)g.total * sizeof(int32_t)))) return rc;
     const int64_t qtotal = ntask;
     if ((rc = W->qslot.ensure((size_t)qtotal * sizeof(int32_t)))) return rc;
-    if ((rc = W->qctl.ensure(2 * 4 * 32 * sizeof(uint32_t) + 256))) return rc;
+    const size_t qctl_bytes = 2 * NQUEUE * 32 * sizeof(uint32_t) + 256 + NQUEUE * sizeof(int64_t);
+    if ((rc = W->qctl.ensure(qctl_bytes))) return rc;
     if ((rc = W->mats.ensure(sizeof(MatDev)))) return rc;
     TQ_HIP(hipMemcpyAsync(W->mats.ptr, &M, sizeof(MatDev), hipMemcpyHostToDevice, st));
     SchedDev S;
@@ -340,15 +353,19 @@ int run_factor(Workspace *W, int nb, int ib, int p, int q, double *T, const tile
     S.counters = (int32_t *)W->counters.ptr;
     S.qslot = (int32_t *)W->qslot.ptr;
     S.qslot_total = qtotal;
+    int64_t qoff[NQUEUE];
     int64_t off = 0;
-    for (int l = 0; l < 4; ++l) {
-        S.qoff[l] = off;
+    for (int l = 0; l < NQUEUE; ++l) {
+        qoff[l] = off;
         off += counts[l];
     }
     S.qhead = (uint32_t *)W->qctl.ptr;
-    S.qtail = S.qhead + 4 * 32;
-    S.done = S.qtail + 4 * 32;
+    S.qtail = S.qhead + NQUEUE * 32;
+    S.done = S.qtail + NQUEUE * 32;
     S.trace_count = S.done + 1;
+    int64_t *qoff_dev = (int64_t *)((char *)W->qctl.ptr + 2 * NQUEUE * 32 * sizeof(uint32_t) + 256);
+    TQ_HIP(hipMemcpyAsync(qoff_dev, qoff, sizeof qoff, hipMemcpyHostToDevice, st));
+    S.qoff = qoff_dev;
     S.status = dstatus;
     S.spin_limit = o.spin_limit > 0 ? o.spin_limit : (int64_t)1 << 24;
     S.shuffle = (o.flags & TILEQR_FLAG_SHUFFLE) ? 1 : 0;
@@ -361,10 +378,17 @@ int run_factor(Workspace *W, int nb, int ib, int p, int q, double *T, const tile
         S.trace_cap = (uint32_t)ntask;
         W->trace_events = ntask;
     }
-    int workers = (int)o.workers;
-    if (workers <= 0) workers = std::max(1, W->num_cu) * worker_occupancy(nb, ib);
+    // Panel workers: one per independent panel chain that can be in flight,
+    // at most one per XCD.  Update workers: the rest of what fits at once.
+    const int occ = worker_occupancy(nb, ib);
+    const int capacity = std::max(2, std::max(1, W->num_cu) * occ);
+    const int panel = std::max(1, std::min({8, g.kmax, capacity / 2}));
+    int update = (int)o.workers > 0 ? (int)o.workers : capacity - panel;
+    update = std::max(1, std::min(update, capacity - panel));
+    S.npanel = panel;
     TQ_HIP(launch_sched_init(S, st));
-    TQ_HIP(launch_worker(nb, ib, S, workers, st));
+    if (ev_setup_done) TQ_HIP(hipEventRecord(ev_setup_done, st));
+    TQ_HIP(launch_worker(nb, ib, S, panel + update, st));
     return 0;
 }
 
@@ -394,12 +418,38 @@ extern "C" int tileqr_factor_ex(int64_t m, int64_t n, double *A, int64_t lda, in
     if ((rc = W->tiles.ensure((size_t)p * q * nb * nb * sizeof(double)))) return rc;
     if ((rc = W->status.ensure(256))) return rc;
     W->trace_events = 0;
+    const bool timing = (o.flags & TILEQR_FLAG_TIMING) && !(o.flags & TILEQR_FLAG_ASYNC);
+    W->have_timing = false;
+    if (timing && !W->ev[0])
+        for (auto &e : W->ev) TQ_HIP(hipEventCreate(&e));
     TQ_HIP(hipMemsetAsync(W->status.ptr, 0, sizeof(int), st));
+    if (timing) TQ_HIP(hipEventRecord(W->ev[0], st));
     TQ_HIP(launch_cm2tile(A, lda, m, n, (double *)W->tiles.ptr, (int)nb, p, q, (int *)W->status.ptr, st));
-    if ((rc = run_factor(W, (int)nb, (int)ib, p, q, T, o, st))) return rc;
+    if (timing) TQ_HIP(hipEventRecord(W->ev[1], st));
+    if ((rc = run_factor(W, (int)nb, (int)ib, p, q, T, o, st, timing ? W->ev[2] : nullptr))) return rc;
+    if (timing) TQ_HIP(hipEventRecord(W->ev[3], st));
     TQ_HIP(launch_tile2cm(A, lda, m, n, (double *)W->tiles.ptr, (int)nb, p, q, (const int *)W->status.ptr, st));
+    if (timing) TQ_HIP(hipEventRecord(W->ev[4], st));
     if (o.flags & TILEQR_FLAG_ASYNC) return TILEQR_OK;
-    return check_status(W, (int *)W->status.ptr, st);
+    rc = check_status(W, (int *)W->status.ptr, st);
+    if (timing) {
+        for (int s = 0; s < 4; ++s) {
+            float ms = 0.f;
+            TQ_HIP(hipEventElapsedTime(&ms, W->ev[s], W->ev[s + 1]));
+            W->last_ms[s] = ms;
+        }
+        W->have_timing = true;
+    }
+    return rc;
+}
+
+extern "C" int tileqr_last_timing(double ms[4])
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    Workspace *W = workspace();
+    if (!W || !W->have_timing) return TILEQR_EUNSUPPORTED;
+    for (int s = 0; s < 4; ++s) ms[s] = W->last_ms[s];
+    return TILEQR_OK;
 }
 
 extern "C" int tileqr_factor(int64_t m, int64_t n, double *A, int64_t lda, int64_t nb, int64_t ib, double *T)
@@ -466,6 +516,8 @@ extern "C" int tileqr_finalize(void)
             w->status.release();
             w->trace.release();
             w->misc.release();
+            for (auto &e : w->ev)
+                if (e) (void)hipEventDestroy(e);
             if (w->host_status) (void)hipHostFree(w->host_status);
         }
         delete w;

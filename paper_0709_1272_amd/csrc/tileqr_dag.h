@@ -184,6 +184,41 @@ TQ_HD int64_t succ(const Grid &g, const Task &t, int32_t n)
     }
 }
 
+// Ready-queue level of a task (0 is served first).  The paper ranks GEQRT >
+// TSQRT > LARFB > SSRFB because nodes with more outgoing edges put more
+// tasks in the ready state (Section 4).  Inside the LARFB/SSRFB levels the
+// same criterion singles out the updates of tile column k+1: they feed the
+// next step's GEQRT and TSQRT chain, whose fan-out is the widest of the
+// graph, so they form their own level ahead of the other updates.
+constexpr int NLEVEL = 5;
+
+TQ_HD int priority_level(const Task &t)
+{
+    switch (t.type) {
+    case GEQRT: return 0;
+    case TSQRT: return 1;
+    case LARFB: return t.j == t.k + 1 ? 2 : 3;
+    default: return t.j == t.k + 1 ? 2 : 4;
+    }
+}
+
+// Ready queues.  The two panel levels have one queue each; each update
+// level has one queue per XCD (8 on MI355X), and a strip task always goes to
+// the queue of XCD (matrix + 8 j ns + s)-hash of its tile-column strip, so
+// successive updates of one strip run where its data already sits in L2 and
+// the workers of one XCD only contend among themselves.
+constexpr int NXQ = 8;
+constexpr int NQUEUE = 2 + (NLEVEL - 2) * NXQ;
+
+TQ_HD int queue_index(int level, int x) { return level < 2 ? level : 2 + (level - 2) * NXQ + x; }
+
+TQ_HD int queue_of(const Task &t, int ns, int mat)
+{
+    const int level = priority_level(t);
+    const int x = (int)(((unsigned)mat * 5u + (unsigned)t.j * (unsigned)ns + (unsigned)t.s) % NXQ);
+    return queue_index(level, x);
+}
+
 // Leading-order flops of one task (Section 3.2.3: SSRFB costs 4b^3 + sb^2;
 // GEQRT 4b^3/3, TSQRT and LARFB 2b^3), for a strip task its share.
 TQ_HD double task_flops(const Task &t, int nb, int ib, int ns)

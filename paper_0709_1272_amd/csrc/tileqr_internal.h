@@ -24,14 +24,15 @@ struct SchedDev {
     MatDev *mats;
     int32_t nmat;
     int32_t ns;               // strips per tile
+    int32_t npanel;           // workgroups 0..npanel-1 take the panel role
     int64_t total_ids;        // size of the id space (with holes)
     uint32_t total_tasks;     // number of real tasks
     int32_t *counters;        // [total_ids] remaining predecessors
-    int32_t *qslot;           // queue slots of the 4 levels, back to back
+    int32_t *qslot;           // slots of all ready queues, back to back
     int64_t qslot_total;
-    int64_t qoff[4];          // offset of each level's slots
-    uint32_t *qhead;          // [4 * 32] (one 128-byte line per level)
-    uint32_t *qtail;          // [4 * 32]
+    const int64_t *qoff;      // [NQUEUE] offset of each queue's slots
+    uint32_t *qhead;          // [NQUEUE * 32] (one 128-byte line per queue)
+    uint32_t *qtail;          // [NQUEUE * 32]
     uint32_t *done;           // completed tasks
     int32_t *status;          // STATUS_* flags
     int64_t spin_limit;       // idle polls without progress before STATUS_TIMEOUT
@@ -49,6 +50,9 @@ hipError_t launch_tile2cm(double *A, int64_t lda, int64_t m, int64_t n, const do
                           int p, int q, const int *status, hipStream_t st);
 hipError_t launch_factor_serial(int nb, int ib, const MatDev &M, const int *status, hipStream_t st);
 hipError_t launch_sched_init(const SchedDev &S, hipStream_t st);
+// The persistent scheduler: `workers` workgroups, the first S.npanel of
+// which run the panel tasks (GEQRT, TSQRT) and the others the updates
+// (LARFB, SSRFB).
 hipError_t launch_worker(int nb, int ib, const SchedDev &S, int workers, hipStream_t st);
 int worker_occupancy(int nb, int ib);
 

@@ -19,13 +19,13 @@
 // LARFB/SSRFB updates as (I - V T V^T) applied to the tiles; applying Q^T
 // needs T^T, which is what every update below does.
 //
-// Work unit.  Every task runs on one workgroup of 256 threads (4 wave64s).
-// The GEMM-shaped parts use v_mfma_f64_16x16x4_f64.  For this instruction
-// lane L (n = L % 16, g = L / 16) supplies A[n][g] and B[g][n] and holds
-// D[4 r + g][n] in accumulator element r (r = 0..3).  A tile strip of
-// 32 columns is held in accumulators, wave w owning rows
-// [w nb/4, (w+1) nb/4): element r of row block rb is row
-// w nb/4 + 16 rb + 4 r + g, column 16 cb + n.  The same registers then serve
+// Work unit.  Every task runs on one workgroup of nb/32 wave64s (2 nb
+// threads), each wave owning 32 rows of a tile.  The GEMM-shaped parts use
+// v_mfma_f64_16x16x4_f64.  For this instruction lane L (n = L % 16,
+// g = L / 16) supplies A[n][g] and B[g][n] and holds D[4 r + g][n] in
+// accumulator element r (r = 0..3).  A tile strip of 32 columns is held in
+// accumulators: element r of row block rb (0..1) of wave w is row
+// 32 w + 16 rb + 4 r + g, column 16 cb + n.  The same registers then serve
 // directly as the B operand of the product V^T X (rows as the contracted
 // index: K-chunk r covers rows 16 rb + 4 r .. + 3).
 #include <hip/hip_runtime.h>
@@ -37,8 +37,14 @@
 namespace tq {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+// Tile and T pointers reach the kernels through structures in device memory,
+// so the compiler cannot tell them from LDS or scratch pointers and would use
+// flat instructions; the explicit global address space gives global loads and
+// stores, which do not hold up LDS traffic behind the same counters.
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) v2d gv2d;
 
-constexpr int NT = 256;   // threads per workgroup
 constexpr int WS = 32;    // strip width (columns) of the GEMM-shaped kernels
 constexpr int CB = WS / 16;
 
@@ -49,14 +55,21 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c)
 
 template <int NB, int IB>
 struct Cfg {
-    static constexpr int RB = NB / 64;       // 16-row blocks per wave
+    static constexpr int NW = NB / 32;       // waves per workgroup
+    static constexpr int NT = 64 * NW;       // threads per workgroup (= 2 nb, the launch bound)
+    static constexpr int NSLOT = NW < 4 ? NW : 4;   // LDS slots of the cross-wave reduction
+    static constexpr int RB = 2;             // 16-row blocks per wave
     static constexpr int IBB = IB / 16;      // 16-wide blocks of the ib dimension
     static constexpr int NPAN = NB / IB;     // inner panels per tile
-    static constexpr int LDP = IB + 1;       // LDS row stride of the panel buffer
+    static constexpr int LDP = IB + 2;       // LDS row stride of the panel buffer (16-byte rows)
     static constexpr int RG = NT / IB;       // row groups of the panel factorisation
     static constexpr int RPT = NB / RG;      // panel rows per thread
     static constexpr int NS = NB / WS;       // strips per tile
-    static_assert(NB % 64 == 0 && IB % 16 == 0 && NB % IB == 0, "blocking");
+    static constexpr int VPT = NB * IB / 2 / NT;              // double2 per thread, full panel
+    static constexpr int TPT = (IB * IB / 2 + NT - 1) / NT;   // double2 per thread, one T
+    static constexpr int EPT = IB * WS / NT;                  // W entries per thread
+    static_assert(NB % 64 == 0 && IB % 16 == 0 && NB % IB == 0 && IB <= WS, "blocking");
+    static_assert(VPT >= 1 && EPT >= 1, "workgroup shape");
 };
 
 // A 32-column strip of a tile in accumulator layout (see the file header).
@@ -65,15 +78,26 @@ struct Strip {
     d4 v[Cfg<NB, IB>::RB][CB];
 };
 
+// Register staging of one inner panel (nb x ib) and its T, so that the
+// global loads of the next panel are in flight while the current one is
+// being applied.
+template <int NB, int IB>
+struct Stage {
+    v2d v[Cfg<NB, IB>::VPT];
+    v2d t[Cfg<NB, IB>::TPT];
+};
+
 template <int NB, int IB>
 struct Smem {
     using C = Cfg<NB, IB>;
     double P[(NB + IB) * C::LDP];    // panel / V: rows 0..nb-1 tile rows, nb.. head rows
-    double Wp[4 * IB * WS];          // per-wave partial products
+    double Wp[C::NSLOT * IB * WS];   // per-wave partial products
     double Wa[IB * WS];              // reduced W (or the Gram matrix V^T V)
     double Wb[IB * WS];              // T^T W
     double Tl[IB * IB];              // T of the current inner panel
     double tau[IB];
+    double xb[2][NB];                // reflector tail broadcast (double-buffered by column parity)
+    double hv[IB];                   // head row broadcast (GEQRT)
     double red[(2 + IB) * C::RG];    // panel reductions: sum of squares, max, dots
 };
 
@@ -82,25 +106,72 @@ struct Smem {
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
-__device__ __forceinline__ double *tile_ptr(const MatDev &M, int nb, int i, int j)
+__device__ __forceinline__ gdouble *tile_ptr(const MatDev &M, int nb, int i, int j)
 {
-    return M.tiles + ((size_t)j * M.p + i) * (size_t)nb * nb;
+    return (gdouble *)(M.tiles + ((size_t)j * M.p + i) * (size_t)nb * nb);
 }
 
-__device__ __forceinline__ double *tblock_ptr(const MatDev &M, int nb, int ib, int k, int i)
+__device__ __forceinline__ gdouble *tblock_ptr(const MatDev &M, int nb, int ib, int k, int i)
 {
-    return M.T + ((size_t)k * M.p + i) * (size_t)ib * nb;
+    return (gdouble *)(M.T + ((size_t)k * M.p + i) * (size_t)ib * nb);
+}
+
+// Stage <- columns [c0, c0 + ib) of rows [r0, nb) of a row-major tile
+// (rows above r0 left zero) and the ib x ib T block at Tg.
+template <int NB, int IB>
+__device__ __forceinline__ void stage_load(Stage<NB, IB> &S, const gdouble *tile, int c0, int r0,
+                                           const gdouble *Tg)
+{
+    using C = Cfg<NB, IB>;
+    constexpr int H = IB / 2;
+#pragma unroll
+    for (int u = 0; u < C::VPT; ++u) {
+        const int e = threadIdx.x + u * C::NT, r = e / H, c2 = e % H;
+        S.v[u] = r >= r0 ? *reinterpret_cast<const gv2d *>(tile + (size_t)r * NB + c0 + 2 * c2)
+                         : v2d{0.0, 0.0};
+    }
+#pragma unroll
+    for (int u = 0; u < C::TPT; ++u) {
+        const int e = threadIdx.x + u * C::NT;
+        S.t[u] = e < IB * IB / 2 ? reinterpret_cast<const gv2d *>(Tg)[e] : v2d{0.0, 0.0};
+    }
+}
+
+// sm.P rows [r0, nb) <- staged panel; with `unit` the block's unit lower
+// triangle is made explicit (ones on the diagonal of rows c0.., zeros above).
+template <int NB, int IB>
+__device__ __forceinline__ void stage_store(Smem<NB, IB> &sm, const Stage<NB, IB> &S, int r0, bool unit,
+                                            int c0)
+{
+    using C = Cfg<NB, IB>;
+    constexpr int H = IB / 2;
+#pragma unroll
+    for (int u = 0; u < C::VPT; ++u) {
+        const int e = threadIdx.x + u * C::NT, r = e / H, c = 2 * (e % H);
+        if (r < r0) continue;
+        double a = S.v[u].x, b = S.v[u].y;
+        if (unit) {
+            const int d = r - c0;
+            a = d < c ? 0.0 : (d == c ? 1.0 : a);
+            b = d < c + 1 ? 0.0 : (d == c + 1 ? 1.0 : b);
+        }
+        *reinterpret_cast<v2d *>(&sm.P[r * C::LDP + c]) = v2d{a, b};
+    }
+#pragma unroll
+    for (int u = 0; u < C::TPT; ++u) {
+        const int e = threadIdx.x + u * C::NT;
+        if (e < IB * IB / 2) reinterpret_cast<v2d *>(sm.Tl)[e] = S.t[u];
+    }
 }
 
 // X (accumulator layout) <- strip of a row-major tile: columns
 // [col0, col0 + 16 cbn), rows of every row block.
 template <int NB, int IB>
-__device__ __forceinline__ void load_strip(Strip<NB, IB> &X, const double *tile, int ld,
-                                           int col0, int cbn)
+__device__ __forceinline__ void load_strip(Strip<NB, IB> &X, const gdouble *tile, int ld, int col0, int cbn)
 {
-    const int n = lane_id() & 15, g = lane_id() >> 4, rowbase = wave_id() * (NB / 4);
+    const int n = lane_id() & 15, g = lane_id() >> 4, rowbase = wave_id() * 32;
 #pragma unroll
-    for (int rb = 0; rb < Cfg<NB, IB>::RB; ++rb)
+    for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
@@ -111,12 +182,12 @@ __device__ __forceinline__ void load_strip(Strip<NB, IB> &X, const double *tile,
 }
 
 template <int NB, int IB>
-__device__ __forceinline__ void store_strip(const Strip<NB, IB> &X, double *tile, int ld,
-                                            int col0, int cbn, int rlo)
+__device__ __forceinline__ void store_strip(const Strip<NB, IB> &X, gdouble *tile, int ld, int col0, int cbn,
+                                            int rlo)
 {
-    const int n = lane_id() & 15, g = lane_id() >> 4, rowbase = wave_id() * (NB / 4);
+    const int n = lane_id() & 15, g = lane_id() >> 4, rowbase = wave_id() * 32;
 #pragma unroll
-    for (int rb = 0; rb < Cfg<NB, IB>::RB; ++rb) {
+    for (int rb = 0; rb < 2; ++rb) {
         if (rowbase + rb * 16 < rlo) continue;
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
@@ -130,18 +201,83 @@ __device__ __forceinline__ void store_strip(const Strip<NB, IB> &X, double *tile
     }
 }
 
+// Per-wave partial accumulators (BA x BB blocks of 16 x 16 in accumulator
+// layout, row stride ld) -> sm.Wp slots 0..NSLOT-1.  With 8 waves the upper
+// four first store, then the lower four add theirs (slot q = P_{q+4} + P_q),
+// which halves the LDS the reduction needs; the caller sums the slots in
+// order.  Ends with a barrier.
+template <int NB, int IB, int BA, int BB>
+__device__ __forceinline__ void waves_to_slots(Smem<NB, IB> &sm, const d4 (&acc)[BA][BB], int ld)
+{
+    using C = Cfg<NB, IB>;
+    constexpr int SLOT = IB * WS;
+    const int w = wave_id(), n = lane_id() & 15, g = lane_id() >> 4;
+    if (C::NW > C::NSLOT) {
+        if (w >= C::NSLOT) {
+#pragma unroll
+            for (int a = 0; a < BA; ++a)
+#pragma unroll
+                for (int b = 0; b < BB; ++b)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        sm.Wp[(w - C::NSLOT) * SLOT + (a * 16 + 4 * r + g) * ld + b * 16 + n] = acc[a][b][r];
+        }
+        __syncthreads();
+        if (w < C::NSLOT) {
+#pragma unroll
+            for (int a = 0; a < BA; ++a)
+#pragma unroll
+                for (int b = 0; b < BB; ++b)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        double *d = &sm.Wp[w * SLOT + (a * 16 + 4 * r + g) * ld + b * 16 + n];
+                        *d = *d + acc[a][b][r];
+                    }
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < BA; ++a)
+#pragma unroll
+            for (int b = 0; b < BB; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    sm.Wp[w * SLOT + (a * 16 + 4 * r + g) * ld + b * 16 + n] = acc[a][b][r];
+    }
+    __syncthreads();
+}
+
+template <int NB, int IB>
+__device__ __forceinline__ double sum_slots(const Smem<NB, IB> &sm, int e)
+{
+    constexpr int SLOT = IB * WS;
+    double s = sm.Wp[e];
+#pragma unroll
+    for (int q = 1; q < Cfg<NB, IB>::NSLOT; ++q) s += sm.Wp[q * SLOT + e];
+    return s;
+}
+
 // Apply the block reflector of one inner panel, held in LDS (sm.P rows
 // 0..nb-1 = V, rows below `rlo` ignored; sm.Tl = T), to a strip X:
 //   W = [top +] V^T X;  W <- T^T W;  [top -= W;]  X -= V W.
 // `top` (may be NULL) points at the ib x (16 cbn) block of the coupled upper
 // tile (the R rows the TS form also updates), row stride ldtop.
+// Three workgroup barriers; the products V^T X, T^T W and V W run on MFMA.
 template <int NB, int IB>
-__device__ void apply_panel(Smem<NB, IB> &sm, Strip<NB, IB> &X, int rlo, double *top,
-                            int ldtop, int cbn)
+__device__ void apply_panel(Smem<NB, IB> &sm, Strip<NB, IB> &X, int rlo, gdouble *top, int ldtop, int cbn)
 {
     using C = Cfg<NB, IB>;
     const int tid = threadIdx.x, w = wave_id();
-    const int n = lane_id() & 15, g = lane_id() >> 4, rowbase = w * (NB / 4);
+    const int n = lane_id() & 15, g = lane_id() >> 4, rowbase = w * 32;
+    const int ncol = cbn * 16;
+
+    double tv[C::EPT];
+    if (top != nullptr) {
+#pragma unroll
+        for (int u = 0; u < C::EPT; ++u) {
+            const int e = tid + u * C::NT, kr = e / WS, c = e % WS;
+            tv[u] = c < ncol ? top[(size_t)kr * ldtop + c] : 0.0;
+        }
+    }
 
     // W partial over this wave's rows.
     d4 Wacc[C::IBB][CB];
@@ -163,28 +299,28 @@ __device__ void apply_panel(Smem<NB, IB> &sm, Strip<NB, IB> &X, int rlo, double 
             }
         }
     }
+    waves_to_slots<NB, IB, C::IBB, CB>(sm, Wacc, WS);
 #pragma unroll
-    for (int a = 0; a < C::IBB; ++a)
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                sm.Wp[w * IB * WS + (a * 16 + 4 * r + g) * WS + cb * 16 + n] = Wacc[a][cb][r];
-    __syncthreads();
-    const int ncol = cbn * 16;
-    for (int e = tid; e < IB * WS; e += NT) {
-        const int kr = e / WS, c = e % WS;
-        double s = ((sm.Wp[e] + sm.Wp[IB * WS + e]) + sm.Wp[2 * IB * WS + e]) + sm.Wp[3 * IB * WS + e];
-        if (top != nullptr && c < ncol) s = top[(size_t)kr * ldtop + c] + s;
+    for (int u = 0; u < C::EPT; ++u) {
+        const int e = tid + u * C::NT, c = e % WS;
+        double s = sum_slots<NB, IB>(sm, e);
+        if (top != nullptr && c < ncol) s = tv[u] + s;
         sm.Wa[e] = s;
     }
     __syncthreads();
-    for (int e = tid; e < IB * WS; e += NT) {
-        const int i = e / WS, c = e % WS;
-        double s = 0.0;
-        for (int kk = 0; kk <= i; ++kk) s += sm.Tl[kk * IB + i] * sm.Wa[kk * WS + c];
-        sm.Wb[e] = s;
-        if (top != nullptr && c < ncol) top[(size_t)i * ldtop + c] -= s;
+    // T^T W: one 16 x 16 output block per wave.
+    for (int blk = w; blk < C::IBB * CB; blk += C::NW) {
+        const int a = blk / CB, cb = blk % CB;
+        d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kc = 0; kc < IB / 4; ++kc)
+            acc = mfma(sm.Tl[(4 * kc + g) * IB + a * 16 + n], sm.Wa[(4 * kc + g) * WS + cb * 16 + n], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = a * 16 + 4 * r + g, c = cb * 16 + n;
+            sm.Wb[i * WS + c] = acc[r];
+            if (top != nullptr && c < ncol) top[(size_t)i * ldtop + c] -= acc[r];
+        }
     }
     __syncthreads();
     // X -= V (T^T W)
@@ -212,7 +348,11 @@ __device__ void apply_panel(Smem<NB, IB> &sm, Strip<NB, IB> &X, int rlo, double 
 //          R is untouched by this reflector.
 // Reflector: beta = -sign(alpha) ||[alpha; x]|| (sign(0) = +1),
 // tau = (beta - alpha) / beta, v = x / (alpha - beta); tau = 0 when x = 0.
-// Each thread owns column c = tid % ib and rows rg, rg + RG, ... of the tail.
+// Thread (rg, c) keeps column c, rows rg, rg + RG, ... in registers; per
+// column two barriers: the reflector's tail is broadcast through LDS (two
+// buffers by column parity, so that column j+1 may publish while column j's
+// update still reads), the norm and the dot products are reduced through LDS
+// partials.
 template <int NB, int IB>
 __device__ void panel_factor(Smem<NB, IB> &sm, int c0, bool ts)
 {
@@ -220,50 +360,66 @@ __device__ void panel_factor(Smem<NB, IB> &sm, int c0, bool ts)
     constexpr int RG = C::RG, RPT = C::RPT, LDP = C::LDP;
     const int tid = threadIdx.x, c = tid % IB, rg = tid / IB;
     double *red_ss = sm.red, *red_mx = sm.red + RG, *red_dot = sm.red + 2 * RG;
+    double pr[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) pr[i] = sm.P[(rg + i * RG) * LDP + c];
+#pragma unroll 1
     for (int j = 0; j < IB; ++j) {
         const int hrow = ts ? NB + j : c0 + j;
         const int tlo = ts ? 0 : c0 + j + 1;
-        const double alpha = sm.P[hrow * LDP + j];
-        double xr[RPT];
-        double hc = 0.0;
-        if (c >= j) {
+        double *xb = sm.xb[j & 1];
+        // A: column j publishes its tail; GEQRT's head row publishes itself.
+        if (c == j) {
             double part = 0.0, mx = 0.0;
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
                 const int r = rg + i * RG;
-                const double x = r >= tlo ? sm.P[r * LDP + j] : 0.0;
-                xr[i] = x;
-                if (c == j) {
-                    part += x * x;
-                    mx = fmax(mx, fabs(x));
-                } else if (r >= tlo) {
-                    part += x * sm.P[r * LDP + c];
-                }
+                const double x = r >= tlo ? pr[i] : 0.0;
+                if (r >= tlo) xb[r] = x;
+                part += x * x;
+                mx = fmax(mx, fabs(x));
             }
-            if (c == j) {
-                red_ss[rg] = part;
-                red_mx[rg] = mx;
-            } else {
-                red_dot[rg * IB + c] = part;
-                hc = sm.P[hrow * LDP + c];
-            }
+            red_ss[rg] = part;
+            red_mx[rg] = mx;
+        }
+        if (!ts && c >= j && rg == hrow % RG) {
+            double h = 0.0;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+                if (rg + i * RG == hrow) h = pr[i];
+            sm.hv[c] = h;
         }
         __syncthreads();
+        // B: partial dot products of the tail with every later column.
+        const double alpha = ts ? sm.P[hrow * LDP + j] : sm.hv[j];
+        double hc = 0.0;
+        if (c > j) {
+            double part = 0.0;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int r = rg + i * RG;
+                if (r >= tlo) part += xb[r] * pr[i];
+            }
+            red_dot[rg * IB + c] = part;
+            hc = ts ? sm.P[hrow * LDP + c] : sm.hv[c];
+        }
         double sig = 0.0, mxa = 0.0;
         for (int q = 0; q < RG; ++q) {
             sig += red_ss[q];
             mxa = fmax(mxa, red_mx[q]);
         }
+        __syncthreads();
+        // C: the reflector and the rank-1 update, in registers.
         double xnorm;
         if (!(sig <= 1.0e300) || (sig < 2.2250738585072014e-308 && mxa > 0.0)) {
             // Sum of squares overflowed or underflowed: recompute it scaled
             // by the largest magnitude (block-uniform branch).
-            __syncthreads();
             if (c == j) {
                 double part = 0.0;
 #pragma unroll
                 for (int i = 0; i < RPT; ++i) {
-                    const double t = xr[i] / mxa;
+                    const int r = rg + i * RG;
+                    const double t = r >= tlo ? pr[i] / mxa : 0.0;
                     part += t * t;
                 }
                 red_ss[rg] = part;
@@ -272,6 +428,7 @@ __device__ void panel_factor(Smem<NB, IB> &sm, int c0, bool ts)
             double s2 = 0.0;
             for (int q = 0; q < RG; ++q) s2 += red_ss[q];
             xnorm = mxa * sqrt(s2);
+            __syncthreads();
         } else {
             xnorm = sqrt(sig);
         }
@@ -284,10 +441,11 @@ __device__ void panel_factor(Smem<NB, IB> &sm, int c0, bool ts)
 #pragma unroll
                 for (int i = 0; i < RPT; ++i) {
                     const int r = rg + i * RG;
-                    if (r >= tlo) sm.P[r * LDP + j] = xr[i] * scal;
+                    if (r >= tlo) pr[i] = pr[i] * scal;
+                    if (!ts && r == hrow) pr[i] = beta;
                 }
                 if (rg == 0) {
-                    sm.P[hrow * LDP + j] = beta;
+                    if (ts) sm.P[hrow * LDP + j] = beta;
                     sm.tau[j] = tau;
                 }
             } else if (c > j) {
@@ -298,15 +456,21 @@ __device__ void panel_factor(Smem<NB, IB> &sm, int c0, bool ts)
 #pragma unroll
                 for (int i = 0; i < RPT; ++i) {
                     const int r = rg + i * RG;
-                    if (r >= tlo) sm.P[r * LDP + c] -= (xr[i] * scal) * tw;
+                    if (r >= tlo) pr[i] -= (xb[r] * scal) * tw;
+                    if (!ts && r == hrow) pr[i] = hc - tw;
                 }
-                if (rg == 0) sm.P[hrow * LDP + c] = hc - tw;
+                if (ts && rg == 0) sm.P[hrow * LDP + c] = hc - tw;
             }
         } else if (tid == 0) {
             sm.tau[j] = 0.0;
         }
-        __syncthreads();
     }
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int r = rg + i * RG;
+        if (ts || r >= c0) sm.P[r * LDP + c] = pr[i];
+    }
+    __syncthreads();
 }
 
 // T of the panel in sm.P (rows >= rlo; V with its unit diagonal explicit):
@@ -314,11 +478,11 @@ __device__ void panel_factor(Smem<NB, IB> &sm, int c0, bool ts)
 //   T[j][j] = tau_j,  T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j].
 // Leaves T in sm.Tl and writes it to Tg (row-major ib x ib).
 template <int NB, int IB>
-__device__ void build_t(Smem<NB, IB> &sm, int rlo, double *Tg)
+__device__ void build_t(Smem<NB, IB> &sm, int rlo, gdouble *Tg)
 {
     using C = Cfg<NB, IB>;
     const int tid = threadIdx.x, w = wave_id();
-    const int n = lane_id() & 15, g = lane_id() >> 4, rowbase = w * (NB / 4);
+    const int n = lane_id() & 15, g = lane_id() >> 4, rowbase = w * 32;
     d4 G[C::IBB][C::IBB];
 #pragma unroll
     for (int a = 0; a < C::IBB; ++a)
@@ -339,16 +503,8 @@ __device__ void build_t(Smem<NB, IB> &sm, int rlo, double *Tg)
                 for (int b = 0; b < C::IBB; ++b) G[a][b] = mfma(v[a], v[b], G[a][b]);
         }
     }
-#pragma unroll
-    for (int a = 0; a < C::IBB; ++a)
-#pragma unroll
-        for (int b = 0; b < C::IBB; ++b)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                sm.Wp[w * IB * IB + (a * 16 + 4 * r + g) * IB + b * 16 + n] = G[a][b][r];
-    __syncthreads();
-    for (int e = tid; e < IB * IB; e += NT)
-        sm.Wa[e] = ((sm.Wp[e] + sm.Wp[IB * IB + e]) + sm.Wp[2 * IB * IB + e]) + sm.Wp[3 * IB * IB + e];
+    waves_to_slots<NB, IB, C::IBB, C::IBB>(sm, G, IB);
+    for (int e = tid; e < IB * IB; e += C::NT) sm.Wa[e] = sum_slots<NB, IB>(sm, e);
     __syncthreads();
     if (tid < IB) {
         const int i = tid;
@@ -365,29 +521,7 @@ __device__ void build_t(Smem<NB, IB> &sm, int rlo, double *Tg)
         }
     }
     __syncthreads();
-    for (int e = tid; e < IB * IB; e += NT) Tg[e] = sm.Tl[e];
-}
-
-// V of inner panel l of the diagonal tile into sm.P rows c0..nb-1 with the
-// unit diagonal and the zeros above it made explicit.
-template <int NB, int IB>
-__device__ void load_v_diag(Smem<NB, IB> &sm, const double *tkk, int c0)
-{
-    using C = Cfg<NB, IB>;
-    for (int e = threadIdx.x; e < (NB - c0) * IB; e += NT) {
-        const int r = c0 + e / IB, c = e % IB;
-        const int d = r - c0;
-        double v = tkk[(size_t)r * NB + c0 + c];
-        if (d < c) v = 0.0;
-        else if (d == c) v = 1.0;
-        sm.P[r * C::LDP + c] = v;
-    }
-}
-
-template <int NB, int IB>
-__device__ void load_t(Smem<NB, IB> &sm, const double *Tg)
-{
-    for (int e = threadIdx.x; e < IB * IB; e += NT) sm.Tl[e] = Tg[e];
+    for (int e = tid; e < IB * IB; e += C::NT) Tg[e] = sm.Tl[e];
 }
 
 // ------------------------------------------------------------ tile kernels
@@ -397,27 +531,35 @@ template <int NB, int IB>
 __device__ void task_geqrt(Smem<NB, IB> &sm, const MatDev &M, int k)
 {
     using C = Cfg<NB, IB>;
-    double *tkk = tile_ptr(M, NB, k, k);
-    double *Tk = tblock_ptr(M, NB, IB, k, k);
+    gdouble *tkk = tile_ptr(M, NB, k, k);
+    gdouble *Tk = tblock_ptr(M, NB, IB, k, k);
+    Stage<NB, IB> S;
+#pragma unroll 1
     for (int l = 0; l < C::NPAN; ++l) {
         const int c0 = l * IB;
-        for (int e = threadIdx.x; e < (NB - c0) * IB; e += NT) {
-            const int r = c0 + e / IB, c = e % IB;
-            sm.P[r * C::LDP + c] = tkk[(size_t)r * NB + c0 + c];
-        }
+        stage_load<NB, IB>(S, tkk, c0, c0, Tk);
+        stage_store<NB, IB>(sm, S, c0, false, c0);
         __syncthreads();
         panel_factor<NB, IB>(sm, c0, false);
         // Write R and V back; keep V with explicit unit diagonal in LDS.
-        for (int e = threadIdx.x; e < (NB - c0) * IB; e += NT) {
-            const int r = c0 + e / IB, c = e % IB;
+        constexpr int H = IB / 2;
+#pragma unroll
+        for (int u = 0; u < C::VPT; ++u) {
+            const int e = threadIdx.x + u * C::NT, r = e / H, cc = 2 * (e % H);
+            if (r < c0) continue;
+            v2d v = *reinterpret_cast<v2d *>(&sm.P[r * C::LDP + cc]);
+            *reinterpret_cast<gv2d *>(tkk + (size_t)r * NB + c0 + cc) = v;
             const int d = r - c0;
-            const double v = sm.P[r * C::LDP + c];
-            tkk[(size_t)r * NB + c0 + c] = v;
-            if (d <= c) sm.P[r * C::LDP + c] = d == c ? 1.0 : 0.0;
+            if (d <= cc + 1) {
+                v.x = d < cc ? 0.0 : (d == cc ? 1.0 : v.x);
+                v.y = d < cc + 1 ? 0.0 : 1.0;
+                *reinterpret_cast<v2d *>(&sm.P[r * C::LDP + cc]) = v;
+            }
         }
         __syncthreads();
         build_t<NB, IB>(sm, c0, Tk + l * IB * IB);
         __syncthreads();
+#pragma unroll 1
         for (int col0 = c0 + IB; col0 < NB; col0 += WS) {
             const int cbn = min(CB, (NB - col0) / 16);
             Strip<NB, IB> X;
@@ -434,31 +576,35 @@ template <int NB, int IB>
 __device__ void task_tsqrt(Smem<NB, IB> &sm, const MatDev &M, int k, int i)
 {
     using C = Cfg<NB, IB>;
-    double *tkk = tile_ptr(M, NB, k, k);
-    double *tik = tile_ptr(M, NB, i, k);
-    double *Ti = tblock_ptr(M, NB, IB, k, i);
+    gdouble *tkk = tile_ptr(M, NB, k, k);
+    gdouble *tik = tile_ptr(M, NB, i, k);
+    gdouble *Ti = tblock_ptr(M, NB, IB, k, i);
+    Stage<NB, IB> S;
+    constexpr int H = IB / 2;
+#pragma unroll 1
     for (int l = 0; l < C::NPAN; ++l) {
         const int c0 = l * IB;
-        for (int e = threadIdx.x; e < IB * IB; e += NT) {
+        stage_load<NB, IB>(S, tik, c0, 0, Ti);
+        for (int e = threadIdx.x; e < IB * IB; e += C::NT) {
             const int r = e / IB, c = e % IB;
             sm.P[(NB + r) * C::LDP + c] = r <= c ? tkk[(size_t)(c0 + r) * NB + c0 + c] : 0.0;
         }
-        for (int e = threadIdx.x; e < NB * IB; e += NT) {
-            const int r = e / IB, c = e % IB;
-            sm.P[r * C::LDP + c] = tik[(size_t)r * NB + c0 + c];
-        }
+        stage_store<NB, IB>(sm, S, 0, false, c0);
         __syncthreads();
         panel_factor<NB, IB>(sm, c0, true);
-        for (int e = threadIdx.x; e < IB * IB; e += NT) {
+        for (int e = threadIdx.x; e < IB * IB; e += C::NT) {
             const int r = e / IB, c = e % IB;
             if (r <= c) tkk[(size_t)(c0 + r) * NB + c0 + c] = sm.P[(NB + r) * C::LDP + c];
         }
-        for (int e = threadIdx.x; e < NB * IB; e += NT) {
-            const int r = e / IB, c = e % IB;
-            tik[(size_t)r * NB + c0 + c] = sm.P[r * C::LDP + c];
+#pragma unroll
+        for (int u = 0; u < C::VPT; ++u) {
+            const int e = threadIdx.x + u * C::NT, r = e / H, cc = 2 * (e % H);
+            *reinterpret_cast<gv2d *>(tik + (size_t)r * NB + c0 + cc) =
+                *reinterpret_cast<v2d *>(&sm.P[r * C::LDP + cc]);
         }
         build_t<NB, IB>(sm, 0, Ti + l * IB * IB);
         __syncthreads();
+#pragma unroll 1
         for (int col0 = c0 + IB; col0 < NB; col0 += WS) {
             const int cbn = min(CB, (NB - col0) / 16);
             Strip<NB, IB> X;
@@ -475,17 +621,20 @@ template <int NB, int IB>
 __device__ void task_larfb(Smem<NB, IB> &sm, const MatDev &M, int k, int j, int s)
 {
     using C = Cfg<NB, IB>;
-    const double *tkk = tile_ptr(M, NB, k, k);
-    double *tkj = tile_ptr(M, NB, k, j);
-    const double *Tk = tblock_ptr(M, NB, IB, k, k);
+    const gdouble *tkk = tile_ptr(M, NB, k, k);
+    gdouble *tkj = tile_ptr(M, NB, k, j);
+    const gdouble *Tk = tblock_ptr(M, NB, IB, k, k);
     const int col0 = s * WS;
+    Stage<NB, IB> S;
+    stage_load<NB, IB>(S, tkk, 0, 0, Tk);
     Strip<NB, IB> X;
     load_strip<NB, IB>(X, tkj, NB, col0, CB);
+#pragma unroll 1
     for (int l = 0; l < C::NPAN; ++l) {
         const int c0 = l * IB;
-        load_v_diag<NB, IB>(sm, tkk, c0);
-        load_t<NB, IB>(sm, Tk + l * IB * IB);
+        stage_store<NB, IB>(sm, S, c0, true, c0);
         __syncthreads();
+        if (l + 1 < C::NPAN) stage_load<NB, IB>(S, tkk, c0 + IB, c0 + IB, Tk + (l + 1) * IB * IB);
         apply_panel<NB, IB>(sm, X, c0, nullptr, 0, CB);
         __syncthreads();
     }
@@ -497,35 +646,42 @@ template <int NB, int IB>
 __device__ void task_ssrfb(Smem<NB, IB> &sm, const MatDev &M, int k, int i, int j, int s)
 {
     using C = Cfg<NB, IB>;
-    const double *tik = tile_ptr(M, NB, i, k);
-    double *tkj = tile_ptr(M, NB, k, j);
-    double *tij = tile_ptr(M, NB, i, j);
-    const double *Ti = tblock_ptr(M, NB, IB, k, i);
+    const gdouble *tik = tile_ptr(M, NB, i, k);
+    gdouble *tkj = tile_ptr(M, NB, k, j);
+    gdouble *tij = tile_ptr(M, NB, i, j);
+    const gdouble *Ti = tblock_ptr(M, NB, IB, k, i);
     const int col0 = s * WS;
+    Stage<NB, IB> S;
+    stage_load<NB, IB>(S, tik, 0, 0, Ti);
     Strip<NB, IB> X;
     load_strip<NB, IB>(X, tij, NB, col0, CB);
+#pragma unroll 1
     for (int l = 0; l < C::NPAN; ++l) {
         const int c0 = l * IB;
-        for (int e = threadIdx.x; e < NB * IB; e += NT) {
-            const int r = e / IB, c = e % IB;
-            sm.P[r * C::LDP + c] = tik[(size_t)r * NB + c0 + c];
-        }
-        load_t<NB, IB>(sm, Ti + l * IB * IB);
+        stage_store<NB, IB>(sm, S, 0, false, c0);
         __syncthreads();
+        if (l + 1 < C::NPAN) stage_load<NB, IB>(S, tik, c0 + IB, 0, Ti + (l + 1) * IB * IB);
         apply_panel<NB, IB>(sm, X, 0, tkj + (size_t)c0 * NB + col0, NB, CB);
         __syncthreads();
     }
     store_strip<NB, IB>(X, tij, NB, col0, CB, 0);
 }
 
-template <int NB, int IB>
-__device__ void run_task(Smem<NB, IB> &sm, const MatDev &M, const Task &t)
+// Workers come in two roles: ROLE_PANEL runs GEQRT and TSQRT (queue
+// levels 0-1), ROLE_UPDATE runs LARFB and SSRFB (levels 2..NLEVEL-1).  The
+// persistent kernel gives the panel role to its lowest workgroup indices,
+// which the dispatcher makes resident first.
+enum { ROLE_PANEL = 0, ROLE_UPDATE = 1 };
+
+template <int NB, int IB, int ROLE>
+__device__ __forceinline__ void run_task(Smem<NB, IB> &sm, const MatDev &M, const Task &t)
 {
-    switch (t.type) {
-    case GEQRT: task_geqrt<NB, IB>(sm, M, t.k); break;
-    case TSQRT: task_tsqrt<NB, IB>(sm, M, t.k, t.i); break;
-    case LARFB: task_larfb<NB, IB>(sm, M, t.k, t.j, t.s); break;
-    default: task_ssrfb<NB, IB>(sm, M, t.k, t.i, t.j, t.s); break;
+    if constexpr (ROLE == ROLE_PANEL) {
+        if (t.type == GEQRT) task_geqrt<NB, IB>(sm, M, t.k);
+        else task_tsqrt<NB, IB>(sm, M, t.k, t.i);
+    } else {
+        if (t.type == LARFB) task_larfb<NB, IB>(sm, M, t.k, t.j, t.s);
+        else task_ssrfb<NB, IB>(sm, M, t.k, t.i, t.j, t.s);
     }
 }
 
@@ -534,19 +690,17 @@ __device__ void run_task(Smem<NB, IB> &sm, const MatDev &M, const Task &t)
 // One launch per group of independent tasks in Algorithm 2's loop order:
 // GEQRT(k) / TSQRT(k, i): one workgroup; LARFB(k, .) / SSRFB(k, i, .):
 // one workgroup per (j, strip).
-template <int NB, int IB>
-__global__ __launch_bounds__(NT) void k_serial(MatDev M, int type, int k, int i, const int *status)
+template <int NB, int IB, int TYPE>
+__global__ __launch_bounds__(2 * NB) void k_serial(MatDev M, int k, int i, const int *status)
 {
     __shared__ Smem<NB, IB> sm;
     if (*status != 0) return;
     constexpr int NS = Cfg<NB, IB>::NS;
-    Task t;
-    t.type = type;
-    t.k = k;
-    t.i = i;
-    t.j = k + 1 + blockIdx.x / NS;
-    t.s = blockIdx.x % NS;
-    run_task<NB, IB>(sm, M, t);
+    const int j = k + 1 + blockIdx.x / NS, s = blockIdx.x % NS;
+    if constexpr (TYPE == GEQRT) task_geqrt<NB, IB>(sm, M, k);
+    else if constexpr (TYPE == TSQRT) task_tsqrt<NB, IB>(sm, M, k, i);
+    else if constexpr (TYPE == LARFB) task_larfb<NB, IB>(sm, M, k, j, s);
+    else task_ssrfb<NB, IB>(sm, M, k, i, j, s);
 }
 
 // ------------------------------------------------------- DAG scheduler
@@ -560,30 +714,33 @@ __device__ __forceinline__ uint32_t ld_rlx(const uint32_t *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ __forceinline__ void push_task(const SchedDev &S, int level, int64_t gid)
+__device__ __forceinline__ void push_task(const SchedDev &S, int queue, int64_t gid)
 {
-    const uint32_t slot = __hip_atomic_fetch_add(&S.qtail[level * 32], 1u, __ATOMIC_RELAXED,
+    const uint32_t slot = __hip_atomic_fetch_add(&S.qtail[queue * 32], 1u, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&S.qslot[S.qoff[level] + slot], (int32_t)(gid + 1), __ATOMIC_RELEASE,
+    __hip_atomic_store(&S.qslot[S.qoff[queue] + slot], (int32_t)(gid + 1), __ATOMIC_RELEASE,
                        __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Non-blocking pop: -1 when the queue has nothing claimable right now.
-__device__ __forceinline__ int64_t pop_task(const SchedDev &S, int level)
+__device__ __forceinline__ int64_t pop_task(const SchedDev &S, int queue)
 {
     for (int attempt = 0; attempt < 4; ++attempt) {
-        const uint32_t h = ld_rlx(&S.qhead[level * 32]);
-        const uint32_t t = ld_rlx(&S.qtail[level * 32]);
+        const uint32_t t = ld_rlx(&S.qtail[queue * 32]);
+        const uint32_t h = ld_rlx(&S.qhead[queue * 32]);
         if (h >= t) return -1;
-        const int32_t v = ld_acq(&S.qslot[S.qoff[level] + h]);
+        const int32_t v = ld_acq(&S.qslot[S.qoff[queue] + h]);
         if (v == 0) return -1;
         uint32_t expect = h;
-        if (__hip_atomic_compare_exchange_strong(&S.qhead[level * 32], &expect, h + 1, __ATOMIC_ACQ_REL,
+        if (__hip_atomic_compare_exchange_strong(&S.qhead[queue * 32], &expect, h + 1, __ATOMIC_ACQ_REL,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             return (int64_t)v - 1;
     }
     return -1;
 }
+
+// XCD this workgroup runs on (hardware register XCC_ID).
+__device__ __forceinline__ int xcd_id() { return __builtin_amdgcn_s_getreg((3 << 11) | 20) & (NXQ - 1); }
 
 __device__ __forceinline__ int find_mat(const SchedDev &S, int64_t gid)
 {
@@ -619,9 +776,9 @@ __global__ void k_sched_init(SchedDev S)
         S.counters[gid] = valid(g, t) ? indegree(g, t) : -1;
     }
     for (int64_t e = tid0; e < S.qslot_total; e += stride) S.qslot[e] = 0;
-    if (tid0 < 4 * 32) {
-        S.qhead[tid0] = 0;
-        S.qtail[tid0] = 0;
+    for (int64_t e = tid0; e < NQUEUE * 32; e += stride) {
+        S.qhead[e] = 0;
+        S.qtail[e] = 0;
     }
     if (tid0 == 0) {
         *S.done = 0;
@@ -634,50 +791,90 @@ __global__ void k_sched_seed(SchedDev S)
     // Runs after k_sched_init (stream order): queue every GEQRT(0).
     // Every matrix in the list is non-empty (the host drops empty ones).
     for (int mi = threadIdx.x; mi < S.nmat; mi += blockDim.x)
-        S.qslot[S.qoff[0] + mi] = (int32_t)(S.mats[mi].task_base + 1);
+        S.qslot[S.qoff[queue_index(0, 0)] + mi] = (int32_t)(S.mats[mi].task_base + 1);
     __syncthreads();
-    if (threadIdx.x == 0) S.qtail[0] = (uint32_t)S.nmat;
+    if (threadIdx.x == 0) S.qtail[queue_index(0, 0) * 32] = (uint32_t)S.nmat;
 }
 
-template <int NB, int IB>
-__global__ __launch_bounds__(NT) void k_worker(SchedDev S)
+// One pass over the queues a worker serves: the panel worker its two
+// levels; an update worker the update levels in priority order, its own
+// XCD's queue first and, when `steal`, the other XCDs' queues after it.
+template <int ROLE>
+__device__ __forceinline__ int64_t pop_any(const SchedDev &S, int xcd, bool steal, uint64_t shuffle_rng)
 {
-    __shared__ Smem<NB, IB> sm;
+    if constexpr (ROLE == ROLE_PANEL) {
+        const int first = (int)(shuffle_rng & 1);
+        int64_t gid = pop_task(S, queue_index(first, 0));
+        if (gid < 0) gid = pop_task(S, queue_index(first ^ 1, 0));
+        return gid;
+    } else {
+        constexpr int NLV = NLEVEL - 2;
+        const int start = (int)(shuffle_rng % NLV);
+        for (int q = 0; q < NLV; ++q) {
+            const int64_t gid = pop_task(S, queue_index(2 + (start + q) % NLV, xcd));
+            if (gid >= 0) return gid;
+        }
+        if (steal) {
+            for (int q = 0; q < NLV; ++q)
+                for (int d = 1; d < NXQ; ++d) {
+                    const int64_t gid = pop_task(S, queue_index(2 + (start + q) % NLV, (xcd + d) % NXQ));
+                    if (gid >= 0) return gid;
+                }
+        }
+        return -1;
+    }
+}
+
+template <int NB, int IB, int ROLE>
+__device__ __forceinline__ void worker_loop(Smem<NB, IB> &sm, const SchedDev &S)
+{
     __shared__ int64_t s_gid;
     __shared__ int s_exit;
     const int tid = threadIdx.x;
     uint64_t rng = mix64(S.seed ^ (0x9e3779b97f4a7c15ULL * (blockIdx.x + 1)));
+    const int xcd = xcd_id();
     for (;;) {
         if (tid == 0) {
+            // Idle loop: poll the queues with exponential back-off, look at
+            // the completion counter and the status word only every few
+            // rounds; every idle round counts towards the watchdog.
             int64_t gid = -1;
             int ex = 0;
             int64_t idle = 0;
             uint32_t seen = ld_rlx(S.done);
-            for (;;) {
-                if (__hip_atomic_load(S.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-                    ex = 1;
-                    break;
-                }
+            int backoff = 0;
+            for (uint32_t round = 0;; ++round) {
+                uint64_t pick = 0;
                 if (S.shuffle) {
                     rng = mix64(rng + 1);
                     for (int z = 0; z < (int)(rng & 7); ++z) __builtin_amdgcn_s_sleep(1);
-                    const int start = (int)((rng >> 8) & 3);
-                    for (int q = 0; q < 4 && gid < 0; ++q) gid = pop_task(S, (start + q) & 3);
-                } else {
-                    for (int q = 0; q < 4 && gid < 0; ++q) gid = pop_task(S, q);
+                    pick = rng >> 8;
                 }
+                gid = pop_any<ROLE>(S, xcd, ROLE == ROLE_UPDATE && (round & 3) == 3, pick);
                 if (gid >= 0) break;
-                const uint32_t d = ld_rlx(S.done);
-                if (d >= S.total_tasks) { ex = 1; break; }
-                if (d != seen) {
-                    seen = d;
-                    idle = 0;
-                } else if (++idle > S.spin_limit) {
+                if ((round & 3) == 0) {
+                    if (__hip_atomic_load(S.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                        ex = 1;
+                        break;
+                    }
+                    const uint32_t d = ld_rlx(S.done);
+                    if (d >= S.total_tasks) {
+                        ex = 1;
+                        break;
+                    }
+                    if (d != seen) {
+                        seen = d;
+                        idle = 0;
+                    }
+                }
+                if (++idle > S.spin_limit) {
                     __hip_atomic_fetch_or(S.status, STATUS_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     ex = 1;
                     break;
                 }
-                __builtin_amdgcn_s_sleep(2);
+                const int cap = ROLE == ROLE_PANEL ? 2 : 5;
+                backoff = backoff < cap ? backoff + 1 : cap;
+                for (int z = 0; z < (1 << backoff); ++z) __builtin_amdgcn_s_sleep(2);
             }
             s_gid = gid;
             s_exit = ex;
@@ -691,16 +888,16 @@ __global__ __launch_bounds__(NT) void k_worker(SchedDev S)
         const Grid g = make_grid(M.p, M.q, S.ns);
         const Task t = decode(g, gid - M.task_base);
         const uint64_t t0 = wall_clock64();
-        run_task<NB, IB>(sm, M, t);
+        run_task<NB, IB, ROLE>(sm, M, t);
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
         const int ns = nsucc(g, t);
-        for (int n = tid; n < ns; n += NT) {
+        for (int n = tid; n < ns; n += Cfg<NB, IB>::NT) {
             if (S.drop_edge >= 0 && gid == S.drop_edge && n == 0) continue;
             const int64_t sl = succ(g, t, n);
             const int32_t old = __hip_atomic_fetch_add(&S.counters[M.task_base + sl], -1, __ATOMIC_ACQ_REL,
                                                        __HIP_MEMORY_SCOPE_AGENT);
-            if (old == 1) push_task(S, decode(g, sl).type, M.task_base + sl);
+            if (old == 1) push_task(S, queue_of(decode(g, sl), S.ns, mi), M.task_base + sl);
         }
         if (tid == 0) {
             if (S.trace != nullptr) {
@@ -709,7 +906,7 @@ __global__ __launch_bounds__(NT) void k_worker(SchedDev S)
                 if (e < S.trace_cap) {
                     int64_t *ev = S.trace + (size_t)e * 8;
                     ev[0] = t.type; ev[1] = t.k; ev[2] = t.i; ev[3] = t.j; ev[4] = t.s;
-                    ev[5] = mi * 65536 + blockIdx.x;
+                    ev[5] = ((int64_t)mi << 20) | (ROLE << 16) | blockIdx.x;
                     ev[6] = (int64_t)t0;
                     ev[7] = (int64_t)wall_clock64();
                 }
@@ -718,6 +915,14 @@ __global__ __launch_bounds__(NT) void k_worker(SchedDev S)
         }
         __syncthreads();
     }
+}
+
+template <int NB, int IB>
+__global__ __launch_bounds__(2 * NB) void k_worker(SchedDev S)
+{
+    __shared__ Smem<NB, IB> sm;
+    if ((int)blockIdx.x < S.npanel) worker_loop<NB, IB, ROLE_PANEL>(sm, S);
+    else worker_loop<NB, IB, ROLE_UPDATE>(sm, S);
 }
 
 // ------------------------------------------------------ layout conversion
@@ -810,16 +1015,15 @@ static hipError_t serial_impl(const MatDev &M, const int *status, hipStream_t st
 {
     constexpr int NS = Cfg<NB, IB>::NS;
     const int p = M.p, q = M.q, kmax = p < q ? p : q;
+    const dim3 blk(Cfg<NB, IB>::NT);
     for (int k = 0; k < kmax; ++k) {
-        hipLaunchKernelGGL((k_serial<NB, IB>), dim3(1), dim3(NT), 0, st, M, (int)GEQRT, k, k, status);
+        hipLaunchKernelGGL((k_serial<NB, IB, GEQRT>), dim3(1), blk, 0, st, M, k, k, status);
         if (q - k - 1 > 0)
-            hipLaunchKernelGGL((k_serial<NB, IB>), dim3((q - k - 1) * NS), dim3(NT), 0, st, M, (int)LARFB, k,
-                               k, status);
+            hipLaunchKernelGGL((k_serial<NB, IB, LARFB>), dim3((q - k - 1) * NS), blk, 0, st, M, k, k, status);
         for (int i = k + 1; i < p; ++i) {
-            hipLaunchKernelGGL((k_serial<NB, IB>), dim3(1), dim3(NT), 0, st, M, (int)TSQRT, k, i, status);
+            hipLaunchKernelGGL((k_serial<NB, IB, TSQRT>), dim3(1), blk, 0, st, M, k, i, status);
             if (q - k - 1 > 0)
-                hipLaunchKernelGGL((k_serial<NB, IB>), dim3((q - k - 1) * NS), dim3(NT), 0, st, M, (int)SSRFB,
-                                   k, i, status);
+                hipLaunchKernelGGL((k_serial<NB, IB, SSRFB>), dim3((q - k - 1) * NS), blk, 0, st, M, k, i, status);
         }
     }
     return hipGetLastError();
@@ -828,16 +1032,17 @@ static hipError_t serial_impl(const MatDev &M, const int *status, hipStream_t st
 template <int NB, int IB>
 static hipError_t worker_impl(const SchedDev &S, int workers, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_worker<NB, IB>), dim3(workers), dim3(NT), 0, st, S);
+    hipLaunchKernelGGL((k_worker<NB, IB>), dim3(workers), dim3(Cfg<NB, IB>::NT), 0, st, S);
     return hipGetLastError();
 }
 
 template <int NB, int IB>
 static int worker_occupancy_impl()
 {
-    int nblk = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, k_worker<NB, IB>, NT, 0) != hipSuccess) return 1;
-    return nblk > 0 ? nblk : 1;
+    int a = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_worker<NB, IB>, Cfg<NB, IB>::NT, 0) != hipSuccess)
+        return 1;
+    return a > 0 ? a : 1;
 }
 
 #define TQ_DISPATCH(nb, ib, CALL)                                   \

@@ -23,7 +23,7 @@ _L = ctypes.CDLL(LIB_PATH)
 
 OK, EHIP, ENONFINITE, ENOCONV, ETIMEOUT, ENOMEM, EUNSUPPORTED, ESINGULAR = range(8)
 FP64, BF16X2, FP16X2, BF16X3 = range(4)
-FLAG_ASYNC, FLAG_SERIAL, FLAG_TRACE, FLAG_SHUFFLE = 1, 2, 4, 8
+FLAG_ASYNC, FLAG_SERIAL, FLAG_TRACE, FLAG_SHUFFLE, FLAG_TIMING = 1, 2, 4, 8, 16
 
 
 class Opts(ctypes.Structure):
@@ -61,6 +61,7 @@ _SIGS = {
     "tileqr_dag_selfcheck": (_int, [_i64, _i64, _i64, _i64, ctypes.c_uint64]),
     "tileqr_trace": (_i64, [_I64P, _i64]),
     "tileqr_trace_clock_hz": (_dbl, []),
+    "tileqr_last_timing": (_int, [ctypes.POINTER(ctypes.c_double)]),
     "tileqr_status_string": (ctypes.c_char_p, [_int]),
     "tileqr_last_hip_error": (ctypes.c_char_p, []),
     "tileqr_finalize": (_int, []),
@@ -162,6 +163,13 @@ def trace():
     buf = (ctypes.c_int64 * (8 * max(n, 1)))()
     n = _L.tileqr_trace(buf, n)
     return [tuple(buf[8 * e: 8 * e + 8]) for e in range(n)], _L.tileqr_trace_clock_hz()
+
+
+def last_timing():
+    """[layout in, scheduler set-up, factorisation kernel(s), layout out] in ms."""
+    ms = (ctypes.c_double * 4)()
+    check(_L.tileqr_last_timing(ms), "tileqr_last_timing")
+    return list(ms)
 
 
 def status_string(s):
