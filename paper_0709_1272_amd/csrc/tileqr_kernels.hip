@@ -96,9 +96,8 @@ struct Smem {
     double Wb[IB * WS];              // T^T W
     double Tl[IB * IB];              // T of the current inner panel
     double tau[IB];
-    double xb[2][NB];                // reflector tail broadcast (double-buffered by column parity)
-    double hv[IB];                   // head row broadcast (GEQRT)
-    double red[(2 + IB) * C::RG];    // panel reductions: sum of squares, max, dots
+    double xb[2][NB];                // reflector broadcast (double-buffered by column parity)
+    double sc[2][2];                 // tau of the broadcast reflector
 };
 
 // ------------------------------------------------------------------ helpers
@@ -339,6 +338,45 @@ __device__ void apply_panel(Smem<NB, IB> &sm, Strip<NB, IB> &X, int rlo, gdouble
     }
 }
 
+// Lane permutations by DPP on the two 32-bit halves of a double: xor 1 and
+// xor 2 inside a quad, mirror inside 8 and inside 16 lanes.
+template <int CTRL>
+__device__ __forceinline__ double dpp_perm(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum / max over the `W` consecutive lanes of a group (W a power of two
+// dividing 64).  Each step pairs every lane with one of the other half of
+// its current block (xor 1, xor 2, mirror in 8, mirror in 16, then xor 16
+// and xor 32 across rows), so after the last step every lane holds the same
+// bits: partners add the same two numbers in swapped order.
+template <int W>
+__device__ __forceinline__ double group_sum(double v)
+{
+    if (W >= 2) v += dpp_perm<0xB1>(v);
+    if (W >= 4) v += dpp_perm<0x4E>(v);
+    if (W >= 8) v += dpp_perm<0x141>(v);
+    if (W >= 16) v += dpp_perm<0x140>(v);
+    if (W >= 32) v += __shfl_xor(v, 16, 64);
+    if (W >= 64) v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+template <int W>
+__device__ __forceinline__ double group_max(double v)
+{
+    if (W >= 2) v = fmax(v, dpp_perm<0xB1>(v));
+    if (W >= 4) v = fmax(v, dpp_perm<0x4E>(v));
+    if (W >= 8) v = fmax(v, dpp_perm<0x141>(v));
+    if (W >= 16) v = fmax(v, dpp_perm<0x140>(v));
+    if (W >= 32) v = fmax(v, __shfl_xor(v, 16, 64));
+    if (W >= 64) v = fmax(v, __shfl_xor(v, 32, 64));
+    return v;
+}
+
 // Householder factorisation of the ib columns held in sm.P (Section 3.2.1:
 // DGEQRT's panel when ts == false, DTSQRT's when ts == true).
 //   GEQRT: column j has its head (diagonal) at P row c0 + j and its tail in
@@ -348,18 +386,19 @@ __device__ void apply_panel(Smem<NB, IB> &sm, Strip<NB, IB> &X, int rlo, gdouble
 //          R is untouched by this reflector.
 // Reflector: beta = -sign(alpha) ||[alpha; x]|| (sign(0) = +1),
 // tau = (beta - alpha) / beta, v = x / (alpha - beta); tau = 0 when x = 0.
-// Thread (rg, c) keeps column c, rows rg, rg + RG, ... in registers; per
-// column two barriers: the reflector's tail is broadcast through LDS (two
-// buffers by column parity, so that column j+1 may publish while column j's
-// update still reads), the norm and the dot products are reduced through LDS
-// partials.
+// Column c is held by the RG consecutive lanes of one wave (rows rg, rg + RG,
+// ... in registers), so norms and dot products reduce with lane shuffles.
+// Per column one barrier: the group of column j forms its reflector and
+// publishes v and tau through LDS (two buffers by column parity, so that
+// column j+1 may publish while column j's updates still read), then every
+// later column applies it.
 template <int NB, int IB>
 __device__ void panel_factor(Smem<NB, IB> &sm, int c0, bool ts)
 {
     using C = Cfg<NB, IB>;
     constexpr int RG = C::RG, RPT = C::RPT, LDP = C::LDP;
-    const int tid = threadIdx.x, c = tid % IB, rg = tid / IB;
-    double *red_ss = sm.red, *red_mx = sm.red + RG, *red_dot = sm.red + 2 * RG;
+    static_assert(64 % RG == 0, "the threads of a column share one wave");
+    const int tid = threadIdx.x, c = tid / RG, rg = tid % RG;
     double pr[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) pr[i] = sm.P[(rg + i * RG) * LDP + c];
@@ -368,101 +407,100 @@ __device__ void panel_factor(Smem<NB, IB> &sm, int c0, bool ts)
         const int hrow = ts ? NB + j : c0 + j;
         const int tlo = ts ? 0 : c0 + j + 1;
         double *xb = sm.xb[j & 1];
-        // A: column j publishes its tail; GEQRT's head row publishes itself.
+        double *sc = sm.sc[j & 1];
         if (c == j) {
-            double part = 0.0, mx = 0.0;
+            double alpha;
+            if (ts) {
+                alpha = sm.P[hrow * LDP + j];
+            } else {
+                double h = 0.0;
+#pragma unroll
+                for (int i = 0; i < RPT; ++i)
+                    if (rg + i * RG == hrow) h = pr[i];
+                alpha = group_sum<RG>(h);   // only the owner contributes
+            }
+            double part = 0.0;
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
-                const int r = rg + i * RG;
-                const double x = r >= tlo ? pr[i] : 0.0;
-                if (r >= tlo) xb[r] = x;
+                const double x = rg + i * RG >= tlo ? pr[i] : 0.0;
                 part += x * x;
-                mx = fmax(mx, fabs(x));
             }
-            red_ss[rg] = part;
-            red_mx[rg] = mx;
-        }
-        if (!ts && c >= j && rg == hrow % RG) {
-            double h = 0.0;
+            const double sig = group_sum<RG>(part);
+            double xnorm, h;
+            if (sig <= 1.0e300 && (sig >= 2.2250738585072014e-308 || sig == 0.0)) {
+                // Nothing over- or underflowed (a zero sum with nonzero
+                // entries is caught by the scaled pass below).
+                xnorm = sqrt(sig);
+                h = fabs(alpha) < 1.0e150 ? sqrt(alpha * alpha + sig) : hypot(alpha, xnorm);
+            } else {
+                xnorm = -1.0;
+                h = 0.0;
+            }
+            if (xnorm < 0.0 || (sig == 0.0 && group_max<RG>(part) != 0.0)) {
+                // Redo the norm scaled by the largest magnitude.
+                double mx = 0.0;
 #pragma unroll
-            for (int i = 0; i < RPT; ++i)
-                if (rg + i * RG == hrow) h = pr[i];
-            sm.hv[c] = h;
+                for (int i = 0; i < RPT; ++i)
+                    if (rg + i * RG >= tlo) mx = fmax(mx, fabs(pr[i]));
+                const double mxa = group_max<RG>(mx);
+                double p2 = 0.0;
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) {
+                    const double t = rg + i * RG >= tlo ? pr[i] / mxa : 0.0;
+                    p2 += t * t;
+                }
+                xnorm = mxa * sqrt(group_sum<RG>(p2));
+                h = hypot(alpha, xnorm);
+            }
+            double tau = 0.0;
+            if (xnorm != 0.0) {
+                const double beta = alpha >= 0.0 ? -h : h;
+                tau = (beta - alpha) / beta;
+                const double scal = 1.0 / (alpha - beta);
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) {
+                    const int r = rg + i * RG;
+                    if (r >= tlo) {
+                        pr[i] = pr[i] * scal;
+                        xb[r] = pr[i];
+                    }
+                    if (!ts && r == hrow) pr[i] = beta;
+                }
+                if (ts && rg == 0) sm.P[hrow * LDP + j] = beta;
+            }
+            if (rg == 0) {
+                sc[0] = tau;
+                sm.tau[j] = tau;
+            }
         }
         __syncthreads();
-        // B: partial dot products of the tail with every later column.
-        const double alpha = ts ? sm.P[hrow * LDP + j] : sm.hv[j];
-        double hc = 0.0;
-        if (c > j) {
+        const double tau = sc[0];
+        if (c > j && tau != 0.0) {
             double part = 0.0;
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
                 const int r = rg + i * RG;
                 if (r >= tlo) part += xb[r] * pr[i];
             }
-            red_dot[rg * IB + c] = part;
-            hc = ts ? sm.P[hrow * LDP + c] : sm.hv[c];
-        }
-        double sig = 0.0, mxa = 0.0;
-        for (int q = 0; q < RG; ++q) {
-            sig += red_ss[q];
-            mxa = fmax(mxa, red_mx[q]);
-        }
-        __syncthreads();
-        // C: the reflector and the rank-1 update, in registers.
-        double xnorm;
-        if (!(sig <= 1.0e300) || (sig < 2.2250738585072014e-308 && mxa > 0.0)) {
-            // Sum of squares overflowed or underflowed: recompute it scaled
-            // by the largest magnitude (block-uniform branch).
-            if (c == j) {
-                double part = 0.0;
+            const double dot = group_sum<RG>(part);
+            double hc;
+            if (ts) {
+                hc = sm.P[hrow * LDP + c];
+            } else {
+                double h = 0.0;
 #pragma unroll
-                for (int i = 0; i < RPT; ++i) {
-                    const int r = rg + i * RG;
-                    const double t = r >= tlo ? pr[i] / mxa : 0.0;
-                    part += t * t;
-                }
-                red_ss[rg] = part;
+                for (int i = 0; i < RPT; ++i)
+                    if (rg + i * RG == hrow) h = pr[i];
+                hc = group_sum<RG>(h);   // only the owner contributes
             }
-            __syncthreads();
-            double s2 = 0.0;
-            for (int q = 0; q < RG; ++q) s2 += red_ss[q];
-            xnorm = mxa * sqrt(s2);
-            __syncthreads();
-        } else {
-            xnorm = sqrt(sig);
-        }
-        if (xnorm != 0.0) {
-            const double h = hypot(alpha, xnorm);
-            const double beta = alpha >= 0.0 ? -h : h;
-            const double tau = (beta - alpha) / beta;
-            const double scal = 1.0 / (alpha - beta);
-            if (c == j) {
+            const double tw = tau * (hc + dot);
 #pragma unroll
-                for (int i = 0; i < RPT; ++i) {
-                    const int r = rg + i * RG;
-                    if (r >= tlo) pr[i] = pr[i] * scal;
-                    if (!ts && r == hrow) pr[i] = beta;
-                }
-                if (rg == 0) {
-                    if (ts) sm.P[hrow * LDP + j] = beta;
-                    sm.tau[j] = tau;
-                }
-            } else if (c > j) {
-                double dot = 0.0;
-                for (int q = 0; q < RG; ++q) dot += red_dot[q * IB + c];
-                const double wv = hc + scal * dot;
-                const double tw = tau * wv;
-#pragma unroll
-                for (int i = 0; i < RPT; ++i) {
-                    const int r = rg + i * RG;
-                    if (r >= tlo) pr[i] -= (xb[r] * scal) * tw;
-                    if (!ts && r == hrow) pr[i] = hc - tw;
-                }
-                if (ts && rg == 0) sm.P[hrow * LDP + c] = hc - tw;
+            for (int i = 0; i < RPT; ++i) {
+                const int r = rg + i * RG;
+                if (r >= tlo) pr[i] -= xb[r] * tw;
+                if (!ts && r == hrow) pr[i] = hc - tw;
             }
-        } else if (tid == 0) {
-            sm.tau[j] = 0.0;
+            if (ts && rg == 0) sm.P[hrow * LDP + c] = hc - tw;
         }
     }
 #pragma unroll
@@ -476,7 +514,10 @@ __device__ void panel_factor(Smem<NB, IB> &sm, int c0, bool ts)
 // T of the panel in sm.P (rows >= rlo; V with its unit diagonal explicit):
 // G = V^T V on MFMA, then column by column (compact WY, forward)
 //   T[j][j] = tau_j,  T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j].
-// Leaves T in sm.Tl and writes it to Tg (row-major ib x ib).
+// Lane i builds row i of T in registers: its entries only depend on the
+// row's earlier entries, and with the loops unrolled each new entry waits
+// for one multiply-add after the previous one.  Leaves T in sm.Tl and writes
+// it to Tg (row-major ib x ib).
 template <int NB, int IB>
 __device__ void build_t(Smem<NB, IB> &sm, int rlo, gdouble *Tg)
 {
@@ -508,17 +549,18 @@ __device__ void build_t(Smem<NB, IB> &sm, int rlo, gdouble *Tg)
     __syncthreads();
     if (tid < IB) {
         const int i = tid;
-        for (int j = 0; j < IB; ++j) {
-            double v;
-            if (i < j) {
-                double s = 0.0;
-                for (int kk = i; kk < j; ++kk) s += sm.Tl[i * IB + kk] * sm.Wa[kk * IB + j];
-                v = -sm.tau[j] * s;
-            } else {
-                v = i == j ? sm.tau[j] : 0.0;
-            }
-            sm.Tl[i * IB + j] = v;
+        double trow[IB];
+#pragma unroll
+        for (int kk = 0; kk < IB; ++kk) trow[kk] = kk == i ? sm.tau[kk] : 0.0;
+#pragma unroll
+        for (int j = 1; j < IB; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < j; ++kk) s += trow[kk] * sm.Wa[kk * IB + j];
+            if (i < j) trow[j] = -sm.tau[j] * s;
         }
+#pragma unroll
+        for (int kk = 0; kk < IB; ++kk) sm.Tl[i * IB + kk] = trow[kk];
     }
     __syncthreads();
     for (int e = tid; e < IB * IB; e += C::NT) Tg[e] = sm.Tl[e];
@@ -882,17 +924,24 @@ __device__ __forceinline__ void worker_loop(Smem<NB, IB> &sm, const SchedDev &S)
         __syncthreads();
         if (s_exit) break;
         const int64_t gid = s_gid;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // Acquire: one wave invalidates the (shared) L1 and L2 lines, the
+        // barrier holds the others back until it has.
+        if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __syncthreads();
         const int mi = find_mat(S, gid);
         const MatDev &M = S.mats[mi];
         const Grid g = make_grid(M.p, M.q, S.ns);
         const Task t = decode(g, gid - M.task_base);
         const uint64_t t0 = wall_clock64();
         run_task<NB, IB, ROLE>(sm, M, t);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // Release: every wave waits for its own stores, then wave 0 writes
+        // the L2 back and releases the successors (in program order after
+        // its fence).
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __syncthreads();
-        const int ns = nsucc(g, t);
-        for (int n = tid; n < ns; n += Cfg<NB, IB>::NT) {
+        if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const int ns = tid < 64 ? nsucc(g, t) : 0;
+        for (int n = tid; n < ns; n += 64) {
             if (S.drop_edge >= 0 && gid == S.drop_edge && n == 0) continue;
             const int64_t sl = succ(g, t, n);
             const int32_t old = __hip_atomic_fetch_add(&S.counters[M.task_base + sl], -1, __ATOMIC_ACQ_REL,
