@@ -61,7 +61,7 @@ struct DevBuf {
 // Library workspace of one device.
 struct Workspace {
     int device = -1;
-    DevBuf tiles, counters, qslot, qctl, mats, status, trace, misc;
+    DevBuf tiles, counters, qslot, qctl, mats, status, trace, misc, rows, prog;
     int *host_status = nullptr;   // pinned
     int64_t trace_events = 0;
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -516,6 +516,8 @@ extern "C" int tileqr_finalize(void)
             w->status.release();
             w->trace.release();
             w->misc.release();
+            w->rows.release();
+            w->prog.release();
             for (auto &e : w->ev)
                 if (e) (void)hipEventDestroy(e);
             if (w->host_status) (void)hipHostFree(w->host_status);
@@ -528,16 +530,6 @@ extern "C" int tileqr_finalize(void)
 }
 // ------------------------------------------- not yet wired (filled in below)
 
-extern "C" int tileqr_apply_qt(int64_t, int64_t, int64_t, const double *, int64_t, int64_t, int64_t,
-                               const double *, double *, int64_t)
-{
-    return TILEQR_EUNSUPPORTED;
-}
-extern "C" int tileqr_apply_q(int64_t, int64_t, int64_t, const double *, int64_t, int64_t, int64_t,
-                              const double *, double *, int64_t)
-{
-    return TILEQR_EUNSUPPORTED;
-}
 extern "C" int tileqr_solve_ls(int64_t, int64_t, int64_t, const double *, int64_t, const double *, int64_t,
                                double *, int64_t, const tileqr_opts *, tileqr_info *)
 {
@@ -548,4 +540,72 @@ extern "C" int tileqr_factor_batched(int64_t, const int64_t *, const int64_t *, 
                                      const tileqr_opts *)
 {
     return TILEQR_EUNSUPPORTED;
+}
+
+// ------------------------------------------------------------- applying Q
+
+namespace {
+
+// B := Q^T B or Q B with the factor (A, T) of tileqr_factor.  The factor is
+// converted to tiles, B to row blocks, and the apply kernel runs the steps.
+int apply_common(bool trans, int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, int64_t nb,
+                 int64_t ib, const double *T, double *B, int64_t ldb)
+{
+    if (m < 0) return -1;
+    if (n < 0) return -2;
+    if (nrhs < 0) return -3;
+    if (A == nullptr && m > 0 && n > 0) return -4;
+    if (lda < std::max<int64_t>(1, m)) return -5;
+    if (nb <= 0) return -6;
+    if (ib <= 0 || ib > nb || nb % ib != 0) return -7;
+    if (T == nullptr && m > 0 && n > 0) return -8;
+    if (B == nullptr && m > 0 && nrhs > 0) return -9;
+    if (ldb < std::max<int64_t>(1, m)) return -10;
+    if (m == 0 || n == 0 || nrhs == 0) return TILEQR_OK;
+    if (!tileqr_blocking_supported(nb, ib)) return TILEQR_EUNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_mu);
+    Workspace *W = workspace();
+    if (!W) return hip_fail(hipErrorNoDevice, "workspace");
+    hipStream_t st = nullptr;
+    const int p = (int)cdiv(m, nb), q = (int)cdiv(n, nb), kmax = std::min(p, q);
+    const int nstrip = (int)cdiv(nrhs, kStripWidth);
+    const int ldt = nstrip * kStripWidth;
+    int rc;
+    if ((rc = W->tiles.ensure((size_t)p * q * nb * nb * sizeof(double)))) return rc;
+    if ((rc = W->rows.ensure((size_t)p * nb * ldt * sizeof(double)))) return rc;
+    if ((rc = W->prog.ensure((size_t)kmax * sizeof(int32_t) + 64))) return rc;
+    if ((rc = W->status.ensure(256))) return rc;
+    TQ_HIP(hipMemsetAsync(W->status.ptr, 0, sizeof(int), st));
+    TQ_HIP(launch_cm2tile(A, lda, m, n, (double *)W->tiles.ptr, (int)nb, p, q, (int *)W->status.ptr, st));
+    TQ_HIP(launch_cm2rows(B, ldb, m, nrhs, (double *)W->rows.ptr, (int64_t)p * nb, ldt, st));
+    ApplyDev D;
+    D.M.tiles = (double *)W->tiles.ptr;
+    D.M.T = const_cast<double *>(T);
+    D.M.p = p;
+    D.M.q = q;
+    D.M.task_base = 0;
+    D.B = (double *)W->rows.ptr;
+    D.ldb = ldt;
+    D.nstrip = nstrip;
+    D.kmax = kmax;
+    D.prog = (int32_t *)W->prog.ptr;
+    D.status = (int32_t *)W->status.ptr;
+    D.spin_limit = (int64_t)1 << 26;
+    TQ_HIP(launch_apply((int)nb, (int)ib, D, trans, st));
+    TQ_HIP(launch_rows2cm(B, ldb, m, nrhs, (double *)W->rows.ptr, ldt, st));
+    return check_status(W, (int *)W->status.ptr, st);
+}
+
+}  // namespace
+
+extern "C" int tileqr_apply_qt(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, int64_t nb,
+                               int64_t ib, const double *T, double *B, int64_t ldb)
+{
+    return apply_common(true, m, n, nrhs, A, lda, nb, ib, T, B, ldb);
+}
+
+extern "C" int tileqr_apply_q(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, int64_t nb,
+                              int64_t ib, const double *T, double *B, int64_t ldb)
+{
+    return apply_common(false, m, n, nrhs, A, lda, nb, ib, T, B, ldb);
 }

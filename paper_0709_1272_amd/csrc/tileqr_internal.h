@@ -44,6 +44,23 @@ struct SchedDev {
     uint32_t trace_cap;
 };
 
+// Applying Q or Q^T of a finished factorisation to row blocks of B.
+struct ApplyDev {
+    MatDev M;                 // factor tiles and T
+    double *B;                // p row blocks of nb x ldb, row-major
+    int32_t ldb;              // a multiple of the strip width
+    int32_t nstrip;           // ldb / strip width
+    int32_t kmax;             // tile steps of the factorisation
+    int32_t *prog;            // [kmax] progress flags
+    int32_t *status;
+    int64_t spin_limit;
+};
+
+hipError_t launch_apply(int nb, int ib, const ApplyDev &D, bool trans, hipStream_t st);
+hipError_t launch_cm2rows(const double *B, int64_t ldb, int64_t m, int64_t nrhs, double *Bt, int64_t rows, int ldt,
+                          hipStream_t st);
+hipError_t launch_rows2cm(double *B, int64_t ldb, int64_t m, int64_t nrhs, const double *Bt, int ldt, hipStream_t st);
+
 hipError_t launch_cm2tile(const double *A, int64_t lda, int64_t m, int64_t n, double *tiles, int nb,
                           int p, int q, int *status, hipStream_t st);
 hipError_t launch_tile2cm(double *A, int64_t lda, int64_t m, int64_t n, const double *tiles, int nb,

@@ -31,6 +31,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "tileqr_dag.h"
 #include "tileqr_internal.h"
 
@@ -257,11 +259,13 @@ __device__ __forceinline__ double sum_slots(const Smem<NB, IB> &sm, int e)
 
 // Apply the block reflector of one inner panel, held in LDS (sm.P rows
 // 0..nb-1 = V, rows below `rlo` ignored; sm.Tl = T), to a strip X:
-//   W = [top +] V^T X;  W <- T^T W;  [top -= W;]  X -= V W.
+//   W = [top +] V^T X;  W <- T^T W;  [top -= W;]  X -= V W
+// (with TRANS == false, W <- T W: the reflector itself instead of its
+// transpose).
 // `top` (may be NULL) points at the ib x (16 cbn) block of the coupled upper
 // tile (the R rows the TS form also updates), row stride ldtop.
 // Three workgroup barriers; the products V^T X, T^T W and V W run on MFMA.
-template <int NB, int IB>
+template <int NB, int IB, bool TRANS = true>
 __device__ void apply_panel(Smem<NB, IB> &sm, Strip<NB, IB> &X, int rlo, gdouble *top, int ldtop, int cbn)
 {
     using C = Cfg<NB, IB>;
@@ -313,7 +317,8 @@ __device__ void apply_panel(Smem<NB, IB> &sm, Strip<NB, IB> &X, int rlo, gdouble
         d4 acc = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int kc = 0; kc < IB / 4; ++kc)
-            acc = mfma(sm.Tl[(4 * kc + g) * IB + a * 16 + n], sm.Wa[(4 * kc + g) * WS + cb * 16 + n], acc);
+            acc = mfma(TRANS ? sm.Tl[(4 * kc + g) * IB + a * 16 + n] : sm.Tl[(a * 16 + n) * IB + 4 * kc + g],
+                       sm.Wa[(4 * kc + g) * WS + cb * 16 + n], acc);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int i = a * 16 + 4 * r + g, c = cb * 16 + n;
@@ -658,55 +663,80 @@ __device__ void task_tsqrt(Smem<NB, IB> &sm, const MatDev &M, int k, int i)
     }
 }
 
+// One strip (32 columns at col0, row stride ldx) of X <- Q_kk^T X (TRANS)
+// or Q_kk X, Q_kk the block reflector of the diagonal tile tkk with T
+// blocks Tk.  Q_kk = H_0 ... H_{t-1} over the inner panels, so Q_kk^T runs
+// the panels forward with T^T and Q_kk backward with T.
+template <int NB, int IB, bool TRANS>
+__device__ void apply_diag_strip(Smem<NB, IB> &sm, const gdouble *tkk, const gdouble *Tk, gdouble *x, int ldx,
+                                 int col0)
+{
+    using C = Cfg<NB, IB>;
+    Stage<NB, IB> S;
+    const int l0 = TRANS ? 0 : C::NPAN - 1;
+    stage_load<NB, IB>(S, tkk, l0 * IB, l0 * IB, Tk + l0 * IB * IB);
+    Strip<NB, IB> X;
+    load_strip<NB, IB>(X, x, ldx, col0, CB);
+#pragma unroll 1
+    for (int q = 0; q < C::NPAN; ++q) {
+        const int l = TRANS ? q : C::NPAN - 1 - q;
+        const int c0 = l * IB;
+        stage_store<NB, IB>(sm, S, c0, true, c0);
+        __syncthreads();
+        if (q + 1 < C::NPAN) {
+            const int ln = TRANS ? l + 1 : l - 1;
+            stage_load<NB, IB>(S, tkk, ln * IB, ln * IB, Tk + ln * IB * IB);
+        }
+        apply_panel<NB, IB, TRANS>(sm, X, c0, nullptr, 0, CB);
+        __syncthreads();
+    }
+    store_strip<NB, IB>(X, x, ldx, col0, CB, 0);
+}
+
+// One strip of [top; X] <- Q_ik^T [top; X] (TRANS) or Q_ik [top; X], Q_ik
+// the coupled block reflector of tile tik (reflectors [e; V2]) with T blocks
+// Ti; `top` is the whole upper tile (its rows c0.. are the ones each inner
+// panel touches).
+template <int NB, int IB, bool TRANS>
+__device__ void apply_ts_strip(Smem<NB, IB> &sm, const gdouble *tik, const gdouble *Ti, gdouble *top, int ldtop,
+                               gdouble *x, int ldx, int col0)
+{
+    using C = Cfg<NB, IB>;
+    Stage<NB, IB> S;
+    const int l0 = TRANS ? 0 : C::NPAN - 1;
+    stage_load<NB, IB>(S, tik, l0 * IB, 0, Ti + l0 * IB * IB);
+    Strip<NB, IB> X;
+    load_strip<NB, IB>(X, x, ldx, col0, CB);
+#pragma unroll 1
+    for (int q = 0; q < C::NPAN; ++q) {
+        const int l = TRANS ? q : C::NPAN - 1 - q;
+        const int c0 = l * IB;
+        stage_store<NB, IB>(sm, S, 0, false, c0);
+        __syncthreads();
+        if (q + 1 < C::NPAN) {
+            const int ln = TRANS ? l + 1 : l - 1;
+            stage_load<NB, IB>(S, tik, ln * IB, 0, Ti + ln * IB * IB);
+        }
+        apply_panel<NB, IB, TRANS>(sm, X, 0, top + (size_t)c0 * ldtop + col0, ldtop, CB);
+        __syncthreads();
+    }
+    store_strip<NB, IB>(X, x, ldx, col0, CB, 0);
+}
+
 // DLARFB: strip s of A_kj <- Q_kk^T A_kj.
 template <int NB, int IB>
 __device__ void task_larfb(Smem<NB, IB> &sm, const MatDev &M, int k, int j, int s)
 {
-    using C = Cfg<NB, IB>;
-    const gdouble *tkk = tile_ptr(M, NB, k, k);
-    gdouble *tkj = tile_ptr(M, NB, k, j);
-    const gdouble *Tk = tblock_ptr(M, NB, IB, k, k);
-    const int col0 = s * WS;
-    Stage<NB, IB> S;
-    stage_load<NB, IB>(S, tkk, 0, 0, Tk);
-    Strip<NB, IB> X;
-    load_strip<NB, IB>(X, tkj, NB, col0, CB);
-#pragma unroll 1
-    for (int l = 0; l < C::NPAN; ++l) {
-        const int c0 = l * IB;
-        stage_store<NB, IB>(sm, S, c0, true, c0);
-        __syncthreads();
-        if (l + 1 < C::NPAN) stage_load<NB, IB>(S, tkk, c0 + IB, c0 + IB, Tk + (l + 1) * IB * IB);
-        apply_panel<NB, IB>(sm, X, c0, nullptr, 0, CB);
-        __syncthreads();
-    }
-    store_strip<NB, IB>(X, tkj, NB, col0, CB, 0);
+    apply_diag_strip<NB, IB, true>(sm, tile_ptr(M, NB, k, k), tblock_ptr(M, NB, IB, k, k), tile_ptr(M, NB, k, j), NB,
+                                   s * WS);
 }
 
 // DSSRFB: strip s of [A_kj; A_ij] <- Q_ik^T [A_kj; A_ij].
 template <int NB, int IB>
 __device__ void task_ssrfb(Smem<NB, IB> &sm, const MatDev &M, int k, int i, int j, int s)
 {
-    using C = Cfg<NB, IB>;
-    const gdouble *tik = tile_ptr(M, NB, i, k);
-    gdouble *tkj = tile_ptr(M, NB, k, j);
-    gdouble *tij = tile_ptr(M, NB, i, j);
-    const gdouble *Ti = tblock_ptr(M, NB, IB, k, i);
-    const int col0 = s * WS;
-    Stage<NB, IB> S;
-    stage_load<NB, IB>(S, tik, 0, 0, Ti);
-    Strip<NB, IB> X;
-    load_strip<NB, IB>(X, tij, NB, col0, CB);
-#pragma unroll 1
-    for (int l = 0; l < C::NPAN; ++l) {
-        const int c0 = l * IB;
-        stage_store<NB, IB>(sm, S, 0, false, c0);
-        __syncthreads();
-        if (l + 1 < C::NPAN) stage_load<NB, IB>(S, tik, c0 + IB, 0, Ti + (l + 1) * IB * IB);
-        apply_panel<NB, IB>(sm, X, 0, tkj + (size_t)c0 * NB + col0, NB, CB);
-        __syncthreads();
-    }
-    store_strip<NB, IB>(X, tij, NB, col0, CB, 0);
+    apply_ts_strip<NB, IB, true>(sm, tile_ptr(M, NB, i, k), tblock_ptr(M, NB, IB, k, i), tile_ptr(M, NB, k, j), NB,
+                                 tile_ptr(M, NB, i, j), NB, s * WS);
 }
 
 // Workers come in two roles: ROLE_PANEL runs GEQRT and TSQRT (queue
@@ -974,6 +1004,103 @@ __global__ __launch_bounds__(2 * NB) void k_worker(SchedDev S)
     else worker_loop<NB, IB, ROLE_UPDATE>(sm, S);
 }
 
+// -------------------------------------------------- applying Q and Q^T
+
+// B <- Q^T B (TRANS) or Q B for Q of a finished factorisation, B held in
+// row blocks of nb rows (row-major, leading dimension D.ldb, a multiple of
+// the strip width).  Q^T applies, for k = 0, 1, ..: Q_kk^T to block k, then
+// Q_ik^T to blocks (k, i) for i = k+1, k+2, ..  (the order in which the
+// factorisation applied them to A); Q applies the transposes in reverse.
+// Workgroup w runs step k (k = w for Q^T, kmax-1-w for Q) over its row
+// blocks in that order; before touching block i it waits until the step
+// that precedes it in the product has finished block i (progress flags in
+// D.prog).  That neighbour always has the lower workgroup index, so it was
+// dispatched first and the waits make progress; every wait is bounded.
+template <int NB, int IB, bool TRANS>
+__global__ __launch_bounds__(2 * NB) void k_apply(ApplyDev D)
+{
+    __shared__ Smem<NB, IB> sm;
+    __shared__ int s_abort;
+    const int tid = threadIdx.x;
+    const int kmax = D.kmax, p = D.M.p;
+    const int k = TRANS ? (int)blockIdx.x : kmax - 1 - (int)blockIdx.x;
+    const gdouble *tkk = tile_ptr(D.M, NB, k, k);
+    gdouble *Bk = (gdouble *)(D.B + (size_t)k * NB * D.ldb);
+    const int nrow = p - k;   // blocks k .. p-1
+    if (*D.status != 0) return;   // input rejected (non-finite factor)
+    for (int q = 0; q < nrow; ++q) {
+        // Q^T: k, k+1, .., p-1.   Q: p-1, .., k+1, then k.
+        const int r = TRANS ? k + q : (q + 1 < nrow ? p - 1 - q : k);
+        const bool wait = TRANS ? k > 0 : (k + 1 < kmax && r != k);
+        if (tid == 0) {
+            int abort = 0;
+            if (wait) {
+                const int *flag = &D.prog[TRANS ? k - 1 : k + 1];
+                int64_t spins = 0;
+                for (;;) {
+                    const int v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    if (TRANS ? v >= r : v <= r) break;
+                    if (__hip_atomic_load(D.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                        ++spins > D.spin_limit) {
+                        __hip_atomic_fetch_or(D.status, STATUS_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        abort = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(2);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+            s_abort = abort;
+        }
+        __syncthreads();
+        if (s_abort) return;
+        gdouble *Br = (gdouble *)(D.B + (size_t)r * NB * D.ldb);
+#pragma unroll 1
+        for (int st = 0; st < D.nstrip; ++st) {
+            if (r == k)
+                apply_diag_strip<NB, IB, TRANS>(sm, tkk, tblock_ptr(D.M, NB, IB, k, k), Bk, D.ldb, st * WS);
+            else
+                apply_ts_strip<NB, IB, TRANS>(sm, tile_ptr(D.M, NB, r, k), tblock_ptr(D.M, NB, IB, k, r), Bk, D.ldb,
+                                              Br, D.ldb, st * WS);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __syncthreads();
+        if (tid == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __hip_atomic_store(&D.prog[k], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
+// Progress flags before an apply: Q^T steps start at k-1 (nothing done),
+// Q steps at p (nothing done, rows are taken in descending order).
+__global__ void k_apply_init(int *prog, int kmax, int p, int trans)
+{
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < kmax; k += gridDim.x * blockDim.x)
+        prog[k] = trans ? k - 1 : p;
+}
+
+// Column-major (B, ldb) m x nrhs <-> row blocks: Bt[(R) * ldt + c], rows
+// R < p nb and columns c < ldt; padding rows and columns are zero.
+__global__ void k_cm2rows(const double *B, int64_t ldb, int64_t m, int64_t nrhs, double *Bt, int64_t rows,
+                          int ldt)
+{
+    const int64_t total = rows * ldt;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t R = e / ldt, c = e % ldt;
+        Bt[e] = (R < m && c < nrhs) ? B[c * ldb + R] : 0.0;
+    }
+}
+
+__global__ void k_rows2cm(double *B, int64_t ldb, int64_t m, int64_t nrhs, const double *Bt, int ldt)
+{
+    const int64_t total = m * nrhs;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t c = e / m, R = e % m;
+        B[c * ldb + R] = Bt[R * ldt + c];
+    }
+}
+
 // ------------------------------------------------------ layout conversion
 
 // Column-major (A, lda) -> zero-padded row-major tiles, 64 x 64 blocks via
@@ -1110,6 +1237,44 @@ hipError_t launch_factor_serial(int nb, int ib, const MatDev &M, const int *stat
 #define TQ_CALL(NB, IB) return serial_impl<NB, IB>(M, status, st)
     TQ_DISPATCH(nb, ib, TQ_CALL);
 #undef TQ_CALL
+}
+
+template <int NB, int IB>
+static hipError_t apply_impl(const ApplyDev &D, bool trans, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_apply_init, dim3(1), dim3(256), 0, st, D.prog, D.kmax, D.M.p, trans ? 1 : 0);
+    if (trans)
+        hipLaunchKernelGGL((k_apply<NB, IB, true>), dim3(D.kmax), dim3(Cfg<NB, IB>::NT), 0, st, D);
+    else
+        hipLaunchKernelGGL((k_apply<NB, IB, false>), dim3(D.kmax), dim3(Cfg<NB, IB>::NT), 0, st, D);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply(int nb, int ib, const ApplyDev &D, bool trans, hipStream_t st)
+{
+    if (D.kmax <= 0) return hipSuccess;
+#define TQ_CALL(NB, IB) return apply_impl<NB, IB>(D, trans, st)
+    TQ_DISPATCH(nb, ib, TQ_CALL);
+#undef TQ_CALL
+}
+
+hipError_t launch_cm2rows(const double *B, int64_t ldb, int64_t m, int64_t nrhs, double *Bt, int64_t rows, int ldt,
+                          hipStream_t st)
+{
+    const int64_t total = rows * ldt;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 8192);
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cm2rows, dim3((unsigned)blocks), dim3(256), 0, st, B, ldb, m, nrhs, Bt, rows, ldt);
+    return hipGetLastError();
+}
+
+hipError_t launch_rows2cm(double *B, int64_t ldb, int64_t m, int64_t nrhs, const double *Bt, int ldt, hipStream_t st)
+{
+    const int64_t total = m * nrhs;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 8192);
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rows2cm, dim3((unsigned)blocks), dim3(256), 0, st, B, ldb, m, nrhs, Bt, ldt);
+    return hipGetLastError();
 }
 
 hipError_t launch_sched_init(const SchedDev &S, hipStream_t st)
