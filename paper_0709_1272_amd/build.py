@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtileqr.so")
-SOURCES = ["tileqr_kernels.hip", "tileqr_api.cpp"]
+SOURCES = ["tileqr_kernels.hip", "tileqr_solve.hip", "tileqr_api.cpp"]
 ARCH = os.environ.get("TILEQR_ARCH", "gfx950")
 
 

@@ -61,7 +61,8 @@ struct DevBuf {
 // Library workspace of one device.
 struct Workspace {
     int device = -1;
-    DevBuf tiles, counters, qslot, qctl, mats, status, trace, misc, rows, prog;
+    DevBuf tiles, counters, qslot, qctl, mats, status, trace, misc, rows, prog, tws, solve, part;
+    double *host_small = nullptr;   // pinned, for norms read back by the solver
     int *host_status = nullptr;   // pinned
     int64_t trace_events = 0;
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -86,7 +87,8 @@ Workspace *workspace()
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) w->num_cu = prop.multiProcessorCount;
     int khz = 0;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess) w->wall_hz = khz * 1e3;
-    if (hipHostMalloc((void **)&w->host_status, 64, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&w->host_status, 64, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&w->host_small, 4096 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         delete w;
         return nullptr;
     }
@@ -296,6 +298,8 @@ extern "C" int tileqr_dag_selfcheck(int64_t p, int64_t q, int64_t strips, int64_
 
 namespace {
 
+bool mixed_supported(int precision) { return precision == TILEQR_FP64; }
+
 int check_status(Workspace *W, int *dstatus, hipStream_t st)
 {
     TQ_HIP(hipMemcpyAsync(W->host_status, dstatus, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -303,6 +307,7 @@ int check_status(Workspace *W, int *dstatus, hipStream_t st)
     const int s = *W->host_status;
     if (s & STATUS_NONFINITE) return TILEQR_ENONFINITE;
     if (s & STATUS_TIMEOUT) return TILEQR_ETIMEOUT;
+    if (s & STATUS_SINGULAR) return TILEQR_ESINGULAR;
     return TILEQR_OK;
 }
 
@@ -518,6 +523,10 @@ extern "C" int tileqr_finalize(void)
             w->misc.release();
             w->rows.release();
             w->prog.release();
+            w->tws.release();
+            w->solve.release();
+            w->part.release();
+            if (w->host_small) (void)hipHostFree(w->host_small);
             for (auto &e : w->ev)
                 if (e) (void)hipEventDestroy(e);
             if (w->host_status) (void)hipHostFree(w->host_status);
@@ -530,11 +539,6 @@ extern "C" int tileqr_finalize(void)
 }
 // ------------------------------------------- not yet wired (filled in below)
 
-extern "C" int tileqr_solve_ls(int64_t, int64_t, int64_t, const double *, int64_t, const double *, int64_t,
-                               double *, int64_t, const tileqr_opts *, tileqr_info *)
-{
-    return TILEQR_EUNSUPPORTED;
-}
 extern "C" int tileqr_factor_batched(int64_t, const int64_t *, const int64_t *, double *const *,
                                      const int64_t *, const int64_t *, const int64_t *, double *const *,
                                      const tileqr_opts *)
@@ -545,6 +549,27 @@ extern "C" int tileqr_factor_batched(int64_t, const int64_t *, const int64_t *, 
 // ------------------------------------------------------------- applying Q
 
 namespace {
+
+// Q^T or Q on row blocks `rows` (leading dimension ldt) with the factor
+// already in W->tiles.  W->prog must hold min(p, q) flags.
+hipError_t apply_rows(Workspace *W, int nb, int ib, int p, int q, const double *T, double *rows, int ldt, bool trans,
+                      hipStream_t st)
+{
+    ApplyDev D;
+    D.M.tiles = (double *)W->tiles.ptr;
+    D.M.T = const_cast<double *>(T);
+    D.M.p = p;
+    D.M.q = q;
+    D.M.task_base = 0;
+    D.B = rows;
+    D.ldb = ldt;
+    D.nstrip = ldt / kStripWidth;
+    D.kmax = std::min(p, q);
+    D.prog = (int32_t *)W->prog.ptr;
+    D.status = (int32_t *)W->status.ptr;
+    D.spin_limit = (int64_t)1 << 26;
+    return launch_apply(nb, ib, D, trans, st);
+}
 
 // B := Q^T B or Q B with the factor (A, T) of tileqr_factor.  The factor is
 // converted to tiles, B to row blocks, and the apply kernel runs the steps.
@@ -578,20 +603,7 @@ int apply_common(bool trans, int64_t m, int64_t n, int64_t nrhs, const double *A
     TQ_HIP(hipMemsetAsync(W->status.ptr, 0, sizeof(int), st));
     TQ_HIP(launch_cm2tile(A, lda, m, n, (double *)W->tiles.ptr, (int)nb, p, q, (int *)W->status.ptr, st));
     TQ_HIP(launch_cm2rows(B, ldb, m, nrhs, (double *)W->rows.ptr, (int64_t)p * nb, ldt, st));
-    ApplyDev D;
-    D.M.tiles = (double *)W->tiles.ptr;
-    D.M.T = const_cast<double *>(T);
-    D.M.p = p;
-    D.M.q = q;
-    D.M.task_base = 0;
-    D.B = (double *)W->rows.ptr;
-    D.ldb = ldt;
-    D.nstrip = nstrip;
-    D.kmax = kmax;
-    D.prog = (int32_t *)W->prog.ptr;
-    D.status = (int32_t *)W->status.ptr;
-    D.spin_limit = (int64_t)1 << 26;
-    TQ_HIP(launch_apply((int)nb, (int)ib, D, trans, st));
+    TQ_HIP(apply_rows(W, (int)nb, (int)ib, p, q, T, (double *)W->rows.ptr, ldt, trans, st));
     TQ_HIP(launch_rows2cm(B, ldb, m, nrhs, (double *)W->rows.ptr, ldt, st));
     return check_status(W, (int *)W->status.ptr, st);
 }
@@ -608,4 +620,209 @@ extern "C" int tileqr_apply_q(int64_t m, int64_t n, int64_t nrhs, const double *
                               int64_t ib, const double *T, double *B, int64_t ldb)
 {
     return apply_common(false, m, n, nrhs, A, lda, nb, ib, T, B, ldb);
+}
+
+// ------------------------------------------------------------ least squares
+
+namespace {
+
+// Row-block buffers of the solver, each p nb x ldt doubles.
+enum { SB = 0, SX, SR, SF, SG, SS, SXB, SNUM };
+
+struct SolveCtx {
+    Workspace *W;
+    hipStream_t st;
+    const double *A;
+    int64_t lda, m, n;
+    int nrhs, ldt, nb, ib, p, q;
+    double *buf[SNUM];
+    double *T;
+    double *part;
+    int64_t part_cap;
+    double *small;   // device: norms
+};
+
+// eta_v = ||A^T (b - A x)||_2 / (||A||_F (||A||_F ||x||_2 + ||b||_2)) per column;
+// returns the largest.  Writes the residual into buf[SS].
+int eta_of(SolveCtx &c, double normA, const double *normb, double *eta_cols)
+{
+    Workspace *W = c.W;
+    double *S = c.buf[SS];
+    TQ_HIP(launch_axpy_rows(c.buf[SB], S, c.ldt, c.m, c.nrhs, 2, c.st));
+    TQ_HIP(launch_gemv_n(c.A, c.lda, c.m, c.n, c.buf[SX], c.ldt, c.nrhs, -1.0, 1.0, S, c.part, c.part_cap, c.st));
+    double *AtS = c.buf[SF];   // scratch n x nrhs (SF is recomputed before use)
+    TQ_HIP(launch_gemv_t(c.A, c.lda, c.m, c.n, S, c.ldt, c.nrhs, 1.0, 0.0, AtS, c.st));
+    double *dev = c.small;
+    TQ_HIP(launch_colsq(AtS, c.ldt, c.n, c.nrhs, dev + 1024, dev, c.st));
+    TQ_HIP(launch_colsq(c.buf[SX], c.ldt, c.n, c.nrhs, dev + 1024, dev + 64, c.st));
+    TQ_HIP(hipMemcpyAsync(W->host_small, dev, 128 * sizeof(double), hipMemcpyDeviceToHost, c.st));
+    TQ_HIP(hipStreamSynchronize(c.st));
+    double worst = 0.0;
+    for (int v = 0; v < c.nrhs; ++v) {
+        const double num = std::sqrt(W->host_small[v]);
+        const double den = normA * (normA * std::sqrt(W->host_small[64 + v]) + normb[v]);
+        const double e = den > 0.0 ? num / den : (num > 0.0 ? INFINITY : 0.0);
+        eta_cols[v] = e;
+        worst = std::max(worst, e);
+    }
+    return 0;
+}
+
+}  // namespace
+
+extern "C" int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
+                               int64_t ldb, double *X, int64_t ldx, const tileqr_opts *opts, tileqr_info *info)
+{
+    if (m < 0) return -1;
+    if (n < 0 || n > m) return -2;
+    if (nrhs < 0 || nrhs > 64) return -3;
+    if (A == nullptr && m > 0 && n > 0) return -4;
+    if (lda < std::max<int64_t>(1, m)) return -5;
+    if (B == nullptr && m > 0 && nrhs > 0) return -6;
+    if (ldb < std::max<int64_t>(1, m)) return -7;
+    if (X == nullptr && n > 0 && nrhs > 0) return -8;
+    if (ldx < std::max<int64_t>(1, n)) return -9;
+    tileqr_opts o;
+    tileqr_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.max_iter < 0 || o.max_iter > 64 || !(o.tol >= 0.0)) return -10;
+    if (o.precision < TILEQR_FP64 || o.precision > TILEQR_BF16X3) return -10;
+    if (info) {
+        std::memset(info, 0, sizeof *info);
+    }
+    if (n == 0 || nrhs == 0) return TILEQR_OK;
+    int64_t nb = o.nb, ib = o.ib;
+    if (nb == 0 || ib == 0) tileqr_choose_blocking(m, n, o.precision, &nb, &ib);
+    if (!tileqr_blocking_supported(nb, ib)) return TILEQR_EUNSUPPORTED;
+    if (o.precision != TILEQR_FP64 && !mixed_supported(o.precision)) return TILEQR_EUNSUPPORTED;
+
+    std::lock_guard<std::mutex> lock(g_mu);
+    Workspace *W = workspace();
+    if (!W) return hip_fail(hipErrorNoDevice, "workspace");
+    hipStream_t st = (hipStream_t)o.stream;
+    const int p = (int)cdiv(m, nb), q = (int)cdiv(n, nb);
+    const int ldt = (int)cdiv(nrhs, kStripWidth) * kStripWidth;
+    const size_t slot = (size_t)p * nb * ldt;
+    int rc;
+    if ((rc = W->tiles.ensure((size_t)p * q * nb * nb * sizeof(double)))) return rc;
+    if ((rc = W->tws.ensure(std::max<size_t>(1, tileqr_t_size(m, n, nb, ib)) * sizeof(double)))) return rc;
+    if ((rc = W->solve.ensure(SNUM * slot * sizeof(double)))) return rc;
+    const int64_t part_cap = std::max<int64_t>(m * 32 * 16, 1 << 20);
+    if ((rc = W->part.ensure((size_t)part_cap * sizeof(double)))) return rc;
+    if ((rc = W->misc.ensure(4096 * sizeof(double)))) return rc;
+    if ((rc = W->prog.ensure((size_t)std::min(p, q) * sizeof(int32_t) + 64))) return rc;
+    if ((rc = W->status.ensure(256))) return rc;
+    if (!W->ev[0])
+        for (auto &e : W->ev) TQ_HIP(hipEventCreate(&e));
+
+    SolveCtx c;
+    c.W = W;
+    c.st = st;
+    c.A = A;
+    c.lda = lda;
+    c.m = m;
+    c.n = n;
+    c.nrhs = (int)nrhs;
+    c.ldt = ldt;
+    c.nb = (int)nb;
+    c.ib = (int)ib;
+    c.p = p;
+    c.q = q;
+    for (int i = 0; i < SNUM; ++i) c.buf[i] = (double *)W->solve.ptr + i * slot;
+    c.T = (double *)W->tws.ptr;
+    c.part = (double *)W->part.ptr;
+    c.part_cap = part_cap;
+    c.small = (double *)W->misc.ptr;
+    int *dstatus = (int *)W->status.ptr;
+
+    // Factor a copy of A (A itself is never written).
+    TQ_HIP(hipEventRecord(W->ev[0], st));
+    TQ_HIP(hipMemsetAsync(dstatus, 0, sizeof(int), st));
+    TQ_HIP(launch_cm2tile(A, lda, m, n, (double *)W->tiles.ptr, (int)nb, p, q, dstatus, st));
+    tileqr_opts fo = o;
+    fo.flags &= ~(unsigned)(TILEQR_FLAG_ASYNC | TILEQR_FLAG_TIMING | TILEQR_FLAG_TRACE);
+    if ((rc = run_factor(W, (int)nb, (int)ib, p, q, c.T, fo, st, nullptr))) return rc;
+    TQ_HIP(hipEventRecord(W->ev[1], st));
+    if ((rc = check_status(W, dstatus, st))) return rc;
+
+    // x0 = R^{-1} (Q^T b)(0:n),  r0 = b - A x0.
+    TQ_HIP(hipMemsetAsync(W->solve.ptr, 0, SNUM * slot * sizeof(double), st));
+    TQ_HIP(launch_cm2rows(B, ldb, m, nrhs, c.buf[SB], (int64_t)p * nb, ldt, st));
+    TQ_HIP(launch_axpy_rows(c.buf[SB], c.buf[SX], ldt, m, c.nrhs, 2, st));
+    TQ_HIP(apply_rows(W, c.nb, c.ib, p, q, c.T, c.buf[SX], ldt, true, st));
+    TQ_HIP(launch_trsm(c.nb, (double *)W->tiles.ptr, p, n, c.buf[SX], ldt, true, dstatus, st));
+    // zero the rows n.. of x (they held (Q^T b)(n:m))
+    TQ_HIP(hipMemsetAsync(c.buf[SX] + (size_t)n * ldt, 0, (size_t)(p * nb - n) * ldt * sizeof(double), st));
+    TQ_HIP(launch_axpy_rows(c.buf[SB], c.buf[SR], ldt, m, c.nrhs, 2, st));
+    TQ_HIP(launch_gemv_n(A, lda, m, n, c.buf[SX], ldt, c.nrhs, -1.0, 1.0, c.buf[SR], c.part, part_cap, st));
+    if ((rc = check_status(W, dstatus, st))) return rc;
+
+    // Norms fixed for the whole refinement.
+    TQ_HIP(launch_frob2(A, lda, m, n, c.small + 1024, c.small + 128, st));
+    TQ_HIP(launch_colsq(c.buf[SB], ldt, m, c.nrhs, c.small + 1024, c.small + 192, st));
+    TQ_HIP(hipMemcpyAsync(W->host_small + 128, c.small + 128, 128 * sizeof(double), hipMemcpyDeviceToHost, st));
+    TQ_HIP(hipStreamSynchronize(st));
+    const double normA = std::sqrt(W->host_small[128]);
+    double normb[64], eta_cols[64];
+    for (int v = 0; v < c.nrhs; ++v) normb[v] = std::sqrt(W->host_small[192 + v]);
+
+    double eta = 0.0;
+    if ((rc = eta_of(c, normA, normb, eta_cols))) return rc;
+    for (int v = 0; v < c.nrhs; ++v) eta = std::max(eta, eta_cols[v]);
+    double best = eta;
+    TQ_HIP(launch_axpy_rows(c.buf[SX], c.buf[SXB], ldt, n, c.nrhs, 2, st));
+    if (info) info->eta_hist[0] = eta;
+    int it = 0, stall = 0;
+    double prev = eta;
+    // Refinement of the augmented system [I A; A^T 0][r; x] = [b; 0]
+    // (residuals in FP64 on the original A, corrections through the factors).
+    while (eta > o.tol && it < o.max_iter) {
+        ++it;
+        double *F = c.buf[SF], *G = c.buf[SG];
+        // f = b - r - A x ;  g = -A^T r
+        TQ_HIP(launch_axpy_rows(c.buf[SB], F, ldt, m, c.nrhs, 2, st));
+        TQ_HIP(launch_axpy_rows(c.buf[SR], F, ldt, m, c.nrhs, 0, st));   // F = R - F = r - b
+        TQ_HIP(launch_axpy_rows(nullptr, F, ldt, m, c.nrhs, 3, st));     // F = b - r
+        TQ_HIP(launch_gemv_n(A, lda, m, n, c.buf[SX], ldt, c.nrhs, -1.0, 1.0, F, c.part, part_cap, st));
+        TQ_HIP(launch_gemv_t(A, lda, m, n, c.buf[SR], ldt, c.nrhs, -1.0, 0.0, G, st));
+        // [f1; f2] = Q^T f ;  d1 = R^{-T} g ;  dx = R^{-1} (f1 - d1) ;  dr = Q [d1; f2]
+        TQ_HIP(apply_rows(W, c.nb, c.ib, p, q, c.T, F, ldt, true, st));
+        TQ_HIP(launch_trsm(c.nb, (double *)W->tiles.ptr, p, n, G, ldt, false, dstatus, st));
+        double *DX = c.buf[SS];
+        TQ_HIP(launch_axpy_rows(F, DX, ldt, n, c.nrhs, 2, st));
+        TQ_HIP(launch_axpy_rows(G, DX, ldt, n, c.nrhs, 0, st));          // DX = G - DX = d1 - f1
+        TQ_HIP(launch_axpy_rows(nullptr, DX, ldt, n, c.nrhs, 3, st));    // DX = f1 - d1
+        TQ_HIP(hipMemsetAsync(DX + (size_t)n * ldt, 0, (size_t)(p * nb - n) * ldt * sizeof(double), st));
+        TQ_HIP(launch_trsm(c.nb, (double *)W->tiles.ptr, p, n, DX, ldt, true, dstatus, st));
+        TQ_HIP(launch_axpy_rows(DX, c.buf[SX], ldt, n, c.nrhs, 1, st));
+        TQ_HIP(launch_axpy_rows(G, F, ldt, n, c.nrhs, 2, st));             // F = [d1; f2]
+        TQ_HIP(apply_rows(W, c.nb, c.ib, p, q, c.T, F, ldt, false, st));
+        TQ_HIP(launch_axpy_rows(F, c.buf[SR], ldt, m, c.nrhs, 1, st));
+        if ((rc = eta_of(c, normA, normb, eta_cols))) return rc;
+        eta = 0.0;
+        for (int v = 0; v < c.nrhs; ++v) eta = std::max(eta, eta_cols[v]);
+        if (info && it < 65) info->eta_hist[it] = eta;
+        if (eta < best) {
+            best = eta;
+            TQ_HIP(launch_axpy_rows(c.buf[SX], c.buf[SXB], ldt, n, c.nrhs, 2, st));
+        }
+        stall = eta > 0.5 * prev ? stall + 1 : 0;
+        prev = eta;
+        if (stall >= 2) break;
+    }
+    TQ_HIP(launch_rows2cm(X, ldx, n, nrhs, c.buf[SXB], ldt, st));
+    TQ_HIP(hipEventRecord(W->ev[2], st));
+    rc = check_status(W, dstatus, st);
+    if (info) {
+        info->iterations = it;
+        info->converged = best <= o.tol;
+        info->eta = best;
+        info->nb = nb;
+        info->ib = ib;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, W->ev[0], W->ev[1]) == hipSuccess) info->ms_factor = ms;
+        if (hipEventElapsedTime(&ms, W->ev[0], W->ev[2]) == hipSuccess) info->ms_total = ms;
+    }
+    if (rc) return rc;
+    return best <= o.tol ? TILEQR_OK : TILEQR_ENOCONV;
 }

@@ -8,7 +8,8 @@ namespace tq {
 
 enum : int {
     STATUS_NONFINITE = 1,   // NaN or Inf in the input
-    STATUS_TIMEOUT = 2      // scheduler watchdog fired
+    STATUS_TIMEOUT = 2,     // scheduler watchdog fired
+    STATUS_SINGULAR = 4     // exact zero on the diagonal of R (triangular solve)
 };
 
 // One matrix as the kernels see it.
@@ -60,6 +61,24 @@ hipError_t launch_apply(int nb, int ib, const ApplyDev &D, bool trans, hipStream
 hipError_t launch_cm2rows(const double *B, int64_t ldb, int64_t m, int64_t nrhs, double *Bt, int64_t rows, int ldt,
                           hipStream_t st);
 hipError_t launch_rows2cm(double *B, int64_t ldb, int64_t m, int64_t nrhs, const double *Bt, int ldt, hipStream_t st);
+
+// Triangular solves with the tiled R on row blocks C (ldt a multiple of 32):
+// R X = C (upper) or R^T X = C, n = order of R.
+hipError_t launch_trsm(int nb, const double *tiles, int p, int64_t n, double *C, int ldt, bool upper, int *status,
+                       hipStream_t st);
+// Y = alpha A X + beta Y (column-major A, m x n; X, Y row blocks); `part`
+// is scratch of part_cap doubles for the deterministic column-slice sums.
+hipError_t launch_gemv_n(const double *A, int64_t lda, int64_t m, int64_t n, const double *X, int ldt, int nrhs,
+                         double alpha, double beta, double *Y, double *part, int64_t part_cap, hipStream_t st);
+// Y = alpha A^T R + beta Y.
+hipError_t launch_gemv_t(const double *A, int64_t lda, int64_t m, int64_t n, const double *R, int ldt, int nrhs,
+                         double alpha, double beta, double *Y, hipStream_t st);
+// out[v] = sum of squares of column v of Y (rows < m); part: 256 * nrhs doubles.
+hipError_t launch_colsq(const double *Y, int ldt, int64_t m, int nrhs, double *part, double *out, hipStream_t st);
+// out[0] = ||A||_F^2; part: 256 doubles.
+hipError_t launch_frob2(const double *A, int64_t lda, int64_t m, int64_t n, double *part, double *out, hipStream_t st);
+// op 0: Y = X - Y, 1: Y += X, 2: Y = X, 3: Y = -Y (rows < m, columns < nrhs).
+hipError_t launch_axpy_rows(const double *X, double *Y, int ldt, int64_t m, int nrhs, int op, hipStream_t st);
 
 hipError_t launch_cm2tile(const double *A, int64_t lda, int64_t m, int64_t n, double *tiles, int nb,
                           int p, int q, int *status, hipStream_t st);

@@ -1,0 +1,372 @@
+// Triangular solves with the tiled R, and the FP64 matrix-vector products and
+// norms the least-squares solver and its refinement need.
+//
+// R lives in the factorisation's tiles (tile (i, j) at tiles + (j p + i) nb^2,
+// row-major inside, R in the upper triangle of tiles i <= j).  Right-hand
+// sides live in row blocks: block i holds rows [i nb, (i+1) nb) of a row-major
+// array with leading dimension ldt (a multiple of 32).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "tileqr_internal.h"
+
+namespace tq {
+
+namespace {
+
+constexpr int SW = 32;   // columns per strip of right-hand sides
+
+__device__ __forceinline__ const double *tile_at(const double *tiles, int p, int nb, int i, int j)
+{
+    return tiles + ((size_t)j * p + i) * (size_t)nb * nb;
+}
+
+}  // namespace
+
+// Solve with the diagonal tile k of R, in place on row block k of C:
+//   upper == true:  R_kk X = C_k (back substitution),
+//   upper == false: R_kk^T X = C_k (forward substitution).
+// The tile is taken in 32 x 32 diagonal blocks (bottom-up for R, top-down for
+// R^T); a block is solved by half-waves, one right-hand side per half-wave
+// with one row per lane, and the rest of the tile is then updated with it.
+// Rows at or beyond `n` (padding) get X = 0; an exact zero on the diagonal of
+// a real row sets STATUS_SINGULAR.
+template <int NB>
+__global__ __launch_bounds__(2 * NB) void k_trsm_diag(const double *tiles, int p, int64_t n, int k, double *C,
+                                                      int ldt, int upper, int *status)
+{
+    constexpr int NT = 2 * NB, NBLK = NB / 32;
+    __shared__ double X[NB][SW + 1];
+    __shared__ double Rb[32][33];
+    const int tid = threadIdx.x, lane = tid & 63, hw = tid >> 5;   // half-wave index
+    const double *R = tile_at(tiles, p, NB, k, k);
+    double *Ck = C + (size_t)k * NB * ldt;
+    for (int s0 = 0; s0 < ldt; s0 += SW) {
+        for (int e = tid; e < NB * SW; e += NT) X[e / SW][e % SW] = Ck[(size_t)(e / SW) * ldt + s0 + e % SW];
+        __syncthreads();
+        for (int bb = 0; bb < NBLK; ++bb) {
+            const int b = upper ? NBLK - 1 - bb : bb;
+            for (int e = tid; e < 32 * 32; e += NT) {
+                const int i = e / 32, j = e % 32;
+                Rb[i][j] = upper ? R[(size_t)(b * 32 + i) * NB + b * 32 + j] : R[(size_t)(b * 32 + j) * NB + b * 32 + i];
+            }
+            __syncthreads();
+            const int i = lane & 31;
+            const int64_t grow = (int64_t)k * NB + b * 32 + i;
+            for (int c = hw; c < SW; c += NT / 32) {
+                double x = X[b * 32 + i][c];
+                for (int q = 0; q < 32; ++q) {
+                    const int r = upper ? 31 - q : q;
+                    const int64_t gr = (int64_t)k * NB + b * 32 + r;
+                    double xr = 0.0;
+                    if (gr < n) {
+                        const double d = Rb[r][r];
+                        xr = __shfl(x, r, 32) / d;
+                    }
+                    if (i == r) x = xr;
+                    else if (upper ? i < r : i > r) x -= Rb[i][r] * xr;
+                }
+                X[b * 32 + i][c] = grow < n ? x : 0.0;
+            }
+            if (tid < 32 && (int64_t)k * NB + b * 32 + tid < n && Rb[tid][tid] == 0.0)
+                atomicOr(status, STATUS_SINGULAR);
+            __syncthreads();
+            // Rows outside the block that depend on it.
+            const int r0 = upper ? 0 : (b + 1) * 32, r1 = upper ? b * 32 : NB;
+            for (int e = tid; e < (r1 - r0) * SW; e += NT) {
+                const int row = r0 + e / SW, c = e % SW;
+                double acc = X[row][c];
+                for (int j = 0; j < 32; ++j) {
+                    const double rv = upper ? R[(size_t)row * NB + b * 32 + j] : R[(size_t)(b * 32 + j) * NB + row];
+                    acc -= rv * X[b * 32 + j][c];
+                }
+                X[row][c] = acc;
+            }
+            __syncthreads();
+        }
+        for (int e = tid; e < NB * SW; e += NT) Ck[(size_t)(e / SW) * ldt + s0 + e % SW] = X[e / SW][e % SW];
+        __syncthreads();
+    }
+}
+
+// Update the other row blocks with the solved block k:
+//   upper:  C_i -= R_ik X_k        for i = blockIdx.x (< k),
+//   !upper: C_i -= R_ki^T X_k      for i = k + 1 + blockIdx.x.
+// One strip of 32 right-hand sides per blockIdx.y; X_k and 32-wide chunks of
+// the R tile are staged in LDS; each thread owns a 4 x 4 block of outputs.
+template <int NB>
+__global__ __launch_bounds__(2 * NB) void k_trsm_update(const double *tiles, int p, int k, double *C, int ldt,
+                                                        int upper)
+{
+    constexpr int NT = 2 * NB;
+    __shared__ double X[NB][SW + 1];
+    __shared__ double Rc[NB][33];
+    const int tid = threadIdx.x;
+    const int i = upper ? (int)blockIdx.x : k + 1 + (int)blockIdx.x;
+    const int s0 = blockIdx.y * SW;
+    const double *Rt = upper ? tile_at(tiles, p, NB, i, k) : tile_at(tiles, p, NB, k, i);
+    const double *Ck = C + (size_t)k * NB * ldt;
+    double *Ci = C + (size_t)i * NB * ldt;
+    for (int e = tid; e < NB * SW; e += NT) X[e / SW][e % SW] = Ck[(size_t)(e / SW) * ldt + s0 + e % SW];
+    const int rgp = tid / 8, cg = tid % 8;   // rows 4 rgp .. +3, columns 4 cg .. +3
+    double acc[4][4] = {};
+    for (int kc = 0; kc < NB; kc += 32) {
+        __syncthreads();
+        // Rc[row][kk] = op(R)[row][kc + kk]
+        for (int e = tid; e < NB * 32; e += NT) {
+            const int row = upper ? e / 32 : e % NB, kk = upper ? e % 32 : e / NB;
+            Rc[row][kk] = upper ? Rt[(size_t)row * NB + kc + kk] : Rt[(size_t)(kc + kk) * NB + row];
+        }
+        __syncthreads();
+        for (int kk = 0; kk < 32; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                a[u] = Rc[4 * rgp + u][kk];
+                b[u] = X[kc + kk][4 * cg + u];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Ci[(size_t)(4 * rgp + u) * ldt + s0 + 4 * cg + v] -= acc[u][v];
+}
+
+// Y (row-major rows, leading dimension ldt, m x nrhs) <- alpha A X + beta Y
+// for column-major A (m x n, lda) and X in row blocks (n x nrhs, ldt).  A is
+// read once: each workgroup takes 256 rows and a slice of the columns; the
+// per-slice partial sums are written to `part` and reduced in a second pass
+// in slice order (deterministic).
+__global__ __launch_bounds__(256) void k_gemv_n_part(const double *A, int64_t lda, int64_t m, int64_t n,
+                                                     const double *X, int ldt, int nrhs, int64_t cols_per_slice,
+                                                     double *part)
+{
+    __shared__ double xs[64][SW];
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t c0 = (int64_t)blockIdx.y * cols_per_slice, c1 = std::min<int64_t>(n, c0 + cols_per_slice);
+    const int nr = std::min(nrhs, SW);
+    double acc[SW];
+#pragma unroll
+    for (int v = 0; v < SW; ++v) acc[v] = 0.0;
+    for (int64_t cb = c0; cb < c1; cb += 64) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < 64 * SW; e += 256) {
+            const int64_t c = cb + e / SW;
+            xs[e / SW][e % SW] = (c < c1 && e % SW < nr) ? X[c * ldt + e % SW] : 0.0;
+        }
+        __syncthreads();
+        if (row < m) {
+            const int cn = (int)std::min<int64_t>(64, c1 - cb);
+            for (int j = 0; j < cn; ++j) {
+                const double a = A[(cb + j) * lda + row];
+#pragma unroll
+                for (int v = 0; v < SW; ++v) acc[v] += a * xs[j][v];
+            }
+        }
+    }
+    if (row < m)
+        for (int v = 0; v < nr; ++v) part[((int64_t)blockIdx.y * m + row) * SW + v] = acc[v];
+}
+
+__global__ void k_gemv_n_sum(const double *part, int nslice, int64_t m, int nrhs, double alpha, double beta, double *Y,
+                             int ldt)
+{
+    const int64_t total = m * nrhs;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = e / nrhs;
+        const int v = (int)(e % nrhs);
+        double s = 0.0;
+        for (int q = 0; q < nslice; ++q) s += part[((int64_t)q * m + row) * SW + v];
+        Y[row * ldt + v] = alpha * s + (beta == 0.0 ? 0.0 : beta * Y[row * ldt + v]);
+    }
+}
+
+// Y (n x nrhs rows) <- alpha A^T R + beta Y: one workgroup per column of A,
+// its threads stride over the rows and reduce in a fixed tree.
+__global__ __launch_bounds__(256) void k_gemv_t(const double *A, int64_t lda, int64_t m, int64_t n, const double *Rv,
+                                                int ldt, int nrhs, double alpha, double beta, double *Y)
+{
+    __shared__ double red[256][9];
+    const int64_t col = blockIdx.x;
+    const double *a = A + col * lda;
+    for (int v0 = 0; v0 < nrhs; v0 += 8) {
+        const int nv = std::min(8, nrhs - v0);
+        double acc[8] = {};
+        for (int64_t r = threadIdx.x; r < m; r += 256) {
+            const double av = a[r];
+#pragma unroll
+            for (int v = 0; v < 8; ++v)
+                if (v < nv) acc[v] += av * Rv[r * ldt + v0 + v];
+        }
+#pragma unroll
+        for (int v = 0; v < 8; ++v) red[threadIdx.x][v] = acc[v];
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h)
+                for (int v = 0; v < 8; ++v) red[threadIdx.x][v] += red[threadIdx.x + h][v];
+            __syncthreads();
+        }
+        if ((int)threadIdx.x < nv) {
+            const int v = threadIdx.x;
+            Y[col * ldt + v0 + v] = alpha * red[0][v] + (beta == 0.0 ? 0.0 : beta * Y[col * ldt + v0 + v]);
+        }
+        __syncthreads();
+    }
+}
+
+// out[v] = sum over rows r < m of Y[r][v]^2 (per column v < nrhs), in a
+// fixed order: per-block partial sums, then one block adds them in order.
+__global__ __launch_bounds__(256) void k_colsq_part(const double *Y, int ldt, int64_t m, int nrhs, double *part)
+{
+    __shared__ double red[256];
+    for (int v = 0; v < nrhs; ++v) {
+        double s = 0.0;
+        for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < m; r += (int64_t)gridDim.x * 256) {
+            const double y = Y[r * ldt + v];
+            s += y * y;
+        }
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(int64_t)v * gridDim.x + blockIdx.x] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ void k_colsq_sum(const double *part, int nblk, int nrhs, double *out)
+{
+    const int v = threadIdx.x;
+    if (v < nrhs) {
+        double s = 0.0;
+        for (int q = 0; q < nblk; ++q) s += part[(int64_t)v * nblk + q];
+        out[v] = s;
+    }
+}
+
+// ||A||_F^2 of a column-major matrix, same two-pass scheme (one column per
+// thread block row of work).
+__global__ __launch_bounds__(256) void k_frob_part(const double *A, int64_t lda, int64_t m, int64_t n, double *part)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t c = blockIdx.x; c < n; c += gridDim.x)
+        for (int64_t r = threadIdx.x; r < m; r += 256) {
+            const double a = A[c * lda + r];
+            s += a * a;
+        }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// Elementwise helpers on row blocks (rows < m, columns < nrhs).
+//   op 0: Y = X - Y       op 1: Y += X      op 2: Y = X      op 3: Y = -Y
+__global__ void k_axpy_rows(const double *X, double *Y, int ldt, int64_t m, int nrhs, int op)
+{
+    const int64_t total = m * nrhs;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t off = (e / nrhs) * ldt + e % nrhs;
+        if (op == 0) Y[off] = X[off] - Y[off];
+        else if (op == 1) Y[off] += X[off];
+        else if (op == 2) Y[off] = X[off];
+        else Y[off] = -Y[off];
+    }
+}
+
+// ------------------------------------------------------------ launchers
+
+template <int NB>
+static hipError_t trsm_impl(const double *tiles, int p, int64_t n, double *C, int ldt, bool upper, int *status,
+                            hipStream_t st)
+{
+    const int q = (int)((n + NB - 1) / NB);
+    const int nstrip = ldt / SW;
+    for (int s = 0; s < q; ++s) {
+        const int k = upper ? q - 1 - s : s;
+        hipLaunchKernelGGL(k_trsm_diag<NB>, dim3(1), dim3(2 * NB), 0, st, tiles, p, n, k, C, ldt, upper ? 1 : 0,
+                           status);
+        const int others = upper ? k : q - 1 - k;
+        if (others > 0)
+            hipLaunchKernelGGL(k_trsm_update<NB>, dim3(others, nstrip), dim3(2 * NB), 0, st, tiles, p, k, C, ldt,
+                               upper ? 1 : 0);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_trsm(int nb, const double *tiles, int p, int64_t n, double *C, int ldt, bool upper, int *status,
+                       hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    if (nb == 64) return trsm_impl<64>(tiles, p, n, C, ldt, upper, status, st);
+    if (nb == 128) return trsm_impl<128>(tiles, p, n, C, ldt, upper, status, st);
+    if (nb == 256) return trsm_impl<256>(tiles, p, n, C, ldt, upper, status, st);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_gemv_n(const double *A, int64_t lda, int64_t m, int64_t n, const double *X, int ldt, int nrhs,
+                         double alpha, double beta, double *Y, double *part, int64_t part_cap, hipStream_t st)
+{
+    if (m <= 0 || nrhs <= 0) return hipSuccess;
+    for (int v0 = 0; v0 < nrhs; v0 += SW) {
+        const int nr = std::min(SW, nrhs - v0);
+        const int64_t rowblk = (m + 255) / 256;
+        int64_t nslice = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048 / std::max<int64_t>(1, rowblk) + 1));
+        nslice = std::min<int64_t>(nslice, std::max<int64_t>(1, part_cap / (m * SW)));
+        const int64_t cps = (n + nslice - 1) / nslice;
+        hipLaunchKernelGGL(k_gemv_n_part, dim3((unsigned)rowblk, (unsigned)nslice), dim3(256), 0, st, A, lda, m, n,
+                           X + v0, ldt, nr, cps, part);
+        const int64_t blocks = std::min<int64_t>((m * nr + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_gemv_n_sum, dim3((unsigned)blocks), dim3(256), 0, st, part, (int)nslice, m, nr, alpha,
+                           beta, Y + v0, ldt);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gemv_t(const double *A, int64_t lda, int64_t m, int64_t n, const double *R, int ldt, int nrhs,
+                         double alpha, double beta, double *Y, hipStream_t st)
+{
+    if (n <= 0 || nrhs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gemv_t, dim3((unsigned)n), dim3(256), 0, st, A, lda, m, n, R, ldt, nrhs, alpha, beta, Y);
+    return hipGetLastError();
+}
+
+hipError_t launch_colsq(const double *Y, int ldt, int64_t m, int nrhs, double *part, double *out, hipStream_t st)
+{
+    const int nblk = 256;
+    hipLaunchKernelGGL(k_colsq_part, dim3(nblk), dim3(256), 0, st, Y, ldt, m, nrhs, part);
+    hipLaunchKernelGGL(k_colsq_sum, dim3(1), dim3(64), 0, st, part, nblk, nrhs, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_frob2(const double *A, int64_t lda, int64_t m, int64_t n, double *part, double *out, hipStream_t st)
+{
+    const int nblk = 256;
+    hipLaunchKernelGGL(k_frob_part, dim3(nblk), dim3(256), 0, st, A, lda, m, n, part);
+    hipLaunchKernelGGL(k_colsq_sum, dim3(1), dim3(64), 0, st, part, nblk, 1, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy_rows(const double *X, double *Y, int ldt, int64_t m, int nrhs, int op, hipStream_t st)
+{
+    const int64_t total = m * nrhs;
+    if (total <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_axpy_rows, dim3((unsigned)blocks), dim3(256), 0, st, X, Y, ldt, m, nrhs, op);
+    return hipGetLastError();
+}
+
+}  // namespace tq

@@ -1,0 +1,95 @@
+"""GPU tests of tileqr_solve_ls (through the C-ABI) against the oracle.
+
+The least-squares solution is unique for a full-rank A, so it is compared
+with the oracle's (Householder QR + back substitution) within the normwise
+perturbation bound c * kappa * u (plus kappa^2 u times the relative
+residual for inconsistent systems); the backward error is recomputed in
+numpy from the returned x.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_0709_1272_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def tq():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_0709_1272_amd import tileqr
+    return tileqr
+
+
+def solve(tq, A, b, **opt):
+    m, n = A.shape
+    b2 = b.reshape(m, -1)
+    nrhs = b2.shape[1]
+    At = tq.to_device(A)
+    Bt = tq.to_device(b2)
+    Xt = torch.zeros((nrhs, n), dtype=torch.float64, device="cuda")
+    info = tq.Info()
+    o = tq.opts(**opt)
+    rc = tq.solve_ls(m, n, nrhs, At.data_ptr(), m, Bt.data_ptr(), m, Xt.data_ptr(), n, o, info)
+    torch.cuda.synchronize()
+    # A and B are left untouched.
+    assert np.array_equal(tq.to_host(At, m), A)
+    assert np.array_equal(tq.to_host(Bt, m), b2)
+    x = tq.to_host(Xt, n)
+    return rc, (x[:, 0] if b.ndim == 1 else x), info
+
+
+@pytest.mark.parametrize("m,n,kappa,nb,ib,nrhs", [(600, 200, 1e4, 64, 16, 1), (1000, 300, 1e6, 128, 32, 3),
+                                                  (777, 777, 1e2, 64, 32, 2), (2048, 256, 1e8, 256, 32, 1),
+                                                  (300, 65, 1e3, 64, 16, 40)])
+def test_fp64_solve_vs_oracle(tq, m, n, kappa, nb, ib, nrhs):
+    A, b, _ = synth.svd_matrix(3 + m, m, n, kappa, nrhs=nrhs)
+    rc, x, info = solve(tq, A, b, nb=nb, ib=ib)
+    assert rc == tq.OK, tq.status_string(rc)
+    xo, ro = oracle.lstsq(A, b)
+    xo2, x2, b2 = xo.reshape(n, -1), x.reshape(n, -1), b.reshape(m, -1)
+    for v in range(x2.shape[1]):
+        rel_res = np.linalg.norm(ro.reshape(m, -1)[:, v]) / (np.linalg.norm(A, 2) * np.linalg.norm(xo2[:, v]))
+        bound = 64 * n * EPS * kappa * (1 + kappa * rel_res)
+        err = np.linalg.norm(x2[:, v] - xo2[:, v]) / np.linalg.norm(xo2[:, v])
+        eta = oracle.eta_ls(A, x2[:, v], b2[:, v])
+        print(f"{m}x{n} kappa={kappa:.0e} rhs {v}: |x - x_oracle|/|x| {err:.2e} (bound {bound:.1e}) eta {eta:.2e}")
+        assert err <= bound
+        assert eta <= 1e-14
+    assert info.converged == 1
+    assert info.eta <= 1e-14
+
+
+def test_square_system_backward_error(tq):
+    # Square systems: the paper's normwise backward error in the inf-norm
+    # (Section 3.2.4), here for the QR-based solve.
+    A = synth.uniform(21, 512, 512)
+    xt = np.random.default_rng(2).standard_normal(512)
+    b = A @ xt
+    rc, x, _ = solve(tq, A, b, nb=64, ib=16)
+    assert rc == tq.OK
+    assert oracle.eta_inf(A, x, b) <= 1e-15
+    xo, _ = oracle.lstsq(A, b)
+    assert np.linalg.norm(x - xo) <= 1e-10 * np.linalg.norm(xo)
+
+
+def test_singular_reported(tq):
+    A = synth.uniform(5, 300, 100)
+    A[:, 17] = 0.0
+    b = np.ones(300)
+    rc, _, _ = solve(tq, A, b, nb=64, ib=16)
+    assert rc == tq.ESINGULAR
+
+
+def test_bad_arguments(tq):
+    o = tq.opts()
+    info = tq.Info()
+    assert tq.solve_ls(5, 6, 1, 1, 5, 1, 5, 1, 6, o, info) == -2
+    assert tq.solve_ls(6, 5, 1, 1, 4, 1, 6, 1, 5, o, info) == -5
+    assert tq.solve_ls(6, 5, 1, 1, 6, 1, 6, 1, 4, o, info) == -9
