@@ -22,9 +22,28 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 (vector and matrix), spec sheet
+PROFILE = os.path.join(ROOT, "profiles", "k_worker_qr8192_fp64.md")
+KERNEL_SRC = os.path.join(ROOT, "paper_0709_1272_amd", "csrc", "tileqr_kernels.hip")
 M = N = 8192
 NB, IB = 256, 32
 CPU_SAMPLE_N = 3072
+
+
+def measured_traffic():
+    """HBM bytes per launch of the worker kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or
+    None when the kernel source changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(PROFILE).read()
+    except OSError:
+        return None
+    h = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if h not in text:
+        return None
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+-]+)", text)
+    return float(m.group(1)) if m else None
 
 
 def cpu_baseline():
@@ -118,7 +137,8 @@ def main():
                       "layout_out": round(float(st[:, 3].mean()), 4)},
         "wall_s_including_restores": round(wall, 4),
         "roofline": {"bound": "mfma", "achieved": round(achieved, 4), "peak": FP64_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                     "traffic": measured_traffic(),
                      "kernel": f"k_worker<{NB},{IB}>",
                      "algorithmic": f"{flops:.4e} flops per launch (2mn^2-2n^3/3)"},
     }
