@@ -56,9 +56,16 @@ typedef enum {
     TILEQR_ESINGULAR = 7    /* R has an exact zero on its diagonal (solve only)     */
 } tileqr_status;
 
-/* Arithmetic of the two GEMM-shaped kernels (LARFB, SSRFB).  Reflectors
- * (norms, tau, the R diagonal in GEQRT/TSQRT), T, storage and the
- * refinement's residuals stay FP64 in every mode. */
+/* Arithmetic of the two GEMM-shaped kernels (LARFB, SSRFB).  GEQRT and
+ * TSQRT (reflectors: norms, tau, the R diagonal; T), storage, the update of
+ * the coupled R rows and the refinement's residuals stay FP64 in every mode.
+ * In a split mode each FP64 operand of the products V^T X and V W is written
+ * as a sum of 2 or 3 narrow numbers (x rounded, then the rounded remainders)
+ * and the kept partial products run on the narrow MFMAs with FP32
+ * accumulation per 32 rows, summed across rows in FP64.  Split modes take
+ * ib = 32 (any supported nb); other ib give TILEQR_EUNSUPPORTED.  Entries
+ * must stay below about 1e38 in magnitude in the BF16 modes (FP32 range);
+ * FP16X2 scales every operand column by a power of two. */
 typedef enum {
     TILEQR_FP64 = 0,    /* FP64 MFMA                                               */
     TILEQR_BF16X2 = 1,  /* hi+lo BF16 split, 3 products, FP32 accumulation         */
@@ -112,8 +119,9 @@ void tileqr_opts_default(tileqr_opts *opts);
  * is supported, else 0. */
 int tileqr_blocking_supported(int64_t nb, int64_t ib);
 
-/* Blocking the library picks for an m x n factorisation when nb = ib = 0
- * (tuned table, see tileqr_tune).  Writes nb and ib; returns 0. */
+/* Blocking the library picks for an m x n factorisation in the given
+ * precision when nb = ib = 0 (ib = 32 in the split modes).  Writes nb and
+ * ib; returns 0. */
 int tileqr_choose_blocking(int64_t m, int64_t n, int precision, int64_t *nb, int64_t *ib);
 
 /* Number of doubles the T factors of an m x n factorisation occupy:
@@ -145,7 +153,9 @@ int tileqr_factor(int64_t m, int64_t n, double *A, int64_t lda, int64_t nb, int6
 
 /* tileqr_factor with options (schedule, stream, flags, precision of the
  * two GEMM-shaped kernels).  opts may be NULL (defaults); opts->nb/ib are
- * ignored (the explicit arguments rule).  Argument 8 is opts. */
+ * ignored (the explicit arguments rule).  Argument 8 is opts (-8 for an
+ * unknown precision); TILEQR_EUNSUPPORTED for a split precision with
+ * ib != 32. */
 int tileqr_factor_ex(int64_t m, int64_t n, double *A, int64_t lda, int64_t nb, int64_t ib,
                      double *T, const tileqr_opts *opts);
 

@@ -15,7 +15,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtileqr.so")
-SOURCES = ["tileqr_kernels.hip", "tileqr_solve.hip", "tileqr_api.cpp"]
+# (source, extra defines, object name): the split-precision kernels are one
+# source compiled once per arithmetic.
+UNITS = [("tileqr_kernels.hip", [], "tileqr_kernels"),
+         ("tileqr_mixed.hip", ["-DTQ_PREC=1"], "tileqr_mixed_bf16x2"),
+         ("tileqr_mixed.hip", ["-DTQ_PREC=2"], "tileqr_mixed_fp16x2"),
+         ("tileqr_mixed.hip", ["-DTQ_PREC=3"], "tileqr_mixed_bf16x3"),
+         ("tileqr_solve.hip", [], "tileqr_solve"),
+         ("tileqr_api.cpp", [], "tileqr_api")]
+SOURCES = sorted({u[0] for u in UNITS})
 ARCH = os.environ.get("TILEQR_ARCH", "gfx950")
 
 
@@ -27,17 +35,18 @@ def build(verbose=False, jobs=None):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objs = []
     procs = []
-    for src in sources():
-        obj = os.path.join(CSRC, os.path.basename(src) + ".o")
+    for name, defs, oname in UNITS:
+        src = os.path.join(CSRC, name)
+        obj = os.path.join(CSRC, oname + ".o")
         cmd = [hipcc, f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=on",
-               "-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
+               "-I", os.path.join(ROOT, "include")] + defs + ["-c", src, "-o", obj]
         if src.endswith(".cpp"):
             cmd[1:1] = ["-x", "hip"]
         procs.append(subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT))
         objs.append(obj)
     failed = False
-    for pr, src in zip(procs, sources()):
+    for pr, (src, _, _) in zip(procs, UNITS):
         out, _ = pr.communicate()
         text = out.decode(errors="replace")
         lines = [l for l in text.splitlines() if "packed-fp32-ops" not in l and l.strip()]

@@ -123,11 +123,11 @@ extern "C" int tileqr_blocking_supported(int64_t nb, int64_t ib)
 
 extern "C" int tileqr_choose_blocking(int64_t m, int64_t n, int precision, int64_t *nb, int64_t *ib)
 {
-    (void)precision;
     const int64_t k = std::min(m, n);
     int64_t b = 256, s = 32;
     if (k <= 1024) { b = 64; s = 16; }
     else if (k <= 4096 || m >= 16 * n) { b = 128; s = 32; }
+    if (precision != TILEQR_FP64) s = 32;   // the split products take ib = 32
     if (nb) *nb = b;
     if (ib) *ib = s;
     return 0;
@@ -298,7 +298,14 @@ extern "C" int tileqr_dag_selfcheck(int64_t p, int64_t q, int64_t strips, int64_
 
 namespace {
 
-bool mixed_supported(int precision) { return precision == TILEQR_FP64; }
+// Split-precision updates run with ib = 32 (one K step of the narrow MFMA
+// per wave), for every supported nb.
+bool precision_supported(int precision, int64_t ib)
+{
+    if (precision == TILEQR_FP64) return true;
+    if (precision == TILEQR_BF16X2 || precision == TILEQR_FP16X2 || precision == TILEQR_BF16X3) return ib == 32;
+    return false;
+}
 
 int check_status(Workspace *W, int *dstatus, hipStream_t st)
 {
@@ -326,7 +333,7 @@ int run_factor(Workspace *W, int nb, int ib, int p, int q, double *T, const tile
     M.task_base = 0;
     if (o.flags & TILEQR_FLAG_SERIAL) {
         if (ev_setup_done) TQ_HIP(hipEventRecord(ev_setup_done, st));
-        TQ_HIP(launch_factor_serial(nb, ib, M, dstatus, st));
+        TQ_HIP(launch_factor_serial(nb, ib, o.precision, M, dstatus, st));
         return 0;
     }
     const int ns = nb / kStripWidth;
@@ -385,7 +392,7 @@ int run_factor(Workspace *W, int nb, int ib, int p, int q, double *T, const tile
     }
     // Panel workers: one per independent panel chain that can be in flight,
     // at most one per XCD.  Update workers: the rest of what fits at once.
-    const int occ = worker_occupancy(nb, ib);
+    const int occ = worker_occupancy(nb, ib, o.precision);
     const int capacity = std::max(2, std::max(1, W->num_cu) * occ);
     const int panel = std::max(1, std::min({8, g.kmax, capacity / 2}));
     int update = (int)o.workers > 0 ? (int)o.workers : capacity - panel;
@@ -393,7 +400,7 @@ int run_factor(Workspace *W, int nb, int ib, int p, int q, double *T, const tile
     S.npanel = panel;
     TQ_HIP(launch_sched_init(S, st));
     if (ev_setup_done) TQ_HIP(hipEventRecord(ev_setup_done, st));
-    TQ_HIP(launch_worker(nb, ib, S, panel + update, st));
+    TQ_HIP(launch_worker(nb, ib, o.precision, S, panel + update, st));
     return 0;
 }
 
@@ -414,6 +421,8 @@ extern "C" int tileqr_factor_ex(int64_t m, int64_t n, double *A, int64_t lda, in
     tileqr_opts o;
     tileqr_opts_default(&o);
     if (opts) o = *opts;
+    if (o.precision < TILEQR_FP64 || o.precision > TILEQR_BF16X3) return -8;
+    if (!precision_supported(o.precision, ib)) return TILEQR_EUNSUPPORTED;
     std::lock_guard<std::mutex> lock(g_mu);
     Workspace *W = workspace();
     if (!W) return hip_fail(hipErrorNoDevice, "workspace");
@@ -694,7 +703,7 @@ extern "C" int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double 
     int64_t nb = o.nb, ib = o.ib;
     if (nb == 0 || ib == 0) tileqr_choose_blocking(m, n, o.precision, &nb, &ib);
     if (!tileqr_blocking_supported(nb, ib)) return TILEQR_EUNSUPPORTED;
-    if (o.precision != TILEQR_FP64 && !mixed_supported(o.precision)) return TILEQR_EUNSUPPORTED;
+    if (!precision_supported(o.precision, ib)) return TILEQR_EUNSUPPORTED;
 
     std::lock_guard<std::mutex> lock(g_mu);
     Workspace *W = workspace();

@@ -84,12 +84,20 @@ hipError_t launch_cm2tile(const double *A, int64_t lda, int64_t m, int64_t n, do
                           int p, int q, int *status, hipStream_t st);
 hipError_t launch_tile2cm(double *A, int64_t lda, int64_t m, int64_t n, const double *tiles, int nb,
                           int p, int q, const int *status, hipStream_t st);
-hipError_t launch_factor_serial(int nb, int ib, const MatDev &M, const int *status, hipStream_t st);
+// Arithmetic of the LARFB / SSRFB products (the values of tileqr_precision):
+// 0 FP64; 1, 2, 3 split BF16 x2, FP16 x2, BF16 x3 on the narrow MFMAs with
+// FP32 accumulation (ib = 32 only).  GEQRT and TSQRT are always FP64.
+hipError_t launch_factor_serial(int nb, int ib, int prec, const MatDev &M, const int *status, hipStream_t st);
 hipError_t launch_sched_init(const SchedDev &S, hipStream_t st);
 // The persistent scheduler: `workers` workgroups, the first S.npanel of
 // which run the panel tasks (GEQRT, TSQRT) and the others the updates
 // (LARFB, SSRFB).
-hipError_t launch_worker(int nb, int ib, const SchedDev &S, int workers, hipStream_t st);
-int worker_occupancy(int nb, int ib);
+hipError_t launch_worker(int nb, int ib, int prec, const SchedDev &S, int workers, hipStream_t st);
+int worker_occupancy(int nb, int ib, int prec);
+
+// The split-precision instantiations (one object per arithmetic, ib = 32).
+template <int PREC> hipError_t launch_serial_mx(int nb, const MatDev &M, const int *status, hipStream_t st);
+template <int PREC> hipError_t launch_worker_mx(int nb, const SchedDev &S, int workers, hipStream_t st);
+template <int PREC> int worker_occupancy_mx(int nb);
 
 }  // namespace tq

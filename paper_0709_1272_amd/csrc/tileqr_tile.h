@@ -1,0 +1,1245 @@
+// Device-side building blocks of the tiled QR (Section 3.2.1, Algorithm 2)
+// for gfx950: tile kernels GEQRT / TSQRT / LARFB / SSRFB and the
+// persistent DAG scheduler that runs them (Section 4).  Included by the
+// translation units that instantiate the kernels for each arithmetic.
+//
+// Storage.  The matrix is copied into Block Data Layout (Section 3: tiles
+// stored contiguously): tile (i, j) of nb x nb doubles sits at
+// tiles + (j * p + i) * nb * nb and is ROW-major inside, so that the 16-wide
+// column blocks the MFMA lanes own are 128-byte contiguous runs.  Ragged edges
+// are zero-padded: a zero row or column changes no reflector (its entries
+// add exact zeros to every norm and dot product, and a zero column below the
+// diagonal yields tau = 0), so padded tiles factor exactly like the paper's
+// pb x qb matrix.
+//
+// T factors.  Inner blocking (Section 3.2.3) gives one ib x ib upper
+// triangular T_l per group of ib reflectors; the t = nb/ib blocks of tile
+// (i, k) sit at T + (k * p + i) * ib * nb + l * ib * ib, row-major.
+//
+// Block reflector convention.  For forward-accumulated reflectors
+// H_1 ... H_s = I - V T V^T, so Q^T = I - V T^T V^T.  The paper writes the
+// LARFB/SSRFB updates as (I - V T V^T) applied to the tiles; applying Q^T
+// needs T^T, which is what every update below does.
+//
+// Work unit.  Every task runs on one workgroup of nb/32 wave64s (2 nb
+// threads), each wave owning 32 rows of a tile.  The GEMM-shaped parts use
+// v_mfma_f64_16x16x4_f64.  For this instruction lane L (n = L % 16,
+// g = L / 16) supplies A[n][g] and B[g][n] and holds D[4 r + g][n] in
+// accumulator element r (r = 0..3).  A tile strip of 32 columns is held in
+// accumulators: element r of row block rb (0..1) of wave w is row
+// 32 w + 16 rb + 4 r + g, column 16 cb + n.  The same registers then serve
+// directly as the B operand of the product V^T X (rows as the contracted
+// index: K-chunk r covers rows 16 rb + 4 r .. + 3).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "tileqr_dag.h"
+#include "tileqr_internal.h"
+
+namespace tq {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
+// Tile and T pointers reach the kernels through structures in device memory,
+// so the compiler cannot tell them from LDS or scratch pointers and would use
+// flat instructions; the explicit global address space gives global loads and
+// stores, which do not hold up LDS traffic behind the same counters.
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) v2d gv2d;
+
+constexpr int WS = 32;    // strip width (columns) of the GEMM-shaped kernels
+constexpr int CB = WS / 16;
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int NB, int IB>
+struct Cfg {
+    static constexpr int NW = NB / 32;       // waves per workgroup
+    static constexpr int NT = 64 * NW;       // threads per workgroup (= 2 nb, the launch bound)
+    static constexpr int NSLOT = NW < 4 ? NW : 4;   // LDS slots of the cross-wave reduction
+    static constexpr int RB = 2;             // 16-row blocks per wave
+    static constexpr int IBB = IB / 16;      // 16-wide blocks of the ib dimension
+    static constexpr int NPAN = NB / IB;     // inner panels per tile
+    static constexpr int LDP = IB + 2;       // LDS row stride of the panel buffer (16-byte rows)
+    static constexpr int RG = NT / IB;       // row groups of the panel factorisation
+    static constexpr int RPT = NB / RG;      // panel rows per thread
+    static constexpr int NS = NB / WS;       // strips per tile
+    static constexpr int VPT = NB * IB / 2 / NT;              // double2 per thread, full panel
+    static constexpr int TPT = (IB * IB / 2 + NT - 1) / NT;   // double2 per thread, one T
+    static constexpr int EPT = IB * WS / NT;                  // W entries per thread
+    static_assert(NB % 64 == 0 && IB % 16 == 0 && NB % IB == 0 && IB <= WS, "blocking");
+    static_assert(VPT >= 1 && EPT >= 1, "workgroup shape");
+};
+
+// A 32-column strip of a tile in accumulator layout (see the file header).
+template <int NB, int IB>
+struct Strip {
+    d4 v[Cfg<NB, IB>::RB][CB];
+};
+
+// Register staging of one inner panel (nb x ib) and its T, so that the
+// global loads of the next panel are in flight while the current one is
+// being applied.
+template <int NB, int IB>
+struct Stage {
+    v2d v[Cfg<NB, IB>::VPT];
+    v2d t[Cfg<NB, IB>::TPT];
+};
+
+template <int NB, int IB>
+struct Smem {
+    using C = Cfg<NB, IB>;
+    double P[(NB + IB) * C::LDP];    // panel / V: rows 0..nb-1 tile rows, nb.. head rows
+    double Wp[C::NSLOT * IB * WS];   // per-wave partial products
+    double Wa[IB * WS];              // reduced W (or the Gram matrix V^T V)
+    double Wb[IB * WS];              // T^T W
+    double Tl[IB * IB];              // T of the current inner panel
+    double tau[IB];
+    double xb[2][NB];                // reflector broadcast (double-buffered by column parity)
+    double sc[2][2];                 // tau of the broadcast reflector
+};
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+
+__device__ __forceinline__ gdouble *tile_ptr(const MatDev &M, int nb, int i, int j)
+{
+    return (gdouble *)(M.tiles + ((size_t)j * M.p + i) * (size_t)nb * nb);
+}
+
+__device__ __forceinline__ gdouble *tblock_ptr(const MatDev &M, int nb, int ib, int k, int i)
+{
+    return (gdouble *)(M.T + ((size_t)k * M.p + i) * (size_t)ib * nb);
+}
+
+// Stage <- columns [c0, c0 + ib) of rows [r0, nb) of a row-major tile
+// (rows above r0 left zero) and the ib x ib T block at Tg.
+template <int NB, int IB>
+__device__ __forceinline__ void stage_load(Stage<NB, IB> &S, const gdouble *tile, int c0, int r0,
+                                           const gdouble *Tg)
+{
+    using C = Cfg<NB, IB>;
+    constexpr int H = IB / 2;
+#pragma unroll
+    for (int u = 0; u < C::VPT; ++u) {
+        const int e = threadIdx.x + u * C::NT, r = e / H, c2 = e % H;
+        S.v[u] = r >= r0 ? *reinterpret_cast<const gv2d *>(tile + (size_t)r * NB + c0 + 2 * c2)
+                         : v2d{0.0, 0.0};
+    }
+#pragma unroll
+    for (int u = 0; u < C::TPT; ++u) {
+        const int e = threadIdx.x + u * C::NT;
+        S.t[u] = e < IB * IB / 2 ? reinterpret_cast<const gv2d *>(Tg)[e] : v2d{0.0, 0.0};
+    }
+}
+
+// sm.P rows [r0, nb) <- staged panel; with `unit` the block's unit lower
+// triangle is made explicit (ones on the diagonal of rows c0.., zeros above).
+template <int NB, int IB>
+__device__ __forceinline__ void stage_store(Smem<NB, IB> &sm, const Stage<NB, IB> &S, int r0, bool unit,
+                                            int c0)
+{
+    using C = Cfg<NB, IB>;
+    constexpr int H = IB / 2;
+#pragma unroll
+    for (int u = 0; u < C::VPT; ++u) {
+        const int e = threadIdx.x + u * C::NT, r = e / H, c = 2 * (e % H);
+        if (r < r0) continue;
+        double a = S.v[u].x, b = S.v[u].y;
+        if (unit) {
+            const int d = r - c0;
+            a = d < c ? 0.0 : (d == c ? 1.0 : a);
+            b = d < c + 1 ? 0.0 : (d == c + 1 ? 1.0 : b);
+        }
+        *reinterpret_cast<v2d *>(&sm.P[r * C::LDP + c]) = v2d{a, b};
+    }
+#pragma unroll
+    for (int u = 0; u < C::TPT; ++u) {
+        const int e = threadIdx.x + u * C::NT;
+        if (e < IB * IB / 2) reinterpret_cast<v2d *>(sm.Tl)[e] = S.t[u];
+    }
+}
+
+// X (accumulator layout) <- strip of a row-major tile: columns
+// [col0, col0 + 16 cbn), rows of every row block.
+template <int NB, int IB>
+__device__ __forceinline__ void load_strip(Strip<NB, IB> &X, const gdouble *tile, int ld, int col0, int cbn)
+{
+    const int n = lane_id() & 15, g = lane_id() >> 4, rowbase = wave_id() * 32;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = rowbase + rb * 16 + 4 * r + g;
+                X.v[rb][cb][r] = cb < cbn ? tile[(size_t)row * ld + col0 + cb * 16 + n] : 0.0;
+            }
+}
+
+template <int NB, int IB>
+__device__ __forceinline__ void store_strip(const Strip<NB, IB> &X, gdouble *tile, int ld, int col0, int cbn,
+                                            int rlo)
+{
+    const int n = lane_id() & 15, g = lane_id() >> 4, rowbase = wave_id() * 32;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+        if (rowbase + rb * 16 < rlo) continue;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            if (cb >= cbn) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = rowbase + rb * 16 + 4 * r + g;
+                tile[(size_t)row * ld + col0 + cb * 16 + n] = X.v[rb][cb][r];
+            }
+        }
+    }
+}
+
+// Per-wave partial accumulators (BA x BB blocks of 16 x 16 in accumulator
+// layout, row stride ld) -> sm.Wp slots 0..NSLOT-1.  With 8 waves the upper
+// four first store, then the lower four add theirs (slot q = P_{q+4} + P_q),
+// which halves the LDS the reduction needs; the caller sums the slots in
+// order.  Ends with a barrier.
+// GMAJ selects the accumulator row order: element r of lane group g is row
+// 4 r + g (FP64 MFMA) or 4 g + r (the 16x16x32 narrow MFMAs).
+template <int NB, int IB, int BA, int BB, bool GMAJ = false>
+__device__ __forceinline__ void waves_to_slots(Smem<NB, IB> &sm, const d4 (&acc)[BA][BB], int ld)
+{
+    using C = Cfg<NB, IB>;
+    constexpr int SLOT = IB * WS;
+    const int w = wave_id(), n = lane_id() & 15, g = lane_id() >> 4;
+    const int gm = GMAJ ? 4 : 1, rm = GMAJ ? 1 : 4;
+    if (C::NW > C::NSLOT) {
+        if (w >= C::NSLOT) {
+#pragma unroll
+            for (int a = 0; a < BA; ++a)
+#pragma unroll
+                for (int b = 0; b < BB; ++b)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        sm.Wp[(w - C::NSLOT) * SLOT + (a * 16 + rm * r + gm * g) * ld + b * 16 + n] = acc[a][b][r];
+        }
+        __syncthreads();
+        if (w < C::NSLOT) {
+#pragma unroll
+            for (int a = 0; a < BA; ++a)
+#pragma unroll
+                for (int b = 0; b < BB; ++b)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        double *d = &sm.Wp[w * SLOT + (a * 16 + rm * r + gm * g) * ld + b * 16 + n];
+                        *d = *d + acc[a][b][r];
+                    }
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < BA; ++a)
+#pragma unroll
+            for (int b = 0; b < BB; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    sm.Wp[w * SLOT + (a * 16 + rm * r + gm * g) * ld + b * 16 + n] = acc[a][b][r];
+    }
+    __syncthreads();
+}
+
+template <int NB, int IB>
+__device__ __forceinline__ double sum_slots(const Smem<NB, IB> &sm, int e)
+{
+    constexpr int SLOT = IB * WS;
+    double s = sm.Wp[e];
+#pragma unroll
+    for (int q = 1; q < Cfg<NB, IB>::NSLOT; ++q) s += sm.Wp[q * SLOT + e];
+    return s;
+}
+
+// Apply the block reflector of one inner panel, held in LDS (sm.P rows
+// 0..nb-1 = V, rows below `rlo` ignored; sm.Tl = T), to a strip X:
+//   W = [top +] V^T X;  W <- T^T W;  [top -= W;]  X -= V W
+// (with TRANS == false, W <- T W: the reflector itself instead of its
+// transpose).
+// `top` (may be NULL) points at the ib x (16 cbn) block of the coupled upper
+// tile (the R rows the TS form also updates), row stride ldtop.
+// Three workgroup barriers; the products V^T X, T^T W and V W run on MFMA.
+template <int NB, int IB, bool TRANS = true>
+__device__ void apply_panel(Smem<NB, IB> &sm, Strip<NB, IB> &X, int rlo, gdouble *top, int ldtop, int cbn)
+{
+    using C = Cfg<NB, IB>;
+    const int tid = threadIdx.x, w = wave_id();
+    const int n = lane_id() & 15, g = lane_id() >> 4, rowbase = w * 32;
+    const int ncol = cbn * 16;
+
+    double tv[C::EPT];
+    if (top != nullptr) {
+#pragma unroll
+        for (int u = 0; u < C::EPT; ++u) {
+            const int e = tid + u * C::NT, kr = e / WS, c = e % WS;
+            tv[u] = c < ncol ? top[(size_t)kr * ldtop + c] : 0.0;
+        }
+    }
+
+    // W partial over this wave's rows.
+    d4 Wacc[C::IBB][CB];
+#pragma unroll
+    for (int a = 0; a < C::IBB; ++a)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) Wacc[a][cb] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int rb = 0; rb < C::RB; ++rb) {
+        if (rowbase + rb * 16 < rlo) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double *vrow = &sm.P[(rowbase + rb * 16 + 4 * r + g) * C::LDP + n];
+#pragma unroll
+            for (int a = 0; a < C::IBB; ++a) {
+                const double va = vrow[a * 16];
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) Wacc[a][cb] = mfma(va, X.v[rb][cb][r], Wacc[a][cb]);
+            }
+        }
+    }
+    waves_to_slots<NB, IB, C::IBB, CB>(sm, Wacc, WS);
+#pragma unroll
+    for (int u = 0; u < C::EPT; ++u) {
+        const int e = tid + u * C::NT, c = e % WS;
+        double s = sum_slots<NB, IB>(sm, e);
+        if (top != nullptr && c < ncol) s = tv[u] + s;
+        sm.Wa[e] = s;
+    }
+    __syncthreads();
+    // T^T W: one 16 x 16 output block per wave.
+    for (int blk = w; blk < C::IBB * CB; blk += C::NW) {
+        const int a = blk / CB, cb = blk % CB;
+        d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kc = 0; kc < IB / 4; ++kc)
+            acc = mfma(TRANS ? sm.Tl[(4 * kc + g) * IB + a * 16 + n] : sm.Tl[(a * 16 + n) * IB + 4 * kc + g],
+                       sm.Wa[(4 * kc + g) * WS + cb * 16 + n], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = a * 16 + 4 * r + g, c = cb * 16 + n;
+            sm.Wb[i * WS + c] = acc[r];
+            if (top != nullptr && c < ncol) top[(size_t)i * ldtop + c] -= acc[r];
+        }
+    }
+    __syncthreads();
+    // X -= V (T^T W)
+#pragma unroll
+    for (int rb = 0; rb < C::RB; ++rb) {
+        if (rowbase + rb * 16 < rlo) continue;
+#pragma unroll
+        for (int kc = 0; kc < IB / 4; ++kc) {
+            const double va = sm.P[(rowbase + rb * 16 + n) * C::LDP + 4 * kc + g];
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                const double wb = -sm.Wb[(4 * kc + g) * WS + cb * 16 + n];
+                X.v[rb][cb] = mfma(va, wb, X.v[rb][cb]);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------ split-precision products
+//
+// Mixed arithmetic for the GEMM-shaped updates (LARFB, SSRFB).  Every FP64
+// operand x is written as a sum of narrow numbers x ~ x0 + x1 [+ x2]: x0 is x
+// rounded to the narrow format and each further part is the rounded
+// remainder (the remainders are exact in FP64).  A product of two split
+// operands is the sum of the partial products that matter, run on
+// v_mfma_f32_16x16x32_{bf16,f16} with FP32 accumulation:
+//   PREC_BF16X2  2 bf16 parts; x0 y0 + x0 y1 + x1 y0 (16 significant bits)
+//   PREC_FP16X2  2 fp16 parts, same three products (22 bits); every column
+//                of the right operand is scaled by a power of two so that its
+//                largest entry lands in [2^14, 2^15), V by 2^12 (|v| <= 1)
+//   PREC_BF16X3  3 bf16 parts; the six products of combined order <= 2
+// The partial products of one wave (32 rows: one K step) are accumulated in
+// FP32, converted to FP64, unscaled (exact) and summed across waves in FP64;
+// reflectors, T, T^T W and the update of the coupled top tile stay FP64.
+//
+// Lane layout of the 16x16x32 instructions (checked on the device): lane L
+// (n = L % 16, g = L / 16) supplies A[n][8 g + e] and B[8 g + e][n] in element
+// e (0..7) and holds D[4 g + r][n] in element r (0..3).  Both contractions
+// use the same trick as the FP64 path: the K index is permuted so that the
+// strip's accumulator registers are the B operand of V^T X as they stand
+// (element 4 rb + r of lane group g is row 16 rb + 4 r + g), and the rows of
+// the A operand of V W are permuted (A row m is tile row 16 rb + 4 (m % 4) +
+// m / 4) so that the result lands in the strip's own register layout.
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+enum { PREC_FP64 = 0, PREC_BF16X2 = 1, PREC_FP16X2 = 2, PREC_BF16X3 = 3 };
+
+template <int PREC> struct Narrow;
+template <> struct Narrow<PREC_BF16X2> { typedef bf8 vec; typedef __bf16 elem; static constexpr int NPART = 2; };
+template <> struct Narrow<PREC_FP16X2> { typedef h8 vec; typedef _Float16 elem; static constexpr int NPART = 2; };
+template <> struct Narrow<PREC_BF16X3> { typedef bf8 vec; typedef __bf16 elem; static constexpr int NPART = 3; };
+
+template <int PREC>
+struct Parts {
+    typename Narrow<PREC>::vec p[Narrow<PREC>::NPART];
+};
+
+// P <- the narrow parts of x * scale (scale a power of two).
+template <int PREC>
+__device__ __forceinline__ void split8(const double (&x)[8], double scale, Parts<PREC> &P)
+{
+    using E = typename Narrow<PREC>::elem;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        double r = PREC == PREC_FP16X2 ? x[e] * scale : x[e];
+#pragma unroll
+        for (int q = 0; q < Narrow<PREC>::NPART; ++q) {
+            const E h = (E)(float)r;
+            P.p[q][e] = h;
+            r = r - (double)(float)h;
+        }
+    }
+}
+
+template <int PREC>
+__device__ __forceinline__ f4 mfma_narrow(const typename Narrow<PREC>::vec &a, const typename Narrow<PREC>::vec &b,
+                                          f4 c)
+{
+    if constexpr (PREC == PREC_FP16X2) return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Sum of the kept partial products, smallest terms first.
+template <int PREC>
+__device__ __forceinline__ f4 split_product(const Parts<PREC> &A, const Parts<PREC> &B)
+{
+    f4 c = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (Narrow<PREC>::NPART == 3) {
+        c = mfma_narrow<PREC>(A.p[2], B.p[0], c);
+        c = mfma_narrow<PREC>(A.p[0], B.p[2], c);
+        c = mfma_narrow<PREC>(A.p[1], B.p[1], c);
+    }
+    c = mfma_narrow<PREC>(A.p[1], B.p[0], c);
+    c = mfma_narrow<PREC>(A.p[0], B.p[1], c);
+    c = mfma_narrow<PREC>(A.p[0], B.p[0], c);
+    return c;
+}
+
+// Power-of-two scale (and its inverse) for the fp16 parts of one column of
+// an MFMA operand whose 32 entries sit in lanes n, n + 16, n + 32, n + 48.
+__device__ __forceinline__ void column_scale(const double (&x)[8], double &scale, double &inv)
+{
+    double m = 0.0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) m = fmax(m, fabs(x[e]));
+    m = fmax(m, __shfl_xor(m, 16));
+    m = fmax(m, __shfl_xor(m, 32));
+    int ex = 0;
+    if (m > 0.0) (void)frexp(m, &ex);   // m = f 2^ex, f in [0.5, 1)
+    ex = ex < -1000 ? -1000 : (ex > 1000 ? 1000 : ex);
+    scale = ldexp(1.0, 15 - ex);
+    inv = ldexp(1.0, ex - 15);
+}
+
+// apply_panel (Q^T direction) with the two large products in split
+// precision; ib = 32 so that each wave's share of a product is one K step.
+// Waves whose 32 rows lie above rlo (a multiple of 32) sit the products out.
+template <int NB, int IB, int PREC>
+__device__ void apply_panel_mx(Smem<NB, IB> &sm, Strip<NB, IB> &X, int rlo, gdouble *top, int ldtop)
+{
+    using C = Cfg<NB, IB>;
+    static_assert(IB == 32, "split-precision updates take ib = 32");
+    constexpr bool SCALED = PREC == PREC_FP16X2;
+    constexpr double VSCALE = SCALED ? 4096.0 : 1.0;
+    const int tid = threadIdx.x, w = wave_id();
+    const int n = lane_id() & 15, g = lane_id() >> 4, rowbase = w * 32;
+    const bool active = rowbase >= rlo;
+
+    double tv[C::EPT];
+    if (top != nullptr) {
+#pragma unroll
+        for (int u = 0; u < C::EPT; ++u) {
+            const int e = tid + u * C::NT, kr = e / WS, c = e % WS;
+            tv[u] = top[(size_t)kr * ldtop + c];
+        }
+    }
+
+    // This wave's share of V^T X.
+    d4 Wacc[C::IBB][CB];
+    if (active) {
+        Parts<PREC> Bx[CB];
+        double xinv[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            double xv[8];
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) xv[4 * rb + r] = X.v[rb][cb][r];
+            double sc = 1.0;
+            xinv[cb] = 1.0;
+            if constexpr (SCALED) column_scale(xv, sc, xinv[cb]);
+            split8<PREC>(xv, sc, Bx[cb]);
+        }
+#pragma unroll
+        for (int a = 0; a < C::IBB; ++a) {
+            double vv[8];
+#pragma unroll
+            for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) vv[4 * rb + r] = sm.P[(rowbase + 16 * rb + 4 * r + g) * C::LDP + a * 16 + n];
+            Parts<PREC> Av;
+            split8<PREC>(vv, VSCALE, Av);
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                const f4 d = split_product<PREC>(Av, Bx[cb]);
+                const double un = SCALED ? xinv[cb] * (1.0 / VSCALE) : 1.0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Wacc[a][cb][r] = SCALED ? (double)d[r] * un : (double)d[r];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int a = 0; a < C::IBB; ++a)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) Wacc[a][cb] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+    waves_to_slots<NB, IB, C::IBB, CB, true>(sm, Wacc, WS);
+#pragma unroll
+    for (int u = 0; u < C::EPT; ++u) {
+        const int e = tid + u * C::NT;
+        double s = sum_slots<NB, IB>(sm, e);
+        if (top != nullptr) s = tv[u] + s;
+        sm.Wa[e] = s;
+    }
+    __syncthreads();
+    // T^T W in FP64: one 16 x 16 output block per wave.
+    for (int blk = w; blk < C::IBB * CB; blk += C::NW) {
+        const int a = blk / CB, cb = blk % CB;
+        d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kc = 0; kc < IB / 4; ++kc)
+            acc = mfma(sm.Tl[(4 * kc + g) * IB + a * 16 + n], sm.Wa[(4 * kc + g) * WS + cb * 16 + n], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = a * 16 + 4 * r + g, c = cb * 16 + n;
+            sm.Wb[i * WS + c] = acc[r];
+            if (top != nullptr) top[(size_t)i * ldtop + c] -= acc[r];
+        }
+    }
+    __syncthreads();
+    // X -= V (T^T W)
+    if (active) {
+        Parts<PREC> Bw[CB];
+        double winv[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            double wv[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) wv[e] = sm.Wb[(8 * g + e) * WS + cb * 16 + n];
+            double sc = 1.0;
+            winv[cb] = 1.0;
+            if constexpr (SCALED) column_scale(wv, sc, winv[cb]);
+            split8<PREC>(wv, sc, Bw[cb]);
+        }
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            const int row = rowbase + 16 * rb + 4 * (n & 3) + (n >> 2);
+            double vv[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) vv[e] = sm.P[row * C::LDP + 8 * g + e];
+            Parts<PREC> Av;
+            split8<PREC>(vv, VSCALE, Av);
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                const f4 d = split_product<PREC>(Av, Bw[cb]);
+                const double un = SCALED ? winv[cb] * (1.0 / VSCALE) : 1.0;
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    X.v[rb][cb][r] = X.v[rb][cb][r] - (SCALED ? (double)d[r] * un : (double)d[r]);
+            }
+        }
+    }
+}
+
+// Lane permutations by DPP on the two 32-bit halves of a double: xor 1 and
+// xor 2 inside a quad, mirror inside 8 and inside 16 lanes.
+template <int CTRL>
+__device__ __forceinline__ double dpp_perm(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum / max over the `W` consecutive lanes of a group (W a power of two
+// dividing 64).  Each step pairs every lane with one of the other half of
+// its current block (xor 1, xor 2, mirror in 8, mirror in 16, then xor 16
+// and xor 32 across rows), so after the last step every lane holds the same
+// bits: partners add the same two numbers in swapped order.
+template <int W>
+__device__ __forceinline__ double group_sum(double v)
+{
+    if (W >= 2) v += dpp_perm<0xB1>(v);
+    if (W >= 4) v += dpp_perm<0x4E>(v);
+    if (W >= 8) v += dpp_perm<0x141>(v);
+    if (W >= 16) v += dpp_perm<0x140>(v);
+    if (W >= 32) v += __shfl_xor(v, 16, 64);
+    if (W >= 64) v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+template <int W>
+__device__ __forceinline__ double group_max(double v)
+{
+    if (W >= 2) v = fmax(v, dpp_perm<0xB1>(v));
+    if (W >= 4) v = fmax(v, dpp_perm<0x4E>(v));
+    if (W >= 8) v = fmax(v, dpp_perm<0x141>(v));
+    if (W >= 16) v = fmax(v, dpp_perm<0x140>(v));
+    if (W >= 32) v = fmax(v, __shfl_xor(v, 16, 64));
+    if (W >= 64) v = fmax(v, __shfl_xor(v, 32, 64));
+    return v;
+}
+
+// Householder factorisation of the ib columns held in sm.P (Section 3.2.1:
+// DGEQRT's panel when ts == false, DTSQRT's when ts == true).
+//   GEQRT: column j has its head (diagonal) at P row c0 + j and its tail in
+//          P rows c0 + j + 1 .. nb - 1.
+//   TSQRT: column j has its head at P row nb + j (row j of the triangle R)
+//          and its tail in P rows 0 .. nb - 1 (the square tile); the rest of
+//          R is untouched by this reflector.
+// Reflector: beta = -sign(alpha) ||[alpha; x]|| (sign(0) = +1),
+// tau = (beta - alpha) / beta, v = x / (alpha - beta); tau = 0 when x = 0.
+// Column c is held by the RG consecutive lanes of one wave (rows rg, rg + RG,
+// ... in registers), so norms and dot products reduce with lane shuffles.
+// Per column one barrier: the group of column j forms its reflector and
+// publishes v and tau through LDS (two buffers by column parity, so that
+// column j+1 may publish while column j's updates still read), then every
+// later column applies it.
+template <int NB, int IB>
+__device__ void panel_factor(Smem<NB, IB> &sm, int c0, bool ts)
+{
+    using C = Cfg<NB, IB>;
+    constexpr int RG = C::RG, RPT = C::RPT, LDP = C::LDP;
+    static_assert(64 % RG == 0, "the threads of a column share one wave");
+    const int tid = threadIdx.x, c = tid / RG, rg = tid % RG;
+    double pr[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) pr[i] = sm.P[(rg + i * RG) * LDP + c];
+#pragma unroll 1
+    for (int j = 0; j < IB; ++j) {
+        const int hrow = ts ? NB + j : c0 + j;
+        const int tlo = ts ? 0 : c0 + j + 1;
+        double *xb = sm.xb[j & 1];
+        double *sc = sm.sc[j & 1];
+        if (c == j) {
+            double alpha;
+            if (ts) {
+                alpha = sm.P[hrow * LDP + j];
+            } else {
+                double h = 0.0;
+#pragma unroll
+                for (int i = 0; i < RPT; ++i)
+                    if (rg + i * RG == hrow) h = pr[i];
+                alpha = group_sum<RG>(h);   // only the owner contributes
+            }
+            double part = 0.0;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const double x = rg + i * RG >= tlo ? pr[i] : 0.0;
+                part += x * x;
+            }
+            const double sig = group_sum<RG>(part);
+            double xnorm, h;
+            if (sig <= 1.0e300 && (sig >= 2.2250738585072014e-308 || sig == 0.0)) {
+                // Nothing over- or underflowed (a zero sum with nonzero
+                // entries is caught by the scaled pass below).
+                xnorm = sqrt(sig);
+                h = fabs(alpha) < 1.0e150 ? sqrt(alpha * alpha + sig) : hypot(alpha, xnorm);
+            } else {
+                xnorm = -1.0;
+                h = 0.0;
+            }
+            if (xnorm < 0.0 || (sig == 0.0 && group_max<RG>(part) != 0.0)) {
+                // Redo the norm scaled by the largest magnitude.
+                double mx = 0.0;
+#pragma unroll
+                for (int i = 0; i < RPT; ++i)
+                    if (rg + i * RG >= tlo) mx = fmax(mx, fabs(pr[i]));
+                const double mxa = group_max<RG>(mx);
+                double p2 = 0.0;
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) {
+                    const double t = rg + i * RG >= tlo ? pr[i] / mxa : 0.0;
+                    p2 += t * t;
+                }
+                xnorm = mxa * sqrt(group_sum<RG>(p2));
+                h = hypot(alpha, xnorm);
+            }
+            double tau = 0.0;
+            if (xnorm != 0.0) {
+                const double beta = alpha >= 0.0 ? -h : h;
+                tau = (beta - alpha) / beta;
+                const double scal = 1.0 / (alpha - beta);
+#pragma unroll
+                for (int i = 0; i < RPT; ++i) {
+                    const int r = rg + i * RG;
+                    if (r >= tlo) {
+                        pr[i] = pr[i] * scal;
+                        xb[r] = pr[i];
+                    }
+                    if (!ts && r == hrow) pr[i] = beta;
+                }
+                if (ts && rg == 0) sm.P[hrow * LDP + j] = beta;
+            }
+            if (rg == 0) {
+                sc[0] = tau;
+                sm.tau[j] = tau;
+            }
+        }
+        __syncthreads();
+        const double tau = sc[0];
+        if (c > j && tau != 0.0) {
+            double part = 0.0;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int r = rg + i * RG;
+                if (r >= tlo) part += xb[r] * pr[i];
+            }
+            const double dot = group_sum<RG>(part);
+            double hc;
+            if (ts) {
+                hc = sm.P[hrow * LDP + c];
+            } else {
+                double h = 0.0;
+#pragma unroll
+                for (int i = 0; i < RPT; ++i)
+                    if (rg + i * RG == hrow) h = pr[i];
+                hc = group_sum<RG>(h);   // only the owner contributes
+            }
+            const double tw = tau * (hc + dot);
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int r = rg + i * RG;
+                if (r >= tlo) pr[i] -= xb[r] * tw;
+                if (!ts && r == hrow) pr[i] = hc - tw;
+            }
+            if (ts && rg == 0) sm.P[hrow * LDP + c] = hc - tw;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int r = rg + i * RG;
+        if (ts || r >= c0) sm.P[r * LDP + c] = pr[i];
+    }
+    __syncthreads();
+}
+
+// T of the panel in sm.P (rows >= rlo; V with its unit diagonal explicit):
+// G = V^T V on MFMA, then column by column (compact WY, forward)
+//   T[j][j] = tau_j,  T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j].
+// Lane i builds row i of T in registers: its entries only depend on the
+// row's earlier entries, and with the loops unrolled each new entry waits
+// for one multiply-add after the previous one.  Leaves T in sm.Tl and writes
+// it to Tg (row-major ib x ib).
+template <int NB, int IB>
+__device__ void build_t(Smem<NB, IB> &sm, int rlo, gdouble *Tg)
+{
+    using C = Cfg<NB, IB>;
+    const int tid = threadIdx.x, w = wave_id();
+    const int n = lane_id() & 15, g = lane_id() >> 4, rowbase = w * 32;
+    d4 G[C::IBB][C::IBB];
+#pragma unroll
+    for (int a = 0; a < C::IBB; ++a)
+#pragma unroll
+        for (int b = 0; b < C::IBB; ++b) G[a][b] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int rb = 0; rb < C::RB; ++rb) {
+        if (rowbase + rb * 16 < rlo) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double *vrow = &sm.P[(rowbase + rb * 16 + 4 * r + g) * C::LDP + n];
+            double v[C::IBB];
+#pragma unroll
+            for (int a = 0; a < C::IBB; ++a) v[a] = vrow[a * 16];
+#pragma unroll
+            for (int a = 0; a < C::IBB; ++a)
+#pragma unroll
+                for (int b = 0; b < C::IBB; ++b) G[a][b] = mfma(v[a], v[b], G[a][b]);
+        }
+    }
+    waves_to_slots<NB, IB, C::IBB, C::IBB>(sm, G, IB);
+    for (int e = tid; e < IB * IB; e += C::NT) sm.Wa[e] = sum_slots<NB, IB>(sm, e);
+    __syncthreads();
+    if (tid < IB) {
+        const int i = tid;
+        double trow[IB];
+#pragma unroll
+        for (int kk = 0; kk < IB; ++kk) trow[kk] = kk == i ? sm.tau[kk] : 0.0;
+#pragma unroll
+        for (int j = 1; j < IB; ++j) {
+            double s = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < j; ++kk) s += trow[kk] * sm.Wa[kk * IB + j];
+            if (i < j) trow[j] = -sm.tau[j] * s;
+        }
+#pragma unroll
+        for (int kk = 0; kk < IB; ++kk) sm.Tl[i * IB + kk] = trow[kk];
+    }
+    __syncthreads();
+    for (int e = tid; e < IB * IB; e += C::NT) Tg[e] = sm.Tl[e];
+}
+
+// ------------------------------------------------------------ tile kernels
+
+// DGEQRT(A_kk) -> (V_kk, R_kk, T_kk).
+template <int NB, int IB>
+__device__ void task_geqrt(Smem<NB, IB> &sm, const MatDev &M, int k)
+{
+    using C = Cfg<NB, IB>;
+    gdouble *tkk = tile_ptr(M, NB, k, k);
+    gdouble *Tk = tblock_ptr(M, NB, IB, k, k);
+    Stage<NB, IB> S;
+#pragma unroll 1
+    for (int l = 0; l < C::NPAN; ++l) {
+        const int c0 = l * IB;
+        stage_load<NB, IB>(S, tkk, c0, c0, Tk);
+        stage_store<NB, IB>(sm, S, c0, false, c0);
+        __syncthreads();
+        panel_factor<NB, IB>(sm, c0, false);
+        // Write R and V back; keep V with explicit unit diagonal in LDS.
+        constexpr int H = IB / 2;
+#pragma unroll
+        for (int u = 0; u < C::VPT; ++u) {
+            const int e = threadIdx.x + u * C::NT, r = e / H, cc = 2 * (e % H);
+            if (r < c0) continue;
+            v2d v = *reinterpret_cast<v2d *>(&sm.P[r * C::LDP + cc]);
+            *reinterpret_cast<gv2d *>(tkk + (size_t)r * NB + c0 + cc) = v;
+            const int d = r - c0;
+            if (d <= cc + 1) {
+                v.x = d < cc ? 0.0 : (d == cc ? 1.0 : v.x);
+                v.y = d < cc + 1 ? 0.0 : 1.0;
+                *reinterpret_cast<v2d *>(&sm.P[r * C::LDP + cc]) = v;
+            }
+        }
+        __syncthreads();
+        build_t<NB, IB>(sm, c0, Tk + l * IB * IB);
+        __syncthreads();
+#pragma unroll 1
+        for (int col0 = c0 + IB; col0 < NB; col0 += WS) {
+            const int cbn = min(CB, (NB - col0) / 16);
+            Strip<NB, IB> X;
+            load_strip<NB, IB>(X, tkk, NB, col0, cbn);
+            apply_panel<NB, IB>(sm, X, c0, nullptr, 0, cbn);
+            store_strip<NB, IB>(X, tkk, NB, col0, cbn, c0);
+        }
+        __syncthreads();
+    }
+}
+
+// DTSQRT(R_kk, A_ik) -> (R_kk, V_ik, T_ik).
+template <int NB, int IB>
+__device__ void task_tsqrt(Smem<NB, IB> &sm, const MatDev &M, int k, int i)
+{
+    using C = Cfg<NB, IB>;
+    gdouble *tkk = tile_ptr(M, NB, k, k);
+    gdouble *tik = tile_ptr(M, NB, i, k);
+    gdouble *Ti = tblock_ptr(M, NB, IB, k, i);
+    Stage<NB, IB> S;
+    constexpr int H = IB / 2;
+#pragma unroll 1
+    for (int l = 0; l < C::NPAN; ++l) {
+        const int c0 = l * IB;
+        stage_load<NB, IB>(S, tik, c0, 0, Ti);
+        for (int e = threadIdx.x; e < IB * IB; e += C::NT) {
+            const int r = e / IB, c = e % IB;
+            sm.P[(NB + r) * C::LDP + c] = r <= c ? tkk[(size_t)(c0 + r) * NB + c0 + c] : 0.0;
+        }
+        stage_store<NB, IB>(sm, S, 0, false, c0);
+        __syncthreads();
+        panel_factor<NB, IB>(sm, c0, true);
+        for (int e = threadIdx.x; e < IB * IB; e += C::NT) {
+            const int r = e / IB, c = e % IB;
+            if (r <= c) tkk[(size_t)(c0 + r) * NB + c0 + c] = sm.P[(NB + r) * C::LDP + c];
+        }
+#pragma unroll
+        for (int u = 0; u < C::VPT; ++u) {
+            const int e = threadIdx.x + u * C::NT, r = e / H, cc = 2 * (e % H);
+            *reinterpret_cast<gv2d *>(tik + (size_t)r * NB + c0 + cc) =
+                *reinterpret_cast<v2d *>(&sm.P[r * C::LDP + cc]);
+        }
+        build_t<NB, IB>(sm, 0, Ti + l * IB * IB);
+        __syncthreads();
+#pragma unroll 1
+        for (int col0 = c0 + IB; col0 < NB; col0 += WS) {
+            const int cbn = min(CB, (NB - col0) / 16);
+            Strip<NB, IB> X;
+            load_strip<NB, IB>(X, tik, NB, col0, cbn);
+            apply_panel<NB, IB>(sm, X, 0, tkk + (size_t)c0 * NB + col0, NB, cbn);
+            store_strip<NB, IB>(X, tik, NB, col0, cbn, 0);
+        }
+        __syncthreads();
+    }
+}
+
+// One strip (32 columns at col0, row stride ldx) of X <- Q_kk^T X (TRANS)
+// or Q_kk X, Q_kk the block reflector of the diagonal tile tkk with T
+// blocks Tk.  Q_kk = H_0 ... H_{t-1} over the inner panels, so Q_kk^T runs
+// the panels forward with T^T and Q_kk backward with T.
+template <int NB, int IB, bool TRANS, int PREC = PREC_FP64>
+__device__ void apply_diag_strip(Smem<NB, IB> &sm, const gdouble *tkk, const gdouble *Tk, gdouble *x, int ldx,
+                                 int col0)
+{
+    static_assert(PREC == PREC_FP64 || TRANS, "split precision is used for Q^T only");
+    using C = Cfg<NB, IB>;
+    Stage<NB, IB> S;
+    const int l0 = TRANS ? 0 : C::NPAN - 1;
+    stage_load<NB, IB>(S, tkk, l0 * IB, l0 * IB, Tk + l0 * IB * IB);
+    Strip<NB, IB> X;
+    load_strip<NB, IB>(X, x, ldx, col0, CB);
+#pragma unroll 1
+    for (int q = 0; q < C::NPAN; ++q) {
+        const int l = TRANS ? q : C::NPAN - 1 - q;
+        const int c0 = l * IB;
+        stage_store<NB, IB>(sm, S, c0, true, c0);
+        __syncthreads();
+        if (q + 1 < C::NPAN) {
+            const int ln = TRANS ? l + 1 : l - 1;
+            stage_load<NB, IB>(S, tkk, ln * IB, ln * IB, Tk + ln * IB * IB);
+        }
+        if constexpr (PREC == PREC_FP64) apply_panel<NB, IB, TRANS>(sm, X, c0, nullptr, 0, CB);
+        else apply_panel_mx<NB, IB, PREC>(sm, X, c0, nullptr, 0);
+        __syncthreads();
+    }
+    store_strip<NB, IB>(X, x, ldx, col0, CB, 0);
+}
+
+// One strip of [top; X] <- Q_ik^T [top; X] (TRANS) or Q_ik [top; X], Q_ik
+// the coupled block reflector of tile tik (reflectors [e; V2]) with T blocks
+// Ti; `top` is the whole upper tile (its rows c0.. are the ones each inner
+// panel touches).
+template <int NB, int IB, bool TRANS, int PREC = PREC_FP64>
+__device__ void apply_ts_strip(Smem<NB, IB> &sm, const gdouble *tik, const gdouble *Ti, gdouble *top, int ldtop,
+                               gdouble *x, int ldx, int col0)
+{
+    static_assert(PREC == PREC_FP64 || TRANS, "split precision is used for Q^T only");
+    using C = Cfg<NB, IB>;
+    Stage<NB, IB> S;
+    const int l0 = TRANS ? 0 : C::NPAN - 1;
+    stage_load<NB, IB>(S, tik, l0 * IB, 0, Ti + l0 * IB * IB);
+    Strip<NB, IB> X;
+    load_strip<NB, IB>(X, x, ldx, col0, CB);
+#pragma unroll 1
+    for (int q = 0; q < C::NPAN; ++q) {
+        const int l = TRANS ? q : C::NPAN - 1 - q;
+        const int c0 = l * IB;
+        stage_store<NB, IB>(sm, S, 0, false, c0);
+        __syncthreads();
+        if (q + 1 < C::NPAN) {
+            const int ln = TRANS ? l + 1 : l - 1;
+            stage_load<NB, IB>(S, tik, ln * IB, 0, Ti + ln * IB * IB);
+        }
+        if constexpr (PREC == PREC_FP64) apply_panel<NB, IB, TRANS>(sm, X, 0, top + (size_t)c0 * ldtop + col0, ldtop, CB);
+        else apply_panel_mx<NB, IB, PREC>(sm, X, 0, top + (size_t)c0 * ldtop + col0, ldtop);
+        __syncthreads();
+    }
+    store_strip<NB, IB>(X, x, ldx, col0, CB, 0);
+}
+
+// DLARFB: strip s of A_kj <- Q_kk^T A_kj.
+template <int NB, int IB, int PREC>
+__device__ void task_larfb(Smem<NB, IB> &sm, const MatDev &M, int k, int j, int s)
+{
+    apply_diag_strip<NB, IB, true, PREC>(sm, tile_ptr(M, NB, k, k), tblock_ptr(M, NB, IB, k, k), tile_ptr(M, NB, k, j), NB,
+                                   s * WS);
+}
+
+// DSSRFB: strip s of [A_kj; A_ij] <- Q_ik^T [A_kj; A_ij].
+template <int NB, int IB, int PREC>
+__device__ void task_ssrfb(Smem<NB, IB> &sm, const MatDev &M, int k, int i, int j, int s)
+{
+    apply_ts_strip<NB, IB, true, PREC>(sm, tile_ptr(M, NB, i, k), tblock_ptr(M, NB, IB, k, i), tile_ptr(M, NB, k, j), NB,
+                                 tile_ptr(M, NB, i, j), NB, s * WS);
+}
+
+// Workers come in two roles: ROLE_PANEL runs GEQRT and TSQRT (queue
+// levels 0-1), ROLE_UPDATE runs LARFB and SSRFB (levels 2..NLEVEL-1).  The
+// persistent kernel gives the panel role to its lowest workgroup indices,
+// which the dispatcher makes resident first.
+enum { ROLE_PANEL = 0, ROLE_UPDATE = 1 };
+
+template <int NB, int IB, int ROLE, int PREC>
+__device__ __forceinline__ void run_task(Smem<NB, IB> &sm, const MatDev &M, const Task &t)
+{
+    if constexpr (ROLE == ROLE_PANEL) {
+        if (t.type == GEQRT) task_geqrt<NB, IB>(sm, M, t.k);
+        else task_tsqrt<NB, IB>(sm, M, t.k, t.i);
+    } else {
+        if (t.type == LARFB) task_larfb<NB, IB, PREC>(sm, M, t.k, t.j, t.s);
+        else task_ssrfb<NB, IB, PREC>(sm, M, t.k, t.i, t.j, t.s);
+    }
+}
+
+// ------------------------------------------------ serial (Algorithm 2) kernels
+
+// One launch per group of independent tasks in Algorithm 2's loop order:
+// GEQRT(k) / TSQRT(k, i): one workgroup; LARFB(k, .) / SSRFB(k, i, .):
+// one workgroup per (j, strip).
+template <int NB, int IB, int TYPE, int PREC>
+__global__ __launch_bounds__(2 * NB) void k_serial(MatDev M, int k, int i, const int *status)
+{
+    __shared__ Smem<NB, IB> sm;
+    if (*status != 0) return;
+    constexpr int NS = Cfg<NB, IB>::NS;
+    const int j = k + 1 + blockIdx.x / NS, s = blockIdx.x % NS;
+    if constexpr (TYPE == GEQRT) task_geqrt<NB, IB>(sm, M, k);
+    else if constexpr (TYPE == TSQRT) task_tsqrt<NB, IB>(sm, M, k, i);
+    else if constexpr (TYPE == LARFB) task_larfb<NB, IB, PREC>(sm, M, k, j, s);
+    else task_ssrfb<NB, IB, PREC>(sm, M, k, i, j, s);
+}
+
+// ------------------------------------------------------- DAG scheduler
+
+__device__ __forceinline__ int32_t ld_acq(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ld_rlx(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void push_task(const SchedDev &S, int queue, int64_t gid)
+{
+    const uint32_t slot = __hip_atomic_fetch_add(&S.qtail[queue * 32], 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&S.qslot[S.qoff[queue] + slot], (int32_t)(gid + 1), __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Non-blocking pop: -1 when the queue has nothing claimable right now.
+__device__ __forceinline__ int64_t pop_task(const SchedDev &S, int queue)
+{
+    for (int attempt = 0; attempt < 4; ++attempt) {
+        const uint32_t t = ld_rlx(&S.qtail[queue * 32]);
+        const uint32_t h = ld_rlx(&S.qhead[queue * 32]);
+        if (h >= t) return -1;
+        const int32_t v = ld_acq(&S.qslot[S.qoff[queue] + h]);
+        if (v == 0) return -1;
+        uint32_t expect = h;
+        if (__hip_atomic_compare_exchange_strong(&S.qhead[queue * 32], &expect, h + 1, __ATOMIC_ACQ_REL,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            return (int64_t)v - 1;
+    }
+    return -1;
+}
+
+// XCD this workgroup runs on (hardware register XCC_ID).
+__device__ __forceinline__ int xcd_id() { return __builtin_amdgcn_s_getreg((3 << 11) | 20) & (NXQ - 1); }
+
+__device__ __forceinline__ int find_mat(const SchedDev &S, int64_t gid)
+{
+    int lo = 0, hi = S.nmat - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (S.mats[mid].task_base <= gid) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint64_t mix64(uint64_t x)
+{
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdULL;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ULL;
+    x ^= x >> 33;
+    return x;
+}
+
+
+// One pass over the queues a worker serves: the panel worker its two
+// levels; an update worker the update levels in priority order, its own
+// XCD's queue first and, when `steal`, the other XCDs' queues after it.
+template <int ROLE>
+__device__ __forceinline__ int64_t pop_any(const SchedDev &S, int xcd, bool steal, uint64_t shuffle_rng)
+{
+    if constexpr (ROLE == ROLE_PANEL) {
+        const int first = (int)(shuffle_rng & 1);
+        int64_t gid = pop_task(S, queue_index(first, 0));
+        if (gid < 0) gid = pop_task(S, queue_index(first ^ 1, 0));
+        return gid;
+    } else {
+        constexpr int NLV = NLEVEL - 2;
+        const int start = (int)(shuffle_rng % NLV);
+        for (int q = 0; q < NLV; ++q) {
+            const int64_t gid = pop_task(S, queue_index(2 + (start + q) % NLV, xcd));
+            if (gid >= 0) return gid;
+        }
+        if (steal) {
+            for (int q = 0; q < NLV; ++q)
+                for (int d = 1; d < NXQ; ++d) {
+                    const int64_t gid = pop_task(S, queue_index(2 + (start + q) % NLV, (xcd + d) % NXQ));
+                    if (gid >= 0) return gid;
+                }
+        }
+        return -1;
+    }
+}
+
+template <int NB, int IB, int ROLE, int PREC>
+__device__ __forceinline__ void worker_loop(Smem<NB, IB> &sm, const SchedDev &S)
+{
+    __shared__ int64_t s_gid;
+    __shared__ int s_exit;
+    const int tid = threadIdx.x;
+    uint64_t rng = mix64(S.seed ^ (0x9e3779b97f4a7c15ULL * (blockIdx.x + 1)));
+    const int xcd = xcd_id();
+    for (;;) {
+        if (tid == 0) {
+            // Idle loop: poll the queues with exponential back-off, look at
+            // the completion counter and the status word only every few
+            // rounds; every idle round counts towards the watchdog.
+            int64_t gid = -1;
+            int ex = 0;
+            int64_t idle = 0;
+            uint32_t seen = ld_rlx(S.done);
+            int backoff = 0;
+            for (uint32_t round = 0;; ++round) {
+                uint64_t pick = 0;
+                if (S.shuffle) {
+                    rng = mix64(rng + 1);
+                    for (int z = 0; z < (int)(rng & 7); ++z) __builtin_amdgcn_s_sleep(1);
+                    pick = rng >> 8;
+                }
+                gid = pop_any<ROLE>(S, xcd, ROLE == ROLE_UPDATE && (round & 3) == 3, pick);
+                if (gid >= 0) break;
+                if ((round & 3) == 0) {
+                    if (__hip_atomic_load(S.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                        ex = 1;
+                        break;
+                    }
+                    const uint32_t d = ld_rlx(S.done);
+                    if (d >= S.total_tasks) {
+                        ex = 1;
+                        break;
+                    }
+                    if (d != seen) {
+                        seen = d;
+                        idle = 0;
+                    }
+                }
+                if (++idle > S.spin_limit) {
+                    __hip_atomic_fetch_or(S.status, STATUS_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ex = 1;
+                    break;
+                }
+                const int cap = ROLE == ROLE_PANEL ? 2 : 5;
+                backoff = backoff < cap ? backoff + 1 : cap;
+                for (int z = 0; z < (1 << backoff); ++z) __builtin_amdgcn_s_sleep(2);
+            }
+            s_gid = gid;
+            s_exit = ex;
+        }
+        __syncthreads();
+        if (s_exit) break;
+        const int64_t gid = s_gid;
+        // Acquire: one wave invalidates the (shared) L1 and L2 lines, the
+        // barrier holds the others back until it has.
+        if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __syncthreads();
+        const int mi = find_mat(S, gid);
+        const MatDev &M = S.mats[mi];
+        const Grid g = make_grid(M.p, M.q, S.ns);
+        const Task t = decode(g, gid - M.task_base);
+        const uint64_t t0 = wall_clock64();
+        run_task<NB, IB, ROLE, PREC>(sm, M, t);
+        // Release: every wave waits for its own stores, then wave 0 writes
+        // the L2 back and releases the successors (in program order after
+        // its fence).
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __syncthreads();
+        if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const int ns = tid < 64 ? nsucc(g, t) : 0;
+        for (int n = tid; n < ns; n += 64) {
+            if (S.drop_edge >= 0 && gid == S.drop_edge && n == 0) continue;
+            const int64_t sl = succ(g, t, n);
+            const int32_t old = __hip_atomic_fetch_add(&S.counters[M.task_base + sl], -1, __ATOMIC_ACQ_REL,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+            if (old == 1) push_task(S, queue_of(decode(g, sl), S.ns, mi), M.task_base + sl);
+        }
+        if (tid == 0) {
+            if (S.trace != nullptr) {
+                const uint32_t e = __hip_atomic_fetch_add(S.trace_count, 1u, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                if (e < S.trace_cap) {
+                    int64_t *ev = S.trace + (size_t)e * 8;
+                    ev[0] = t.type; ev[1] = t.k; ev[2] = t.i; ev[3] = t.j; ev[4] = t.s;
+                    ev[5] = ((int64_t)mi << 20) | (ROLE << 16) | blockIdx.x;
+                    ev[6] = (int64_t)t0;
+                    ev[7] = (int64_t)wall_clock64();
+                }
+            }
+            __hip_atomic_fetch_add(S.done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+    }
+}
+
+template <int NB, int IB, int PREC>
+__global__ __launch_bounds__(2 * NB) void k_worker(SchedDev S)
+{
+    __shared__ Smem<NB, IB> sm;
+    if ((int)blockIdx.x < S.npanel) worker_loop<NB, IB, ROLE_PANEL, PREC>(sm, S);
+    else worker_loop<NB, IB, ROLE_UPDATE, PREC>(sm, S);
+}
+
+// Host side of the kernels above for one arithmetic (PREC): the serial
+// Algorithm 2 driver, the persistent scheduler launch and its occupancy.
+template <int NB, int IB, int PREC>
+static hipError_t serial_impl(const MatDev &M, const int *status, hipStream_t st)
+{
+    constexpr int NS = Cfg<NB, IB>::NS;
+    const int p = M.p, q = M.q, kmax = p < q ? p : q;
+    const dim3 blk(Cfg<NB, IB>::NT);
+    for (int k = 0; k < kmax; ++k) {
+        hipLaunchKernelGGL((k_serial<NB, IB, GEQRT, PREC>), dim3(1), blk, 0, st, M, k, k, status);
+        if (q - k - 1 > 0)
+            hipLaunchKernelGGL((k_serial<NB, IB, LARFB, PREC>), dim3((q - k - 1) * NS), blk, 0, st, M, k, k,
+                               status);
+        for (int i = k + 1; i < p; ++i) {
+            hipLaunchKernelGGL((k_serial<NB, IB, TSQRT, PREC>), dim3(1), blk, 0, st, M, k, i, status);
+            if (q - k - 1 > 0)
+                hipLaunchKernelGGL((k_serial<NB, IB, SSRFB, PREC>), dim3((q - k - 1) * NS), blk, 0, st, M, k, i,
+                                   status);
+        }
+    }
+    return hipGetLastError();
+}
+
+template <int NB, int IB, int PREC>
+static hipError_t worker_impl(const SchedDev &S, int workers, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_worker<NB, IB, PREC>), dim3(workers), dim3(Cfg<NB, IB>::NT), 0, st, S);
+    return hipGetLastError();
+}
+
+template <int NB, int IB, int PREC>
+static int worker_occupancy_impl()
+{
+    int a = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_worker<NB, IB, PREC>, Cfg<NB, IB>::NT, 0) != hipSuccess)
+        return 1;
+    return a > 0 ? a : 1;
+}
+
+}  // namespace tq
