@@ -80,8 +80,10 @@ enum {
     TILEQR_FLAG_TRACE = 1u << 2,   /* record one trace event per task (tileqr_trace)   */
     TILEQR_FLAG_SHUFFLE = 1u << 3, /* DAG scheduler pops ready tasks in a seeded
                                       pseudo-random order (schedule-independence test) */
-    TILEQR_FLAG_TIMING = 1u << 4   /* time each stage with HIP events on the call's
+    TILEQR_FLAG_TIMING = 1u << 4,  /* time each stage with HIP events on the call's
                                       stream (tileqr_last_timing)                      */
+    TILEQR_FLAG_NO_GRAPH = 1u << 5 /* tileqr_factor_batched: launch the kernels directly
+                                      instead of replaying a captured HIP graph        */
 };
 
 typedef struct {
@@ -98,7 +100,19 @@ typedef struct {
                              as fit beside the panel worker                          */
     int64_t drop_edge;    /* test hook for the watchdog: the task with this id skips
                              its first successor release; -1 (default) = none        */
+    int64_t panel_workers;/* panel-role workgroups of the DAG scheduler (GEQRT, TSQRT);
+                             0 = automatic (one matrix: one per concurrent panel
+                             chain, at most 8; a batch: in proportion to the panel
+                             flops)                                                  */
 } tileqr_opts;
+
+/* Blocking and schedule of a factorisation, as chosen by tileqr_tune. */
+typedef struct {
+    int64_t nb, ib;           /* tile size and inner block                           */
+    int64_t panel_workers;    /* tileqr_opts.panel_workers                           */
+    int64_t workers;          /* tileqr_opts.workers (update workgroups)             */
+    double ms;                /* device time of the best trial                       */
+} tileqr_tuning;
 
 typedef struct {
     int iterations;       /* refinement steps taken                                  */
@@ -203,14 +217,39 @@ int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t
  *   A, T              : host arrays of `batch` device pointers; T[i] holds
  *                       tileqr_t_size(m[i], n[i], nb[i], ib[i]) doubles.
  * Each result equals, bit for bit, tileqr_factor on that matrix alone with
- * the same nb, ib.  The launch sequence is captured once per distinct batch
- * shape into a HIP graph and replayed.
+ * the same nb, ib and precision.  Matrices with different (nb, ib) form
+ * groups, one persistent launch each (nb = ib = NULL: one (nb, ib) for the
+ * whole batch, tileqr_tune's if it has seen these shapes, else by size).
+ * The launch sequence (layout conversion, scheduler set-up, workers,
+ * conversion back) is captured into a HIP graph on first use and replayed
+ * while the shapes, blocking and options stay the same; the matrix and T
+ * pointers are read from device memory at run time, so new pointers need no
+ * new capture.  opts->stream orders the call; TILEQR_FLAG_ASYNC returns
+ * without waiting (status then unchecked), TILEQR_FLAG_NO_GRAPH launches
+ * directly, TILEQR_FLAG_SERIAL and TILEQR_FLAG_TRACE are not supported here
+ * (TILEQR_EUNSUPPORTED).  With NaN/Inf in any matrix no matrix is written
+ * (TILEQR_ENONFINITE).
  * Errors: -1 batch, -2 m, -3 n, -4 A, -5 lda, -6 nb, -7 ib, -8 T, -9 opts
  * (for an array argument: the first bad entry).
  */
 int tileqr_factor_batched(int64_t batch, const int64_t *m, const int64_t *n,
                           double *const *A, const int64_t *lda, const int64_t *nb,
                           const int64_t *ib, double *const *T, const tileqr_opts *opts);
+
+/*
+ * Autotuner: times trial factorisations of synthetic matrices with the given
+ * shapes (batch >= 1; batch = 1 tunes one m x n matrix) in the given
+ * precision on the current device, over every supported (nb, ib) and a few
+ * splits of the workgroups between the panel and update roles, `trials`
+ * runs each (best time counts).  The fastest choice is written to *best and
+ * remembered for this multiset of shapes and precision for the rest of the
+ * process: tileqr_factor_batched with nb = ib = NULL and tileqr_solve_ls /
+ * tileqr_choose_blocking with automatic blocking use it.  Allocates scratch
+ * device memory for the trial matrices (freed before returning).
+ * Errors: -1 batch, -2 m, -3 n, -4 precision, -5 trials, -6 best.
+ */
+int tileqr_tune(int64_t batch, const int64_t *m, const int64_t *n, int precision, int trials,
+                tileqr_tuning *best);
 
 /* Operation counts.  tileqr_flops_lapack: 2mn^2 - 2n^3/3 (m >= n; the
  * mirror formula for m < n), the count the paper reports rates with

@@ -13,13 +13,19 @@
 
 #include "../../include/tileqr.h"
 #include "tileqr_dag.h"
+#include "tileqr_host.h"
 #include "tileqr_internal.h"
 
 using namespace tq;
 
-namespace {
+namespace tq {
 
+namespace {
 char g_hip_error[256] = "";
+std::vector<Workspace *> g_ws;
+}  // namespace
+
+std::mutex g_mu;
 
 int hip_fail(hipError_t e, const char *what)
 {
@@ -27,53 +33,43 @@ int hip_fail(hipError_t e, const char *what)
     return TILEQR_EHIP;
 }
 
-#define TQ_HIP(expr)                                   \
-    do {                                               \
-        hipError_t e_ = (expr);                        \
-        if (e_ != hipSuccess) return hip_fail(e_, #expr); \
-    } while (0)
-
-// Grow-only device buffer.
-struct DevBuf {
-    void *ptr = nullptr;
-    size_t bytes = 0;
-    int ensure(size_t need)
-    {
-        if (need <= bytes) return 0;
-        if (ptr) (void)hipFree(ptr);
-        ptr = nullptr;
-        bytes = 0;
-        if (hipMalloc(&ptr, need) != hipSuccess) {
-            (void)hipGetLastError();
-            return TILEQR_ENOMEM;
-        }
-        bytes = need;
-        return 0;
+int DevBuf::ensure(size_t need)
+{
+    if (need <= bytes) return 0;
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+    if (hipMalloc(&ptr, need) != hipSuccess) {
+        (void)hipGetLastError();
+        return TILEQR_ENOMEM;
     }
-    void release()
-    {
-        if (ptr) (void)hipFree(ptr);
-        ptr = nullptr;
-        bytes = 0;
-    }
-};
+    bytes = need;
+    return 0;
+}
 
-// Library workspace of one device.
-struct Workspace {
-    int device = -1;
-    DevBuf tiles, counters, qslot, qctl, mats, status, trace, misc, rows, prog, tws, solve, part;
-    double *host_small = nullptr;   // pinned, for norms read back by the solver
-    int *host_status = nullptr;   // pinned
-    int64_t trace_events = 0;
-    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-    double last_ms[4] = {0, 0, 0, 0};
-    bool have_timing = false;
-    int num_cu = 0;
-    double wall_hz = 0.0;
-};
+void DevBuf::release()
+{
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
 
-std::mutex g_mu;
-std::vector<Workspace *> g_ws;
+void SchedBufs::release()
+{
+    counters.release();
+    qslot.release();
+    qctl.release();
+    mats.release();
+}
+
+Workspace *existing_workspace()
+{
+    int dev = 0;
+    if (g_ws.empty() || hipGetDevice(&dev) != hipSuccess) return nullptr;
+    for (auto *w : g_ws)
+        if (w->device == dev) return w;
+    return nullptr;
+}
 
 Workspace *workspace()
 {
@@ -96,11 +92,7 @@ Workspace *workspace()
     return w;
 }
 
-int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
-
-constexpr int kStripWidth = 32;   // columns per LARFB/SSRFB strip task
-
-}  // namespace
+}  // namespace tq
 
 // ------------------------------------------------------------------ basics
 
@@ -123,6 +115,15 @@ extern "C" int tileqr_blocking_supported(int64_t nb, int64_t ib)
 
 extern "C" int tileqr_choose_blocking(int64_t m, int64_t n, int precision, int64_t *nb, int64_t *ib)
 {
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        tileqr_tuning t;
+        if (tuned_single(m, n, precision, &t)) {
+            if (nb) *nb = t.nb;
+            if (ib) *ib = t.ib;
+            return 0;
+        }
+    }
     const int64_t k = std::min(m, n);
     int64_t b = 256, s = 32;
     if (k <= 1024) { b = 64; s = 16; }
@@ -296,7 +297,7 @@ extern "C" int tileqr_dag_selfcheck(int64_t p, int64_t q, int64_t strips, int64_
 
 // ------------------------------------------------------------ factorisation
 
-namespace {
+namespace tq {
 
 // Split-precision updates run with ib = 32 (one K step of the narrow MFMA
 // per wave), for every supported nb.
@@ -318,6 +319,111 @@ int check_status(Workspace *W, int *dstatus, hipStream_t st)
     return TILEQR_OK;
 }
 
+int prepare_schedule(Workspace *W, SchedBufs &B, std::vector<MatDev> &mats, int nb, int ib, const tileqr_opts &o,
+                     hipStream_t st, SchedDev &S, int *workers)
+{
+    const int ns = nb / kStripWidth;
+    const int nmat = (int)mats.size();
+    // Tasks per ready queue, counted by index ranges (no id decoding):
+    // GEQRT and TSQRT have one queue each; strip tasks go to the queue of
+    // their level and XCD hash.
+    int64_t counts[NQUEUE] = {0};
+    int64_t total_ids = 0, ntask = 0, kmax_max = 0;
+    double panel_flops = 0.0, all_flops = 0.0;
+    const double b3 = (double)nb * nb * nb;
+    for (int mi = 0; mi < nmat; ++mi) {
+        MatDev &M = mats[mi];
+        const Grid g = make_grid(M.p, M.q, ns);
+        M.task_base = total_ids;
+        total_ids += g.total;
+        kmax_max = std::max<int64_t>(kmax_max, g.kmax);
+        for (int k = 0; k < g.kmax; ++k) {
+            const int64_t rows = g.p - k - 1;   // TSQRT(k, .) and SSRFB(k, ., j, s) per (j, s)
+            counts[queue_index(0, 0)] += 1;
+            counts[queue_index(1, 0)] += rows;
+            ntask += 1 + rows;
+            panel_flops += (4.0 / 3.0) * b3 + 2.0 * b3 * rows;
+            for (int j = k + 1; j < g.q; ++j)
+                for (int s = 0; s < ns; ++s) {
+                    Task t;
+                    t.k = k;
+                    t.j = j;
+                    t.s = s;
+                    t.i = k;
+                    t.type = LARFB;
+                    counts[queue_of(t, ns, mi)] += 1;
+                    t.type = SSRFB;
+                    t.i = k + 1;
+                    counts[queue_of(t, ns, mi)] += rows;
+                    ntask += 1 + rows;
+                }
+            all_flops += (double)(g.q - k - 1) * (2.0 * b3 + (4.0 * b3 + (double)ib * nb * nb) * rows);
+        }
+    }
+    all_flops += panel_flops;
+    int rc;
+    if ((rc = B.counters.ensure((size_t)total_ids * sizeof(int32_t)))) return rc;
+    if ((rc = B.qslot.ensure((size_t)std::max<int64_t>(ntask, 1) * sizeof(int32_t)))) return rc;
+    const size_t qctl_bytes = 2 * NQUEUE * 32 * sizeof(uint32_t) + 256 + NQUEUE * sizeof(int64_t);
+    if ((rc = B.qctl.ensure(qctl_bytes))) return rc;
+    if ((rc = B.mats.ensure((size_t)nmat * sizeof(MatDev)))) return rc;
+    TQ_HIP(hipMemcpyAsync(B.mats.ptr, mats.data(), (size_t)nmat * sizeof(MatDev), hipMemcpyHostToDevice, st));
+    std::memset(&S, 0, sizeof S);
+    S.mats = (MatDev *)B.mats.ptr;
+    S.nmat = nmat;
+    S.ns = ns;
+    S.total_ids = total_ids;
+    S.total_tasks = (uint32_t)ntask;
+    S.counters = (int32_t *)B.counters.ptr;
+    S.qslot = (int32_t *)B.qslot.ptr;
+    S.qslot_total = ntask;
+    int64_t qoff[NQUEUE];
+    int64_t off = 0;
+    for (int l = 0; l < NQUEUE; ++l) {
+        qoff[l] = off;
+        off += counts[l];
+    }
+    S.qhead = (uint32_t *)B.qctl.ptr;
+    S.qtail = S.qhead + NQUEUE * 32;
+    S.done = S.qtail + NQUEUE * 32;
+    S.trace_count = S.done + 1;
+    int64_t *qoff_dev = (int64_t *)((char *)B.qctl.ptr + 2 * NQUEUE * 32 * sizeof(uint32_t) + 256);
+    TQ_HIP(hipMemcpyAsync(qoff_dev, qoff, sizeof qoff, hipMemcpyHostToDevice, st));
+    S.qoff = qoff_dev;
+    S.status = (int32_t *)W->status.ptr;
+    S.spin_limit = o.spin_limit > 0 ? o.spin_limit : (int64_t)1 << 24;
+    S.shuffle = (o.flags & TILEQR_FLAG_SHUFFLE) ? 1 : 0;
+    S.seed = o.seed;
+    S.drop_edge = o.drop_edge;
+    S.trace = nullptr;
+    if (o.flags & TILEQR_FLAG_TRACE) {
+        if ((rc = W->trace.ensure((size_t)std::max<int64_t>(ntask, 1) * 8 * sizeof(int64_t)))) return rc;
+        S.trace = (int64_t *)W->trace.ptr;
+        S.trace_cap = (uint32_t)ntask;
+        W->trace_events = ntask;
+    }
+    // Panel workers: one matrix has at most one panel chain per step in
+    // flight, so a few suffice (at most one per XCD); many matrices get a
+    // share of the workgroups in proportion to their panel flops.  Update
+    // workers: the rest of what fits at once.
+    const int occ = worker_occupancy(nb, ib, o.precision);
+    const int capacity = std::max(2, std::max(1, W->num_cu) * occ);
+    int panel;
+    if (o.panel_workers > 0) panel = (int)o.panel_workers;
+    else if (nmat == 1) panel = (int)std::min<int64_t>(8, kmax_max);
+    else panel = (int)std::lround(1.5 * capacity * panel_flops / std::max(all_flops, 1.0));
+    panel = std::max(1, std::min(panel, capacity / 2));
+    int update = o.workers > 0 ? (int)o.workers : capacity - panel;
+    update = std::max(1, std::min(update, capacity - panel));
+    S.npanel = panel;
+    *workers = panel + update;
+    return 0;
+}
+
+}  // namespace tq
+
+namespace {
+
 // Runs the factorisation of the tiles already in W->tiles (status already
 // cleared and set by the conversion).  Either the serial Algorithm 2 driver
 // or the persistent DAG scheduler.
@@ -336,71 +442,13 @@ int run_factor(Workspace *W, int nb, int ib, int p, int q, double *T, const tile
         TQ_HIP(launch_factor_serial(nb, ib, o.precision, M, dstatus, st));
         return 0;
     }
-    const int ns = nb / kStripWidth;
-    const Grid g = make_grid(p, q, ns);
-    int64_t counts[NQUEUE] = {0};
-    int64_t ntask = 0;
-    for (int64_t id = 0; id < g.total; ++id) {
-        const Task t = decode(g, id);
-        if (valid(g, t)) {
-            ++counts[queue_of(t, ns, 0)];
-            ++ntask;
-        }
-    }
-    int rc;
-    if ((rc = W->counters.ensure((size_t)g.total * sizeof(int32_t)))) return rc;
-    const int64_t qtotal = ntask;
-    if ((rc = W->qslot.ensure((size_t)qtotal * sizeof(int32_t)))) return rc;
-    const size_t qctl_bytes = 2 * NQUEUE * 32 * sizeof(uint32_t) + 256 + NQUEUE * sizeof(int64_t);
-    if ((rc = W->qctl.ensure(qctl_bytes))) return rc;
-    if ((rc = W->mats.ensure(sizeof(MatDev)))) return rc;
-    TQ_HIP(hipMemcpyAsync(W->mats.ptr, &M, sizeof(MatDev), hipMemcpyHostToDevice, st));
+    std::vector<MatDev> mats(1, M);
     SchedDev S;
-    std::memset(&S, 0, sizeof S);
-    S.mats = (MatDev *)W->mats.ptr;
-    S.nmat = 1;
-    S.ns = ns;
-    S.total_ids = g.total;
-    S.total_tasks = (uint32_t)ntask;
-    S.counters = (int32_t *)W->counters.ptr;
-    S.qslot = (int32_t *)W->qslot.ptr;
-    S.qslot_total = qtotal;
-    int64_t qoff[NQUEUE];
-    int64_t off = 0;
-    for (int l = 0; l < NQUEUE; ++l) {
-        qoff[l] = off;
-        off += counts[l];
-    }
-    S.qhead = (uint32_t *)W->qctl.ptr;
-    S.qtail = S.qhead + NQUEUE * 32;
-    S.done = S.qtail + NQUEUE * 32;
-    S.trace_count = S.done + 1;
-    int64_t *qoff_dev = (int64_t *)((char *)W->qctl.ptr + 2 * NQUEUE * 32 * sizeof(uint32_t) + 256);
-    TQ_HIP(hipMemcpyAsync(qoff_dev, qoff, sizeof qoff, hipMemcpyHostToDevice, st));
-    S.qoff = qoff_dev;
-    S.status = dstatus;
-    S.spin_limit = o.spin_limit > 0 ? o.spin_limit : (int64_t)1 << 24;
-    S.shuffle = (o.flags & TILEQR_FLAG_SHUFFLE) ? 1 : 0;
-    S.seed = o.seed;
-    S.drop_edge = o.drop_edge;
-    S.trace = nullptr;
-    if (o.flags & TILEQR_FLAG_TRACE) {
-        if ((rc = W->trace.ensure((size_t)ntask * 8 * sizeof(int64_t)))) return rc;
-        S.trace = (int64_t *)W->trace.ptr;
-        S.trace_cap = (uint32_t)ntask;
-        W->trace_events = ntask;
-    }
-    // Panel workers: one per independent panel chain that can be in flight,
-    // at most one per XCD.  Update workers: the rest of what fits at once.
-    const int occ = worker_occupancy(nb, ib, o.precision);
-    const int capacity = std::max(2, std::max(1, W->num_cu) * occ);
-    const int panel = std::max(1, std::min({8, g.kmax, capacity / 2}));
-    int update = (int)o.workers > 0 ? (int)o.workers : capacity - panel;
-    update = std::max(1, std::min(update, capacity - panel));
-    S.npanel = panel;
+    int workers = 0, rc;
+    if ((rc = prepare_schedule(W, W->sched, mats, nb, ib, o, st, S, &workers))) return rc;
     TQ_HIP(launch_sched_init(S, st));
     if (ev_setup_done) TQ_HIP(hipEventRecord(ev_setup_done, st));
-    TQ_HIP(launch_worker(nb, ib, o.precision, S, panel + update, st));
+    TQ_HIP(launch_worker(nb, ib, o.precision, S, workers, st));
     return 0;
 }
 
@@ -523,10 +571,12 @@ extern "C" int tileqr_finalize(void)
         if (hipSetDevice(w->device) == hipSuccess) {
             (void)hipDeviceSynchronize();
             w->tiles.release();
-            w->counters.release();
-            w->qslot.release();
-            w->qctl.release();
-            w->mats.release();
+            w->sched.release();
+            w->btiles.release();
+            w->bconv.release();
+            for (auto &b : w->bsched) b.release();
+            if (w->bgraph) (void)hipGraphExecDestroy(w->bgraph);
+            if (w->cap_stream) (void)hipStreamDestroy(w->cap_stream);
             w->status.release();
             w->trace.release();
             w->misc.release();
@@ -546,15 +596,6 @@ extern "C" int tileqr_finalize(void)
     (void)hipSetDevice(cur);
     return TILEQR_OK;
 }
-// ------------------------------------------- not yet wired (filled in below)
-
-extern "C" int tileqr_factor_batched(int64_t, const int64_t *, const int64_t *, double *const *,
-                                     const int64_t *, const int64_t *, const int64_t *, double *const *,
-                                     const tileqr_opts *)
-{
-    return TILEQR_EUNSUPPORTED;
-}
-
 // ------------------------------------------------------------- applying Q
 
 namespace {

@@ -1,0 +1,429 @@
+// Batched tiled QR: many independent factorisations in one persistent
+// launch per (nb, ib) group, one global task space over all of them (each
+// matrix its own DAG of Section 4), captured into a HIP graph and replayed;
+// and the autotuner that picks nb, ib and the split of the workgroups
+// between the panel and update roles by timing trial runs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "../../include/tileqr.h"
+#include "tileqr_dag.h"
+#include "tileqr_host.h"
+#include "tileqr_internal.h"
+
+using namespace tq;
+
+namespace {
+
+struct Group {
+    int nb, ib;
+    std::vector<int64_t> members;   // batch indices (non-empty matrices only)
+    std::vector<ConvDesc> conv;
+    int64_t nblk = 0;               // 64 x 64 conversion blocks
+    SchedDev S;
+    int workers = 0;
+};
+
+const tileqr_tuning *find_tuned(Workspace *W, const std::vector<int64_t> &key)
+{
+    for (const auto &e : W->tuned)
+        if (e.key == key) return &e.best;
+    return nullptr;
+}
+
+std::vector<int64_t> shape_key(int64_t batch, const int64_t *m, const int64_t *n, int precision)
+{
+    std::vector<std::pair<int64_t, int64_t>> sh((size_t)batch);
+    for (int64_t i = 0; i < batch; ++i) sh[(size_t)i] = {m[i], n[i]};
+    std::sort(sh.begin(), sh.end());
+    std::vector<int64_t> key;
+    key.reserve(2 + 2 * (size_t)batch);
+    key.push_back(precision);
+    key.push_back(batch);
+    for (const auto &s : sh) {
+        key.push_back(s.first);
+        key.push_back(s.second);
+    }
+    return key;
+}
+
+// Blocking for a whole batch without a tuned entry: the one a single matrix
+// of the flop-weighted typical size would get.
+void default_batch_blocking(int64_t batch, const int64_t *m, const int64_t *n, int precision, int64_t *nb,
+                            int64_t *ib)
+{
+    double wsum = 0.0, ksum = 0.0;
+    for (int64_t i = 0; i < batch; ++i) {
+        const double f = tileqr_flops_lapack(m[i], n[i]);
+        wsum += f;
+        ksum += f * (double)std::min(m[i], n[i]);
+    }
+    const int64_t k = wsum > 0.0 ? (int64_t)(ksum / wsum) : 1;
+    tileqr_choose_blocking(k, k, precision, nb, ib);
+}
+
+int argcheck(int64_t batch, const int64_t *m, const int64_t *n, double *const *A, const int64_t *lda,
+             const int64_t *nb, const int64_t *ib, double *const *T)
+{
+    if (batch < 0) return -1;
+    if (batch > 0 && (!m || !n || !A || !lda || !T)) return !m ? -2 : !n ? -3 : !A ? -4 : !lda ? -5 : -8;
+    if ((nb == nullptr) != (ib == nullptr)) return nb == nullptr ? -6 : -7;
+    for (int64_t i = 0; i < batch; ++i) {
+        if (m[i] < 0 || m[i] > INT32_MAX) return -2;
+        if (n[i] < 0 || n[i] > INT32_MAX) return -3;
+        const bool empty = m[i] == 0 || n[i] == 0;
+        if (!empty && A[i] == nullptr) return -4;
+        if (lda[i] < std::max<int64_t>(1, m[i])) return -5;
+        if (nb) {
+            if (nb[i] <= 0) return -6;
+            if (ib[i] <= 0 || ib[i] > nb[i] || nb[i] % ib[i] != 0) return -7;
+        }
+        if (!empty && T[i] == nullptr) return -8;
+    }
+    return 0;
+}
+
+// The kernels of one call in stream order: clear the status, convert every
+// matrix to tiles, then per group the scheduler set-up and the persistent
+// workers, then convert every matrix back.  No memset nodes, so that the
+// sequence may be captured.
+int enqueue_batched(Workspace *W, std::vector<Group> &groups, const ConvDesc *conv_dev, int precision,
+                    hipStream_t st)
+{
+    int *dstatus = (int *)W->status.ptr;
+    TQ_HIP(launch_fill_int(dstatus, 1, 0, st));
+    size_t off = 0;
+    for (auto &g : groups) {
+        TQ_HIP(launch_cm2tile_batched(conv_dev + off, (int)g.members.size(), g.nblk, g.nb, dstatus, st));
+        off += g.members.size();
+    }
+    for (auto &g : groups) {
+        TQ_HIP(launch_sched_init(g.S, st));
+        TQ_HIP(launch_worker(g.nb, g.ib, precision, g.S, g.workers, st));
+    }
+    off = 0;
+    for (auto &g : groups) {
+        TQ_HIP(launch_tile2cm_batched(conv_dev + off, (int)g.members.size(), g.nblk, g.nb, dstatus, st));
+        off += g.members.size();
+    }
+    return 0;
+}
+
+// Arguments already checked, g_mu held.  nbv/ibv: per-matrix blocking.
+int run_batched(Workspace *W, int64_t batch, const int64_t *m, const int64_t *n, double *const *A,
+                const int64_t *lda, const int64_t *nbv, const int64_t *ibv, double *const *T, const tileqr_opts &o,
+                hipStream_t st)
+{
+    std::vector<Group> groups;
+    int64_t tile_doubles = 0;
+    for (int64_t i = 0; i < batch; ++i) {
+        if (m[i] == 0 || n[i] == 0) continue;
+        if (!tileqr_blocking_supported(nbv[i], ibv[i]) || !precision_supported(o.precision, ibv[i]))
+            return TILEQR_EUNSUPPORTED;
+        Group *g = nullptr;
+        for (auto &x : groups)
+            if (x.nb == nbv[i] && x.ib == ibv[i]) g = &x;
+        if (!g) {
+            groups.emplace_back();
+            g = &groups.back();
+            g->nb = (int)nbv[i];
+            g->ib = (int)ibv[i];
+        }
+        g->members.push_back(i);
+        const int64_t p = cdiv(m[i], nbv[i]), q = cdiv(n[i], nbv[i]);
+        tile_doubles += p * q * nbv[i] * nbv[i];
+    }
+    if (groups.empty()) return TILEQR_OK;
+    int rc;
+    if ((rc = W->btiles.ensure((size_t)tile_doubles * sizeof(double)))) return rc;
+    if ((rc = W->status.ensure(256))) return rc;
+    int64_t nconv = 0;
+    for (auto &g : groups) nconv += (int64_t)g.members.size();
+    if ((rc = W->bconv.ensure((size_t)nconv * sizeof(ConvDesc)))) return rc;
+    if (W->bsched.size() < groups.size()) W->bsched.resize(groups.size());
+
+    // Descriptors: tiles of all matrices back to back in the workspace.
+    double *tiles = (double *)W->btiles.ptr;
+    std::vector<ConvDesc> conv_all;
+    conv_all.reserve((size_t)nconv);
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+        Group &g = groups[gi];
+        std::vector<MatDev> mats;
+        mats.reserve(g.members.size());
+        for (int64_t i : g.members) {
+            ConvDesc d;
+            d.A = A[i];
+            d.lda = lda[i];
+            d.m = m[i];
+            d.n = n[i];
+            d.tiles = tiles;
+            d.p = (int32_t)cdiv(m[i], g.nb);
+            d.q = (int32_t)cdiv(n[i], g.nb);
+            d.blk0 = g.nblk;
+            g.nblk += (int64_t)d.p * d.q * (g.nb / 64) * (g.nb / 64);
+            conv_all.push_back(d);
+            MatDev M;
+            M.tiles = tiles;
+            M.T = T[i];
+            M.p = d.p;
+            M.q = d.q;
+            M.task_base = 0;
+            mats.push_back(M);
+            tiles += (size_t)d.p * d.q * g.nb * g.nb;
+        }
+        if ((rc = prepare_schedule(W, W->bsched[gi], mats, g.nb, g.ib, o, st, g.S, &g.workers))) return rc;
+    }
+    const ConvDesc *conv_dev = (const ConvDesc *)W->bconv.ptr;
+    TQ_HIP(hipMemcpyAsync(W->bconv.ptr, conv_all.data(), conv_all.size() * sizeof(ConvDesc), hipMemcpyHostToDevice,
+                          st));
+
+    if (o.flags & TILEQR_FLAG_NO_GRAPH) return enqueue_batched(W, groups, conv_dev, o.precision, st);
+
+    // Everything the captured launches hold by value.
+    std::vector<int64_t> key;
+    key.push_back(o.precision);
+    key.push_back((int64_t)(intptr_t)W->status.ptr);
+    key.push_back((int64_t)(intptr_t)conv_dev);
+    for (auto &g : groups) {
+        key.push_back(g.nb);
+        key.push_back(g.ib);
+        key.push_back((int64_t)g.members.size());
+        key.push_back(g.nblk);
+        key.push_back(g.workers);
+        int64_t words[sizeof(SchedDev) / sizeof(int64_t) + 1] = {0};
+        std::memcpy(words, &g.S, sizeof(SchedDev));
+        key.insert(key.end(), words, words + sizeof(words) / sizeof(words[0]));
+    }
+    if (!W->bgraph || key != W->bgraph_key) {
+        if (!W->cap_stream) TQ_HIP(hipStreamCreateWithFlags(&W->cap_stream, hipStreamNonBlocking));
+        if (W->bgraph) {
+            TQ_HIP(hipGraphExecDestroy(W->bgraph));
+            W->bgraph = nullptr;
+            W->bgraph_key.clear();
+        }
+        hipGraph_t graph = nullptr;
+        TQ_HIP(hipStreamBeginCapture(W->cap_stream, hipStreamCaptureModeThreadLocal));
+        const int erc = enqueue_batched(W, groups, conv_dev, o.precision, W->cap_stream);
+        const hipError_t ce = hipStreamEndCapture(W->cap_stream, &graph);
+        if (erc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return erc;
+        }
+        TQ_HIP(ce);
+        const hipError_t ie = hipGraphInstantiate(&W->bgraph, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        TQ_HIP(ie);
+        W->bgraph_key = key;
+    }
+    TQ_HIP(hipGraphLaunch(W->bgraph, st));
+    return 0;
+}
+
+}  // namespace
+
+extern "C" int tileqr_factor_batched(int64_t batch, const int64_t *m, const int64_t *n, double *const *A,
+                                     const int64_t *lda, const int64_t *nb, const int64_t *ib, double *const *T,
+                                     const tileqr_opts *opts)
+{
+    int rc = argcheck(batch, m, n, A, lda, nb, ib, T);
+    if (rc) return rc;
+    tileqr_opts o;
+    tileqr_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.precision < TILEQR_FP64 || o.precision > TILEQR_BF16X3) return -9;
+    if (o.flags & (TILEQR_FLAG_SERIAL | TILEQR_FLAG_TRACE)) return TILEQR_EUNSUPPORTED;
+    if (batch == 0) return TILEQR_OK;
+    std::lock_guard<std::mutex> lock(g_mu);
+    Workspace *W = workspace();
+    if (!W) return hip_fail(hipErrorNoDevice, "workspace");
+    hipStream_t st = (hipStream_t)o.stream;
+    std::vector<int64_t> nbv, ibv;
+    if (nb) {
+        nbv.assign(nb, nb + batch);
+        ibv.assign(ib, ib + batch);
+    } else {
+        int64_t b = 0, s = 0;
+        const tileqr_tuning *t = find_tuned(W, shape_key(batch, m, n, o.precision));
+        if (t) {
+            b = t->nb;
+            s = t->ib;
+            if (o.panel_workers == 0 && o.workers == 0) {
+                o.panel_workers = t->panel_workers;
+                o.workers = t->workers;
+            }
+        } else {
+            default_batch_blocking(batch, m, n, o.precision, &b, &s);
+        }
+        nbv.assign((size_t)batch, b);
+        ibv.assign((size_t)batch, s);
+    }
+    const bool timing = (o.flags & TILEQR_FLAG_TIMING) && !(o.flags & TILEQR_FLAG_ASYNC);
+    W->have_timing = false;
+    if (timing && !W->ev[0])
+        for (auto &e : W->ev) TQ_HIP(hipEventCreate(&e));
+    if (timing) TQ_HIP(hipEventRecord(W->ev[0], st));
+    if ((rc = run_batched(W, batch, m, n, A, lda, nbv.data(), ibv.data(), T, o, st))) return rc;
+    if (timing) TQ_HIP(hipEventRecord(W->ev[1], st));
+    if (o.flags & TILEQR_FLAG_ASYNC) return TILEQR_OK;
+    rc = check_status(W, (int *)W->status.ptr, st);
+    if (timing) {
+        float ms = 0.f;
+        TQ_HIP(hipEventElapsedTime(&ms, W->ev[0], W->ev[1]));
+        W->last_ms[0] = W->last_ms[1] = W->last_ms[3] = 0.0;
+        W->last_ms[2] = ms;
+        W->have_timing = true;
+    }
+    return rc;
+}
+
+// ------------------------------------------------------------------ tuner
+
+namespace tq {
+
+// Tuned blocking for one m x n matrix, if tileqr_tune has seen it.
+bool tuned_single(int64_t m, int64_t n, int precision, tileqr_tuning *out)
+{
+    Workspace *W = existing_workspace();
+    if (!W) return false;
+    const tileqr_tuning *t = find_tuned(W, shape_key(1, &m, &n, precision));
+    if (!t) return false;
+    *out = *t;
+    return true;
+}
+
+}  // namespace tq
+
+extern "C" int tileqr_tune(int64_t batch, const int64_t *m, const int64_t *n, int precision, int trials,
+                           tileqr_tuning *best)
+{
+    if (batch < 1) return -1;
+    if (!m) return -2;
+    if (!n) return -3;
+    for (int64_t i = 0; i < batch; ++i) {
+        if (m[i] < 0 || m[i] > INT32_MAX) return -2;
+        if (n[i] < 0 || n[i] > INT32_MAX) return -3;
+    }
+    if (precision < TILEQR_FP64 || precision > TILEQR_BF16X3) return -4;
+    if (trials < 1 || trials > 100) return -5;
+    if (!best) return -6;
+    std::lock_guard<std::mutex> lock(g_mu);
+    Workspace *W = workspace();
+    if (!W) return hip_fail(hipErrorNoDevice, "workspace");
+    if (!W->ev[0])
+        for (auto &e : W->ev) TQ_HIP(hipEventCreate(&e));
+
+    int64_t maxdim = 1, elems = 0;
+    for (int64_t i = 0; i < batch; ++i) {
+        maxdim = std::max(maxdim, std::max(m[i], n[i]));
+        elems += m[i] * n[i];
+    }
+    // Candidate blockings: every supported (nb, ib) the precision allows,
+    // skipping tile sizes larger than every matrix (their runs only pad).
+    std::vector<std::pair<int64_t, int64_t>> blockings;
+    for (int64_t b : {64, 128, 256})
+        for (int64_t s : {16, 32})
+            if ((b == 64 || b <= maxdim) && tileqr_blocking_supported(b, s) && precision_supported(precision, s))
+                blockings.push_back({b, s});
+    // Candidate splits of the workgroups: automatic, then fixed panel shares.
+    std::vector<int64_t> panels = {0};
+    if (batch == 1) {
+        panels.push_back(1);
+        panels.push_back(4);
+    } else {
+        const int64_t cu = std::max(1, W->num_cu);
+        panels.push_back(cu / 8);
+        panels.push_back(cu / 4);
+        panels.push_back(cu / 2 - 1);
+    }
+
+    // Scratch matrices (column-major, lda = m) and T areas sized for the
+    // largest T over the candidates.
+    std::vector<int64_t> lda(m, m + batch);
+    for (auto &x : lda) x = std::max<int64_t>(1, x);
+    int64_t tdoubles = 0;
+    for (int64_t i = 0; i < batch; ++i) {
+        int64_t mx = 0;
+        for (auto &bs : blockings) mx = std::max<int64_t>(mx, (int64_t)tileqr_t_size(m[i], n[i], bs.first, bs.second));
+        tdoubles += mx;
+    }
+    DevBuf Abuf, Tbuf;
+    int rc;
+    if ((rc = Abuf.ensure((size_t)std::max<int64_t>(elems, 1) * sizeof(double)))) return rc;
+    if ((rc = Tbuf.ensure((size_t)std::max<int64_t>(tdoubles, 1) * sizeof(double)))) {
+        Abuf.release();
+        return rc;
+    }
+    std::vector<double *> Ap((size_t)batch), Tp((size_t)batch);
+    {
+        double *a = (double *)Abuf.ptr, *t = (double *)Tbuf.ptr;
+        for (int64_t i = 0; i < batch; ++i) {
+            Ap[(size_t)i] = a;
+            Tp[(size_t)i] = t;
+            a += m[i] * n[i];
+            int64_t mx = 0;
+            for (auto &bs : blockings)
+                mx = std::max<int64_t>(mx, (int64_t)tileqr_t_size(m[i], n[i], bs.first, bs.second));
+            t += mx;
+        }
+    }
+    hipStream_t st = nullptr;
+    tileqr_tuning top;
+    top.ms = -1.0;
+    for (auto &bs : blockings) {
+        std::vector<int64_t> nbv((size_t)batch, bs.first), ibv((size_t)batch, bs.second);
+        for (int64_t pw : panels) {
+            tileqr_opts o;
+            tileqr_opts_default(&o);
+            o.precision = precision;
+            o.panel_workers = pw;
+            o.flags = TILEQR_FLAG_NO_GRAPH;
+            double bestms = -1.0;
+            for (int r = 0; r < trials && rc == 0; ++r) {
+                if ((rc = launch_fill_uniform((double *)Abuf.ptr, elems, 1234 + r, st)) != hipSuccess) {
+                    rc = hip_fail((hipError_t)rc, "fill");
+                    break;
+                }
+                if ((rc = hipEventRecord(W->ev[0], st)) != hipSuccess) {
+                    rc = hip_fail((hipError_t)rc, "event");
+                    break;
+                }
+                rc = run_batched(W, batch, m, n, Ap.data(), lda.data(), nbv.data(), ibv.data(), Tp.data(), o, st);
+                if (rc) break;
+                if ((rc = hipEventRecord(W->ev[1], st)) != hipSuccess) {
+                    rc = hip_fail((hipError_t)rc, "event");
+                    break;
+                }
+                if ((rc = check_status(W, (int *)W->status.ptr, st))) break;
+                float ms = 0.f;
+                (void)hipEventElapsedTime(&ms, W->ev[0], W->ev[1]);
+                if (bestms < 0.0 || ms < bestms) bestms = ms;
+            }
+            if (rc) break;
+            if (top.ms < 0.0 || bestms < top.ms) {
+                top.nb = bs.first;
+                top.ib = bs.second;
+                top.panel_workers = pw;
+                top.workers = 0;
+                top.ms = bestms;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipStreamSynchronize(st);
+    Abuf.release();
+    Tbuf.release();
+    if (rc) return rc;
+    const std::vector<int64_t> key = shape_key(batch, m, n, precision);
+    bool found = false;
+    for (auto &e : W->tuned)
+        if (e.key == key) {
+            e.best = top;
+            found = true;
+        }
+    if (!found) W->tuned.push_back(TuneEntry{key, top});
+    *best = top;
+    return TILEQR_OK;
+}

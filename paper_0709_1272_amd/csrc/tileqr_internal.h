@@ -57,6 +57,22 @@ struct ApplyDev {
     int64_t spin_limit;
 };
 
+// One matrix of a batched layout conversion.
+struct ConvDesc {
+    double *A;                // column-major caller matrix (device)
+    int64_t lda, m, n;
+    double *tiles;            // its tiles in the workspace
+    int32_t p, q;
+    int64_t blk0;             // index of its first 64 x 64 block in the launch
+};
+
+hipError_t launch_cm2tile_batched(const ConvDesc *D, int nmat, int64_t nblk, int nb, int *status, hipStream_t st);
+hipError_t launch_tile2cm_batched(const ConvDesc *D, int nmat, int64_t nblk, int nb, const int *status,
+                                  hipStream_t st);
+hipError_t launch_fill_int(int *p, int n, int v, hipStream_t st);
+// Synthetic uniform(-1, 1) entries (timing runs of the tuner).
+hipError_t launch_fill_uniform(double *A, int64_t count, uint64_t seed, hipStream_t st);
+
 hipError_t launch_apply(int nb, int ib, const ApplyDev &D, bool trans, hipStream_t st);
 hipError_t launch_cm2rows(const double *B, int64_t ldb, int64_t m, int64_t nrhs, double *Bt, int64_t rows, int ldt,
                           hipStream_t st);

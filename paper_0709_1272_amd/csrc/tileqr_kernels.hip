@@ -138,14 +138,13 @@ __global__ void k_rows2cm(double *B, int64_t ldb, int64_t m, int64_t nrhs, const
 
 // ------------------------------------------------------ layout conversion
 
-// Column-major (A, lda) -> zero-padded row-major tiles, 64 x 64 blocks via
-// an LDS transpose.  Flags NaN/Inf in *status.
-__global__ __launch_bounds__(256) void k_cm2tile(const double *A, int64_t lda, int64_t m, int64_t n,
-                                                 double *tiles, int nb, int p, int q, int *status)
+// Column-major (A, lda) -> zero-padded row-major tiles, one 64 x 64 block
+// `blk` of one matrix via an LDS transpose.  Flags NaN/Inf in *status.
+__device__ __forceinline__ void cm2tile_block(const double *A, int64_t lda, int64_t m, int64_t n, double *tiles,
+                                              int nb, int p, int64_t blk, int *status)
 {
     __shared__ double buf[64][65];
     const int sub = nb / 64;
-    const int64_t blk = blockIdx.x;
     const int si = (int)(blk % sub), sj = (int)((blk / sub) % sub);
     const int64_t tl = blk / ((int64_t)sub * sub);
     const int ti = (int)(tl % p), tj = (int)(tl / p);
@@ -171,16 +170,13 @@ __global__ __launch_bounds__(256) void k_cm2tile(const double *A, int64_t lda, i
     }
 }
 
-// Tiles -> column-major (A, lda), entries inside m x n only.  Skipped when
-// the status flags an error so that A is left as the caller gave it.
-__global__ __launch_bounds__(256) void k_tile2cm(double *A, int64_t lda, int64_t m, int64_t n,
-                                                 const double *tiles, int nb, int p, int q,
-                                                 const int *status)
+// Tiles -> column-major (A, lda), entries inside m x n only, one 64 x 64
+// block.
+__device__ __forceinline__ void tile2cm_block(double *A, int64_t lda, int64_t m, int64_t n, const double *tiles,
+                                              int nb, int p, int64_t blk)
 {
-    if (*status != 0) return;
     __shared__ double buf[64][65];
     const int sub = nb / 64;
-    const int64_t blk = blockIdx.x;
     const int si = (int)(blk % sub), sj = (int)((blk / sub) % sub);
     const int64_t tl = blk / ((int64_t)sub * sub);
     const int ti = (int)(tl % p), tj = (int)(tl / p);
@@ -196,6 +192,69 @@ __global__ __launch_bounds__(256) void k_tile2cm(double *A, int64_t lda, int64_t
         const int cc = it * 4 + t / 64, rr = t % 64;
         const int64_t r = row0 + rr, c = col0 + cc;
         if (r < m && c < n) A[c * lda + r] = buf[cc][rr];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cm2tile(const double *A, int64_t lda, int64_t m, int64_t n,
+                                                 double *tiles, int nb, int p, int q, int *status)
+{
+    cm2tile_block(A, lda, m, n, tiles, nb, p, blockIdx.x, status);
+}
+
+// Skipped when the status flags an error so that A is left as the caller
+// gave it.
+__global__ __launch_bounds__(256) void k_tile2cm(double *A, int64_t lda, int64_t m, int64_t n,
+                                                 const double *tiles, int nb, int p, int q,
+                                                 const int *status)
+{
+    if (*status != 0) return;
+    tile2cm_block(A, lda, m, n, tiles, nb, p, blockIdx.x);
+}
+
+// Matrix of a batched conversion that owns block `blk` (blocks of the
+// matrices are numbered consecutively from D[i].blk0).
+__device__ __forceinline__ int conv_owner(const ConvDesc *D, int nmat, int64_t blk)
+{
+    int lo = 0, hi = nmat - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (D[mid].blk0 <= blk) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_cm2tile_batched(const ConvDesc *D, int nmat, int nb, int *status)
+{
+    const int64_t blk = blockIdx.x;
+    const ConvDesc &d = D[conv_owner(D, nmat, blk)];
+    cm2tile_block(d.A, d.lda, d.m, d.n, d.tiles, nb, d.p, blk - d.blk0, status);
+}
+
+// All or nothing: with any input rejected no matrix is written back.
+__global__ __launch_bounds__(256) void k_tile2cm_batched(const ConvDesc *D, int nmat, int nb, const int *status)
+{
+    if (*status != 0) return;
+    const int64_t blk = blockIdx.x;
+    const ConvDesc &d = D[conv_owner(D, nmat, blk)];
+    tile2cm_block(d.A, d.lda, d.m, d.n, d.tiles, nb, d.p, blk - d.blk0);
+}
+
+// p[0..n) <- v (a kernel, so that it may sit in a captured graph).
+__global__ void k_fill_int(int *p, int n, int v)
+{
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) p[e] = v;
+}
+
+// A[e] <- uniform(-1, 1) from a counter-based hash of (seed, e): synthetic
+// matrices for timing runs only.
+__global__ void k_fill_uniform(double *A, int64_t count, uint64_t seed)
+{
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        uint64_t x = seed * 0x9e3779b97f4a7c15ULL + (uint64_t)e;
+        x = mix64(x + 0x632be59bd9b4e019ULL);
+        A[e] = (double)(x >> 11) * (2.0 / 9007199254740992.0) - 1.0;
     }
 }
 
@@ -231,6 +290,36 @@ hipError_t launch_tile2cm(double *A, int64_t lda, int64_t m, int64_t n, const do
         else if (nb == 256 && ib == 32) { CALL(256, 32); }          \
         else return hipErrorInvalidValue;                           \
     } while (0)
+
+hipError_t launch_cm2tile_batched(const ConvDesc *D, int nmat, int64_t nblk, int nb, int *status, hipStream_t st)
+{
+    if (nblk == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cm2tile_batched, dim3((unsigned)nblk), dim3(256), 0, st, D, nmat, nb, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile2cm_batched(const ConvDesc *D, int nmat, int64_t nblk, int nb, const int *status,
+                                  hipStream_t st)
+{
+    if (nblk == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile2cm_batched, dim3((unsigned)nblk), dim3(256), 0, st, D, nmat, nb, status);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int *p, int n, int v, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_int, dim3((unsigned)std::min(1024, (n + 255) / 256)), dim3(256), 0, st, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_uniform(double *A, int64_t count, uint64_t seed, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_fill_uniform, dim3((unsigned)blocks), dim3(256), 0, st, A, count, seed);
+    return hipGetLastError();
+}
 
 hipError_t launch_factor_serial(int nb, int ib, int prec, const MatDev &M, const int *status, hipStream_t st)
 {

@@ -23,14 +23,20 @@ _L = ctypes.CDLL(LIB_PATH)
 
 OK, EHIP, ENONFINITE, ENOCONV, ETIMEOUT, ENOMEM, EUNSUPPORTED, ESINGULAR = range(8)
 FP64, BF16X2, FP16X2, BF16X3 = range(4)
-FLAG_ASYNC, FLAG_SERIAL, FLAG_TRACE, FLAG_SHUFFLE, FLAG_TIMING = 1, 2, 4, 8, 16
+FLAG_ASYNC, FLAG_SERIAL, FLAG_TRACE, FLAG_SHUFFLE, FLAG_TIMING, FLAG_NO_GRAPH = 1, 2, 4, 8, 16, 32
 
 
 class Opts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("nb", ctypes.c_int64), ("ib", ctypes.c_int64),
                 ("max_iter", ctypes.c_int), ("tol", ctypes.c_double), ("stream", ctypes.c_void_p),
                 ("flags", ctypes.c_uint), ("seed", ctypes.c_uint64), ("spin_limit", ctypes.c_int64),
-                ("workers", ctypes.c_int64), ("drop_edge", ctypes.c_int64)]
+                ("workers", ctypes.c_int64), ("drop_edge", ctypes.c_int64),
+                ("panel_workers", ctypes.c_int64)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("nb", ctypes.c_int64), ("ib", ctypes.c_int64), ("panel_workers", ctypes.c_int64),
+                ("workers", ctypes.c_int64), ("ms", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
@@ -55,6 +61,7 @@ _SIGS = {
                                ctypes.POINTER(Opts), ctypes.POINTER(Info)]),
     "tileqr_factor_batched": (_int, [_i64, _I64P, _I64P, ctypes.POINTER(_vp), _I64P, _I64P, _I64P,
                                      ctypes.POINTER(_vp), ctypes.POINTER(Opts)]),
+    "tileqr_tune": (_int, [_i64, _I64P, _I64P, _int, _int, ctypes.POINTER(Tuning)]),
     "tileqr_flops_lapack": (_dbl, [_i64, _i64]),
     "tileqr_flops_tiled": (_dbl, [_i64, _i64, _i64, _i64]),
     "tileqr_dag_counts": (_i64, [_i64, _i64, _i64, _I64P]),
@@ -138,6 +145,16 @@ def factor_batched(ms, ns, A_ptrs, ldas, nbs, ibs, T_ptrs, o=None):
     return _L.tileqr_factor_batched(b, arr(ms), arr(ns), ptrs(A_ptrs), arr(ldas),
                                     arr(nbs) if nbs is not None else None,
                                     arr(ibs) if ibs is not None else None, ptrs(T_ptrs), _ptr_opts(o))
+
+
+def tune(ms, ns, precision=FP64, trials=2):
+    """Autotune (tileqr_tune) for matrices of these shapes; returns a Tuning
+    (nb, ib, panel_workers, workers, ms) and raises on an error status."""
+    b = len(ms)
+    arr = lambda vals: (ctypes.c_int64 * b)(*[int(v) for v in vals])
+    t = Tuning()
+    check(_L.tileqr_tune(b, arr(ms), arr(ns), precision, trials, ctypes.byref(t)), "tileqr_tune")
+    return t
 
 
 def flops_lapack(m, n):
