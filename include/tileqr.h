@@ -274,10 +274,13 @@ int64_t tileqr_dag_counts(int64_t p, int64_t q, int64_t strips, int64_t counts[4
 int tileqr_dag_selfcheck(int64_t p, int64_t q, int64_t strips, int64_t trials, uint64_t seed);
 
 /* Trace of the last factorisation run with TILEQR_FLAG_TRACE: up to `cap`
- * events copied to host memory, 8 int64 each: {type, k, i, j, strip,
- * worker, t_start, t_end} (types 0 GEQRT, 1 TSQRT, 2 LARFB, 3 SSRFB;
- * times in ticks of the device wall clock, tileqr_trace_clock_hz per second).
- * Returns the number of events available. */
+ * events copied to host memory, 10 int64 each: {type, k, i, j, strip,
+ * worker, t_pop, t_start, t_body_end, t_end} (types 0 GEQRT, 1 TSQRT,
+ * 2 LARFB, 3 SSRFB; worker = (role << 16) | workgroup; times in ticks of
+ * the device wall clock, tileqr_trace_clock_hz per second: when the task
+ * was taken from its queue, when its body started after the acquire fence,
+ * when the body ended, and when the release fence and the successor
+ * updates were done).  Returns the number of events available. */
 int64_t tileqr_trace(int64_t *events, int64_t cap);
 double tileqr_trace_clock_hz(void);
 

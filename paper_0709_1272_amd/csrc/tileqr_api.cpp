@@ -364,7 +364,7 @@ int prepare_schedule(Workspace *W, SchedBufs &B, std::vector<MatDev> &mats, int 
     int rc;
     if ((rc = B.counters.ensure((size_t)total_ids * sizeof(int32_t)))) return rc;
     if ((rc = B.qslot.ensure((size_t)std::max<int64_t>(ntask, 1) * sizeof(int32_t)))) return rc;
-    const size_t qctl_bytes = 2 * NQUEUE * 32 * sizeof(uint32_t) + 256 + NQUEUE * sizeof(int64_t);
+    const size_t qctl_bytes = 2 * NQUEUE * QSTRIDE * sizeof(uint32_t) + 256 + NQUEUE * sizeof(int64_t);
     if ((rc = B.qctl.ensure(qctl_bytes))) return rc;
     if ((rc = B.mats.ensure((size_t)nmat * sizeof(MatDev)))) return rc;
     TQ_HIP(hipMemcpyAsync(B.mats.ptr, mats.data(), (size_t)nmat * sizeof(MatDev), hipMemcpyHostToDevice, st));
@@ -384,10 +384,10 @@ int prepare_schedule(Workspace *W, SchedBufs &B, std::vector<MatDev> &mats, int 
         off += counts[l];
     }
     S.qhead = (uint32_t *)B.qctl.ptr;
-    S.qtail = S.qhead + NQUEUE * 32;
-    S.done = S.qtail + NQUEUE * 32;
+    S.qtail = S.qhead + NQUEUE * QSTRIDE;
+    S.done = S.qtail + NQUEUE * QSTRIDE;
     S.trace_count = S.done + 1;
-    int64_t *qoff_dev = (int64_t *)((char *)B.qctl.ptr + 2 * NQUEUE * 32 * sizeof(uint32_t) + 256);
+    int64_t *qoff_dev = (int64_t *)((char *)B.qctl.ptr + 2 * NQUEUE * QSTRIDE * sizeof(uint32_t) + 256);
     TQ_HIP(hipMemcpyAsync(qoff_dev, qoff, sizeof qoff, hipMemcpyHostToDevice, st));
     S.qoff = qoff_dev;
     S.status = (int32_t *)W->status.ptr;
@@ -397,7 +397,7 @@ int prepare_schedule(Workspace *W, SchedBufs &B, std::vector<MatDev> &mats, int 
     S.drop_edge = o.drop_edge;
     S.trace = nullptr;
     if (o.flags & TILEQR_FLAG_TRACE) {
-        if ((rc = W->trace.ensure((size_t)std::max<int64_t>(ntask, 1) * 8 * sizeof(int64_t)))) return rc;
+        if ((rc = W->trace.ensure((size_t)std::max<int64_t>(ntask, 1) * TRACE_WORDS * sizeof(int64_t)))) return rc;
         S.trace = (int64_t *)W->trace.ptr;
         S.trace_cap = (uint32_t)ntask;
         W->trace_events = ntask;
@@ -529,7 +529,8 @@ extern "C" int64_t tileqr_trace(int64_t *events, int64_t cap)
     const int64_t n = std::min(cap, W->trace_events);
     if (events && n > 0) {
         if (hipDeviceSynchronize() != hipSuccess) return 0;
-        if (hipMemcpy(events, W->trace.ptr, (size_t)n * 8 * sizeof(int64_t), hipMemcpyDeviceToHost) != hipSuccess)
+        if (hipMemcpy(events, W->trace.ptr, (size_t)n * TRACE_WORDS * sizeof(int64_t), hipMemcpyDeviceToHost) !=
+            hipSuccess)
             return 0;
     }
     return W->trace_events;

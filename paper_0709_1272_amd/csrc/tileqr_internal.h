@@ -20,6 +20,15 @@ struct MatDev {
     int64_t task_base;   // first global task id of this matrix
 };
 
+// Words of one trace event: type, k, i, j, strip, worker, then the device
+// wall clock when the task was popped, when it started (after the acquire),
+// when its body ended and when its successors were released.
+constexpr int TRACE_WORDS = 10;
+
+// Words between the head (or tail) words of two ready queues: 4 KiB, so
+// that the queues' control words sit on different memory channels.
+constexpr int QSTRIDE = 1024;
+
 // Scheduler state in device memory (all pointers are device pointers).
 struct SchedDev {
     MatDev *mats;
@@ -32,15 +41,15 @@ struct SchedDev {
     int32_t *qslot;           // slots of all ready queues, back to back
     int64_t qslot_total;
     const int64_t *qoff;      // [NQUEUE] offset of each queue's slots
-    uint32_t *qhead;          // [NQUEUE * 32] (one 128-byte line per queue)
-    uint32_t *qtail;          // [NQUEUE * 32]
+    uint32_t *qhead;          // [NQUEUE * QSTRIDE], word q * QSTRIDE for queue q
+    uint32_t *qtail;          // [NQUEUE * QSTRIDE]
     uint32_t *done;           // completed tasks
     int32_t *status;          // STATUS_* flags
     int64_t spin_limit;       // idle polls without progress before STATUS_TIMEOUT
     int32_t shuffle;          // pseudo-random pop order
     uint64_t seed;
     int64_t drop_edge;        // debug: task whose first release is skipped (-1: none)
-    int64_t *trace;           // [trace_cap * 8] or NULL
+    int64_t *trace;           // [trace_cap * TRACE_WORDS] or NULL
     uint32_t *trace_count;
     uint32_t trace_cap;
 };

@@ -19,9 +19,9 @@ __global__ void k_sched_init(SchedDev S)
         S.counters[gid] = valid(g, t) ? indegree(g, t) : -1;
     }
     for (int64_t e = tid0; e < S.qslot_total; e += stride) S.qslot[e] = 0;
-    for (int64_t e = tid0; e < NQUEUE * 32; e += stride) {
-        S.qhead[e] = 0;
-        S.qtail[e] = 0;
+    for (int64_t e = tid0; e < NQUEUE; e += stride) {
+        S.qhead[e * QSTRIDE] = 0;
+        S.qtail[e * QSTRIDE] = 0;
     }
     if (tid0 == 0) {
         *S.done = 0;
@@ -36,7 +36,7 @@ __global__ void k_sched_seed(SchedDev S)
     for (int mi = threadIdx.x; mi < S.nmat; mi += blockDim.x)
         S.qslot[S.qoff[queue_index(0, 0)] + mi] = (int32_t)(S.mats[mi].task_base + 1);
     __syncthreads();
-    if (threadIdx.x == 0) S.qtail[queue_index(0, 0) * 32] = (uint32_t)S.nmat;
+    if (threadIdx.x == 0) S.qtail[queue_index(0, 0) * QSTRIDE] = (uint32_t)S.nmat;
 }
 
 // -------------------------------------------------- applying Q and Q^T

@@ -273,7 +273,7 @@ __device__ __forceinline__ double sum_slots(const Smem<NB, IB> &sm, int e)
 // tile (the R rows the TS form also updates), row stride ldtop.
 // Three workgroup barriers; the products V^T X, T^T W and V W run on MFMA.
 template <int NB, int IB, bool TRANS = true>
-__device__ void apply_panel(Smem<NB, IB> &sm, Strip<NB, IB> &X, int rlo, gdouble *top, int ldtop, int cbn)
+__device__ __forceinline__ void apply_panel(Smem<NB, IB> &sm, Strip<NB, IB> &X, int rlo, gdouble *top, int ldtop, int cbn)
 {
     using C = Cfg<NB, IB>;
     const int tid = threadIdx.x, w = wave_id();
@@ -453,7 +453,7 @@ __device__ __forceinline__ void column_scale(const double (&x)[8], double &scale
 // precision; ib = 32 so that each wave's share of a product is one K step.
 // Waves whose 32 rows lie above rlo (a multiple of 32) sit the products out.
 template <int NB, int IB, int PREC>
-__device__ void apply_panel_mx(Smem<NB, IB> &sm, Strip<NB, IB> &X, int rlo, gdouble *top, int ldtop)
+__device__ __forceinline__ void apply_panel_mx(Smem<NB, IB> &sm, Strip<NB, IB> &X, int rlo, gdouble *top, int ldtop)
 {
     using C = Cfg<NB, IB>;
     static_assert(IB == 32, "split-precision updates take ib = 32");
@@ -624,39 +624,58 @@ __device__ __forceinline__ double group_max(double v)
 // publishes v and tau through LDS (two buffers by column parity, so that
 // column j+1 may publish while column j's updates still read), then every
 // later column applies it.
-template <int NB, int IB>
-__device__ void panel_factor(Smem<NB, IB> &sm, int c0, bool ts)
+template <int NB, int IB, bool TS>
+__device__ __forceinline__ void panel_factor(Smem<NB, IB> &sm, int c0)
 {
     using C = Cfg<NB, IB>;
     constexpr int RG = C::RG, RPT = C::RPT, LDP = C::LDP;
     static_assert(64 % RG == 0, "the threads of a column share one wave");
+    static_assert(RPT % 4 == 0, "four partial sums per thread");
+    // Register slot i of lane rg holds relative row rr = rg + i RG of the
+    // column, absolute row rbase + rr: GEQRT counts from the diagonal block
+    // (rows below nb are zero padding, which no reflector changes), so only
+    // the slots i RG < ib can lie on or above a column's diagonal and need
+    // a per-row test; TSQRT's tile rows are all below its head.
+    constexpr int NHEAD = TS ? 0 : (IB + RG - 1) / RG;
     const int tid = threadIdx.x, c = tid / RG, rg = tid % RG;
+    const int rbase = TS ? 0 : c0;
     double pr[RPT];
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) pr[i] = sm.P[(rg + i * RG) * LDP + c];
+    for (int i = 0; i < RPT; ++i) {
+        const int row = rbase + rg + i * RG;
+        pr[i] = (TS || row < NB) ? sm.P[row * LDP + c] : 0.0;
+    }
+    // The later columns read the reflector buffers with a zero weight when a
+    // column has no reflector (tau = 0), so they must hold finite numbers.
+    for (int e = tid; e < 2 * NB; e += C::NT) (&sm.xb[0][0])[e] = 0.0;
+    __syncthreads();
 #pragma unroll 1
     for (int j = 0; j < IB; ++j) {
-        const int hrow = ts ? NB + j : c0 + j;
-        const int tlo = ts ? 0 : c0 + j + 1;
+        const int hrow = NB + j;   // TSQRT: row j of the triangle, kept in P
         double *xb = sm.xb[j & 1];
         double *sc = sm.sc[j & 1];
+        // tail(i): slot i is below column j's diagonal; head(i): on it.
+        auto tail = [&](int i) { return TS || i >= NHEAD || rg + i * RG > j; };
+        auto head = [&](int i) { return !TS && i < NHEAD && rg + i * RG == j; };
         if (c == j) {
             double alpha;
-            if (ts) {
+            if constexpr (TS) {
                 alpha = sm.P[hrow * LDP + j];
             } else {
                 double h = 0.0;
 #pragma unroll
-                for (int i = 0; i < RPT; ++i)
-                    if (rg + i * RG == hrow) h = pr[i];
+                for (int i = 0; i < NHEAD; ++i)
+                    if (head(i)) h = pr[i];
                 alpha = group_sum<RG>(h);   // only the owner contributes
             }
-            double part = 0.0;
+            // Sum of squares of the tail in four independent chains.
+            double q[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
-                const double x = rg + i * RG >= tlo ? pr[i] : 0.0;
-                part += x * x;
+                const double x = tail(i) ? pr[i] : 0.0;
+                q[i & 3] += x * x;
             }
+            const double part = (q[0] + q[1]) + (q[2] + q[3]);
             const double sig = group_sum<RG>(part);
             double xnorm, h;
             if (sig <= 1.0e300 && (sig >= 2.2250738585072014e-308 || sig == 0.0)) {
@@ -673,12 +692,12 @@ __device__ void panel_factor(Smem<NB, IB> &sm, int c0, bool ts)
                 double mx = 0.0;
 #pragma unroll
                 for (int i = 0; i < RPT; ++i)
-                    if (rg + i * RG >= tlo) mx = fmax(mx, fabs(pr[i]));
+                    if (tail(i)) mx = fmax(mx, fabs(pr[i]));
                 const double mxa = group_max<RG>(mx);
                 double p2 = 0.0;
 #pragma unroll
                 for (int i = 0; i < RPT; ++i) {
-                    const double t = rg + i * RG >= tlo ? pr[i] / mxa : 0.0;
+                    const double t = tail(i) ? pr[i] / mxa : 0.0;
                     p2 += t * t;
                 }
                 xnorm = mxa * sqrt(group_sum<RG>(p2));
@@ -691,14 +710,13 @@ __device__ void panel_factor(Smem<NB, IB> &sm, int c0, bool ts)
                 const double scal = 1.0 / (alpha - beta);
 #pragma unroll
                 for (int i = 0; i < RPT; ++i) {
-                    const int r = rg + i * RG;
-                    if (r >= tlo) {
+                    if (tail(i)) {
                         pr[i] = pr[i] * scal;
-                        xb[r] = pr[i];
+                        xb[rg + i * RG] = pr[i];
                     }
-                    if (!ts && r == hrow) pr[i] = beta;
+                    if (head(i)) pr[i] = beta;
                 }
-                if (ts && rg == 0) sm.P[hrow * LDP + j] = beta;
+                if (TS && rg == 0) sm.P[hrow * LDP + j] = beta;
             }
             if (rg == 0) {
                 sc[0] = tau;
@@ -706,52 +724,50 @@ __device__ void panel_factor(Smem<NB, IB> &sm, int c0, bool ts)
             }
         }
         __syncthreads();
-        const double tau = sc[0];
-        if (c > j && tau != 0.0) {
-            double part = 0.0;
-#pragma unroll
-            for (int i = 0; i < RPT; ++i) {
-                const int r = rg + i * RG;
-                if (r >= tlo) part += xb[r] * pr[i];
-            }
-            const double dot = group_sum<RG>(part);
+        if (c > j) {
+            // Loads of tau, v and the head entry are issued together; with
+            // tau = 0 the update below subtracts exact zeros.
+            const double tau = sc[0];
             double hc;
-            if (ts) {
-                hc = sm.P[hrow * LDP + c];
-            } else {
+            if constexpr (TS) hc = sm.P[hrow * LDP + c];
+            double q[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+                if (tail(i)) q[i & 3] += xb[rg + i * RG] * pr[i];
+            const double dot = group_sum<RG>((q[0] + q[1]) + (q[2] + q[3]));
+            if constexpr (!TS) {
                 double h = 0.0;
 #pragma unroll
-                for (int i = 0; i < RPT; ++i)
-                    if (rg + i * RG == hrow) h = pr[i];
+                for (int i = 0; i < NHEAD; ++i)
+                    if (head(i)) h = pr[i];
                 hc = group_sum<RG>(h);   // only the owner contributes
             }
             const double tw = tau * (hc + dot);
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
-                const int r = rg + i * RG;
-                if (r >= tlo) pr[i] -= xb[r] * tw;
-                if (!ts && r == hrow) pr[i] = hc - tw;
+                if (tail(i)) pr[i] -= xb[rg + i * RG] * tw;
+                if (head(i)) pr[i] = hc - tw;
             }
-            if (ts && rg == 0) sm.P[hrow * LDP + c] = hc - tw;
+            if (TS && rg == 0) sm.P[hrow * LDP + c] = hc - tw;
         }
     }
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-        const int r = rg + i * RG;
-        if (ts || r >= c0) sm.P[r * LDP + c] = pr[i];
+        const int row = rbase + rg + i * RG;
+        if (TS || row < NB) sm.P[row * LDP + c] = pr[i];
     }
     __syncthreads();
 }
 
 // T of the panel in sm.P (rows >= rlo; V with its unit diagonal explicit):
 // G = V^T V on MFMA, then column by column (compact WY, forward)
-//   T[j][j] = tau_j,  T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j].
-// Lane i builds row i of T in registers: its entries only depend on the
-// row's earlier entries, and with the loops unrolled each new entry waits
-// for one multiply-add after the previous one.  Leaves T in sm.Tl and writes
-// it to Tg (row-major ib x ib).
+//   T[j][j] = tau_j,  T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j]
+// inside diagonal blocks of 16 (lane i builds row i of its block in
+// registers: each new entry waits for one multiply-add after the previous
+// one), and for ib = 32 the off-diagonal block from the two diagonal ones.
+// Leaves T in sm.Tl and writes it to Tg (row-major ib x ib).
 template <int NB, int IB>
-__device__ void build_t(Smem<NB, IB> &sm, int rlo, gdouble *Tg)
+__device__ __forceinline__ void build_t(Smem<NB, IB> &sm, int rlo, gdouble *Tg)
 {
     using C = Cfg<NB, IB>;
     const int tid = threadIdx.x, w = wave_id();
@@ -779,20 +795,49 @@ __device__ void build_t(Smem<NB, IB> &sm, int rlo, gdouble *Tg)
     waves_to_slots<NB, IB, C::IBB, C::IBB>(sm, G, IB);
     for (int e = tid; e < IB * IB; e += C::NT) sm.Wa[e] = sum_slots<NB, IB>(sm, e);
     __syncthreads();
+    // Diagonal blocks of 16 (T11, T22 for ib = 32) by the recurrence, one
+    // lane per row, both blocks at once.
+    constexpr int HB = 16;
     if (tid < IB) {
-        const int i = tid;
-        double trow[IB];
+        const int i = tid, base = (i / HB) * HB, li = i - base;
+        double trow[HB];
 #pragma unroll
-        for (int kk = 0; kk < IB; ++kk) trow[kk] = kk == i ? sm.tau[kk] : 0.0;
+        for (int kk = 0; kk < HB; ++kk) trow[kk] = kk == li ? sm.tau[base + kk] : 0.0;
 #pragma unroll
-        for (int j = 1; j < IB; ++j) {
+        for (int j = 1; j < HB; ++j) {
             double s = 0.0;
 #pragma unroll
-            for (int kk = 0; kk < j; ++kk) s += trow[kk] * sm.Wa[kk * IB + j];
-            if (i < j) trow[j] = -sm.tau[j] * s;
+            for (int kk = 0; kk < j; ++kk) s += trow[kk] * sm.Wa[(base + kk) * IB + base + j];
+            if (li < j) trow[j] = -sm.tau[base + j] * s;
         }
 #pragma unroll
-        for (int kk = 0; kk < IB; ++kk) sm.Tl[i * IB + kk] = trow[kk];
+        for (int kk = 0; kk < HB; ++kk) {
+            sm.Tl[i * IB + base + kk] = trow[kk];
+            if constexpr (IB == 2 * HB) sm.Tl[i * IB + (HB - base) + kk] = 0.0;
+        }
+    }
+    if constexpr (IB == 2 * HB) {
+        // Off-diagonal block: the product of the two block reflectors gives
+        // T12 = -T11 (V1^T V2) T22 (G12 = V1^T V2 is block (0, 1) of G).
+        // One wave, two 16 x 16 x 16 products on MFMA via sm.Wb.
+        __syncthreads();
+        if (w == 0) {
+            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kc = 0; kc < HB / 4; ++kc)
+                acc = mfma(sm.Wa[n * IB + HB + 4 * kc + g], sm.Tl[(HB + 4 * kc + g) * IB + HB + n], acc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sm.Wb[(4 * r + g) * HB + n] = acc[r];
+        }
+        __syncthreads();
+        if (w == 0) {
+            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kc = 0; kc < HB / 4; ++kc)
+                acc = mfma(sm.Tl[n * IB + 4 * kc + g], sm.Wb[(4 * kc + g) * HB + n], acc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sm.Tl[(4 * r + g) * IB + HB + n] = -acc[r];
+        }
     }
     __syncthreads();
     for (int e = tid; e < IB * IB; e += C::NT) Tg[e] = sm.Tl[e];
@@ -802,7 +847,7 @@ __device__ void build_t(Smem<NB, IB> &sm, int rlo, gdouble *Tg)
 
 // DGEQRT(A_kk) -> (V_kk, R_kk, T_kk).
 template <int NB, int IB>
-__device__ void task_geqrt(Smem<NB, IB> &sm, const MatDev &M, int k)
+__device__ __forceinline__ void task_geqrt(Smem<NB, IB> &sm, const MatDev &M, int k)
 {
     using C = Cfg<NB, IB>;
     gdouble *tkk = tile_ptr(M, NB, k, k);
@@ -814,7 +859,7 @@ __device__ void task_geqrt(Smem<NB, IB> &sm, const MatDev &M, int k)
         stage_load<NB, IB>(S, tkk, c0, c0, Tk);
         stage_store<NB, IB>(sm, S, c0, false, c0);
         __syncthreads();
-        panel_factor<NB, IB>(sm, c0, false);
+        panel_factor<NB, IB, false>(sm, c0);
         // Write R and V back; keep V with explicit unit diagonal in LDS.
         constexpr int H = IB / 2;
 #pragma unroll
@@ -847,7 +892,7 @@ __device__ void task_geqrt(Smem<NB, IB> &sm, const MatDev &M, int k)
 
 // DTSQRT(R_kk, A_ik) -> (R_kk, V_ik, T_ik).
 template <int NB, int IB>
-__device__ void task_tsqrt(Smem<NB, IB> &sm, const MatDev &M, int k, int i)
+__device__ __forceinline__ void task_tsqrt(Smem<NB, IB> &sm, const MatDev &M, int k, int i)
 {
     using C = Cfg<NB, IB>;
     gdouble *tkk = tile_ptr(M, NB, k, k);
@@ -865,7 +910,7 @@ __device__ void task_tsqrt(Smem<NB, IB> &sm, const MatDev &M, int k, int i)
         }
         stage_store<NB, IB>(sm, S, 0, false, c0);
         __syncthreads();
-        panel_factor<NB, IB>(sm, c0, true);
+        panel_factor<NB, IB, true>(sm, c0);
         for (int e = threadIdx.x; e < IB * IB; e += C::NT) {
             const int r = e / IB, c = e % IB;
             if (r <= c) tkk[(size_t)(c0 + r) * NB + c0 + c] = sm.P[(NB + r) * C::LDP + c];
@@ -895,7 +940,7 @@ __device__ void task_tsqrt(Smem<NB, IB> &sm, const MatDev &M, int k, int i)
 // blocks Tk.  Q_kk = H_0 ... H_{t-1} over the inner panels, so Q_kk^T runs
 // the panels forward with T^T and Q_kk backward with T.
 template <int NB, int IB, bool TRANS, int PREC = PREC_FP64>
-__device__ void apply_diag_strip(Smem<NB, IB> &sm, const gdouble *tkk, const gdouble *Tk, gdouble *x, int ldx,
+__device__ __forceinline__ void apply_diag_strip(Smem<NB, IB> &sm, const gdouble *tkk, const gdouble *Tk, gdouble *x, int ldx,
                                  int col0)
 {
     static_assert(PREC == PREC_FP64 || TRANS, "split precision is used for Q^T only");
@@ -927,7 +972,7 @@ __device__ void apply_diag_strip(Smem<NB, IB> &sm, const gdouble *tkk, const gdo
 // Ti; `top` is the whole upper tile (its rows c0.. are the ones each inner
 // panel touches).
 template <int NB, int IB, bool TRANS, int PREC = PREC_FP64>
-__device__ void apply_ts_strip(Smem<NB, IB> &sm, const gdouble *tik, const gdouble *Ti, gdouble *top, int ldtop,
+__device__ __forceinline__ void apply_ts_strip(Smem<NB, IB> &sm, const gdouble *tik, const gdouble *Ti, gdouble *top, int ldtop,
                                gdouble *x, int ldx, int col0)
 {
     static_assert(PREC == PREC_FP64 || TRANS, "split precision is used for Q^T only");
@@ -956,7 +1001,7 @@ __device__ void apply_ts_strip(Smem<NB, IB> &sm, const gdouble *tik, const gdoub
 
 // DLARFB: strip s of A_kj <- Q_kk^T A_kj.
 template <int NB, int IB, int PREC>
-__device__ void task_larfb(Smem<NB, IB> &sm, const MatDev &M, int k, int j, int s)
+__device__ __forceinline__ void task_larfb(Smem<NB, IB> &sm, const MatDev &M, int k, int j, int s)
 {
     apply_diag_strip<NB, IB, true, PREC>(sm, tile_ptr(M, NB, k, k), tblock_ptr(M, NB, IB, k, k), tile_ptr(M, NB, k, j), NB,
                                    s * WS);
@@ -964,7 +1009,7 @@ __device__ void task_larfb(Smem<NB, IB> &sm, const MatDev &M, int k, int j, int 
 
 // DSSRFB: strip s of [A_kj; A_ij] <- Q_ik^T [A_kj; A_ij].
 template <int NB, int IB, int PREC>
-__device__ void task_ssrfb(Smem<NB, IB> &sm, const MatDev &M, int k, int i, int j, int s)
+__device__ __forceinline__ void task_ssrfb(Smem<NB, IB> &sm, const MatDev &M, int k, int i, int j, int s)
 {
     apply_ts_strip<NB, IB, true, PREC>(sm, tile_ptr(M, NB, i, k), tblock_ptr(M, NB, IB, k, i), tile_ptr(M, NB, k, j), NB,
                                  tile_ptr(M, NB, i, j), NB, s * WS);
@@ -1019,7 +1064,7 @@ __device__ __forceinline__ uint32_t ld_rlx(const uint32_t *p)
 
 __device__ __forceinline__ void push_task(const SchedDev &S, int queue, int64_t gid)
 {
-    const uint32_t slot = __hip_atomic_fetch_add(&S.qtail[queue * 32], 1u, __ATOMIC_RELAXED,
+    const uint32_t slot = __hip_atomic_fetch_add(&S.qtail[queue * QSTRIDE], 1u, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
     __hip_atomic_store(&S.qslot[S.qoff[queue] + slot], (int32_t)(gid + 1), __ATOMIC_RELEASE,
                        __HIP_MEMORY_SCOPE_AGENT);
@@ -1029,13 +1074,13 @@ __device__ __forceinline__ void push_task(const SchedDev &S, int queue, int64_t 
 __device__ __forceinline__ int64_t pop_task(const SchedDev &S, int queue)
 {
     for (int attempt = 0; attempt < 4; ++attempt) {
-        const uint32_t t = ld_rlx(&S.qtail[queue * 32]);
-        const uint32_t h = ld_rlx(&S.qhead[queue * 32]);
+        const uint32_t t = ld_rlx(&S.qtail[queue * QSTRIDE]);
+        const uint32_t h = ld_rlx(&S.qhead[queue * QSTRIDE]);
         if (h >= t) return -1;
         const int32_t v = ld_acq(&S.qslot[S.qoff[queue] + h]);
         if (v == 0) return -1;
         uint32_t expect = h;
-        if (__hip_atomic_compare_exchange_strong(&S.qhead[queue * 32], &expect, h + 1, __ATOMIC_ACQ_REL,
+        if (__hip_atomic_compare_exchange_strong(&S.qhead[queue * QSTRIDE], &expect, h + 1, __ATOMIC_ACQ_REL,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             return (int64_t)v - 1;
     }
@@ -1099,56 +1144,66 @@ __device__ __forceinline__ int64_t pop_any(const SchedDev &S, int xcd, bool stea
 template <int NB, int IB, int ROLE, int PREC>
 __device__ __forceinline__ void worker_loop(Smem<NB, IB> &sm, const SchedDev &S)
 {
-    __shared__ int64_t s_gid;
+    __shared__ int64_t s_gid, s_next;
     __shared__ int s_exit;
+    __shared__ uint64_t s_tpop, s_trun;
     const int tid = threadIdx.x;
     uint64_t rng = mix64(S.seed ^ (0x9e3779b97f4a7c15ULL * (blockIdx.x + 1)));
     const int xcd = xcd_id();
+    // Idle polling goes to a few memory lines that every worker shares, so
+    // it is kept sparse: update workers back off to about 7 us between
+    // polls and look at other XCDs' queues every eighth round; the few
+    // panel workers of a single matrix poll every few hundred cycles.
+    const int cap = ROLE == ROLE_PANEL ? (S.npanel <= 8 ? 2 : 5) : 7;
+    if (tid == 0) s_next = -1;
     for (;;) {
         if (tid == 0) {
-            // Idle loop: poll the queues with exponential back-off, look at
-            // the completion counter and the status word only every few
-            // rounds; every idle round counts towards the watchdog.
-            int64_t gid = -1;
+            int64_t gid = s_next;
             int ex = 0;
-            int64_t idle = 0;
-            uint32_t seen = ld_rlx(S.done);
-            int backoff = 0;
-            for (uint32_t round = 0;; ++round) {
-                uint64_t pick = 0;
-                if (S.shuffle) {
-                    rng = mix64(rng + 1);
-                    for (int z = 0; z < (int)(rng & 7); ++z) __builtin_amdgcn_s_sleep(1);
-                    pick = rng >> 8;
-                }
-                gid = pop_any<ROLE>(S, xcd, ROLE == ROLE_UPDATE && (round & 3) == 3, pick);
-                if (gid >= 0) break;
-                if ((round & 3) == 0) {
-                    if (__hip_atomic_load(S.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            s_next = -1;
+            if (gid < 0) {
+                // Poll the queues with exponential back-off, look at the
+                // completion counter and the status word only every few
+                // rounds; every idle round counts towards the watchdog.
+                int64_t idle = 0;
+                uint32_t seen = ld_rlx(S.done);
+                int backoff = 0;
+                for (uint32_t round = 0;; ++round) {
+                    uint64_t pick = 0;
+                    if (S.shuffle) {
+                        rng = mix64(rng + 1);
+                        for (int z = 0; z < (int)(rng & 7); ++z) __builtin_amdgcn_s_sleep(1);
+                        pick = rng >> 8;
+                    }
+                    gid = pop_any<ROLE>(S, xcd, ROLE == ROLE_UPDATE && (round & 7) == 7, pick);
+                    if (gid >= 0) break;
+                    if ((round & 3) == 0) {
+                        if (__hip_atomic_load(S.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                            ex = 1;
+                            break;
+                        }
+                        const uint32_t d = ld_rlx(S.done);
+                        if (d >= S.total_tasks) {
+                            ex = 1;
+                            break;
+                        }
+                        if (d != seen) {
+                            seen = d;
+                            idle = 0;
+                        }
+                    }
+                    if (++idle > S.spin_limit) {
+                        __hip_atomic_fetch_or(S.status, STATUS_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         ex = 1;
                         break;
                     }
-                    const uint32_t d = ld_rlx(S.done);
-                    if (d >= S.total_tasks) {
-                        ex = 1;
-                        break;
-                    }
-                    if (d != seen) {
-                        seen = d;
-                        idle = 0;
-                    }
+                    backoff = backoff < cap ? backoff + 1 : cap;
+                    for (int z = 0; z < (1 << backoff); ++z) __builtin_amdgcn_s_sleep(2);
                 }
-                if (++idle > S.spin_limit) {
-                    __hip_atomic_fetch_or(S.status, STATUS_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ex = 1;
-                    break;
-                }
-                const int cap = ROLE == ROLE_PANEL ? 2 : 5;
-                backoff = backoff < cap ? backoff + 1 : cap;
-                for (int z = 0; z < (1 << backoff); ++z) __builtin_amdgcn_s_sleep(2);
             }
             s_gid = gid;
             s_exit = ex;
+            s_tpop = wall_clock64();
         }
         __syncthreads();
         if (s_exit) break;
@@ -1165,28 +1220,55 @@ __device__ __forceinline__ void worker_loop(Smem<NB, IB> &sm, const SchedDev &S)
         run_task<NB, IB, ROLE, PREC>(sm, M, t);
         // Release: every wave waits for its own stores, then wave 0 writes
         // the L2 back and releases the successors (in program order after
-        // its fence).
+        // its fence).  Of the successors this task makes ready, the first
+        // one of this worker's role is kept and run next without a trip
+        // through the queues (a TSQRT chain, or a strip's chain of updates,
+        // stays on one workgroup); the others are queued.
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __syncthreads();
-        if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const int ns = tid < 64 ? nsucc(g, t) : 0;
-        for (int n = tid; n < ns; n += 64) {
-            if (S.drop_edge >= 0 && gid == S.drop_edge && n == 0) continue;
-            const int64_t sl = succ(g, t, n);
-            const int32_t old = __hip_atomic_fetch_add(&S.counters[M.task_base + sl], -1, __ATOMIC_ACQ_REL,
-                                                       __HIP_MEMORY_SCOPE_AGENT);
-            if (old == 1) push_task(S, queue_of(decode(g, sl), S.ns, mi), M.task_base + sl);
+        if (tid == 0) s_trun = wall_clock64();
+        if (tid < 64) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const int ns = nsucc(g, t);
+            bool kept = false;
+            for (int base = 0; base < ns; base += 64) {
+                const int n = base + tid;
+                bool ready = false, mine = false;
+                int64_t sgid = -1;
+                int queue = 0;
+                if (n < ns && !(S.drop_edge >= 0 && gid == S.drop_edge && n == 0)) {
+                    const int64_t sl = succ(g, t, n);
+                    const int32_t old = __hip_atomic_fetch_add(&S.counters[M.task_base + sl], -1, __ATOMIC_ACQ_REL,
+                                                               __HIP_MEMORY_SCOPE_AGENT);
+                    if (old == 1) {
+                        const Task nt = decode(g, sl);
+                        ready = true;
+                        mine = (nt.type == GEQRT || nt.type == TSQRT) == (ROLE == ROLE_PANEL);
+                        sgid = M.task_base + sl;
+                        queue = queue_of(nt, S.ns, mi);
+                    }
+                }
+                const uint64_t cand = __ballot(ready && mine);
+                const int keeper = (!kept && cand != 0) ? __ffsll((unsigned long long)cand) - 1 : -1;
+                if (ready) {
+                    if (tid == keeper) s_next = sgid;
+                    else push_task(S, queue, sgid);
+                }
+                kept = kept || keeper >= 0;
+            }
         }
         if (tid == 0) {
             if (S.trace != nullptr) {
                 const uint32_t e = __hip_atomic_fetch_add(S.trace_count, 1u, __ATOMIC_RELAXED,
                                                           __HIP_MEMORY_SCOPE_AGENT);
                 if (e < S.trace_cap) {
-                    int64_t *ev = S.trace + (size_t)e * 8;
+                    int64_t *ev = S.trace + (size_t)e * TRACE_WORDS;
                     ev[0] = t.type; ev[1] = t.k; ev[2] = t.i; ev[3] = t.j; ev[4] = t.s;
                     ev[5] = ((int64_t)mi << 20) | (ROLE << 16) | blockIdx.x;
-                    ev[6] = (int64_t)t0;
-                    ev[7] = (int64_t)wall_clock64();
+                    ev[6] = (int64_t)s_tpop;
+                    ev[7] = (int64_t)t0;
+                    ev[8] = (int64_t)s_trun;
+                    ev[9] = (int64_t)wall_clock64();
                 }
             }
             __hip_atomic_fetch_add(S.done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);

@@ -175,11 +175,16 @@ def dag_selfcheck(p, q, strips, trials, seed):
     return _L.tileqr_dag_selfcheck(p, q, strips, trials, seed)
 
 
+TRACE_WORDS = 10
+
+
 def trace():
+    """(events, clock_hz): events are tuples (type, k, i, j, strip, worker,
+    t_pop, t_start, t_body_end, t_end) in device clock ticks."""
     n = _L.tileqr_trace(None, 0)
-    buf = (ctypes.c_int64 * (8 * max(n, 1)))()
+    buf = (ctypes.c_int64 * (TRACE_WORDS * max(n, 1)))()
     n = _L.tileqr_trace(buf, n)
-    return [tuple(buf[8 * e: 8 * e + 8]) for e in range(n)], _L.tileqr_trace_clock_hz()
+    return [tuple(buf[TRACE_WORDS * e: TRACE_WORDS * (e + 1)]) for e in range(n)], _L.tileqr_trace_clock_hz()
 
 
 def last_timing():
