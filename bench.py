@@ -8,8 +8,19 @@ restored from a pristine device copy before each step, outside the timed
 stages.  Rate: LAPACK operation count 2mn^2 - 2n^3/3 over the summed device
 time of the stages, as the paper reports its rates (Section 5).
 
+Beside the headline, the same line carries two further measurements (skip
+them with --no-extras):
+  "mixed_ls"  least squares with A 65536 x 1024 (A = U diag(s) V^T, s
+              log-spaced to 1/kappa, kappa 1e6, b = A x + 1e-6 noise, seed 0):
+              time to solution of the FP64 path (factor + solve) and of the
+              split-MFMA paths (factor + solve + refinement until the backward
+              error is <= 1e-14), each with its backward error;
+  "batched"   4000 FP64 matrices, m ~ U{32..768}, n ~ U{16..m}, N(0,1), seed 0,
+              in one call of tileqr_factor_batched (blocking and schedule from
+              tileqr_tune, run beforehand; the captured graph replayed).
+
 Prints one JSON line.  Flags: --gpus N (only 1 is supported: the build runs
-on one GPU), --steps K, --warmup W, --no-cpu-baseline.
+on one GPU), --steps K, --warmup W, --no-cpu-baseline, --no-extras.
 """
 import argparse
 import json
@@ -63,12 +74,82 @@ def cpu_baseline():
                       f"matrix, seed 0: {dt:.2f} s for {flops:.3e} flops (LAPACK count)"}
 
 
+def mixed_ls(tq, torch, dev, st):
+    """FP64 vs split-precision least squares on one 65536 x 1024 system."""
+    import numpy as np
+    from paper_0709_1272_amd import synth
+    m, n, kappa = 65536, 1024, 1e6
+    A, b, _ = synth.svd_matrix(0, m, n, kappa)
+    At = tq.to_device(A, dev)
+    Bt = tq.to_device(b, dev)
+    Xt = torch.zeros((1, n), dtype=torch.float64, device=dev)
+    flops = tq.flops_lapack(m, n)
+    out = {"workload": f"least squares {m}x{n}, kappa {kappa:.0e}, 1 rhs, SVD construction seed 0",
+           "flops_counted": flops, "tol": 1e-14}
+    xs = {}
+    for name, prec in (("fp64", tq.FP64), ("fp16x2", tq.FP16X2), ("bf16x3", tq.BF16X3), ("bf16x2", tq.BF16X2)):
+        best = None
+        for _ in range(3):
+            info = tq.Info()
+            o = tq.opts(precision=prec, nb=128, ib=32, stream=st.cuda_stream)
+            rc = tq.solve_ls(m, n, 1, At.data_ptr(), m, Bt.data_ptr(), m, Xt.data_ptr(), n, o, info)
+            if best is None or info.ms_total < best[1].ms_total:
+                best = (rc, info)
+        rc, info = best
+        xs[name] = tq.to_host(Xt, n)[:, 0].copy()
+        out[name] = {"status": tq.status_string(rc), "ms_total": round(info.ms_total, 3),
+                     "ms_factor": round(info.ms_factor, 3), "iterations": info.iterations,
+                     "eta": info.eta, "tflops": round(flops / (info.ms_total * 1e-3) / 1e12, 4)}
+    for name in ("fp16x2", "bf16x3", "bf16x2"):
+        out[name]["speedup_vs_fp64"] = round(out["fp64"]["ms_total"] / out[name]["ms_total"], 3)
+        out[name]["rel_diff_x_vs_fp64"] = float(np.linalg.norm(xs[name] - xs["fp64"]) / np.linalg.norm(xs["fp64"]))
+    return out
+
+
+def batched(tq, torch, dev, st):
+    """4000 FP64 matrices of uneven sizes in one call."""
+    import numpy as np
+    from paper_0709_1272_amd import synth
+    ms, ns, mats = synth.batch_matrices(0)
+    ms = [int(x) for x in ms]
+    ns = [int(x) for x in ns]
+    flops = sum(tq.flops_lapack(a, b) for a, b in zip(ms, ns))
+    off = np.concatenate([[0], np.cumsum([a.size for a in mats])]).astype(np.int64)
+    pristine = torch.from_numpy(np.concatenate([a.ravel(order="F") for a in mats])).to(dev)
+    work = torch.empty_like(pristine)
+    tmax = [max(tq.t_size(a, b, nb, ib) for nb in (64, 128, 256) for ib in (16, 32)) for a, b in zip(ms, ns)]
+    toff = np.concatenate([[0], np.cumsum(tmax)]).astype(np.int64)
+    T = torch.empty(int(toff[-1]) + 1, dtype=torch.float64, device=dev)
+    Ap = [work.data_ptr() + 8 * int(o) for o in off[:-1]]
+    Tp = [T.data_ptr() + 8 * int(o) for o in toff[:-1]]
+    t0 = time.perf_counter()
+    tune = tq.tune(ms, ns, tq.FP64, trials=1)
+    tune_s = time.perf_counter() - t0
+    times = []
+    for r in range(4):
+        work.copy_(pristine)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        rc = tq.factor_batched(ms, ns, Ap, ms, None, None, Tp, tq.opts(stream=st.cuda_stream))
+        e1.record(st)
+        torch.cuda.synchronize()
+        tq.check(rc, "tileqr_factor_batched")
+        if r:
+            times.append(e0.elapsed_time(e1))
+    best = min(times)
+    return {"workload": "4000 FP64 matrices, m ~ U{32..768}, n ~ U{16..m}, N(0,1), seed 0, one call",
+            "flops_counted": flops, "ms": round(best, 3), "tflops": round(flops / (best * 1e-3) / 1e12, 4),
+            "tuned": {"nb": tune.nb, "ib": tune.ib, "panel_workers": tune.panel_workers,
+                      "tuning_s": round(tune_s, 2)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build factors on one GPU "
@@ -142,6 +223,9 @@ def main():
                      "kernel": f"k_worker<{NB},{IB}>",
                      "algorithmic": f"{flops:.4e} flops per launch (2mn^2-2n^3/3)"},
     }
+    if not args.no_extras:
+        out["mixed_ls"] = mixed_ls(tq, torch, dev, stream)
+        out["batched"] = batched(tq, torch, dev, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

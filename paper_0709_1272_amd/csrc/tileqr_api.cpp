@@ -695,6 +695,13 @@ struct SolveCtx {
 
 // eta_v = ||A^T (b - A x)||_2 / (||A||_F (||A||_F ||x||_2 + ||b||_2)) per column;
 // returns the largest.  Writes the residual into buf[SS].
+// Device scratch of the solver's norms (W->misc): results in doubles
+// [0, SMALL_PART) (per-column sums at 0, 64, 128, 192), partial sums of the
+// norm kernels in [SMALL_PART, SMALL_PART + SMALL_PART_CAP), enough for
+// COLSQ_BLOCKS blocks times the largest nrhs (64).
+constexpr int64_t SMALL_PART = 1024;
+constexpr int64_t SMALL_PART_CAP = (int64_t)COLSQ_BLOCKS * 64;
+
 int eta_of(SolveCtx &c, double normA, const double *normb, double *eta_cols)
 {
     Workspace *W = c.W;
@@ -704,8 +711,8 @@ int eta_of(SolveCtx &c, double normA, const double *normb, double *eta_cols)
     double *AtS = c.buf[SF];   // scratch n x nrhs (SF is recomputed before use)
     TQ_HIP(launch_gemv_t(c.A, c.lda, c.m, c.n, S, c.ldt, c.nrhs, 1.0, 0.0, AtS, c.st));
     double *dev = c.small;
-    TQ_HIP(launch_colsq(AtS, c.ldt, c.n, c.nrhs, dev + 1024, dev, c.st));
-    TQ_HIP(launch_colsq(c.buf[SX], c.ldt, c.n, c.nrhs, dev + 1024, dev + 64, c.st));
+    TQ_HIP(launch_colsq(AtS, c.ldt, c.n, c.nrhs, dev + SMALL_PART, SMALL_PART_CAP, dev, c.st));
+    TQ_HIP(launch_colsq(c.buf[SX], c.ldt, c.n, c.nrhs, dev + SMALL_PART, SMALL_PART_CAP, dev + 64, c.st));
     TQ_HIP(hipMemcpyAsync(W->host_small, dev, 128 * sizeof(double), hipMemcpyDeviceToHost, c.st));
     TQ_HIP(hipStreamSynchronize(c.st));
     double worst = 0.0;
@@ -760,7 +767,7 @@ extern "C" int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double 
     if ((rc = W->solve.ensure(SNUM * slot * sizeof(double)))) return rc;
     const int64_t part_cap = std::max<int64_t>(m * 32 * 16, 1 << 20);
     if ((rc = W->part.ensure((size_t)part_cap * sizeof(double)))) return rc;
-    if ((rc = W->misc.ensure(4096 * sizeof(double)))) return rc;
+    if ((rc = W->misc.ensure((SMALL_PART + SMALL_PART_CAP) * sizeof(double)))) return rc;
     if ((rc = W->prog.ensure((size_t)std::min(p, q) * sizeof(int32_t) + 64))) return rc;
     if ((rc = W->status.ensure(256))) return rc;
     if (!W->ev[0])
@@ -809,8 +816,8 @@ extern "C" int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double 
     if ((rc = check_status(W, dstatus, st))) return rc;
 
     // Norms fixed for the whole refinement.
-    TQ_HIP(launch_frob2(A, lda, m, n, c.small + 1024, c.small + 128, st));
-    TQ_HIP(launch_colsq(c.buf[SB], ldt, m, c.nrhs, c.small + 1024, c.small + 192, st));
+    TQ_HIP(launch_frob2(A, lda, m, n, c.small + SMALL_PART, SMALL_PART_CAP, c.small + 128, st));
+    TQ_HIP(launch_colsq(c.buf[SB], ldt, m, c.nrhs, c.small + SMALL_PART, SMALL_PART_CAP, c.small + 192, st));
     TQ_HIP(hipMemcpyAsync(W->host_small + 128, c.small + 128, 128 * sizeof(double), hipMemcpyDeviceToHost, st));
     TQ_HIP(hipStreamSynchronize(st));
     const double normA = std::sqrt(W->host_small[128]);

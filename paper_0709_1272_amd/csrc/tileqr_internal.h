@@ -98,10 +98,15 @@ hipError_t launch_gemv_n(const double *A, int64_t lda, int64_t m, int64_t n, con
 // Y = alpha A^T R + beta Y.
 hipError_t launch_gemv_t(const double *A, int64_t lda, int64_t m, int64_t n, const double *R, int ldt, int nrhs,
                          double alpha, double beta, double *Y, hipStream_t st);
-// out[v] = sum of squares of column v of Y (rows < m); part: 256 * nrhs doubles.
-hipError_t launch_colsq(const double *Y, int ldt, int64_t m, int nrhs, double *part, double *out, hipStream_t st);
-// out[0] = ||A||_F^2; part: 256 doubles.
-hipError_t launch_frob2(const double *A, int64_t lda, int64_t m, int64_t n, double *part, double *out, hipStream_t st);
+// Partial sums per column of the two norm kernels below.
+constexpr int COLSQ_BLOCKS = 256;
+// out[v] = sum of squares of column v of Y (rows < m); part holds part_cap
+// doubles and needs COLSQ_BLOCKS * nrhs (hipErrorInvalidValue otherwise).
+hipError_t launch_colsq(const double *Y, int ldt, int64_t m, int nrhs, double *part, int64_t part_cap, double *out,
+                        hipStream_t st);
+// out[0] = ||A||_F^2; part: COLSQ_BLOCKS doubles.
+hipError_t launch_frob2(const double *A, int64_t lda, int64_t m, int64_t n, double *part, int64_t part_cap,
+                        double *out, hipStream_t st);
 // op 0: Y = X - Y, 1: Y += X, 2: Y = X, 3: Y = -Y (rows < m, columns < nrhs).
 hipError_t launch_axpy_rows(const double *X, double *Y, int ldt, int64_t m, int nrhs, int op, hipStream_t st);
 

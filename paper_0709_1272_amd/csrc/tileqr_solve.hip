@@ -344,17 +344,21 @@ hipError_t launch_gemv_t(const double *A, int64_t lda, int64_t m, int64_t n, con
     return hipGetLastError();
 }
 
-hipError_t launch_colsq(const double *Y, int ldt, int64_t m, int nrhs, double *part, double *out, hipStream_t st)
+hipError_t launch_colsq(const double *Y, int ldt, int64_t m, int nrhs, double *part, int64_t part_cap, double *out,
+                        hipStream_t st)
 {
-    const int nblk = 256;
+    const int nblk = COLSQ_BLOCKS;
+    if ((int64_t)nblk * nrhs > part_cap) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_colsq_part, dim3(nblk), dim3(256), 0, st, Y, ldt, m, nrhs, part);
     hipLaunchKernelGGL(k_colsq_sum, dim3(1), dim3(64), 0, st, part, nblk, nrhs, out);
     return hipGetLastError();
 }
 
-hipError_t launch_frob2(const double *A, int64_t lda, int64_t m, int64_t n, double *part, double *out, hipStream_t st)
+hipError_t launch_frob2(const double *A, int64_t lda, int64_t m, int64_t n, double *part, int64_t part_cap,
+                        double *out, hipStream_t st)
 {
-    const int nblk = 256;
+    const int nblk = COLSQ_BLOCKS;
+    if (nblk > part_cap) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_frob_part, dim3(nblk), dim3(256), 0, st, A, lda, m, n, part);
     hipLaunchKernelGGL(k_colsq_sum, dim3(1), dim3(64), 0, st, part, nblk, 1, out);
     return hipGetLastError();
