@@ -122,7 +122,8 @@ __device__ __forceinline__ gdouble *tblock_ptr(const MatDev &M, int nb, int ib, 
 }
 
 // Stage <- columns [c0, c0 + ib) of rows [r0, nb) of a row-major tile
-// (rows above r0 left zero) and the ib x ib T block at Tg.
+// (rows above r0 left zero) and the ib x ib T block at Tg (zeros when Tg is
+// NULL).
 template <int NB, int IB>
 __device__ __forceinline__ void stage_load(Stage<NB, IB> &S, const gdouble *tile, int c0, int r0,
                                            const gdouble *Tg)
@@ -138,7 +139,7 @@ __device__ __forceinline__ void stage_load(Stage<NB, IB> &S, const gdouble *tile
 #pragma unroll
     for (int u = 0; u < C::TPT; ++u) {
         const int e = threadIdx.x + u * C::NT;
-        S.t[u] = e < IB * IB / 2 ? reinterpret_cast<const gv2d *>(Tg)[e] : v2d{0.0, 0.0};
+        S.t[u] = (Tg != nullptr && e < IB * IB / 2) ? reinterpret_cast<const gv2d *>(Tg)[e] : v2d{0.0, 0.0};
     }
 }
 
@@ -186,14 +187,15 @@ __device__ __forceinline__ void load_strip(Strip<NB, IB> &X, const gdouble *tile
             }
 }
 
+// Strip -> rows [rlo, rhi) of a row-major tile (both multiples of 16).
 template <int NB, int IB>
 __device__ __forceinline__ void store_strip(const Strip<NB, IB> &X, gdouble *tile, int ld, int col0, int cbn,
-                                            int rlo)
+                                            int rlo, int rhi = NB)
 {
     const int n = lane_id() & 15, g = lane_id() >> 4, rowbase = wave_id() * 32;
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) {
-        if (rowbase + rb * 16 < rlo) continue;
+        if (rowbase + rb * 16 < rlo || rowbase + rb * 16 >= rhi) continue;
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
             if (cb >= cbn) continue;
@@ -203,6 +205,23 @@ __device__ __forceinline__ void store_strip(const Strip<NB, IB> &X, gdouble *til
                 tile[(size_t)row * ld + col0 + cb * 16 + n] = X.v[rb][cb][r];
             }
         }
+    }
+}
+
+// Rows [rfrom, nb) of a full strip (rfrom a multiple of 16) -> columns
+// 0 .. 31 of the panel buffer sm.P.
+template <int NB, int IB>
+__device__ __forceinline__ void strip_to_panel(Smem<NB, IB> &sm, const Strip<NB, IB> &X, int rfrom)
+{
+    using C = Cfg<NB, IB>;
+    const int n = lane_id() & 15, g = lane_id() >> 4, rowbase = wave_id() * 32;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+        if (rowbase + rb * 16 < rfrom) continue;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sm.P[(rowbase + rb * 16 + 4 * r + g) * C::LDP + cb * 16 + n] = X.v[rb][cb][r];
     }
 }
 
@@ -570,6 +589,35 @@ __device__ __forceinline__ void apply_panel_mx(Smem<NB, IB> &sm, Strip<NB, IB> &
     }
 }
 
+// 1/d for a normal d: the hardware estimate refined by two Newton-Raphson
+// steps for the reciprocal (y <- y + y (1 - d y)), which give full double
+// precision (not always the correctly rounded quotient).
+__device__ __forceinline__ double recip_nr(double d)
+{
+    double y = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-d, y, 1.0);
+    return fma(y, e, y);
+}
+
+// sqrt(a) for a normal positive a: the hardware estimate y of 1/sqrt(a)
+// refined by the coupled Newton iteration for g = a y -> sqrt(a) and
+// h = y / 2 -> 1 / (2 sqrt(a)), two steps, then one residual correction
+// g + (a - g^2) h.
+__device__ __forceinline__ double sqrt_nr(double a)
+{
+    const double y = __builtin_amdgcn_rsq(a);
+    double g = a * y, h = 0.5 * y;
+    double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    return fma(fma(-g, g, a), h, g);
+}
+
 // Lane permutations by DPP on the two 32-bit halves of a double: xor 1 and
 // xor 2 inside a quad, mirror inside 8 and inside 16 lanes.
 template <int CTRL>
@@ -623,7 +671,9 @@ __device__ __forceinline__ double group_max(double v)
 // Per column one barrier: the group of column j forms its reflector and
 // publishes v and tau through LDS (two buffers by column parity, so that
 // column j+1 may publish while column j's updates still read), then every
-// later column applies it.
+// later column applies it.  The scalars take one square root and one
+// division; extreme magnitudes go through a norm scaled by the largest
+// entry.
 template <int NB, int IB, bool TS>
 __device__ __forceinline__ void panel_factor(Smem<NB, IB> &sm, int c0)
 {
@@ -677,18 +727,18 @@ __device__ __forceinline__ void panel_factor(Smem<NB, IB> &sm, int c0)
             }
             const double part = (q[0] + q[1]) + (q[2] + q[3]);
             const double sig = group_sum<RG>(part);
-            double xnorm, h;
-            if (sig <= 1.0e300 && (sig >= 2.2250738585072014e-308 || sig == 0.0)) {
-                // Nothing over- or underflowed (a zero sum with nonzero
-                // entries is caught by the scaled pass below).
-                xnorm = sqrt(sig);
-                h = fabs(alpha) < 1.0e150 ? sqrt(alpha * alpha + sig) : hypot(alpha, xnorm);
-            } else {
-                xnorm = -1.0;
-                h = 0.0;
-            }
-            if (xnorm < 0.0 || (sig == 0.0 && group_max<RG>(part) != 0.0)) {
-                // Redo the norm scaled by the largest magnitude.
+            double tau = 0.0, scal = 0.0, beta = alpha;
+            if (sig <= 1.0e300 && sig >= 2.2250738585072014e-308 && fabs(alpha) < 1.0e150) {
+                // Nothing over- or underflowed: one square root and one
+                // reciprocal, 1 / (beta (alpha - beta)), give both scalars.
+                const double h = sqrt_nr(alpha * alpha + sig);
+                beta = alpha >= 0.0 ? -h : h;
+                const double amb = alpha - beta;
+                const double rd = recip_nr(beta * amb);
+                scal = beta * rd;
+                tau = (beta - alpha) * amb * rd;
+            } else if (sig != 0.0 || group_max<RG>(part) != 0.0) {
+                // Extreme magnitudes: the norm scaled by the largest entry.
                 double mx = 0.0;
 #pragma unroll
                 for (int i = 0; i < RPT; ++i)
@@ -700,14 +750,14 @@ __device__ __forceinline__ void panel_factor(Smem<NB, IB> &sm, int c0)
                     const double t = tail(i) ? pr[i] / mxa : 0.0;
                     p2 += t * t;
                 }
-                xnorm = mxa * sqrt(group_sum<RG>(p2));
-                h = hypot(alpha, xnorm);
-            }
-            double tau = 0.0;
-            if (xnorm != 0.0) {
-                const double beta = alpha >= 0.0 ? -h : h;
+                const double xnorm = mxa * sqrt(group_sum<RG>(p2));
+                const double h = hypot(alpha, xnorm);
+                beta = alpha >= 0.0 ? -h : h;
                 tau = (beta - alpha) / beta;
-                const double scal = 1.0 / (alpha - beta);
+                scal = 1.0 / (alpha - beta);
+            }
+            // (a zero tail: no reflector, tau = 0, the column stays as it is)
+            if (tau != 0.0) {
 #pragma unroll
                 for (int i = 0; i < RPT; ++i) {
                     if (tail(i)) {
@@ -845,19 +895,53 @@ __device__ __forceinline__ void build_t(Smem<NB, IB> &sm, int rlo, gdouble *Tg)
 
 // ------------------------------------------------------------ tile kernels
 
+// Trailing update inside GEQRT / TSQRT after the panel at c0 (its V in
+// sm.P, its T in sm.Tl): the panel's reflector is applied to every strip
+// right of it, the strip next to the panel last.  With ib equal to the
+// strip width that strip is exactly the next panel, so when `chain` is set
+// its result goes straight into sm.P (GEQRT also stores its rows above the
+// next panel, which are final rows of R, to the tile) instead of a round
+// trip through memory.
+template <int NB, int IB, bool TS>
+__device__ __forceinline__ void panel_trailing(Smem<NB, IB> &sm, gdouble *tile, gdouble *tkk, int c0, bool chain)
+{
+    const int first = c0 + IB;
+    if (first >= NB) return;
+    const int rlo = TS ? 0 : c0;
+    const int nst = (NB - first + WS - 1) / WS;
+#pragma unroll 1
+    for (int q = 0; q < nst; ++q) {
+        const int col0 = first + (nst - 1 - q) * WS;
+        const int cbn = min(CB, (NB - col0) / 16);
+        Strip<NB, IB> X;
+        load_strip<NB, IB>(X, tile, NB, col0, cbn);
+        apply_panel<NB, IB>(sm, X, rlo, TS ? tkk + (size_t)c0 * NB + col0 : nullptr, NB, cbn);
+        if (chain && q + 1 == nst) {
+            if constexpr (!TS) store_strip<NB, IB>(X, tile, NB, col0, cbn, rlo, c0 + IB);
+            __syncthreads();
+            strip_to_panel<NB, IB>(sm, X, TS ? 0 : c0 + IB);
+        } else {
+            store_strip<NB, IB>(X, tile, NB, col0, cbn, rlo);
+        }
+    }
+}
+
 // DGEQRT(A_kk) -> (V_kk, R_kk, T_kk).
 template <int NB, int IB>
 __device__ __forceinline__ void task_geqrt(Smem<NB, IB> &sm, const MatDev &M, int k)
 {
     using C = Cfg<NB, IB>;
+    constexpr bool CHAIN = IB == WS;
     gdouble *tkk = tile_ptr(M, NB, k, k);
     gdouble *Tk = tblock_ptr(M, NB, IB, k, k);
-    Stage<NB, IB> S;
 #pragma unroll 1
     for (int l = 0; l < C::NPAN; ++l) {
         const int c0 = l * IB;
-        stage_load<NB, IB>(S, tkk, c0, c0, Tk);
-        stage_store<NB, IB>(sm, S, c0, false, c0);
+        if (l == 0 || !CHAIN) {
+            Stage<NB, IB> S;
+            stage_load<NB, IB>(S, tkk, c0, c0, nullptr);
+            stage_store<NB, IB>(sm, S, c0, false, c0);
+        }
         __syncthreads();
         panel_factor<NB, IB, false>(sm, c0);
         // Write R and V back; keep V with explicit unit diagonal in LDS.
@@ -878,14 +962,7 @@ __device__ __forceinline__ void task_geqrt(Smem<NB, IB> &sm, const MatDev &M, in
         __syncthreads();
         build_t<NB, IB>(sm, c0, Tk + l * IB * IB);
         __syncthreads();
-#pragma unroll 1
-        for (int col0 = c0 + IB; col0 < NB; col0 += WS) {
-            const int cbn = min(CB, (NB - col0) / 16);
-            Strip<NB, IB> X;
-            load_strip<NB, IB>(X, tkk, NB, col0, cbn);
-            apply_panel<NB, IB>(sm, X, c0, nullptr, 0, cbn);
-            store_strip<NB, IB>(X, tkk, NB, col0, cbn, c0);
-        }
+        panel_trailing<NB, IB, false>(sm, tkk, nullptr, c0, CHAIN);
         __syncthreads();
     }
 }
@@ -895,20 +972,23 @@ template <int NB, int IB>
 __device__ __forceinline__ void task_tsqrt(Smem<NB, IB> &sm, const MatDev &M, int k, int i)
 {
     using C = Cfg<NB, IB>;
+    constexpr bool CHAIN = IB == WS;
     gdouble *tkk = tile_ptr(M, NB, k, k);
     gdouble *tik = tile_ptr(M, NB, i, k);
     gdouble *Ti = tblock_ptr(M, NB, IB, k, i);
-    Stage<NB, IB> S;
     constexpr int H = IB / 2;
 #pragma unroll 1
     for (int l = 0; l < C::NPAN; ++l) {
         const int c0 = l * IB;
-        stage_load<NB, IB>(S, tik, c0, 0, Ti);
+        if (l == 0 || !CHAIN) {
+            Stage<NB, IB> S;
+            stage_load<NB, IB>(S, tik, c0, 0, nullptr);
+            stage_store<NB, IB>(sm, S, 0, false, c0);
+        }
         for (int e = threadIdx.x; e < IB * IB; e += C::NT) {
             const int r = e / IB, c = e % IB;
             sm.P[(NB + r) * C::LDP + c] = r <= c ? tkk[(size_t)(c0 + r) * NB + c0 + c] : 0.0;
         }
-        stage_store<NB, IB>(sm, S, 0, false, c0);
         __syncthreads();
         panel_factor<NB, IB, true>(sm, c0);
         for (int e = threadIdx.x; e < IB * IB; e += C::NT) {
@@ -923,14 +1003,7 @@ __device__ __forceinline__ void task_tsqrt(Smem<NB, IB> &sm, const MatDev &M, in
         }
         build_t<NB, IB>(sm, 0, Ti + l * IB * IB);
         __syncthreads();
-#pragma unroll 1
-        for (int col0 = c0 + IB; col0 < NB; col0 += WS) {
-            const int cbn = min(CB, (NB - col0) / 16);
-            Strip<NB, IB> X;
-            load_strip<NB, IB>(X, tik, NB, col0, cbn);
-            apply_panel<NB, IB>(sm, X, 0, tkk + (size_t)c0 * NB + col0, NB, cbn);
-            store_strip<NB, IB>(X, tik, NB, col0, cbn, 0);
-        }
+        panel_trailing<NB, IB, true>(sm, tik, tkk, c0, CHAIN);
         __syncthreads();
     }
 }
