@@ -15,6 +15,9 @@ them with --no-extras):
               time to solution of the FP64 path (factor + solve) and of the
               split-MFMA paths (factor + solve + refinement until the backward
               error is <= 1e-14), each with its backward error;
+  "mixed_ls_square"  the same comparison on a 32768 x 32768 system with 16
+              right-hand sides (kappa 1e6; Hadamard-based orthogonal factors
+              generated on the GPU);
   "batched"   4000 FP64 matrices, m ~ U{32..768}, n ~ U{16..m}, N(0,1), seed 0,
               in one call of tileqr_factor_batched (blocking and schedule from
               tileqr_tune, run beforehand; the captured graph replayed).
@@ -34,7 +37,18 @@ if ROOT not in sys.path:
 
 FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 (vector and matrix), spec sheet
 PROFILE = os.path.join(ROOT, "profiles", "k_worker_qr8192_fp64.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_0709_1272_amd", "csrc", "tileqr_kernels.hip")
+# Sources the worker kernel is compiled from (the traffic figures of the
+# profile are valid only for the build whose hash they record).
+KERNEL_SRCS = [os.path.join(ROOT, "paper_0709_1272_amd", "csrc", f)
+               for f in ("tileqr_kernels.hip", "tileqr_tile.h", "tileqr_dag.h", "tileqr_internal.h")]
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 M = N = 8192
 NB, IB = 256, 32
 CPU_SAMPLE_N = 3072
@@ -44,14 +58,12 @@ def measured_traffic():
     """HBM bytes per launch of the worker kernel from the committed rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain copy), or
     None when the kernel source changed since the counters were taken."""
-    import hashlib
     import re
     try:
         text = open(PROFILE).read()
     except OSError:
         return None
-    h = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-    if h not in text:
+    if kernel_hash() not in text:
         return None
     m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+-]+)", text)
     return float(m.group(1)) if m else None
@@ -103,6 +115,38 @@ def mixed_ls(tq, torch, dev, st):
     for name in ("fp16x2", "bf16x3", "bf16x2"):
         out[name]["speedup_vs_fp64"] = round(out["fp64"]["ms_total"] / out[name]["ms_total"], 3)
         out[name]["rel_diff_x_vs_fp64"] = float(np.linalg.norm(xs[name] - xs["fp64"]) / np.linalg.norm(xs["fp64"]))
+    return out
+
+
+def mixed_ls_square(tq, torch, dev, st, n=32768):
+    """FP64 vs split-precision least squares on one n x n system with 16
+    right-hand sides (kappa 1e6), the square least-squares workload."""
+    import numpy as np
+    from paper_0709_1272_amd import synth
+    t0 = time.perf_counter()
+    At, Bt, _ = synth.svd_matrix_device(0, n, 1e6, nrhs=16, device=dev)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    Xt = torch.zeros((16, n), dtype=torch.float64, device=dev)
+    flops = tq.flops_lapack(n, n)
+    out = {"workload": f"least squares {n}x{n}, kappa 1e6, 16 rhs, A = U diag(s) V^T with Hadamard-based "
+                       f"orthogonal U, V (seed 0), nb 256, ib 32",
+           "flops_counted": flops, "tol": 1e-14, "generation_s": round(gen_s, 2)}
+    xs = {}
+    for name, prec in (("fp64", tq.FP64), ("fp16x2", tq.FP16X2), ("bf16x3", tq.BF16X3)):
+        info = tq.Info()
+        o = tq.opts(precision=prec, nb=256, ib=32, stream=st.cuda_stream)
+        rc = tq.solve_ls(n, n, 16, At.data_ptr(), n, Bt.data_ptr(), n, Xt.data_ptr(), n, o, info)
+        xs[name] = Xt.clone()
+        out[name] = {"status": tq.status_string(rc), "ms_total": round(info.ms_total, 3),
+                     "ms_factor": round(info.ms_factor, 3), "iterations": info.iterations,
+                     "eta": info.eta, "tflops": round(flops / (info.ms_total * 1e-3) / 1e12, 4)}
+    for name in ("fp16x2", "bf16x3"):
+        out[name]["speedup_vs_fp64"] = round(out["fp64"]["ms_total"] / out[name]["ms_total"], 3)
+        out[name]["rel_diff_x_vs_fp64"] = float(torch.linalg.norm(xs[name] - xs["fp64"]) /
+                                                torch.linalg.norm(xs["fp64"]))
+    del At, Bt, Xt, xs
+    torch.cuda.empty_cache()
     return out
 
 
@@ -225,6 +269,7 @@ def main():
     }
     if not args.no_extras:
         out["mixed_ls"] = mixed_ls(tq, torch, dev, stream)
+        out["mixed_ls_square"] = mixed_ls_square(tq, torch, dev, stream)
         out["batched"] = batched(tq, torch, dev, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()

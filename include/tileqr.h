@@ -56,16 +56,17 @@ typedef enum {
     TILEQR_ESINGULAR = 7    /* R has an exact zero on its diagonal (solve only)     */
 } tileqr_status;
 
-/* Arithmetic of the two GEMM-shaped kernels (LARFB, SSRFB).  GEQRT and
- * TSQRT (reflectors: norms, tau, the R diagonal; T), storage, the update of
- * the coupled R rows and the refinement's residuals stay FP64 in every mode.
- * In a split mode each FP64 operand of the products V^T X and V W is written
- * as a sum of 2 or 3 narrow numbers (x rounded, then the rounded remainders)
- * and the kept partial products run on the narrow MFMAs with FP32
- * accumulation per 32 rows, summed across rows in FP64.  Split modes take
- * ib = 32 (any supported nb); other ib give TILEQR_EUNSUPPORTED.  Entries
- * must stay below about 1e38 in magnitude in the BF16 modes (FP32 range);
- * FP16X2 scales every operand column by a power of two. */
+/* Arithmetic of the block-reflector products: LARFB, SSRFB and the updates
+ * of the remaining panel columns inside GEQRT and TSQRT.  Reflector
+ * generation (norms, tau, beta = the R diagonal) and T, storage, the update
+ * of the coupled R rows and the refinement's residuals stay FP64 in every
+ * mode.  In a split mode each FP64 operand of the products V^T X and V W is
+ * written as a sum of 2 or 3 narrow numbers (x rounded, then the rounded
+ * remainders) and the kept partial products run on the narrow MFMAs with
+ * FP32 accumulation per 32 rows, summed across rows in FP64.  Split modes
+ * take ib = 32 (any supported nb); other ib give TILEQR_EUNSUPPORTED.
+ * Entries must stay below about 1e38 in magnitude in the BF16 modes (FP32
+ * range); FP16X2 scales every operand column by a power of two. */
 typedef enum {
     TILEQR_FP64 = 0,    /* FP64 MFMA                                               */
     TILEQR_BF16X2 = 1,  /* hi+lo BF16 split, 3 products, FP32 accumulation         */

@@ -602,7 +602,7 @@ extern "C" int tileqr_finalize(void)
 namespace {
 
 // Q^T or Q on row blocks `rows` (leading dimension ldt) with the factor
-// already in W->tiles.  W->prog must hold min(p, q) flags.
+// already in W->tiles.  W->prog must hold min(p, q) flags (PROG_STRIDE apart).
 hipError_t apply_rows(Workspace *W, int nb, int ib, int p, int q, const double *T, double *rows, int ldt, bool trans,
                       hipStream_t st)
 {
@@ -649,7 +649,7 @@ int apply_common(bool trans, int64_t m, int64_t n, int64_t nrhs, const double *A
     int rc;
     if ((rc = W->tiles.ensure((size_t)p * q * nb * nb * sizeof(double)))) return rc;
     if ((rc = W->rows.ensure((size_t)p * nb * ldt * sizeof(double)))) return rc;
-    if ((rc = W->prog.ensure((size_t)kmax * sizeof(int32_t) + 64))) return rc;
+    if ((rc = W->prog.ensure((size_t)kmax * PROG_STRIDE * sizeof(int32_t) + 64))) return rc;
     if ((rc = W->status.ensure(256))) return rc;
     TQ_HIP(hipMemsetAsync(W->status.ptr, 0, sizeof(int), st));
     TQ_HIP(launch_cm2tile(A, lda, m, n, (double *)W->tiles.ptr, (int)nb, p, q, (int *)W->status.ptr, st));
@@ -709,7 +709,7 @@ int eta_of(SolveCtx &c, double normA, const double *normb, double *eta_cols)
     TQ_HIP(launch_axpy_rows(c.buf[SB], S, c.ldt, c.m, c.nrhs, 2, c.st));
     TQ_HIP(launch_gemv_n(c.A, c.lda, c.m, c.n, c.buf[SX], c.ldt, c.nrhs, -1.0, 1.0, S, c.part, c.part_cap, c.st));
     double *AtS = c.buf[SF];   // scratch n x nrhs (SF is recomputed before use)
-    TQ_HIP(launch_gemv_t(c.A, c.lda, c.m, c.n, S, c.ldt, c.nrhs, 1.0, 0.0, AtS, c.st));
+    TQ_HIP(launch_gemv_t(c.A, c.lda, c.m, c.n, S, c.ldt, c.nrhs, 1.0, 0.0, AtS, c.part, c.part_cap, c.st));
     double *dev = c.small;
     TQ_HIP(launch_colsq(AtS, c.ldt, c.n, c.nrhs, dev + SMALL_PART, SMALL_PART_CAP, dev, c.st));
     TQ_HIP(launch_colsq(c.buf[SX], c.ldt, c.n, c.nrhs, dev + SMALL_PART, SMALL_PART_CAP, dev + 64, c.st));
@@ -768,7 +768,7 @@ extern "C" int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double 
     const int64_t part_cap = std::max<int64_t>(m * 32 * 16, 1 << 20);
     if ((rc = W->part.ensure((size_t)part_cap * sizeof(double)))) return rc;
     if ((rc = W->misc.ensure((SMALL_PART + SMALL_PART_CAP) * sizeof(double)))) return rc;
-    if ((rc = W->prog.ensure((size_t)std::min(p, q) * sizeof(int32_t) + 64))) return rc;
+    if ((rc = W->prog.ensure((size_t)std::min(p, q) * PROG_STRIDE * sizeof(int32_t) + 64))) return rc;
     if ((rc = W->status.ensure(256))) return rc;
     if (!W->ev[0])
         for (auto &e : W->ev) TQ_HIP(hipEventCreate(&e));
@@ -842,7 +842,7 @@ extern "C" int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double 
         TQ_HIP(launch_axpy_rows(c.buf[SR], F, ldt, m, c.nrhs, 0, st));   // F = R - F = r - b
         TQ_HIP(launch_axpy_rows(nullptr, F, ldt, m, c.nrhs, 3, st));     // F = b - r
         TQ_HIP(launch_gemv_n(A, lda, m, n, c.buf[SX], ldt, c.nrhs, -1.0, 1.0, F, c.part, part_cap, st));
-        TQ_HIP(launch_gemv_t(A, lda, m, n, c.buf[SR], ldt, c.nrhs, -1.0, 0.0, G, st));
+        TQ_HIP(launch_gemv_t(A, lda, m, n, c.buf[SR], ldt, c.nrhs, -1.0, 0.0, G, c.part, part_cap, st));
         // [f1; f2] = Q^T f ;  d1 = R^{-T} g ;  dx = R^{-1} (f1 - d1) ;  dr = Q [d1; f2]
         TQ_HIP(apply_rows(W, c.nb, c.ib, p, q, c.T, F, ldt, true, st));
         TQ_HIP(launch_trsm(c.nb, (double *)W->tiles.ptr, p, n, G, ldt, false, dstatus, st));

@@ -54,6 +54,9 @@ struct SchedDev {
     uint32_t trace_cap;
 };
 
+// Words between two progress flags of the Q / Q^T application (256 bytes).
+constexpr int PROG_STRIDE = 64;
+
 // Applying Q or Q^T of a finished factorisation to row blocks of B.
 struct ApplyDev {
     MatDev M;                 // factor tiles and T
@@ -61,7 +64,7 @@ struct ApplyDev {
     int32_t ldb;              // a multiple of the strip width
     int32_t nstrip;           // ldb / strip width
     int32_t kmax;             // tile steps of the factorisation
-    int32_t *prog;            // [kmax] progress flags
+    int32_t *prog;            // [kmax * PROG_STRIDE] progress flags, one per 256 bytes
     int32_t *status;
     int64_t spin_limit;
 };
@@ -95,9 +98,10 @@ hipError_t launch_trsm(int nb, const double *tiles, int p, int64_t n, double *C,
 // is scratch of part_cap doubles for the deterministic column-slice sums.
 hipError_t launch_gemv_n(const double *A, int64_t lda, int64_t m, int64_t n, const double *X, int ldt, int nrhs,
                          double alpha, double beta, double *Y, double *part, int64_t part_cap, hipStream_t st);
-// Y = alpha A^T R + beta Y.
+// Y = alpha A^T R + beta Y; `part` is scratch of part_cap doubles for the
+// deterministic row-slice sums (at least 32 n).
 hipError_t launch_gemv_t(const double *A, int64_t lda, int64_t m, int64_t n, const double *R, int ldt, int nrhs,
-                         double alpha, double beta, double *Y, hipStream_t st);
+                         double alpha, double beta, double *Y, double *part, int64_t part_cap, hipStream_t st);
 // Partial sums per column of the two norm kernels below.
 constexpr int COLSQ_BLOCKS = 256;
 // out[v] = sum of squares of column v of Y (rows < m); part holds part_cap
@@ -114,9 +118,10 @@ hipError_t launch_cm2tile(const double *A, int64_t lda, int64_t m, int64_t n, do
                           int p, int q, int *status, hipStream_t st);
 hipError_t launch_tile2cm(double *A, int64_t lda, int64_t m, int64_t n, const double *tiles, int nb,
                           int p, int q, const int *status, hipStream_t st);
-// Arithmetic of the LARFB / SSRFB products (the values of tileqr_precision):
+// Arithmetic of the block-reflector products (the values of tileqr_precision):
 // 0 FP64; 1, 2, 3 split BF16 x2, FP16 x2, BF16 x3 on the narrow MFMAs with
-// FP32 accumulation (ib = 32 only).  GEQRT and TSQRT are always FP64.
+// FP32 accumulation (ib = 32 only) in every block-reflector product; the
+// reflectors and T are always formed in FP64.
 hipError_t launch_factor_serial(int nb, int ib, int prec, const MatDev &M, const int *status, hipStream_t st);
 hipError_t launch_sched_init(const SchedDev &S, hipStream_t st);
 // The persistent scheduler: `workers` workgroups, the first S.npanel of

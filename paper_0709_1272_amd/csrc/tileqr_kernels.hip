@@ -49,7 +49,7 @@ __global__ void k_sched_seed(SchedDev S)
 // Workgroup w runs step k (k = w for Q^T, kmax-1-w for Q) over its row
 // blocks in that order; before touching block i it waits until the step
 // that precedes it in the product has finished block i (progress flags in
-// D.prog).  That neighbour always has the lower workgroup index, so it was
+// D.prog, one per PROG_STRIDE words).  That neighbour always has the lower workgroup index, so it was
 // dispatched first and the waits make progress; every wait is bounded.
 template <int NB, int IB, bool TRANS>
 __global__ __launch_bounds__(2 * NB) void k_apply(ApplyDev D)
@@ -70,8 +70,9 @@ __global__ __launch_bounds__(2 * NB) void k_apply(ApplyDev D)
         if (tid == 0) {
             int abort = 0;
             if (wait) {
-                const int *flag = &D.prog[TRANS ? k - 1 : k + 1];
+                const int *flag = &D.prog[(TRANS ? k - 1 : k + 1) * PROG_STRIDE];
                 int64_t spins = 0;
+                int backoff = 0;
                 for (;;) {
                     const int v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if (TRANS ? v >= r : v <= r) break;
@@ -81,7 +82,10 @@ __global__ __launch_bounds__(2 * NB) void k_apply(ApplyDev D)
                         abort = 1;
                         break;
                     }
-                    __builtin_amdgcn_s_sleep(2);
+                    // Back off (up to about 3 us between polls): the waiting
+                    // workgroups poll lines that the working ones also use.
+                    backoff = backoff < 6 ? backoff + 1 : 6;
+                    for (int z = 0; z < (1 << backoff); ++z) __builtin_amdgcn_s_sleep(2);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
@@ -102,7 +106,7 @@ __global__ __launch_bounds__(2 * NB) void k_apply(ApplyDev D)
         __syncthreads();
         if (tid == 0) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __hip_atomic_store(&D.prog[k], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&D.prog[k * PROG_STRIDE], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -112,7 +116,7 @@ __global__ __launch_bounds__(2 * NB) void k_apply(ApplyDev D)
 __global__ void k_apply_init(int *prog, int kmax, int p, int trans)
 {
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < kmax; k += gridDim.x * blockDim.x)
-        prog[k] = trans ? k - 1 : p;
+        prog[k * PROG_STRIDE] = trans ? k - 1 : p;
 }
 
 // Column-major (B, ldb) m x nrhs <-> row blocks: Bt[(R) * ldt + c], rows

@@ -1,7 +1,8 @@
 // Tiled QR kernels with split-precision LARFB / SSRFB products, instantiated
 // for one arithmetic per object: the build compiles this file once for each
 // value of TQ_PREC (1 BF16 x2, 2 FP16 x2, 3 BF16 x3), always with ib = 32.
-// GEQRT and TSQRT, which generate the reflectors and T, stay FP64.
+// Reflectors and T are formed in FP64; the block-reflector products (in
+// LARFB, SSRFB and the trailing updates inside GEQRT / TSQRT) are split.
 #include "tileqr_tile.h"
 
 #ifndef TQ_PREC

@@ -29,28 +29,41 @@ __device__ __forceinline__ const double *tile_at(const double *tiles, int p, int
 //   upper == true:  R_kk X = C_k (back substitution),
 //   upper == false: R_kk^T X = C_k (forward substitution).
 // The tile is taken in 32 x 32 diagonal blocks (bottom-up for R, top-down for
-// R^T); a block is solved by half-waves, one right-hand side per half-wave
-// with one row per lane, and the rest of the tile is then updated with it.
-// Rows at or beyond `n` (padding) get X = 0; an exact zero on the diagonal of
-// a real row sets STATUS_SINGULAR.
+// R^T).  For each block the 32 columns of op(R) that hold it are staged in
+// LDS (coalesced), the block is solved by half-waves (one right-hand side per
+// half-wave, one row per lane, reciprocals of the diagonal computed once),
+// and the rows of the tile that depend on it are updated by a register-
+// blocked product (4 x 4 outputs per thread).  Rows at or beyond `n`
+// (padding) get X = 0; an exact zero on the diagonal of a real row sets
+// STATUS_SINGULAR.
 template <int NB>
 __global__ __launch_bounds__(2 * NB) void k_trsm_diag(const double *tiles, int p, int64_t n, int k, double *C,
                                                       int ldt, int upper, int *status)
 {
     constexpr int NT = 2 * NB, NBLK = NB / 32;
     __shared__ double X[NB][SW + 1];
-    __shared__ double Rb[32][33];
+    __shared__ double Rc[NB][33];   // Rc[row][j] = op(R)[row][32 b + j]
+    __shared__ double dinv[32];
     const int tid = threadIdx.x, lane = tid & 63, hw = tid >> 5;   // half-wave index
     const double *R = tile_at(tiles, p, NB, k, k);
     double *Ck = C + (size_t)k * NB * ldt;
+    const int rgp = tid / 8, cg = tid % 8;   // update: rows 4 rgp .. +3, columns 4 cg .. +3
     for (int s0 = 0; s0 < ldt; s0 += SW) {
         for (int e = tid; e < NB * SW; e += NT) X[e / SW][e % SW] = Ck[(size_t)(e / SW) * ldt + s0 + e % SW];
-        __syncthreads();
         for (int bb = 0; bb < NBLK; ++bb) {
             const int b = upper ? NBLK - 1 - bb : bb;
-            for (int e = tid; e < 32 * 32; e += NT) {
-                const int i = e / 32, j = e % 32;
-                Rb[i][j] = upper ? R[(size_t)(b * 32 + i) * NB + b * 32 + j] : R[(size_t)(b * 32 + j) * NB + b * 32 + i];
+            __syncthreads();
+            if (upper) {
+                for (int e = tid; e < NB * 32; e += NT) Rc[e / 32][e % 32] = R[(size_t)(e / 32) * NB + b * 32 + e % 32];
+            } else {
+                for (int e = tid; e < NB * 32; e += NT) Rc[e % NB][e / NB] = R[(size_t)(b * 32 + e / NB) * NB + e % NB];
+            }
+            __syncthreads();
+            if (tid < 32) {
+                const double d = Rc[b * 32 + tid][tid];
+                const bool real = (int64_t)k * NB + b * 32 + tid < n;
+                if (real && d == 0.0) atomicOr(status, STATUS_SINGULAR);
+                dinv[tid] = (real && d != 0.0) ? 1.0 / d : 0.0;
             }
             __syncthreads();
             const int i = lane & 31;
@@ -59,33 +72,36 @@ __global__ __launch_bounds__(2 * NB) void k_trsm_diag(const double *tiles, int p
                 double x = X[b * 32 + i][c];
                 for (int q = 0; q < 32; ++q) {
                     const int r = upper ? 31 - q : q;
-                    const int64_t gr = (int64_t)k * NB + b * 32 + r;
-                    double xr = 0.0;
-                    if (gr < n) {
-                        const double d = Rb[r][r];
-                        xr = __shfl(x, r, 32) / d;
-                    }
+                    const double xr = __shfl(x, r, 32) * dinv[r];
                     if (i == r) x = xr;
-                    else if (upper ? i < r : i > r) x -= Rb[i][r] * xr;
+                    else if (upper ? i < r : i > r) x -= Rc[b * 32 + i][r] * xr;
                 }
                 X[b * 32 + i][c] = grow < n ? x : 0.0;
             }
-            if (tid < 32 && (int64_t)k * NB + b * 32 + tid < n && Rb[tid][tid] == 0.0)
-                atomicOr(status, STATUS_SINGULAR);
             __syncthreads();
             // Rows outside the block that depend on it.
             const int r0 = upper ? 0 : (b + 1) * 32, r1 = upper ? b * 32 : NB;
-            for (int e = tid; e < (r1 - r0) * SW; e += NT) {
-                const int row = r0 + e / SW, c = e % SW;
-                double acc = X[row][c];
+            if (4 * rgp >= r0 && 4 * rgp < r1) {
+                double acc[4][4] = {};
                 for (int j = 0; j < 32; ++j) {
-                    const double rv = upper ? R[(size_t)row * NB + b * 32 + j] : R[(size_t)(b * 32 + j) * NB + row];
-                    acc -= rv * X[b * 32 + j][c];
+                    double a[4], xv[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        a[u] = Rc[4 * rgp + u][j];
+                        xv[u] = X[b * 32 + j][4 * cg + u];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * xv[v];
                 }
-                X[row][c] = acc;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) X[4 * rgp + u][4 * cg + v] -= acc[u][v];
             }
-            __syncthreads();
         }
+        __syncthreads();
         for (int e = tid; e < NB * SW; e += NT) Ck[(size_t)(e / SW) * ldt + s0 + e % SW] = X[e / SW][e % SW];
         __syncthreads();
     }
@@ -188,36 +204,58 @@ __global__ void k_gemv_n_sum(const double *part, int nslice, int64_t m, int nrhs
     }
 }
 
-// Y (n x nrhs rows) <- alpha A^T R + beta Y: one workgroup per column of A,
-// its threads stride over the rows and reduce in a fixed tree.
-__global__ __launch_bounds__(256) void k_gemv_t(const double *A, int64_t lda, int64_t m, int64_t n, const double *Rv,
-                                                int ldt, int nrhs, double alpha, double beta, double *Y)
+// Y (n x nrhs rows) <- alpha A^T R + beta Y.  Workgroup (x, y) takes 64
+// columns of A and a slice of its rows: per chunk of 64 rows the chunk of R
+// and the 64 x 64 block of A are staged in LDS (A read once, coalesced down
+// its columns), each thread keeps 8 outputs (one column, 8 right-hand
+// sides); the per-slice partial sums go to `part` and a second pass adds
+// them in slice order (deterministic).
+__global__ __launch_bounds__(256) void k_gemv_t_part(const double *A, int64_t lda, int64_t m, int64_t n,
+                                                     const double *Rv, int ldt, int nr, int64_t rows_per_slice,
+                                                     double *part)
 {
-    __shared__ double red[256][9];
-    const int64_t col = blockIdx.x;
-    const double *a = A + col * lda;
-    for (int v0 = 0; v0 < nrhs; v0 += 8) {
-        const int nv = std::min(8, nrhs - v0);
-        double acc[8] = {};
-        for (int64_t r = threadIdx.x; r < m; r += 256) {
-            const double av = a[r];
-#pragma unroll
-            for (int v = 0; v < 8; ++v)
-                if (v < nv) acc[v] += av * Rv[r * ldt + v0 + v];
-        }
-#pragma unroll
-        for (int v = 0; v < 8; ++v) red[threadIdx.x][v] = acc[v];
+    __shared__ double rs[64][SW + 1];
+    __shared__ double as[64][65];
+    const int tid = threadIdx.x, cl = tid % 64, vg = tid / 64;
+    const int64_t c0 = (int64_t)blockIdx.x * 64;
+    const int64_t r0 = (int64_t)blockIdx.y * rows_per_slice, r1 = std::min<int64_t>(m, r0 + rows_per_slice);
+    double acc[8] = {};
+    for (int64_t rb = r0; rb < r1; rb += 64) {
         __syncthreads();
-        for (int h = 128; h > 0; h >>= 1) {
-            if ((int)threadIdx.x < h)
-                for (int v = 0; v < 8; ++v) red[threadIdx.x][v] += red[threadIdx.x + h][v];
-            __syncthreads();
+        for (int e = tid; e < 64 * SW; e += 256) {
+            const int rr = e / SW, v = e % SW;
+            const int64_t row = rb + rr;
+            rs[rr][v] = (row < r1 && v < nr) ? Rv[row * ldt + v] : 0.0;
         }
-        if ((int)threadIdx.x < nv) {
-            const int v = threadIdx.x;
-            Y[col * ldt + v0 + v] = alpha * red[0][v] + (beta == 0.0 ? 0.0 : beta * Y[col * ldt + v0 + v]);
+        for (int e = tid; e < 64 * 64; e += 256) {
+            const int cc = e / 64, rr = e % 64;
+            const int64_t row = rb + rr, col = c0 + cc;
+            as[cc][rr] = (row < r1 && col < n) ? A[col * lda + row] : 0.0;
         }
         __syncthreads();
+        for (int rr = 0; rr < 64; ++rr) {
+            const double a = as[cl][rr];
+#pragma unroll
+            for (int v = 0; v < 8; ++v) acc[v] += a * rs[rr][vg * 8 + v];
+        }
+    }
+    const int64_t col = c0 + cl;
+    if (col < n)
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+            if (vg * 8 + v < nr) part[((int64_t)blockIdx.y * n + col) * SW + vg * 8 + v] = acc[v];
+}
+
+__global__ void k_gemv_t_sum(const double *part, int nslice, int64_t n, int nr, double alpha, double beta, double *Y,
+                             int ldt)
+{
+    const int64_t total = n * nr;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t col = e / nr;
+        const int v = (int)(e % nr);
+        double s = 0.0;
+        for (int q = 0; q < nslice; ++q) s += part[((int64_t)q * n + col) * SW + v];
+        Y[col * ldt + v] = alpha * s + (beta == 0.0 ? 0.0 : beta * Y[col * ldt + v]);
     }
 }
 
@@ -337,10 +375,23 @@ hipError_t launch_gemv_n(const double *A, int64_t lda, int64_t m, int64_t n, con
 }
 
 hipError_t launch_gemv_t(const double *A, int64_t lda, int64_t m, int64_t n, const double *R, int ldt, int nrhs,
-                         double alpha, double beta, double *Y, hipStream_t st)
+                         double alpha, double beta, double *Y, double *part, int64_t part_cap, hipStream_t st)
 {
     if (n <= 0 || nrhs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gemv_t, dim3((unsigned)n), dim3(256), 0, st, A, lda, m, n, R, ldt, nrhs, alpha, beta, Y);
+    const int64_t colblk = (n + 63) / 64, rowchunks = std::max<int64_t>(1, (m + 63) / 64);
+    int64_t nslice = std::max<int64_t>(1, std::min<int64_t>(rowchunks, (2048 + colblk - 1) / colblk));
+    nslice = std::min<int64_t>(nslice, part_cap / (n * SW));
+    if (nslice < 1) return hipErrorInvalidValue;
+    const int64_t rps = ((m + nslice - 1) / nslice + 63) / 64 * 64;
+    nslice = std::max<int64_t>(1, (m + rps - 1) / rps);
+    for (int v0 = 0; v0 < nrhs; v0 += SW) {
+        const int nr = std::min(SW, nrhs - v0);
+        hipLaunchKernelGGL(k_gemv_t_part, dim3((unsigned)colblk, (unsigned)nslice), dim3(256), 0, st, A, lda, m, n,
+                           R + v0, ldt, nr, rps, part);
+        const int64_t blocks = std::min<int64_t>((n * nr + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_gemv_t_sum, dim3((unsigned)blocks), dim3(256), 0, st, part, (int)nslice, n, nr, alpha,
+                           beta, Y + v0, ldt);
+    }
     return hipGetLastError();
 }
 

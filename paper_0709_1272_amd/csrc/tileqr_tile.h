@@ -897,12 +897,13 @@ __device__ __forceinline__ void build_t(Smem<NB, IB> &sm, int rlo, gdouble *Tg)
 
 // Trailing update inside GEQRT / TSQRT after the panel at c0 (its V in
 // sm.P, its T in sm.Tl): the panel's reflector is applied to every strip
-// right of it, the strip next to the panel last.  With ib equal to the
+// right of it, the strip next to the panel last, with the products in the
+// task's arithmetic (the reflectors themselves are always formed in FP64).  With ib equal to the
 // strip width that strip is exactly the next panel, so when `chain` is set
 // its result goes straight into sm.P (GEQRT also stores its rows above the
 // next panel, which are final rows of R, to the tile) instead of a round
 // trip through memory.
-template <int NB, int IB, bool TS>
+template <int NB, int IB, bool TS, int PREC>
 __device__ __forceinline__ void panel_trailing(Smem<NB, IB> &sm, gdouble *tile, gdouble *tkk, int c0, bool chain)
 {
     const int first = c0 + IB;
@@ -915,7 +916,8 @@ __device__ __forceinline__ void panel_trailing(Smem<NB, IB> &sm, gdouble *tile, 
         const int cbn = min(CB, (NB - col0) / 16);
         Strip<NB, IB> X;
         load_strip<NB, IB>(X, tile, NB, col0, cbn);
-        apply_panel<NB, IB>(sm, X, rlo, TS ? tkk + (size_t)c0 * NB + col0 : nullptr, NB, cbn);
+        if constexpr (PREC == PREC_FP64) apply_panel<NB, IB>(sm, X, rlo, TS ? tkk + (size_t)c0 * NB + col0 : nullptr, NB, cbn);
+        else apply_panel_mx<NB, IB, PREC>(sm, X, rlo, TS ? tkk + (size_t)c0 * NB + col0 : nullptr, NB);
         if (chain && q + 1 == nst) {
             if constexpr (!TS) store_strip<NB, IB>(X, tile, NB, col0, cbn, rlo, c0 + IB);
             __syncthreads();
@@ -927,7 +929,7 @@ __device__ __forceinline__ void panel_trailing(Smem<NB, IB> &sm, gdouble *tile, 
 }
 
 // DGEQRT(A_kk) -> (V_kk, R_kk, T_kk).
-template <int NB, int IB>
+template <int NB, int IB, int PREC>
 __device__ __forceinline__ void task_geqrt(Smem<NB, IB> &sm, const MatDev &M, int k)
 {
     using C = Cfg<NB, IB>;
@@ -962,13 +964,13 @@ __device__ __forceinline__ void task_geqrt(Smem<NB, IB> &sm, const MatDev &M, in
         __syncthreads();
         build_t<NB, IB>(sm, c0, Tk + l * IB * IB);
         __syncthreads();
-        panel_trailing<NB, IB, false>(sm, tkk, nullptr, c0, CHAIN);
+        panel_trailing<NB, IB, false, PREC>(sm, tkk, nullptr, c0, CHAIN);
         __syncthreads();
     }
 }
 
 // DTSQRT(R_kk, A_ik) -> (R_kk, V_ik, T_ik).
-template <int NB, int IB>
+template <int NB, int IB, int PREC>
 __device__ __forceinline__ void task_tsqrt(Smem<NB, IB> &sm, const MatDev &M, int k, int i)
 {
     using C = Cfg<NB, IB>;
@@ -1003,7 +1005,7 @@ __device__ __forceinline__ void task_tsqrt(Smem<NB, IB> &sm, const MatDev &M, in
         }
         build_t<NB, IB>(sm, 0, Ti + l * IB * IB);
         __syncthreads();
-        panel_trailing<NB, IB, true>(sm, tik, tkk, c0, CHAIN);
+        panel_trailing<NB, IB, true, PREC>(sm, tik, tkk, c0, CHAIN);
         __syncthreads();
     }
 }
@@ -1098,8 +1100,8 @@ template <int NB, int IB, int ROLE, int PREC>
 __device__ __forceinline__ void run_task(Smem<NB, IB> &sm, const MatDev &M, const Task &t)
 {
     if constexpr (ROLE == ROLE_PANEL) {
-        if (t.type == GEQRT) task_geqrt<NB, IB>(sm, M, t.k);
-        else task_tsqrt<NB, IB>(sm, M, t.k, t.i);
+        if (t.type == GEQRT) task_geqrt<NB, IB, PREC>(sm, M, t.k);
+        else task_tsqrt<NB, IB, PREC>(sm, M, t.k, t.i);
     } else {
         if (t.type == LARFB) task_larfb<NB, IB, PREC>(sm, M, t.k, t.j, t.s);
         else task_ssrfb<NB, IB, PREC>(sm, M, t.k, t.i, t.j, t.s);
@@ -1118,8 +1120,8 @@ __global__ __launch_bounds__(2 * NB) void k_serial(MatDev M, int k, int i, const
     if (*status != 0) return;
     constexpr int NS = Cfg<NB, IB>::NS;
     const int j = k + 1 + blockIdx.x / NS, s = blockIdx.x % NS;
-    if constexpr (TYPE == GEQRT) task_geqrt<NB, IB>(sm, M, k);
-    else if constexpr (TYPE == TSQRT) task_tsqrt<NB, IB>(sm, M, k, i);
+    if constexpr (TYPE == GEQRT) task_geqrt<NB, IB, PREC>(sm, M, k);
+    else if constexpr (TYPE == TSQRT) task_tsqrt<NB, IB, PREC>(sm, M, k, i);
     else if constexpr (TYPE == LARFB) task_larfb<NB, IB, PREC>(sm, M, k, j, s);
     else task_ssrfb<NB, IB, PREC>(sm, M, k, i, j, s);
 }

@@ -12,6 +12,11 @@ experiments draw entries with randn):
 * ``uniform``      entries i.i.d. uniform(-1, 1)            (square FP64 QR)
 * ``svd_matrix``   A = U diag(s) V^T with random orthogonal U, V and s
                    log-spaced from 1 to 1/kappa              (least squares)
+* ``svd_matrix_device``  the same spectrum at sizes where a host QR of a
+                   Gaussian matrix is too slow: U and V are products of
+                   normalised Walsh-Hadamard transforms, random signs and
+                   random permutations (dense and exactly orthogonal), built
+                   on the GPU with torch                     (large least squares)
 * ``batch_sizes`` / ``batch_matrices``  m ~ U{32..768}, n ~ U{16..m},
                    entries N(0, 1)                           (batched QR)
 """
@@ -52,6 +57,56 @@ def svd_matrix(seed, m, n, kappa, nrhs=1, noise=1e-6):
     if nrhs == 1:
         return A, np.ascontiguousarray(b[:, 0]), np.ascontiguousarray(x[:, 0])
     return A, np.asfortranarray(b), np.asfortranarray(x)
+
+
+def _hadamard(M, dim):
+    """Normalised Walsh-Hadamard transform of M (torch, power-of-two size)
+    along dimension `dim`, in log2(n) butterfly passes."""
+    import torch
+    n = M.shape[dim]
+    x = M if dim == 0 else M.t()
+    x = x.contiguous()
+    cols = x.shape[1]
+    h = 1
+    while h < n:
+        y = x.view(n // (2 * h), 2, h, cols)
+        x = torch.stack((y[:, 0] + y[:, 1], y[:, 0] - y[:, 1]), dim=1).view(n, cols)
+        h *= 2
+    x = x * (1.0 / float(n) ** 0.5)
+    return x if dim == 0 else x.t().contiguous()
+
+
+def svd_matrix_device(seed, n, kappa, nrhs=1, noise=1e-6, device="cuda"):
+    """(A, B, X) as torch tensors on `device`, A n x n with singular values
+    logspace(0, -log10(kappa), n): A = U diag(s) V^T with U = H D1 P1 H D2 and
+    V^T = H D3 P2 H D4 (H the normalised Walsh-Hadamard matrix, D random
+    signs, P random permutations; n a power of two).  A is returned as a
+    contiguous (n, n) tensor holding A column-major (that is, A^T row-major);
+    X ~ N(0, 1) (n x nrhs) and B = A X + noise N(0, 1), both column-major
+    (nrhs, n)."""
+    import torch
+    assert n & (n - 1) == 0, "n must be a power of two"
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    sign = lambda: torch.randint(0, 2, (n,), generator=g, device=device, dtype=torch.int64).to(torch.float64) * 2 - 1
+    perm = lambda: torch.randperm(n, generator=g, device=device)
+    d1, d2, d3, d4 = sign(), sign(), sign(), sign()
+    p1, p2 = perm(), perm()
+    s = torch.logspace(0.0, -float(torch.log10(torch.tensor(kappa))), n, dtype=torch.float64, device=device)
+    # M = U diag(s): columns of diag(s) scaled by d2 ... built row by row
+    M = torch.diag(s * d2)                      # D2 S
+    M = _hadamard(M, 0)                         # H D2 S
+    M = M[p1]                                   # P1 H D2 S
+    M = M * d1[:, None]                         # D1 P1 H D2 S
+    M = _hadamard(M, 0)                         # U S
+    M = _hadamard(M, 1)                         # U S H
+    M = M * d3[None, :]
+    M = M[:, p2]
+    M = _hadamard(M, 1)
+    M = M * d4[None, :]                         # U S V^T
+    X = torch.randn((n, nrhs), generator=g, device=device, dtype=torch.float64)
+    B = M @ X + noise * torch.randn((n, nrhs), generator=g, device=device, dtype=torch.float64)
+    return M.t().contiguous(), B.t().contiguous(), X.t().contiguous()
 
 
 def batch_sizes(seed, count=4000, m_lo=32, m_hi=768, n_lo=16):
