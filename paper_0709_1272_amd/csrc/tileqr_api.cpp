@@ -586,6 +586,7 @@ extern "C" int tileqr_finalize(void)
             w->tws.release();
             w->solve.release();
             w->part.release();
+            w->tflags.release();
             if (w->host_small) (void)hipHostFree(w->host_small);
             for (auto &e : w->ev)
                 if (e) (void)hipEventDestroy(e);
@@ -769,6 +770,9 @@ extern "C" int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double 
     if ((rc = W->part.ensure((size_t)part_cap * sizeof(double)))) return rc;
     if ((rc = W->misc.ensure((SMALL_PART + SMALL_PART_CAP) * sizeof(double)))) return rc;
     if ((rc = W->prog.ensure((size_t)std::min(p, q) * PROG_STRIDE * sizeof(int32_t) + 64))) return rc;
+    const int64_t tflags_cap = cdiv(n, nb) * (ldt / kStripWidth) * FLAG_STRIDE;
+    if ((rc = W->tflags.ensure((size_t)tflags_cap * sizeof(int32_t)))) return rc;
+    const int64_t spin = o.spin_limit > 0 ? o.spin_limit : (int64_t)1 << 24;
     if ((rc = W->status.ensure(256))) return rc;
     if (!W->ev[0])
         for (auto &e : W->ev) TQ_HIP(hipEventCreate(&e));
@@ -808,7 +812,8 @@ extern "C" int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double 
     TQ_HIP(launch_cm2rows(B, ldb, m, nrhs, c.buf[SB], (int64_t)p * nb, ldt, st));
     TQ_HIP(launch_axpy_rows(c.buf[SB], c.buf[SX], ldt, m, c.nrhs, 2, st));
     TQ_HIP(apply_rows(W, c.nb, c.ib, p, q, c.T, c.buf[SX], ldt, true, st));
-    TQ_HIP(launch_trsm(c.nb, (double *)W->tiles.ptr, p, n, c.buf[SX], ldt, true, dstatus, st));
+    TQ_HIP(launch_trsm(c.nb, (double *)W->tiles.ptr, p, n, c.buf[SX], ldt, true, (int *)W->tflags.ptr, tflags_cap,
+                       dstatus, spin, st));
     // zero the rows n.. of x (they held (Q^T b)(n:m))
     TQ_HIP(hipMemsetAsync(c.buf[SX] + (size_t)n * ldt, 0, (size_t)(p * nb - n) * ldt * sizeof(double), st));
     TQ_HIP(launch_axpy_rows(c.buf[SB], c.buf[SR], ldt, m, c.nrhs, 2, st));
@@ -845,13 +850,15 @@ extern "C" int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double 
         TQ_HIP(launch_gemv_t(A, lda, m, n, c.buf[SR], ldt, c.nrhs, -1.0, 0.0, G, c.part, part_cap, st));
         // [f1; f2] = Q^T f ;  d1 = R^{-T} g ;  dx = R^{-1} (f1 - d1) ;  dr = Q [d1; f2]
         TQ_HIP(apply_rows(W, c.nb, c.ib, p, q, c.T, F, ldt, true, st));
-        TQ_HIP(launch_trsm(c.nb, (double *)W->tiles.ptr, p, n, G, ldt, false, dstatus, st));
+        TQ_HIP(launch_trsm(c.nb, (double *)W->tiles.ptr, p, n, G, ldt, false, (int *)W->tflags.ptr, tflags_cap,
+                           dstatus, spin, st));
         double *DX = c.buf[SS];
         TQ_HIP(launch_axpy_rows(F, DX, ldt, n, c.nrhs, 2, st));
         TQ_HIP(launch_axpy_rows(G, DX, ldt, n, c.nrhs, 0, st));          // DX = G - DX = d1 - f1
         TQ_HIP(launch_axpy_rows(nullptr, DX, ldt, n, c.nrhs, 3, st));    // DX = f1 - d1
         TQ_HIP(hipMemsetAsync(DX + (size_t)n * ldt, 0, (size_t)(p * nb - n) * ldt * sizeof(double), st));
-        TQ_HIP(launch_trsm(c.nb, (double *)W->tiles.ptr, p, n, DX, ldt, true, dstatus, st));
+        TQ_HIP(launch_trsm(c.nb, (double *)W->tiles.ptr, p, n, DX, ldt, true, (int *)W->tflags.ptr, tflags_cap,
+                           dstatus, spin, st));
         TQ_HIP(launch_axpy_rows(DX, c.buf[SX], ldt, n, c.nrhs, 1, st));
         TQ_HIP(launch_axpy_rows(G, F, ldt, n, c.nrhs, 2, st));             // F = [d1; f2]
         TQ_HIP(apply_rows(W, c.nb, c.ib, p, q, c.T, F, ldt, false, st));

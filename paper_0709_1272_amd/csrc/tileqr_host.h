@@ -51,7 +51,7 @@ struct TuneEntry {
 // Library workspace of one device.
 struct Workspace {
     int device = -1;
-    DevBuf tiles, status, trace, misc, rows, prog, tws, solve, part;
+    DevBuf tiles, status, trace, misc, rows, prog, tws, solve, part, tflags;
     SchedBufs sched;                      // single-matrix calls
     // Batched calls keep their own buffers so that a captured graph stays
     // valid across single-matrix calls.

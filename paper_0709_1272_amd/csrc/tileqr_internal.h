@@ -91,9 +91,12 @@ hipError_t launch_cm2rows(const double *B, int64_t ldb, int64_t m, int64_t nrhs,
 hipError_t launch_rows2cm(double *B, int64_t ldb, int64_t m, int64_t nrhs, const double *Bt, int ldt, hipStream_t st);
 
 // Triangular solves with the tiled R on row blocks C (ldt a multiple of 32):
-// R X = C (upper) or R^T X = C, n = order of R.
-hipError_t launch_trsm(int nb, const double *tiles, int p, int64_t n, double *C, int ldt, bool upper, int *status,
-                       hipStream_t st);
+// R X = C (upper) or R^T X = C, n = order of R.  One persistent launch;
+// `flags` holds flags_cap ints, ceil(n / nb) * (ldt / 32) * FLAG_STRIDE are
+// needed (hipErrorInvalidValue otherwise).
+constexpr int FLAG_STRIDE = 64;
+hipError_t launch_trsm(int nb, const double *tiles, int p, int64_t n, double *C, int ldt, bool upper, int *flags,
+                       int64_t flags_cap, int *status, int64_t spin_limit, hipStream_t st);
 // Y = alpha A X + beta Y (column-major A, m x n; X, Y row blocks); `part`
 // is scratch of part_cap doubles for the deterministic column-slice sums.
 hipError_t launch_gemv_n(const double *A, int64_t lda, int64_t m, int64_t n, const double *X, int ldt, int nrhs,

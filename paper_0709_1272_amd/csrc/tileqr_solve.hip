@@ -25,134 +25,157 @@ __device__ __forceinline__ const double *tile_at(const double *tiles, int p, int
 
 }  // namespace
 
-// Solve with the diagonal tile k of R, in place on row block k of C:
-//   upper == true:  R_kk X = C_k (back substitution),
-//   upper == false: R_kk^T X = C_k (forward substitution).
-// The tile is taken in 32 x 32 diagonal blocks (bottom-up for R, top-down for
-// R^T).  For each block the 32 columns of op(R) that hold it are staged in
-// LDS (coalesced), the block is solved by half-waves (one right-hand side per
-// half-wave, one row per lane, reciprocals of the diagonal computed once),
-// and the rows of the tile that depend on it are updated by a register-
-// blocked product (4 x 4 outputs per thread).  Rows at or beyond `n`
-// (padding) get X = 0; an exact zero on the diagonal of a real row sets
+// Triangular solve with the tiled R on a 32-wide strip of right-hand sides,
+// one workgroup per row block i (and strip, blockIdx.y):
+//   upper == true:  R X = C,   X_i = R_ii^{-1} (C_i - sum_{j > i} R_ij X_j)
+//   upper == false: R^T X = C, X_i = R_ii^{-T} (C_i - sum_{j < i} R_ji^T X_j)
+// The workgroup applies the solved blocks X_j as soon as their workgroup
+// publishes them (progress flags, FLAG_STRIDE words apart), accumulating
+// op(R)_ij X_j in registers (4 x 4 outputs per thread, op(R) staged in LDS by
+// 32-column chunks), then solves with its diagonal tile and publishes X_i.
+// Producers have the lower workgroup indices (for R the last block comes
+// first), so every wait is on a workgroup that was dispatched earlier; every
+// wait is bounded (STATUS_TIMEOUT).  The diagonal tile is taken in 32 x 32
+// blocks: the 32 columns of op(R) holding a block are staged in LDS, the
+// block is solved by half-waves (one right-hand side per half-wave, one row
+// per lane, reciprocals of the diagonal computed once) and the rows that
+// depend on it are updated by a register-blocked product.  Rows at or beyond
+// `n` (padding) get X = 0; an exact zero on the diagonal of a real row sets
 // STATUS_SINGULAR.
 template <int NB>
-__global__ __launch_bounds__(2 * NB) void k_trsm_diag(const double *tiles, int p, int64_t n, int k, double *C,
-                                                      int ldt, int upper, int *status)
+__global__ __launch_bounds__(2 * NB) void k_trsm(const double *tiles, int p, int q, int64_t n, double *C, int ldt,
+                                                 int upper, int *flags, int *status, int64_t spin_limit)
 {
     constexpr int NT = 2 * NB, NBLK = NB / 32;
-    __shared__ double X[NB][SW + 1];
-    __shared__ double Rc[NB][33];   // Rc[row][j] = op(R)[row][32 b + j]
+    __shared__ double Xs[NB][SW + 1];
+    __shared__ double Rc[NB][33];
     __shared__ double dinv[32];
+    __shared__ int s_abort;
     const int tid = threadIdx.x, lane = tid & 63, hw = tid >> 5;   // half-wave index
-    const double *R = tile_at(tiles, p, NB, k, k);
-    double *Ck = C + (size_t)k * NB * ldt;
-    const int rgp = tid / 8, cg = tid % 8;   // update: rows 4 rgp .. +3, columns 4 cg .. +3
-    for (int s0 = 0; s0 < ldt; s0 += SW) {
-        for (int e = tid; e < NB * SW; e += NT) X[e / SW][e % SW] = Ck[(size_t)(e / SW) * ldt + s0 + e % SW];
-        for (int bb = 0; bb < NBLK; ++bb) {
-            const int b = upper ? NBLK - 1 - bb : bb;
-            __syncthreads();
-            if (upper) {
-                for (int e = tid; e < NB * 32; e += NT) Rc[e / 32][e % 32] = R[(size_t)(e / 32) * NB + b * 32 + e % 32];
-            } else {
-                for (int e = tid; e < NB * 32; e += NT) Rc[e % NB][e / NB] = R[(size_t)(b * 32 + e / NB) * NB + e % NB];
-            }
-            __syncthreads();
-            if (tid < 32) {
-                const double d = Rc[b * 32 + tid][tid];
-                const bool real = (int64_t)k * NB + b * 32 + tid < n;
-                if (real && d == 0.0) atomicOr(status, STATUS_SINGULAR);
-                dinv[tid] = (real && d != 0.0) ? 1.0 / d : 0.0;
-            }
-            __syncthreads();
-            const int i = lane & 31;
-            const int64_t grow = (int64_t)k * NB + b * 32 + i;
-            for (int c = hw; c < SW; c += NT / 32) {
-                double x = X[b * 32 + i][c];
-                for (int q = 0; q < 32; ++q) {
-                    const int r = upper ? 31 - q : q;
-                    const double xr = __shfl(x, r, 32) * dinv[r];
-                    if (i == r) x = xr;
-                    else if (upper ? i < r : i > r) x -= Rc[b * 32 + i][r] * xr;
+    const int strip = blockIdx.y, nstrip = gridDim.y, s0 = strip * SW;
+    const int i = upper ? q - 1 - (int)blockIdx.x : (int)blockIdx.x;
+    double *Ci = C + (size_t)i * NB * ldt;
+    const int rgp = tid / 8, cg = tid % 8;   // rows 4 rgp .. +3, columns 4 cg .. +3
+    double acc[4][4] = {};
+    const int nj = upper ? q - 1 - i : i;
+    for (int t = 0; t < nj; ++t) {
+        const int j = upper ? q - 1 - t : t;
+        if (tid == 0) {
+            const int *flag = &flags[(j * nstrip + strip) * FLAG_STRIDE];
+            int abort = 0, backoff = 0;
+            int64_t spins = 0;
+            while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+                if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & STATUS_TIMEOUT ||
+                    ++spins > spin_limit) {
+                    __hip_atomic_fetch_or(status, STATUS_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    abort = 1;
+                    break;
                 }
-                X[b * 32 + i][c] = grow < n ? x : 0.0;
+                backoff = backoff < 6 ? backoff + 1 : 6;
+                for (int z = 0; z < (1 << backoff); ++z) __builtin_amdgcn_s_sleep(2);
+            }
+            s_abort = abort;
+        }
+        __syncthreads();
+        if (s_abort) return;
+        if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        __syncthreads();
+        const double *Rt = upper ? tile_at(tiles, p, NB, i, j) : tile_at(tiles, p, NB, j, i);
+        const double *Cj = C + (size_t)j * NB * ldt;
+        for (int e = tid; e < NB * SW; e += NT) Xs[e / SW][e % SW] = Cj[(size_t)(e / SW) * ldt + s0 + e % SW];
+        for (int kc = 0; kc < NB; kc += 32) {
+            __syncthreads();
+            // Rc[row][kk] = op(R)_ij[row][kc + kk]
+            if (upper) {
+                for (int e = tid; e < NB * 32; e += NT) Rc[e / 32][e % 32] = Rt[(size_t)(e / 32) * NB + kc + e % 32];
+            } else {
+                for (int e = tid; e < NB * 32; e += NT) Rc[e % NB][e / NB] = Rt[(size_t)(kc + e / NB) * NB + e % NB];
             }
             __syncthreads();
-            // Rows outside the block that depend on it.
-            const int r0 = upper ? 0 : (b + 1) * 32, r1 = upper ? b * 32 : NB;
-            if (4 * rgp >= r0 && 4 * rgp < r1) {
-                double acc[4][4] = {};
-                for (int j = 0; j < 32; ++j) {
-                    double a[4], xv[4];
+            for (int kk = 0; kk < 32; ++kk) {
+                double a[4], b[4];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        a[u] = Rc[4 * rgp + u][j];
-                        xv[u] = X[b * 32 + j][4 * cg + u];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * xv[v];
+                for (int u = 0; u < 4; ++u) {
+                    a[u] = Rc[4 * rgp + u][kk];
+                    b[u] = Xs[kc + kk][4 * cg + u];
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) X[4 * rgp + u][4 * cg + v] -= acc[u][v];
+                    for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
             }
         }
         __syncthreads();
-        for (int e = tid; e < NB * SW; e += NT) Ck[(size_t)(e / SW) * ldt + s0 + e % SW] = X[e / SW][e % SW];
-        __syncthreads();
     }
-}
-
-// Update the other row blocks with the solved block k:
-//   upper:  C_i -= R_ik X_k        for i = blockIdx.x (< k),
-//   !upper: C_i -= R_ki^T X_k      for i = k + 1 + blockIdx.x.
-// One strip of 32 right-hand sides per blockIdx.y; X_k and 32-wide chunks of
-// the R tile are staged in LDS; each thread owns a 4 x 4 block of outputs.
-template <int NB>
-__global__ __launch_bounds__(2 * NB) void k_trsm_update(const double *tiles, int p, int k, double *C, int ldt,
-                                                        int upper)
-{
-    constexpr int NT = 2 * NB;
-    __shared__ double X[NB][SW + 1];
-    __shared__ double Rc[NB][33];
-    const int tid = threadIdx.x;
-    const int i = upper ? (int)blockIdx.x : k + 1 + (int)blockIdx.x;
-    const int s0 = blockIdx.y * SW;
-    const double *Rt = upper ? tile_at(tiles, p, NB, i, k) : tile_at(tiles, p, NB, k, i);
-    const double *Ck = C + (size_t)k * NB * ldt;
-    double *Ci = C + (size_t)i * NB * ldt;
-    for (int e = tid; e < NB * SW; e += NT) X[e / SW][e % SW] = Ck[(size_t)(e / SW) * ldt + s0 + e % SW];
-    const int rgp = tid / 8, cg = tid % 8;   // rows 4 rgp .. +3, columns 4 cg .. +3
-    double acc[4][4] = {};
-    for (int kc = 0; kc < NB; kc += 32) {
+    // X_i <- C_i - accumulated products, then the diagonal solve in place.
+    for (int e = tid; e < NB * SW; e += NT) Xs[e / SW][e % SW] = Ci[(size_t)(e / SW) * ldt + s0 + e % SW];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Xs[4 * rgp + u][4 * cg + v] -= acc[u][v];
+    const double *R = tile_at(tiles, p, NB, i, i);
+    for (int bb = 0; bb < NBLK; ++bb) {
+        const int b = upper ? NBLK - 1 - bb : bb;
         __syncthreads();
-        // Rc[row][kk] = op(R)[row][kc + kk]
-        for (int e = tid; e < NB * 32; e += NT) {
-            const int row = upper ? e / 32 : e % NB, kk = upper ? e % 32 : e / NB;
-            Rc[row][kk] = upper ? Rt[(size_t)row * NB + kc + kk] : Rt[(size_t)(kc + kk) * NB + row];
+        if (upper) {
+            for (int e = tid; e < NB * 32; e += NT) Rc[e / 32][e % 32] = R[(size_t)(e / 32) * NB + b * 32 + e % 32];
+        } else {
+            for (int e = tid; e < NB * 32; e += NT) Rc[e % NB][e / NB] = R[(size_t)(b * 32 + e / NB) * NB + e % NB];
         }
         __syncthreads();
-        for (int kk = 0; kk < 32; ++kk) {
-            double a[4], b[4];
+        if (tid < 32) {
+            const double d = Rc[b * 32 + tid][tid];
+            const bool real = (int64_t)i * NB + b * 32 + tid < n;
+            if (real && d == 0.0) atomicOr(status, STATUS_SINGULAR);
+            dinv[tid] = (real && d != 0.0) ? 1.0 / d : 0.0;
+        }
+        __syncthreads();
+        const int r_i = lane & 31;
+        const int64_t grow = (int64_t)i * NB + b * 32 + r_i;
+        for (int c = hw; c < SW; c += NT / 32) {
+            double x = Xs[b * 32 + r_i][c];
+            for (int qq = 0; qq < 32; ++qq) {
+                const int r = upper ? 31 - qq : qq;
+                const double xr = __shfl(x, r, 32) * dinv[r];
+                if (r_i == r) x = xr;
+                else if (upper ? r_i < r : r_i > r) x -= Rc[b * 32 + r_i][r] * xr;
+            }
+            Xs[b * 32 + r_i][c] = grow < n ? x : 0.0;
+        }
+        __syncthreads();
+        // Rows outside the block that depend on it.
+        const int r0 = upper ? 0 : (b + 1) * 32, r1 = upper ? b * 32 : NB;
+        if (4 * rgp >= r0 && 4 * rgp < r1) {
+            double d4a[4][4] = {};
+            for (int jj = 0; jj < 32; ++jj) {
+                double a[4], xv[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                a[u] = Rc[4 * rgp + u][kk];
-                b[u] = X[kc + kk][4 * cg + u];
+                for (int u = 0; u < 4; ++u) {
+                    a[u] = Rc[4 * rgp + u][jj];
+                    xv[u] = Xs[b * 32 + jj][4 * cg + u];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) d4a[u][v] += a[u] * xv[v];
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+                for (int v = 0; v < 4; ++v) Xs[4 * rgp + u][4 * cg + v] -= d4a[u][v];
         }
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Ci[(size_t)(4 * rgp + u) * ldt + s0 + 4 * cg + v] -= acc[u][v];
+    __syncthreads();
+    for (int e = tid; e < NB * SW; e += NT) Ci[(size_t)(e / SW) * ldt + s0 + e % SW] = Xs[e / SW][e % SW];
+    // Publish X_i: every wave waits for its stores, then one writes back
+    // and raises the flag.
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __syncthreads();
+    if (tid == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_store(&flags[(i * nstrip + strip) * FLAG_STRIDE], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // Y (row-major rows, leading dimension ldt, m x nrhs) <- alpha A X + beta Y
@@ -325,33 +348,37 @@ __global__ void k_axpy_rows(const double *X, double *Y, int ldt, int64_t m, int 
     }
 }
 
+// Progress flags of k_trsm <- 0 (one per FLAG_STRIDE words).
+__global__ void k_fill_flags(int *flags, int count)
+{
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < count; e += gridDim.x * blockDim.x)
+        flags[e * FLAG_STRIDE] = 0;
+}
+
 // ------------------------------------------------------------ launchers
 
 template <int NB>
-static hipError_t trsm_impl(const double *tiles, int p, int64_t n, double *C, int ldt, bool upper, int *status,
-                            hipStream_t st)
+static hipError_t trsm_impl(const double *tiles, int p, int64_t n, double *C, int ldt, bool upper, int *flags,
+                            int *status, int64_t spin_limit, hipStream_t st)
 {
     const int q = (int)((n + NB - 1) / NB);
     const int nstrip = ldt / SW;
-    for (int s = 0; s < q; ++s) {
-        const int k = upper ? q - 1 - s : s;
-        hipLaunchKernelGGL(k_trsm_diag<NB>, dim3(1), dim3(2 * NB), 0, st, tiles, p, n, k, C, ldt, upper ? 1 : 0,
-                           status);
-        const int others = upper ? k : q - 1 - k;
-        if (others > 0)
-            hipLaunchKernelGGL(k_trsm_update<NB>, dim3(others, nstrip), dim3(2 * NB), 0, st, tiles, p, k, C, ldt,
-                               upper ? 1 : 0);
-    }
+    hipLaunchKernelGGL(k_fill_flags, dim3((unsigned)std::max(1, std::min(1024, (q * nstrip + 255) / 256))), dim3(256),
+                       0, st, flags, q * nstrip);
+    hipLaunchKernelGGL(k_trsm<NB>, dim3(q, nstrip), dim3(2 * NB), 0, st, tiles, p, q, n, C, ldt, upper ? 1 : 0, flags,
+                       status, spin_limit);
     return hipGetLastError();
 }
 
-hipError_t launch_trsm(int nb, const double *tiles, int p, int64_t n, double *C, int ldt, bool upper, int *status,
-                       hipStream_t st)
+hipError_t launch_trsm(int nb, const double *tiles, int p, int64_t n, double *C, int ldt, bool upper, int *flags,
+                       int64_t flags_cap, int *status, int64_t spin_limit, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    if (nb == 64) return trsm_impl<64>(tiles, p, n, C, ldt, upper, status, st);
-    if (nb == 128) return trsm_impl<128>(tiles, p, n, C, ldt, upper, status, st);
-    if (nb == 256) return trsm_impl<256>(tiles, p, n, C, ldt, upper, status, st);
+    const int64_t q = (n + nb - 1) / nb;
+    if (q * (ldt / SW) * FLAG_STRIDE > flags_cap) return hipErrorInvalidValue;
+    if (nb == 64) return trsm_impl<64>(tiles, p, n, C, ldt, upper, flags, status, spin_limit, st);
+    if (nb == 128) return trsm_impl<128>(tiles, p, n, C, ldt, upper, flags, status, spin_limit, st);
+    if (nb == 256) return trsm_impl<256>(tiles, p, n, C, ldt, upper, flags, status, spin_limit, st);
     return hipErrorInvalidValue;
 }
 
