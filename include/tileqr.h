@@ -270,8 +270,10 @@ int64_t tileqr_dag_counts(int64_t p, int64_t q, int64_t strips, int64_t counts[4
  * symbolic tile-version model and checks that every task sees each tile in
  * the state Algorithm 2's loop order would give it.  Also checks that
  * in-degrees equal the number of predecessors that release each task.
- * Returns 0 if all orders pass, else the 1-based number of the failing
- * trial.  Host only. */
+ * Also checks that the per-queue task counts the scheduler derives by index
+ * ranges equal the tasks each ready queue receives.  Returns 0 if all pass,
+ * else the 1-based number of the failing trial (trials + 1 for a queue count
+ * mismatch).  Host only. */
 int tileqr_dag_selfcheck(int64_t p, int64_t q, int64_t strips, int64_t trials, uint64_t seed);
 
 /* Trace of the last factorisation run with TILEQR_FLAG_TRACE: up to `cap`

@@ -292,6 +292,18 @@ extern "C" int tileqr_dag_selfcheck(int64_t p, int64_t q, int64_t strips, int64_
         for (int64_t id = 0; id < g.total; ++id)
             if (cnt[id] > 0) return (int)(trial + 1);
     }
+    // The queue capacities the scheduler derives by index ranges must equal
+    // the number of tasks each queue receives.
+    for (int mat : {0, 1, 7}) {
+        int64_t a[NQUEUE] = {0}, b[NQUEUE] = {0};
+        for (int64_t id = 0; id < g.total; ++id) {
+            const Task t = decode(g, id);
+            if (valid(g, t)) ++a[queue_of(t, g.ns, mat)];
+        }
+        count_queue_tasks(g, mat, b);
+        for (int l = 0; l < NQUEUE; ++l)
+            if (a[l] != b[l]) return (int)(trials + 1);
+    }
     return 0;
 }
 
@@ -337,26 +349,11 @@ int prepare_schedule(Workspace *W, SchedBufs &B, std::vector<MatDev> &mats, int 
         M.task_base = total_ids;
         total_ids += g.total;
         kmax_max = std::max<int64_t>(kmax_max, g.kmax);
+        count_queue_tasks(g, mi, counts);
         for (int k = 0; k < g.kmax; ++k) {
-            const int64_t rows = g.p - k - 1;   // TSQRT(k, .) and SSRFB(k, ., j, s) per (j, s)
-            counts[queue_index(0, 0)] += 1;
-            counts[queue_index(1, 0)] += rows;
-            ntask += 1 + rows;
+            const int64_t rows = g.p - k - 1;
+            ntask += 1 + rows + (int64_t)(1 + rows) * (g.q - k - 1) * ns;
             panel_flops += (4.0 / 3.0) * b3 + 2.0 * b3 * rows;
-            for (int j = k + 1; j < g.q; ++j)
-                for (int s = 0; s < ns; ++s) {
-                    Task t;
-                    t.k = k;
-                    t.j = j;
-                    t.s = s;
-                    t.i = k;
-                    t.type = LARFB;
-                    counts[queue_of(t, ns, mi)] += 1;
-                    t.type = SSRFB;
-                    t.i = k + 1;
-                    counts[queue_of(t, ns, mi)] += rows;
-                    ntask += 1 + rows;
-                }
             all_flops += (double)(g.q - k - 1) * (2.0 * b3 + (4.0 * b3 + (double)ib * nb * nb) * rows);
         }
     }

@@ -219,6 +219,31 @@ TQ_HD int queue_of(const Task &t, int ns, int mat)
     return queue_index(level, x);
 }
 
+// Tasks of each ready queue for one matrix (number `mat` of a batch),
+// counted by index ranges rather than by decoding every id: the capacities
+// the scheduler gives the queues.  Adds to counts[0 .. NQUEUE-1].
+inline void count_queue_tasks(const Grid &g, int mat, int64_t *counts)
+{
+    for (int k = 0; k < g.kmax; ++k) {
+        const int64_t rows = g.p - k - 1;   // TSQRT(k, .), and SSRFB(k, ., j, s) per (j, s)
+        counts[queue_index(0, 0)] += 1;
+        counts[queue_index(1, 0)] += rows;
+        for (int j = k + 1; j < g.q; ++j)
+            for (int s = 0; s < g.ns; ++s) {
+                Task t;
+                t.k = k;
+                t.j = j;
+                t.s = s;
+                t.i = k;
+                t.type = LARFB;
+                counts[queue_of(t, g.ns, mat)] += 1;
+                t.type = SSRFB;
+                t.i = k + 1;
+                counts[queue_of(t, g.ns, mat)] += rows;   // the queue does not depend on i
+            }
+    }
+}
+
 // Leading-order flops of one task (Section 3.2.3: SSRFB costs 4b^3 + sb^2;
 // GEQRT 4b^3/3, TSQRT and LARFB 2b^3), for a strip task its share.
 TQ_HD double task_flops(const Task &t, int nb, int ib, int ns)

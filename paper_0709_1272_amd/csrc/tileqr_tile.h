@@ -1220,6 +1220,7 @@ template <int NB, int IB, int ROLE, int PREC>
 __device__ __forceinline__ void worker_loop(Smem<NB, IB> &sm, const SchedDev &S)
 {
     __shared__ int64_t s_gid, s_next;
+    __shared__ int s_next_queue;
     __shared__ int s_exit;
     __shared__ uint64_t s_tpop, s_trun;
     const int tid = threadIdx.x;
@@ -1236,6 +1237,17 @@ __device__ __forceinline__ void worker_loop(Smem<NB, IB> &sm, const SchedDev &S)
             int64_t gid = s_next;
             int ex = 0;
             s_next = -1;
+            // A kept update below the lookahead level yields to a lookahead
+            // update waiting in this XCD's queue (the kept one is queued).
+            if constexpr (ROLE == ROLE_UPDATE) {
+                if (gid >= 0 && s_next_queue >= queue_index(3, 0)) {
+                    const int64_t la = pop_task(S, queue_index(2, xcd));
+                    if (la >= 0) {
+                        push_task(S, s_next_queue, gid);
+                        gid = la;
+                    }
+                }
+            }
             if (gid < 0) {
                 // Poll the queues with exponential back-off, look at the
                 // completion counter and the status word only every few
@@ -1326,7 +1338,10 @@ __device__ __forceinline__ void worker_loop(Smem<NB, IB> &sm, const SchedDev &S)
                 const uint64_t cand = __ballot(ready && mine);
                 const int keeper = (!kept && cand != 0) ? __ffsll((unsigned long long)cand) - 1 : -1;
                 if (ready) {
-                    if (tid == keeper) s_next = sgid;
+                    if (tid == keeper) {
+                        s_next = sgid;
+                        s_next_queue = queue;
+                    }
                     else push_task(S, queue, sgid);
                 }
                 kept = kept || keeper >= 0;
