@@ -103,7 +103,8 @@ typedef struct {
                              its first successor release; -1 (default) = none        */
     int64_t panel_workers;/* panel-role workgroups of the DAG scheduler (GEQRT, TSQRT);
                              0 = automatic (one matrix: one per concurrent panel
-                             chain, at most 8; a batch: in proportion to the panel
+                             chain, at most 16 with up to 32 tile steps, else
+                             at most 8; a batch: in proportion to the panel
                              flops)                                                  */
 } tileqr_opts;
 

@@ -399,15 +399,17 @@ int prepare_schedule(Workspace *W, SchedBufs &B, std::vector<MatDev> &mats, int 
         S.trace_cap = (uint32_t)ntask;
         W->trace_events = ntask;
     }
-    // Panel workers: one matrix has at most one panel chain per step in
-    // flight, so a few suffice (at most one per XCD); many matrices get a
-    // share of the workgroups in proportion to their panel flops.  Update
-    // workers: the rest of what fits at once.
+    // Panel workers: one matrix has one panel chain per step in flight and
+    // a few steps overlap, so a few suffice: 16 when there are at most 32
+    // tile steps (the panel chains are then most of the critical path),
+    // else 8 (the updates dominate and every panel workgroup is one fewer
+    // for them).  Many matrices get a share of the workgroups in proportion
+    // to their panel flops.  Update workers: the rest of what fits at once.
     const int occ = worker_occupancy(nb, ib, o.precision);
     const int capacity = std::max(2, std::max(1, W->num_cu) * occ);
     int panel;
     if (o.panel_workers > 0) panel = (int)o.panel_workers;
-    else if (nmat == 1) panel = (int)std::min<int64_t>(8, kmax_max);
+    else if (nmat == 1) panel = (int)std::min<int64_t>(kmax_max <= 32 ? 16 : 8, kmax_max);
     else panel = (int)std::lround(1.5 * capacity * panel_flops / std::max(all_flops, 1.0));
     panel = std::max(1, std::min(panel, capacity / 2));
     int update = o.workers > 0 ? (int)o.workers : capacity - panel;
