@@ -122,24 +122,32 @@ __device__ __forceinline__ gdouble *tblock_ptr(const MatDev &M, int nb, int ib, 
 }
 
 // Stage <- columns [c0, c0 + ib) of rows [r0, nb) of a row-major tile
-// (rows above r0 left zero) and the ib x ib T block at Tg (zeros when Tg is
-// NULL).
-template <int NB, int IB>
+// (rows above r0 read as zero) and, with HAS_T, the ib x ib T block at Tg
+// (else zeros).  Every thread issues the same loads whatever r0 (the rows
+// above it are read and dropped), so that the compiler's count of loads in
+// flight is exact and a later wait for older loads does not also wait for
+// these.
+template <int NB, int IB, bool HAS_T = true>
 __device__ __forceinline__ void stage_load(Stage<NB, IB> &S, const gdouble *tile, int c0, int r0,
                                            const gdouble *Tg)
 {
     using C = Cfg<NB, IB>;
-    constexpr int H = IB / 2;
+    constexpr int H = IB / 2, TE = IB * IB / 2;
 #pragma unroll
     for (int u = 0; u < C::VPT; ++u) {
         const int e = threadIdx.x + u * C::NT, r = e / H, c2 = e % H;
-        S.v[u] = r >= r0 ? *reinterpret_cast<const gv2d *>(tile + (size_t)r * NB + c0 + 2 * c2)
-                         : v2d{0.0, 0.0};
+        const v2d x = *reinterpret_cast<const gv2d *>(tile + (size_t)r * NB + c0 + 2 * c2);
+        S.v[u] = r >= r0 ? x : v2d{0.0, 0.0};
     }
 #pragma unroll
     for (int u = 0; u < C::TPT; ++u) {
         const int e = threadIdx.x + u * C::NT;
-        S.t[u] = (Tg != nullptr && e < IB * IB / 2) ? reinterpret_cast<const gv2d *>(Tg)[e] : v2d{0.0, 0.0};
+        if constexpr (HAS_T) {
+            const v2d t = reinterpret_cast<const gv2d *>(Tg)[e < TE ? e : TE - 1];
+            S.t[u] = e < TE ? t : v2d{0.0, 0.0};
+        } else {
+            S.t[u] = v2d{0.0, 0.0};
+        }
     }
 }
 
@@ -283,30 +291,53 @@ __device__ __forceinline__ double sum_slots(const Smem<NB, IB> &sm, int e)
     return s;
 }
 
+// Rows 0..ib-1, columns 0..ncol-1 of the coupled upper tile block `top`
+// (row stride ldtop) -> registers in the entry order of sm.Wa (entry
+// e = tid + u * NT is row e / WS, column e % WS; columns from ncol on read
+// as zero).  The callers issue these loads ahead of the next panel's
+// prefetch, so that waiting for them does not wait for the prefetch.
+template <int NB, int IB>
+__device__ __forceinline__ void load_top(double (&tv)[(Cfg<NB, IB>::EPT)], const gdouble *top, int ldtop, int ncol)
+{
+    using C = Cfg<NB, IB>;
+#pragma unroll
+    for (int u = 0; u < C::EPT; ++u) {
+        const int e = threadIdx.x + u * C::NT, kr = e / WS, c = e % WS;
+        tv[u] = (top != nullptr && c < ncol) ? top[(size_t)kr * ldtop + c] : 0.0;
+    }
+}
+
+// top <- tv - sm.Wb over the entries load_top read (a store only: the old
+// values are already in tv).
+template <int NB, int IB>
+__device__ __forceinline__ void store_top(const Smem<NB, IB> &sm, const double (&tv)[Cfg<NB, IB>::EPT], gdouble *top,
+                                          int ldtop, int ncol)
+{
+    using C = Cfg<NB, IB>;
+#pragma unroll
+    for (int u = 0; u < C::EPT; ++u) {
+        const int e = threadIdx.x + u * C::NT, kr = e / WS, c = e % WS;
+        if (c < ncol) top[(size_t)kr * ldtop + c] = tv[u] - sm.Wb[e];
+    }
+}
+
 // Apply the block reflector of one inner panel, held in LDS (sm.P rows
 // 0..nb-1 = V, rows below `rlo` ignored; sm.Tl = T), to a strip X:
 //   W = [top +] V^T X;  W <- T^T W;  [top -= W;]  X -= V W
 // (with TRANS == false, W <- T W: the reflector itself instead of its
 // transpose).
 // `top` (may be NULL) points at the ib x (16 cbn) block of the coupled upper
-// tile (the R rows the TS form also updates), row stride ldtop.
+// tile (the R rows the TS form also updates), row stride ldtop; tv holds
+// that block as load_top read it.
 // Three workgroup barriers; the products V^T X, T^T W and V W run on MFMA.
 template <int NB, int IB, bool TRANS = true>
-__device__ __forceinline__ void apply_panel(Smem<NB, IB> &sm, Strip<NB, IB> &X, int rlo, gdouble *top, int ldtop, int cbn)
+__device__ __forceinline__ void apply_panel(Smem<NB, IB> &sm, Strip<NB, IB> &X, int rlo, gdouble *top, int ldtop, int cbn,
+                                            const double (&tv)[Cfg<NB, IB>::EPT])
 {
     using C = Cfg<NB, IB>;
     const int tid = threadIdx.x, w = wave_id();
     const int n = lane_id() & 15, g = lane_id() >> 4, rowbase = w * 32;
     const int ncol = cbn * 16;
-
-    double tv[C::EPT];
-    if (top != nullptr) {
-#pragma unroll
-        for (int u = 0; u < C::EPT; ++u) {
-            const int e = tid + u * C::NT, kr = e / WS, c = e % WS;
-            tv[u] = c < ncol ? top[(size_t)kr * ldtop + c] : 0.0;
-        }
-    }
 
     // W partial over this wave's rows.
     d4 Wacc[C::IBB][CB];
@@ -346,13 +377,10 @@ __device__ __forceinline__ void apply_panel(Smem<NB, IB> &sm, Strip<NB, IB> &X, 
             acc = mfma(TRANS ? sm.Tl[(4 * kc + g) * IB + a * 16 + n] : sm.Tl[(a * 16 + n) * IB + 4 * kc + g],
                        sm.Wa[(4 * kc + g) * WS + cb * 16 + n], acc);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = a * 16 + 4 * r + g, c = cb * 16 + n;
-            sm.Wb[i * WS + c] = acc[r];
-            if (top != nullptr && c < ncol) top[(size_t)i * ldtop + c] -= acc[r];
-        }
+        for (int r = 0; r < 4; ++r) sm.Wb[(a * 16 + 4 * r + g) * WS + cb * 16 + n] = acc[r];
     }
     __syncthreads();
+    if (top != nullptr) store_top<NB, IB>(sm, tv, top, ldtop, ncol);
     // X -= V (T^T W)
 #pragma unroll
     for (int rb = 0; rb < C::RB; ++rb) {
@@ -472,7 +500,8 @@ __device__ __forceinline__ void column_scale(const double (&x)[8], double &scale
 // precision; ib = 32 so that each wave's share of a product is one K step.
 // Waves whose 32 rows lie above rlo (a multiple of 32) sit the products out.
 template <int NB, int IB, int PREC>
-__device__ __forceinline__ void apply_panel_mx(Smem<NB, IB> &sm, Strip<NB, IB> &X, int rlo, gdouble *top, int ldtop)
+__device__ __forceinline__ void apply_panel_mx(Smem<NB, IB> &sm, Strip<NB, IB> &X, int rlo, gdouble *top, int ldtop,
+                                               const double (&tv)[Cfg<NB, IB>::EPT])
 {
     using C = Cfg<NB, IB>;
     static_assert(IB == 32, "split-precision updates take ib = 32");
@@ -481,15 +510,6 @@ __device__ __forceinline__ void apply_panel_mx(Smem<NB, IB> &sm, Strip<NB, IB> &
     const int tid = threadIdx.x, w = wave_id();
     const int n = lane_id() & 15, g = lane_id() >> 4, rowbase = w * 32;
     const bool active = rowbase >= rlo;
-
-    double tv[C::EPT];
-    if (top != nullptr) {
-#pragma unroll
-        for (int u = 0; u < C::EPT; ++u) {
-            const int e = tid + u * C::NT, kr = e / WS, c = e % WS;
-            tv[u] = top[(size_t)kr * ldtop + c];
-        }
-    }
 
     // This wave's share of V^T X.
     d4 Wacc[C::IBB][CB];
@@ -548,13 +568,10 @@ __device__ __forceinline__ void apply_panel_mx(Smem<NB, IB> &sm, Strip<NB, IB> &
         for (int kc = 0; kc < IB / 4; ++kc)
             acc = mfma(sm.Tl[(4 * kc + g) * IB + a * 16 + n], sm.Wa[(4 * kc + g) * WS + cb * 16 + n], acc);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = a * 16 + 4 * r + g, c = cb * 16 + n;
-            sm.Wb[i * WS + c] = acc[r];
-            if (top != nullptr) top[(size_t)i * ldtop + c] -= acc[r];
-        }
+        for (int r = 0; r < 4; ++r) sm.Wb[(a * 16 + 4 * r + g) * WS + cb * 16 + n] = acc[r];
     }
     __syncthreads();
+    if (top != nullptr) store_top<NB, IB>(sm, tv, top, ldtop, WS);
     // X -= V (T^T W)
     if (active) {
         Parts<PREC> Bw[CB];
@@ -916,8 +933,11 @@ __device__ __forceinline__ void panel_trailing(Smem<NB, IB> &sm, gdouble *tile, 
         const int cbn = min(CB, (NB - col0) / 16);
         Strip<NB, IB> X;
         load_strip<NB, IB>(X, tile, NB, col0, cbn);
-        if constexpr (PREC == PREC_FP64) apply_panel<NB, IB>(sm, X, rlo, TS ? tkk + (size_t)c0 * NB + col0 : nullptr, NB, cbn);
-        else apply_panel_mx<NB, IB, PREC>(sm, X, rlo, TS ? tkk + (size_t)c0 * NB + col0 : nullptr, NB);
+        gdouble *top = TS ? tkk + (size_t)c0 * NB + col0 : nullptr;
+        double tv[Cfg<NB, IB>::EPT] = {};
+        if constexpr (TS) load_top<NB, IB>(tv, top, NB, cbn * 16);
+        if constexpr (PREC == PREC_FP64) apply_panel<NB, IB>(sm, X, rlo, top, NB, cbn, tv);
+        else apply_panel_mx<NB, IB, PREC>(sm, X, rlo, top, NB, tv);
         if (chain && q + 1 == nst) {
             if constexpr (!TS) store_strip<NB, IB>(X, tile, NB, col0, cbn, rlo, c0 + IB);
             __syncthreads();
@@ -941,7 +961,7 @@ __device__ __forceinline__ void task_geqrt(Smem<NB, IB> &sm, const MatDev &M, in
         const int c0 = l * IB;
         if (l == 0 || !CHAIN) {
             Stage<NB, IB> S;
-            stage_load<NB, IB>(S, tkk, c0, c0, nullptr);
+            stage_load<NB, IB, false>(S, tkk, c0, c0, nullptr);
             stage_store<NB, IB>(sm, S, c0, false, c0);
         }
         __syncthreads();
@@ -984,7 +1004,7 @@ __device__ __forceinline__ void task_tsqrt(Smem<NB, IB> &sm, const MatDev &M, in
         const int c0 = l * IB;
         if (l == 0 || !CHAIN) {
             Stage<NB, IB> S;
-            stage_load<NB, IB>(S, tik, c0, 0, nullptr);
+            stage_load<NB, IB, false>(S, tik, c0, 0, nullptr);
             stage_store<NB, IB>(sm, S, 0, false, c0);
         }
         for (int e = threadIdx.x; e < IB * IB; e += C::NT) {
@@ -1025,18 +1045,22 @@ __device__ __forceinline__ void apply_diag_strip(Smem<NB, IB> &sm, const gdouble
     stage_load<NB, IB>(S, tkk, l0 * IB, l0 * IB, Tk + l0 * IB * IB);
     Strip<NB, IB> X;
     load_strip<NB, IB>(X, x, ldx, col0, CB);
+    // Wait for the strip here, once: inside the loop the only loads in
+    // flight are then the next panel's, and the products do not wait for them.
+    __builtin_amdgcn_s_waitcnt(0);
+    double tv[C::EPT] = {};
 #pragma unroll 1
     for (int q = 0; q < C::NPAN; ++q) {
         const int l = TRANS ? q : C::NPAN - 1 - q;
         const int c0 = l * IB;
         stage_store<NB, IB>(sm, S, c0, true, c0);
         __syncthreads();
-        if (q + 1 < C::NPAN) {
-            const int ln = TRANS ? l + 1 : l - 1;
-            stage_load<NB, IB>(S, tkk, ln * IB, ln * IB, Tk + ln * IB * IB);
-        }
-        if constexpr (PREC == PREC_FP64) apply_panel<NB, IB, TRANS>(sm, X, c0, nullptr, 0, CB);
-        else apply_panel_mx<NB, IB, PREC>(sm, X, c0, nullptr, 0);
+        // The next panel's prefetch (after the last panel a harmless reload
+        // of this one, so that the loads issued do not depend on q).
+        const int ln = q + 1 < C::NPAN ? (TRANS ? l + 1 : l - 1) : l;
+        stage_load<NB, IB>(S, tkk, ln * IB, ln * IB, Tk + ln * IB * IB);
+        if constexpr (PREC == PREC_FP64) apply_panel<NB, IB, TRANS>(sm, X, c0, nullptr, 0, CB, tv);
+        else apply_panel_mx<NB, IB, PREC>(sm, X, c0, nullptr, 0, tv);
         __syncthreads();
     }
     store_strip<NB, IB>(X, x, ldx, col0, CB, 0);
@@ -1057,18 +1081,22 @@ __device__ __forceinline__ void apply_ts_strip(Smem<NB, IB> &sm, const gdouble *
     stage_load<NB, IB>(S, tik, l0 * IB, 0, Ti + l0 * IB * IB);
     Strip<NB, IB> X;
     load_strip<NB, IB>(X, x, ldx, col0, CB);
+    // As in apply_diag_strip: the strip is waited for once, before the loop.
+    __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll 1
     for (int q = 0; q < C::NPAN; ++q) {
         const int l = TRANS ? q : C::NPAN - 1 - q;
         const int c0 = l * IB;
         stage_store<NB, IB>(sm, S, 0, false, c0);
         __syncthreads();
-        if (q + 1 < C::NPAN) {
-            const int ln = TRANS ? l + 1 : l - 1;
-            stage_load<NB, IB>(S, tik, ln * IB, 0, Ti + ln * IB * IB);
-        }
-        if constexpr (PREC == PREC_FP64) apply_panel<NB, IB, TRANS>(sm, X, 0, top + (size_t)c0 * ldtop + col0, ldtop, CB);
-        else apply_panel_mx<NB, IB, PREC>(sm, X, 0, top + (size_t)c0 * ldtop + col0, ldtop);
+        // The top rows first, then the next panel's prefetch.
+        gdouble *tp = top + (size_t)c0 * ldtop + col0;
+        double tv[C::EPT];
+        load_top<NB, IB>(tv, tp, ldtop, WS);
+        const int ln = q + 1 < C::NPAN ? (TRANS ? l + 1 : l - 1) : l;
+        stage_load<NB, IB>(S, tik, ln * IB, 0, Ti + ln * IB * IB);
+        if constexpr (PREC == PREC_FP64) apply_panel<NB, IB, TRANS>(sm, X, 0, tp, ldtop, CB, tv);
+        else apply_panel_mx<NB, IB, PREC>(sm, X, 0, tp, ldtop, tv);
         __syncthreads();
     }
     store_strip<NB, IB>(X, x, ldx, col0, CB, 0);
