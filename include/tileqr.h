@@ -106,6 +106,11 @@ typedef struct {
                              chain, at most 16 with up to 32 tile steps, else
                              at most 8; a batch: in proportion to the panel
                              flops)                                                  */
+    int64_t panel_tasks;  /* DAG tasks per GEQRT and TSQRT: 1 (the whole tile
+                             kernel) or nb / ib (one per inner panel, which lets
+                             the panel chains of a step overlap); 0 = automatic
+                             (one matrix with at most 32 tile steps: nb / ib,
+                             otherwise 1)                                           */
 } tileqr_opts;
 
 /* Blocking and schedule of a factorisation, as chosen by tileqr_tune. */
@@ -261,13 +266,16 @@ double tileqr_flops_lapack(int64_t m, int64_t n);
 double tileqr_flops_tiled(int64_t m, int64_t n, int64_t nb, int64_t ib);
 
 /* Tasks of the DAG (Section 4) for a p x q tile grid with `strips` column
- * strips per tile (strips = 1: the paper's tasks).  counts[0..3] receive the
- * numbers of GEQRT, TSQRT, LARFB and SSRFB tasks; returns their sum.
- * Host only, no GPU needed. */
-int64_t tileqr_dag_counts(int64_t p, int64_t q, int64_t strips, int64_t counts[4]);
+ * strips per tile (LARFB and SSRFB split by columns) and `panels` inner
+ * panels per tile (GEQRT and TSQRT split into their ib-column panels; the
+ * scheduler uses strips = nb / 32, panels = nb / ib; strips = panels = 1:
+ * the paper's tasks).  counts[0..3] receive the numbers of GEQRT, TSQRT,
+ * LARFB and SSRFB tasks; returns their sum.  Host only, no GPU needed. */
+int64_t tileqr_dag_counts(int64_t p, int64_t q, int64_t strips, int64_t panels, int64_t counts[4]);
 
 /* Host-side check of the dependency rules the scheduler uses: executes the
- * DAG of a p x q grid in `trials` random topological orders (seeded) on a
+ * DAG of a p x q grid (strips and panels as for tileqr_dag_counts) in
+ * `trials` random topological orders (seeded) on a
  * symbolic tile-version model and checks that every task sees each tile in
  * the state Algorithm 2's loop order would give it.  Also checks that
  * in-degrees equal the number of predecessors that release each task.
@@ -275,10 +283,11 @@ int64_t tileqr_dag_counts(int64_t p, int64_t q, int64_t strips, int64_t counts[4
  * ranges equal the tasks each ready queue receives.  Returns 0 if all pass,
  * else the 1-based number of the failing trial (trials + 1 for a queue count
  * mismatch).  Host only. */
-int tileqr_dag_selfcheck(int64_t p, int64_t q, int64_t strips, int64_t trials, uint64_t seed);
+int tileqr_dag_selfcheck(int64_t p, int64_t q, int64_t strips, int64_t panels, int64_t trials, uint64_t seed);
 
 /* Trace of the last factorisation run with TILEQR_FLAG_TRACE: up to `cap`
- * events copied to host memory, 10 int64 each: {type, k, i, j, strip,
+ * events copied to host memory, 10 int64 each: {type, k, i, j, strip (the
+ * inner panel for GEQRT and TSQRT),
  * worker, t_pop, t_start, t_body_end, t_end} (types 0 GEQRT, 1 TSQRT,
  * 2 LARFB, 3 SSRFB; worker = (role << 16) | workgroup; times in ticks of
  * the device wall clock, tileqr_trace_clock_hz per second: when the task

@@ -152,20 +152,20 @@ extern "C" double tileqr_flops_tiled(int64_t m, int64_t n, int64_t nb, int64_t i
 {
     if (m <= 0 || n <= 0 || nb <= 0 || ib <= 0) return 0.0;
     const int p = (int)cdiv(m, nb), q = (int)cdiv(n, nb);
-    const Grid g = make_grid(p, q, 1);
+    const Grid g = make_grid(p, q, 1, 1);
     double f = 0.0;
     for (int64_t id = 0; id < g.total; ++id) {
         const Task t = decode(g, id);
-        if (valid(g, t)) f += task_flops(t, (int)nb, (int)ib, 1);
+        if (valid(g, t)) f += task_flops(t, (int)nb, (int)ib, 1, 1);
     }
     return f;
 }
 
-extern "C" int64_t tileqr_dag_counts(int64_t p, int64_t q, int64_t strips, int64_t counts[4])
+extern "C" int64_t tileqr_dag_counts(int64_t p, int64_t q, int64_t strips, int64_t panels, int64_t counts[4])
 {
     int64_t c[4] = {0, 0, 0, 0};
-    if (p > 0 && q > 0 && strips > 0) {
-        const Grid g = make_grid((int)p, (int)q, (int)strips);
+    if (p > 0 && q > 0 && strips > 0 && panels > 0) {
+        const Grid g = make_grid((int)p, (int)q, (int)strips, (int)panels);
         for (int64_t id = 0; id < g.total; ++id) {
             const Task t = decode(g, id);
             if (valid(g, t)) ++c[t.type];
@@ -180,16 +180,21 @@ extern "C" int64_t tileqr_dag_counts(int64_t p, int64_t q, int64_t strips, int64
 
 namespace {
 
-// Regions: strip s of tile (i, j), plus the R and V halves of diagonal tiles.
+// Regions: strip s of tile (i, j), plus the R rows of each inner panel and
+// the V half of the diagonal tiles.
 struct RegionMap {
-    int p, q, ns;
+    int p, q, ns, np;
     int64_t strip(int i, int j, int s) const { return ((int64_t)j * p + i) * ns + s; }
-    int64_t rpart(int k) const { return (int64_t)p * q * ns + k; }
-    int64_t vpart(int k) const { return (int64_t)p * q * ns + std::min(p, q) + k; }
-    int64_t size() const { return (int64_t)p * q * ns + 2 * std::min(p, q); }
+    int64_t rrows(int k, int l) const { return (int64_t)p * q * ns + (int64_t)k * np + l; }
+    int64_t vpart(int k) const { return (int64_t)p * q * ns + (int64_t)std::min(p, q) * np + k; }
+    int64_t size() const { return (int64_t)p * q * ns + (int64_t)std::min(p, q) * (np + 1); }
 };
 
-// Reads and writes of a task (Algorithm 2, the table in tileqr_dag.h).
+// Reads and writes of a task (Algorithm 2, the table in tileqr_dag.h).  A
+// panel task of tile (i, k) is modelled as touching every strip of it;
+// GEQRT(k, l) also rewrites the R rows of panels l.. (its trailing update
+// reaches every row below the panel's first), TSQRT(k, ., l) the R rows of
+// panel l only.
 void task_access(const RegionMap &R, const Task &t, std::vector<int64_t> &rd, std::vector<int64_t> &wr)
 {
     rd.clear();
@@ -200,7 +205,7 @@ void task_access(const RegionMap &R, const Task &t, std::vector<int64_t> &rd, st
             rd.push_back(R.strip(t.k, t.k, s));
             wr.push_back(R.strip(t.k, t.k, s));
         }
-        wr.push_back(R.rpart(t.k));
+        for (int l = t.l; l < R.np; ++l) wr.push_back(R.rrows(t.k, l));
         wr.push_back(R.vpart(t.k));
         break;
     case LARFB:
@@ -209,8 +214,8 @@ void task_access(const RegionMap &R, const Task &t, std::vector<int64_t> &rd, st
         wr.push_back(R.strip(t.k, t.j, t.s));
         break;
     case TSQRT:
-        rd.push_back(R.rpart(t.k));
-        wr.push_back(R.rpart(t.k));
+        rd.push_back(R.rrows(t.k, t.l));
+        wr.push_back(R.rrows(t.k, t.l));
         for (int s = 0; s < R.ns; ++s) {
             rd.push_back(R.strip(t.i, t.k, s));
             wr.push_back(R.strip(t.i, t.k, s));
@@ -228,20 +233,22 @@ void task_access(const RegionMap &R, const Task &t, std::vector<int64_t> &rd, st
 
 }  // namespace
 
-extern "C" int tileqr_dag_selfcheck(int64_t p, int64_t q, int64_t strips, int64_t trials, uint64_t seed)
+extern "C" int tileqr_dag_selfcheck(int64_t p, int64_t q, int64_t strips, int64_t panels, int64_t trials,
+                                   uint64_t seed)
 {
-    if (p <= 0 || q <= 0 || strips <= 0) return 0;
-    const Grid g = make_grid((int)p, (int)q, (int)strips);
-    const RegionMap R{(int)p, (int)q, (int)strips};
+    if (p <= 0 || q <= 0 || strips <= 0 || panels <= 0) return 0;
+    const Grid g = make_grid((int)p, (int)q, (int)strips, (int)panels);
+    const RegionMap R{(int)p, (int)q, (int)strips, (int)panels};
     std::vector<int64_t> rd, wr;
-    // Reference: Algorithm 2's loop order.
+    // Reference: Algorithm 2's loop order (a tile kernel's inner panels in
+    // order).
     std::vector<int64_t> order;
     for (int k = 0; k < g.kmax; ++k) {
-        order.push_back(id_geqrt(g, k));
+        for (int l = 0; l < g.np; ++l) order.push_back(id_geqrt(g, k, l));
         for (int j = k + 1; j < g.q; ++j)
             for (int s = 0; s < g.ns; ++s) order.push_back(id_larfb(g, k, j, s));
         for (int i = k + 1; i < g.p; ++i) {
-            order.push_back(id_tsqrt(g, k, i));
+            for (int l = 0; l < g.np; ++l) order.push_back(id_tsqrt(g, k, i, l));
             for (int j = k + 1; j < g.q; ++j)
                 for (int s = 0; s < g.ns; ++s) order.push_back(id_ssrfb(g, k, i, j, s));
         }
@@ -313,6 +320,11 @@ namespace tq {
 
 // Split-precision updates run with ib = 32 (one K step of the narrow MFMA
 // per wave), for every supported nb.
+bool panel_tasks_ok(int64_t panel_tasks, int64_t nb, int64_t ib)
+{
+    return panel_tasks == 0 || panel_tasks == 1 || panel_tasks == nb / ib;
+}
+
 bool precision_supported(int precision, int64_t ib)
 {
     if (precision == TILEQR_FP64) return true;
@@ -336,6 +348,14 @@ int prepare_schedule(Workspace *W, SchedBufs &B, std::vector<MatDev> &mats, int 
 {
     const int ns = nb / kStripWidth;
     const int nmat = (int)mats.size();
+    // GEQRT / TSQRT tasks per tile.  One matrix with few tile steps is
+    // bound by its chain of panel tasks, so each inner panel becomes a task
+    // of its own and the panels of one step overlap; otherwise the update
+    // throughput dominates and whole tile kernels (panels chained through
+    // LDS, fewer tasks) do better.
+    int64_t kmax_all = 0;
+    for (const MatDev &M : mats) kmax_all = std::max<int64_t>(kmax_all, std::min(M.p, M.q));
+    const int np = o.panel_tasks > 0 ? (int)o.panel_tasks : (nmat == 1 && kmax_all <= 32 ? nb / ib : 1);
     // Tasks per ready queue, counted by index ranges (no id decoding):
     // GEQRT and TSQRT have one queue each; strip tasks go to the queue of
     // their level and XCD hash.
@@ -345,14 +365,14 @@ int prepare_schedule(Workspace *W, SchedBufs &B, std::vector<MatDev> &mats, int 
     const double b3 = (double)nb * nb * nb;
     for (int mi = 0; mi < nmat; ++mi) {
         MatDev &M = mats[mi];
-        const Grid g = make_grid(M.p, M.q, ns);
+        const Grid g = make_grid(M.p, M.q, ns, np);
         M.task_base = total_ids;
         total_ids += g.total;
         kmax_max = std::max<int64_t>(kmax_max, g.kmax);
         count_queue_tasks(g, mi, counts);
         for (int k = 0; k < g.kmax; ++k) {
             const int64_t rows = g.p - k - 1;
-            ntask += 1 + rows + (int64_t)(1 + rows) * (g.q - k - 1) * ns;
+            ntask += (int64_t)(1 + rows) * np + (int64_t)(1 + rows) * (g.q - k - 1) * ns;
             panel_flops += (4.0 / 3.0) * b3 + 2.0 * b3 * rows;
             all_flops += (double)(g.q - k - 1) * (2.0 * b3 + (4.0 * b3 + (double)ib * nb * nb) * rows);
         }
@@ -369,6 +389,7 @@ int prepare_schedule(Workspace *W, SchedBufs &B, std::vector<MatDev> &mats, int 
     S.mats = (MatDev *)B.mats.ptr;
     S.nmat = nmat;
     S.ns = ns;
+    S.np = np;
     S.total_ids = total_ids;
     S.total_tasks = (uint32_t)ntask;
     S.counters = (int32_t *)B.counters.ptr;
@@ -469,6 +490,7 @@ extern "C" int tileqr_factor_ex(int64_t m, int64_t n, double *A, int64_t lda, in
     tileqr_opts_default(&o);
     if (opts) o = *opts;
     if (o.precision < TILEQR_FP64 || o.precision > TILEQR_BF16X3) return -8;
+    if (!panel_tasks_ok(o.panel_tasks, nb, ib)) return -8;
     if (!precision_supported(o.precision, ib)) return TILEQR_EUNSUPPORTED;
     std::lock_guard<std::mutex> lock(g_mu);
     Workspace *W = workspace();
@@ -752,6 +774,7 @@ extern "C" int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double 
     int64_t nb = o.nb, ib = o.ib;
     if (nb == 0 || ib == 0) tileqr_choose_blocking(m, n, o.precision, &nb, &ib);
     if (!tileqr_blocking_supported(nb, ib)) return TILEQR_EUNSUPPORTED;
+    if (!panel_tasks_ok(o.panel_tasks, nb, ib)) return -10;
     if (!precision_supported(o.precision, ib)) return TILEQR_EUNSUPPORTED;
 
     std::lock_guard<std::mutex> lock(g_mu);

@@ -123,6 +123,7 @@ int run_batched(Workspace *W, int64_t batch, const int64_t *m, const int64_t *n,
         if (m[i] == 0 || n[i] == 0) continue;
         if (!tileqr_blocking_supported(nbv[i], ibv[i]) || !precision_supported(o.precision, ibv[i]))
             return TILEQR_EUNSUPPORTED;
+        if (!panel_tasks_ok(o.panel_tasks, nbv[i], ibv[i])) return -9;
         Group *g = nullptr;
         for (auto &x : groups)
             if (x.nb == nbv[i] && x.ib == ibv[i]) g = &x;

@@ -2,29 +2,38 @@
 // sees it (Section 4): task ids, in-degrees and successors, shared by the
 // persistent GPU scheduler and by the host-side self-check.
 //
-// Tasks of one p x q tile grid with kmax = min(p, q) steps and NS column
-// strips per tile (the GEMM-shaped kernels are column-separable: column c of
-// their output depends on column c of their inputs only, so LARFB and SSRFB
-// are split into NS strip tasks; GEQRT and TSQRT stay whole):
-//   GEQRT(k)            k < kmax
-//   TSQRT(k, i)         k < i < p
+// Tasks of one p x q tile grid with kmax = min(p, q) steps, NS column
+// strips per tile and NP inner panels per tile (ib-column blocks, Section
+// 3.2.3).  The GEMM-shaped kernels are column-separable (column c of their
+// output depends on column c of their inputs only), so LARFB and SSRFB are
+// split into NS strip tasks.  GEQRT and TSQRT are split into their NP inner
+// panels: panel l factors columns [l ib, (l+1) ib) of its tile and applies
+// its block reflector to the columns right of it, which is exactly the l-th
+// pass of the tile kernel's own loop.
+//   GEQRT(k, l)         k < kmax, l < NP
+//   TSQRT(k, i, l)      k < i < p, l < NP
 //   LARFB(k, j, s)      k < j < q, s < NS
 //   SSRFB(k, i, j, s)   k < i < p, k < j < q, s < NS
 //
 // Data each task touches and the task that last wrote it (Algorithm 2 order):
-//   GEQRT(k)       tile (k,k)                <- SSRFB(k-1, k, k, *)
-//   LARFB(k,j,s)   V_kk, T_kk                <- GEQRT(k)
+//   GEQRT(k,l)     tile (k,k) rows >= l ib  <- GEQRT(k, l-1), or SSRFB(k-1, k, k, *) for l = 0
+//   LARFB(k,j,s)   V_kk, T_kk                <- GEQRT(k, NP-1) (and so every panel)
 //                  tile (k,j) strip s        <- SSRFB(k-1, k, j, s)
-//   TSQRT(k,i)     R_kk (upper triangle)     <- TSQRT(k, i-1) or GEQRT(k)
-//                  tile (i,k)                <- SSRFB(k-1, i, k, *)
-//   SSRFB(k,i,j,s) V_ik, T_ik                <- TSQRT(k, i)
+//   TSQRT(k,i,l)   R_kk rows of panel l      <- TSQRT(k, i-1, l) or GEQRT(k, l)
+//                  tile (i,k) columns >= l ib <- TSQRT(k, i, l-1), or SSRFB(k-1, i, k, *) for l = 0
+//   SSRFB(k,i,j,s) V_ik, T_ik                <- TSQRT(k, i, NP-1)
 //                  tile (k,j) strip s        <- SSRFB(k, i-1, j, s) or LARFB(k, j, s)
 //                  tile (i,j) strip s        <- SSRFB(k-1, i, j, s)
-// V_kk (strict lower triangle of the diagonal tile) and R_kk (its upper
-// triangle) are separate regions: LARFB(k, .) reads the first while the
-// TSQRT(k, .) chain rewrites the second, so they do not wait for each other.
-// Every earlier reader of a region is itself a predecessor of its next
-// writer, so these read-after-write edges also cover write-after-read.
+// R rows of panel l are final for GEQRT(k, .) once its panel l is done: the
+// later panels touch only rows below them.  The TSQRT(k, ., l) tasks rewrite
+// only those rows of R_kk, so the panel chains of one step form a wavefront
+// over (i, l): TSQRT(k, i, l) may run beside TSQRT(k, i+1, l-1) and
+// GEQRT(k, l+1).  V_kk (strict lower triangle of the diagonal tile) and R_kk
+// (its upper triangle) are separate regions: LARFB(k, .) reads the first
+// while the TSQRT(k, .) chain rewrites the second, so they do not wait for
+// each other.  Every earlier reader of a region is itself a predecessor of
+// its next writer, so these read-after-write edges also cover
+// write-after-read.
 //
 // The paper gives four priority levels, GEQRT > TSQRT > LARFB > SSRFB
 // (Section 4): the nodes with more outgoing edges come first.
@@ -43,23 +52,25 @@ namespace tq {
 enum TaskType { GEQRT = 0, TSQRT = 1, LARFB = 2, SSRFB = 3 };
 
 struct Grid {
-    int32_t p, q, kmax, ns;   // tile rows, tile columns, steps, strips per tile
+    int32_t p, q, kmax, ns, np;   // tile rows, tile columns, steps, strips and panels per tile
     int64_t baseT, baseL, baseS, total;  // id ranges of the four types
 };
 
+// One task; l is the inner panel of GEQRT and TSQRT (0 for the strip tasks).
 struct Task {
-    int32_t type, k, i, j, s;
+    int32_t type, k, i, j, s, l;
 };
 
-TQ_HD Grid make_grid(int32_t p, int32_t q, int32_t ns)
+TQ_HD Grid make_grid(int32_t p, int32_t q, int32_t ns, int32_t np)
 {
     Grid g;
     g.p = p;
     g.q = q;
     g.kmax = p < q ? p : q;
     g.ns = ns;
-    g.baseT = g.kmax;
-    g.baseL = g.baseT + (int64_t)g.kmax * p;
+    g.np = np;
+    g.baseT = (int64_t)g.kmax * np;
+    g.baseL = g.baseT + (int64_t)g.kmax * p * np;
     g.baseS = g.baseL + (int64_t)g.kmax * q * ns;
     g.total = g.baseS + (int64_t)g.kmax * p * q * ns;
     return g;
@@ -67,8 +78,8 @@ TQ_HD Grid make_grid(int32_t p, int32_t q, int32_t ns)
 
 // Dense id space with holes (ids of impossible index combinations, e.g.
 // i <= k, are never used); decoding is plain division.
-TQ_HD int64_t id_geqrt(const Grid &g, int k) { return k; }
-TQ_HD int64_t id_tsqrt(const Grid &g, int k, int i) { return g.baseT + (int64_t)k * g.p + i; }
+TQ_HD int64_t id_geqrt(const Grid &g, int k, int l) { return (int64_t)k * g.np + l; }
+TQ_HD int64_t id_tsqrt(const Grid &g, int k, int i, int l) { return g.baseT + ((int64_t)k * g.p + i) * g.np + l; }
 TQ_HD int64_t id_larfb(const Grid &g, int k, int j, int s)
 {
     return g.baseL + ((int64_t)k * g.q + j) * g.ns + s;
@@ -81,14 +92,17 @@ TQ_HD int64_t id_ssrfb(const Grid &g, int k, int i, int j, int s)
 TQ_HD Task decode(const Grid &g, int64_t id)
 {
     Task t;
-    t.i = t.j = t.s = 0;
+    t.i = t.j = t.s = t.l = 0;
     if (id < g.baseT) {
         t.type = GEQRT;
-        t.k = (int32_t)id;
+        t.k = (int32_t)(id / g.np);
+        t.l = (int32_t)(id % g.np);
         t.i = t.j = t.k;
     } else if (id < g.baseL) {
         int64_t r = id - g.baseT;
         t.type = TSQRT;
+        t.l = (int32_t)(r % g.np);
+        r /= g.np;
         t.k = (int32_t)(r / g.p);
         t.i = (int32_t)(r % g.p);
         t.j = t.k;
@@ -130,8 +144,8 @@ TQ_HD int32_t indegree(const Grid &g, const Task &t)
 {
     const int prev = t.k > 0 ? 1 : 0;
     switch (t.type) {
-    case GEQRT: return prev * g.ns;
-    case TSQRT: return 1 + prev * g.ns;
+    case GEQRT: return t.l > 0 ? 1 : prev * g.ns;
+    case TSQRT: return 1 + (t.l > 0 ? 1 : prev * g.ns);
     case LARFB: return 1 + prev;
     default: return 2 + prev;
     }
@@ -143,21 +157,24 @@ TQ_HD int64_t next_step_consumer(const Grid &g, int k, int i, int j, int s)
 {
     const int k1 = k + 1;
     if (k1 >= g.kmax) return -1;
-    if (i == k1 && j == k1) return id_geqrt(g, k1);
+    if (i == k1 && j == k1) return id_geqrt(g, k1, 0);
     if (i == k1) return id_larfb(g, k1, j, s);
-    if (j == k1) return id_tsqrt(g, k1, i);
+    if (j == k1) return id_tsqrt(g, k1, i, 0);
     return id_ssrfb(g, k1, i, j, s);
 }
 
-// Successors of a task.  GEQRT and TSQRT fan out to a whole tile row of strip
-// tasks; `nsucc` tells how many, `succ(n)` gives the n-th.  Pure functions
-// of the task, so the threads of a workgroup can release successors in
-// parallel.
+// Successors of a task.  The last panel of a GEQRT or TSQRT fans out to a
+// whole tile row of strip tasks; `nsucc` tells how many, `succ(n)` gives the
+// n-th.  Pure functions of the task, so the threads of a workgroup can
+// release successors in parallel.  A panel task lists the next panel of its
+// own tile first, then the same panel of the next tile, then the strips.
 TQ_HD int32_t nsucc(const Grid &g, const Task &t)
 {
+    const int strips = (g.q - t.k - 1) * g.ns;
+    const int more = t.l + 1 < g.np ? 1 : 0;
     switch (t.type) {
-    case GEQRT: return (g.q - t.k - 1) * g.ns + (t.k + 1 < g.p ? 1 : 0);
-    case TSQRT: return (g.q - t.k - 1) * g.ns + (t.i + 1 < g.p ? 1 : 0);
+    case GEQRT: return more + (t.k + 1 < g.p ? 1 : 0) + (more ? 0 : strips);
+    case TSQRT: return more + (t.i + 1 < g.p ? 1 : 0) + (more ? 0 : strips);
     case LARFB: return t.k + 1 < g.p ? 1 : 0;
     default: {
         int n = t.i + 1 < g.p ? 1 : 0;
@@ -168,14 +185,28 @@ TQ_HD int32_t nsucc(const Grid &g, const Task &t)
 
 TQ_HD int64_t succ(const Grid &g, const Task &t, int32_t n)
 {
-    const int row = (g.q - t.k - 1) * g.ns;   // strip tasks of the tile row
+    const bool more = t.l + 1 < g.np;
     switch (t.type) {
     case GEQRT:
-        if (n < row) return id_larfb(g, t.k, t.k + 1 + n / g.ns, n % g.ns);
-        return id_tsqrt(g, t.k, t.k + 1);
+        if (more) {
+            if (n == 0) return id_geqrt(g, t.k, t.l + 1);
+            --n;
+        }
+        if (t.k + 1 < g.p) {
+            if (n == 0) return id_tsqrt(g, t.k, t.k + 1, t.l);
+            --n;
+        }
+        return id_larfb(g, t.k, t.k + 1 + n / g.ns, n % g.ns);
     case TSQRT:
-        if (n < row) return id_ssrfb(g, t.k, t.i, t.k + 1 + n / g.ns, n % g.ns);
-        return id_tsqrt(g, t.k, t.i + 1);
+        if (more) {
+            if (n == 0) return id_tsqrt(g, t.k, t.i, t.l + 1);
+            --n;
+        }
+        if (t.i + 1 < g.p) {
+            if (n == 0) return id_tsqrt(g, t.k, t.i + 1, t.l);
+            --n;
+        }
+        return id_ssrfb(g, t.k, t.i, t.k + 1 + n / g.ns, n % g.ns);
     case LARFB:
         return id_ssrfb(g, t.k, t.k + 1, t.j, t.s);
     default:
@@ -225,9 +256,9 @@ TQ_HD int queue_of(const Task &t, int ns, int mat)
 inline void count_queue_tasks(const Grid &g, int mat, int64_t *counts)
 {
     for (int k = 0; k < g.kmax; ++k) {
-        const int64_t rows = g.p - k - 1;   // TSQRT(k, .), and SSRFB(k, ., j, s) per (j, s)
-        counts[queue_index(0, 0)] += 1;
-        counts[queue_index(1, 0)] += rows;
+        const int64_t rows = g.p - k - 1;   // TSQRT(k, ., l) per l, and SSRFB(k, ., j, s) per (j, s)
+        counts[queue_index(0, 0)] += g.np;
+        counts[queue_index(1, 0)] += rows * g.np;
         for (int j = k + 1; j < g.q; ++j)
             for (int s = 0; s < g.ns; ++s) {
                 Task t;
@@ -245,13 +276,14 @@ inline void count_queue_tasks(const Grid &g, int mat, int64_t *counts)
 }
 
 // Leading-order flops of one task (Section 3.2.3: SSRFB costs 4b^3 + sb^2;
-// GEQRT 4b^3/3, TSQRT and LARFB 2b^3), for a strip task its share.
-TQ_HD double task_flops(const Task &t, int nb, int ib, int ns)
+// GEQRT 4b^3/3, TSQRT and LARFB 2b^3), for a strip or panel task an equal
+// share of its tile kernel's.
+TQ_HD double task_flops(const Task &t, int nb, int ib, int ns, int np)
 {
     const double b = nb, s = ib;
     switch (t.type) {
-    case GEQRT: return 4.0 * b * b * b / 3.0;
-    case TSQRT: return 2.0 * b * b * b;
+    case GEQRT: return 4.0 * b * b * b / 3.0 / np;
+    case TSQRT: return 2.0 * b * b * b / np;
     case LARFB: return 2.0 * b * b * b / ns;
     default: return (4.0 * b * b * b + s * b * b) / ns;
     }

@@ -82,6 +82,8 @@ bool tuned_single(int64_t m, int64_t n, int precision, tileqr_tuning *out);
 
 // Split precisions need ib = 32.
 bool precision_supported(int precision, int64_t ib);
+// opts.panel_tasks is 0 (automatic), 1 or nb / ib.
+bool panel_tasks_ok(int64_t panel_tasks, int64_t nb, int64_t ib);
 // Reads the device status word (synchronises st) and maps it to a status.
 int check_status(Workspace *W, int *dstatus, hipStream_t st);
 

@@ -34,6 +34,7 @@ struct SchedDev {
     MatDev *mats;
     int32_t nmat;
     int32_t ns;               // strips per tile
+    int32_t np;               // GEQRT / TSQRT tasks per tile: 1 or nb / ib (one per inner panel)
     int32_t npanel;           // workgroups 0..npanel-1 take the panel role
     int64_t total_ids;        // size of the id space (with holes)
     uint32_t total_tasks;     // number of real tasks

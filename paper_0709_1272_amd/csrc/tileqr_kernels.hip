@@ -6,7 +6,7 @@
 
 namespace tq {
 
-// Counters <- in-degrees, queues cleared, GEQRT(0) of every matrix queued.
+// Counters <- in-degrees, queues cleared, GEQRT(0, 0) of every matrix queued.
 __global__ void k_sched_init(SchedDev S)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -14,7 +14,7 @@ __global__ void k_sched_init(SchedDev S)
     for (int64_t gid = tid0; gid < S.total_ids; gid += stride) {
         const int mi = find_mat(S, gid);
         const MatDev &M = S.mats[mi];
-        const Grid g = make_grid(M.p, M.q, S.ns);
+        const Grid g = make_grid(M.p, M.q, S.ns, S.np);
         const Task t = decode(g, gid - M.task_base);
         S.counters[gid] = valid(g, t) ? indegree(g, t) : -1;
     }
@@ -31,7 +31,8 @@ __global__ void k_sched_init(SchedDev S)
 
 __global__ void k_sched_seed(SchedDev S)
 {
-    // Runs after k_sched_init (stream order): queue every GEQRT(0).
+    // Runs after k_sched_init (stream order): queue every GEQRT(0, 0) (id 0
+    // of its matrix).
     // Every matrix in the list is non-empty (the host drops empty ones).
     for (int mi = threadIdx.x; mi < S.nmat; mi += blockDim.x)
         S.qslot[S.qoff[queue_index(0, 0)] + mi] = (int32_t)(S.mats[mi].task_base + 1);

@@ -948,86 +948,108 @@ __device__ __forceinline__ void panel_trailing(Smem<NB, IB> &sm, gdouble *tile, 
     }
 }
 
-// DGEQRT(A_kk) -> (V_kk, R_kk, T_kk).
+// Inner panel l of DGEQRT(A_kk) -> (V_kk, R_kk, T_kk): factor columns
+// [l ib, (l+1) ib) (rows from l ib down), write V, R and T_l, and apply the
+// panel's reflector to the columns right of it.  `from_lds`: the panel is
+// already in sm.P (rows from l ib), chained there by panel l-1; `chain`:
+// leave the next panel in sm.P (the strip next to this panel is then not
+// written back below the next panel's first row).  With both false the
+// panel is a self-contained task that reads and writes only memory.
+template <int NB, int IB, int PREC>
+__device__ __forceinline__ void geqrt_panel(Smem<NB, IB> &sm, const MatDev &M, int k, int l, bool from_lds, bool chain)
+{
+    using C = Cfg<NB, IB>;
+    gdouble *tkk = tile_ptr(M, NB, k, k);
+    gdouble *Tk = tblock_ptr(M, NB, IB, k, k);
+    const int c0 = l * IB;
+    if (!from_lds) {
+        Stage<NB, IB> S;
+        stage_load<NB, IB, false>(S, tkk, c0, c0, nullptr);
+        stage_store<NB, IB>(sm, S, c0, false, c0);
+    }
+    __syncthreads();
+    panel_factor<NB, IB, false>(sm, c0);
+    // Write R and V back; keep V with explicit unit diagonal in LDS.
+    constexpr int H = IB / 2;
+#pragma unroll
+    for (int u = 0; u < C::VPT; ++u) {
+        const int e = threadIdx.x + u * C::NT, r = e / H, cc = 2 * (e % H);
+        if (r < c0) continue;
+        v2d v = *reinterpret_cast<v2d *>(&sm.P[r * C::LDP + cc]);
+        *reinterpret_cast<gv2d *>(tkk + (size_t)r * NB + c0 + cc) = v;
+        const int d = r - c0;
+        if (d <= cc + 1) {
+            v.x = d < cc ? 0.0 : (d == cc ? 1.0 : v.x);
+            v.y = d < cc + 1 ? 0.0 : 1.0;
+            *reinterpret_cast<v2d *>(&sm.P[r * C::LDP + cc]) = v;
+        }
+    }
+    __syncthreads();
+    build_t<NB, IB>(sm, c0, Tk + l * IB * IB);
+    __syncthreads();
+    panel_trailing<NB, IB, false, PREC>(sm, tkk, nullptr, c0, chain);
+    __syncthreads();
+}
+
+// DGEQRT(A_kk) -> (V_kk, R_kk, T_kk): the inner panels in order, each one
+// chained to the next through LDS when ib equals the strip width.
 template <int NB, int IB, int PREC>
 __device__ __forceinline__ void task_geqrt(Smem<NB, IB> &sm, const MatDev &M, int k)
 {
-    using C = Cfg<NB, IB>;
     constexpr bool CHAIN = IB == WS;
-    gdouble *tkk = tile_ptr(M, NB, k, k);
-    gdouble *Tk = tblock_ptr(M, NB, IB, k, k);
 #pragma unroll 1
-    for (int l = 0; l < C::NPAN; ++l) {
-        const int c0 = l * IB;
-        if (l == 0 || !CHAIN) {
-            Stage<NB, IB> S;
-            stage_load<NB, IB, false>(S, tkk, c0, c0, nullptr);
-            stage_store<NB, IB>(sm, S, c0, false, c0);
-        }
-        __syncthreads();
-        panel_factor<NB, IB, false>(sm, c0);
-        // Write R and V back; keep V with explicit unit diagonal in LDS.
-        constexpr int H = IB / 2;
-#pragma unroll
-        for (int u = 0; u < C::VPT; ++u) {
-            const int e = threadIdx.x + u * C::NT, r = e / H, cc = 2 * (e % H);
-            if (r < c0) continue;
-            v2d v = *reinterpret_cast<v2d *>(&sm.P[r * C::LDP + cc]);
-            *reinterpret_cast<gv2d *>(tkk + (size_t)r * NB + c0 + cc) = v;
-            const int d = r - c0;
-            if (d <= cc + 1) {
-                v.x = d < cc ? 0.0 : (d == cc ? 1.0 : v.x);
-                v.y = d < cc + 1 ? 0.0 : 1.0;
-                *reinterpret_cast<v2d *>(&sm.P[r * C::LDP + cc]) = v;
-            }
-        }
-        __syncthreads();
-        build_t<NB, IB>(sm, c0, Tk + l * IB * IB);
-        __syncthreads();
-        panel_trailing<NB, IB, false, PREC>(sm, tkk, nullptr, c0, CHAIN);
-        __syncthreads();
-    }
+    for (int l = 0; l < Cfg<NB, IB>::NPAN; ++l) geqrt_panel<NB, IB, PREC>(sm, M, k, l, CHAIN && l > 0, CHAIN);
 }
 
-// DTSQRT(R_kk, A_ik) -> (R_kk, V_ik, T_ik).
+// Inner panel l of DTSQRT(R_kk, A_ik) -> (R_kk, V_ik, T_ik): factor
+// [R_kk rows of panel l; columns [l ib, (l+1) ib) of A_ik], write them and
+// T_l, and apply the reflector to the columns right of the panel (rows of
+// the panel in R_kk, all rows of A_ik).  `from_lds` / `chain` as for
+// geqrt_panel.
 template <int NB, int IB, int PREC>
-__device__ __forceinline__ void task_tsqrt(Smem<NB, IB> &sm, const MatDev &M, int k, int i)
+__device__ __forceinline__ void tsqrt_panel(Smem<NB, IB> &sm, const MatDev &M, int k, int i, int l, bool from_lds,
+                                            bool chain)
 {
     using C = Cfg<NB, IB>;
-    constexpr bool CHAIN = IB == WS;
     gdouble *tkk = tile_ptr(M, NB, k, k);
     gdouble *tik = tile_ptr(M, NB, i, k);
     gdouble *Ti = tblock_ptr(M, NB, IB, k, i);
     constexpr int H = IB / 2;
-#pragma unroll 1
-    for (int l = 0; l < C::NPAN; ++l) {
-        const int c0 = l * IB;
-        if (l == 0 || !CHAIN) {
-            Stage<NB, IB> S;
-            stage_load<NB, IB, false>(S, tik, c0, 0, nullptr);
-            stage_store<NB, IB>(sm, S, 0, false, c0);
-        }
-        for (int e = threadIdx.x; e < IB * IB; e += C::NT) {
-            const int r = e / IB, c = e % IB;
-            sm.P[(NB + r) * C::LDP + c] = r <= c ? tkk[(size_t)(c0 + r) * NB + c0 + c] : 0.0;
-        }
-        __syncthreads();
-        panel_factor<NB, IB, true>(sm, c0);
-        for (int e = threadIdx.x; e < IB * IB; e += C::NT) {
-            const int r = e / IB, c = e % IB;
-            if (r <= c) tkk[(size_t)(c0 + r) * NB + c0 + c] = sm.P[(NB + r) * C::LDP + c];
-        }
-#pragma unroll
-        for (int u = 0; u < C::VPT; ++u) {
-            const int e = threadIdx.x + u * C::NT, r = e / H, cc = 2 * (e % H);
-            *reinterpret_cast<gv2d *>(tik + (size_t)r * NB + c0 + cc) =
-                *reinterpret_cast<v2d *>(&sm.P[r * C::LDP + cc]);
-        }
-        build_t<NB, IB>(sm, 0, Ti + l * IB * IB);
-        __syncthreads();
-        panel_trailing<NB, IB, true, PREC>(sm, tik, tkk, c0, CHAIN);
-        __syncthreads();
+    const int c0 = l * IB;
+    if (!from_lds) {
+        Stage<NB, IB> S;
+        stage_load<NB, IB, false>(S, tik, c0, 0, nullptr);
+        stage_store<NB, IB>(sm, S, 0, false, c0);
     }
+    for (int e = threadIdx.x; e < IB * IB; e += C::NT) {
+        const int r = e / IB, c = e % IB;
+        sm.P[(NB + r) * C::LDP + c] = r <= c ? tkk[(size_t)(c0 + r) * NB + c0 + c] : 0.0;
+    }
+    __syncthreads();
+    panel_factor<NB, IB, true>(sm, c0);
+    for (int e = threadIdx.x; e < IB * IB; e += C::NT) {
+        const int r = e / IB, c = e % IB;
+        if (r <= c) tkk[(size_t)(c0 + r) * NB + c0 + c] = sm.P[(NB + r) * C::LDP + c];
+    }
+#pragma unroll
+    for (int u = 0; u < C::VPT; ++u) {
+        const int e = threadIdx.x + u * C::NT, r = e / H, cc = 2 * (e % H);
+        *reinterpret_cast<gv2d *>(tik + (size_t)r * NB + c0 + cc) =
+            *reinterpret_cast<v2d *>(&sm.P[r * C::LDP + cc]);
+    }
+    build_t<NB, IB>(sm, 0, Ti + l * IB * IB);
+    __syncthreads();
+    panel_trailing<NB, IB, true, PREC>(sm, tik, tkk, c0, chain);
+    __syncthreads();
+}
+
+// DTSQRT(R_kk, A_ik) -> (R_kk, V_ik, T_ik): the inner panels in order.
+template <int NB, int IB, int PREC>
+__device__ __forceinline__ void task_tsqrt(Smem<NB, IB> &sm, const MatDev &M, int k, int i)
+{
+    constexpr bool CHAIN = IB == WS;
+#pragma unroll 1
+    for (int l = 0; l < Cfg<NB, IB>::NPAN; ++l) tsqrt_panel<NB, IB, PREC>(sm, M, k, i, l, CHAIN && l > 0, CHAIN);
 }
 
 // One strip (32 columns at col0, row stride ldx) of X <- Q_kk^T X (TRANS)
@@ -1124,12 +1146,19 @@ __device__ __forceinline__ void task_ssrfb(Smem<NB, IB> &sm, const MatDev &M, in
 // which the dispatcher makes resident first.
 enum { ROLE_PANEL = 0, ROLE_UPDATE = 1 };
 
-template <int NB, int IB, int ROLE, int PREC>
+// With SPLIT a panel task is one inner panel of its tile kernel (the grid
+// has nb / ib panel tasks per tile), else the whole tile kernel.
+template <int NB, int IB, int ROLE, int PREC, bool SPLIT>
 __device__ __forceinline__ void run_task(Smem<NB, IB> &sm, const MatDev &M, const Task &t)
 {
     if constexpr (ROLE == ROLE_PANEL) {
-        if (t.type == GEQRT) task_geqrt<NB, IB, PREC>(sm, M, t.k);
-        else task_tsqrt<NB, IB, PREC>(sm, M, t.k, t.i);
+        if constexpr (SPLIT) {
+            if (t.type == GEQRT) geqrt_panel<NB, IB, PREC>(sm, M, t.k, t.l, false, false);
+            else tsqrt_panel<NB, IB, PREC>(sm, M, t.k, t.i, t.l, false, false);
+        } else {
+            if (t.type == GEQRT) task_geqrt<NB, IB, PREC>(sm, M, t.k);
+            else task_tsqrt<NB, IB, PREC>(sm, M, t.k, t.i);
+        }
     } else {
         if (t.type == LARFB) task_larfb<NB, IB, PREC>(sm, M, t.k, t.j, t.s);
         else task_ssrfb<NB, IB, PREC>(sm, M, t.k, t.i, t.j, t.s);
@@ -1244,7 +1273,7 @@ __device__ __forceinline__ int64_t pop_any(const SchedDev &S, int xcd, bool stea
     }
 }
 
-template <int NB, int IB, int ROLE, int PREC>
+template <int NB, int IB, int ROLE, int PREC, bool SPLIT>
 __device__ __forceinline__ void worker_loop(Smem<NB, IB> &sm, const SchedDev &S)
 {
     __shared__ int64_t s_gid, s_next;
@@ -1329,10 +1358,13 @@ __device__ __forceinline__ void worker_loop(Smem<NB, IB> &sm, const SchedDev &S)
         __syncthreads();
         const int mi = find_mat(S, gid);
         const MatDev &M = S.mats[mi];
-        const Grid g = make_grid(M.p, M.q, S.ns);
+        // Strips and panels per tile are compile-time constants here (the
+        // host sets S.ns = nb / 32 and S.np to match the kernel), which
+        // keeps the id arithmetic to shifts.
+        const Grid g = make_grid(M.p, M.q, Cfg<NB, IB>::NS, SPLIT ? Cfg<NB, IB>::NPAN : 1);
         const Task t = decode(g, gid - M.task_base);
         const uint64_t t0 = wall_clock64();
-        run_task<NB, IB, ROLE, PREC>(sm, M, t);
+        run_task<NB, IB, ROLE, PREC, SPLIT>(sm, M, t);
         // Release: every wave waits for its own stores, then wave 0 writes
         // the L2 back and releases the successors (in program order after
         // its fence).  Of the successors this task makes ready, the first
@@ -1381,7 +1413,8 @@ __device__ __forceinline__ void worker_loop(Smem<NB, IB> &sm, const SchedDev &S)
                                                           __HIP_MEMORY_SCOPE_AGENT);
                 if (e < S.trace_cap) {
                     int64_t *ev = S.trace + (size_t)e * TRACE_WORDS;
-                    ev[0] = t.type; ev[1] = t.k; ev[2] = t.i; ev[3] = t.j; ev[4] = t.s;
+                    ev[0] = t.type; ev[1] = t.k; ev[2] = t.i; ev[3] = t.j;
+                    ev[4] = t.type <= TSQRT ? t.l : t.s;
                     ev[5] = ((int64_t)mi << 20) | (ROLE << 16) | blockIdx.x;
                     ev[6] = (int64_t)s_tpop;
                     ev[7] = (int64_t)t0;
@@ -1395,12 +1428,15 @@ __device__ __forceinline__ void worker_loop(Smem<NB, IB> &sm, const SchedDev &S)
     }
 }
 
-template <int NB, int IB, int PREC>
+// The persistent workers; SPLIT: the grid has one panel task per inner
+// panel (S.np == nb / ib), else one per tile kernel (S.np == 1).  Separate
+// kernels, so that each keeps its panel code with compile-time loop bounds.
+template <int NB, int IB, int PREC, bool SPLIT>
 __global__ __launch_bounds__(2 * NB) void k_worker(SchedDev S)
 {
     __shared__ Smem<NB, IB> sm;
-    if ((int)blockIdx.x < S.npanel) worker_loop<NB, IB, ROLE_PANEL, PREC>(sm, S);
-    else worker_loop<NB, IB, ROLE_UPDATE, PREC>(sm, S);
+    if ((int)blockIdx.x < S.npanel) worker_loop<NB, IB, ROLE_PANEL, PREC, SPLIT>(sm, S);
+    else worker_loop<NB, IB, ROLE_UPDATE, PREC, SPLIT>(sm, S);
 }
 
 // Host side of the kernels above for one arithmetic (PREC): the serial
@@ -1429,16 +1465,26 @@ static hipError_t serial_impl(const MatDev &M, const int *status, hipStream_t st
 template <int NB, int IB, int PREC>
 static hipError_t worker_impl(const SchedDev &S, int workers, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_worker<NB, IB, PREC>), dim3(workers), dim3(Cfg<NB, IB>::NT), 0, st, S);
+    if (S.np == Cfg<NB, IB>::NPAN && S.np > 1)
+        hipLaunchKernelGGL((k_worker<NB, IB, PREC, true>), dim3(workers), dim3(Cfg<NB, IB>::NT), 0, st, S);
+    else if (S.np == 1)
+        hipLaunchKernelGGL((k_worker<NB, IB, PREC, false>), dim3(workers), dim3(Cfg<NB, IB>::NT), 0, st, S);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
+// Workgroups per CU of both worker kernels (the smaller, should they differ).
 template <int NB, int IB, int PREC>
 static int worker_occupancy_impl()
 {
-    int a = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_worker<NB, IB, PREC>, Cfg<NB, IB>::NT, 0) != hipSuccess)
+    int a = 0, b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, k_worker<NB, IB, PREC, false>, Cfg<NB, IB>::NT, 0) !=
+            hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k_worker<NB, IB, PREC, true>, Cfg<NB, IB>::NT, 0) !=
+            hipSuccess)
         return 1;
+    a = a < b ? a : b;
     return a > 0 ? a : 1;
 }
 

@@ -31,7 +31,7 @@ class Opts(ctypes.Structure):
                 ("max_iter", ctypes.c_int), ("tol", ctypes.c_double), ("stream", ctypes.c_void_p),
                 ("flags", ctypes.c_uint), ("seed", ctypes.c_uint64), ("spin_limit", ctypes.c_int64),
                 ("workers", ctypes.c_int64), ("drop_edge", ctypes.c_int64),
-                ("panel_workers", ctypes.c_int64)]
+                ("panel_workers", ctypes.c_int64), ("panel_tasks", ctypes.c_int64)]
 
 
 class Tuning(ctypes.Structure):
@@ -64,8 +64,8 @@ _SIGS = {
     "tileqr_tune": (_int, [_i64, _I64P, _I64P, _int, _int, ctypes.POINTER(Tuning)]),
     "tileqr_flops_lapack": (_dbl, [_i64, _i64]),
     "tileqr_flops_tiled": (_dbl, [_i64, _i64, _i64, _i64]),
-    "tileqr_dag_counts": (_i64, [_i64, _i64, _i64, _I64P]),
-    "tileqr_dag_selfcheck": (_int, [_i64, _i64, _i64, _i64, ctypes.c_uint64]),
+    "tileqr_dag_counts": (_i64, [_i64, _i64, _i64, _i64, _I64P]),
+    "tileqr_dag_selfcheck": (_int, [_i64, _i64, _i64, _i64, _i64, ctypes.c_uint64]),
     "tileqr_trace": (_i64, [_I64P, _i64]),
     "tileqr_trace_clock_hz": (_dbl, []),
     "tileqr_last_timing": (_int, [ctypes.POINTER(ctypes.c_double)]),
@@ -165,14 +165,14 @@ def flops_tiled(m, n, nb, ib):
     return _L.tileqr_flops_tiled(m, n, nb, ib)
 
 
-def dag_counts(p, q, strips=1):
+def dag_counts(p, q, strips=1, panels=1):
     c = (ctypes.c_int64 * 4)()
-    total = _L.tileqr_dag_counts(p, q, strips, c)
+    total = _L.tileqr_dag_counts(p, q, strips, panels, c)
     return total, list(c)
 
 
-def dag_selfcheck(p, q, strips, trials, seed):
-    return _L.tileqr_dag_selfcheck(p, q, strips, trials, seed)
+def dag_selfcheck(p, q, strips, trials, seed, panels=1):
+    return _L.tileqr_dag_selfcheck(p, q, strips, panels, trials, seed)
 
 
 TRACE_WORDS = 10

@@ -50,18 +50,20 @@ def test_dag_counts_closed_form(p, q):
     larfb = sum(q - k - 1 for k in range(kmax))
     ssrfb = sum((p - k - 1) * (q - k - 1) for k in range(kmax))
     for strips in (1, 8):
-        total, c = tq.dag_counts(p, q, strips)
-        assert c == [geqrt, tsqrt, larfb * strips, ssrfb * strips]
+        for panels in (1, 4):
+            total, c = tq.dag_counts(p, q, strips, panels)
+            assert c == [geqrt * panels, tsqrt * panels, larfb * strips, ssrfb * strips]
 
 
 @pytest.mark.parametrize("p,q,strips,trials", [(1, 1, 1, 3), (3, 3, 1, 50), (3, 3, 4, 50), (5, 2, 2, 50),
                                                (2, 6, 2, 50), (6, 6, 8, 20), (12, 4, 2, 10), (1, 5, 2, 10),
                                                (5, 1, 2, 10)])
-def test_dag_rules_random_orders(p, q, strips, trials):
+@pytest.mark.parametrize("panels", [1, 2, 8])
+def test_dag_rules_random_orders(p, q, strips, trials, panels):
     # Random topological orders of the scheduler's DAG must show every task
     # the tile versions that Algorithm 2's loop order shows it.
     tq = _tq()
-    assert tq.dag_selfcheck(p, q, strips, trials, 1234 + p * 100 + q) == 0
+    assert tq.dag_selfcheck(p, q, strips, trials, 1234 + p * 100 + q, panels) == 0
 
 
 def test_flop_model():

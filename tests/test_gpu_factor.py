@@ -120,15 +120,26 @@ def test_ragged_shapes(tq, m, n, nb, ib):
 @pytest.mark.parametrize("m,n,nb,ib", [(512, 512, 64, 16), (700, 300, 64, 32), (300, 700, 128, 16),
                                        (1024, 1024, 256, 32), (2000, 640, 128, 32)])
 def test_dag_bitwise_equals_serial(tq, m, n, nb, ib):
+    # Whole tile kernels (panel_tasks = 1) and one task per inner panel
+    # (nb / ib) run the same arithmetic per strip as Algorithm 2's serial
+    # order, so every schedule gives the same bits.
     A = synth.uniform(3, m, n)
     Fs, Ts = run_factor(tq, A, nb, ib, flags=tq.FLAG_SERIAL)
     Fd, Td = run_factor(tq, A, nb, ib)
     assert np.array_equal(Fs, Fd)
     assert np.array_equal(Ts, Td)
-    for seed in (1, 2):
-        Fr, Tr = run_factor(tq, A, nb, ib, flags=tq.FLAG_SHUFFLE, seed=seed)
-        assert np.array_equal(Fs, Fr)
-        assert np.array_equal(Ts, Tr)
+    for pt in (1, nb // ib):
+        for seed in (1, 2):
+            Fr, Tr = run_factor(tq, A, nb, ib, flags=tq.FLAG_SHUFFLE, seed=seed, panel_tasks=pt)
+            assert np.array_equal(Fs, Fr), (pt, seed)
+            assert np.array_equal(Ts, Tr), (pt, seed)
+
+
+def test_panel_tasks_option_checked(tq):
+    A = tq.to_device(synth.uniform(4, 256, 256))
+    T = torch.empty(tq.t_size(256, 256, 64, 16), dtype=torch.float64, device="cuda")
+    for bad in (-1, 2, 3, 5):   # only 0, 1 and nb / ib = 4 are accepted
+        assert tq.factor(256, 256, A.data_ptr(), 256, 64, 16, T.data_ptr(), tq.opts(panel_tasks=bad)) == -8
 
 
 def test_single_tile_matches_signs(tq):
