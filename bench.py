@@ -96,14 +96,14 @@ def mixed_ls(tq, torch, dev, st):
     Bt = tq.to_device(b, dev)
     Xt = torch.zeros((1, n), dtype=torch.float64, device=dev)
     flops = tq.flops_lapack(m, n)
-    out = {"workload": f"least squares {m}x{n}, kappa {kappa:.0e}, 1 rhs, SVD construction seed 0",
+    out = {"workload": f"least squares {m}x{n}, kappa {kappa:.0e}, 1 rhs, SVD construction seed 0, nb 256, ib 32",
            "flops_counted": flops, "tol": 1e-14}
     xs = {}
     for name, prec in (("fp64", tq.FP64), ("fp16x2", tq.FP16X2), ("bf16x3", tq.BF16X3), ("bf16x2", tq.BF16X2)):
         best = None
         for _ in range(3):
             info = tq.Info()
-            o = tq.opts(precision=prec, nb=128, ib=32, stream=st.cuda_stream)
+            o = tq.opts(precision=prec, nb=256, ib=32, stream=st.cuda_stream)
             rc = tq.solve_ls(m, n, 1, At.data_ptr(), m, Bt.data_ptr(), m, Xt.data_ptr(), n, o, info)
             if best is None or info.ms_total < best[1].ms_total:
                 best = (rc, info)

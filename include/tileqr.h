@@ -102,10 +102,11 @@ typedef struct {
     int64_t drop_edge;    /* test hook for the watchdog: the task with this id skips
                              its first successor release; -1 (default) = none        */
     int64_t panel_workers;/* panel-role workgroups of the DAG scheduler (GEQRT, TSQRT);
-                             0 = automatic (one matrix: one per concurrent panel
-                             chain, at most 16 with up to 32 tile steps, else
-                             at most 8; a batch: in proportion to the panel
-                             flops)                                                  */
+                             0 = automatic: in proportion to the panel flops for a
+                             batch, and for one matrix split into panel tasks (at
+                             least 16, at most nb/ib per tile step); one matrix
+                             with whole tile kernels: 16 with up to 32 tile
+                             steps, else 8                                         */
     int64_t panel_tasks;  /* DAG tasks per GEQRT and TSQRT: 1 (the whole tile
                              kernel) or nb / ib (one per inner panel, which lets
                              the panel chains of a step overlap); 0 = automatic

@@ -124,10 +124,14 @@ extern "C" int tileqr_choose_blocking(int64_t m, int64_t n, int precision, int64
             return 0;
         }
     }
+    // Measured with one task per inner panel (the automatic split for up to
+    // 32 tile steps): tall matrices and large ones run best with 256 x 256
+    // tiles (more work per panel task on the chains that bound them),
+    // near-square ones up to 4096 with 128, tiny ones with 64.
     const int64_t k = std::min(m, n);
     int64_t b = 256, s = 32;
-    if (k <= 1024) { b = 64; s = 16; }
-    else if (k <= 4096 || m >= 16 * n) { b = 128; s = 32; }
+    if (k <= 256) { b = 64; s = 16; }
+    else if (k <= 4096 && std::max(m, n) < 4 * k) { b = 128; s = 32; }
     if (precision != TILEQR_FP64) s = 32;   // the split products take ib = 32
     if (nb) *nb = b;
     if (ib) *ib = s;
@@ -420,18 +424,22 @@ int prepare_schedule(Workspace *W, SchedBufs &B, std::vector<MatDev> &mats, int 
         S.trace_cap = (uint32_t)ntask;
         W->trace_events = ntask;
     }
-    // Panel workers: one matrix has one panel chain per step in flight and
-    // a few steps overlap, so a few suffice: 16 when there are at most 32
-    // tile steps (the panel chains are then most of the critical path),
-    // else 8 (the updates dominate and every panel workgroup is one fewer
-    // for them).  Many matrices get a share of the workgroups in proportion
-    // to their panel flops.  Update workers: the rest of what fits at once.
+    // Panel workers.  A share of the workgroups in proportion to the panel
+    // flops suits many matrices, and one matrix split into panel tasks,
+    // whose panel wavefront holds up to nb/ib tasks per step in flight
+    // (tall matrices: many; square ones: few, so at least 16 there).  One
+    // matrix with whole tile kernels has one panel chain per step in
+    // flight: 16 workgroups when there are at most 32 tile steps, else 8
+    // (the updates dominate and every panel workgroup is one fewer for
+    // them).  Update workers: the rest of what fits at once.
     const int occ = worker_occupancy(nb, ib, o.precision);
     const int capacity = std::max(2, std::max(1, W->num_cu) * occ);
+    const int share = (int)std::lround(1.5 * capacity * panel_flops / std::max(all_flops, 1.0));
     int panel;
     if (o.panel_workers > 0) panel = (int)o.panel_workers;
-    else if (nmat == 1) panel = (int)std::min<int64_t>(kmax_max <= 32 ? 16 : 8, kmax_max);
-    else panel = (int)std::lround(1.5 * capacity * panel_flops / std::max(all_flops, 1.0));
+    else if (nmat > 1) panel = share;
+    else if (np > 1) panel = (int)std::min<int64_t>(std::max(share, 16), (int64_t)np * kmax_max);
+    else panel = (int)std::min<int64_t>(kmax_max <= 32 ? 16 : 8, kmax_max);
     panel = std::max(1, std::min(panel, capacity / 2));
     int update = o.workers > 0 ? (int)o.workers : capacity - panel;
     update = std::max(1, std::min(update, capacity - panel));
