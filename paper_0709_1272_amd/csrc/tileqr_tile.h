@@ -178,6 +178,68 @@ __device__ __forceinline__ void stage_store(Smem<NB, IB> &sm, const Stage<NB, IB
     }
 }
 
+// Staging for the update tasks with the rows split by wave: wave w loads
+// and stores rows 32 w .. 32 w + 31 of the panel, the only rows its own
+// products read (VᵀX and V W both take the wave's 32 rows).  No workgroup
+// barrier is then needed between staging a panel and using it, nor before
+// overwriting it with the next one.  Same contents as stage_load /
+// stage_store.
+template <int NB, int IB>
+__device__ __forceinline__ int stage_row(int u)
+{
+    constexpr int H = IB / 2, RPP = 64 / H;   // column pairs per row, rows per pass
+    return wave_id() * 32 + lane_id() / H + RPP * u;
+}
+
+template <int NB, int IB>
+__device__ __forceinline__ void stage_load_rows(Stage<NB, IB> &S, const gdouble *tile, int c0, int r0, const gdouble *Tg)
+{
+    using C = Cfg<NB, IB>;
+    constexpr int H = IB / 2, TE = IB * IB / 2;
+    static_assert(C::VPT * (64 / H) == 32, "one pass per group of rows");
+    const int c2 = lane_id() % H;
+#pragma unroll
+    for (int u = 0; u < C::VPT; ++u) {
+        const int r = stage_row<NB, IB>(u);
+        const v2d x = *reinterpret_cast<const gv2d *>(tile + (size_t)r * NB + c0 + 2 * c2);
+        S.v[u] = r >= r0 ? x : v2d{0.0, 0.0};
+    }
+#pragma unroll
+    for (int u = 0; u < C::TPT; ++u) {
+        const int e = threadIdx.x + u * C::NT;
+        const v2d t = reinterpret_cast<const gv2d *>(Tg)[e < TE ? e : TE - 1];
+        S.t[u] = e < TE ? t : v2d{0.0, 0.0};
+    }
+}
+
+template <int NB, int IB>
+__device__ __forceinline__ void stage_store_rows(Smem<NB, IB> &sm, const Stage<NB, IB> &S, int r0, bool unit, int c0)
+{
+    using C = Cfg<NB, IB>;
+    constexpr int H = IB / 2;
+    const int c = 2 * (lane_id() % H);
+#pragma unroll
+    for (int u = 0; u < C::VPT; ++u) {
+        const int r = stage_row<NB, IB>(u);
+        if (r < r0) continue;
+        double a = S.v[u].x, b = S.v[u].y;
+        if (unit) {
+            const int d = r - c0;
+            a = d < c ? 0.0 : (d == c ? 1.0 : a);
+            b = d < c + 1 ? 0.0 : (d == c + 1 ? 1.0 : b);
+        }
+        *reinterpret_cast<v2d *>(&sm.P[r * C::LDP + c]) = v2d{a, b};
+    }
+#pragma unroll
+    for (int u = 0; u < C::TPT; ++u) {
+        const int e = threadIdx.x + u * C::NT;
+        if (e < IB * IB / 2) reinterpret_cast<v2d *>(sm.Tl)[e] = S.t[u];
+    }
+    // The wave reads these rows next: keep the compiler from moving its
+    // LDS accesses across (the hardware runs one wave's LDS accesses in order).
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+}
+
 // X (accumulator layout) <- strip of a row-major tile: columns
 // [col0, col0 + 16 cbn), rows of every row block.
 template <int NB, int IB>
@@ -1064,26 +1126,27 @@ __device__ __forceinline__ void apply_diag_strip(Smem<NB, IB> &sm, const gdouble
     using C = Cfg<NB, IB>;
     Stage<NB, IB> S;
     const int l0 = TRANS ? 0 : C::NPAN - 1;
-    stage_load<NB, IB>(S, tkk, l0 * IB, l0 * IB, Tk + l0 * IB * IB);
+    stage_load_rows<NB, IB>(S, tkk, l0 * IB, l0 * IB, Tk + l0 * IB * IB);
     Strip<NB, IB> X;
     load_strip<NB, IB>(X, x, ldx, col0, CB);
     // Wait for the strip here, once: inside the loop the only loads in
     // flight are then the next panel's, and the products do not wait for them.
     __builtin_amdgcn_s_waitcnt(0);
     double tv[C::EPT] = {};
+    // Each wave stages the panel rows it uses itself (stage_store_rows), so
+    // the loop has only apply_panel's barriers; those also order sm.Tl's
+    // rewrite after the previous panel's T^T W.
 #pragma unroll 1
     for (int q = 0; q < C::NPAN; ++q) {
         const int l = TRANS ? q : C::NPAN - 1 - q;
         const int c0 = l * IB;
-        stage_store<NB, IB>(sm, S, c0, true, c0);
-        __syncthreads();
+        stage_store_rows<NB, IB>(sm, S, c0, true, c0);
         // The next panel's prefetch (after the last panel a harmless reload
         // of this one, so that the loads issued do not depend on q).
         const int ln = q + 1 < C::NPAN ? (TRANS ? l + 1 : l - 1) : l;
-        stage_load<NB, IB>(S, tkk, ln * IB, ln * IB, Tk + ln * IB * IB);
+        stage_load_rows<NB, IB>(S, tkk, ln * IB, ln * IB, Tk + ln * IB * IB);
         if constexpr (PREC == PREC_FP64) apply_panel<NB, IB, TRANS>(sm, X, c0, nullptr, 0, CB, tv);
         else apply_panel_mx<NB, IB, PREC>(sm, X, c0, nullptr, 0, tv);
-        __syncthreads();
     }
     store_strip<NB, IB>(X, x, ldx, col0, CB, 0);
 }
@@ -1100,26 +1163,25 @@ __device__ __forceinline__ void apply_ts_strip(Smem<NB, IB> &sm, const gdouble *
     using C = Cfg<NB, IB>;
     Stage<NB, IB> S;
     const int l0 = TRANS ? 0 : C::NPAN - 1;
-    stage_load<NB, IB>(S, tik, l0 * IB, 0, Ti + l0 * IB * IB);
+    stage_load_rows<NB, IB>(S, tik, l0 * IB, 0, Ti + l0 * IB * IB);
     Strip<NB, IB> X;
     load_strip<NB, IB>(X, x, ldx, col0, CB);
-    // As in apply_diag_strip: the strip is waited for once, before the loop.
+    // As in apply_diag_strip: the strip is waited for once, before the loop,
+    // and each wave stages its own panel rows.
     __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll 1
     for (int q = 0; q < C::NPAN; ++q) {
         const int l = TRANS ? q : C::NPAN - 1 - q;
         const int c0 = l * IB;
-        stage_store<NB, IB>(sm, S, 0, false, c0);
-        __syncthreads();
+        stage_store_rows<NB, IB>(sm, S, 0, false, c0);
         // The top rows first, then the next panel's prefetch.
         gdouble *tp = top + (size_t)c0 * ldtop + col0;
         double tv[C::EPT];
         load_top<NB, IB>(tv, tp, ldtop, WS);
         const int ln = q + 1 < C::NPAN ? (TRANS ? l + 1 : l - 1) : l;
-        stage_load<NB, IB>(S, tik, ln * IB, 0, Ti + ln * IB * IB);
+        stage_load_rows<NB, IB>(S, tik, ln * IB, 0, Ti + ln * IB * IB);
         if constexpr (PREC == PREC_FP64) apply_panel<NB, IB, TRANS>(sm, X, 0, tp, ldtop, CB, tv);
         else apply_panel_mx<NB, IB, PREC>(sm, X, 0, tp, ldtop, tv);
-        __syncthreads();
     }
     store_strip<NB, IB>(X, x, ldx, col0, CB, 0);
 }
