@@ -635,7 +635,7 @@ extern "C" int tileqr_finalize(void)
 namespace {
 
 // Q^T or Q on row blocks `rows` (leading dimension ldt) with the factor
-// already in W->tiles.  W->prog must hold min(p, q) flags (PROG_STRIDE apart).
+// already in W->tiles.  W->prog must hold min(p, q) nb/ib flags (PROG_STRIDE apart).
 hipError_t apply_rows(Workspace *W, int nb, int ib, int p, int q, const double *T, double *rows, int ldt, bool trans,
                       hipStream_t st)
 {
@@ -682,7 +682,7 @@ int apply_common(bool trans, int64_t m, int64_t n, int64_t nrhs, const double *A
     int rc;
     if ((rc = W->tiles.ensure((size_t)p * q * nb * nb * sizeof(double)))) return rc;
     if ((rc = W->rows.ensure((size_t)p * nb * ldt * sizeof(double)))) return rc;
-    if ((rc = W->prog.ensure((size_t)kmax * PROG_STRIDE * sizeof(int32_t) + 64))) return rc;
+    if ((rc = W->prog.ensure((size_t)kmax * (nb / ib) * PROG_STRIDE * sizeof(int32_t) + 64))) return rc;
     if ((rc = W->status.ensure(256))) return rc;
     TQ_HIP(hipMemsetAsync(W->status.ptr, 0, sizeof(int), st));
     TQ_HIP(launch_cm2tile(A, lda, m, n, (double *)W->tiles.ptr, (int)nb, p, q, (int *)W->status.ptr, st));
@@ -802,7 +802,7 @@ extern "C" int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double 
     const int64_t part_cap = std::max<int64_t>(m * 32 * 16, 1 << 20);
     if ((rc = W->part.ensure((size_t)part_cap * sizeof(double)))) return rc;
     if ((rc = W->misc.ensure((SMALL_PART + SMALL_PART_CAP) * sizeof(double)))) return rc;
-    if ((rc = W->prog.ensure((size_t)std::min(p, q) * PROG_STRIDE * sizeof(int32_t) + 64))) return rc;
+    if ((rc = W->prog.ensure((size_t)std::min(p, q) * (nb / ib) * PROG_STRIDE * sizeof(int32_t) + 64))) return rc;
     const int64_t tflags_cap = cdiv(n, nb) * (ldt / kStripWidth) * FLAG_STRIDE;
     if ((rc = W->tflags.ensure((size_t)tflags_cap * sizeof(int32_t)))) return rc;
     const int64_t spin = o.spin_limit > 0 ? o.spin_limit : (int64_t)1 << 24;

@@ -65,7 +65,7 @@ struct ApplyDev {
     int32_t ldb;              // a multiple of the strip width
     int32_t nstrip;           // ldb / strip width
     int32_t kmax;             // tile steps of the factorisation
-    int32_t *prog;            // [kmax * PROG_STRIDE] progress flags, one per 256 bytes
+    int32_t *prog;            // [kmax * (nb / ib) * PROG_STRIDE] progress flags, one per 256 bytes
     int32_t *status;
     int64_t spin_limit;
 };

@@ -45,37 +45,54 @@ __global__ void k_sched_seed(SchedDev S)
 // B <- Q^T B (TRANS) or Q B for Q of a finished factorisation, B held in
 // row blocks of nb rows (row-major, leading dimension D.ldb, a multiple of
 // the strip width).  Q^T applies, for k = 0, 1, ..: Q_kk^T to block k, then
-// Q_ik^T to blocks (k, i) for i = k+1, k+2, ..  (the order in which the
+// Q_ik^T to blocks (k, i) for i = k+1, k+2, .. (the order in which the
 // factorisation applied them to A); Q applies the transposes in reverse.
-// Workgroup w runs step k (k = w for Q^T, kmax-1-w for Q) over its row
-// blocks in that order; before touching block i it waits until the step
-// that precedes it in the product has finished block i (progress flags in
-// D.prog, one per PROG_STRIDE words).  That neighbour always has the lower workgroup index, so it was
-// dispatched first and the waits make progress; every wait is bounded.
+// Each tile reflector is the product of its nb/ib inner panels, and the
+// work is spread over (step, panel) pairs: workgroup (k, l) applies inner
+// panel l of every reflector of step k, row block after row block.  Panel l
+// of the TS reflector (k, i) touches only rows [l ib, (l+1) ib) of block k
+// and all of block i, so workgroup (k, l) on block i waits only for panel
+// l-1 (TRANS; l+1 for Q) of the same step to have finished block i, and the
+// first panel of a step for the previous step (in the product's order) to
+// have finished it: a wavefront over (row block, panel) instead of a chain
+// of whole tiles.  Progress flags (the last block done) sit PROG_STRIDE
+// words apart in D.prog, one per (step, panel).  A workgroup waits only for
+// lower-numbered ones, which were dispatched first, so the waits make
+// progress; every wait is bounded.
 template <int NB, int IB, bool TRANS>
 __global__ __launch_bounds__(2 * NB) void k_apply(ApplyDev D)
 {
     __shared__ Smem<NB, IB> sm;
     __shared__ int s_abort;
+    constexpr int NP = Cfg<NB, IB>::NPAN;
     const int tid = threadIdx.x;
     const int kmax = D.kmax, p = D.M.p;
-    const int k = TRANS ? (int)blockIdx.x : kmax - 1 - (int)blockIdx.x;
+    const int sidx = (int)blockIdx.x / NP, pidx = (int)blockIdx.x % NP;
+    const int k = TRANS ? sidx : kmax - 1 - sidx;
+    const int l = TRANS ? pidx : NP - 1 - pidx;
+    if (*D.status != 0) return;   // input rejected (non-finite factor)
     const gdouble *tkk = tile_ptr(D.M, NB, k, k);
     gdouble *Bk = (gdouble *)(D.B + (size_t)k * NB * D.ldb);
+    // The first panel of a step (l = 0 for Q^T, nb/ib - 1 for Q) follows the
+    // last panel of the previous step in the product; the others follow the
+    // neighbouring panel of the same step.
+    const bool first = pidx == 0;
+    const int *pred = nullptr;
+    if (!first) pred = &D.prog[(k * NP + (TRANS ? l - 1 : l + 1)) * PROG_STRIDE];
+    else if (TRANS ? k > 0 : k + 1 < kmax) pred = &D.prog[((TRANS ? k - 1 : k + 1) * NP + (TRANS ? NP - 1 : 0)) * PROG_STRIDE];
     const int nrow = p - k;   // blocks k .. p-1
-    if (*D.status != 0) return;   // input rejected (non-finite factor)
     for (int q = 0; q < nrow; ++q) {
         // Q^T: k, k+1, .., p-1.   Q: p-1, .., k+1, then k.
         const int r = TRANS ? k + q : (q + 1 < nrow ? p - 1 - q : k);
-        const bool wait = TRANS ? k > 0 : (k + 1 < kmax && r != k);
+        // Block k under Q never sees step k+1 (which starts at block k+1).
+        const bool wait = pred != nullptr && !(first && !TRANS && r == k);
         if (tid == 0) {
             int abort = 0;
             if (wait) {
-                const int *flag = &D.prog[(TRANS ? k - 1 : k + 1) * PROG_STRIDE];
                 int64_t spins = 0;
                 int backoff = 0;
                 for (;;) {
-                    const int v = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    const int v = __hip_atomic_load(pred, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     if (TRANS ? v >= r : v <= r) break;
                     if (__hip_atomic_load(D.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
                         ++spins > D.spin_limit) {
@@ -98,26 +115,27 @@ __global__ __launch_bounds__(2 * NB) void k_apply(ApplyDev D)
 #pragma unroll 1
         for (int st = 0; st < D.nstrip; ++st) {
             if (r == k)
-                apply_diag_strip<NB, IB, TRANS>(sm, tkk, tblock_ptr(D.M, NB, IB, k, k), Bk, D.ldb, st * WS);
+                apply_one_panel<NB, IB, TRANS>(sm, tkk, tblock_ptr(D.M, NB, IB, k, k), l, true, nullptr, 0, Bk, D.ldb,
+                                               st * WS);
             else
-                apply_ts_strip<NB, IB, TRANS>(sm, tile_ptr(D.M, NB, r, k), tblock_ptr(D.M, NB, IB, k, r), Bk, D.ldb,
-                                              Br, D.ldb, st * WS);
+                apply_one_panel<NB, IB, TRANS>(sm, tile_ptr(D.M, NB, r, k), tblock_ptr(D.M, NB, IB, k, r), l, false,
+                                               Bk, D.ldb, Br, D.ldb, st * WS);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __syncthreads();
         if (tid == 0) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __hip_atomic_store(&D.prog[k * PROG_STRIDE], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&D.prog[(k * NP + l) * PROG_STRIDE], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
 
-// Progress flags before an apply: Q^T steps start at k-1 (nothing done),
-// Q steps at p (nothing done, rows are taken in descending order).
-__global__ void k_apply_init(int *prog, int kmax, int p, int trans)
+// Progress flags before an apply, one per (step, panel): -1 for Q^T (rows
+// are taken in ascending order), p for Q (descending).
+__global__ void k_apply_init(int *prog, int nflag, int p, int trans)
 {
-    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < kmax; k += gridDim.x * blockDim.x)
-        prog[k * PROG_STRIDE] = trans ? k - 1 : p;
+    for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < nflag; f += gridDim.x * blockDim.x)
+        prog[f * PROG_STRIDE] = trans ? -1 : p;
 }
 
 // Column-major (B, ldb) m x nrhs <-> row blocks: Bt[(R) * ldt + c], rows
@@ -343,11 +361,12 @@ hipError_t launch_factor_serial(int nb, int ib, int prec, const MatDev &M, const
 template <int NB, int IB>
 static hipError_t apply_impl(const ApplyDev &D, bool trans, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_apply_init, dim3(1), dim3(256), 0, st, D.prog, D.kmax, D.M.p, trans ? 1 : 0);
+    const int nflag = D.kmax * Cfg<NB, IB>::NPAN;
+    hipLaunchKernelGGL(k_apply_init, dim3(1), dim3(256), 0, st, D.prog, nflag, D.M.p, trans ? 1 : 0);
     if (trans)
-        hipLaunchKernelGGL((k_apply<NB, IB, true>), dim3(D.kmax), dim3(Cfg<NB, IB>::NT), 0, st, D);
+        hipLaunchKernelGGL((k_apply<NB, IB, true>), dim3(nflag), dim3(Cfg<NB, IB>::NT), 0, st, D);
     else
-        hipLaunchKernelGGL((k_apply<NB, IB, false>), dim3(D.kmax), dim3(Cfg<NB, IB>::NT), 0, st, D);
+        hipLaunchKernelGGL((k_apply<NB, IB, false>), dim3(nflag), dim3(Cfg<NB, IB>::NT), 0, st, D);
     return hipGetLastError();
 }
 

@@ -1186,6 +1186,33 @@ __device__ __forceinline__ void apply_ts_strip(Smem<NB, IB> &sm, const gdouble *
     store_strip<NB, IB>(X, x, ldx, col0, CB, 0);
 }
 
+// Inner panel l alone of the block reflector of tile vt applied to one
+// strip (32 columns at col0) of x: H_l^T (TRANS) or H_l.  With `diag`, vt
+// is a diagonal tile (V unit lower triangular from row l ib, the rows above
+// untouched); otherwise the coupled TS form, whose ib top rows are rows
+// [l ib, (l+1) ib) of `top`.  Loads the strip, applies the panel and
+// stores back the rows it changed, so that consecutive panels may run on
+// different workgroups.
+template <int NB, int IB, bool TRANS>
+__device__ __forceinline__ void apply_one_panel(Smem<NB, IB> &sm, const gdouble *vt, const gdouble *Tg, int l, bool diag,
+                                                gdouble *top, int ldtop, gdouble *x, int ldx, int col0)
+{
+    using C = Cfg<NB, IB>;
+    const int c0 = l * IB, r0 = diag ? c0 : 0;
+    Stage<NB, IB> S;
+    stage_load_rows<NB, IB>(S, vt, c0, r0, Tg + l * IB * IB);
+    Strip<NB, IB> X;
+    load_strip<NB, IB>(X, x, ldx, col0, CB);
+    gdouble *tp = diag ? nullptr : top + (size_t)c0 * ldtop + col0;
+    double tv[C::EPT] = {};
+    if (!diag) load_top<NB, IB>(tv, tp, ldtop, WS);
+    stage_store_rows<NB, IB>(sm, S, r0, diag, c0);
+    apply_panel<NB, IB, TRANS>(sm, X, r0, tp, ldtop, CB, tv);
+    // Only the rows the panel changed go back: the rows above a diagonal
+    // panel may meanwhile be updated by another panel's workgroup.
+    store_strip<NB, IB>(X, x, ldx, col0, CB, r0);
+}
+
 // DLARFB: strip s of A_kj <- Q_kk^T A_kj.
 template <int NB, int IB, int PREC>
 __device__ __forceinline__ void task_larfb(Smem<NB, IB> &sm, const MatDev &M, int k, int j, int s)
