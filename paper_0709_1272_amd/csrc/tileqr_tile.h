@@ -63,7 +63,7 @@ template <int NB, int IB>
 struct Cfg {
     static constexpr int NW = NB / 32;       // waves per workgroup
     static constexpr int NT = 64 * NW;       // threads per workgroup (= 2 nb, the launch bound)
-    static constexpr int NSLOT = NW < 4 ? NW : 4;   // LDS slots of the cross-wave reduction
+    static constexpr int NSLOT = NW;         // LDS slots of the cross-wave reduction (one per wave)
     static constexpr int RB = 2;             // 16-row blocks per wave
     static constexpr int IBB = IB / 16;      // 16-wide blocks of the ib dimension
     static constexpr int NPAN = NB / IB;     // inner panels per tile
@@ -97,13 +97,19 @@ template <int NB, int IB>
 struct Smem {
     using C = Cfg<NB, IB>;
     double P[(NB + IB) * C::LDP];    // panel / V: rows 0..nb-1 tile rows, nb.. head rows
-    double Wp[C::NSLOT * IB * WS];   // per-wave partial products
-    double Wa[IB * WS];              // reduced W (or the Gram matrix V^T V)
+    union {
+        // Per-wave partial products, one slot per wave; their sum (W, or
+        // the Gram matrix V^T V) is formed in place in slot 0.
+        double Wp[C::NSLOT * IB * WS];
+        // Reflector broadcast of the panel factorisation (double-buffered by
+        // column parity); never live at the same time as the slots.
+        double xb[2][NB];
+    };
     double Wb[IB * WS];              // T^T W
     double Tl[IB * IB];              // T of the current inner panel
     double tau[IB];
-    double xb[2][NB];                // reflector broadcast (double-buffered by column parity)
     double sc[2][2];                 // tau of the broadcast reflector
+    static_assert(C::NSLOT * IB * WS >= 2 * NB, "the broadcast buffers fit in the slots");
 };
 
 // ------------------------------------------------------------------ helpers
@@ -296,50 +302,23 @@ __device__ __forceinline__ void strip_to_panel(Smem<NB, IB> &sm, const Strip<NB,
 }
 
 // Per-wave partial accumulators (BA x BB blocks of 16 x 16 in accumulator
-// layout, row stride ld) -> sm.Wp slots 0..NSLOT-1.  With 8 waves the upper
-// four first store, then the lower four add theirs (slot q = P_{q+4} + P_q),
-// which halves the LDS the reduction needs; the caller sums the slots in
-// order.  Ends with a barrier.
+// layout, row stride ld) -> sm.Wp slot w (the wave's own).  Ends with a
+// barrier; sum_slots then adds the slots in wave order.
 // GMAJ selects the accumulator row order: element r of lane group g is row
 // 4 r + g (FP64 MFMA) or 4 g + r (the 16x16x32 narrow MFMAs).
 template <int NB, int IB, int BA, int BB, bool GMAJ = false>
 __device__ __forceinline__ void waves_to_slots(Smem<NB, IB> &sm, const d4 (&acc)[BA][BB], int ld)
 {
-    using C = Cfg<NB, IB>;
     constexpr int SLOT = IB * WS;
     const int w = wave_id(), n = lane_id() & 15, g = lane_id() >> 4;
     const int gm = GMAJ ? 4 : 1, rm = GMAJ ? 1 : 4;
-    if (C::NW > C::NSLOT) {
-        if (w >= C::NSLOT) {
 #pragma unroll
-            for (int a = 0; a < BA; ++a)
+    for (int a = 0; a < BA; ++a)
 #pragma unroll
-                for (int b = 0; b < BB; ++b)
+        for (int b = 0; b < BB; ++b)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        sm.Wp[(w - C::NSLOT) * SLOT + (a * 16 + rm * r + gm * g) * ld + b * 16 + n] = acc[a][b][r];
-        }
-        __syncthreads();
-        if (w < C::NSLOT) {
-#pragma unroll
-            for (int a = 0; a < BA; ++a)
-#pragma unroll
-                for (int b = 0; b < BB; ++b)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        double *d = &sm.Wp[w * SLOT + (a * 16 + rm * r + gm * g) * ld + b * 16 + n];
-                        *d = *d + acc[a][b][r];
-                    }
-        }
-    } else {
-#pragma unroll
-        for (int a = 0; a < BA; ++a)
-#pragma unroll
-            for (int b = 0; b < BB; ++b)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    sm.Wp[w * SLOT + (a * 16 + rm * r + gm * g) * ld + b * 16 + n] = acc[a][b][r];
-    }
+            for (int r = 0; r < 4; ++r)
+                sm.Wp[w * SLOT + (a * 16 + rm * r + gm * g) * ld + b * 16 + n] = acc[a][b][r];
     __syncthreads();
 }
 
@@ -354,9 +333,9 @@ __device__ __forceinline__ double sum_slots(const Smem<NB, IB> &sm, int e)
 }
 
 // Rows 0..ib-1, columns 0..ncol-1 of the coupled upper tile block `top`
-// (row stride ldtop) -> registers in the entry order of sm.Wa (entry
-// e = tid + u * NT is row e / WS, column e % WS; columns from ncol on read
-// as zero).  The callers issue these loads ahead of the next panel's
+// (row stride ldtop) -> registers in the entry order of the reduced W in
+// sm.Wp slot 0 (entry e = tid + u * NT is row e / WS, column e % WS;
+// columns from ncol on read as zero).  The callers issue these loads ahead of the next panel's
 // prefetch, so that waiting for them does not wait for the prefetch.
 template <int NB, int IB>
 __device__ __forceinline__ void load_top(double (&tv)[(Cfg<NB, IB>::EPT)], const gdouble *top, int ldtop, int ncol)
@@ -427,7 +406,7 @@ __device__ __forceinline__ void apply_panel(Smem<NB, IB> &sm, Strip<NB, IB> &X, 
         const int e = tid + u * C::NT, c = e % WS;
         double s = sum_slots<NB, IB>(sm, e);
         if (top != nullptr && c < ncol) s = tv[u] + s;
-        sm.Wa[e] = s;
+        sm.Wp[e] = s;
     }
     __syncthreads();
     // T^T W: one 16 x 16 output block per wave.
@@ -437,7 +416,7 @@ __device__ __forceinline__ void apply_panel(Smem<NB, IB> &sm, Strip<NB, IB> &X, 
 #pragma unroll
         for (int kc = 0; kc < IB / 4; ++kc)
             acc = mfma(TRANS ? sm.Tl[(4 * kc + g) * IB + a * 16 + n] : sm.Tl[(a * 16 + n) * IB + 4 * kc + g],
-                       sm.Wa[(4 * kc + g) * WS + cb * 16 + n], acc);
+                       sm.Wp[(4 * kc + g) * WS + cb * 16 + n], acc);
 #pragma unroll
         for (int r = 0; r < 4; ++r) sm.Wb[(a * 16 + 4 * r + g) * WS + cb * 16 + n] = acc[r];
     }
@@ -619,7 +598,7 @@ __device__ __forceinline__ void apply_panel_mx(Smem<NB, IB> &sm, Strip<NB, IB> &
         const int e = tid + u * C::NT;
         double s = sum_slots<NB, IB>(sm, e);
         if (top != nullptr) s = tv[u] + s;
-        sm.Wa[e] = s;
+        sm.Wp[e] = s;
     }
     __syncthreads();
     // T^T W in FP64: one 16 x 16 output block per wave.
@@ -628,7 +607,7 @@ __device__ __forceinline__ void apply_panel_mx(Smem<NB, IB> &sm, Strip<NB, IB> &
         d4 acc = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int kc = 0; kc < IB / 4; ++kc)
-            acc = mfma(sm.Tl[(4 * kc + g) * IB + a * 16 + n], sm.Wa[(4 * kc + g) * WS + cb * 16 + n], acc);
+            acc = mfma(sm.Tl[(4 * kc + g) * IB + a * 16 + n], sm.Wp[(4 * kc + g) * WS + cb * 16 + n], acc);
 #pragma unroll
         for (int r = 0; r < 4; ++r) sm.Wb[(a * 16 + 4 * r + g) * WS + cb * 16 + n] = acc[r];
     }
@@ -922,7 +901,7 @@ __device__ __forceinline__ void build_t(Smem<NB, IB> &sm, int rlo, gdouble *Tg)
         }
     }
     waves_to_slots<NB, IB, C::IBB, C::IBB>(sm, G, IB);
-    for (int e = tid; e < IB * IB; e += C::NT) sm.Wa[e] = sum_slots<NB, IB>(sm, e);
+    for (int e = tid; e < IB * IB; e += C::NT) sm.Wp[e] = sum_slots<NB, IB>(sm, e);
     __syncthreads();
     // Diagonal blocks of 16 (T11, T22 for ib = 32) by the recurrence, one
     // lane per row, both blocks at once.
@@ -936,7 +915,7 @@ __device__ __forceinline__ void build_t(Smem<NB, IB> &sm, int rlo, gdouble *Tg)
         for (int j = 1; j < HB; ++j) {
             double s = 0.0;
 #pragma unroll
-            for (int kk = 0; kk < j; ++kk) s += trow[kk] * sm.Wa[(base + kk) * IB + base + j];
+            for (int kk = 0; kk < j; ++kk) s += trow[kk] * sm.Wp[(base + kk) * IB + base + j];
             if (li < j) trow[j] = -sm.tau[base + j] * s;
         }
 #pragma unroll
@@ -954,7 +933,7 @@ __device__ __forceinline__ void build_t(Smem<NB, IB> &sm, int rlo, gdouble *Tg)
             d4 acc = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int kc = 0; kc < HB / 4; ++kc)
-                acc = mfma(sm.Wa[n * IB + HB + 4 * kc + g], sm.Tl[(HB + 4 * kc + g) * IB + HB + n], acc);
+                acc = mfma(sm.Wp[n * IB + HB + 4 * kc + g], sm.Tl[(HB + 4 * kc + g) * IB + HB + n], acc);
 #pragma unroll
             for (int r = 0; r < 4; ++r) sm.Wb[(4 * r + g) * HB + n] = acc[r];
         }

@@ -115,6 +115,23 @@ def test_graph_replay_and_direct_launch_agree(tq):
     assert torch.equal(B1.buf, B4.buf)
 
 
+def test_batch_of_one_uses_panel_tasks(tq):
+    # A batch of one matrix with few tile steps is scheduled like a single
+    # call (one task per inner panel); a two-matrix batch of the same shapes
+    # keeps whole tile kernels.  All give the same bits.
+    A = synth.uniform(8, 1100, 700)
+    F, T = single(tq, A, 128, 32)
+    B1 = Batch(tq, [A], [(128, 32)])
+    assert B1.factor([128], [32]) == tq.OK
+    assert np.array_equal(B1.result(0), F)
+    B2 = Batch(tq, [A, A], [(128, 32)])
+    assert B2.factor([128] * 2, [32] * 2) == tq.OK
+    assert np.array_equal(B2.result(0), F) and np.array_equal(B2.result(1), F)
+    Bp = Batch(tq, [A, A], [(128, 32)])
+    assert Bp.factor([128] * 2, [32] * 2, panel_tasks=4) == tq.OK
+    assert np.array_equal(Bp.result(1), F)
+
+
 def test_groups_of_blockings(tq):
     mats = small_batch(3, 24)
     nbs = [64, 128, 256] * 8
