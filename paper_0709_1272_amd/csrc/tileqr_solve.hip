@@ -23,6 +23,19 @@ __device__ __forceinline__ const double *tile_at(const double *tiles, int p, int
     return tiles + ((size_t)j * p + i) * (size_t)nb * nb;
 }
 
+// store(e, load(e)) for e = tid, tid + nt, .. (COUNT per thread), with every
+// load issued before the first store, so that the loads' latencies overlap
+// (a plain copy loop waits for each load before the next one).
+template <int COUNT, typename Load, typename Store>
+__device__ __forceinline__ void batched_copy(int tid, int nt, Load load, Store store)
+{
+    double v[COUNT];
+#pragma unroll
+    for (int u = 0; u < COUNT; ++u) v[u] = load(tid + u * nt);
+#pragma unroll
+    for (int u = 0; u < COUNT; ++u) store(tid + u * nt, v[u]);
+}
+
 }  // namespace
 
 // Triangular solve with the tiled R on a 32-wide strip of right-hand sides,
@@ -82,15 +95,17 @@ __global__ __launch_bounds__(2 * NB) void k_trsm(const double *tiles, int p, int
         __syncthreads();
         const double *Rt = upper ? tile_at(tiles, p, NB, i, j) : tile_at(tiles, p, NB, j, i);
         const double *Cj = C + (size_t)j * NB * ldt;
-        for (int e = tid; e < NB * SW; e += NT) Xs[e / SW][e % SW] = Cj[(size_t)(e / SW) * ldt + s0 + e % SW];
+        batched_copy<NB * SW / NT>(tid, NT, [&](int e) { return Cj[(size_t)(e / SW) * ldt + s0 + e % SW]; },
+                                   [&](int e, double v) { Xs[e / SW][e % SW] = v; });
         for (int kc = 0; kc < NB; kc += 32) {
             __syncthreads();
             // Rc[row][kk] = op(R)_ij[row][kc + kk]
-            if (upper) {
-                for (int e = tid; e < NB * 32; e += NT) Rc[e / 32][e % 32] = Rt[(size_t)(e / 32) * NB + kc + e % 32];
-            } else {
-                for (int e = tid; e < NB * 32; e += NT) Rc[e % NB][e / NB] = Rt[(size_t)(kc + e / NB) * NB + e % NB];
-            }
+            if (upper)
+                batched_copy<NB * 32 / NT>(tid, NT, [&](int e) { return Rt[(size_t)(e / 32) * NB + kc + e % 32]; },
+                                           [&](int e, double v) { Rc[e / 32][e % 32] = v; });
+            else
+                batched_copy<NB * 32 / NT>(tid, NT, [&](int e) { return Rt[(size_t)(kc + e / NB) * NB + e % NB]; },
+                                           [&](int e, double v) { Rc[e % NB][e / NB] = v; });
             __syncthreads();
             for (int kk = 0; kk < 32; ++kk) {
                 double a[4], b[4];
@@ -108,7 +123,8 @@ __global__ __launch_bounds__(2 * NB) void k_trsm(const double *tiles, int p, int
         __syncthreads();
     }
     // X_i <- C_i - accumulated products, then the diagonal solve in place.
-    for (int e = tid; e < NB * SW; e += NT) Xs[e / SW][e % SW] = Ci[(size_t)(e / SW) * ldt + s0 + e % SW];
+    batched_copy<NB * SW / NT>(tid, NT, [&](int e) { return Ci[(size_t)(e / SW) * ldt + s0 + e % SW]; },
+                               [&](int e, double v) { Xs[e / SW][e % SW] = v; });
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -118,11 +134,12 @@ __global__ __launch_bounds__(2 * NB) void k_trsm(const double *tiles, int p, int
     for (int bb = 0; bb < NBLK; ++bb) {
         const int b = upper ? NBLK - 1 - bb : bb;
         __syncthreads();
-        if (upper) {
-            for (int e = tid; e < NB * 32; e += NT) Rc[e / 32][e % 32] = R[(size_t)(e / 32) * NB + b * 32 + e % 32];
-        } else {
-            for (int e = tid; e < NB * 32; e += NT) Rc[e % NB][e / NB] = R[(size_t)(b * 32 + e / NB) * NB + e % NB];
-        }
+        if (upper)
+            batched_copy<NB * 32 / NT>(tid, NT, [&](int e) { return R[(size_t)(e / 32) * NB + b * 32 + e % 32]; },
+                                       [&](int e, double v) { Rc[e / 32][e % 32] = v; });
+        else
+            batched_copy<NB * 32 / NT>(tid, NT, [&](int e) { return R[(size_t)(b * 32 + e / NB) * NB + e % NB]; },
+                                       [&](int e, double v) { Rc[e % NB][e / NB] = v; });
         __syncthreads();
         if (tid < 32) {
             const double d = Rc[b * 32 + tid][tid];
@@ -196,14 +213,27 @@ __global__ __launch_bounds__(256) void k_gemv_n_part(const double *A, int64_t ld
     for (int v = 0; v < SW; ++v) acc[v] = 0.0;
     for (int64_t cb = c0; cb < c1; cb += 64) {
         __syncthreads();
-        for (int e = threadIdx.x; e < 64 * SW; e += 256) {
-            const int64_t c = cb + e / SW;
-            xs[e / SW][e % SW] = (c < c1 && e % SW < nr) ? X[c * ldt + e % SW] : 0.0;
-        }
+        batched_copy<64 * SW / 256>((int)threadIdx.x, 256,
+                                    [&](int e) {
+                                        const int64_t c = cb + e / SW;
+                                        return (c < c1 && e % SW < nr) ? X[c * ldt + e % SW] : 0.0;
+                                    },
+                                    [&](int e, double v) { xs[e / SW][e % SW] = v; });
         __syncthreads();
         if (row < m) {
             const int cn = (int)std::min<int64_t>(64, c1 - cb);
-            for (int j = 0; j < cn; ++j) {
+            int j = 0;
+            // Eight columns' loads in flight at a time.
+            for (; j + 8 <= cn; j += 8) {
+                double a[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a[u] = A[(cb + j + u) * lda + row];
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+#pragma unroll
+                    for (int v = 0; v < SW; ++v) acc[v] += a[u] * xs[j + u][v];
+            }
+            for (; j < cn; ++j) {
                 const double a = A[(cb + j) * lda + row];
 #pragma unroll
                 for (int v = 0; v < SW; ++v) acc[v] += a * xs[j][v];
@@ -245,16 +275,18 @@ __global__ __launch_bounds__(256) void k_gemv_t_part(const double *A, int64_t ld
     double acc[8] = {};
     for (int64_t rb = r0; rb < r1; rb += 64) {
         __syncthreads();
-        for (int e = tid; e < 64 * SW; e += 256) {
-            const int rr = e / SW, v = e % SW;
-            const int64_t row = rb + rr;
-            rs[rr][v] = (row < r1 && v < nr) ? Rv[row * ldt + v] : 0.0;
-        }
-        for (int e = tid; e < 64 * 64; e += 256) {
-            const int cc = e / 64, rr = e % 64;
-            const int64_t row = rb + rr, col = c0 + cc;
-            as[cc][rr] = (row < r1 && col < n) ? A[col * lda + row] : 0.0;
-        }
+        batched_copy<64 * SW / 256>(tid, 256,
+                                    [&](int e) {
+                                        const int64_t row = rb + e / SW;
+                                        return (row < r1 && e % SW < nr) ? Rv[row * ldt + e % SW] : 0.0;
+                                    },
+                                    [&](int e, double v) { rs[e / SW][e % SW] = v; });
+        batched_copy<64 * 64 / 256>(tid, 256,
+                                    [&](int e) {
+                                        const int64_t row = rb + e % 64, col = c0 + e / 64;
+                                        return (row < r1 && col < n) ? A[col * lda + row] : 0.0;
+                                    },
+                                    [&](int e, double v) { as[e / 64][e % 64] = v; });
         __syncthreads();
         for (int rr = 0; rr < 64; ++rr) {
             const double a = as[cl][rr];
