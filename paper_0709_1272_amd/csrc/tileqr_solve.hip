@@ -150,16 +150,24 @@ __global__ __launch_bounds__(2 * NB) void k_trsm(const double *tiles, int p, int
         __syncthreads();
         const int r_i = lane & 31;
         const int64_t grow = (int64_t)i * NB + b * 32 + r_i;
-        for (int c = hw; c < SW; c += NT / 32) {
-            double x = Xs[b * 32 + r_i][c];
-            for (int qq = 0; qq < 32; ++qq) {
-                const int r = upper ? 31 - qq : qq;
-                const double xr = __shfl(x, r, 32) * dinv[r];
-                if (r_i == r) x = xr;
-                else if (upper ? r_i < r : r_i > r) x -= Rc[b * 32 + r_i][r] * xr;
+        // The half-wave's right-hand sides (columns hw, hw + HW, ..) advance
+        // together, so that their substitution chains overlap.
+        constexpr int HW = NT / 32, CPH = SW / HW;
+        double x[CPH];
+#pragma unroll
+        for (int u = 0; u < CPH; ++u) x[u] = Xs[b * 32 + r_i][hw + u * HW];
+        for (int qq = 0; qq < 32; ++qq) {
+            const int r = upper ? 31 - qq : qq;
+            const double rv = Rc[b * 32 + r_i][r], dr = dinv[r];
+#pragma unroll
+            for (int u = 0; u < CPH; ++u) {
+                const double xr = __shfl(x[u], r, 32) * dr;
+                if (r_i == r) x[u] = xr;
+                else if (upper ? r_i < r : r_i > r) x[u] -= rv * xr;
             }
-            Xs[b * 32 + r_i][c] = grow < n ? x : 0.0;
         }
+#pragma unroll
+        for (int u = 0; u < CPH; ++u) Xs[b * 32 + r_i][hw + u * HW] = grow < n ? x[u] : 0.0;
         __syncthreads();
         // Rows outside the block that depend on it.
         const int r0 = upper ? 0 : (b + 1) * 32, r1 = upper ? b * 32 : NB;
@@ -222,18 +230,7 @@ __global__ __launch_bounds__(256) void k_gemv_n_part(const double *A, int64_t ld
         __syncthreads();
         if (row < m) {
             const int cn = (int)std::min<int64_t>(64, c1 - cb);
-            int j = 0;
-            // Eight columns' loads in flight at a time.
-            for (; j + 8 <= cn; j += 8) {
-                double a[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) a[u] = A[(cb + j + u) * lda + row];
-#pragma unroll
-                for (int u = 0; u < 8; ++u)
-#pragma unroll
-                    for (int v = 0; v < SW; ++v) acc[v] += a[u] * xs[j + u][v];
-            }
-            for (; j < cn; ++j) {
+            for (int j = 0; j < cn; ++j) {
                 const double a = A[(cb + j) * lda + row];
 #pragma unroll
                 for (int v = 0; v < SW; ++v) acc[v] += a * xs[j][v];
