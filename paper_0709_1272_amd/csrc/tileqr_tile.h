@@ -1062,9 +1062,21 @@ __device__ __forceinline__ void tsqrt_panel(Smem<NB, IB> &sm, const MatDev &M, i
         stage_load<NB, IB, false>(S, tik, c0, 0, nullptr);
         stage_store<NB, IB>(sm, S, 0, false, c0);
     }
-    for (int e = threadIdx.x; e < IB * IB; e += C::NT) {
-        const int r = e / IB, c = e % IB;
-        sm.P[(NB + r) * C::LDP + c] = r <= c ? tkk[(size_t)(c0 + r) * NB + c0 + c] : 0.0;
+    // The ib x ib triangle of R_kk at the panel (both loads of a thread in
+    // flight together; the entries below its diagonal read as zero).
+    {
+        constexpr int TRI = (IB * IB + C::NT - 1) / C::NT;
+        double tri[TRI];
+#pragma unroll
+        for (int u = 0; u < TRI; ++u) {
+            const int e = min((int)threadIdx.x + u * C::NT, IB * IB - 1);
+            tri[u] = tkk[(size_t)(c0 + e / IB) * NB + c0 + e % IB];
+        }
+#pragma unroll
+        for (int u = 0; u < TRI; ++u) {
+            const int e = threadIdx.x + u * C::NT, r = e / IB, c = e % IB;
+            if (e < IB * IB) sm.P[(NB + r) * C::LDP + c] = r <= c ? tri[u] : 0.0;
+        }
     }
     __syncthreads();
     panel_factor<NB, IB, true>(sm, c0);
