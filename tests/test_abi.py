@@ -89,3 +89,22 @@ def test_blocking_rules():
     assert tq.t_size(512, 512, 64, 16) == 8 * 8 * 16 * 64
     assert tq.t_size(0, 5, 64, 16) == 0
     assert tq.t_size(100, 300, 64, 16) == 2 * 2 * 16 * 64   # p = 2, q = 5, min = 2
+
+
+def test_automatic_blocking():
+    # The untuned choice (the tuner's entries override it; none exist in a
+    # fresh process): tiny -> 64/16, tall up to 2048 columns -> 256/16, tall
+    # beyond -> 256/32, near-square up to 4096 -> 128/32, larger -> 256/32;
+    # the split modes always take ib = 32.
+    tq = _tq()
+    assert tq.choose_blocking(200, 100) == (64, 16)
+    assert tq.choose_blocking(65536, 1024) == (256, 16)
+    assert tq.choose_blocking(16384, 2048) == (256, 16)
+    assert tq.choose_blocking(32768, 4096) == (256, 32)
+    assert tq.choose_blocking(4096, 4096) == (128, 32)
+    assert tq.choose_blocking(8192, 8192) == (256, 32)
+    assert tq.choose_blocking(65536, 1024, tq.BF16X3) == (256, 32)
+    assert tq.choose_blocking(200, 100, tq.FP16X2) == (64, 32)
+    for m, n in ((1, 1), (300, 7000), (100000, 64)):
+        nb, ib = tq.choose_blocking(m, n)
+        assert tq.blocking_supported(nb, ib)
