@@ -1264,10 +1264,21 @@ __global__ __launch_bounds__(2 * NB) void k_serial(MatDev M, int k, int i, const
 }
 
 // ------------------------------------------------------- DAG scheduler
+//
+// Memory ordering.  A task's results are published by one agent-scope
+// release fence (after a workgroup barrier that orders every wave's stores
+// before it) ahead of its successor releases, and every task starts with an
+// agent-scope acquire fence.  The counter decrement that finds a successor
+// ready acquires (so that whatever it publishes next carries every
+// predecessor's results) but needs no release of its own after the fence;
+// a queue slot is written with release and read relaxed (the popper's
+// acquire fence completes the pair); the queue heads and the completion
+// count order no data.  Each release or acquire on an atomic costs a cache
+// write-back or invalidation, hence only these.
 
-__device__ __forceinline__ int32_t ld_acq(const int32_t *p)
+__device__ __forceinline__ int32_t ld_rlx_i(const int32_t *p)
 {
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ uint32_t ld_rlx(const uint32_t *p)
 {
@@ -1289,10 +1300,10 @@ __device__ __forceinline__ int64_t pop_task(const SchedDev &S, int queue)
         const uint32_t t = ld_rlx(&S.qtail[queue * QSTRIDE]);
         const uint32_t h = ld_rlx(&S.qhead[queue * QSTRIDE]);
         if (h >= t) return -1;
-        const int32_t v = ld_acq(&S.qslot[S.qoff[queue] + h]);
-        if (v == 0) return -1;
+        const int32_t v = ld_rlx_i(&S.qslot[S.qoff[queue] + h]);
+        if (v == 0) return -1;   // pushed, but its slot not written yet
         uint32_t expect = h;
-        if (__hip_atomic_compare_exchange_strong(&S.qhead[queue * QSTRIDE], &expect, h + 1, __ATOMIC_ACQ_REL,
+        if (__hip_atomic_compare_exchange_strong(&S.qhead[queue * QSTRIDE], &expect, h + 1, __ATOMIC_RELAXED,
                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
             return (int64_t)v - 1;
     }
@@ -1465,7 +1476,7 @@ __device__ __forceinline__ void worker_loop(Smem<NB, IB> &sm, const SchedDev &S)
                 int queue = 0;
                 if (n < ns && !(S.drop_edge >= 0 && gid == S.drop_edge && n == 0)) {
                     const int64_t sl = succ(g, t, n);
-                    const int32_t old = __hip_atomic_fetch_add(&S.counters[M.task_base + sl], -1, __ATOMIC_ACQ_REL,
+                    const int32_t old = __hip_atomic_fetch_add(&S.counters[M.task_base + sl], -1, __ATOMIC_ACQUIRE,
                                                                __HIP_MEMORY_SCOPE_AGENT);
                     if (old == 1) {
                         const Task nt = decode(g, sl);
@@ -1502,7 +1513,7 @@ __device__ __forceinline__ void worker_loop(Smem<NB, IB> &sm, const SchedDev &S)
                     ev[9] = (int64_t)wall_clock64();
                 }
             }
-            __hip_atomic_fetch_add(S.done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(S.done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
     }
