@@ -903,43 +903,50 @@ __device__ __forceinline__ void build_t(Smem<NB, IB> &sm, int rlo, gdouble *Tg)
     waves_to_slots<NB, IB, C::IBB, C::IBB>(sm, G, IB);
     for (int e = tid; e < IB * IB; e += C::NT) sm.Wp[e] = sum_slots<NB, IB>(sm, e);
     __syncthreads();
-    // Diagonal blocks of 16 (T11, T22 for ib = 32) by the recurrence, one
-    // lane per row, both blocks at once.
+    // Diagonal blocks of 16 (T11, T22 for ib = 32) by the recurrence, on
+    // wave 0: lane i < ib builds row i of its block in registers (lanes from
+    // ib on repeat those rows and store nothing).  The loop has no branch,
+    // so the loads of the block's tau and G entries are in flight together;
+    // G is symmetric, and row j of the block holds the entries G[0:j, j]
+    // contiguously.
     constexpr int HB = 16;
-    if (tid < IB) {
-        const int i = tid, base = (i / HB) * HB, li = i - base;
-        double trow[HB];
+    if (w == 0) {
+        const int i = lane_id() & (IB - 1), base = (i / HB) * HB, li = i - base;
+        double tb[HB], trow[HB];
 #pragma unroll
-        for (int kk = 0; kk < HB; ++kk) trow[kk] = kk == li ? sm.tau[base + kk] : 0.0;
+        for (int kk = 0; kk < HB; ++kk) tb[kk] = sm.tau[base + kk];
+#pragma unroll
+        for (int kk = 0; kk < HB; ++kk) trow[kk] = kk == li ? tb[kk] : 0.0;
 #pragma unroll
         for (int j = 1; j < HB; ++j) {
+            const double *grow = &sm.Wp[(base + j) * IB + base];
             double s = 0.0;
 #pragma unroll
-            for (int kk = 0; kk < j; ++kk) s += trow[kk] * sm.Wp[(base + kk) * IB + base + j];
-            if (li < j) trow[j] = -sm.tau[base + j] * s;
+            for (int kk = 0; kk < j; ++kk) s += trow[kk] * grow[kk];
+            trow[j] = li < j ? -tb[j] * s : trow[j];
         }
+        if (lane_id() < IB) {
 #pragma unroll
-        for (int kk = 0; kk < HB; ++kk) {
-            sm.Tl[i * IB + base + kk] = trow[kk];
-            if constexpr (IB == 2 * HB) sm.Tl[i * IB + (HB - base) + kk] = 0.0;
+            for (int kk = 0; kk < HB; ++kk) {
+                sm.Tl[i * IB + base + kk] = trow[kk];
+                if constexpr (IB == 2 * HB) sm.Tl[i * IB + (HB - base) + kk] = 0.0;
+            }
         }
-    }
-    if constexpr (IB == 2 * HB) {
-        // Off-diagonal block: the product of the two block reflectors gives
-        // T12 = -T11 (V1^T V2) T22 (G12 = V1^T V2 is block (0, 1) of G).
-        // One wave, two 16 x 16 x 16 products on MFMA via sm.Wb.
-        __syncthreads();
-        if (w == 0) {
+        if constexpr (IB == 2 * HB) {
+            // Off-diagonal block: the product of the two block reflectors
+            // gives T12 = -T11 (V1^T V2) T22 (G12 = V1^T V2 is block (0, 1)
+            // of G), two 16 x 16 x 16 products on MFMA via sm.Wb.  Only this
+            // wave touches Tl and Wb here, and it runs its LDS accesses in
+            // order, so the fences only keep the compiler from moving them.
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             d4 acc = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int kc = 0; kc < HB / 4; ++kc)
                 acc = mfma(sm.Wp[n * IB + HB + 4 * kc + g], sm.Tl[(HB + 4 * kc + g) * IB + HB + n], acc);
 #pragma unroll
             for (int r = 0; r < 4; ++r) sm.Wb[(4 * r + g) * HB + n] = acc[r];
-        }
-        __syncthreads();
-        if (w == 0) {
-            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            acc = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int kc = 0; kc < HB / 4; ++kc)
                 acc = mfma(sm.Tl[n * IB + 4 * kc + g], sm.Wb[(4 * kc + g) * HB + n], acc);
