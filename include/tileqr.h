@@ -109,7 +109,9 @@ typedef struct {
                              steps, else 8                                         */
     int64_t panel_tasks;  /* DAG tasks per GEQRT and TSQRT: 1 (the whole tile
                              kernel) or nb / ib (one per inner panel, which lets
-                             the panel chains of a step overlap); 0 = automatic
+                             the panel chains of a step overlap; with ib = 32
+                             each panel's update of every later strip of its
+                             tile is then a task of its own); 0 = automatic
                              (one matrix with at most 32 tile steps: nb / ib,
                              otherwise 1)                                           */
 } tileqr_opts;
@@ -270,9 +272,12 @@ double tileqr_flops_tiled(int64_t m, int64_t n, int64_t nb, int64_t ib);
  * strips per tile (LARFB and SSRFB split by columns) and `panels` inner
  * panels per tile (GEQRT and TSQRT split into their ib-column panels; the
  * scheduler uses strips = nb / 32, panels = nb / ib; strips = panels = 1:
- * the paper's tasks).  counts[0..3] receive the numbers of GEQRT, TSQRT,
- * LARFB and SSRFB tasks; returns their sum.  Host only, no GPU needed. */
-int64_t tileqr_dag_counts(int64_t p, int64_t q, int64_t strips, int64_t panels, int64_t counts[4]);
+ * the paper's tasks).  With panels == strips > 1 (ib = 32) the panel tasks
+ * only factor their panel and each later strip of the tile (or tile pair)
+ * gets the panel's reflector in a task of its own, PUPD.  counts[0..4]
+ * receive the numbers of GEQRT, TSQRT, LARFB, SSRFB and PUPD tasks;
+ * returns their sum.  Host only, no GPU needed. */
+int64_t tileqr_dag_counts(int64_t p, int64_t q, int64_t strips, int64_t panels, int64_t counts[5]);
 
 /* Host-side check of the dependency rules the scheduler uses: executes the
  * DAG of a p x q grid (strips and panels as for tileqr_dag_counts) in
@@ -290,7 +295,8 @@ int tileqr_dag_selfcheck(int64_t p, int64_t q, int64_t strips, int64_t panels, i
  * events copied to host memory, 10 int64 each: {type, k, i, j, strip (the
  * inner panel for GEQRT and TSQRT),
  * worker, t_pop, t_start, t_body_end, t_end} (types 0 GEQRT, 1 TSQRT,
- * 2 LARFB, 3 SSRFB; worker = (role << 16) | workgroup; times in ticks of
+ * 2 LARFB, 3 SSRFB, 4 PUPD, whose j field holds its inner panel;
+ * worker = (role << 16) | workgroup; times in ticks of
  * the device wall clock, tileqr_trace_clock_hz per second: when the task
  * was taken from its queue, when its body started after the acquire fence,
  * when the body ended, and when the release fence and the successor

@@ -168,9 +168,9 @@ extern "C" double tileqr_flops_tiled(int64_t m, int64_t n, int64_t nb, int64_t i
     return f;
 }
 
-extern "C" int64_t tileqr_dag_counts(int64_t p, int64_t q, int64_t strips, int64_t panels, int64_t counts[4])
+extern "C" int64_t tileqr_dag_counts(int64_t p, int64_t q, int64_t strips, int64_t panels, int64_t counts[5])
 {
-    int64_t c[4] = {0, 0, 0, 0};
+    int64_t c[NTYPE] = {0, 0, 0, 0, 0};
     if (p > 0 && q > 0 && strips > 0 && panels > 0) {
         const Grid g = make_grid((int)p, (int)q, (int)strips, (int)panels);
         for (int64_t id = 0; id < g.total; ++id) {
@@ -179,8 +179,8 @@ extern "C" int64_t tileqr_dag_counts(int64_t p, int64_t q, int64_t strips, int64
         }
     }
     if (counts)
-        for (int k = 0; k < 4; ++k) counts[k] = c[k];
-    return c[0] + c[1] + c[2] + c[3];
+        for (int k = 0; k < NTYPE; ++k) counts[k] = c[k];
+    return c[0] + c[1] + c[2] + c[3] + c[4];
 }
 
 // ------------------------------------------------------- DAG self-check
@@ -238,6 +238,88 @@ void task_access(const RegionMap &R, const Task &t, std::vector<int64_t> &rd, st
     }
 }
 
+// With PUPD tasks (one panel per strip) the regions are finer: block
+// (a, s) of tile (i, j) is rows of panel a in strip s, and a block on a
+// tile's diagonal (a == s) has two halves, its strict lower part (V on the
+// diagonal tile) and its upper part (R).  T_l of tile (i, k) is a region of
+// its own, so the reads of V and T by the update tasks are checked too.
+struct BlockMap {
+    int p, q, n;   // n = panels = strips per tile
+    int64_t blk(int i, int j, int s, int a, int h) const
+    {
+        return (((((int64_t)j * p + i) * n + s) * n + a) * 2) + h;
+    }
+    int64_t tblk(int k, int i, int l) const { return (int64_t)p * q * n * n * 2 + ((int64_t)k * p + i) * n + l; }
+    int64_t size() const { return (int64_t)p * q * n * n * 2 + (int64_t)std::min(p, q) * p * n; }
+    // Every half of blocks a0.. of strip s of tile (i, j).
+    void strip(std::vector<int64_t> &v, int i, int j, int s, int a0 = 0) const
+    {
+        for (int a = a0; a < n; ++a) {
+            v.push_back(blk(i, j, s, a, 0));
+            if (a == s) v.push_back(blk(i, j, s, a, 1));
+        }
+    }
+    // V of panel l of the diagonal tile (k, k): blocks below the diagonal
+    // block and its lower half.
+    void vpanel(std::vector<int64_t> &v, int k, int l) const
+    {
+        for (int a = l; a < n; ++a) v.push_back(blk(k, k, l, a, 0));
+    }
+};
+
+void task_access_pu(const BlockMap &B, const Task &t, std::vector<int64_t> &rd, std::vector<int64_t> &wr)
+{
+    rd.clear();
+    wr.clear();
+    const int k = t.k;
+    switch (t.type) {
+    case GEQRT:   // factor strip l of tile (k, k) from row l ib down; write T_l
+        B.strip(rd, k, k, t.l, t.l);
+        B.strip(wr, k, k, t.l, t.l);
+        wr.push_back(B.tblk(k, k, t.l));
+        break;
+    case TSQRT:   // R triangle of panel l, strip l of tile (i, k); write T_l
+        rd.push_back(B.blk(k, k, t.l, t.l, 1));
+        wr.push_back(B.blk(k, k, t.l, t.l, 1));
+        B.strip(rd, t.i, k, t.l);
+        B.strip(wr, t.i, k, t.l);
+        wr.push_back(B.tblk(k, t.i, t.l));
+        break;
+    case PUPD:
+        rd.push_back(B.tblk(k, t.i, t.l));
+        if (t.i == k) {
+            B.vpanel(rd, k, t.l);
+            B.strip(rd, k, k, t.s, t.l);
+            B.strip(wr, k, k, t.s, t.l);
+        } else {
+            B.strip(rd, t.i, k, t.l);
+            rd.push_back(B.blk(k, k, t.s, t.l, 0));
+            wr.push_back(B.blk(k, k, t.s, t.l, 0));
+            B.strip(rd, t.i, k, t.s);
+            B.strip(wr, t.i, k, t.s);
+        }
+        break;
+    case LARFB:
+        for (int l = 0; l < B.n; ++l) {
+            B.vpanel(rd, k, l);
+            rd.push_back(B.tblk(k, k, l));
+        }
+        B.strip(rd, k, t.j, t.s);
+        B.strip(wr, k, t.j, t.s);
+        break;
+    default:
+        for (int l = 0; l < B.n; ++l) {
+            B.strip(rd, t.i, k, l);
+            rd.push_back(B.tblk(k, t.i, l));
+        }
+        B.strip(rd, k, t.j, t.s);
+        B.strip(rd, t.i, t.j, t.s);
+        B.strip(wr, k, t.j, t.s);
+        B.strip(wr, t.i, t.j, t.s);
+        break;
+    }
+}
+
 }  // namespace
 
 extern "C" int tileqr_dag_selfcheck(int64_t p, int64_t q, int64_t strips, int64_t panels, int64_t trials,
@@ -246,25 +328,38 @@ extern "C" int tileqr_dag_selfcheck(int64_t p, int64_t q, int64_t strips, int64_
     if (p <= 0 || q <= 0 || strips <= 0 || panels <= 0) return 0;
     const Grid g = make_grid((int)p, (int)q, (int)strips, (int)panels);
     const RegionMap R{(int)p, (int)q, (int)strips, (int)panels};
+    const BlockMap B{(int)p, (int)q, (int)panels};
+    auto access = [&](const Task &t, std::vector<int64_t> &rd, std::vector<int64_t> &wr) {
+        if (g.pu) task_access_pu(B, t, rd, wr);
+        else task_access(R, t, rd, wr);
+    };
+    const int64_t nregion = g.pu ? B.size() : R.size();
     std::vector<int64_t> rd, wr;
     // Reference: Algorithm 2's loop order (a tile kernel's inner panels in
-    // order).
+    // order, each followed by its trailing update strip by strip).
     std::vector<int64_t> order;
+    auto panels_of = [&](int k, int i) {
+        for (int l = 0; l < g.np; ++l) {
+            order.push_back(id_panel(g, k, i, l));
+            if (g.pu)
+                for (int s = l + 1; s < g.np; ++s) order.push_back(id_pupd(g, k, i, l, s));
+        }
+    };
     for (int k = 0; k < g.kmax; ++k) {
-        for (int l = 0; l < g.np; ++l) order.push_back(id_geqrt(g, k, l));
+        panels_of(k, k);
         for (int j = k + 1; j < g.q; ++j)
             for (int s = 0; s < g.ns; ++s) order.push_back(id_larfb(g, k, j, s));
         for (int i = k + 1; i < g.p; ++i) {
-            for (int l = 0; l < g.np; ++l) order.push_back(id_tsqrt(g, k, i, l));
+            panels_of(k, i);
             for (int j = k + 1; j < g.q; ++j)
                 for (int s = 0; s < g.ns; ++s) order.push_back(id_ssrfb(g, k, i, j, s));
         }
     }
     std::vector<std::vector<int64_t>> expect(g.total);
     {
-        std::vector<int64_t> ver(R.size(), 0);
+        std::vector<int64_t> ver(nregion, 0);
         for (int64_t id : order) {
-            task_access(R, decode(g, id), rd, wr);
+            access(decode(g, id), rd, wr);
             for (int64_t r : rd) expect[id].push_back(ver[r]);
             for (int64_t w : wr) ++ver[w];
         }
@@ -281,7 +376,7 @@ extern "C" int tileqr_dag_selfcheck(int64_t p, int64_t q, int64_t strips, int64_
                 if (cnt[id] == 0) ready.push_back(id);
             }
         }
-        std::vector<int64_t> ver(R.size(), 0);
+        std::vector<int64_t> ver(nregion, 0);
         int64_t executed = 0;
         while (!ready.empty()) {
             const size_t pick = (size_t)(rng() % ready.size());
@@ -289,7 +384,7 @@ extern "C" int tileqr_dag_selfcheck(int64_t p, int64_t q, int64_t strips, int64_
             ready[pick] = ready.back();
             ready.pop_back();
             const Task t = decode(g, id);
-            task_access(R, t, rd, wr);
+            access(t, rd, wr);
             for (size_t e = 0; e < rd.size(); ++e)
                 if (ver[rd[e]] != expect[id][e]) return (int)(trial + 1);
             for (int64_t w : wr) ++ver[w];
@@ -380,6 +475,7 @@ int prepare_schedule(Workspace *W, SchedBufs &B, std::vector<MatDev> &mats, int 
         for (int k = 0; k < g.kmax; ++k) {
             const int64_t rows = g.p - k - 1;
             ntask += (int64_t)(1 + rows) * np + (int64_t)(1 + rows) * (g.q - k - 1) * ns;
+            if (g.pu) ntask += (int64_t)(1 + rows) * np * (np - 1) / 2;   // PUPD
             panel_flops += (4.0 / 3.0) * b3 + 2.0 * b3 * rows;
             all_flops += (double)(g.q - k - 1) * (2.0 * b3 + (4.0 * b3 + (double)ib * nb * nb) * rows);
         }

@@ -14,6 +14,14 @@
 //   TSQRT(k, i, l)      k < i < p, l < NP
 //   LARFB(k, j, s)      k < j < q, s < NS
 //   SSRFB(k, i, j, s)   k < i < p, k < j < q, s < NS
+//   PUPD(k, i, l, s)    k <= i < p, l < s < NP   (only when NP == NS > 1)
+// With one panel per strip (ib equal to the strip width), a panel task only
+// factors its panel and forms its T, and the application of that panel's
+// reflector to each later strip s of the same tile (GEQRT, i == k) or tile
+// pair (TSQRT, i > k: the panel's R rows and strip s of A_ik) is a task of
+// its own, PUPD.  The chain of panels of one tile then carries one
+// factorisation and one strip update per link instead of a whole trailing
+// update, and TSQRT(k, i+1, l) waits only for the R triangle of panel l.
 //
 // Data each task touches and the task that last wrote it (Algorithm 2 order):
 //   GEQRT(k,l)     tile (k,k) rows >= l ib  <- GEQRT(k, l-1), or SSRFB(k-1, k, k, *) for l = 0
@@ -24,6 +32,14 @@
 //   SSRFB(k,i,j,s) V_ik, T_ik                <- TSQRT(k, i, NP-1)
 //                  tile (k,j) strip s        <- SSRFB(k, i-1, j, s) or LARFB(k, j, s)
 //                  tile (i,j) strip s        <- SSRFB(k-1, i, j, s)
+// With PUPD tasks (strip s = panel s):
+//   GEQRT(k,l)     tile (k,k) strip l rows >= l ib <- PUPD(k, k, l-1, l), or SSRFB(k-1, k, k, 0) for l = 0
+//   TSQRT(k,i,l)   R_kk triangle of panel l  <- TSQRT(k, i-1, l) or GEQRT(k, l)
+//                  tile (i,k) strip l        <- PUPD(k, i, l-1, l), or SSRFB(k-1, i, k, 0) for l = 0
+//   PUPD(k,i,l,s)  V and T of panel l of tile (i,k) <- GEQRT(k, l) / TSQRT(k, i, l)
+//                  strip s of tile (i,k) (rows >= l ib for i = k) <- PUPD(k, i, l-1, s), or
+//                                          SSRFB(k-1, i, k, s) for l = 0
+//                  R rows of panel l in strip s (i > k) <- PUPD(k, i-1, l, s)
 // R rows of panel l are final for GEQRT(k, .) once its panel l is done: the
 // later panels touch only rows below them.  The TSQRT(k, ., l) tasks rewrite
 // only those rows of R_kk, so the panel chains of one step form a wavefront
@@ -49,14 +65,17 @@
 
 namespace tq {
 
-enum TaskType { GEQRT = 0, TSQRT = 1, LARFB = 2, SSRFB = 3 };
+enum TaskType { GEQRT = 0, TSQRT = 1, LARFB = 2, SSRFB = 3, PUPD = 4 };
+constexpr int NTYPE = 5;
 
 struct Grid {
     int32_t p, q, kmax, ns, np;   // tile rows, tile columns, steps, strips and panels per tile
-    int64_t baseT, baseL, baseS, total;  // id ranges of the four types
+    int32_t pu;                   // 1: panel updates are PUPD tasks (np == ns > 1)
+    int64_t baseT, baseL, baseS, baseU, total;  // id ranges of the five types
 };
 
-// One task; l is the inner panel of GEQRT and TSQRT (0 for the strip tasks).
+// One task; l is the inner panel of GEQRT, TSQRT and PUPD (0 for the strip
+// tasks), s the strip of LARFB, SSRFB and PUPD; PUPD has j = k.
 struct Task {
     int32_t type, k, i, j, s, l;
 };
@@ -69,10 +88,12 @@ TQ_HD Grid make_grid(int32_t p, int32_t q, int32_t ns, int32_t np)
     g.kmax = p < q ? p : q;
     g.ns = ns;
     g.np = np;
+    g.pu = (np > 1 && np == ns) ? 1 : 0;
     g.baseT = (int64_t)g.kmax * np;
     g.baseL = g.baseT + (int64_t)g.kmax * p * np;
     g.baseS = g.baseL + (int64_t)g.kmax * q * ns;
-    g.total = g.baseS + (int64_t)g.kmax * p * q * ns;
+    g.baseU = g.baseS + (int64_t)g.kmax * p * q * ns;
+    g.total = g.baseU + (g.pu ? (int64_t)g.kmax * p * np * np : 0);
     return g;
 }
 
@@ -87,6 +108,15 @@ TQ_HD int64_t id_larfb(const Grid &g, int k, int j, int s)
 TQ_HD int64_t id_ssrfb(const Grid &g, int k, int i, int j, int s)
 {
     return g.baseS + (((int64_t)k * g.p + i) * g.q + j) * g.ns + s;
+}
+TQ_HD int64_t id_pupd(const Grid &g, int k, int i, int l, int s)
+{
+    return g.baseU + (((int64_t)k * g.p + i) * g.np + l) * g.np + s;
+}
+// The panel task of panel l of tile (i, k): GEQRT on the diagonal tile.
+TQ_HD int64_t id_panel(const Grid &g, int k, int i, int l)
+{
+    return i == k ? id_geqrt(g, k, l) : id_tsqrt(g, k, i, l);
 }
 
 TQ_HD Task decode(const Grid &g, int64_t id)
@@ -114,7 +144,7 @@ TQ_HD Task decode(const Grid &g, int64_t id)
         t.j = (int32_t)(r % g.q);
         t.k = (int32_t)(r / g.q);
         t.i = t.k;
-    } else {
+    } else if (id < g.baseU) {
         int64_t r = id - g.baseS;
         t.type = SSRFB;
         t.s = (int32_t)(r % g.ns);
@@ -123,6 +153,16 @@ TQ_HD Task decode(const Grid &g, int64_t id)
         r /= g.q;
         t.i = (int32_t)(r % g.p);
         t.k = (int32_t)(r / g.p);
+    } else {
+        int64_t r = id - g.baseU;
+        t.type = PUPD;
+        t.s = (int32_t)(r % g.np);
+        r /= g.np;
+        t.l = (int32_t)(r % g.np);
+        r /= g.np;
+        t.i = (int32_t)(r % g.p);
+        t.k = (int32_t)(r / g.p);
+        t.j = t.k;
     }
     return t;
 }
@@ -135,7 +175,8 @@ TQ_HD bool valid(const Grid &g, const Task &t)
     case GEQRT: return true;
     case TSQRT: return t.i > t.k && t.i < g.p;
     case LARFB: return t.j > t.k && t.j < g.q && t.s < g.ns;
-    default: return t.i > t.k && t.i < g.p && t.j > t.k && t.j < g.q && t.s < g.ns;
+    case SSRFB: return t.i > t.k && t.i < g.p && t.j > t.k && t.j < g.q && t.s < g.ns;
+    default: return g.pu && t.i >= t.k && t.i < g.p && t.l < t.s && t.s < g.np;
     }
 }
 
@@ -143,11 +184,15 @@ TQ_HD bool valid(const Grid &g, const Task &t)
 TQ_HD int32_t indegree(const Grid &g, const Task &t)
 {
     const int prev = t.k > 0 ? 1 : 0;
+    // Without PUPD the first panel waits for every strip of its tile, with
+    // them for strip 0 only.
+    const int first = g.pu ? prev : prev * g.ns;
     switch (t.type) {
-    case GEQRT: return t.l > 0 ? 1 : prev * g.ns;
-    case TSQRT: return 1 + (t.l > 0 ? 1 : prev * g.ns);
+    case GEQRT: return t.l > 0 ? 1 : first;
+    case TSQRT: return 1 + (t.l > 0 ? 1 : first);
     case LARFB: return 1 + prev;
-    default: return 2 + prev;
+    case SSRFB: return 2 + prev;
+    default: return 1 + (t.i > t.k ? 1 : 0) + (t.l > 0 ? 1 : prev);
     }
 }
 
@@ -157,9 +202,8 @@ TQ_HD int64_t next_step_consumer(const Grid &g, int k, int i, int j, int s)
 {
     const int k1 = k + 1;
     if (k1 >= g.kmax) return -1;
-    if (i == k1 && j == k1) return id_geqrt(g, k1, 0);
+    if (j == k1) return (g.pu && s > 0) ? id_pupd(g, k1, i, 0, s) : id_panel(g, k1, i, 0);
     if (i == k1) return id_larfb(g, k1, j, s);
-    if (j == k1) return id_tsqrt(g, k1, i, 0);
     return id_ssrfb(g, k1, i, j, s);
 }
 
@@ -168,10 +212,23 @@ TQ_HD int64_t next_step_consumer(const Grid &g, int k, int i, int j, int s)
 // n-th.  Pure functions of the task, so the threads of a workgroup can
 // release successors in parallel.  A panel task lists the next panel of its
 // own tile first, then the same panel of the next tile, then the strips.
+// With PUPD tasks a panel task lists the same panel of the next tile, then
+// its strip updates, then (last panel) the strips; a PUPD lists the next
+// panel task of its strip (or the strip's update by the next panel), then
+// the same update of the next tile.
 TQ_HD int32_t nsucc(const Grid &g, const Task &t)
 {
     const int strips = (g.q - t.k - 1) * g.ns;
     const int more = t.l + 1 < g.np ? 1 : 0;
+    if (g.pu) {
+        const int last = more ? 0 : strips;
+        switch (t.type) {
+        case GEQRT: return (t.k + 1 < g.p ? 1 : 0) + (g.np - 1 - t.l) + last;
+        case TSQRT: return (t.i + 1 < g.p ? 1 : 0) + (g.np - 1 - t.l) + last;
+        case PUPD: return 1 + (t.i + 1 < g.p ? 1 : 0);
+        default: break;
+        }
+    }
     switch (t.type) {
     case GEQRT: return more + (t.k + 1 < g.p ? 1 : 0) + (more ? 0 : strips);
     case TSQRT: return more + (t.i + 1 < g.p ? 1 : 0) + (more ? 0 : strips);
@@ -186,6 +243,20 @@ TQ_HD int32_t nsucc(const Grid &g, const Task &t)
 TQ_HD int64_t succ(const Grid &g, const Task &t, int32_t n)
 {
     const bool more = t.l + 1 < g.np;
+    if (g.pu && t.type != LARFB && t.type != SSRFB) {
+        if (t.type == PUPD) {
+            if (n == 0) return t.s == t.l + 1 ? id_panel(g, t.k, t.i, t.l + 1) : id_pupd(g, t.k, t.i, t.l + 1, t.s);
+            return id_pupd(g, t.k, t.i + 1, t.l, t.s);
+        }
+        if (t.i + 1 < g.p) {
+            if (n == 0) return id_tsqrt(g, t.k, t.i + 1, t.l);
+            --n;
+        }
+        if (n < g.np - 1 - t.l) return id_pupd(g, t.k, t.i, t.l, t.l + 1 + n);
+        n -= g.np - 1 - t.l;
+        return t.type == GEQRT ? id_larfb(g, t.k, t.k + 1 + n / g.ns, n % g.ns)
+                               : id_ssrfb(g, t.k, t.i, t.k + 1 + n / g.ns, n % g.ns);
+    }
     switch (t.type) {
     case GEQRT:
         if (more) {
@@ -229,7 +300,8 @@ TQ_HD int priority_level(const Task &t)
     case GEQRT: return 0;
     case TSQRT: return 1;
     case LARFB: return t.j == t.k + 1 ? 2 : 3;
-    default: return t.j == t.k + 1 ? 2 : 4;
+    case SSRFB: return t.j == t.k + 1 ? 2 : 4;
+    default: return 2;   // PUPD: on the panel chain
     }
 }
 
@@ -272,6 +344,17 @@ inline void count_queue_tasks(const Grid &g, int mat, int64_t *counts)
                 t.i = k + 1;
                 counts[queue_of(t, g.ns, mat)] += rows;   // the queue does not depend on i
             }
+        if (g.pu) {
+            // PUPD(k, i, l, s) for k <= i < p, l < s: s (i, l) pairs per row
+            for (int s = 1; s < g.np; ++s) {
+                Task t;
+                t.type = PUPD;
+                t.k = t.j = t.i = k;
+                t.l = 0;
+                t.s = s;
+                counts[queue_of(t, g.ns, mat)] += (rows + 1) * s;
+            }
+        }
     }
 }
 
@@ -285,7 +368,8 @@ TQ_HD double task_flops(const Task &t, int nb, int ib, int ns, int np)
     case GEQRT: return 4.0 * b * b * b / 3.0 / np;
     case TSQRT: return 2.0 * b * b * b / np;
     case LARFB: return 2.0 * b * b * b / ns;
-    default: return (4.0 * b * b * b + s * b * b) / ns;
+    case SSRFB: return (4.0 * b * b * b + s * b * b) / ns;
+    default: return 4.0 * b * s * s;   // PUPD: one ib-wide panel on one strip (ib = strip width)
     }
 }
 

@@ -1002,9 +1002,11 @@ __device__ __forceinline__ void panel_trailing(Smem<NB, IB> &sm, gdouble *tile, 
 // already in sm.P (rows from l ib), chained there by panel l-1; `chain`:
 // leave the next panel in sm.P (the strip next to this panel is then not
 // written back below the next panel's first row).  With both false the
-// panel is a self-contained task that reads and writes only memory.
+// panel is a self-contained task that reads and writes only memory.  Without
+// `trailing` the columns right of the panel are left to PUPD tasks.
 template <int NB, int IB, int PREC>
-__device__ __forceinline__ void geqrt_panel(Smem<NB, IB> &sm, const MatDev &M, int k, int l, bool from_lds, bool chain)
+__device__ __forceinline__ void geqrt_panel(Smem<NB, IB> &sm, const MatDev &M, int k, int l, bool from_lds, bool chain,
+                                            bool trailing = true)
 {
     using C = Cfg<NB, IB>;
     gdouble *tkk = tile_ptr(M, NB, k, k);
@@ -1035,6 +1037,7 @@ __device__ __forceinline__ void geqrt_panel(Smem<NB, IB> &sm, const MatDev &M, i
     __syncthreads();
     build_t<NB, IB>(sm, c0, Tk + l * IB * IB);
     __syncthreads();
+    if (!trailing) return;
     panel_trailing<NB, IB, false, PREC>(sm, tkk, nullptr, c0, chain);
     __syncthreads();
 }
@@ -1052,11 +1055,11 @@ __device__ __forceinline__ void task_geqrt(Smem<NB, IB> &sm, const MatDev &M, in
 // Inner panel l of DTSQRT(R_kk, A_ik) -> (R_kk, V_ik, T_ik): factor
 // [R_kk rows of panel l; columns [l ib, (l+1) ib) of A_ik], write them and
 // T_l, and apply the reflector to the columns right of the panel (rows of
-// the panel in R_kk, all rows of A_ik).  `from_lds` / `chain` as for
-// geqrt_panel.
+// the panel in R_kk, all rows of A_ik).  `from_lds` / `chain` / `trailing`
+// as for geqrt_panel.
 template <int NB, int IB, int PREC>
 __device__ __forceinline__ void tsqrt_panel(Smem<NB, IB> &sm, const MatDev &M, int k, int i, int l, bool from_lds,
-                                            bool chain)
+                                            bool chain, bool trailing = true)
 {
     using C = Cfg<NB, IB>;
     gdouble *tkk = tile_ptr(M, NB, k, k);
@@ -1099,6 +1102,7 @@ __device__ __forceinline__ void tsqrt_panel(Smem<NB, IB> &sm, const MatDev &M, i
     }
     build_t<NB, IB>(sm, 0, Ti + l * IB * IB);
     __syncthreads();
+    if (!trailing) return;
     panel_trailing<NB, IB, true, PREC>(sm, tik, tkk, c0, chain);
     __syncthreads();
 }
@@ -1227,8 +1231,35 @@ __device__ __forceinline__ void task_ssrfb(Smem<NB, IB> &sm, const MatDev &M, in
                                  tile_ptr(M, NB, i, j), NB, s * WS);
 }
 
+// PUPD(k, i, l, s): one strip of a panel task's trailing update as a task of
+// its own.  The block reflector of inner panel l of tile (i, k) (V read back
+// from the tile, T_l from its T blocks) is applied to strip s of the same
+// tile, rows from l ib on, for the diagonal tile (GEQRT, i == k), and for
+// i > k (TSQRT) to the pair [R rows of panel l in strip s; strip s of A_ik].
+// Same operands and the same product code as the panel task's own trailing
+// update, so the result does not depend on which of the two ran it.
+template <int NB, int IB, int PREC>
+__device__ __forceinline__ void task_pupd(Smem<NB, IB> &sm, const MatDev &M, int k, int i, int l, int s)
+{
+    using C = Cfg<NB, IB>;
+    const bool diag = i == k;
+    gdouble *tik = tile_ptr(M, NB, i, k);
+    const int c0 = l * IB, r0 = diag ? c0 : 0, col0 = s * WS;
+    Stage<NB, IB> S;
+    stage_load_rows<NB, IB>(S, tik, c0, r0, tblock_ptr(M, NB, IB, k, i) + l * IB * IB);
+    Strip<NB, IB> X;
+    load_strip<NB, IB>(X, tik, NB, col0, CB);
+    gdouble *top = diag ? nullptr : tile_ptr(M, NB, k, k) + (size_t)c0 * NB + col0;
+    double tv[C::EPT] = {};
+    if (!diag) load_top<NB, IB>(tv, top, NB, WS);
+    stage_store_rows<NB, IB>(sm, S, r0, diag, c0);
+    if constexpr (PREC == PREC_FP64) apply_panel<NB, IB>(sm, X, r0, top, NB, CB, tv);
+    else apply_panel_mx<NB, IB, PREC>(sm, X, r0, top, NB, tv);
+    store_strip<NB, IB>(X, tik, NB, col0, CB, r0);
+}
+
 // Workers come in two roles: ROLE_PANEL runs GEQRT and TSQRT (queue
-// levels 0-1), ROLE_UPDATE runs LARFB and SSRFB (levels 2..NLEVEL-1).  The
+// levels 0-1), ROLE_UPDATE runs LARFB, SSRFB and PUPD (levels 2..NLEVEL-1).  The
 // persistent kernel gives the panel role to its lowest workgroup indices,
 // which the dispatcher makes resident first.
 enum { ROLE_PANEL = 0, ROLE_UPDATE = 1 };
@@ -1238,16 +1269,20 @@ enum { ROLE_PANEL = 0, ROLE_UPDATE = 1 };
 template <int NB, int IB, int ROLE, int PREC, bool SPLIT>
 __device__ __forceinline__ void run_task(Smem<NB, IB> &sm, const MatDev &M, const Task &t)
 {
+    // One panel per strip: the panel tasks leave their trailing updates to
+    // PUPD tasks (the grid has them exactly then).
+    constexpr bool PU = SPLIT && Cfg<NB, IB>::NPAN == Cfg<NB, IB>::NS && Cfg<NB, IB>::NPAN > 1;
     if constexpr (ROLE == ROLE_PANEL) {
         if constexpr (SPLIT) {
-            if (t.type == GEQRT) geqrt_panel<NB, IB, PREC>(sm, M, t.k, t.l, false, false);
-            else tsqrt_panel<NB, IB, PREC>(sm, M, t.k, t.i, t.l, false, false);
+            if (t.type == GEQRT) geqrt_panel<NB, IB, PREC>(sm, M, t.k, t.l, false, false, !PU);
+            else tsqrt_panel<NB, IB, PREC>(sm, M, t.k, t.i, t.l, false, false, !PU);
         } else {
             if (t.type == GEQRT) task_geqrt<NB, IB, PREC>(sm, M, t.k);
             else task_tsqrt<NB, IB, PREC>(sm, M, t.k, t.i);
         }
     } else {
         if (t.type == LARFB) task_larfb<NB, IB, PREC>(sm, M, t.k, t.j, t.s);
+        else if (PU && t.type == PUPD) task_pupd<NB, IB, PREC>(sm, M, t.k, t.i, t.l, t.s);
         else task_ssrfb<NB, IB, PREC>(sm, M, t.k, t.i, t.j, t.s);
     }
 }
@@ -1511,7 +1546,7 @@ __device__ __forceinline__ void worker_loop(Smem<NB, IB> &sm, const SchedDev &S)
                                                           __HIP_MEMORY_SCOPE_AGENT);
                 if (e < S.trace_cap) {
                     int64_t *ev = S.trace + (size_t)e * TRACE_WORDS;
-                    ev[0] = t.type; ev[1] = t.k; ev[2] = t.i; ev[3] = t.j;
+                    ev[0] = t.type; ev[1] = t.k; ev[2] = t.i; ev[3] = t.type == PUPD ? t.l : t.j;
                     ev[4] = t.type <= TSQRT ? t.l : t.s;
                     ev[5] = ((int64_t)mi << 20) | (ROLE << 16) | blockIdx.x;
                     ev[6] = (int64_t)s_tpop;

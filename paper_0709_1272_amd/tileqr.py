@@ -166,7 +166,7 @@ def flops_tiled(m, n, nb, ib):
 
 
 def dag_counts(p, q, strips=1, panels=1):
-    c = (ctypes.c_int64 * 4)()
+    c = (ctypes.c_int64 * 5)()
     total = _L.tileqr_dag_counts(p, q, strips, panels, c)
     return total, list(c)
 

@@ -38,7 +38,7 @@ def test_dag_counts_p3q3():
     tq = _tq()
     total, c = tq.dag_counts(3, 3, 1)
     assert total == 14
-    assert c == [3, 3, 3, 5]
+    assert c == [3, 3, 3, 5, 0]
 
 
 @pytest.mark.parametrize("p,q", [(1, 1), (4, 4), (8, 8), (32, 32), (256, 4), (3, 7), (7, 3)])
@@ -50,9 +50,14 @@ def test_dag_counts_closed_form(p, q):
     larfb = sum(q - k - 1 for k in range(kmax))
     ssrfb = sum((p - k - 1) * (q - k - 1) for k in range(kmax))
     for strips in (1, 8):
-        for panels in (1, 4):
+        for panels in (1, 4, 8):
             total, c = tq.dag_counts(p, q, strips, panels)
-            assert c == [geqrt * panels, tsqrt * panels, larfb * strips, ssrfb * strips]
+            # One panel per strip: every tile of column k gets, for each
+            # panel l, one PUPD task per later strip.
+            pupd = (sum(p - k for k in range(kmax)) * panels * (panels - 1) // 2
+                    if panels == strips and panels > 1 else 0)
+            assert c == [geqrt * panels, tsqrt * panels, larfb * strips, ssrfb * strips, pupd]
+            assert total == sum(c)
 
 
 @pytest.mark.parametrize("p,q,strips,trials", [(1, 1, 1, 3), (3, 3, 1, 50), (3, 3, 4, 50), (5, 2, 2, 50),
