@@ -125,16 +125,15 @@ extern "C" int tileqr_choose_blocking(int64_t m, int64_t n, int precision, int64
         }
     }
     // Measured with one task per inner panel (the automatic split for up to
-    // 32 tile steps): tall matrices and large ones run best with 256 x 256
-    // tiles (more work per panel task on the chains that bound them), and
-    // tall ones up to 2048 columns with ib = 16 (a finer panel wavefront:
-    // 65536 x 1024 takes 20 ms instead of 29); near-square ones up to 4096
-    // run best with 128, tiny ones with 64.
+    // 32 tile steps) and, at ib = 32, PUPD tasks for the in-tile updates:
+    // tall matrices and all but small ones run best with 256 x 256 tiles and
+    // ib = 32 (65536 x 1024: 15.0 ms against 17.7 with ib = 16 and 18.4 with
+    // nb = 128); near-square ones up to 2048 with 128 / 16 (2048^2: 3.6 ms
+    // against 3.9 with 256 / 32), tiny ones with 64 / 16.
     const int64_t k = std::min(m, n);
     int64_t b = 256, s = 32;
     if (k <= 256) { b = 64; s = 16; }
-    else if (m >= 4 * n) s = k <= 2048 ? 16 : 32;
-    else if (k <= 4096 && std::max(m, n) < 4 * k) { b = 128; s = 32; }
+    else if (m < 4 * n && n < 4 * m && k <= 2048) { b = 128; s = 16; }
     if (precision != TILEQR_FP64) s = 32;   // the split products take ib = 32
     if (nb) *nb = b;
     if (ib) *ib = s;

@@ -98,16 +98,18 @@ def test_blocking_rules():
 
 def test_automatic_blocking():
     # The untuned choice (the tuner's entries override it; none exist in a
-    # fresh process): tiny -> 64/16, tall up to 2048 columns -> 256/16, tall
-    # beyond -> 256/32, near-square up to 4096 -> 128/32, larger -> 256/32;
-    # the split modes always take ib = 32.
+    # fresh process): tiny -> 64/16, near-square up to 2048 -> 128/16, tall
+    # and larger -> 256/32; the split modes always take ib = 32.
     tq = _tq()
     assert tq.choose_blocking(200, 100) == (64, 16)
-    assert tq.choose_blocking(65536, 1024) == (256, 16)
-    assert tq.choose_blocking(16384, 2048) == (256, 16)
+    assert tq.choose_blocking(2048, 2048) == (128, 16)
+    assert tq.choose_blocking(1024, 1500) == (128, 16)
+    assert tq.choose_blocking(65536, 1024) == (256, 32)
+    assert tq.choose_blocking(16384, 2048) == (256, 32)
     assert tq.choose_blocking(32768, 4096) == (256, 32)
-    assert tq.choose_blocking(4096, 4096) == (128, 32)
+    assert tq.choose_blocking(4096, 4096) == (256, 32)
     assert tq.choose_blocking(8192, 8192) == (256, 32)
+    assert tq.choose_blocking(2048, 2048, tq.FP16X2) == (128, 32)
     assert tq.choose_blocking(65536, 1024, tq.BF16X3) == (256, 32)
     assert tq.choose_blocking(200, 100, tq.FP16X2) == (64, 32)
     for m, n in ((1, 1), (300, 7000), (100000, 64)):
