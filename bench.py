@@ -23,7 +23,9 @@ them with --no-extras):
               tileqr_tune, run beforehand; the captured graph replayed).
 
 Prints one JSON line.  Flags: --gpus N (only 1 is supported: the build runs
-on one GPU), --steps K, --warmup W, --no-cpu-baseline, --no-extras.
+on one GPU), --steps K, --warmup W, --no-cpu-baseline, --no-extras,
+--extras LIST (a comma-separated subset of mixed_ls, mixed_ls_square,
+batched; default all three).
 """
 import argparse
 import json
@@ -194,7 +196,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default="mixed_ls,mixed_ls_square,batched",
+                    help="comma-separated extra measurements to run (default: all three)")
     args = ap.parse_args()
+    extras = [] if args.no_extras else [e for e in args.extras.split(",") if e]
+    for e in extras:
+        if e not in ("mixed_ls", "mixed_ls_square", "batched"):
+            ap.error(f"unknown extra measurement {e!r}")
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported; this build factors on one GPU "
               f"(run with --gpus 1)", file=sys.stderr)
@@ -267,9 +275,11 @@ def main():
                      "kernel": f"k_worker<{NB},{IB}>",
                      "algorithmic": f"{flops:.4e} flops per launch (2mn^2-2n^3/3)"},
     }
-    if not args.no_extras:
+    if "mixed_ls" in extras:
         out["mixed_ls"] = mixed_ls(tq, torch, dev, stream)
+    if "mixed_ls_square" in extras:
         out["mixed_ls_square"] = mixed_ls_square(tq, torch, dev, stream)
+    if "batched" in extras:
         out["batched"] = batched(tq, torch, dev, stream)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
