@@ -169,7 +169,7 @@ def batched(tq, torch, dev, st):
     Ap = [work.data_ptr() + 8 * int(o) for o in off[:-1]]
     Tp = [T.data_ptr() + 8 * int(o) for o in toff[:-1]]
     t0 = time.perf_counter()
-    tune = tq.tune(ms, ns, tq.FP64, trials=1)
+    tune = tq.tune(ms, ns, tq.FP64, trials=2)
     tune_s = time.perf_counter() - t0
     times = []
     for r in range(4):

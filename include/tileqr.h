@@ -250,8 +250,9 @@ int tileqr_factor_batched(int64_t batch, const int64_t *m, const int64_t *n,
  * Autotuner: times trial factorisations of synthetic matrices with the given
  * shapes (batch >= 1; batch = 1 tunes one m x n matrix) in the given
  * precision on the current device, over every supported (nb, ib) and a few
- * splits of the workgroups between the panel and update roles, `trials`
- * runs each (best time counts).  The fastest choice is written to *best and
+ * splits of the workgroups between the panel and update roles, one untimed
+ * warm-up run and then `trials` timed runs each (best time counts).  The
+ * fastest choice is written to *best and
  * remembered for this multiset of shapes and precision for the rest of the
  * process: tileqr_factor_batched with nb = ib = NULL and tileqr_solve_ls /
  * tileqr_choose_blocking with automatic blocking use it.  Allocates scratch

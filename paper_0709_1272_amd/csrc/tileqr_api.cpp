@@ -406,7 +406,7 @@ extern "C" int tileqr_dag_selfcheck(int64_t p, int64_t q, int64_t strips, int64_
         int64_t a[NQUEUE] = {0}, b[NQUEUE] = {0};
         for (int64_t id = 0; id < g.total; ++id) {
             const Task t = decode(g, id);
-            if (valid(g, t)) ++a[queue_of(t, g.ns, g.np, mat)];
+            if (valid(g, t)) ++a[queue_of(t, g.ns, mat)];
         }
         count_queue_tasks(g, mat, b);
         for (int l = 0; l < NQUEUE; ++l)

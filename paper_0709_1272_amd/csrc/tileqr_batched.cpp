@@ -382,6 +382,16 @@ extern "C" int tileqr_tune(int64_t batch, const int64_t *m, const int64_t *n, in
             o.panel_workers = pw;
             o.flags = TILEQR_FLAG_NO_GRAPH;
             double bestms = -1.0;
+            // One untimed run first: the first launch of a kernel
+            // instantiation and the growth of the workspace would otherwise
+            // weigh on whichever configuration meets them first.
+            if ((rc = launch_fill_uniform((double *)Abuf.ptr, elems, 1233, st)) != hipSuccess) {
+                rc = hip_fail((hipError_t)rc, "fill");
+                break;
+            }
+            if ((rc = run_batched(W, batch, m, n, Ap.data(), lda.data(), nbv.data(), ibv.data(), Tp.data(), o, st)))
+                break;
+            if ((rc = check_status(W, (int *)W->status.ptr, st))) break;
             for (int r = 0; r < trials && rc == 0; ++r) {
                 if ((rc = launch_fill_uniform((double *)Abuf.ptr, elems, 1234 + r, st)) != hipSuccess) {
                     rc = hip_fail((hipError_t)rc, "fill");

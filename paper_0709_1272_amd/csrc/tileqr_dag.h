@@ -291,20 +291,16 @@ TQ_HD int64_t succ(const Grid &g, const Task &t, int32_t n)
 // tasks in the ready state (Section 4).  Inside the LARFB/SSRFB levels the
 // same criterion singles out the updates of tile column k+1: they feed the
 // next step's GEQRT and TSQRT chain, whose fan-out is the widest of the
-// graph, so they form their own level ahead of the other updates.  With
-// panel tasks (np > 1) a step's panel chain is short enough that the step
-// after next soon waits for its column as well, so the updates of column
-// k+2 get the next level.
-constexpr int NLEVEL = 6;
+// graph, so they form their own level ahead of the other updates.
+constexpr int NLEVEL = 5;
 
-TQ_HD int priority_level(const Task &t, int np)
+TQ_HD int priority_level(const Task &t)
 {
-    const int near = t.j == t.k + 1 ? 2 : (np > 1 && t.j == t.k + 2 ? 3 : 0);
     switch (t.type) {
     case GEQRT: return 0;
     case TSQRT: return 1;
-    case LARFB: return near ? near : 4;
-    case SSRFB: return near ? near : 5;
+    case LARFB: return t.j == t.k + 1 ? 2 : 3;
+    case SSRFB: return t.j == t.k + 1 ? 2 : 4;
     default: return 2;   // PUPD: on the panel chain
     }
 }
@@ -319,9 +315,9 @@ constexpr int NQUEUE = 2 + (NLEVEL - 2) * NXQ;
 
 TQ_HD int queue_index(int level, int x) { return level < 2 ? level : 2 + (level - 2) * NXQ + x; }
 
-TQ_HD int queue_of(const Task &t, int ns, int np, int mat)
+TQ_HD int queue_of(const Task &t, int ns, int mat)
 {
-    const int level = priority_level(t, np);
+    const int level = priority_level(t);
     const int x = (int)(((unsigned)mat * 5u + (unsigned)t.j * (unsigned)ns + (unsigned)t.s) % NXQ);
     return queue_index(level, x);
 }
@@ -343,10 +339,10 @@ inline void count_queue_tasks(const Grid &g, int mat, int64_t *counts)
                 t.s = s;
                 t.i = k;
                 t.type = LARFB;
-                counts[queue_of(t, g.ns, g.np, mat)] += 1;
+                counts[queue_of(t, g.ns, mat)] += 1;
                 t.type = SSRFB;
                 t.i = k + 1;
-                counts[queue_of(t, g.ns, g.np, mat)] += rows;   // the queue does not depend on i
+                counts[queue_of(t, g.ns, mat)] += rows;   // the queue does not depend on i
             }
         if (g.pu) {
             // PUPD(k, i, l, s) for k <= i < p, l < s: s (i, l) pairs per row
@@ -356,7 +352,7 @@ inline void count_queue_tasks(const Grid &g, int mat, int64_t *counts)
                 t.k = t.j = t.i = k;
                 t.l = 0;
                 t.s = s;
-                counts[queue_of(t, g.ns, g.np, mat)] += (rows + 1) * s;
+                counts[queue_of(t, g.ns, mat)] += (rows + 1) * s;
             }
         }
     }

@@ -1525,7 +1525,7 @@ __device__ __forceinline__ void worker_loop(Smem<NB, IB> &sm, const SchedDev &S)
                         ready = true;
                         mine = (nt.type == GEQRT || nt.type == TSQRT) == (ROLE == ROLE_PANEL);
                         sgid = M.task_base + sl;
-                        queue = queue_of(nt, S.ns, g.np, mi);
+                        queue = queue_of(nt, S.ns, mi);
                     }
                 }
                 const uint64_t cand = __ballot(ready && mine);
