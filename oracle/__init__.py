@@ -6,7 +6,7 @@ library: the two share no code.
 
 ``oracle.c`` holds the arithmetic (unblocked Householder QR, application of
 Q and Q^T, back substitution, least squares).  This module marshals numpy
-arrays into it and adds the error measures used to judge a factorisation:
+arrays into it and adds the error measures used to assess a factorisation:
 
 * ``beta_fact``  = ||A - Q [R; 0]||_F / ||A||_F       (factorisation residual)
 * ``beta_orth``  = ||Q_thin^T Q_thin - I_n||_F        (loss of orthogonality)
