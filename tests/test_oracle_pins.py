@@ -266,3 +266,108 @@ def test_mutants_are_caught():
         assert not survivors, f"planted mistakes not caught by any pin: {survivors}"
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
+
+
+# ------------------------------------------------------------ metric pins
+# The error measures of oracle/metrics.py against values worked out by hand
+# from their definitions (tests/golden/metrics.txt).  Each check takes a
+# namespace holding the metric functions, so that the mutation test below can
+# run the same checks on a copy with a planted mistake.
+
+def _mat(g, key, rows):
+    v = np.array(g[key])
+    return v.reshape(rows, -1)
+
+
+def check_metric_r_diff(M):
+    g = load_golden("metrics.txt")
+    for case in ("rdiff1", "rdiff2", "rdiff3"):
+        got = M.r_diff(_mat(g, case + "_test", 2), _mat(g, case + "_ref", 2))
+        assert abs(got - g[case][0]) <= 4 * EPS, (case, got, g[case][0])
+
+
+def check_metric_beta_orth(M):
+    g = load_golden("metrics.txt")
+    for case in ("orth1", "orth2"):
+        got = M.beta_orth(_mat(g, case + "_q", 3))
+        assert abs(got - g[case][0]) <= 8 * EPS * max(1.0, g[case][0]), (case, got)
+
+
+def check_metric_beta_fact(M):
+    g = load_golden("metrics.txt")
+    for case in ("fact1", "fact2"):
+        got = M.beta_fact(_mat(g, case + "_a", 2), _mat(g, case + "_qr", 2))
+        assert abs(got - g[case][0]) <= 4 * EPS, (case, got)
+
+
+def check_metric_eta_inf(M):
+    g = load_golden("metrics.txt")
+    A, x = _mat(g, "inf1_a", 2), np.array(g["inf1_x"])
+    got = M.eta_inf(A, x, np.array(g["inf1_b"]))
+    assert abs(got - g["inf1"][0]) <= 4 * EPS, got
+    assert M.eta_inf(A, x, np.array(g["inf2_b"])) == g["inf2"][0]
+
+
+def check_metric_eta_ls(M):
+    g = load_golden("metrics.txt")
+    A, b = _mat(g, "ls1_a", 3), np.array(g["ls1_b"])
+    assert M.eta_ls(A, np.array(g["ls1_xopt"]), b) == g["ls1_xopt_eta"][0]
+    got = M.eta_ls(A, np.array(g["ls1_x"]), b)
+    assert abs(got - g["ls1"][0]) <= 4 * EPS, got
+    A, b = _mat(g, "ls2_a", 3), np.array(g["ls2_b"])
+    got = M.eta_ls(A, np.array(g["ls2_x"]), b)
+    assert abs(got - g["ls2"][0]) <= 1e-14, got
+    assert M.eta_ls(A, np.array(g["ls2_xopt"]), b) <= 1e-16
+
+
+METRIC_BATTERY = [check_metric_r_diff, check_metric_beta_orth, check_metric_beta_fact,
+                  check_metric_eta_inf, check_metric_eta_ls]
+
+
+@pytest.mark.parametrize("check", METRIC_BATTERY, ids=lambda f: f.__name__)
+def test_metric_pin(check):
+    from oracle import metrics
+    check(metrics)
+
+
+METRIC_MUTANTS = {
+    "unsigned_rows": ("Rt = R_test[:k] * row_signs(R_test)[:k, None]", "Rt = R_test[:k]"),
+    "unsigned_ref": ("Rr = R_ref[:k] * row_signs(R_ref)[:k, None]", "Rr = R_ref[:k]"),
+    "sign_of_zero": ("d[d == 0] = 1.0", "pass"),
+    "r_diff_unnormalised": ("return float(np.linalg.norm(Rt - Rr) / (den if den > 0 else 1.0))",
+                            "return float(np.linalg.norm(Rt - Rr))"),
+    "orth_outer_gram": ("np.linalg.norm(Qthin.T @ Qthin - np.eye(n))",
+                        "np.linalg.norm(Qthin @ Qthin.T - np.eye(Qthin.shape[0]))"),
+    "orth_two_norm": ("np.linalg.norm(Qthin.T @ Qthin - np.eye(n))", "np.linalg.norm(Qthin.T @ Qthin - np.eye(n), 2)"),
+    "fact_wrong_denominator": ("den = np.linalg.norm(A)\n    return float(np.linalg.norm(A - QR)",
+                               "den = np.linalg.norm(QR)\n    return float(np.linalg.norm(A - QR)"),
+    "inf_one_norm_of_a": ("np.linalg.norm(A, np.inf) * np.linalg.norm(x, np.inf)",
+                          "np.linalg.norm(A, 1) * np.linalg.norm(x, np.inf)"),
+    "inf_two_norm_of_r": ("float(np.linalg.norm(r, np.inf) / den)", "float(np.linalg.norm(r) / den)"),
+    "inf_two_norm_of_x": ("np.linalg.norm(A, np.inf) * np.linalg.norm(x, np.inf)",
+                          "np.linalg.norm(A, np.inf) * np.linalg.norm(x)"),
+    "ls_dropped_b": ("den = nA * (nA * np.linalg.norm(x) + np.linalg.norm(b))", "den = nA * (nA * np.linalg.norm(x))"),
+    "ls_spectral_norm": ("nA = np.linalg.norm(A)\n", "nA = np.linalg.norm(A, 2)\n"),
+    "ls_residual_not_projected": ("float(np.linalg.norm(A.T @ r) / den)", "float(np.linalg.norm(r) / den)"),
+    "ls_residual_sign": ("r = b - A @ x\n    nA", "r = b + A @ x\n    nA"),
+}
+
+
+def test_metric_mutants_are_caught():
+    import types
+    src = open(os.path.join(ROOT, "oracle", "metrics.py")).read()
+    survivors = []
+    for name, (old, new) in METRIC_MUTANTS.items():
+        assert src.count(old) == 1, f"mutation anchor for {name} not unique"
+        mod = types.ModuleType("metrics_" + name)
+        exec(compile(src.replace(old, new), f"metrics_{name}.py", "exec"), mod.__dict__)
+        caught = False
+        for check in METRIC_BATTERY:
+            try:
+                check(mod)
+            except (AssertionError, ValueError, np.linalg.LinAlgError):
+                caught = True
+                break
+        if not caught:
+            survivors.append(name)
+    assert not survivors, f"planted mistakes in the metrics not caught by any pin: {survivors}"
