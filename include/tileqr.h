@@ -32,8 +32,9 @@
  *  - Return value: TILEQR_OK (0) on success; -i when argument i (1-based) is
  *    invalid, in which case nothing is touched (LAPACK INFO style); a
  *    positive tileqr_status otherwise.  A dimension of zero returns 0 at once.
- *  - Calls into one library instance are not thread-safe: the workspace is
- *    shared.  Serialise calls from several host threads.
+ *  - Each (device, stream) pair gets a workspace of its own, so calls with
+ *    TILEQR_FLAG_ASYNC on different streams may overlap on the device.
+ *    Calls from several host threads are serialised by a library lock.
  */
 #ifndef TILEQR_H
 #define TILEQR_H
@@ -83,8 +84,10 @@ enum {
                                       pseudo-random order (schedule-independence test) */
     TILEQR_FLAG_TIMING = 1u << 4,  /* time each stage with HIP events on the call's
                                       stream (tileqr_last_timing)                      */
-    TILEQR_FLAG_NO_GRAPH = 1u << 5 /* tileqr_factor_batched: launch the kernels directly
+    TILEQR_FLAG_NO_GRAPH = 1u << 5,/* tileqr_factor_batched: launch the kernels directly
                                       instead of replaying a captured HIP graph        */
+    TILEQR_FLAG_CHECK = 1u << 6    /* tileqr_solve_ls: also estimate the factorisation's
+                                      backward error (tileqr_info.beta_fact_est)       */
 };
 
 typedef struct {
@@ -127,11 +130,24 @@ typedef struct {
 typedef struct {
     int iterations;       /* refinement steps taken                                  */
     int converged;        /* 1 if the backward error reached tol                     */
-    double eta;           /* final backward error (normwise, see tileqr_solve_ls)    */
-    double eta_hist[65];  /* eta after 0, 1, ... iterations                          */
+    double eta;           /* stopping measure of the returned X (see tileqr_solve_ls):
+                             eta_ls, and for m == n the larger of eta_ls, eta_inf    */
+    double eta_hist[65];  /* the stopping measure after 0, 1, ... iterations         */
     int64_t nb, ib;       /* blocking used                                           */
     double ms_factor;     /* device time of the factorisation                        */
     double ms_total;      /* device time of the whole call                           */
+    double eta_ls;        /* ||A^T (B - A X)||_2 / (||A||_F (||A||_F ||X||_2 +
+                             ||B||_2)) of the returned X, worst column               */
+    double eta_inf;       /* m == n: ||B - A X||_inf / (||A||_inf ||X||_inf) of the
+                             returned X, worst column (the solution backward error
+                             of Section 3.2.4); 0 for m > n                          */
+    double beta_fact_est; /* with TILEQR_FLAG_CHECK: ||A - Q [R; 0]||_F / ||A||_F
+                             estimated from `probes` Gaussian probe vectors z
+                             (E ||E z||^2 = ||E||_F^2), else -1                      */
+    int probes;           /* probe vectors behind beta_fact_est                      */
+    double ms_worker;     /* device time of the factorisation kernel(s) alone
+                             (within ms_factor, which adds the layout conversion
+                             and the scheduler set-up)                             */
 } tileqr_info;
 
 /* Fill *opts with the defaults: FP64, automatic nb/ib, max_iter 30,
@@ -200,16 +216,23 @@ int tileqr_apply_q(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t 
 /*
  * Least squares X = argmin ||B - A X||_2 for m >= n and A of full column
  * rank, one column per right-hand side.  A and B are left untouched (the
- * library factors a copy).  With opts->precision = TILEQR_FP64 the solution
- * is R^{-1} (Q^T B)(0:n).  With a split precision the factorisation's
- * GEMM-shaped kernels run in that arithmetic and the solution is refined in
- * FP64 on the original A (augmented-system refinement: residuals f = B - R
- * - A X and g = -A^T R in FP64, corrections through the mixed factors) until
- * the backward error eta = ||A^T (B - A X)||_2 / (||A||_F (||A||_F ||X||_2
- * + ||B||_2)) (worst column) is <= opts->tol, stagnates, or max_iter steps
- * are taken.  The paper advises checking the backward error of a solve and
- * refining when needed (Section 3.2.4); the refinement scheme is this
- * library's reading.
+ * library factors a copy).  The solution is first R^{-1} (Q^T B)(0:n); then,
+ * as Section 3.2.4 advises (check the backward error of a solve, refine
+ * when needed), it is refined in FP64 on the original A until the stopping
+ * measure is <= opts->tol, stagnates (two steps that fail to halve it), or
+ * max_iter steps are taken; the best iterate is returned.  The stopping
+ * measure is eta_ls = ||A^T (B - A X)||_2 / (||A||_F (||A||_F ||X||_2 +
+ * ||B||_2)) (worst column); for m == n it is the larger of eta_ls and the
+ * paper's eta_inf = ||B - A X||_inf / (||A||_inf ||X||_inf).  Refinement for
+ * m > n is on the augmented system (residuals f = B - R - A X and
+ * g = -A^T R in FP64, corrections through the factors); for m == n, whose
+ * least-squares residual is zero, it is classical refinement
+ * dX = R^{-1} Q^T (B - A X).  With a split precision the factorisation's
+ * block-reflector products run in that arithmetic and the refinement wins
+ * back the FP64 backward error; with TILEQR_FP64 the first solution
+ * normally meets tol already.  With TILEQR_FLAG_CHECK the factorisation's
+ * backward error is estimated from Gaussian probes (info->beta_fact_est);
+ * its cost is outside ms_factor but inside ms_total.
  *   X device, n x nrhs, ldx >= max(1, n), written.  info may be NULL.
  * Errors: -1 m, -2 n (n > m), -3 nrhs, -4 A, -5 lda, -6 B, -7 ldb, -8 X,
  *         -9 ldx, -10 opts; TILEQR_ENOCONV (best iterate in X) when the
@@ -311,6 +334,16 @@ double tileqr_trace_clock_hz(void);
  * persistent worker, or all launches of the serial driver), ms[3] layout
  * conversion out.  Returns 0, or TILEQR_EUNSUPPORTED if no timed call ran. */
 int tileqr_last_timing(double ms[4]);
+
+/* Measured matrix-core peak of the current device, a diagnostic for
+ * reading the factorisation's rates (the rates of Section 5 are quoted
+ * against the machine's peak): a full-chip launch in which every wave
+ * issues long chains of independent MFMAs of one kind, timed with HIP
+ * events (best of three after a warm-up).  kind 0: FP64 16x16x4 (the FP64
+ * products); 1: BF16 16x16x32 and 2: FP16 16x16x32 with FP32 accumulation
+ * (the split products).  Writes TFLOP/s (2 flops per multiply-add) to
+ * *tflops.  Errors: -1 kind, -2 tflops. */
+int tileqr_mfma_peak(int kind, double *tflops);
 
 const char *tileqr_status_string(int status);
 const char *tileqr_last_hip_error(void);

@@ -62,23 +62,15 @@ void SchedBufs::release()
     mats.release();
 }
 
-Workspace *existing_workspace()
-{
-    int dev = 0;
-    if (g_ws.empty() || hipGetDevice(&dev) != hipSuccess) return nullptr;
-    for (auto *w : g_ws)
-        if (w->device == dev) return w;
-    return nullptr;
-}
-
-Workspace *workspace()
+Workspace *workspace(hipStream_t stream)
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return nullptr;
     for (auto *w : g_ws)
-        if (w->device == dev) return w;
+        if (w->device == dev && w->stream == stream) return w;
     auto *w = new Workspace;
     w->device = dev;
+    w->stream = stream;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) w->num_cu = prop.multiProcessorCount;
     int khz = 0;
@@ -90,6 +82,22 @@ Workspace *workspace()
     }
     g_ws.push_back(w);
     return w;
+}
+
+Workspace *g_last_timed = nullptr;
+Workspace *g_last_traced = nullptr;
+
+std::vector<TuneEntry> *tuned_entries(bool create)
+{
+    static std::vector<std::pair<int, std::vector<TuneEntry>>> per_device;
+    int dev = 0;
+    if (per_device.empty() && !create) return nullptr;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    for (auto &e : per_device)
+        if (e.first == dev) return &e.second;
+    if (!create) return nullptr;
+    per_device.push_back({dev, {}});
+    return &per_device.back().second;
 }
 
 }  // namespace tq
@@ -599,14 +607,15 @@ extern "C" int tileqr_factor_ex(int64_t m, int64_t n, double *A, int64_t lda, in
     if (!panel_tasks_ok(o.panel_tasks, nb, ib)) return -8;
     if (!precision_supported(o.precision, ib)) return TILEQR_EUNSUPPORTED;
     std::lock_guard<std::mutex> lock(g_mu);
-    Workspace *W = workspace();
-    if (!W) return hip_fail(hipErrorNoDevice, "workspace");
     hipStream_t st = (hipStream_t)o.stream;
+    Workspace *W = workspace(st);
+    if (!W) return hip_fail(hipErrorNoDevice, "workspace");
     const int p = (int)cdiv(m, nb), q = (int)cdiv(n, nb);
     int rc;
     if ((rc = W->tiles.ensure((size_t)p * q * nb * nb * sizeof(double)))) return rc;
     if ((rc = W->status.ensure(256))) return rc;
     W->trace_events = 0;
+    if (o.flags & TILEQR_FLAG_TRACE) g_last_traced = W;
     const bool timing = (o.flags & TILEQR_FLAG_TIMING) && !(o.flags & TILEQR_FLAG_ASYNC);
     W->have_timing = false;
     if (timing && !W->ev[0])
@@ -628,6 +637,7 @@ extern "C" int tileqr_factor_ex(int64_t m, int64_t n, double *A, int64_t lda, in
             W->last_ms[s] = ms;
         }
         W->have_timing = true;
+        g_last_timed = W;
     }
     return rc;
 }
@@ -635,7 +645,7 @@ extern "C" int tileqr_factor_ex(int64_t m, int64_t n, double *A, int64_t lda, in
 extern "C" int tileqr_last_timing(double ms[4])
 {
     std::lock_guard<std::mutex> lock(g_mu);
-    Workspace *W = workspace();
+    Workspace *W = g_last_timed;
     if (!W || !W->have_timing) return TILEQR_EUNSUPPORTED;
     for (int s = 0; s < 4; ++s) ms[s] = W->last_ms[s];
     return TILEQR_OK;
@@ -651,7 +661,7 @@ extern "C" int tileqr_factor(int64_t m, int64_t n, double *A, int64_t lda, int64
 extern "C" int64_t tileqr_trace(int64_t *events, int64_t cap)
 {
     std::lock_guard<std::mutex> lock(g_mu);
-    Workspace *W = workspace();
+    Workspace *W = g_last_traced;
     if (!W || W->trace_events == 0 || !W->trace.ptr) return 0;
     const int64_t n = std::min(cap, W->trace_events);
     if (events && n > 0) {
@@ -665,9 +675,11 @@ extern "C" int64_t tileqr_trace(int64_t *events, int64_t cap)
 
 extern "C" double tileqr_trace_clock_hz(void)
 {
-    std::lock_guard<std::mutex> lock(g_mu);
-    Workspace *W = workspace();
-    return W ? W->wall_hz : 0.0;
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess)
+        return 0.0;
+    return khz * 1e3;
 }
 
 // ------------------------------------------------------------------ misc
@@ -722,6 +734,7 @@ extern "C" int tileqr_finalize(void)
         delete w;
     }
     g_ws.clear();
+    g_last_timed = g_last_traced = nullptr;
     (void)hipSetDevice(cur);
     return TILEQR_OK;
 }
@@ -768,9 +781,9 @@ int apply_common(bool trans, int64_t m, int64_t n, int64_t nrhs, const double *A
     if (m == 0 || n == 0 || nrhs == 0) return TILEQR_OK;
     if (!tileqr_blocking_supported(nb, ib)) return TILEQR_EUNSUPPORTED;
     std::lock_guard<std::mutex> lock(g_mu);
-    Workspace *W = workspace();
-    if (!W) return hip_fail(hipErrorNoDevice, "workspace");
     hipStream_t st = nullptr;
+    Workspace *W = workspace(st);
+    if (!W) return hip_fail(hipErrorNoDevice, "workspace");
     const int p = (int)cdiv(m, nb), q = (int)cdiv(n, nb), kmax = std::min(p, q);
     const int nstrip = (int)cdiv(nrhs, kStripWidth);
     const int ldt = nstrip * kStripWidth;
@@ -821,36 +834,86 @@ struct SolveCtx {
     double *small;   // device: norms
 };
 
-// eta_v = ||A^T (b - A x)||_2 / (||A||_F (||A||_F ||x||_2 + ||b||_2)) per column;
-// returns the largest.  Writes the residual into buf[SS].
 // Device scratch of the solver's norms (W->misc): results in doubles
-// [0, SMALL_PART) (per-column sums at 0, 64, 128, 192), partial sums of the
-// norm kernels in [SMALL_PART, SMALL_PART + SMALL_PART_CAP), enough for
-// COLSQ_BLOCKS blocks times the largest nrhs (64).
+// [0, SMALL_PART) (per-column results at 0, 64, 128, 192, 256, 320), partial
+// sums of the norm kernels in [SMALL_PART, SMALL_PART + SMALL_PART_CAP),
+// enough for COLSQ_BLOCKS blocks times the largest nrhs (64).
 constexpr int64_t SMALL_PART = 1024;
 constexpr int64_t SMALL_PART_CAP = (int64_t)COLSQ_BLOCKS * 64;
+constexpr int NPROBE = 8;
 
-int eta_of(SolveCtx &c, double normA, const double *normb, double *eta_cols)
+// Backward errors of the iterate in buf[SX], per column v, from the residual
+// S = B - A X (formed here into buf[SS]):
+//   eta_ls[v]  = ||A^T S_v||_2 / (||A||_F (||A||_F ||X_v||_2 + ||B_v||_2))
+//   eta_inf[v] = ||S_v||_inf / (||A||_inf ||X_v||_inf)     (square systems only)
+int eta_of(SolveCtx &c, double normA, double normAinf, const double *normb, bool square, double *eta_ls,
+           double *eta_inf)
 {
     Workspace *W = c.W;
     double *S = c.buf[SS];
     TQ_HIP(launch_axpy_rows(c.buf[SB], S, c.ldt, c.m, c.nrhs, 2, c.st));
     TQ_HIP(launch_gemv_n(c.A, c.lda, c.m, c.n, c.buf[SX], c.ldt, c.nrhs, -1.0, 1.0, S, c.part, c.part_cap, c.st));
-    double *AtS = c.buf[SF];   // scratch n x nrhs (SF is recomputed before use)
+    double *AtS = c.buf[SG];   // scratch n x nrhs (SG is recomputed before use)
     TQ_HIP(launch_gemv_t(c.A, c.lda, c.m, c.n, S, c.ldt, c.nrhs, 1.0, 0.0, AtS, c.part, c.part_cap, c.st));
     double *dev = c.small;
     TQ_HIP(launch_colsq(AtS, c.ldt, c.n, c.nrhs, dev + SMALL_PART, SMALL_PART_CAP, dev, c.st));
     TQ_HIP(launch_colsq(c.buf[SX], c.ldt, c.n, c.nrhs, dev + SMALL_PART, SMALL_PART_CAP, dev + 64, c.st));
+    if (square) {
+        TQ_HIP(launch_colmax(S, c.ldt, c.m, c.nrhs, dev + SMALL_PART, SMALL_PART_CAP, dev + 256, c.st));
+        TQ_HIP(launch_colmax(c.buf[SX], c.ldt, c.n, c.nrhs, dev + SMALL_PART, SMALL_PART_CAP, dev + 320, c.st));
+    }
     TQ_HIP(hipMemcpyAsync(W->host_small, dev, 128 * sizeof(double), hipMemcpyDeviceToHost, c.st));
+    if (square)
+        TQ_HIP(hipMemcpyAsync(W->host_small + 256, dev + 256, 128 * sizeof(double), hipMemcpyDeviceToHost, c.st));
     TQ_HIP(hipStreamSynchronize(c.st));
-    double worst = 0.0;
     for (int v = 0; v < c.nrhs; ++v) {
         const double num = std::sqrt(W->host_small[v]);
         const double den = normA * (normA * std::sqrt(W->host_small[64 + v]) + normb[v]);
-        const double e = den > 0.0 ? num / den : (num > 0.0 ? INFINITY : 0.0);
-        eta_cols[v] = e;
-        worst = std::max(worst, e);
+        eta_ls[v] = den > 0.0 ? num / den : (num > 0.0 ? INFINITY : 0.0);
+        eta_inf[v] = 0.0;
+        if (square) {
+            const double r = W->host_small[256 + v], d = normAinf * W->host_small[320 + v];
+            eta_inf[v] = d > 0.0 ? r / d : (r > 0.0 ? INFINITY : 0.0);
+        }
     }
+    return 0;
+}
+
+// beta_fact estimate ||A - Q [R; 0]||_F / ||A||_F from NPROBE Gaussian probes
+// z (E ||E z||^2 = ||E||_F^2): A Z against Q [R Z; 0], with A the caller's
+// matrix and the factor in W->tiles / c.T.  Uses buf[SF], buf[SG], buf[SS].
+int beta_fact_probe(SolveCtx &c, double normA, uint64_t seed, double *out)
+{
+    Workspace *W = c.W;
+    double *Z = c.buf[SG], *Y = c.buf[SF], *V = c.buf[SS];
+    const size_t slot = (size_t)c.p * c.nb * c.ldt;
+    TQ_HIP(hipMemsetAsync(Z, 0, slot * sizeof(double), c.st));
+    TQ_HIP(hipMemsetAsync(Y, 0, slot * sizeof(double), c.st));
+    TQ_HIP(launch_fill_normal(Z, c.ldt, c.n, NPROBE, seed, c.st));
+    TQ_HIP(launch_gemv_n(c.A, c.lda, c.m, c.n, Z, c.ldt, NPROBE, 1.0, 0.0, Y, c.part, c.part_cap, c.st));
+    TQ_HIP(launch_trmm(c.nb, (double *)W->tiles.ptr, c.p, c.n, V, Z, c.ldt, c.st));
+    ApplyDev D;
+    D.M.tiles = (double *)W->tiles.ptr;
+    D.M.T = c.T;
+    D.M.p = c.p;
+    D.M.q = c.q;
+    D.M.task_base = 0;
+    D.B = V;
+    D.ldb = c.ldt;
+    D.nstrip = c.ldt / kStripWidth;
+    D.kmax = std::min(c.p, c.q);
+    D.prog = (int32_t *)W->prog.ptr;
+    D.status = (int32_t *)W->status.ptr;
+    D.spin_limit = (int64_t)1 << 26;
+    TQ_HIP(launch_apply(c.nb, c.ib, D, false, c.st));
+    TQ_HIP(launch_axpy_rows(V, Y, c.ldt, c.m, NPROBE, 0, c.st));   // Y = Q [R Z; 0] - A Z
+    TQ_HIP(launch_colsq(Y, c.ldt, c.m, NPROBE, c.small + SMALL_PART, SMALL_PART_CAP, c.small + 384, c.st));
+    TQ_HIP(hipMemcpyAsync(W->host_small + 384, c.small + 384, NPROBE * sizeof(double), hipMemcpyDeviceToHost,
+                          c.st));
+    TQ_HIP(hipStreamSynchronize(c.st));
+    double ss = 0.0;
+    for (int v = 0; v < NPROBE; ++v) ss += W->host_small[384 + v];
+    *out = normA > 0.0 ? std::sqrt(ss / NPROBE) / normA : 0.0;
     return 0;
 }
 
@@ -875,6 +938,7 @@ extern "C" int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double 
     if (o.precision < TILEQR_FP64 || o.precision > TILEQR_BF16X3) return -10;
     if (info) {
         std::memset(info, 0, sizeof *info);
+        info->beta_fact_est = -1.0;
     }
     if (n == 0 || nrhs == 0) return TILEQR_OK;
     int64_t nb = o.nb, ib = o.ib;
@@ -884,12 +948,13 @@ extern "C" int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double 
     if (!precision_supported(o.precision, ib)) return TILEQR_EUNSUPPORTED;
 
     std::lock_guard<std::mutex> lock(g_mu);
-    Workspace *W = workspace();
-    if (!W) return hip_fail(hipErrorNoDevice, "workspace");
     hipStream_t st = (hipStream_t)o.stream;
+    Workspace *W = workspace(st);
+    if (!W) return hip_fail(hipErrorNoDevice, "workspace");
     const int p = (int)cdiv(m, nb), q = (int)cdiv(n, nb);
     const int ldt = (int)cdiv(nrhs, kStripWidth) * kStripWidth;
     const size_t slot = (size_t)p * nb * ldt;
+    const bool square = m == n;
     int rc;
     if ((rc = W->tiles.ensure((size_t)p * q * nb * nb * sizeof(double)))) return rc;
     if ((rc = W->tws.ensure(std::max<size_t>(1, tileqr_t_size(m, n, nb, ib)) * sizeof(double)))) return rc;
@@ -931,72 +996,108 @@ extern "C" int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double 
     TQ_HIP(launch_cm2tile(A, lda, m, n, (double *)W->tiles.ptr, (int)nb, p, q, dstatus, st));
     tileqr_opts fo = o;
     fo.flags &= ~(unsigned)(TILEQR_FLAG_ASYNC | TILEQR_FLAG_TIMING | TILEQR_FLAG_TRACE);
-    if ((rc = run_factor(W, (int)nb, (int)ib, p, q, c.T, fo, st, nullptr))) return rc;
+    if ((rc = run_factor(W, (int)nb, (int)ib, p, q, c.T, fo, st, W->ev[3]))) return rc;
     TQ_HIP(hipEventRecord(W->ev[1], st));
     if ((rc = check_status(W, dstatus, st))) return rc;
 
-    // x0 = R^{-1} (Q^T b)(0:n),  r0 = b - A x0.
+    // Norms fixed for the whole refinement.
     TQ_HIP(hipMemsetAsync(W->solve.ptr, 0, SNUM * slot * sizeof(double), st));
     TQ_HIP(launch_cm2rows(B, ldb, m, nrhs, c.buf[SB], (int64_t)p * nb, ldt, st));
+    TQ_HIP(launch_frob2(A, lda, m, n, c.small + SMALL_PART, SMALL_PART_CAP, c.small + 128, st));
+    TQ_HIP(launch_colsq(c.buf[SB], ldt, m, c.nrhs, c.small + SMALL_PART, SMALL_PART_CAP, c.small + 192, st));
+    if (square) TQ_HIP(launch_norm_inf(A, lda, m, n, c.part, part_cap, c.small + 129, st));
+    TQ_HIP(hipMemcpyAsync(W->host_small + 128, c.small + 128, 128 * sizeof(double), hipMemcpyDeviceToHost, st));
+    TQ_HIP(hipStreamSynchronize(st));
+    const double normA = std::sqrt(W->host_small[128]);
+    const double normAinf = square ? W->host_small[129] : 0.0;
+    double normb[64], eta_ls[64], eta_inf[64];
+    for (int v = 0; v < c.nrhs; ++v) normb[v] = std::sqrt(W->host_small[192 + v]);
+
+    // Optional check of the factorisation (not part of the solve proper).
+    if ((o.flags & TILEQR_FLAG_CHECK) && info) {
+        double bf = -1.0;
+        if ((rc = beta_fact_probe(c, normA, o.seed ^ 0x5eedULL, &bf))) return rc;
+        info->beta_fact_est = bf;
+        info->probes = NPROBE;
+        TQ_HIP(hipMemsetAsync(W->solve.ptr, 0, SNUM * slot * sizeof(double), st));
+        TQ_HIP(launch_cm2rows(B, ldb, m, nrhs, c.buf[SB], (int64_t)p * nb, ldt, st));
+    }
+
+    // x0 = R^{-1} (Q^T b)(0:n),  r0 = b - A x0.
     TQ_HIP(launch_axpy_rows(c.buf[SB], c.buf[SX], ldt, m, c.nrhs, 2, st));
     TQ_HIP(apply_rows(W, c.nb, c.ib, p, q, c.T, c.buf[SX], ldt, true, st));
     TQ_HIP(launch_trsm(c.nb, (double *)W->tiles.ptr, p, n, c.buf[SX], ldt, true, (int *)W->tflags.ptr, tflags_cap,
                        dstatus, spin, st));
     // zero the rows n.. of x (they held (Q^T b)(n:m))
     TQ_HIP(hipMemsetAsync(c.buf[SX] + (size_t)n * ldt, 0, (size_t)(p * nb - n) * ldt * sizeof(double), st));
-    TQ_HIP(launch_axpy_rows(c.buf[SB], c.buf[SR], ldt, m, c.nrhs, 2, st));
-    TQ_HIP(launch_gemv_n(A, lda, m, n, c.buf[SX], ldt, c.nrhs, -1.0, 1.0, c.buf[SR], c.part, part_cap, st));
+    if (!square) {
+        TQ_HIP(launch_axpy_rows(c.buf[SB], c.buf[SR], ldt, m, c.nrhs, 2, st));
+        TQ_HIP(launch_gemv_n(A, lda, m, n, c.buf[SX], ldt, c.nrhs, -1.0, 1.0, c.buf[SR], c.part, part_cap, st));
+    }
     if ((rc = check_status(W, dstatus, st))) return rc;
 
-    // Norms fixed for the whole refinement.
-    TQ_HIP(launch_frob2(A, lda, m, n, c.small + SMALL_PART, SMALL_PART_CAP, c.small + 128, st));
-    TQ_HIP(launch_colsq(c.buf[SB], ldt, m, c.nrhs, c.small + SMALL_PART, SMALL_PART_CAP, c.small + 192, st));
-    TQ_HIP(hipMemcpyAsync(W->host_small + 128, c.small + 128, 128 * sizeof(double), hipMemcpyDeviceToHost, st));
-    TQ_HIP(hipStreamSynchronize(st));
-    const double normA = std::sqrt(W->host_small[128]);
-    double normb[64], eta_cols[64];
-    for (int v = 0; v < c.nrhs; ++v) normb[v] = std::sqrt(W->host_small[192 + v]);
-
-    double eta = 0.0;
-    if ((rc = eta_of(c, normA, normb, eta_cols))) return rc;
-    for (int v = 0; v < c.nrhs; ++v) eta = std::max(eta, eta_cols[v]);
-    double best = eta;
+    // The stopping measure: eta_LS, and for square systems also the
+    // infinity-norm backward error of Section 3.2.4 (whichever is larger).
+    auto measure = [&](double &worst, double &wls, double &winf) {
+        worst = wls = winf = 0.0;
+        for (int v = 0; v < c.nrhs; ++v) {
+            wls = std::max(wls, eta_ls[v]);
+            winf = std::max(winf, eta_inf[v]);
+            worst = std::max(worst, std::max(eta_ls[v], eta_inf[v]));
+        }
+    };
+    double eta, e_ls, e_inf;
+    if ((rc = eta_of(c, normA, normAinf, normb, square, eta_ls, eta_inf))) return rc;
+    measure(eta, e_ls, e_inf);
+    double best = eta, best_ls = e_ls, best_inf = e_inf;
     TQ_HIP(launch_axpy_rows(c.buf[SX], c.buf[SXB], ldt, n, c.nrhs, 2, st));
     if (info) info->eta_hist[0] = eta;
     int it = 0, stall = 0;
     double prev = eta;
-    // Refinement of the augmented system [I A; A^T 0][r; x] = [b; 0]
-    // (residuals in FP64 on the original A, corrections through the factors).
     while (eta > o.tol && it < o.max_iter) {
         ++it;
         double *F = c.buf[SF], *G = c.buf[SG];
-        // f = b - r - A x ;  g = -A^T r
-        TQ_HIP(launch_axpy_rows(c.buf[SB], F, ldt, m, c.nrhs, 2, st));
-        TQ_HIP(launch_axpy_rows(c.buf[SR], F, ldt, m, c.nrhs, 0, st));   // F = R - F = r - b
-        TQ_HIP(launch_axpy_rows(nullptr, F, ldt, m, c.nrhs, 3, st));     // F = b - r
-        TQ_HIP(launch_gemv_n(A, lda, m, n, c.buf[SX], ldt, c.nrhs, -1.0, 1.0, F, c.part, part_cap, st));
-        TQ_HIP(launch_gemv_t(A, lda, m, n, c.buf[SR], ldt, c.nrhs, -1.0, 0.0, G, c.part, part_cap, st));
-        // [f1; f2] = Q^T f ;  d1 = R^{-T} g ;  dx = R^{-1} (f1 - d1) ;  dr = Q [d1; f2]
-        TQ_HIP(apply_rows(W, c.nb, c.ib, p, q, c.T, F, ldt, true, st));
-        TQ_HIP(launch_trsm(c.nb, (double *)W->tiles.ptr, p, n, G, ldt, false, (int *)W->tflags.ptr, tflags_cap,
-                           dstatus, spin, st));
-        double *DX = c.buf[SS];
-        TQ_HIP(launch_axpy_rows(F, DX, ldt, n, c.nrhs, 2, st));
-        TQ_HIP(launch_axpy_rows(G, DX, ldt, n, c.nrhs, 0, st));          // DX = G - DX = d1 - f1
-        TQ_HIP(launch_axpy_rows(nullptr, DX, ldt, n, c.nrhs, 3, st));    // DX = f1 - d1
-        TQ_HIP(hipMemsetAsync(DX + (size_t)n * ldt, 0, (size_t)(p * nb - n) * ldt * sizeof(double), st));
-        TQ_HIP(launch_trsm(c.nb, (double *)W->tiles.ptr, p, n, DX, ldt, true, (int *)W->tflags.ptr, tflags_cap,
-                           dstatus, spin, st));
-        TQ_HIP(launch_axpy_rows(DX, c.buf[SX], ldt, n, c.nrhs, 1, st));
-        TQ_HIP(launch_axpy_rows(G, F, ldt, n, c.nrhs, 2, st));             // F = [d1; f2]
-        TQ_HIP(apply_rows(W, c.nb, c.ib, p, q, c.T, F, ldt, false, st));
-        TQ_HIP(launch_axpy_rows(F, c.buf[SR], ldt, m, c.nrhs, 1, st));
-        if ((rc = eta_of(c, normA, normb, eta_cols))) return rc;
-        eta = 0.0;
-        for (int v = 0; v < c.nrhs; ++v) eta = std::max(eta, eta_cols[v]);
+        if (square) {
+            // Classical refinement (the augmented system with m = n, whose
+            // least-squares residual is zero): dx = R^{-1} Q^T (b - A x), with
+            // the residual b - A x that eta_of left in buf[SS].
+            TQ_HIP(launch_axpy_rows(c.buf[SS], F, ldt, m, c.nrhs, 2, st));
+            TQ_HIP(apply_rows(W, c.nb, c.ib, p, q, c.T, F, ldt, true, st));
+            TQ_HIP(launch_trsm(c.nb, (double *)W->tiles.ptr, p, n, F, ldt, true, (int *)W->tflags.ptr, tflags_cap,
+                               dstatus, spin, st));
+            TQ_HIP(launch_axpy_rows(F, c.buf[SX], ldt, n, c.nrhs, 1, st));
+        } else {
+            // Refinement of the augmented system [I A; A^T 0][r; x] = [b; 0]
+            // (residuals in FP64 on the original A, corrections through the
+            // factors): f = b - r - A x ;  g = -A^T r
+            TQ_HIP(launch_axpy_rows(c.buf[SB], F, ldt, m, c.nrhs, 2, st));
+            TQ_HIP(launch_axpy_rows(c.buf[SR], F, ldt, m, c.nrhs, 0, st));   // F = R - F = r - b
+            TQ_HIP(launch_axpy_rows(nullptr, F, ldt, m, c.nrhs, 3, st));     // F = b - r
+            TQ_HIP(launch_gemv_n(A, lda, m, n, c.buf[SX], ldt, c.nrhs, -1.0, 1.0, F, c.part, part_cap, st));
+            TQ_HIP(launch_gemv_t(A, lda, m, n, c.buf[SR], ldt, c.nrhs, -1.0, 0.0, G, c.part, part_cap, st));
+            // [f1; f2] = Q^T f ;  d1 = R^{-T} g ;  dx = R^{-1} (f1 - d1) ;  dr = Q [d1; f2]
+            TQ_HIP(apply_rows(W, c.nb, c.ib, p, q, c.T, F, ldt, true, st));
+            TQ_HIP(launch_trsm(c.nb, (double *)W->tiles.ptr, p, n, G, ldt, false, (int *)W->tflags.ptr, tflags_cap,
+                               dstatus, spin, st));
+            double *DX = c.buf[SS];
+            TQ_HIP(launch_axpy_rows(F, DX, ldt, n, c.nrhs, 2, st));
+            TQ_HIP(launch_axpy_rows(G, DX, ldt, n, c.nrhs, 0, st));          // DX = G - DX = d1 - f1
+            TQ_HIP(launch_axpy_rows(nullptr, DX, ldt, n, c.nrhs, 3, st));    // DX = f1 - d1
+            TQ_HIP(hipMemsetAsync(DX + (size_t)n * ldt, 0, (size_t)(p * nb - n) * ldt * sizeof(double), st));
+            TQ_HIP(launch_trsm(c.nb, (double *)W->tiles.ptr, p, n, DX, ldt, true, (int *)W->tflags.ptr, tflags_cap,
+                               dstatus, spin, st));
+            TQ_HIP(launch_axpy_rows(DX, c.buf[SX], ldt, n, c.nrhs, 1, st));
+            TQ_HIP(launch_axpy_rows(G, F, ldt, n, c.nrhs, 2, st));             // F = [d1; f2]
+            TQ_HIP(apply_rows(W, c.nb, c.ib, p, q, c.T, F, ldt, false, st));
+            TQ_HIP(launch_axpy_rows(F, c.buf[SR], ldt, m, c.nrhs, 1, st));
+        }
+        if ((rc = eta_of(c, normA, normAinf, normb, square, eta_ls, eta_inf))) return rc;
+        measure(eta, e_ls, e_inf);
         if (info && it < 65) info->eta_hist[it] = eta;
         if (eta < best) {
             best = eta;
+            best_ls = e_ls;
+            best_inf = e_inf;
             TQ_HIP(launch_axpy_rows(c.buf[SX], c.buf[SXB], ldt, n, c.nrhs, 2, st));
         }
         stall = eta > 0.5 * prev ? stall + 1 : 0;
@@ -1010,11 +1111,14 @@ extern "C" int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double 
         info->iterations = it;
         info->converged = best <= o.tol;
         info->eta = best;
+        info->eta_ls = best_ls;
+        info->eta_inf = best_inf;
         info->nb = nb;
         info->ib = ib;
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, W->ev[0], W->ev[1]) == hipSuccess) info->ms_factor = ms;
         if (hipEventElapsedTime(&ms, W->ev[0], W->ev[2]) == hipSuccess) info->ms_total = ms;
+        if (hipEventElapsedTime(&ms, W->ev[3], W->ev[1]) == hipSuccess) info->ms_worker = ms;
     }
     if (rc) return rc;
     return best <= o.tol ? TILEQR_OK : TILEQR_ENOCONV;

@@ -27,9 +27,11 @@ struct Group {
     int workers = 0;
 };
 
-const tileqr_tuning *find_tuned(Workspace *W, const std::vector<int64_t> &key)
+const tileqr_tuning *find_tuned(const std::vector<int64_t> &key)
 {
-    for (const auto &e : W->tuned)
+    const std::vector<TuneEntry> *tab = tuned_entries(false);
+    if (!tab) return nullptr;
+    for (const auto &e : *tab)
         if (e.key == key) return &e.best;
     return nullptr;
 }
@@ -238,16 +240,16 @@ extern "C" int tileqr_factor_batched(int64_t batch, const int64_t *m, const int6
     if (o.flags & (TILEQR_FLAG_SERIAL | TILEQR_FLAG_TRACE)) return TILEQR_EUNSUPPORTED;
     if (batch == 0) return TILEQR_OK;
     std::lock_guard<std::mutex> lock(g_mu);
-    Workspace *W = workspace();
-    if (!W) return hip_fail(hipErrorNoDevice, "workspace");
     hipStream_t st = (hipStream_t)o.stream;
+    Workspace *W = workspace(st);
+    if (!W) return hip_fail(hipErrorNoDevice, "workspace");
     std::vector<int64_t> nbv, ibv;
     if (nb) {
         nbv.assign(nb, nb + batch);
         ibv.assign(ib, ib + batch);
     } else {
         int64_t b = 0, s = 0;
-        const tileqr_tuning *t = find_tuned(W, shape_key(batch, m, n, o.precision));
+        const tileqr_tuning *t = find_tuned(shape_key(batch, m, n, o.precision));
         if (t) {
             b = t->nb;
             s = t->ib;
@@ -276,6 +278,7 @@ extern "C" int tileqr_factor_batched(int64_t batch, const int64_t *m, const int6
         W->last_ms[0] = W->last_ms[1] = W->last_ms[3] = 0.0;
         W->last_ms[2] = ms;
         W->have_timing = true;
+        g_last_timed = W;
     }
     return rc;
 }
@@ -287,9 +290,7 @@ namespace tq {
 // Tuned blocking for one m x n matrix, if tileqr_tune has seen it.
 bool tuned_single(int64_t m, int64_t n, int precision, tileqr_tuning *out)
 {
-    Workspace *W = existing_workspace();
-    if (!W) return false;
-    const tileqr_tuning *t = find_tuned(W, shape_key(1, &m, &n, precision));
+    const tileqr_tuning *t = find_tuned(shape_key(1, &m, &n, precision));
     if (!t) return false;
     *out = *t;
     return true;
@@ -311,7 +312,7 @@ extern "C" int tileqr_tune(int64_t batch, const int64_t *m, const int64_t *n, in
     if (trials < 1 || trials > 100) return -5;
     if (!best) return -6;
     std::lock_guard<std::mutex> lock(g_mu);
-    Workspace *W = workspace();
+    Workspace *W = workspace(nullptr);
     if (!W) return hip_fail(hipErrorNoDevice, "workspace");
     if (!W->ev[0])
         for (auto &e : W->ev) TQ_HIP(hipEventCreate(&e));
@@ -428,13 +429,15 @@ extern "C" int tileqr_tune(int64_t batch, const int64_t *m, const int64_t *n, in
     Tbuf.release();
     if (rc) return rc;
     const std::vector<int64_t> key = shape_key(batch, m, n, precision);
+    std::vector<TuneEntry> *tab = tuned_entries(true);
+    if (!tab) return hip_fail(hipErrorNoDevice, "tuner table");
     bool found = false;
-    for (auto &e : W->tuned)
+    for (auto &e : *tab)
         if (e.key == key) {
             e.best = top;
             found = true;
         }
-    if (!found) W->tuned.push_back(TuneEntry{key, top});
+    if (!found) tab->push_back(TuneEntry{key, top});
     *best = top;
     return TILEQR_OK;
 }

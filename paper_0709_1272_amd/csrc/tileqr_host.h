@@ -48,9 +48,12 @@ struct TuneEntry {
     tileqr_tuning best;
 };
 
-// Library workspace of one device.
+// Library workspace of one (device, stream) pair: calls on different
+// streams never share buffers, so asynchronous calls on two streams (or a
+// captured graph and calls on another stream) cannot race on them.
 struct Workspace {
     int device = -1;
+    hipStream_t stream = nullptr;
     DevBuf tiles, status, trace, misc, rows, prog, tws, solve, part, tflags;
     SchedBufs sched;                      // single-matrix calls
     // Batched calls keep their own buffers so that a captured graph stays
@@ -60,7 +63,6 @@ struct Workspace {
     hipGraphExec_t bgraph = nullptr;
     std::vector<int64_t> bgraph_key;
     hipStream_t cap_stream = nullptr;     // private stream for graph capture
-    std::vector<TuneEntry> tuned;
     double *host_small = nullptr;         // pinned, for norms read back by the solver
     int *host_status = nullptr;           // pinned
     int64_t trace_events = 0;
@@ -72,11 +74,15 @@ struct Workspace {
 };
 
 extern std::mutex g_mu;
-// The current device's workspace, created on first use (nullptr without a
-// device).  existing_workspace() never creates one (and makes no HIP call
-// before any workspace exists).
-Workspace *workspace();
-Workspace *existing_workspace();
+// The workspace of the current device and `stream`, created on first use
+// (nullptr without a device).
+Workspace *workspace(hipStream_t stream);
+// Workspaces of the last synchronous timed call and of the last traced call.
+extern Workspace *g_last_timed;
+extern Workspace *g_last_traced;
+// The tuner's entries for the current device; with create == false,
+// nullptr if there are none (and no HIP call is made before the first).
+std::vector<TuneEntry> *tuned_entries(bool create);
 // Blocking and schedule tileqr_tune found for one m x n matrix (g_mu held).
 bool tuned_single(int64_t m, int64_t n, int precision, tileqr_tuning *out);
 

@@ -115,6 +115,19 @@ hipError_t launch_colsq(const double *Y, int ldt, int64_t m, int nrhs, double *p
 // out[0] = ||A||_F^2; part: COLSQ_BLOCKS doubles.
 hipError_t launch_frob2(const double *A, int64_t lda, int64_t m, int64_t n, double *part, int64_t part_cap,
                         double *out, hipStream_t st);
+// out[v] = max |Y[r][v]| over rows r < m; part as for launch_colsq.
+hipError_t launch_colmax(const double *Y, int ldt, int64_t m, int nrhs, double *part, int64_t part_cap, double *out,
+                         hipStream_t st);
+// out[0] = ||A||_inf (largest absolute row sum of column-major A); part holds
+// part_cap doubles (column-slice row sums, then COLSQ_BLOCKS maxima).
+hipError_t launch_norm_inf(const double *A, int64_t lda, int64_t m, int64_t n, double *part, int64_t part_cap,
+                           double *out, hipStream_t st);
+// Y (row blocks, rows < rows, columns < cols of ldt) <- N(0, 1) from a
+// counter-based hash of (seed, position); other columns zero.
+hipError_t launch_fill_normal(double *Y, int ldt, int64_t rows, int cols, uint64_t seed, hipStream_t st);
+// W = R Z (row blocks of p nb rows; R the n x n upper triangle of the tiles).
+hipError_t launch_trmm(int nb, const double *tiles, int p, int64_t n, double *W, const double *Z, int ldt,
+                       hipStream_t st);
 // op 0: Y = X - Y, 1: Y += X, 2: Y = X, 3: Y = -Y (rows < m, columns < nrhs).
 hipError_t launch_axpy_rows(const double *X, double *Y, int ldt, int64_t m, int nrhs, int op, hipStream_t st);
 

@@ -363,6 +363,151 @@ __global__ __launch_bounds__(256) void k_frob_part(const double *A, int64_t lda,
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// out[v] = max over rows r < m of |Y[r][v]| (per column v < nrhs): per-block
+// maxima, then one block takes the maximum of those (order-independent).
+__global__ __launch_bounds__(256) void k_colmax_part(const double *Y, int ldt, int64_t m, int nrhs, double *part)
+{
+    __shared__ double red[256];
+    for (int v = 0; v < nrhs; ++v) {
+        double s = 0.0;
+        for (int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x; r < m; r += (int64_t)gridDim.x * 256)
+            s = fmax(s, fabs(Y[r * ldt + v]));
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(int64_t)v * gridDim.x + blockIdx.x] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ void k_colmax_sum(const double *part, int nblk, int nrhs, double *out)
+{
+    const int v = threadIdx.x;
+    if (v < nrhs) {
+        double s = 0.0;
+        for (int q = 0; q < nblk; ++q) s = fmax(s, part[(int64_t)v * nblk + q]);
+        out[v] = s;
+    }
+}
+
+// ||A||_inf = max over rows of sum_c |A[r][c]| for column-major A.  Pass 1:
+// workgroup (x, y) sums rows [256 x, 256 x + 256) over the column slice y
+// (consecutive threads read consecutive rows: coalesced); pass 2 adds the
+// slices of each row in slice order and takes per-block maxima; pass 3 the
+// maximum of those.
+__global__ __launch_bounds__(256) void k_absrow_part(const double *A, int64_t lda, int64_t m, int64_t n,
+                                                     int64_t cols_per_slice, double *part)
+{
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t c0 = (int64_t)blockIdx.y * cols_per_slice, c1 = std::min<int64_t>(n, c0 + cols_per_slice);
+    if (row >= m) return;
+    double s = 0.0;
+    for (int64_t c = c0; c < c1; ++c) s += fabs(A[c * lda + row]);
+    part[(int64_t)blockIdx.y * m + row] = s;
+}
+
+__global__ __launch_bounds__(256) void k_absrow_max(const double *part, int nslice, int64_t m, double *out)
+{
+    __shared__ double red[256];
+    double mx = 0.0;
+    for (int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x; row < m; row += (int64_t)gridDim.x * 256) {
+        double s = 0.0;
+        for (int q = 0; q < nslice; ++q) s += part[(int64_t)q * m + row];
+        mx = fmax(mx, s);
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + h]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[blockIdx.x] = red[0];
+}
+
+// Y[r][v] <- N(0, 1) for r < rows, v < cols (zero in the other columns up to
+// ldt), by the Box-Muller transform of two uniforms drawn from a
+// counter-based hash of (seed, r, v): probe vectors of the factorisation
+// check.
+__device__ __forceinline__ uint64_t hash64(uint64_t x)
+{
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdULL;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ULL;
+    x ^= x >> 33;
+    return x;
+}
+
+__global__ void k_fill_normal(double *Y, int ldt, int64_t rows, int cols, uint64_t seed)
+{
+    const int64_t total = rows * ldt;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int v = (int)(e % ldt);
+        double z = 0.0;
+        if (v < cols) {
+            const uint64_t h1 = hash64(seed * 0x9e3779b97f4a7c15ULL + 2 * (uint64_t)e + 1);
+            const uint64_t h2 = hash64(h1 ^ 0x632be59bd9b4e019ULL);
+            const double u1 = ((double)(h1 >> 11) + 0.5) * (1.0 / 9007199254740992.0);   // (0, 1)
+            const double u2 = (double)(h2 >> 11) * (1.0 / 9007199254740992.0);
+            z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+        }
+        Y[e] = z;
+    }
+}
+
+// W = R Z for the tiled R (upper triangle of tiles i <= j < q, R_ii its upper
+// triangle only) and Z in row blocks (rows >= n zero): workgroup (i, strip)
+// forms W_i = sum_{j >= i} R_ij Z_j for one 32-wide strip, staging Z_j and
+// 32-column chunks of R_ij in LDS; row blocks i >= q get W_i = 0.
+template <int NB>
+__global__ __launch_bounds__(2 * NB) void k_trmm(const double *tiles, int p, int q, double *W, const double *Z,
+                                                 int ldt)
+{
+    constexpr int NT = 2 * NB;
+    __shared__ double Zs[NB][SW + 1];
+    __shared__ double Rc[NB][33];
+    const int tid = threadIdx.x, i = (int)blockIdx.x, s0 = (int)blockIdx.y * SW;
+    const int rgp = tid / 8, cg = tid % 8;   // rows 4 rgp .. +3, columns 4 cg .. +3
+    double acc[4][4] = {};
+    for (int j = i; j < q; ++j) {
+        const double *Rt = tile_at(tiles, p, NB, i, j);
+        const double *Zj = Z + (size_t)j * NB * ldt;
+        __syncthreads();
+        batched_copy<NB * SW / NT>(tid, NT, [&](int e) { return Zj[(size_t)(e / SW) * ldt + s0 + e % SW]; },
+                                   [&](int e, double v) { Zs[e / SW][e % SW] = v; });
+        for (int kc = 0; kc < NB; kc += 32) {
+            __syncthreads();
+            batched_copy<NB * 32 / NT>(tid, NT,
+                                       [&](int e) {
+                                           const int r = e / 32, c = kc + e % 32;
+                                           return (j > i || c >= r) ? Rt[(size_t)r * NB + c] : 0.0;
+                                       },
+                                       [&](int e, double v) { Rc[e / 32][e % 32] = v; });
+            __syncthreads();
+            for (int kk = 0; kk < 32; ++kk) {
+                double a[4], b[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    a[u] = Rc[4 * rgp + u][kk];
+                    b[u] = Zs[kc + kk][4 * cg + u];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+            }
+        }
+    }
+    double *Wi = W + (size_t)i * NB * ldt;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Wi[(size_t)(4 * rgp + u) * ldt + s0 + 4 * cg + v] = acc[u][v];
+}
+
 // Elementwise helpers on row blocks (rows < m, columns < nrhs).
 //   op 0: Y = X - Y       op 1: Y += X      op 2: Y = X      op 3: Y = -Y
 __global__ void k_axpy_rows(const double *X, double *Y, int ldt, int64_t m, int nrhs, int op)
@@ -468,6 +613,56 @@ hipError_t launch_frob2(const double *A, int64_t lda, int64_t m, int64_t n, doub
     if (nblk > part_cap) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_frob_part, dim3(nblk), dim3(256), 0, st, A, lda, m, n, part);
     hipLaunchKernelGGL(k_colsq_sum, dim3(1), dim3(64), 0, st, part, nblk, 1, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_colmax(const double *Y, int ldt, int64_t m, int nrhs, double *part, int64_t part_cap, double *out,
+                         hipStream_t st)
+{
+    const int nblk = COLSQ_BLOCKS;
+    if ((int64_t)nblk * nrhs > part_cap) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_colmax_part, dim3(nblk), dim3(256), 0, st, Y, ldt, m, nrhs, part);
+    hipLaunchKernelGGL(k_colmax_sum, dim3(1), dim3(64), 0, st, part, nblk, nrhs, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm_inf(const double *A, int64_t lda, int64_t m, int64_t n, double *part, int64_t part_cap,
+                           double *out, hipStream_t st)
+{
+    if (m <= 0 || n <= 0) return hipSuccess;
+    const int64_t rowblk = (m + 255) / 256;
+    int64_t nslice = std::max<int64_t>(1, std::min<int64_t>((n + 63) / 64, 4096 / rowblk + 1));
+    nslice = std::min<int64_t>(nslice, (part_cap - COLSQ_BLOCKS) / m);
+    if (nslice < 1) return hipErrorInvalidValue;
+    const int64_t cps = (n + nslice - 1) / nslice;
+    nslice = (n + cps - 1) / cps;
+    double *part2 = part + nslice * m;
+    hipLaunchKernelGGL(k_absrow_part, dim3((unsigned)rowblk, (unsigned)nslice), dim3(256), 0, st, A, lda, m, n,
+                       cps, part);
+    hipLaunchKernelGGL(k_absrow_max, dim3(COLSQ_BLOCKS), dim3(256), 0, st, part, (int)nslice, m, part2);
+    hipLaunchKernelGGL(k_colmax_sum, dim3(1), dim3(64), 0, st, part2, COLSQ_BLOCKS, 1, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_normal(double *Y, int ldt, int64_t rows, int cols, uint64_t seed, hipStream_t st)
+{
+    const int64_t total = rows * ldt;
+    if (total <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_fill_normal, dim3((unsigned)blocks), dim3(256), 0, st, Y, ldt, rows, cols, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_trmm(int nb, const double *tiles, int p, int64_t n, double *W, const double *Z, int ldt,
+                       hipStream_t st)
+{
+    const int q = (int)((n + nb - 1) / nb);
+    const dim3 grid((unsigned)p, (unsigned)(ldt / SW));
+    // Row blocks i >= q (below R) hold zeros: the loop over j >= i is empty.
+    if (nb == 64) hipLaunchKernelGGL(k_trmm<64>, grid, dim3(128), 0, st, tiles, p, q, W, Z, ldt);
+    else if (nb == 128) hipLaunchKernelGGL(k_trmm<128>, grid, dim3(256), 0, st, tiles, p, q, W, Z, ldt);
+    else if (nb == 256) hipLaunchKernelGGL(k_trmm<256>, grid, dim3(512), 0, st, tiles, p, q, W, Z, ldt);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

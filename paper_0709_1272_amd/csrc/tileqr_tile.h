@@ -447,10 +447,12 @@ __device__ __forceinline__ void apply_panel(Smem<NB, IB> &sm, Strip<NB, IB> &X, 
 // operands is the sum of the partial products that matter, run on
 // v_mfma_f32_16x16x32_{bf16,f16} with FP32 accumulation:
 //   PREC_BF16X2  2 bf16 parts; x0 y0 + x0 y1 + x1 y0 (16 significant bits)
-//   PREC_FP16X2  2 fp16 parts, same three products (22 bits); every column
-//                of the right operand is scaled by a power of two so that its
-//                largest entry lands in [2^14, 2^15), V by 2^12 (|v| <= 1)
+//   PREC_FP16X2  2 fp16 parts, same three products (22 bits); V is scaled
+//                by 2^12 (|v| <= 1)
 //   PREC_BF16X3  3 bf16 parts; the six products of combined order <= 2
+// In every mode each column of the right operand is scaled by a power of two
+// so that its largest entry lands in [2^14, 2^15): the parts then stay in the
+// narrow format's range whatever the magnitude of the column.
 // The partial products of one wave (32 rows: one K step) are accumulated in
 // FP32, converted to FP64, unscaled (exact) and summed across waves in FP64;
 // reflectors, T, T^T W and the update of the coupled top tile stay FP64.
@@ -487,7 +489,7 @@ __device__ __forceinline__ void split8(const double (&x)[8], double scale, Parts
     using E = typename Narrow<PREC>::elem;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
-        double r = PREC == PREC_FP16X2 ? x[e] * scale : x[e];
+        double r = x[e] * scale;
 #pragma unroll
         for (int q = 0; q < Narrow<PREC>::NPART; ++q) {
             const E h = (E)(float)r;
@@ -546,8 +548,12 @@ __device__ __forceinline__ void apply_panel_mx(Smem<NB, IB> &sm, Strip<NB, IB> &
 {
     using C = Cfg<NB, IB>;
     static_assert(IB == 32, "split-precision updates take ib = 32");
-    constexpr bool SCALED = PREC == PREC_FP16X2;
-    constexpr double VSCALE = SCALED ? 4096.0 : 1.0;
+    // Every right operand column is scaled by a power of two (exact): FP16
+    // needs it for its narrow exponent range, the BF16 splits for entries
+    // beyond the FP32 range their parts pass through.  V (|v| <= 1) needs
+    // it only for FP16, whose low parts would otherwise go subnormal.
+    constexpr bool SCALED = true;
+    constexpr double VSCALE = PREC == PREC_FP16X2 ? 4096.0 : 1.0;
     const int tid = threadIdx.x, w = wave_id();
     const int n = lane_id() & 15, g = lane_id() >> 4, rowbase = w * 32;
     const bool active = rowbase >= rlo;

@@ -12,11 +12,14 @@ experiments draw entries with randn):
 * ``uniform``      entries i.i.d. uniform(-1, 1)            (square FP64 QR)
 * ``svd_matrix``   A = U diag(s) V^T with random orthogonal U, V and s
                    log-spaced from 1 to 1/kappa              (least squares)
-* ``svd_matrix_device``  the same spectrum at sizes where a host QR of a
-                   Gaussian matrix is too slow: U and V are products of
-                   normalised Walsh-Hadamard transforms, random signs and
-                   random permutations (dense and exactly orthogonal), built
-                   on the GPU with torch                     (large least squares)
+* ``svd_matrix_haar_device``  the same construction at sizes where a host QR
+                   of a Gaussian matrix is too slow: U and V are the Q factors
+                   of Gaussian matrices (Haar-distributed, column signs fixed)
+                   computed on the GPU by torch.linalg.qr   (large least squares)
+* ``svd_matrix_device``  the same spectrum with structured orthogonal factors:
+                   U and V are products of normalised Walsh-Hadamard
+                   transforms, random signs and random permutations (dense and
+                   exactly orthogonal), built on the GPU with torch
 * ``batch_sizes`` / ``batch_matrices``  m ~ U{32..768}, n ~ U{16..m},
                    entries N(0, 1)                           (batched QR)
 """
@@ -107,6 +110,41 @@ def svd_matrix_device(seed, n, kappa, nrhs=1, noise=1e-6, device="cuda"):
     X = torch.randn((n, nrhs), generator=g, device=device, dtype=torch.float64)
     B = M @ X + noise * torch.randn((n, nrhs), generator=g, device=device, dtype=torch.float64)
     return M.t().contiguous(), B.t().contiguous(), X.t().contiguous()
+
+
+def svd_matrix_haar_device(seed, m, n, kappa, nrhs=1, noise=1e-6, device="cuda"):
+    """(A, B, X) as torch tensors on `device`: A m x n = U diag(s) V^T with U
+    (m x n) and V (n x n) the orthonormal factors of the QR of Gaussian
+    matrices (Haar distributed once the column signs make diag(R) positive),
+    computed on the GPU by torch.linalg.qr; s = logspace(0, -log10(kappa), n);
+    X ~ N(0, 1) (n x nrhs); B = A X + noise N(0, 1) (m x nrhs).  A is returned
+    as a contiguous (n, m) tensor holding A column-major; B (nrhs, m) and
+    X (nrhs, n) column-major likewise.  Seeded with a torch generator on the
+    device."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+
+    def haar(rows, cols):
+        G = torch.randn((rows, cols), generator=g, device=device, dtype=torch.float64)
+        Q, R = torch.linalg.qr(G)
+        del G
+        d = torch.sign(torch.diagonal(R))
+        d[d == 0] = 1.0
+        del R
+        return Q * d[None, :]
+
+    U = haar(m, n)
+    V = haar(n, n)
+    s = torch.logspace(0.0, -float(torch.log10(torch.tensor(kappa, dtype=torch.float64))), n, dtype=torch.float64,
+                       device=device)
+    U.mul_(s[None, :])
+    # A^T = V (U diag(s))^T, stored row-major: that is A column-major.
+    At = V @ U.t()
+    del U, V
+    X = torch.randn((nrhs, n), generator=g, device=device, dtype=torch.float64)
+    Bt = X @ At + noise * torch.randn((nrhs, m), generator=g, device=device, dtype=torch.float64)
+    return At.contiguous(), Bt.contiguous(), X.contiguous()
 
 
 def batch_sizes(seed, count=4000, m_lo=32, m_hi=768, n_lo=16):

@@ -23,7 +23,7 @@ _L = ctypes.CDLL(LIB_PATH)
 
 OK, EHIP, ENONFINITE, ENOCONV, ETIMEOUT, ENOMEM, EUNSUPPORTED, ESINGULAR = range(8)
 FP64, BF16X2, FP16X2, BF16X3 = range(4)
-FLAG_ASYNC, FLAG_SERIAL, FLAG_TRACE, FLAG_SHUFFLE, FLAG_TIMING, FLAG_NO_GRAPH = 1, 2, 4, 8, 16, 32
+FLAG_ASYNC, FLAG_SERIAL, FLAG_TRACE, FLAG_SHUFFLE, FLAG_TIMING, FLAG_NO_GRAPH, FLAG_CHECK = 1, 2, 4, 8, 16, 32, 64
 
 
 class Opts(ctypes.Structure):
@@ -42,7 +42,9 @@ class Tuning(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("eta", ctypes.c_double),
                 ("eta_hist", ctypes.c_double * 65), ("nb", ctypes.c_int64), ("ib", ctypes.c_int64),
-                ("ms_factor", ctypes.c_double), ("ms_total", ctypes.c_double)]
+                ("ms_factor", ctypes.c_double), ("ms_total", ctypes.c_double),
+                ("eta_ls", ctypes.c_double), ("eta_inf", ctypes.c_double),
+                ("beta_fact_est", ctypes.c_double), ("probes", ctypes.c_int), ("ms_worker", ctypes.c_double)]
 
 
 _i64, _int, _vp, _dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p, ctypes.c_double
@@ -69,6 +71,7 @@ _SIGS = {
     "tileqr_trace": (_i64, [_I64P, _i64]),
     "tileqr_trace_clock_hz": (_dbl, []),
     "tileqr_last_timing": (_int, [ctypes.POINTER(ctypes.c_double)]),
+    "tileqr_mfma_peak": (_int, [_int, ctypes.POINTER(ctypes.c_double)]),
     "tileqr_status_string": (ctypes.c_char_p, [_int]),
     "tileqr_last_hip_error": (ctypes.c_char_p, []),
     "tileqr_finalize": (_int, []),
@@ -192,6 +195,14 @@ def last_timing():
     ms = (ctypes.c_double * 4)()
     check(_L.tileqr_last_timing(ms), "tileqr_last_timing")
     return list(ms)
+
+
+def mfma_peak(kind):
+    """Measured MFMA rate in TFLOP/s: kind 0 FP64 16x16x4, 1 BF16 16x16x32,
+    2 FP16 16x16x32."""
+    t = ctypes.c_double()
+    check(_L.tileqr_mfma_peak(kind, ctypes.byref(t)), "tileqr_mfma_peak")
+    return t.value
 
 
 def status_string(s):

@@ -160,3 +160,76 @@ def test_mixed_ls_refinement(tq, name, kappa):
         assert eta <= 1e-14
         rel_res = np.linalg.norm(ro) / (np.linalg.norm(A, 2) * np.linalg.norm(xo))
         assert err <= 64 * n * EPS * kappa * (1 + kappa * rel_res)
+
+
+@pytest.mark.parametrize("name", ["BF16X2", "FP16X2", "BF16X3"])
+@pytest.mark.parametrize("nb", [128, 256])
+def test_mixed_whole_tile_workers(tq, name, nb):
+    # Whole tile kernels (panel_tasks = 1: the worker kind that large
+    # matrices such as 32768^2 run) against the serial Algorithm 2 driver
+    # and the panel-task split, bit for bit, then the invariants.
+    m, n = 1024, 768
+    A = synth.uniform(90 + nb, m, n)
+    p = prec_of(tq, name)
+    Fs, Ts = run_factor(tq, A, nb, 32, precision=p, flags=tq.FLAG_SERIAL)
+    F1, T1 = run_factor(tq, A, nb, 32, precision=p, panel_tasks=1)
+    Fp, Tp = run_factor(tq, A, nb, 32, precision=p, panel_tasks=nb // 32)
+    F2, T2 = run_factor(tq, A, nb, 32, precision=p, panel_tasks=1, flags=tq.FLAG_SHUFFLE, seed=5)
+    assert np.array_equal(F1, Fs) and np.array_equal(T1, Ts)
+    assert np.array_equal(F1, Fp) and np.array_equal(T1, Tp)
+    assert np.array_equal(F1, F2) and np.array_equal(T1, T2)
+    Q = rebuild_q(F1, T1, nb, 32)[:m, :m]
+    RR = np.zeros((m, n))
+    RR[:n] = r_of(F1)
+    bfact = np.linalg.norm(A - Q @ RR) / np.linalg.norm(A)
+    borth = np.linalg.norm(Q[:, :n].T @ Q[:, :n] - np.eye(n))
+    Fo, _ = oracle.geqr2(A)
+    rdiff = oracle.r_diff(r_of(F1), oracle.r_factor(Fo))
+    u = U_SPLIT[name]
+    print(f"{name} nb={nb} whole tiles: beta_fact {bfact:.2e} beta_orth {borth:.2e} R vs oracle {rdiff:.2e}")
+    assert borth <= 1e-14 * n
+    assert EPS <= bfact <= 8 * u
+    assert rdiff <= 64 * u * np.linalg.cond(A)
+
+
+@pytest.mark.parametrize("name", ["BF16X2", "BF16X3"])
+def test_bf16_splits_handle_tiny_and_huge_columns(tq, name):
+    # Columns spread over 2^-140 .. 2^140, beyond the FP32 exponent range
+    # that the BF16 parts pass through: the per-column power-of-two scaling
+    # keeps them finite and the error relative per column.
+    rng = np.random.default_rng(4)
+    A = synth.uniform(9, 512, 256) * np.exp2(rng.integers(-140, 141, size=256))[None, :]
+    F, T = run_factor(tq, A, 64, 32, precision=prec_of(tq, name))
+    assert np.all(np.isfinite(F))
+    Q = rebuild_q(F, T, 64, 32)[:512, :512]
+    RR = np.zeros((512, 256))
+    RR[:256] = r_of(F)
+    E = A - Q @ RR
+    colerr = np.linalg.norm(E, axis=0) / np.linalg.norm(A, axis=0)
+    print(f"{name}: max column error {colerr.max():.2e}")
+    assert colerr.max() <= 8 * U_SPLIT[name] * 64
+
+
+@pytest.mark.parametrize("name", ["FP16X2", "BF16X3"])
+@pytest.mark.parametrize("pt", [0, 1])
+def test_square_mixed_refinement(tq, name, pt):
+    # Square systems stop on the paper's solution backward error
+    # ||b - A x||_inf / (||A||_inf ||x||_inf) (Section 3.2.4) as well as on
+    # eta_LS; the refined x must also agree with the FP64 solution to the
+    # conditioning bound.  pt = 1 forces whole tile kernels (the large-matrix
+    # worker), pt = 0 the automatic panel-task split.
+    n, kappa = 2048, 1e6
+    A, b, _ = synth.svd_matrix(17, n, n, kappa, nrhs=3)
+    rc, x, info = solve(tq, A, b, precision=prec_of(tq, name), nb=256, ib=32, panel_tasks=pt)
+    rc64, x64, info64 = solve(tq, A, b, nb=256, ib=32)
+    assert rc64 == tq.OK
+    eta = max(oracle.eta_inf(A, x[:, v], b[:, v]) for v in range(3))
+    etals = max(oracle.eta_ls(A, x[:, v], b[:, v]) for v in range(3))
+    err = np.linalg.norm(x - x64) / np.linalg.norm(x64)
+    print(f"{name} pt={pt}: rc={tq.status_string(rc)} iterations {info.iterations} eta_inf {eta:.2e} "
+          f"(library {info.eta_inf:.2e}) eta_ls {etals:.2e} (library {info.eta_ls:.2e}) |x - x64|/|x64| {err:.2e}")
+    assert rc == tq.OK
+    assert eta <= 1e-14 and etals <= 1e-14
+    assert eta <= 2 * info.eta_inf + 1e-18
+    assert info.eta == max(info.eta_inf, info.eta_ls)
+    assert err <= 64 * n * EPS * kappa

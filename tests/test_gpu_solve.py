@@ -93,3 +93,62 @@ def test_bad_arguments(tq):
     assert tq.solve_ls(5, 6, 1, 1, 5, 1, 5, 1, 6, o, info) == -2
     assert tq.solve_ls(6, 5, 1, 1, 4, 1, 6, 1, 5, o, info) == -5
     assert tq.solve_ls(6, 5, 1, 1, 6, 1, 6, 1, 4, o, info) == -9
+
+
+@pytest.mark.parametrize("name", ["FP64", "BF16X2"])
+def test_check_flag_estimates_beta_fact(tq, name):
+    # TILEQR_FLAG_CHECK estimates ||A - Q [R; 0]||_F / ||A||_F with 8 probes;
+    # compared with the exact value of the same factorisation (tileqr_factor
+    # with the same blocking gives the same bits), Q rebuilt in numpy.
+    from test_gpu_factor import rebuild_q
+    m, n, nb, ib = 1500, 700, 128, 32
+    A, b, _ = synth.svd_matrix(8, m, n, 1e3)
+    rc, x, info = solve(tq, A, b, nb=nb, ib=ib, precision=getattr(tq, name), flags=tq.FLAG_CHECK)
+    assert rc == tq.OK
+    At = tq.to_device(A)
+    T = tq.factor_tensor(At, m, nb, ib, tq.opts(precision=getattr(tq, name)))
+    torch.cuda.synchronize()
+    F = tq.to_host(At, m)
+    Q = rebuild_q(F, T.cpu().numpy(), nb, ib)[:m, :m]
+    RR = np.zeros((m, n))
+    RR[:n] = np.triu(F[:n])
+    exact = np.linalg.norm(A - Q @ RR) / np.linalg.norm(A)
+    print(f"{name}: beta_fact exact {exact:.3e}, estimate {info.beta_fact_est:.3e} ({info.probes} probes)")
+    assert info.probes == 8
+    assert 0.3 * exact <= info.beta_fact_est <= 3.0 * exact
+
+
+def test_info_without_check(tq):
+    A, b, _ = synth.svd_matrix(2, 300, 100, 1e2)
+    rc, x, info = solve(tq, A, b, nb=64, ib=16)
+    assert rc == tq.OK
+    assert info.beta_fact_est == -1.0 and info.probes == 0
+    assert info.eta_inf == 0.0                      # m > n: not defined
+    assert info.eta == info.eta_ls
+
+
+def test_two_streams_async_match_sync(tq):
+    # Each stream has its own workspace: two asynchronous factorisations on
+    # two streams, left to overlap, give the bits of synchronous calls.
+    mats = [synth.uniform(30 + s, 1536, 1024) for s in range(2)]
+    ref = []
+    for A in mats:
+        At = tq.to_device(A)
+        T = tq.factor_tensor(At, 1536, 256, 32)
+        torch.cuda.synchronize()
+        ref.append((At.clone(), T.clone()))
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    work = [tq.to_device(A) for A in mats]
+    Ts = [torch.empty(tq.t_size(1536, 1024, 256, 32), dtype=torch.float64, device="cuda") for _ in mats]
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for s in range(2):
+            work[s].copy_(tq.to_device(mats[s]))
+        torch.cuda.synchronize()
+        for s in range(2):
+            o = tq.opts(stream=streams[s].cuda_stream, flags=tq.FLAG_ASYNC)
+            tq.check(tq.factor(1536, 1024, work[s].data_ptr(), 1536, 256, 32, Ts[s].data_ptr(), o), "factor")
+        torch.cuda.synchronize()
+        for s in range(2):
+            assert torch.equal(work[s], ref[s][0]), (rep, s)
+            assert torch.equal(Ts[s], ref[s][1]), (rep, s)
