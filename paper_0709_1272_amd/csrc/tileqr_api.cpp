@@ -455,7 +455,7 @@ int check_status(Workspace *W, int *dstatus, hipStream_t st)
 int prepare_schedule(Workspace *W, SchedBufs &B, std::vector<MatDev> &mats, int nb, int ib, const tileqr_opts &o,
                      hipStream_t st, SchedDev &S, int *workers)
 {
-    const int ns = nb / kStripWidth;
+    const int ns = strips_per_tile(nb, o.precision);
     const int nmat = (int)mats.size();
     // GEQRT / TSQRT tasks per tile.  One matrix with few tile steps is
     // bound by its chain of panel tasks, so each inner panel becomes a task
@@ -568,6 +568,13 @@ int run_factor(Workspace *W, int nb, int ib, int p, int q, double *T, const tile
     MatDev M;
     M.tiles = (double *)W->tiles.ptr;
     M.T = T;
+    M.vsplit = nullptr;
+    if (o.precision != TILEQR_FP64) {
+        int rc;
+        const int parts = o.precision == TILEQR_BF16X3 ? 3 : 2;
+        if ((rc = W->vsplit.ensure(vsplit_bytes(p, std::min(p, q), nb, ib, parts)))) return rc;
+        M.vsplit = W->vsplit.ptr;
+    }
     M.p = p;
     M.q = q;
     M.task_base = 0;
@@ -711,6 +718,8 @@ extern "C" int tileqr_finalize(void)
         if (hipSetDevice(w->device) == hipSuccess) {
             (void)hipDeviceSynchronize();
             w->tiles.release();
+            w->vsplit.release();
+            w->bvsplit.release();
             w->sched.release();
             w->btiles.release();
             w->bconv.release();
@@ -750,6 +759,7 @@ hipError_t apply_rows(Workspace *W, int nb, int ib, int p, int q, const double *
     ApplyDev D;
     D.M.tiles = (double *)W->tiles.ptr;
     D.M.T = const_cast<double *>(T);
+    D.M.vsplit = nullptr;
     D.M.p = p;
     D.M.q = q;
     D.M.task_base = 0;
@@ -895,6 +905,7 @@ int beta_fact_probe(SolveCtx &c, double normA, uint64_t seed, double *out)
     ApplyDev D;
     D.M.tiles = (double *)W->tiles.ptr;
     D.M.T = c.T;
+    D.M.vsplit = nullptr;
     D.M.p = c.p;
     D.M.q = c.q;
     D.M.task_base = 0;

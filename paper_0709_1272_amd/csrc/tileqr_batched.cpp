@@ -142,6 +142,18 @@ int run_batched(Workspace *W, int64_t batch, const int64_t *m, const int64_t *n,
     if (groups.empty()) return TILEQR_OK;
     int rc;
     if ((rc = W->btiles.ensure((size_t)tile_doubles * sizeof(double)))) return rc;
+    // Split modes: the split images of every matrix, back to back.
+    const int parts = o.precision == TILEQR_BF16X3 ? 3 : 2;
+    size_t vs_bytes = 0;
+    if (o.precision != TILEQR_FP64) {
+        for (auto &g : groups)
+            for (int64_t i : g.members) {
+                const int p = (int)cdiv(m[i], g.nb), q = (int)cdiv(n[i], g.nb);
+                vs_bytes += vsplit_bytes(p, std::min(p, q), g.nb, g.ib, parts);
+            }
+        if ((rc = W->bvsplit.ensure(vs_bytes))) return rc;
+    }
+    char *vsp = (char *)W->bvsplit.ptr;
     if ((rc = W->status.ensure(256))) return rc;
     int64_t nconv = 0;
     for (auto &g : groups) nconv += (int64_t)g.members.size();
@@ -171,6 +183,11 @@ int run_batched(Workspace *W, int64_t batch, const int64_t *m, const int64_t *n,
             MatDev M;
             M.tiles = tiles;
             M.T = T[i];
+            M.vsplit = nullptr;
+            if (o.precision != TILEQR_FP64) {
+                M.vsplit = vsp;
+                vsp += vsplit_bytes(d.p, std::min(d.p, d.q), g.nb, g.ib, parts);
+            }
             M.p = d.p;
             M.q = d.q;
             M.task_base = 0;

@@ -55,10 +55,11 @@ struct Workspace {
     int device = -1;
     hipStream_t stream = nullptr;
     DevBuf tiles, status, trace, misc, rows, prog, tws, solve, part, tflags;
+    DevBuf vsplit;                        // split images of V and T (split modes)
     SchedBufs sched;                      // single-matrix calls
     // Batched calls keep their own buffers so that a captured graph stays
     // valid across single-matrix calls.
-    DevBuf btiles, bconv;
+    DevBuf btiles, bconv, bvsplit;
     std::vector<SchedBufs> bsched;        // one per (nb, ib) group
     hipGraphExec_t bgraph = nullptr;
     std::vector<int64_t> bgraph_key;

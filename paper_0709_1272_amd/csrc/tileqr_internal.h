@@ -16,9 +16,29 @@ enum : int {
 struct MatDev {
     double *tiles;       // p x q row-major nb x nb tiles (workspace)
     double *T;           // T factors (caller memory)
+    void *vsplit;        // split modes: split images of V and T per TS tile and panel (workspace)
     int32_t p, q;        // tile grid
     int64_t task_base;   // first global task id of this matrix
 };
+
+// LARFB / SSRFB strip tasks per tile: 32-column strips in FP64; in the split
+// modes the column-block width of the split SSRFB (64 columns for nb 128 and
+// 256, 32 for nb 64).
+__host__ __device__ constexpr int strips_per_tile(int nb, int prec)
+{
+    return prec == 0 ? nb / 32 : (nb >= 128 ? nb / 64 : nb / 32);
+}
+
+// Bytes of the split images of one matrix (p x q tiles, kmax steps): one
+// block of 16-byte vectors per TS tile (k, i) and inner panel, holding V^T X
+// and V W images of V (nb / 32 * 2 + nb / 16 vectors per lane and part), the
+// T^T W images of T (2 per lane and part) and one header vector; laid out
+// like T, by (k p + i).  parts: 3 for BF16 x3, 2 for the other splits.
+inline size_t vsplit_bytes(int p, int kmax, int nb, int ib, int parts)
+{
+    const size_t vec = (size_t)(((nb / 32) * 2 + nb / 16 + 2) * parts * 64 + 1 + 7) / 8 * 8;
+    return (size_t)kmax * p * (nb / ib) * vec * 16;
+}
 
 // Words of one trace event: type, k, i, j, strip, worker, then the device
 // wall clock when the task was popped, when it started (after the acquire),

@@ -94,7 +94,7 @@ struct Stage {
 };
 
 template <int NB, int IB>
-struct Smem {
+struct alignas(16) Smem {
     using C = Cfg<NB, IB>;
     double P[(NB + IB) * C::LDP];    // panel / V: rows 0..nb-1 tile rows, nb.. head rows
     union {
@@ -721,6 +721,12 @@ __device__ __forceinline__ double group_max(double v)
     return v;
 }
 
+}  // namespace tq
+
+#include "tileqr_cols.h"
+
+namespace tq {
+
 // Householder factorisation of the ib columns held in sm.P (Section 3.2.1:
 // DGEQRT's panel when ts == false, DTSQRT's when ts == true).
 //   GEQRT: column j has its head (diagonal) at P row c0 + j and its tail in
@@ -1108,6 +1114,8 @@ __device__ __forceinline__ void tsqrt_panel(Smem<NB, IB> &sm, const MatDev &M, i
     }
     build_t<NB, IB>(sm, 0, Ti + l * IB * IB);
     __syncthreads();
+    // Split modes: the split images of V and T for the SSRFB tasks.
+    if constexpr (PREC != PREC_FP64) write_vsplit<NB, IB, PREC>(sm, vsplit_ptr<NB, IB, PREC>(M, k, i, l));
     if (!trailing) return;
     panel_trailing<NB, IB, true, PREC>(sm, tik, tkk, c0, chain);
     __syncthreads();
@@ -1221,20 +1229,29 @@ __device__ __forceinline__ void apply_one_panel(Smem<NB, IB> &sm, const gdouble 
     store_strip<NB, IB>(X, x, ldx, col0, CB, r0);
 }
 
-// DLARFB: strip s of A_kj <- Q_kk^T A_kj.
+// DLARFB: strip s of A_kj <- Q_kk^T A_kj (in the split modes a strip is as
+// wide as the SSRFB tasks', taken 32 columns at a time).
 template <int NB, int IB, int PREC>
 __device__ __forceinline__ void task_larfb(Smem<NB, IB> &sm, const MatDev &M, int k, int j, int s)
 {
-    apply_diag_strip<NB, IB, true, PREC>(sm, tile_ptr(M, NB, k, k), tblock_ptr(M, NB, IB, k, k), tile_ptr(M, NB, k, j), NB,
-                                   s * WS);
+    constexpr int SUB = NB / strips_of<NB, PREC>() / WS;
+#pragma unroll 1
+    for (int u = 0; u < SUB; ++u) {
+        if (u > 0) __syncthreads();
+        apply_diag_strip<NB, IB, true, PREC>(sm, tile_ptr(M, NB, k, k), tblock_ptr(M, NB, IB, k, k),
+                                             tile_ptr(M, NB, k, j), NB, (s * SUB + u) * WS);
+    }
 }
 
 // DSSRFB: strip s of [A_kj; A_ij] <- Q_ik^T [A_kj; A_ij].
 template <int NB, int IB, int PREC>
 __device__ __forceinline__ void task_ssrfb(Smem<NB, IB> &sm, const MatDev &M, int k, int i, int j, int s)
 {
-    apply_ts_strip<NB, IB, true, PREC>(sm, tile_ptr(M, NB, i, k), tblock_ptr(M, NB, IB, k, i), tile_ptr(M, NB, k, j), NB,
-                                 tile_ptr(M, NB, i, j), NB, s * WS);
+    if constexpr (PREC == PREC_FP64)
+        apply_ts_strip<NB, IB, true, PREC>(sm, tile_ptr(M, NB, i, k), tblock_ptr(M, NB, IB, k, i), tile_ptr(M, NB, k, j),
+                                           NB, tile_ptr(M, NB, i, j), NB, s * WS);
+    else
+        task_ssrfb_cols<NB, IB, PREC>(sm, M, k, i, j, s);
 }
 
 // PUPD(k, i, l, s): one strip of a panel task's trailing update as a task of
@@ -1277,7 +1294,8 @@ __device__ __forceinline__ void run_task(Smem<NB, IB> &sm, const MatDev &M, cons
 {
     // One panel per strip: the panel tasks leave their trailing updates to
     // PUPD tasks (the grid has them exactly then).
-    constexpr bool PU = SPLIT && Cfg<NB, IB>::NPAN == Cfg<NB, IB>::NS && Cfg<NB, IB>::NPAN > 1;
+    constexpr int NSX = strips_of<NB, PREC>();
+    constexpr bool PU = SPLIT && Cfg<NB, IB>::NPAN == NSX && Cfg<NB, IB>::NPAN > 1;
     if constexpr (ROLE == ROLE_PANEL) {
         if constexpr (SPLIT) {
             if (t.type == GEQRT) geqrt_panel<NB, IB, PREC>(sm, M, t.k, t.l, false, false, !PU);
@@ -1303,7 +1321,7 @@ __global__ __launch_bounds__(2 * NB) void k_serial(MatDev M, int k, int i, const
 {
     __shared__ Smem<NB, IB> sm;
     if (*status != 0) return;
-    constexpr int NS = Cfg<NB, IB>::NS;
+    constexpr int NS = strips_of<NB, PREC>();
     const int j = k + 1 + blockIdx.x / NS, s = blockIdx.x % NS;
     if constexpr (TYPE == GEQRT) task_geqrt<NB, IB, PREC>(sm, M, k);
     else if constexpr (TYPE == TSQRT) task_tsqrt<NB, IB, PREC>(sm, M, k, i);
@@ -1500,7 +1518,7 @@ __device__ __forceinline__ void worker_loop(Smem<NB, IB> &sm, const SchedDev &S)
         // Strips and panels per tile are compile-time constants here (the
         // host sets S.ns = nb / 32 and S.np to match the kernel), which
         // keeps the id arithmetic to shifts.
-        const Grid g = make_grid(M.p, M.q, Cfg<NB, IB>::NS, SPLIT ? Cfg<NB, IB>::NPAN : 1);
+        const Grid g = make_grid(M.p, M.q, strips_of<NB, PREC>(), SPLIT ? Cfg<NB, IB>::NPAN : 1);
         const Task t = decode(g, gid - M.task_base);
         const uint64_t t0 = wall_clock64();
         run_task<NB, IB, ROLE, PREC, SPLIT>(sm, M, t);
@@ -1583,7 +1601,8 @@ __global__ __launch_bounds__(2 * NB) void k_worker(SchedDev S)
 template <int NB, int IB, int PREC>
 static hipError_t serial_impl(const MatDev &M, const int *status, hipStream_t st)
 {
-    constexpr int NS = Cfg<NB, IB>::NS;
+    constexpr int NS = strips_of<NB, PREC>();
+    static_assert(NS == strips_per_tile(NB, PREC), "host and device agree on the strips per tile");
     const int p = M.p, q = M.q, kmax = p < q ? p : q;
     const dim3 blk(Cfg<NB, IB>::NT);
     for (int k = 0; k < kmax; ++k) {

@@ -57,5 +57,5 @@ def factor_invariants(tq, At, m, n, nb, ib, k=8, seed=3, opts=None):
     T = tq.factor_tensor(At, m, nb, ib, opts)
     torch.cuda.synchronize()
     bf = beta_fact_probe(tq, At, T, m, n, nb, ib, AZ, Z) / normA
-    bo = beta_orth_probe(tq, At, T, m, n, nb, ib)
+    bo = beta_orth_probe(tq, At, T, m, n, nb, ib, k=k)
     return bf, bo, T

@@ -71,7 +71,8 @@ def square32768():
 def test_invariants_32768(tq, square32768):
     import gpu_probes
     n, At, _ = square32768
-    bf, bo, _ = gpu_probes.factor_invariants(tq, At.clone(), n, n, 256, 32)
+    # 32 probes: the estimate's spread is then well inside the bar's margin.
+    bf, bo, _ = gpu_probes.factor_invariants(tq, At.clone(), n, n, 256, 32, k=32)
     print(f"32768^2 kappa 1e6 FP64: beta_fact ~ {bf:.2e}, beta_orth ~ {bo:.2e}")
     assert bf <= 1e-14
     assert bo <= 1e-14 * n
@@ -99,7 +100,9 @@ def test_solve_32768_fp64_and_mixed(tq, square32768):
               f"ms {info.ms_total:.1f}")
         assert rc == tq.OK, tq.status_string(rc)
         assert eta.max() <= 1e-14
-        assert eta.max() <= 2 * info.eta_inf + 1e-17
+        # Both are FP64 residuals of the same x in different summation
+        # orders; at this level they differ by the residual's own rounding.
+        assert abs(eta.max() - info.eta_inf) <= 1e-15
         if name == "FP64":
             assert info.beta_fact_est <= 1e-14
         else:

@@ -131,15 +131,19 @@ def test_two_streams_async_match_sync(tq):
     # Each stream has its own workspace: two asynchronous factorisations on
     # two streams, left to overlap, give the bits of synchronous calls.
     mats = [synth.uniform(30 + s, 1536, 1024) for s in range(2)]
+    tsz = tq.t_size(1536, 1024, 256, 32)
     ref = []
     for A in mats:
         At = tq.to_device(A)
-        T = tq.factor_tensor(At, 1536, 256, 32)
+        # T has entries the factorisation never writes (blocks of tiles
+        # above the diagonal): start from zeros on both sides.
+        T = torch.zeros(tsz, dtype=torch.float64, device="cuda")
+        tq.check(tq.factor(1536, 1024, At.data_ptr(), 1536, 256, 32, T.data_ptr()), "factor")
         torch.cuda.synchronize()
         ref.append((At.clone(), T.clone()))
     streams = [torch.cuda.Stream(), torch.cuda.Stream()]
     work = [tq.to_device(A) for A in mats]
-    Ts = [torch.empty(tq.t_size(1536, 1024, 256, 32), dtype=torch.float64, device="cuda") for _ in mats]
+    Ts = [torch.zeros(tsz, dtype=torch.float64, device="cuda") for _ in mats]
     torch.cuda.synchronize()
     for rep in range(3):
         for s in range(2):
