@@ -199,6 +199,31 @@ int tileqr_factor(int64_t m, int64_t n, double *A, int64_t lda, int64_t nb, int6
 int tileqr_factor_ex(int64_t m, int64_t n, double *A, int64_t lda, int64_t nb, int64_t ib,
                      double *T, const tileqr_opts *opts);
 
+/* Size of the fixed device array tileqr_factor_noalloc takes its workspace
+ * from (64 MiB per device, held from the library's load to the end of the
+ * process). */
+#define TILEQR_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, kernels, schedule and result (bit for bit) as tileqr_factor_ex,
+ * but no hipMalloc, hipFree or other allocating call is made: the tile
+ * workspace, the status word, the scheduler's counters and queues and (split
+ * precisions) the split images of V and T are carved from one fixed device
+ * array of TILEQR_NOALLOC_SCRATCH_BYTES per device.  A shape whose workspace
+ * does not fit (p q nb^2 doubles of tiles, 4 bytes per task id and per task,
+ * the split images) returns TILEQR_ENOMEM before anything is launched, A
+ * untouched; every shape up to 2048 x 2048 fits at each supported blocking
+ * and precision.  TILEQR_FLAG_TRACE and TILEQR_FLAG_TIMING are not supported
+ * here (TILEQR_EUNSUPPORTED).  The array is shared by every call on the
+ * device and keeps the last call's contents (each call clears what must
+ * start at zero): calls that overlap on one device (TILEQR_FLAG_ASYNC calls
+ * on two streams, or from two host threads) race and must not be issued.
+ */
+int tileqr_factor_noalloc(int64_t m, int64_t n, double *A, int64_t lda, int64_t nb, int64_t ib,
+                          double *T, const tileqr_opts *opts);
+
 /*
  * B := Q^T B (tileqr_apply_qt) or B := Q B (tileqr_apply_q) for Q of a
  * previous tileqr_factor(m, n, A, lda, nb, ib, T).  Q^T applies, for each

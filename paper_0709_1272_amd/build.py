@@ -23,6 +23,7 @@ UNITS = [("tileqr_kernels.hip", [], "tileqr_kernels"),
          ("tileqr_mixed.hip", ["-DTQ_PREC=3"], "tileqr_mixed_bf16x3"),
          ("tileqr_solve.hip", [], "tileqr_solve"),
          ("tileqr_peak.hip", [], "tileqr_peak"),
+         ("tileqr_noalloc.hip", [], "tileqr_noalloc"),
          ("tileqr_api.cpp", [], "tileqr_api"),
          ("tileqr_batched.cpp", [], "tileqr_batched")]
 SOURCES = sorted({u[0] for u in UNITS})

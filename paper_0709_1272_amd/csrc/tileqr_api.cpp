@@ -36,6 +36,14 @@ int hip_fail(hipError_t e, const char *what)
 int DevBuf::ensure(size_t need)
 {
     if (need <= bytes) return 0;
+    if (arena) {
+        const size_t off = (arena->used + 255) & ~(size_t)255;
+        if (off > arena->cap || need > arena->cap - off) return TILEQR_ENOMEM;
+        ptr = arena->base + off;
+        bytes = need;
+        arena->used = off + need;
+        return 0;
+    }
     if (ptr) (void)hipFree(ptr);
     ptr = nullptr;
     bytes = 0;
@@ -49,7 +57,7 @@ int DevBuf::ensure(size_t need)
 
 void DevBuf::release()
 {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr && !arena) (void)hipFree(ptr);
     ptr = nullptr;
     bytes = 0;
 }

@@ -27,10 +27,21 @@ constexpr int kStripWidth = 32;   // columns per LARFB/SSRFB strip task
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Grow-only device buffer.
+// A fixed region of device memory that buffers are carved from in order
+// (256-byte aligned), for calls that must not allocate.
+struct Arena {
+    char *base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+};
+
+// Grow-only device buffer.  With `arena` set, ensure() takes the buffer from
+// the arena instead of allocating, and fails with TILEQR_ENOMEM when the
+// arena is too small; release() then frees nothing.
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
+    Arena *arena = nullptr;
     int ensure(size_t need);
     void release();
 };

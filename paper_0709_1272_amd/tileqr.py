@@ -57,6 +57,7 @@ _SIGS = {
     "tileqr_t_size": (ctypes.c_size_t, [_i64, _i64, _i64, _i64]),
     "tileqr_factor": (_int, [_i64, _i64, _vp, _i64, _i64, _i64, _vp]),
     "tileqr_factor_ex": (_int, [_i64, _i64, _vp, _i64, _i64, _i64, _vp, ctypes.POINTER(Opts)]),
+    "tileqr_factor_noalloc": (_int, [_i64, _i64, _vp, _i64, _i64, _i64, _vp, ctypes.POINTER(Opts)]),
     "tileqr_apply_qt": (_int, [_i64, _i64, _i64, _vp, _i64, _i64, _i64, _vp, _vp, _i64]),
     "tileqr_apply_q": (_int, [_i64, _i64, _i64, _vp, _i64, _i64, _i64, _vp, _vp, _i64]),
     "tileqr_solve_ls": (_int, [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
@@ -126,6 +127,10 @@ def factor(m, n, A, lda, nb, ib, T, o=None):
     if o is None:
         return _L.tileqr_factor(m, n, A, lda, nb, ib, T)
     return _L.tileqr_factor_ex(m, n, A, lda, nb, ib, T, _ptr_opts(o))
+
+
+def factor_noalloc(m, n, A, lda, nb, ib, T, o=None):
+    return _L.tileqr_factor_noalloc(m, n, A, lda, nb, ib, T, _ptr_opts(o))
 
 
 def apply_qt(m, n, nrhs, A, lda, nb, ib, T, B, ldb):
