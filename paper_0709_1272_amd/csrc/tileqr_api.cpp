@@ -982,7 +982,7 @@ extern "C" int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double 
     if ((rc = W->part.ensure((size_t)part_cap * sizeof(double)))) return rc;
     if ((rc = W->misc.ensure((SMALL_PART + SMALL_PART_CAP) * sizeof(double)))) return rc;
     if ((rc = W->prog.ensure((size_t)std::min(p, q) * (nb / ib) * PROG_STRIDE * sizeof(int32_t) + 64))) return rc;
-    const int64_t tflags_cap = cdiv(n, nb) * (ldt / kStripWidth) * FLAG_STRIDE;
+    const int64_t tflags_cap = trsm_flags_needed(n, ldt);
     if ((rc = W->tflags.ensure((size_t)tflags_cap * sizeof(int32_t)))) return rc;
     const int64_t spin = o.spin_limit > 0 ? o.spin_limit : (int64_t)1 << 24;
     if ((rc = W->status.ensure(256))) return rc;

@@ -113,9 +113,10 @@ hipError_t launch_rows2cm(double *B, int64_t ldb, int64_t m, int64_t nrhs, const
 
 // Triangular solves with the tiled R on row blocks C (ldt a multiple of 32):
 // R X = C (upper) or R^T X = C, n = order of R.  One persistent launch;
-// `flags` holds flags_cap ints, ceil(n / nb) * (ldt / 32) * FLAG_STRIDE are
-// needed (hipErrorInvalidValue otherwise).
+// `flags` holds flags_cap ints, trsm_flags_needed(n, ldt) are needed
+// (hipErrorInvalidValue otherwise).
 constexpr int FLAG_STRIDE = 64;
+int64_t trsm_flags_needed(int64_t n, int ldt);
 hipError_t launch_trsm(int nb, const double *tiles, int p, int64_t n, double *C, int ldt, bool upper, int *flags,
                        int64_t flags_cap, int *status, int64_t spin_limit, hipStream_t st);
 // Y = alpha A X + beta Y (column-major A, m x n; X, Y row blocks); `part`

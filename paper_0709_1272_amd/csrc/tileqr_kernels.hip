@@ -81,9 +81,17 @@ __global__ __launch_bounds__(2 * NB) void k_apply(ApplyDev D)
     if (!first) pred = &D.prog[(k * NP + (TRANS ? l - 1 : l + 1)) * PROG_STRIDE];
     else if (TRANS ? k > 0 : k + 1 < kmax) pred = &D.prog[((TRANS ? k - 1 : k + 1) * NP + (TRANS ? NP - 1 : 0)) * PROG_STRIDE];
     const int nrow = p - k;   // blocks k .. p-1
+    // Q^T: k, k+1, .., p-1.   Q: p-1, .., k+1, then k.
+    auto row_of = [&](int qq) { return TRANS ? k + qq : (qq + 1 < nrow ? p - 1 - qq : k); };
+    // The panel of the first block is loaded before the first wait, and each
+    // later one while the previous block is applied (the factor is final).
+    Stage<NB, IB> S;
+    {
+        const int r = row_of(0);
+        apply_panel_stage<NB, IB>(S, r == k ? tkk : tile_ptr(D.M, NB, r, k), tblock_ptr(D.M, NB, IB, k, r), l, r == k);
+    }
     for (int q = 0; q < nrow; ++q) {
-        // Q^T: k, k+1, .., p-1.   Q: p-1, .., k+1, then k.
-        const int r = TRANS ? k + q : (q + 1 < nrow ? p - 1 - q : k);
+        const int r = row_of(q);
         // Block k under Q never sees step k+1 (which starts at block k+1).
         const bool wait = pred != nullptr && !(first && !TRANS && r == k);
         if (tid == 0) {
@@ -100,9 +108,9 @@ __global__ __launch_bounds__(2 * NB) void k_apply(ApplyDev D)
                         abort = 1;
                         break;
                     }
-                    // Back off (up to about 3 us between polls): the waiting
-                    // workgroups poll lines that the working ones also use.
-                    backoff = backoff < 6 ? backoff + 1 : 6;
+                    // Short back-off (up to about 0.4 us between polls): the
+                    // predecessor is usually one block ahead.
+                    backoff = backoff < 3 ? backoff + 1 : 3;
                     for (int z = 0; z < (1 << backoff); ++z) __builtin_amdgcn_s_sleep(2);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
@@ -115,17 +123,22 @@ __global__ __launch_bounds__(2 * NB) void k_apply(ApplyDev D)
 #pragma unroll 1
         for (int st = 0; st < D.nstrip; ++st) {
             if (r == k)
-                apply_one_panel<NB, IB, TRANS>(sm, tkk, tblock_ptr(D.M, NB, IB, k, k), l, true, nullptr, 0, Bk, D.ldb,
-                                               st * WS);
+                apply_one_panel<NB, IB, TRANS>(sm, S, l, true, nullptr, 0, Bk, D.ldb, st * WS);
             else
-                apply_one_panel<NB, IB, TRANS>(sm, tile_ptr(D.M, NB, r, k), tblock_ptr(D.M, NB, IB, k, r), l, false,
-                                               Bk, D.ldb, Br, D.ldb, st * WS);
+                apply_one_panel<NB, IB, TRANS>(sm, S, l, false, Bk, D.ldb, Br, D.ldb, st * WS);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __syncthreads();
         if (tid == 0) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __hip_atomic_store(&D.prog[(k * NP + l) * PROG_STRIDE], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        // Prefetch the next block's panel once this block is published
+        // (after the last block a reload of this one).
+        {
+            const int rn = row_of(q + 1 < nrow ? q + 1 : q);
+            apply_panel_stage<NB, IB>(S, rn == k ? tkk : tile_ptr(D.M, NB, rn, k), tblock_ptr(D.M, NB, IB, k, rn), l,
+                                      rn == k);
         }
     }
 }

@@ -39,42 +39,84 @@ __device__ __forceinline__ void batched_copy(int tid, int nt, Load load, Store s
 }  // namespace
 
 // Triangular solve with the tiled R on a 32-wide strip of right-hand sides,
-// one workgroup per row block i (and strip, blockIdx.y):
-//   upper == true:  R X = C,   X_i = R_ii^{-1} (C_i - sum_{j > i} R_ij X_j)
-//   upper == false: R^T X = C, X_i = R_ii^{-T} (C_i - sum_{j < i} R_ji^T X_j)
-// The workgroup applies the solved blocks X_j as soon as their workgroup
-// publishes them (progress flags, FLAG_STRIDE words apart), accumulating
-// op(R)_ij X_j in registers (4 x 4 outputs per thread, op(R) staged in LDS by
-// 32-column chunks), then solves with its diagonal tile and publishes X_i.
-// Producers have the lower workgroup indices (for R the last block comes
-// first), so every wait is on a workgroup that was dispatched earlier; every
-// wait is bounded (STATUS_TIMEOUT).  The diagonal tile is taken in 32 x 32
-// blocks: the 32 columns of op(R) holding a block are staged in LDS, the
-// block is solved by half-waves (one right-hand side per half-wave, one row
-// per lane, reciprocals of the diagonal computed once) and the rows that
-// depend on it are updated by a register-blocked product.  Rows at or beyond
-// `n` (padding) get X = 0; an exact zero on the diagonal of a real row sets
-// STATUS_SINGULAR.
-template <int NB>
-__global__ __launch_bounds__(2 * NB) void k_trsm(const double *tiles, int p, int q, int64_t n, double *C, int ldt,
-                                                 int upper, int *flags, int *status, int64_t spin_limit)
+// by row blocks of RB = 64 rows (a tile holds nb / 64 of them), one
+// workgroup of four waves per row block r (and strip, blockIdx.y):
+//   upper == true:  R X = C,   X_r = R_rr^{-1} (C_r - sum_{c > r} R_rc X_c)
+//   upper == false: R^T X = C, X_r = R_rr^{-T} (C_r - sum_{c < r} R_cr^T X_c)
+// The workgroup applies each solved block X_c as soon as its workgroup
+// publishes it (progress flags, FLAG_STRIDE words apart): op(R)_rc X_c is a
+// 64 x 64 by 64 x 32 product on v_mfma_f64_16x16x4_f64, wave w owning rows
+// 16 w .. 16 w + 15.  The K index of chunk kk and lane group g is 16 g + kk,
+// so that a lane's A operands for the 16 chunks are 16 consecutive entries
+// of one row of R (upper) and are loaded before the wait (R is final).
+// The diagonal block is then solved by substitution (backward for R,
+// forward for R^T), each wave taking 8 right-hand sides with 8 lanes per
+// right-hand side holding 8 rows each: per block of 8 rows the owning lane
+// solves its triangle locally, its 8 values go to the column's other lanes
+// by shuffles, and they update their rows.  Producers have the lower
+// workgroup indices (for R the last block comes first), so every wait is on
+// a workgroup that was dispatched earlier; every wait is bounded
+// (STATUS_TIMEOUT).  Rows at or beyond `n` (padding) get X = 0; an exact
+// zero on the diagonal of a real row sets STATUS_SINGULAR.
+constexpr int RB = 64;
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c)
 {
-    constexpr int NT = 2 * NB, NBLK = NB / 32;
-    __shared__ double Xs[NB][SW + 1];
-    __shared__ double Rc[NB][33];
-    __shared__ double dinv[32];
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_trsm(const double *tiles, int p, int nrb, int64_t n, double *C, int ldt,
+                                              int upper, int *flags, int *status, int64_t spin_limit)
+{
+    __shared__ double Xs[RB][SW + 1];
+    __shared__ double Rd[RB][RB + 1];
+    __shared__ double dinv[RB];
     __shared__ int s_abort;
-    const int tid = threadIdx.x, lane = tid & 63, hw = tid >> 5;   // half-wave index
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, ln = lane & 15, g = lane >> 4;
     const int strip = blockIdx.y, nstrip = gridDim.y, s0 = strip * SW;
-    const int i = upper ? q - 1 - (int)blockIdx.x : (int)blockIdx.x;
-    double *Ci = C + (size_t)i * NB * ldt;
-    const int rgp = tid / 8, cg = tid % 8;   // rows 4 rgp .. +3, columns 4 cg .. +3
-    double acc[4][4] = {};
-    const int nj = upper ? q - 1 - i : i;
-    for (int t = 0; t < nj; ++t) {
-        const int j = upper ? q - 1 - t : t;
+    const int r = upper ? nrb - 1 - (int)blockIdx.x : (int)blockIdx.x;
+    const int rt = r * RB / NB, ro = r * RB % NB;
+
+    // The diagonal block as the triangle solved with: Rd = op(R)_rr.
+    {
+        const double *Rt = tile_at(tiles, p, NB, rt, rt);
+        if (upper)
+            batched_copy<RB * RB / 256>(tid, 256, [&](int e) { return Rt[(size_t)(ro + e / RB) * NB + ro + e % RB]; },
+                                        [&](int e, double v) { Rd[e / RB][e % RB] = v; });
+        else
+            batched_copy<RB * RB / 256>(tid, 256, [&](int e) { return Rt[(size_t)(ro + e / RB) * NB + ro + e % RB]; },
+                                        [&](int e, double v) { Rd[e % RB][e / RB] = v; });
+        __syncthreads();
+        if (tid < RB) {
+            const double d = Rd[tid][tid];
+            const bool real = (int64_t)r * RB + tid < n;
+            if (real && d == 0.0) atomicOr(status, STATUS_SINGULAR);
+            dinv[tid] = (real && d != 0.0) ? 1.0 / d : 0.0;
+        }
+    }
+
+    d4 acc[2] = {};   // element e: row 16 w + 4 e + g, column 16 cb + ln
+    const int nc = upper ? nrb - 1 - r : r;
+    for (int u = 0; u < nc; ++u) {
+        const int c = upper ? nrb - 1 - u : u;
+        const int ct = c * RB / NB, co = c * RB % NB;
+        double a[16];
+        if (upper) {
+            const double *Rb = tile_at(tiles, p, NB, rt, ct) + (size_t)(ro + 16 * w + ln) * NB + co + 16 * g;
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) a[kk] = Rb[kk];
+        } else {
+            const double *Rb = tile_at(tiles, p, NB, ct, rt) + (size_t)(co + 16 * g) * NB + ro + 16 * w + ln;
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) a[kk] = Rb[(size_t)kk * NB];
+        }
         if (tid == 0) {
-            const int *flag = &flags[(j * nstrip + strip) * FLAG_STRIDE];
+            const int *flag = &flags[(c * nstrip + strip) * FLAG_STRIDE];
+            // The block solved just before this one is on the critical path:
+            // poll it without backing off.
+            const bool next = upper ? c == r + 1 : c == r - 1;
             int abort = 0, backoff = 0;
             int64_t spins = 0;
             while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
@@ -84,161 +126,148 @@ __global__ __launch_bounds__(2 * NB) void k_trsm(const double *tiles, int p, int
                     abort = 1;
                     break;
                 }
-                backoff = backoff < 6 ? backoff + 1 : 6;
-                for (int z = 0; z < (1 << backoff); ++z) __builtin_amdgcn_s_sleep(2);
+                if (next) {
+                    __builtin_amdgcn_s_sleep(1);
+                } else {
+                    backoff = backoff < 5 ? backoff + 1 : 5;
+                    for (int z = 0; z < (1 << backoff); ++z) __builtin_amdgcn_s_sleep(2);
+                }
             }
+            // Acquire before the barrier: the other waves read X_c after it.
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             s_abort = abort;
         }
         __syncthreads();
         if (s_abort) return;
-        if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const double *Cc = C + (size_t)c * RB * ldt;
+        batched_copy<RB * SW / 256>(tid, 256, [&](int e) { return Cc[(size_t)(e / SW) * ldt + s0 + e % SW]; },
+                                    [&](int e, double v) { Xs[e / SW][e % SW] = v; });
         __syncthreads();
-        const double *Rt = upper ? tile_at(tiles, p, NB, i, j) : tile_at(tiles, p, NB, j, i);
-        const double *Cj = C + (size_t)j * NB * ldt;
-        batched_copy<NB * SW / NT>(tid, NT, [&](int e) { return Cj[(size_t)(e / SW) * ldt + s0 + e % SW]; },
-                                   [&](int e, double v) { Xs[e / SW][e % SW] = v; });
-        for (int kc = 0; kc < NB; kc += 32) {
-            __syncthreads();
-            // Rc[row][kk] = op(R)_ij[row][kc + kk]
-            if (upper)
-                batched_copy<NB * 32 / NT>(tid, NT, [&](int e) { return Rt[(size_t)(e / 32) * NB + kc + e % 32]; },
-                                           [&](int e, double v) { Rc[e / 32][e % 32] = v; });
-            else
-                batched_copy<NB * 32 / NT>(tid, NT, [&](int e) { return Rt[(size_t)(kc + e / NB) * NB + e % NB]; },
-                                           [&](int e, double v) { Rc[e % NB][e / NB] = v; });
-            __syncthreads();
-            for (int kk = 0; kk < 32; ++kk) {
-                double a[4], b[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    a[u] = Rc[4 * rgp + u][kk];
-                    b[u] = Xs[kc + kk][4 * cg + u];
-                }
+        for (int kk = 0; kk < 16; ++kk)
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
-            }
-        }
+            for (int cb = 0; cb < 2; ++cb) acc[cb] = mfma_f64(a[kk], Xs[16 * g + kk][16 * cb + ln], acc[cb]);
         __syncthreads();
     }
-    // X_i <- C_i - accumulated products, then the diagonal solve in place.
-    batched_copy<NB * SW / NT>(tid, NT, [&](int e) { return Ci[(size_t)(e / SW) * ldt + s0 + e % SW]; },
-                               [&](int e, double v) { Xs[e / SW][e % SW] = v; });
+
+    // Y = C_r - accumulated products, in Xs.
+    double *Cr = C + (size_t)r * RB * ldt;
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int row = 16 * w + 4 * e + g, col = 16 * cb + ln;
+            Xs[row][col] = Cr[(size_t)row * ldt + s0 + col] - acc[cb][e];
+        }
     __syncthreads();
+
+    // Substitution with op(R)_rr: lane (cl, part) of wave w holds rows
+    // 8 part .. 8 part + 7 of right-hand side 8 w + cl.
+    const int cl = lane >> 3, part = lane & 7, col = 8 * w + cl;
+    double y[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int e = 0; e < 8; ++e) y[e] = Xs[8 * part + e][col];
+#pragma unroll 1
+    for (int bb = 0; bb < 8; ++bb) {
+        const int pb = upper ? 7 - bb : bb;
+        // The owning lane solves the 8 x 8 triangle of block pb (every lane
+        // runs the same steps on its own rows; only the owner's are used).
+        double z[8];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Xs[4 * rgp + u][4 * cg + v] -= acc[u][v];
-    const double *R = tile_at(tiles, p, NB, i, i);
-    for (int bb = 0; bb < NBLK; ++bb) {
-        const int b = upper ? NBLK - 1 - bb : bb;
-        __syncthreads();
-        if (upper)
-            batched_copy<NB * 32 / NT>(tid, NT, [&](int e) { return R[(size_t)(e / 32) * NB + b * 32 + e % 32]; },
-                                       [&](int e, double v) { Rc[e / 32][e % 32] = v; });
-        else
-            batched_copy<NB * 32 / NT>(tid, NT, [&](int e) { return R[(size_t)(b * 32 + e / NB) * NB + e % NB]; },
-                                       [&](int e, double v) { Rc[e % NB][e / NB] = v; });
-        __syncthreads();
-        if (tid < 32) {
-            const double d = Rc[b * 32 + tid][tid];
-            const bool real = (int64_t)i * NB + b * 32 + tid < n;
-            if (real && d == 0.0) atomicOr(status, STATUS_SINGULAR);
-            dinv[tid] = (real && d != 0.0) ? 1.0 / d : 0.0;
-        }
-        __syncthreads();
-        const int r_i = lane & 31;
-        const int64_t grow = (int64_t)i * NB + b * 32 + r_i;
-        // The half-wave's right-hand sides (columns hw, hw + HW, ..) advance
-        // together, so that their substitution chains overlap.
-        constexpr int HW = NT / 32, CPH = SW / HW;
-        double x[CPH];
+        for (int e = 0; e < 8; ++e) z[e] = y[e];
+        if (upper) {
 #pragma unroll
-        for (int u = 0; u < CPH; ++u) x[u] = Xs[b * 32 + r_i][hw + u * HW];
-        for (int qq = 0; qq < 32; ++qq) {
-            const int r = upper ? 31 - qq : qq;
-            const double rv = Rc[b * 32 + r_i][r], dr = dinv[r];
+            for (int e = 7; e >= 0; --e) {
+                z[e] *= dinv[8 * pb + e];
 #pragma unroll
-            for (int u = 0; u < CPH; ++u) {
-                const double xr = __shfl(x[u], r, 32) * dr;
-                if (r_i == r) x[u] = xr;
-                else if (upper ? r_i < r : r_i > r) x[u] -= rv * xr;
+                for (int f = 0; f < e; ++f) z[f] -= Rd[8 * pb + f][8 * pb + e] * z[e];
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                z[e] *= dinv[8 * pb + e];
+#pragma unroll
+                for (int f = e + 1; f < 8; ++f) z[f] -= Rd[8 * pb + f][8 * pb + e] * z[e];
             }
         }
+        double x[8];
+        const int owner = (lane & ~7) | pb;
 #pragma unroll
-        for (int u = 0; u < CPH; ++u) Xs[b * 32 + r_i][hw + u * HW] = grow < n ? x[u] : 0.0;
-        __syncthreads();
-        // Rows outside the block that depend on it.
-        const int r0 = upper ? 0 : (b + 1) * 32, r1 = upper ? b * 32 : NB;
-        if (4 * rgp >= r0 && 4 * rgp < r1) {
-            double d4a[4][4] = {};
-            for (int jj = 0; jj < 32; ++jj) {
-                double a[4], xv[4];
+        for (int e = 0; e < 8; ++e) x[e] = __shfl(z[e], owner, 64);
+        if (part == pb) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    a[u] = Rc[4 * rgp + u][jj];
-                    xv[u] = Xs[b * 32 + jj][4 * cg + u];
-                }
+            for (int e = 0; e < 8; ++e) y[e] = x[e];
+        } else if (upper ? part < pb : part > pb) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+            for (int f = 0; f < 8; ++f) {
+                double s = y[f];
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) d4a[u][v] += a[u] * xv[v];
+                for (int e = 0; e < 8; ++e) s -= Rd[8 * part + f][8 * pb + e] * x[e];
+                y[f] = s;
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) Xs[4 * rgp + u][4 * cg + v] -= d4a[u][v];
         }
     }
-    __syncthreads();
-    for (int e = tid; e < NB * SW; e += NT) Ci[(size_t)(e / SW) * ldt + s0 + e % SW] = Xs[e / SW][e % SW];
-    // Publish X_i: every wave waits for its stores, then one writes back
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int row = 8 * part + e;
+        Cr[(size_t)row * ldt + s0 + col] = (int64_t)r * RB + row < n ? y[e] : 0.0;
+    }
+    // Publish X_r: every wave waits for its stores, then one writes back
     // and raises the flag.
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __syncthreads();
     if (tid == 0) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __hip_atomic_store(&flags[(i * nstrip + strip) * FLAG_STRIDE], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&flags[(r * nstrip + strip) * FLAG_STRIDE], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
 // Y (row-major rows, leading dimension ldt, m x nrhs) <- alpha A X + beta Y
-// for column-major A (m x n, lda) and X in row blocks (n x nrhs, ldt).  A is
-// read once: each workgroup takes 256 rows and a slice of the columns; the
-// per-slice partial sums are written to `part` and reduced in a second pass
-// in slice order (deterministic).
+// for column-major A (m x n, lda) and X in row blocks (n x nrhs, ldt): a
+// product with 16 or 32 columns, on v_mfma_f64_16x16x4_f64.  Each wave
+// forms one 16-row tile over a slice of the columns of A (workgroup of four
+// waves: 64 rows); the K index of chunk kk and lane group g is 16 g + kk, so
+// that for each chunk the 16 lanes of a group read 16 consecutive rows of
+// one column of A (128 bytes).  A is read once.  The per-slice partial sums
+// go to `part` and are added in slice order by a second pass
+// (deterministic).
+template <int NV>
 __global__ __launch_bounds__(256) void k_gemv_n_part(const double *A, int64_t lda, int64_t m, int64_t n,
-                                                     const double *X, int ldt, int nrhs, int64_t cols_per_slice,
+                                                     const double *X, int ldt, int nr, int64_t cols_per_slice,
                                                      double *part)
 {
-    __shared__ double xs[64][SW];
-    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, ln = lane & 15, g = lane >> 4;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + w) * 16;
+    if (row0 >= m) return;
+    const int64_t row = row0 + ln;
+    const bool rin = row < m;
+    const double *Ar = A + (rin ? row : m - 1);
     const int64_t c0 = (int64_t)blockIdx.y * cols_per_slice, c1 = std::min<int64_t>(n, c0 + cols_per_slice);
-    const int nr = std::min(nrhs, SW);
-    double acc[SW];
+    d4 acc[NV] = {};
+    for (int64_t kb = c0; kb < c1; kb += 64) {
+        double a[16], b[NV][16];
 #pragma unroll
-    for (int v = 0; v < SW; ++v) acc[v] = 0.0;
-    for (int64_t cb = c0; cb < c1; cb += 64) {
-        __syncthreads();
-        batched_copy<64 * SW / 256>((int)threadIdx.x, 256,
-                                    [&](int e) {
-                                        const int64_t c = cb + e / SW;
-                                        return (c < c1 && e % SW < nr) ? X[c * ldt + e % SW] : 0.0;
-                                    },
-                                    [&](int e, double v) { xs[e / SW][e % SW] = v; });
-        __syncthreads();
-        if (row < m) {
-            const int cn = (int)std::min<int64_t>(64, c1 - cb);
-            for (int j = 0; j < cn; ++j) {
-                const double a = A[(cb + j) * lda + row];
+        for (int kk = 0; kk < 16; ++kk) {
+            const int64_t k = kb + 16 * g + kk;
+            const bool kin = k < c1;
+            a[kk] = (kin && rin) ? Ar[k * lda] : 0.0;
 #pragma unroll
-                for (int v = 0; v < SW; ++v) acc[v] += a * xs[j][v];
-            }
+            for (int cb = 0; cb < NV; ++cb) b[cb][kk] = kin ? X[k * ldt + 16 * cb + ln] : 0.0;
         }
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk)
+#pragma unroll
+            for (int cb = 0; cb < NV; ++cb) acc[cb] = mfma_f64(a[kk], b[cb][kk], acc[cb]);
     }
-    if (row < m)
-        for (int v = 0; v < nr; ++v) part[((int64_t)blockIdx.y * m + row) * SW + v] = acc[v];
+    // Element e of acc[cb]: row row0 + 4 e + g, column 16 cb + ln.
+#pragma unroll
+    for (int cb = 0; cb < NV; ++cb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t rr = row0 + 4 * e + g;
+            const int v = 16 * cb + ln;
+            if (rr < m && v < nr) part[((int64_t)blockIdx.y * m + rr) * SW + v] = acc[cb][e];
+        }
 }
 
 __global__ void k_gemv_n_sum(const double *part, int nslice, int64_t m, int nrhs, double alpha, double beta, double *Y,
@@ -254,48 +283,56 @@ __global__ void k_gemv_n_sum(const double *part, int nslice, int64_t m, int nrhs
     }
 }
 
-// Y (n x nrhs rows) <- alpha A^T R + beta Y.  Workgroup (x, y) takes 64
-// columns of A and a slice of its rows: per chunk of 64 rows the chunk of R
-// and the 64 x 64 block of A are staged in LDS (A read once, coalesced down
-// its columns), each thread keeps 8 outputs (one column, 8 right-hand
-// sides); the per-slice partial sums go to `part` and a second pass adds
-// them in slice order (deterministic).
+// Y (n x nrhs rows) <- alpha A^T R + beta Y, on v_mfma_f64_16x16x4_f64.
+// Workgroup (x, y) takes 64 columns of A and a slice of its rows: per chunk
+// of 64 rows the 64 x 64 block of A is staged in LDS (read once, coalesced
+// down its columns) and wave w forms the 16 x (16 NV) tile of columns
+// 16 w .. 16 w + 15 (A^T as the left operand from LDS, R from memory, the K
+// index of chunk kk and lane group g is 16 g + kk).  The per-slice partial
+// sums go to `part` and a second pass adds them in slice order
+// (deterministic).
+template <int NV>
 __global__ __launch_bounds__(256) void k_gemv_t_part(const double *A, int64_t lda, int64_t m, int64_t n,
                                                      const double *Rv, int ldt, int nr, int64_t rows_per_slice,
                                                      double *part)
 {
-    __shared__ double rs[64][SW + 1];
-    __shared__ double as[64][65];
-    const int tid = threadIdx.x, cl = tid % 64, vg = tid / 64;
+    __shared__ double as[64][66];   // as[column][row]
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, ln = lane & 15, g = lane >> 4;
     const int64_t c0 = (int64_t)blockIdx.x * 64;
     const int64_t r0 = (int64_t)blockIdx.y * rows_per_slice, r1 = std::min<int64_t>(m, r0 + rows_per_slice);
-    double acc[8] = {};
+    d4 acc[NV] = {};
     for (int64_t rb = r0; rb < r1; rb += 64) {
         __syncthreads();
-        batched_copy<64 * SW / 256>(tid, 256,
-                                    [&](int e) {
-                                        const int64_t row = rb + e / SW;
-                                        return (row < r1 && e % SW < nr) ? Rv[row * ldt + e % SW] : 0.0;
-                                    },
-                                    [&](int e, double v) { rs[e / SW][e % SW] = v; });
         batched_copy<64 * 64 / 256>(tid, 256,
                                     [&](int e) {
                                         const int64_t row = rb + e % 64, col = c0 + e / 64;
                                         return (row < r1 && col < n) ? A[col * lda + row] : 0.0;
                                     },
                                     [&](int e, double v) { as[e / 64][e % 64] = v; });
-        __syncthreads();
-        for (int rr = 0; rr < 64; ++rr) {
-            const double a = as[cl][rr];
+        double b[NV][16];
 #pragma unroll
-            for (int v = 0; v < 8; ++v) acc[v] += a * rs[rr][vg * 8 + v];
+        for (int kk = 0; kk < 16; ++kk) {
+            const int64_t row = rb + 16 * g + kk;
+#pragma unroll
+            for (int cb = 0; cb < NV; ++cb) b[cb][kk] = row < r1 ? Rv[row * ldt + 16 * cb + ln] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            const double a = as[16 * w + ln][16 * g + kk];
+#pragma unroll
+            for (int cb = 0; cb < NV; ++cb) acc[cb] = mfma_f64(a, b[cb][kk], acc[cb]);
         }
     }
-    const int64_t col = c0 + cl;
-    if (col < n)
+    // Element e of acc[cb]: column c0 + 16 w + 4 e + g of A, right-hand side 16 cb + ln.
 #pragma unroll
-        for (int v = 0; v < 8; ++v)
-            if (vg * 8 + v < nr) part[((int64_t)blockIdx.y * n + col) * SW + vg * 8 + v] = acc[v];
+    for (int cb = 0; cb < NV; ++cb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t col = c0 + 16 * w + 4 * e + g;
+            const int v = 16 * cb + ln;
+            if (col < n && v < nr) part[((int64_t)blockIdx.y * n + col) * SW + v] = acc[cb][e];
+        }
 }
 
 __global__ void k_gemv_t_sum(const double *part, int nslice, int64_t n, int nr, double alpha, double beta, double *Y,
@@ -348,12 +385,20 @@ __global__ void k_colsq_sum(const double *part, int nblk, int nrhs, double *out)
 __global__ __launch_bounds__(256) void k_frob_part(const double *A, int64_t lda, int64_t m, int64_t n, double *part)
 {
     __shared__ double red[256];
-    double s = 0.0;
+    // Eight rows per thread and pass, in eight partial sums, so that eight
+    // loads are in flight together; the sums are added in a fixed order.
+    double s8[8] = {};
     for (int64_t c = blockIdx.x; c < n; c += gridDim.x)
-        for (int64_t r = threadIdx.x; r < m; r += 256) {
-            const double a = A[c * lda + r];
-            s += a * a;
+        for (int64_t r0 = threadIdx.x; r0 < m; r0 += 256 * 8) {
+            double a[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[u] = r0 + 256 * u < m ? A[c * lda + r0 + 256 * u] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) s8[u] += a[u] * a[u];
         }
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += s8[u];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
@@ -535,21 +580,22 @@ template <int NB>
 static hipError_t trsm_impl(const double *tiles, int p, int64_t n, double *C, int ldt, bool upper, int *flags,
                             int *status, int64_t spin_limit, hipStream_t st)
 {
-    const int q = (int)((n + NB - 1) / NB);
+    const int nrb = (int)((n + RB - 1) / RB);
     const int nstrip = ldt / SW;
-    hipLaunchKernelGGL(k_fill_flags, dim3((unsigned)std::max(1, std::min(1024, (q * nstrip + 255) / 256))), dim3(256),
-                       0, st, flags, q * nstrip);
-    hipLaunchKernelGGL(k_trsm<NB>, dim3(q, nstrip), dim3(2 * NB), 0, st, tiles, p, q, n, C, ldt, upper ? 1 : 0, flags,
-                       status, spin_limit);
+    hipLaunchKernelGGL(k_fill_flags, dim3((unsigned)std::max(1, std::min(1024, (nrb * nstrip + 255) / 256))),
+                       dim3(256), 0, st, flags, nrb * nstrip);
+    hipLaunchKernelGGL(k_trsm<NB>, dim3(nrb, nstrip), dim3(256), 0, st, tiles, p, nrb, n, C, ldt, upper ? 1 : 0,
+                       flags, status, spin_limit);
     return hipGetLastError();
 }
+
+int64_t trsm_flags_needed(int64_t n, int ldt) { return (n + RB - 1) / RB * (ldt / SW) * FLAG_STRIDE; }
 
 hipError_t launch_trsm(int nb, const double *tiles, int p, int64_t n, double *C, int ldt, bool upper, int *flags,
                        int64_t flags_cap, int *status, int64_t spin_limit, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    const int64_t q = (n + nb - 1) / nb;
-    if (q * (ldt / SW) * FLAG_STRIDE > flags_cap) return hipErrorInvalidValue;
+    if (trsm_flags_needed(n, ldt) > flags_cap) return hipErrorInvalidValue;
     if (nb == 64) return trsm_impl<64>(tiles, p, n, C, ldt, upper, flags, status, spin_limit, st);
     if (nb == 128) return trsm_impl<128>(tiles, p, n, C, ldt, upper, flags, status, spin_limit, st);
     if (nb == 256) return trsm_impl<256>(tiles, p, n, C, ldt, upper, flags, status, spin_limit, st);
@@ -562,12 +608,18 @@ hipError_t launch_gemv_n(const double *A, int64_t lda, int64_t m, int64_t n, con
     if (m <= 0 || nrhs <= 0) return hipSuccess;
     for (int v0 = 0; v0 < nrhs; v0 += SW) {
         const int nr = std::min(SW, nrhs - v0);
-        const int64_t rowblk = (m + 255) / 256;
-        int64_t nslice = std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 2048 / std::max<int64_t>(1, rowblk) + 1));
+        const int64_t rowblk = (m + 63) / 64;
+        // About 8192 waves in flight: slices of the columns when the rows alone give fewer.
+        int64_t nslice = std::max<int64_t>(1, std::min<int64_t>((n + 63) / 64, 2048 / rowblk));
         nslice = std::min<int64_t>(nslice, std::max<int64_t>(1, part_cap / (m * SW)));
-        const int64_t cps = (n + nslice - 1) / nslice;
-        hipLaunchKernelGGL(k_gemv_n_part, dim3((unsigned)rowblk, (unsigned)nslice), dim3(256), 0, st, A, lda, m, n,
-                           X + v0, ldt, nr, cps, part);
+        const int64_t cps = ((n + nslice - 1) / nslice + 63) / 64 * 64;
+        nslice = std::max<int64_t>(1, (n + cps - 1) / cps);
+        if (nr <= 16)
+            hipLaunchKernelGGL(k_gemv_n_part<1>, dim3((unsigned)rowblk, (unsigned)nslice), dim3(256), 0, st, A, lda,
+                               m, n, X + v0, ldt, nr, cps, part);
+        else
+            hipLaunchKernelGGL(k_gemv_n_part<2>, dim3((unsigned)rowblk, (unsigned)nslice), dim3(256), 0, st, A, lda,
+                               m, n, X + v0, ldt, nr, cps, part);
         const int64_t blocks = std::min<int64_t>((m * nr + 255) / 256, 4096);
         hipLaunchKernelGGL(k_gemv_n_sum, dim3((unsigned)blocks), dim3(256), 0, st, part, (int)nslice, m, nr, alpha,
                            beta, Y + v0, ldt);
@@ -587,8 +639,12 @@ hipError_t launch_gemv_t(const double *A, int64_t lda, int64_t m, int64_t n, con
     nslice = std::max<int64_t>(1, (m + rps - 1) / rps);
     for (int v0 = 0; v0 < nrhs; v0 += SW) {
         const int nr = std::min(SW, nrhs - v0);
-        hipLaunchKernelGGL(k_gemv_t_part, dim3((unsigned)colblk, (unsigned)nslice), dim3(256), 0, st, A, lda, m, n,
-                           R + v0, ldt, nr, rps, part);
+        if (nr <= 16)
+            hipLaunchKernelGGL(k_gemv_t_part<1>, dim3((unsigned)colblk, (unsigned)nslice), dim3(256), 0, st, A, lda,
+                               m, n, R + v0, ldt, nr, rps, part);
+        else
+            hipLaunchKernelGGL(k_gemv_t_part<2>, dim3((unsigned)colblk, (unsigned)nslice), dim3(256), 0, st, A, lda,
+                               m, n, R + v0, ldt, nr, rps, part);
         const int64_t blocks = std::min<int64_t>((n * nr + 255) / 256, 4096);
         hipLaunchKernelGGL(k_gemv_t_sum, dim3((unsigned)blocks), dim3(256), 0, st, part, (int)nslice, n, nr, alpha,
                            beta, Y + v0, ldt);

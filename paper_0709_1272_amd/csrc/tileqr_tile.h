@@ -1206,17 +1206,24 @@ __device__ __forceinline__ void apply_ts_strip(Smem<NB, IB> &sm, const gdouble *
 // strip (32 columns at col0) of x: H_l^T (TRANS) or H_l.  With `diag`, vt
 // is a diagonal tile (V unit lower triangular from row l ib, the rows above
 // untouched); otherwise the coupled TS form, whose ib top rows are rows
-// [l ib, (l+1) ib) of `top`.  Loads the strip, applies the panel and
-// stores back the rows it changed, so that consecutive panels may run on
+// [l ib, (l+1) ib) of `top`.  S holds the panel and its T as
+// apply_panel_stage loaded them (the caller may issue that load early: the
+// factor does not change).  Loads the strip, applies the panel and stores
+// back the rows it changed, so that consecutive panels may run on
 // different workgroups.
+template <int NB, int IB>
+__device__ __forceinline__ void apply_panel_stage(Stage<NB, IB> &S, const gdouble *vt, const gdouble *Tg, int l, bool diag)
+{
+    const int c0 = l * IB;
+    stage_load_rows<NB, IB>(S, vt, c0, diag ? c0 : 0, Tg + l * IB * IB);
+}
+
 template <int NB, int IB, bool TRANS>
-__device__ __forceinline__ void apply_one_panel(Smem<NB, IB> &sm, const gdouble *vt, const gdouble *Tg, int l, bool diag,
+__device__ __forceinline__ void apply_one_panel(Smem<NB, IB> &sm, const Stage<NB, IB> &S, int l, bool diag,
                                                 gdouble *top, int ldtop, gdouble *x, int ldx, int col0)
 {
     using C = Cfg<NB, IB>;
     const int c0 = l * IB, r0 = diag ? c0 : 0;
-    Stage<NB, IB> S;
-    stage_load_rows<NB, IB>(S, vt, c0, r0, Tg + l * IB * IB);
     Strip<NB, IB> X;
     load_strip<NB, IB>(X, x, ldx, col0, CB);
     gdouble *tp = diag ? nullptr : top + (size_t)c0 * ldtop + col0;
