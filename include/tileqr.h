@@ -294,6 +294,49 @@ int tileqr_factor_batched(int64_t batch, const int64_t *m, const int64_t *n,
                           double *const *A, const int64_t *lda, const int64_t *nb,
                           const int64_t *ib, double *const *T, const tileqr_opts *opts);
 
+/* Outcome of a tileqr_solve_ls_batched call. */
+typedef struct {
+    int64_t converged;      /* matrices whose backward error reached tol         */
+    int64_t not_converged;  /* matrices returned with their best iterate         */
+    int max_iterations;     /* most refinement steps any matrix took             */
+    double max_eta;         /* largest backward error over the batch             */
+    double ms_factor;       /* device time of the batched factorisation          */
+    double ms_total;        /* device time of the whole call                     */
+} tileqr_batch_info;
+
+/*
+ * Least squares for `batch` independent systems min ||b_i - A_i x_i||_2,
+ * one right-hand side each (m_i >= n_i), the batched counterpart of
+ * tileqr_solve_ls: the matrices are factored together as in
+ * tileqr_factor_batched (a copy in the library's tiles; A_i and b_i are not
+ * written), in opts->precision, then one workgroup per matrix forms
+ * (Q^T b)(0:n), solves with R and refines with FP64 residuals on A_i
+ * (Bjorck's augmented-system refinement for m > n, classical refinement for
+ * m == n) until its own backward error (eta_ls, and for m == n the larger of
+ * eta_ls and eta_inf, as in tileqr_solve_ls) is <= opts->tol, for at most
+ * opts->max_iter steps, stopping early after two steps that do not halve it
+ * (Section 3.2.4 advises checking the backward error and refining).
+ *   m, n, lda      : host arrays of `batch` entries (n_i = 0: nothing done)
+ *   A, b, x        : host arrays of `batch` device pointers; A_i column-major
+ *                    m_i x n_i, b_i m_i entries, x_i n_i entries (written:
+ *                    the iterate with the smallest backward error)
+ *   opts           : precision, tol, max_iter, stream; opts->nb and ib both
+ *                    0 (the tuner's or the default blocking for the batch)
+ *                    or a blocking used for every matrix
+ *   eta, iterations: optional HOST arrays of `batch` entries receiving each
+ *                    matrix's backward error and refinement steps
+ *   info           : optional summary (synchronous call)
+ * Returns TILEQR_ENOCONV if some matrix stayed above tol (its best iterate is
+ * in x_i), TILEQR_ESINGULAR for an exact zero on some R's diagonal,
+ * TILEQR_ENONFINITE for NaN/Inf in some A_i (nothing solved).
+ * Errors: -1 batch, -2 m, -3 n (n > m), -4 A, -5 lda, -6 b, -7 x, -8 opts
+ * (TILEQR_FLAG_ASYNC, _SERIAL and _TRACE give TILEQR_EUNSUPPORTED).
+ */
+int tileqr_solve_ls_batched(int64_t batch, const int64_t *m, const int64_t *n,
+                            const double *const *A, const int64_t *lda, const double *const *b,
+                            double *const *x, const tileqr_opts *opts, double *eta,
+                            int32_t *iterations, tileqr_batch_info *info);
+
 /*
  * Autotuner: times trial factorisations of synthetic matrices with the given
  * shapes (batch >= 1; batch = 1 tunes one m x n matrix) in the given

@@ -24,6 +24,7 @@ UNITS = [("tileqr_kernels.hip", [], "tileqr_kernels"),
          ("tileqr_solve.hip", [], "tileqr_solve"),
          ("tileqr_peak.hip", [], "tileqr_peak"),
          ("tileqr_noalloc.hip", [], "tileqr_noalloc"),
+         ("tileqr_lsbatch.hip", [], "tileqr_lsbatch"),
          ("tileqr_api.cpp", [], "tileqr_api"),
          ("tileqr_batched.cpp", [], "tileqr_batched")]
 SOURCES = sorted({u[0] for u in UNITS})

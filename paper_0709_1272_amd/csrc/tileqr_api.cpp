@@ -129,16 +129,16 @@ extern "C" int tileqr_blocking_supported(int64_t nb, int64_t ib)
     return nb % ib == 0 && ib <= nb;
 }
 
-extern "C" int tileqr_choose_blocking(int64_t m, int64_t n, int precision, int64_t *nb, int64_t *ib)
+namespace tq {
+
+// tileqr_choose_blocking with g_mu already held by the caller.
+void choose_blocking_held(int64_t m, int64_t n, int precision, int64_t *nb, int64_t *ib)
 {
-    {
-        std::lock_guard<std::mutex> lock(g_mu);
-        tileqr_tuning t;
-        if (tuned_single(m, n, precision, &t)) {
-            if (nb) *nb = t.nb;
-            if (ib) *ib = t.ib;
-            return 0;
-        }
+    tileqr_tuning t;
+    if (tuned_single(m, n, precision, &t)) {
+        if (nb) *nb = t.nb;
+        if (ib) *ib = t.ib;
+        return;
     }
     // Measured with one task per inner panel (the automatic split for up to
     // 32 tile steps) and, at ib = 32, PUPD tasks for the in-tile updates:
@@ -153,6 +153,14 @@ extern "C" int tileqr_choose_blocking(int64_t m, int64_t n, int precision, int64
     if (precision != TILEQR_FP64) s = 32;   // the split products take ib = 32
     if (nb) *nb = b;
     if (ib) *ib = s;
+}
+
+}  // namespace tq
+
+extern "C" int tileqr_choose_blocking(int64_t m, int64_t n, int precision, int64_t *nb, int64_t *ib)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    choose_blocking_held(m, n, precision, nb, ib);
     return 0;
 }
 
@@ -731,6 +739,10 @@ extern "C" int tileqr_finalize(void)
             w->sched.release();
             w->btiles.release();
             w->bconv.release();
+            w->lsT.release();
+            w->lswork.release();
+            w->lsdesc.release();
+            w->lsout.release();
             for (auto &b : w->bsched) b.release();
             if (w->bgraph) (void)hipGraphExecDestroy(w->bgraph);
             if (w->cap_stream) (void)hipStreamDestroy(w->cap_stream);

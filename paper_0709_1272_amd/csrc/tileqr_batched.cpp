@@ -64,7 +64,33 @@ void default_batch_blocking(int64_t batch, const int64_t *m, const int64_t *n, i
         ksum += f * (double)std::min(m[i], n[i]);
     }
     const int64_t k = wsum > 0.0 ? (int64_t)(ksum / wsum) : 1;
-    tileqr_choose_blocking(k, k, precision, nb, ib);
+    choose_blocking_held(k, k, precision, nb, ib);   // g_mu is held by every caller
+}
+
+// Per-matrix blocking of a batched call: the caller's, or the tuner's entry
+// for these shapes (with its split of the workgroups), or the default.
+void batch_blocking(int64_t batch, const int64_t *m, const int64_t *n, const int64_t *nb, const int64_t *ib,
+                    tileqr_opts &o, std::vector<int64_t> &nbv, std::vector<int64_t> &ibv)
+{
+    if (nb) {
+        nbv.assign(nb, nb + batch);
+        ibv.assign(ib, ib + batch);
+        return;
+    }
+    int64_t b = 0, s = 0;
+    const tileqr_tuning *t = find_tuned(shape_key(batch, m, n, o.precision));
+    if (t) {
+        b = t->nb;
+        s = t->ib;
+        if (o.panel_workers == 0 && o.workers == 0) {
+            o.panel_workers = t->panel_workers;
+            o.workers = t->workers;
+        }
+    } else {
+        default_batch_blocking(batch, m, n, o.precision, &b, &s);
+    }
+    nbv.assign((size_t)batch, b);
+    ibv.assign((size_t)batch, s);
 }
 
 int argcheck(int64_t batch, const int64_t *m, const int64_t *n, double *const *A, const int64_t *lda,
@@ -90,10 +116,10 @@ int argcheck(int64_t batch, const int64_t *m, const int64_t *n, double *const *A
 
 // The kernels of one call in stream order: clear the status, convert every
 // matrix to tiles, then per group the scheduler set-up and the persistent
-// workers, then convert every matrix back.  No memset nodes, so that the
-// sequence may be captured.
+// workers, then (with `back`) convert every matrix back.  No memset nodes,
+// so that the sequence may be captured.
 int enqueue_batched(Workspace *W, std::vector<Group> &groups, const ConvDesc *conv_dev, int precision,
-                    hipStream_t st)
+                    hipStream_t st, bool back = true)
 {
     int *dstatus = (int *)W->status.ptr;
     TQ_HIP(launch_fill_int(dstatus, 1, 0, st));
@@ -106,6 +132,7 @@ int enqueue_batched(Workspace *W, std::vector<Group> &groups, const ConvDesc *co
         TQ_HIP(launch_sched_init(g.S, st));
         TQ_HIP(launch_worker(g.nb, g.ib, precision, g.S, g.workers, st));
     }
+    if (!back) return 0;
     off = 0;
     for (auto &g : groups) {
         TQ_HIP(launch_tile2cm_batched(conv_dev + off, (int)g.members.size(), g.nblk, g.nb, dstatus, st));
@@ -115,9 +142,12 @@ int enqueue_batched(Workspace *W, std::vector<Group> &groups, const ConvDesc *co
 }
 
 // Arguments already checked, g_mu held.  nbv/ibv: per-matrix blocking.
+// With tiles_out (least squares): the factored tiles stay in the workspace,
+// A is only read (no conversion back), the kernels are launched directly,
+// and tiles_out[i] receives matrix i's first tile.
 int run_batched(Workspace *W, int64_t batch, const int64_t *m, const int64_t *n, double *const *A,
                 const int64_t *lda, const int64_t *nbv, const int64_t *ibv, double *const *T, const tileqr_opts &o,
-                hipStream_t st)
+                hipStream_t st, std::vector<const double *> *tiles_out = nullptr)
 {
     std::vector<Group> groups;
     int64_t tile_doubles = 0;
@@ -192,6 +222,7 @@ int run_batched(Workspace *W, int64_t batch, const int64_t *m, const int64_t *n,
             M.q = d.q;
             M.task_base = 0;
             mats.push_back(M);
+            if (tiles_out) (*tiles_out)[(size_t)i] = tiles;
             tiles += (size_t)d.p * d.q * g.nb * g.nb;
         }
         if ((rc = prepare_schedule(W, W->bsched[gi], mats, g.nb, g.ib, o, st, g.S, &g.workers))) return rc;
@@ -200,6 +231,7 @@ int run_batched(Workspace *W, int64_t batch, const int64_t *m, const int64_t *n,
     TQ_HIP(hipMemcpyAsync(W->bconv.ptr, conv_all.data(), conv_all.size() * sizeof(ConvDesc), hipMemcpyHostToDevice,
                           st));
 
+    if (tiles_out) return enqueue_batched(W, groups, conv_dev, o.precision, st, false);
     if (o.flags & TILEQR_FLAG_NO_GRAPH) return enqueue_batched(W, groups, conv_dev, o.precision, st);
 
     // Everything the captured launches hold by value.
@@ -261,25 +293,7 @@ extern "C" int tileqr_factor_batched(int64_t batch, const int64_t *m, const int6
     Workspace *W = workspace(st);
     if (!W) return hip_fail(hipErrorNoDevice, "workspace");
     std::vector<int64_t> nbv, ibv;
-    if (nb) {
-        nbv.assign(nb, nb + batch);
-        ibv.assign(ib, ib + batch);
-    } else {
-        int64_t b = 0, s = 0;
-        const tileqr_tuning *t = find_tuned(shape_key(batch, m, n, o.precision));
-        if (t) {
-            b = t->nb;
-            s = t->ib;
-            if (o.panel_workers == 0 && o.workers == 0) {
-                o.panel_workers = t->panel_workers;
-                o.workers = t->workers;
-            }
-        } else {
-            default_batch_blocking(batch, m, n, o.precision, &b, &s);
-        }
-        nbv.assign((size_t)batch, b);
-        ibv.assign((size_t)batch, s);
-    }
+    batch_blocking(batch, m, n, nb, ib, o, nbv, ibv);
     const bool timing = (o.flags & TILEQR_FLAG_TIMING) && !(o.flags & TILEQR_FLAG_ASYNC);
     W->have_timing = false;
     if (timing && !W->ev[0])
@@ -457,4 +471,140 @@ extern "C" int tileqr_tune(int64_t batch, const int64_t *m, const int64_t *n, in
     if (!found) tab->push_back(TuneEntry{key, top});
     *best = top;
     return TILEQR_OK;
+}
+
+extern "C" int tileqr_solve_ls_batched(int64_t batch, const int64_t *m, const int64_t *n, const double *const *A,
+                                       const int64_t *lda, const double *const *b, double *const *x,
+                                       const tileqr_opts *opts, double *eta, int32_t *iterations,
+                                       tileqr_batch_info *info)
+{
+    if (batch < 0) return -1;
+    if (batch > 0 && (!m || !n || !A || !lda || !b || !x)) return !m ? -2 : !n ? -3 : !A ? -4 : !lda ? -5 : !b ? -6 : -7;
+    for (int64_t i = 0; i < batch; ++i) {
+        if (m[i] < 0 || m[i] > INT32_MAX) return -2;
+        if (n[i] < 0 || n[i] > m[i]) return -3;
+        if (n[i] > 0 && A[i] == nullptr) return -4;
+        if (lda[i] < std::max<int64_t>(1, m[i])) return -5;
+        if (n[i] > 0 && b[i] == nullptr) return -6;
+        if (n[i] > 0 && x[i] == nullptr) return -7;
+    }
+    tileqr_opts o;
+    tileqr_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.precision < TILEQR_FP64 || o.precision > TILEQR_BF16X3) return -8;
+    if (o.max_iter < 0 || o.max_iter > 64 || !(o.tol >= 0.0)) return -8;
+    if ((o.nb == 0) != (o.ib == 0)) return -8;
+    if (o.flags & (TILEQR_FLAG_SERIAL | TILEQR_FLAG_TRACE | TILEQR_FLAG_ASYNC)) return TILEQR_EUNSUPPORTED;
+    if (info) std::memset(info, 0, sizeof *info);
+    if (batch == 0) return TILEQR_OK;
+    std::lock_guard<std::mutex> lock(g_mu);
+    hipStream_t st = (hipStream_t)o.stream;
+    Workspace *W = workspace(st);
+    if (!W) return hip_fail(hipErrorNoDevice, "workspace");
+    std::vector<int64_t> nbv, ibv, nbu, ibu;
+    if (o.nb) {
+        nbu.assign((size_t)batch, o.nb);
+        ibu.assign((size_t)batch, o.ib);
+    }
+    batch_blocking(batch, m, n, o.nb ? nbu.data() : nullptr, o.nb ? ibu.data() : nullptr, o, nbv, ibv);
+    for (int64_t i = 0; i < batch; ++i)
+        if (n[i] > 0 && (!tileqr_blocking_supported(nbv[(size_t)i], ibv[(size_t)i]) ||
+                         !precision_supported(o.precision, ibv[(size_t)i])))
+            return TILEQR_EUNSUPPORTED;
+    // T blocks and the solver's scratch vectors, per matrix, back to back.
+    std::vector<size_t> toff((size_t)batch + 1, 0), woff((size_t)batch + 1, 0);
+    for (int64_t i = 0; i < batch; ++i) {
+        const bool empty = n[i] == 0;
+        toff[(size_t)i + 1] = toff[(size_t)i] + (empty ? 0 : tileqr_t_size(m[i], n[i], nbv[(size_t)i], ibv[(size_t)i]));
+        woff[(size_t)i + 1] = woff[(size_t)i] + (empty ? 0 : (size_t)7 * cdiv(m[i], nbv[(size_t)i]) * nbv[(size_t)i]);
+    }
+    int rc;
+    if ((rc = W->lsT.ensure(std::max<size_t>(1, toff.back()) * sizeof(double)))) return rc;
+    if ((rc = W->lswork.ensure(std::max<size_t>(1, woff.back()) * sizeof(double)))) return rc;
+    std::vector<double *> Tp((size_t)batch), Ap((size_t)batch);
+    std::vector<int64_t> mf((size_t)batch), nf((size_t)batch);
+    for (int64_t i = 0; i < batch; ++i) {
+        Tp[(size_t)i] = (double *)W->lsT.ptr + toff[(size_t)i];
+        Ap[(size_t)i] = const_cast<double *>(A[i]);   // only read: no conversion back in this mode
+        mf[(size_t)i] = n[i] == 0 ? 0 : m[i];           // m > 0 = n: nothing to factor or solve
+        nf[(size_t)i] = n[i];
+    }
+    const bool timing = (o.flags & TILEQR_FLAG_TIMING) != 0 || info != nullptr;
+    if (timing && !W->ev[0])
+        for (auto &e : W->ev) TQ_HIP(hipEventCreate(&e));
+    if (timing) TQ_HIP(hipEventRecord(W->ev[0], st));
+    std::vector<const double *> tiles((size_t)batch, nullptr);
+    if ((rc = run_batched(W, batch, mf.data(), nf.data(), Ap.data(), lda, nbv.data(), ibv.data(), Tp.data(), o, st,
+                          &tiles)))
+        return rc;
+    if (timing) TQ_HIP(hipEventRecord(W->ev[1], st));
+    if ((rc = check_status(W, (int *)W->status.ptr, st))) return rc;
+
+    // One workgroup per matrix, the largest first.
+    std::vector<int64_t> order;
+    for (int64_t i = 0; i < batch; ++i)
+        if (n[i] > 0) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t c) {
+        return tileqr_flops_lapack(m[a], n[a]) > tileqr_flops_lapack(m[c], n[c]);
+    });
+    std::vector<LsDesc> descs;
+    descs.reserve(order.size());
+    for (int64_t i : order) {
+        LsDesc d;
+        d.A = A[i];
+        d.lda = lda[i];
+        d.b = b[i];
+        d.x = x[i];
+        d.tiles = tiles[(size_t)i];
+        d.T = Tp[(size_t)i];
+        d.work = (double *)W->lswork.ptr + woff[(size_t)i];
+        d.m = (int32_t)m[i];
+        d.n = (int32_t)n[i];
+        d.nb = (int32_t)nbv[(size_t)i];
+        d.ib = (int32_t)ibv[(size_t)i];
+        d.p = (int32_t)cdiv(m[i], d.nb);
+        d.q = (int32_t)cdiv(n[i], d.nb);
+        descs.push_back(d);
+    }
+    const int count = (int)descs.size();
+    if ((rc = W->lsdesc.ensure(std::max<size_t>(1, descs.size()) * sizeof(LsDesc)))) return rc;
+    if ((rc = W->lsout.ensure(std::max<size_t>(1, descs.size()) * sizeof(LsOut)))) return rc;
+    if (count > 0) {
+        TQ_HIP(hipMemcpyAsync(W->lsdesc.ptr, descs.data(), descs.size() * sizeof(LsDesc), hipMemcpyHostToDevice, st));
+        TQ_HIP(launch_ls_batched((const LsDesc *)W->lsdesc.ptr, count, o.tol, o.max_iter, (LsOut *)W->lsout.ptr,
+                                 (int *)W->status.ptr, st));
+    }
+    if (timing) TQ_HIP(hipEventRecord(W->ev[2], st));
+    std::vector<LsOut> res(descs.size());
+    if (count > 0)
+        TQ_HIP(hipMemcpyAsync(res.data(), W->lsout.ptr, res.size() * sizeof(LsOut), hipMemcpyDeviceToHost, st));
+    rc = check_status(W, (int *)W->status.ptr, st);   // synchronises st
+    int64_t conv = 0, noconv = 0;
+    int maxit = 0;
+    double maxeta = 0.0;
+    for (size_t u = 0; u < order.size(); ++u) {
+        const int64_t i = order[u];
+        if (eta) eta[i] = res[u].eta;
+        if (iterations) iterations[i] = res[u].iterations;
+        if (res[u].eta <= o.tol) ++conv;
+        else ++noconv;
+        maxit = std::max(maxit, (int)res[u].iterations);
+        maxeta = std::max(maxeta, res[u].eta);
+    }
+    for (int64_t i = 0; i < batch; ++i)
+        if (n[i] == 0) {
+            if (eta) eta[i] = 0.0;
+            if (iterations) iterations[i] = 0;
+        }
+    if (info) {
+        info->converged = conv;
+        info->not_converged = noconv;
+        info->max_iterations = maxit;
+        info->max_eta = maxeta;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, W->ev[0], W->ev[1]) == hipSuccess) info->ms_factor = ms;
+        if (hipEventElapsedTime(&ms, W->ev[0], W->ev[2]) == hipSuccess) info->ms_total = ms;
+    }
+    if (rc) return rc;
+    return noconv > 0 ? TILEQR_ENOCONV : TILEQR_OK;
 }

@@ -71,6 +71,7 @@ struct Workspace {
     // Batched calls keep their own buffers so that a captured graph stays
     // valid across single-matrix calls.
     DevBuf btiles, bconv, bvsplit;
+    DevBuf lsT, lswork, lsdesc, lsout;    // batched least squares
     std::vector<SchedBufs> bsched;        // one per (nb, ib) group
     hipGraphExec_t bgraph = nullptr;
     std::vector<int64_t> bgraph_key;
@@ -95,6 +96,8 @@ extern Workspace *g_last_traced;
 // The tuner's entries for the current device; with create == false,
 // nullptr if there are none (and no HIP call is made before the first).
 std::vector<TuneEntry> *tuned_entries(bool create);
+// tileqr_choose_blocking for callers that hold g_mu.
+void choose_blocking_held(int64_t m, int64_t n, int precision, int64_t *nb, int64_t *ib);
 // Blocking and schedule tileqr_tune found for one m x n matrix (g_mu held).
 bool tuned_single(int64_t m, int64_t n, int precision, tileqr_tuning *out);
 

@@ -22,6 +22,8 @@ experiments draw entries with randn):
                    exactly orthogonal), built on the GPU with torch
 * ``batch_sizes`` / ``batch_matrices``  m ~ U{32..768}, n ~ U{16..m},
                    entries N(0, 1)                           (batched QR)
+* ``batch_ls``     the same matrices, then one consistent right-hand side
+                   each, b_i = A_i x_i with x_i ~ N(0, 1)    (batched least squares)
 """
 import numpy as np
 
@@ -161,6 +163,16 @@ def batch_matrices(seed, count=4000, m_lo=32, m_hi=768, n_lo=16):
     m, n, rng = batch_sizes(seed, count, m_lo, m_hi, n_lo)
     mats = [np.asfortranarray(rng.standard_normal((int(mi), int(ni)))) for mi, ni in zip(m, n)]
     return m, n, mats
+
+
+def batch_ls(seed, count=4000, m_lo=32, m_hi=768, n_lo=16):
+    """(m, n, mats, bs, xs): ``batch_matrices`` drawn first, then from the same
+    generator x_i ~ N(0, 1) (n_i entries) in order, and b_i = A_i x_i."""
+    m, n, rng = batch_sizes(seed, count, m_lo, m_hi, n_lo)
+    mats = [np.asfortranarray(rng.standard_normal((int(mi), int(ni)))) for mi, ni in zip(m, n)]
+    xs = [rng.standard_normal(int(ni)) for ni in n]
+    bs = [A @ x for A, x in zip(mats, xs)]
+    return m, n, mats, bs, xs
 
 
 def qr_flops(m, n):

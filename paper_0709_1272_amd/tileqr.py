@@ -39,6 +39,11 @@ class Tuning(ctypes.Structure):
                 ("workers", ctypes.c_int64), ("ms", ctypes.c_double)]
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("converged", ctypes.c_int64), ("not_converged", ctypes.c_int64), ("max_iterations", ctypes.c_int),
+                ("max_eta", ctypes.c_double), ("ms_factor", ctypes.c_double), ("ms_total", ctypes.c_double)]
+
+
 class Info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("eta", ctypes.c_double),
                 ("eta_hist", ctypes.c_double * 65), ("nb", ctypes.c_int64), ("ib", ctypes.c_int64),
@@ -64,6 +69,9 @@ _SIGS = {
                                ctypes.POINTER(Opts), ctypes.POINTER(Info)]),
     "tileqr_factor_batched": (_int, [_i64, _I64P, _I64P, ctypes.POINTER(_vp), _I64P, _I64P, _I64P,
                                      ctypes.POINTER(_vp), ctypes.POINTER(Opts)]),
+    "tileqr_solve_ls_batched": (_int, [_i64, _I64P, _I64P, ctypes.POINTER(_vp), _I64P, ctypes.POINTER(_vp),
+                                       ctypes.POINTER(_vp), ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(BatchInfo)]),
     "tileqr_tune": (_int, [_i64, _I64P, _I64P, _int, _int, ctypes.POINTER(Tuning)]),
     "tileqr_flops_lapack": (_dbl, [_i64, _i64]),
     "tileqr_flops_tiled": (_dbl, [_i64, _i64, _i64, _i64]),
@@ -144,6 +152,18 @@ def apply_q(m, n, nrhs, A, lda, nb, ib, T, B, ldb):
 def solve_ls(m, n, nrhs, A, lda, B, ldb, X, ldx, o=None, info=None):
     return _L.tileqr_solve_ls(m, n, nrhs, A, lda, B, ldb, X, ldx, _ptr_opts(o),
                               ctypes.byref(info) if info is not None else None)
+
+
+def solve_ls_batched(ms, ns, A_ptrs, ldas, b_ptrs, x_ptrs, o=None, info=None):
+    """Returns (status, eta list, iterations list)."""
+    b = len(ms)
+    arr = lambda vals: (ctypes.c_int64 * b)(*[int(v) for v in vals])
+    ptrs = lambda vals: (ctypes.c_void_p * b)(*[int(v) for v in vals])
+    eta = (ctypes.c_double * b)()
+    its = (ctypes.c_int32 * b)()
+    rc = _L.tileqr_solve_ls_batched(b, arr(ms), arr(ns), ptrs(A_ptrs), arr(ldas), ptrs(b_ptrs), ptrs(x_ptrs),
+                                    _ptr_opts(o), eta, its, ctypes.byref(info) if info is not None else None)
+    return rc, list(eta), list(its)
 
 
 def factor_batched(ms, ns, A_ptrs, ldas, nbs, ibs, T_ptrs, o=None):

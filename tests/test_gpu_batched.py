@@ -194,6 +194,17 @@ def test_bad_arguments(tq):
     assert tq.factor_batched([5], [5], [1], [5], [64], [16], [1], tq.opts(flags=tq.FLAG_SERIAL)) == tq.EUNSUPPORTED
 
 
+def test_default_blocking_when_nothing_is_tuned(tq):
+    # nb = ib = NULL for shapes the tuner has not seen: the library's own
+    # blocking for the batch (the path takes the library lock only once).
+    mats = small_batch(13, 10, m_hi=200)
+    B = Batch(tq, mats, [(64, 16), (64, 32), (128, 16), (128, 32), (256, 16), (256, 32)])
+    assert B.factor() == tq.OK
+    for i in range(0, 10, 3):
+        Fo, _ = oracle.geqr2(mats[i])
+        assert oracle.r_diff(r_of(B.result(i)), oracle.r_factor(Fo)) <= 1e-12, i
+
+
 def test_tuner_picks_a_supported_blocking_and_is_used(tq):
     mats = small_batch(7, 50)
     ms = [a.shape[0] for a in mats]
