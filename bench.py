@@ -52,7 +52,7 @@ PROFILE_DIR = os.path.join(ROOT, "profiles")
 # Sources the worker kernels are compiled from: a traffic figure in a profile
 # is valid only for the build whose hash it records.
 KERNEL_SRCS = [os.path.join(ROOT, "paper_0709_1272_amd", "csrc", f)
-               for f in ("tileqr_kernels.hip", "tileqr_mixed.hip", "tileqr_tile.h", "tileqr_dag.h",
+               for f in ("tileqr_kernels.hip", "tileqr_mixed.hip", "tileqr_tile.h", "tileqr_cols.h", "tileqr_dag.h",
                          "tileqr_internal.h")]
 
 

@@ -1,27 +1,28 @@
-// Split-precision SSRFB by reflector blocks of up to four inner panels.
+// Split-precision SSRFB by column blocks, with reflectors split once.
 // Included by tileqr_tile.h after the split-precision helpers.
 //
 // DSSRFB (Section 3.2.1) applies the coupled block reflector of TSQRT(k, i)
-// to the tile pair [A_kj; A_ij].  Inner blocking (Section 3.2.3) applies it
-// one group of s reflectors at a time; here a group is a "half" of up to
-// HP = 4 inner panels of 32 (s = 128 at nb = 256, s = nb below), whose
-// T_h = [[T_a, -T_a (V_a^T V_b) T_b], [0, T_b]] (recursively over the
-// panels) is formed once per TS tile by the last TSQRT panel.  Per half:
-//   W = A_kj[half rows] + V_h^T A_ij      (K = nb)
-//   W' = T_h^T W;  A_kj[half rows] -= W'
-//   A_ij -= V_h W'                       (K = s)
-// so the strip of A_ij is split into narrow parts once per half, not once
-// per inner panel, and each product is a block of MFMAs with few
-// workgroup barriers between the phases.  The paper's cost 4b^3 + s b^2
-// (Section 3.2.3) grows by the larger s: 4.5 b^3 at b = 256, s = 128.
+// to the tile pair [A_kj; A_ij], one inner panel of ib = 32 reflectors at a
+// time (Section 3.2.3):
+//   W = A_kj[panel rows] + V_l^T A_ij;  W <- T_l^T W;
+//   A_kj[panel rows] -= W;  A_ij -= V_l W.
+// Here a task takes a strip of WSX columns, and each wave owns a block of
+// 16 columns over RPW rows of A_ij, held in FP64 registers for the whole
+// task.  V_l^T A_ij then needs no reduction across waves except between the
+// two row halves of a tile of 256 rows (one exchange through LDS), so an
+// inner panel costs one exchange and two barriers around the staging of the
+// next panel instead of three barriers and a slot reduction per 32 columns.
 //
 // The operands of the three products are split into narrow parts
 // (x = x0 + x1 [+ x2], each part the rounded remainder, formed in FP32 from
 // x rounded to FP32) and run on the 16x16x32 narrow MFMAs with FP32
-// accumulation.  V is split once, by the TSQRT panel that forms it, into the
-// exact register images the MFMAs take (one 16-byte vector of 8 narrow
-// values per lane), in two layouts: one for V^T X (a lane takes 8 rows of
-// one column) and one for V W (8 columns of one row); T_h^T likewise.
+// accumulation per 32-row chunk and FP64 accumulation across chunks.  V and
+// T are split once, by the TSQRT panel that forms them, into the exact
+// register images the MFMAs take (one 16-byte vector of 8 narrow values per
+// lane), in two layouts for V: one for V^T X (a lane takes 8 rows of one
+// column) and one for V W (8 columns of one row).  The update task stages a
+// panel's images in LDS with plain 16-byte copies, prefetched one panel
+// ahead into registers.
 //
 // Lane layout of v_mfma_f32_16x16x32_{bf16,f16} (lane L = 16 g + n): A[n][8g+e]
 // and B[8g+e][n] in element e, D[4g+r][n] in element r.  The K index of every
@@ -34,44 +35,49 @@
 namespace tq {
 
 typedef uint32_t u4 __attribute__((ext_vector_type(4)));
-typedef uint32_t u2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(1))) u4 gu4;
 
-// LDS bytes the split update needs (parts: 3 at most).
+// Geometry of the column-block update for tile size NB.
 template <int NB>
-struct SxLds {
-    using C = SxCfg<NB>;
-    static constexpr int XS = C::NCH * C::NCB * 3 * 64 * 16;   // X images
-    static constexpr int WS = C::HP * C::NCB * 3 * 64 * 16;    // W or W' images
-    static constexpr int XSC = C::NCH * C::WSX * 8;            // inverse X scales per chunk and column
-    static constexpr int WMAX = C::NW * C::WSX * 8;            // column maxima per wave
-    static constexpr int BYTES = XS + WS + XSC + WMAX;
-    // T_h build in the TSQRT task: Gram blocks, T_h blocks, Y scratch (FP32).
-    static constexpr int BUILD = (C::NPAIR + C::NTB + C::HP) * 1024 * 4 + 16 * 8;
+struct ColCfg {
+    static constexpr int NW = NB / 32;             // waves of the workgroup
+    static constexpr int RH = NB >= 256 ? 2 : 1;   // row halves of a tile
+    static constexpr int NCB = NW / RH;            // 16-column blocks per strip
+    static constexpr int WSX = 16 * NCB;           // strip width (64 for nb 128, 256; 32 for nb 64)
+    static constexpr int NSX = NB / WSX;           // strips per tile
+    static constexpr int RPW = NB / RH;            // rows per wave
+    static constexpr int RBW = RPW / 16;           // 16-row blocks per wave
+    static constexpr int CHW = RPW / 32;           // 32-row chunks per wave
+};
+
+// Split images of one inner panel of one TS tile, in 16-byte vectors, in
+// two regions: A (the images the products before the coupled-row update
+// read) and B (those of the product after it), staged into LDS at
+// different points of the panel.
+template <int NB, int P>
+struct VsLayout {
+    static constexpr int VTX = 0;                                // A: [chunk c][block a][part][lane]
+    static constexpr int TT = VTX + (NB / 32) * 2 * P * 64;      // A: [block a][part][lane]
+    static constexpr int HDR = TT + 2 * P * 64;                  // A: {1 / V scale, 1 / T scale}
+    static constexpr int ASIZE = (HDR + 1 + 7) / 8 * 8;
+    static constexpr int VW = ASIZE;                             // B: [row block][part][lane]
+    static constexpr int BSIZE = (NB / 16) * P * 64;
+    static constexpr int SIZE = VW + BSIZE;
 };
 
 // Strips per tile of the LARFB / SSRFB tasks: 32 columns in FP64, the
-// split update's strip width in the split modes.
+// column-block width in the split modes.
 template <int NB, int PREC>
 __host__ __device__ constexpr int strips_of()
 {
-    return PREC == PREC_FP64 ? NB / WS : SxCfg<NB>::NSX;
+    return PREC == PREC_FP64 ? NB / WS : ColCfg<NB>::NSX;
 }
 
-template <int NB, int PREC>
-__device__ __forceinline__ gu4 *sx_tile(const MatDev &M, int k, int i)
+template <int NB, int IB, int PREC>
+__device__ __forceinline__ gu4 *vsplit_ptr(const MatDev &M, int k, int i, int l)
 {
-    using L = SxLayout<NB, Narrow<PREC>::NPART>;
-    return (gu4 *)M.vsplit + ((size_t)k * M.p + i) * L::TILE;
-}
-
-// Scale applied to V's parts: |v| <= 1 for every reflector entry
-// (|alpha - beta| >= |x_i|), so a fixed power of two keeps the FP16 parts
-// out of the subnormal range.
-template <int PREC>
-__device__ __forceinline__ constexpr double v_scale()
-{
-    return PREC == PREC_FP16X2 ? 4096.0 : 1.0;
+    using L = VsLayout<NB, Narrow<PREC>::NPART>;
+    return (gu4 *)M.vsplit + (((size_t)k * M.p + i) * (NB / IB) + l) * L::SIZE;
 }
 
 // Power-of-two scale s (and 1 / s) that brings m > 0 into [2^14, 2^15).
@@ -109,27 +115,82 @@ __device__ __forceinline__ u4 as_u4(const typename Narrow<PREC>::vec &v)
 }
 
 template <int PREC>
-__device__ __forceinline__ typename Narrow<PREC>::vec from_u4(u4 v)
+__device__ __forceinline__ typename Narrow<PREC>::vec from_u4(const u4 &v)
 {
     return __builtin_bit_cast(typename Narrow<PREC>::vec, v);
 }
 
-template <int PREC>
-__device__ __forceinline__ void load_parts(Parts<PREC> &A, const gu4 *src)
+// Writes the split images of inner panel l of TS tile (i, k): V (rows 0..nb-1,
+// columns 0..ib-1 of sm.P, FP64) and T (sm.Tl, row-major ib x ib), both
+// complete in LDS (the caller has passed a barrier since they were formed).
+// Every thread writes V vectors; wave 0 also writes T's and the header.
+template <int NB, int IB, int PREC>
+__device__ __forceinline__ void write_vsplit(const Smem<NB, IB> &sm, gu4 *dst)
 {
+    static_assert(IB == 32, "split images take ib = 32");
+    using C = Cfg<NB, IB>;
+    constexpr int P = Narrow<PREC>::NPART;
+    using L = VsLayout<NB, P>;
+    // |v| <= 1 for every reflector entry (|alpha - beta| >= |x_i|): a fixed
+    // scale keeps the FP16 parts out of the subnormal range.
+    constexpr double VS = PREC == PREC_FP16X2 ? 4096.0 : 1.0;
+    const int tid = threadIdx.x, lane = lane_id(), n = lane & 15, g = lane >> 4;
+    // V^T X images: chunk c, block a, lane (n, g), element e = V[32c + 16(e/4) + 4g + e%4][16a + n].
+    constexpr int NVTX = (NB / 32) * 2 * 64;
 #pragma unroll
-    for (int q = 0; q < Narrow<PREC>::NPART; ++q) A.p[q] = from_u4<PREC>(src[q * 64]);
+    for (int u = 0; u < NVTX / C::NT; ++u) {
+        const int v = tid + u * C::NT, ln = v & 63, ca = v >> 6, c = ca >> 1, a = ca & 1;
+        const int nn = ln & 15, gg = ln >> 4;
+        double xv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xv[e] = sm.P[(32 * c + 16 * (e >> 2) + 4 * gg + (e & 3)) * C::LDP + 16 * a + nn];
+        Parts<PREC> Pt;
+        split8_f32<PREC>(xv, VS, Pt);
+#pragma unroll
+        for (int q = 0; q < P; ++q) dst[L::VTX + (ca * P + q) * 64 + ln] = as_u4<PREC>(Pt.p[q]);
+    }
+    // V W images: row block rb, lane (n, g), element e = V[16 rb + n][16(e/4) + 4g + e%4].
+    constexpr int NVW = (NB / 16) * 64;
+#pragma unroll
+    for (int u = 0; u < NVW / C::NT; ++u) {
+        const int v = tid + u * C::NT, ln = v & 63, rb = v >> 6;
+        const int nn = ln & 15, gg = ln >> 4;
+        double xv[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xv[e] = sm.P[(16 * rb + nn) * C::LDP + 16 * (e >> 2) + 4 * gg + (e & 3)];
+        Parts<PREC> Pt;
+        split8_f32<PREC>(xv, VS, Pt);
+#pragma unroll
+        for (int q = 0; q < P; ++q) dst[L::VW + (rb * P + q) * 64 + ln] = as_u4<PREC>(Pt.p[q]);
+    }
+    if (wave_id() == 0) {
+        // T images for T^T W: block a, element e = T[16(e/4) + 4g + e%4][16a + n],
+        // T scaled by a power of two from its largest entry.
+        double mx = 0.0;
+#pragma unroll
+        for (int u = 0; u < IB * IB / 64; ++u) mx = fmax(mx, fabs(sm.Tl[lane + 64 * u]));
+        mx = group_max<64>(mx);
+        double ts, tinv;
+        pow2_scale(mx, ts, tinv);
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            double xv[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) xv[e] = sm.Tl[(16 * (e >> 2) + 4 * g + (e & 3)) * IB + 16 * a + n];
+            Parts<PREC> Pt;
+            split8_f32<PREC>(xv, ts, Pt);
+#pragma unroll
+            for (int q = 0; q < P; ++q) dst[L::TT + (a * P + q) * 64 + lane] = as_u4<PREC>(Pt.p[q]);
+        }
+        if (lane == 0) {
+            const v2d hdr = {1.0 / VS, tinv};
+            dst[L::HDR] = __builtin_bit_cast(u4, hdr);
+        }
+    }
 }
 
-template <int PREC>
-__device__ __forceinline__ void load_parts_lds(Parts<PREC> &A, const u4 *src)
-{
-#pragma unroll
-    for (int q = 0; q < Narrow<PREC>::NPART; ++q) A.p[q] = from_u4<PREC>(src[q * 64]);
-}
-
-// Largest |value| of a 16-column block column over a wave: the lane's own
-// entries and those of the three other lanes of its column.
+// Column scale of a wave's 16-column block: the largest |value| of the
+// lane's own entries and of the three other lanes of its column.
 template <int CNT>
 __device__ __forceinline__ double column_max(const double *v)
 {
@@ -141,397 +202,196 @@ __device__ __forceinline__ double column_max(const double *v)
     return m;
 }
 
-// Writes the V images of inner panel l of TS tile (i, k): V (rows 0..nb-1,
-// columns 0..ib-1 of sm.P, FP64), complete in LDS (the caller has passed a
-// barrier since it was formed).
-template <int NB, int IB, int PREC>
-__device__ __forceinline__ void write_vsplit(const Smem<NB, IB> &sm, gu4 *dst)
+// Staging of COUNT vectors of a panel's images: global -> registers (every
+// thread the same number of loads, indexes clamped) and registers -> LDS.
+template <int NB, int COUNT>
+struct VsStage {
+    static constexpr int NT = 2 * NB;
+    static constexpr int SPT = (COUNT + NT - 1) / NT;
+    u4 v[SPT];
+};
+
+template <int NB, int COUNT>
+__device__ __forceinline__ void vs_load(VsStage<NB, COUNT> &S, const gu4 *src)
 {
-    static_assert(IB == 32, "split images take ib = 32");
-    using C = Cfg<NB, IB>;
-    using X = SxCfg<NB>;
-    constexpr int P = Narrow<PREC>::NPART;
-    using L = SxLayout<NB, P>;
-    constexpr double VS = v_scale<PREC>();
-    const int tid = threadIdx.x;
-    // V^T X images: chunk c, block a, lane (n, g), element e = V[32c + 16(e/4) + 4g + e%4][16a + n].
-    constexpr int NVTX = X::NCH * 2 * 64;
 #pragma unroll
-    for (int u = 0; u < NVTX / C::NT; ++u) {
-        const int v = tid + u * C::NT, ln = v & 63, ca = v >> 6, c = ca >> 1, a = ca & 1;
-        const int nn = ln & 15, gg = ln >> 4;
-        double xv[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) xv[e] = sm.P[(32 * c + 16 * (e >> 2) + 4 * gg + (e & 3)) * C::LDP + 16 * a + nn];
-        Parts<PREC> Pt;
-        split8_f32<PREC>(xv, VS, Pt);
-#pragma unroll
-        for (int q = 0; q < P; ++q) dst[(ca * P + q) * 64 + ln] = as_u4<PREC>(Pt.p[q]);
-    }
-    // V W images: row block rb, lane (n, g), element e = V[16 rb + n][16(e/4) + 4g + e%4].
-    constexpr int NVW = X::NRB * 64;
-#pragma unroll
-    for (int u = 0; u < NVW / C::NT; ++u) {
-        const int v = tid + u * C::NT, ln = v & 63, rb = v >> 6;
-        const int nn = ln & 15, gg = ln >> 4;
-        double xv[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) xv[e] = sm.P[(16 * rb + nn) * C::LDP + 16 * (e >> 2) + 4 * gg + (e & 3)];
-        Parts<PREC> Pt;
-        split8_f32<PREC>(xv, VS, Pt);
-#pragma unroll
-        for (int q = 0; q < P; ++q) dst[L::VTX_SZ + (rb * P + q) * 64 + ln] = as_u4<PREC>(Pt.p[q]);
+    for (int u = 0; u < VsStage<NB, COUNT>::SPT; ++u) {
+        const int e = threadIdx.x + u * VsStage<NB, COUNT>::NT;
+        S.v[u] = src[e < COUNT ? e : COUNT - 1];
     }
 }
 
-// After the last inner panel of TS tile (i, k) (every panel's V images and
-// T_l in memory): for each reflector block h, T_h in FP32 by the column
-// recurrence T_{0:m+1} = [[T_{0:m}, -T_{0:m} G_{0:m,m} T_m], [0, T_m]] with
-// the Gram blocks G_lm = V_l^T V_m (from the V images on the narrow MFMAs),
-// then the T_h^T images with one power-of-two scale per 16-column block of
-// T_h.  Uses the workgroup's LDS (nothing else live) and ends with a barrier.
-template <int NB, int IB, int PREC>
-__device__ __forceinline__ void build_th(Smem<NB, IB> &sm, const MatDev &M, int k, int i)
+template <int NB, int COUNT>
+__device__ __forceinline__ void vs_store(u4 *lv, const VsStage<NB, COUNT> &S)
 {
-    using C = SxCfg<NB>;
-    constexpr int P = Narrow<PREC>::NPART;
-    using L = SxLayout<NB, P>;
-    static_assert(SxLds<NB>::BUILD <= (int)sizeof(Smem<NB, IB>), "T_h build fits in LDS");
-    constexpr int NT = 64 * C::NW;
-    constexpr double VS = v_scale<PREC>();
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, n = lane & 15, g = lane >> 4;
-    float *Gs = reinterpret_cast<float *>(&sm);       // [pair][32][32]
-    float *Tb = Gs + C::NPAIR * 1024;                   // [block (l <= m)][32][32]
-    float *Ys = Tb + C::NTB * 1024;                     // [l][32][32]
-    double *sinv = reinterpret_cast<double *>(Ys + C::HP * 1024);   // [16]
-    gu4 *base = sx_tile<NB, PREC>(M, k, i);
-    const gdouble *Ti = tblock_ptr(M, NB, IB, k, i);
-    // Block index of T_h[l][m] (l <= m) and pair index of G[l][m] (l < m).
-    auto tb = [](int l, int m) { return m * (m + 1) / 2 + l; };
-    auto pr = [](int l, int m) { return m * (m - 1) / 2 + l; };
-#pragma unroll 1
-    for (int h = 0; h < C::NH; ++h) {
-        const int l0 = h * C::HP;
-        __syncthreads();
-        // Gram blocks: 16 x 16 tiles (pair, a, a'), K over the tile's chunks.
-#pragma unroll 1
-        for (int it = w; it < C::NPAIR * 4; it += C::NW) {
-            const int pi = it >> 2, a = (it >> 1) & 1, a2 = it & 1;
-            int m = 1;
-            while (m * (m + 1) / 2 <= pi) ++m;
-            const int l = pi - m * (m - 1) / 2;
-            const gu4 *vl = base + (size_t)(l0 + l) * L::PANEL, *vm = base + (size_t)(l0 + m) * L::PANEL;
-            f4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
-            for (int c = 0; c < C::NCH; ++c) {
-                Parts<PREC> A, B;
-                load_parts<PREC>(A, vl + ((c * 2 + a) * P) * 64 + lane);
-                load_parts<PREC>(B, vm + ((c * 2 + a2) * P) * 64 + lane);
-                acc += split_product<PREC>(A, B);
-            }
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                Gs[pi * 1024 + (16 * a + 4 * g + r) * 32 + 16 * a2 + n] = acc[r] * (float)(1.0 / (VS * VS));
-        }
-        // Diagonal blocks T_l (upper triangular, from memory).
-        for (int e = tid; e < C::HP * 1024; e += NT) {
-            const int l = e >> 10, r = (e >> 5) & 31, c = e & 31;
-            Tb[tb(l, l) * 1024 + r * 32 + c] = r <= c ? (float)Ti[(size_t)(l0 + l) * 1024 + r * 32 + c] : 0.f;
-        }
-        __syncthreads();
-#pragma unroll 1
-        for (int m = 1; m < C::HP; ++m) {
-            // Y_l = G_lm T_m (l < m).
-            for (int e = tid; e < m * 1024; e += NT) {
-                const int l = e >> 10, r = (e >> 5) & 31, c = e & 31;
-                const float *gr = Gs + pr(l, m) * 1024 + r * 32;
-                const float *tm = Tb + tb(m, m) * 1024;
-                float s = 0.f;
-                for (int q = 0; q <= c; ++q) s += gr[q] * tm[q * 32 + c];
-                Ys[l * 1024 + r * 32 + c] = s;
-            }
-            __syncthreads();
-            // T_h[l][m] = -sum_{l' = l .. m-1} T_h[l][l'] Y_l'.
-            for (int e = tid; e < m * 1024; e += NT) {
-                const int l = e >> 10, r = (e >> 5) & 31, c = e & 31;
-                float s = 0.f;
-                for (int lp = l; lp < m; ++lp) {
-                    const float *tr = Tb + tb(l, lp) * 1024 + r * 32;
-                    const float *yc = Ys + lp * 1024 + c;
-                    for (int q = lp == l ? r : 0; q < 32; ++q) s += tr[q] * yc[q * 32];
-                }
-                Tb[tb(l, m) * 1024 + r * 32 + c] = -s;
-            }
-            __syncthreads();
-        }
-        // One scale per 16-column block rb of T_h (rows 0 .. 32 (rb / 2) + 31).
-        if (tid < 64 * ((C::HRB + 3) / 4)) {
-            // wave-sized groups of 16 lanes per block: lane n of group rb.
-            const int rb = tid >> 4, cn = tid & 15;
-            float mx = 0.f;
-            if (rb < C::HRB) {
-                const int mblk = rb >> 1, c = 16 * (rb & 1) + cn;
-                for (int l = 0; l <= mblk; ++l)
-                    for (int r = 0; r < 32; ++r) mx = fmaxf(mx, fabsf(Tb[tb(l, mblk) * 1024 + r * 32 + c]));
-            }
-#pragma unroll
-            for (int o = 1; o < 16; o <<= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 16));
-            if (rb < C::HRB && cn == 0) {
-                double s, inv;
-                pow2_scale((double)mx, s, inv);
-                sinv[rb] = inv;
-            }
-        }
-        __syncthreads();
-        gu4 *th = base + (size_t)C::NP * L::PANEL + (size_t)h * L::HALF;
-        // Images: row block rb, chunk kc <= rb / 2, lane (n, g), element
-        // e = T_h[32 kc + 16(e/4) + 4g + e%4][16 rb + n] (times the block's scale).
-        for (int v = tid; v < C::HRB * C::HP * 64; v += NT) {
-            const int ln = v & 63, blk = v >> 6, rb = blk / C::HP, kc = blk % C::HP;
-            if (kc > rb / 2) continue;
-            const int nn = ln & 15, gg = ln >> 4, mblk = rb >> 1, c = 16 * (rb & 1) + nn;
-            const double s = 1.0 / sinv[rb];
-            double xv[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) xv[e] = (double)Tb[tb(kc, mblk) * 1024 + (16 * (e >> 2) + 4 * gg + (e & 3)) * 32 + c];
-            Parts<PREC> Pt;
-            split8_f32<PREC>(xv, s, Pt);
-#pragma unroll
-            for (int q = 0; q < P; ++q) th[((rb * C::HP + kc) * P + q) * 64 + ln] = as_u4<PREC>(Pt.p[q]);
-        }
-        if (tid < C::HRB) reinterpret_cast<gdouble *>(th + L::TH_IMG)[tid] = sinv[tid];
+    for (int u = 0; u < VsStage<NB, COUNT>::SPT; ++u) {
+        const int e = threadIdx.x + u * VsStage<NB, COUNT>::NT;
+        if (e < COUNT) lv[e] = S.v[u];
     }
-    __syncthreads();
 }
 
-// DSSRFB(k, i, j, s) in a split precision: strip s (64 columns) of
-// [A_kj; A_ij] <- Q_ik^T [A_kj; A_ij], one reflector block of up to four
-// inner panels at a time, with the images TSQRT(k, i) wrote.  Wave w keeps
-// rows 32 w .. 32 w + 31 of the strip of A_ij (chunk w) in FP64 registers
-// for the whole task, and per block the rows RPW w .. of W.
+// DSSRFB(k, i, j, s) in a split precision: strip s (ColCfg::WSX columns) of
+// [A_kj; A_ij] <- Q_ik^T [A_kj; A_ij], with the split images of V_ik and T_ik
+// that the TSQRT(k, i) panels wrote.
 template <int NB, int IB, int PREC>
-__device__ __forceinline__ void task_ssrfb_mx(Smem<NB, IB> &sm, const MatDev &M, int k, int i, int j, int s)
+__device__ __forceinline__ void task_ssrfb_cols(Smem<NB, IB> &sm, const MatDev &M, int k, int i, int j, int s)
 {
-    using C = SxCfg<NB>;
+    using C = ColCfg<NB>;
     constexpr int P = Narrow<PREC>::NPART;
-    using L = SxLayout<NB, P>;
-    using LD = SxLds<NB>;
+    constexpr int NPAN = NB / IB;
+    using L = VsLayout<NB, P>;
     static_assert(IB == 32, "split images take ib = 32");
-    static_assert(LD::BYTES <= (int)sizeof(Smem<NB, IB>), "the split update fits in LDS");
-    constexpr double VINV = 1.0 / v_scale<PREC>();
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, n = lane & 15, g = lane >> 4;
-    const int col0 = s * C::WSX;
+    static_assert(L::SIZE * 16 + (C::RH == 2 ? C::NW * 8 * 64 * 8 : 0) <= (int)sizeof(Smem<NB, IB>),
+                  "panel images and the exchange slots fit in the workgroup's LDS");
+    const int w = wave_id(), lane = lane_id(), n = lane & 15, g = lane >> 4;
+    const int cb = w % C::NCB, h = w / C::NCB;
+    const int col = s * C::WSX + 16 * cb + n;
+    const int row0 = h * C::RPW;
     gdouble *X = tile_ptr(M, NB, i, j);
     gdouble *top = tile_ptr(M, NB, k, j);
-    const gu4 *img = sx_tile<NB, PREC>(M, k, i);
-    char *raw = reinterpret_cast<char *>(&sm);
-    u4 *XS = reinterpret_cast<u4 *>(raw);                          // [c][cb][q][lane]
-    u4 *WSm = reinterpret_cast<u4 *>(raw + LD::XS);                // [kc][cb][q][lane]
-    double *xsc = reinterpret_cast<double *>(raw + LD::XS + LD::WS);   // [c][64]
-    double *wmax = xsc + C::NCH * C::WSX;                          // [w][64]
+    const gu4 *vs0 = vsplit_ptr<NB, IB, PREC>(M, k, i, 0);
+    u4 *lv = reinterpret_cast<u4 *>(&sm);
+    double *slots = reinterpret_cast<double *>(lv + L::SIZE);
 
-    // The wave's rows of A_ij: row blocks 2w, 2w + 1, element r of lane
-    // (n, g) is row 16 rb + 4g + r, column col0 + 16 cb + n.
-    double x[2][C::NCB][4];
+    double x[C::RBW][4];
 #pragma unroll
-    for (int jj = 0; jj < 2; ++jj)
+    for (int rb = 0; rb < C::RBW; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < C::NCB; ++cb)
+        for (int r = 0; r < 4; ++r) x[rb][r] = X[(size_t)(row0 + 16 * rb + 4 * g + r) * NB + col];
+    double tv[2][4];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) x[jj][cb][r] = X[(size_t)(32 * w + 16 * jj + 4 * g + r) * NB + col0 + 16 * cb + n];
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) tv[a][r] = top[(size_t)(16 * a + 4 * g + r) * NB + col];
+    // Region A of a panel is staged once every wave has read the previous
+    // panel's (after T^T W), region B once every wave is done with V W; the
+    // register copies of the two are never live at the same time.
+    VsStage<NB, L::ASIZE> SA;
+    VsStage<NB, L::BSIZE> SB;
+    vs_load<NB, L::ASIZE>(SA, vs0);
+    vs_load<NB, L::BSIZE>(SB, vs0 + L::VW);
+    vs_store<NB, L::ASIZE>(lv, SA);
+    vs_store<NB, L::BSIZE>(lv + L::VW, SB);
+    vs_load<NB, L::ASIZE>(SA, vs0 + (NPAN > 1 ? 1 : 0) * L::SIZE);
+    __syncthreads();
 
 #pragma unroll 1
-    for (int h = 0; h < C::NH; ++h) {
-        // X images of chunk w, one scale per column over the chunk's rows.
+    for (int l = 0; l < NPAN; ++l) {
+        const v2d hdr = __builtin_bit_cast(v2d, lv[L::HDR]);
+        const double vinv = hdr.x, tinv = hdr.y;
+        // W = V_l^T X over this wave's rows, FP32 per 32-row chunk, FP64 across.
+        double xs, xinv;
+        pow2_scale(column_max<C::RBW * 4>(&x[0][0]), xs, xinv);
+        const double ux = xinv * vinv;
+        double W[2][4] = {};
 #pragma unroll
-        for (int cb = 0; cb < C::NCB; ++cb) {
+        for (int cc = 0; cc < C::CHW; ++cc) {
+            const int c = h * C::CHW + cc;
             double xv[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) xv[e] = x[e >> 2][cb][e & 3];
-            double sc, inv;
-            pow2_scale(column_max<8>(xv), sc, inv);
-            Parts<PREC> Pt;
-            split8_f32<PREC>(xv, sc, Pt);
+            for (int e = 0; e < 8; ++e) xv[e] = x[2 * cc + (e >> 2)][e & 3];
+            Parts<PREC> Bx;
+            split8_f32<PREC>(xv, xs, Bx);
 #pragma unroll
-            for (int q = 0; q < P; ++q) XS[((w * C::NCB + cb) * P + q) * 64 + lane] = as_u4<PREC>(Pt.p[q]);
-            if (g == 0) xsc[w * C::WSX + 16 * cb + n] = inv * VINV;
-        }
-        // W = top rows + V_h^T X for the wave's row blocks of this block
-        // (local rb = RPW w + jj: panel HP h + rb / 2, block rb % 2).
-        double W[C::RPW][C::NCB][4];
-#pragma unroll
-        for (int jj = 0; jj < C::RPW; ++jj) {
-            const int row = 16 * (C::HRB * h + C::RPW * w + jj);
-#pragma unroll
-            for (int cb = 0; cb < C::NCB; ++cb)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) W[jj][cb][r] = top[(size_t)(row + 4 * g + r) * NB + col0 + 16 * cb + n];
-        }
-        __syncthreads();
-#pragma unroll 1
-        for (int c = 0; c < C::NCH; ++c) {
-            Parts<PREC> Bx[C::NCB];
-#pragma unroll
-            for (int cb = 0; cb < C::NCB; ++cb) load_parts_lds<PREC>(Bx[cb], XS + ((c * C::NCB + cb) * P) * 64 + lane);
-            double u[C::NCB];
-#pragma unroll
-            for (int cb = 0; cb < C::NCB; ++cb) u[cb] = xsc[c * C::WSX + 16 * cb + n];
-#pragma unroll
-            for (int jj = 0; jj < C::RPW; ++jj) {
-                const int rb = C::RPW * w + jj;
+            for (int a = 0; a < 2; ++a) {
                 Parts<PREC> Av;
-                load_parts<PREC>(Av, img + (size_t)(C::HP * h + rb / 2) * L::PANEL + ((c * 2 + (rb & 1)) * P) * 64 + lane);
 #pragma unroll
-                for (int cb = 0; cb < C::NCB; ++cb) {
-                    const f4 d = split_product<PREC>(Av, Bx[cb]);
+                for (int q = 0; q < P; ++q) Av.p[q] = from_u4<PREC>(lv[L::VTX + ((c * 2 + a) * P + q) * 64 + lane]);
+                const f4 d = split_product<PREC>(Av, Bx);
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) W[jj][cb][r] += (double)d[r] * u[cb];
-                }
+                for (int r = 0; r < 4; ++r) W[a][r] += (double)d[r] * ux;
             }
         }
-        // Column maxima of W over the block's rows (all waves).
+        // The two row halves' partial sums, added in the same order by both.
+        if constexpr (C::RH == 2) {
 #pragma unroll
-        for (int cb = 0; cb < C::NCB; ++cb) {
-            double m = 0.0;
+            for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int jj = 0; jj < C::RPW; ++jj)
+                for (int r = 0; r < 4; ++r) slots[(w * 8 + 4 * a + r) * 64 + lane] = W[a][r];
+            __syncthreads();
 #pragma unroll
-                for (int r = 0; r < 4; ++r) m = fmax(m, fabs(W[jj][cb][r]));
-            m = fmax(m, __shfl_xor(m, 16));
-            m = fmax(m, __shfl_xor(m, 32));
-            if (g == 0) wmax[w * C::WSX + 16 * cb + n] = m;
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    W[a][r] = slots[(cb * 8 + 4 * a + r) * 64 + lane] + slots[((cb + C::NCB) * 8 + 4 * a + r) * 64 + lane];
         }
-        __syncthreads();
-        double wsi[C::NCB];
 #pragma unroll
-        for (int cb = 0; cb < C::NCB; ++cb) {
-            double m = 0.0;
+        for (int a = 0; a < 2; ++a)
 #pragma unroll
-            for (int ww = 0; ww < C::NW; ++ww) m = fmax(m, wmax[ww * C::WSX + 16 * cb + n]);
-            double sc, inv;
-            pow2_scale(m, sc, inv);
-            wsi[cb] = inv;
-            // The wave's rows are elements 4 (rb % 2) .. of chunk rb / 2.
+            for (int r = 0; r < 4; ++r) W[a][r] = tv[a][r] + W[a][r];
+        // W' = T_l^T W.
+        double ws, winv;
+        pow2_scale(column_max<8>(&W[0][0]), ws, winv);
+        double Wp[2][4];
+        {
+            double wv[8];
 #pragma unroll
-            for (int jj = 0; jj < C::RPW; ++jj) {
-                const int rb = C::RPW * w + jj;
-                double xv[8];
+            for (int e = 0; e < 8; ++e) wv[e] = W[e >> 2][e & 3];
+            Parts<PREC> Bw;
+            split8_f32<PREC>(wv, ws, Bw);
+            const double ut = winv * tinv;
 #pragma unroll
-                for (int e = 0; e < 8; ++e) xv[e] = W[jj][cb][e & 3];
-                Parts<PREC> Pt;
-                split8_f32<PREC>(xv, sc, Pt);
-#pragma unroll
-                for (int q = 0; q < P; ++q) {
-                    const u4 v = as_u4<PREC>(Pt.p[q]);
-                    u2 *dst = reinterpret_cast<u2 *>(WSm + (((rb >> 1) * C::NCB + cb) * P + q) * 64 + lane) + (rb & 1);
-                    *dst = (u2){v.x, v.y};
-                }
-            }
-        }
-        __syncthreads();
-        // W' = T_h^T W for the wave's row blocks; the top rows take -W'.
-        const gu4 *th = img + (size_t)C::NP * L::PANEL + (size_t)h * L::HALF;
-        const gdouble *thsc = reinterpret_cast<const gdouble *>(th + L::TH_IMG);
-        double Wp[C::RPW][C::NCB][4];
-#pragma unroll
-        for (int jj = 0; jj < C::RPW; ++jj) {
-            const int rb = C::RPW * w + jj;
-            f4 acc[C::NCB];
-#pragma unroll
-            for (int cb = 0; cb < C::NCB; ++cb) acc[cb] = (f4){0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
-            for (int kc = 0; kc <= rb / 2; ++kc) {
+            for (int a = 0; a < 2; ++a) {
                 Parts<PREC> At;
-                load_parts<PREC>(At, th + ((rb * C::HP + kc) * P) * 64 + lane);
 #pragma unroll
-                for (int cb = 0; cb < C::NCB; ++cb) {
-                    Parts<PREC> Bw;
-                    load_parts_lds<PREC>(Bw, WSm + ((kc * C::NCB + cb) * P) * 64 + lane);
-                    acc[cb] += split_product<PREC>(At, Bw);
-                }
-            }
-            const double tsi = thsc[rb];
-            const int row = 16 * (C::HRB * h + rb);
+                for (int q = 0; q < P; ++q) At.p[q] = from_u4<PREC>(lv[L::TT + (a * P + q) * 64 + lane]);
+                const f4 d = split_product<PREC>(At, Bw);
 #pragma unroll
-            for (int cb = 0; cb < C::NCB; ++cb)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    Wp[jj][cb][r] = (double)acc[cb][r] * (tsi * wsi[cb]);
-                    gdouble *tp = top + (size_t)(row + 4 * g + r) * NB + col0 + 16 * cb + n;
-                    *tp = *tp - Wp[jj][cb][r];
-                }
-        }
-        // Column maxima of W' (every wave is past its reads of W's images).
-#pragma unroll
-        for (int cb = 0; cb < C::NCB; ++cb) {
-            double m = 0.0;
-#pragma unroll
-            for (int jj = 0; jj < C::RPW; ++jj)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) m = fmax(m, fabs(Wp[jj][cb][r]));
-            m = fmax(m, __shfl_xor(m, 16));
-            m = fmax(m, __shfl_xor(m, 32));
-            if (g == 0) wmax[w * C::WSX + 16 * cb + n] = m;
-        }
-        __syncthreads();
-        double wpi[C::NCB];
-#pragma unroll
-        for (int cb = 0; cb < C::NCB; ++cb) {
-            double m = 0.0;
-#pragma unroll
-            for (int ww = 0; ww < C::NW; ++ww) m = fmax(m, wmax[ww * C::WSX + 16 * cb + n]);
-            double sc, inv;
-            pow2_scale(m, sc, inv);
-            wpi[cb] = inv * VINV;
-#pragma unroll
-            for (int jj = 0; jj < C::RPW; ++jj) {
-                const int rb = C::RPW * w + jj;
-                double xv[8];
-#pragma unroll
-                for (int e = 0; e < 8; ++e) xv[e] = Wp[jj][cb][e & 3];
-                Parts<PREC> Pt;
-                split8_f32<PREC>(xv, sc, Pt);
-#pragma unroll
-                for (int q = 0; q < P; ++q) {
-                    const u4 v = as_u4<PREC>(Pt.p[q]);
-                    u2 *dst = reinterpret_cast<u2 *>(WSm + (((rb >> 1) * C::NCB + cb) * P + q) * 64 + lane) + (rb & 1);
-                    *dst = (u2){v.x, v.y};
-                }
+                for (int r = 0; r < 4; ++r) Wp[a][r] = (double)d[r] * ut;
             }
         }
+        // Every wave has read region A of this panel: stage the next one's
+        // (after the last panel a repeat of its own, so that every iteration
+        // issues the same loads) and prefetch the next region B.
         __syncthreads();
-        // X -= V_h W' for the wave's rows (chunk w), K over the block's panels.
+        const int l1 = l + 1 < NPAN ? l + 1 : l;
+        vs_store<NB, L::ASIZE>(lv, SA);
+        vs_load<NB, L::BSIZE>(SB, vs0 + (size_t)l1 * L::SIZE + L::VW);
+        // The coupled rows of A_kj: each row half writes one 16-row block.
 #pragma unroll
-        for (int jj = 0; jj < 2; ++jj) {
-            f4 acc[C::NCB];
+        for (int a = 0; a < 2; ++a)
+            if (C::RH == 1 || a == h)
 #pragma unroll
-            for (int cb = 0; cb < C::NCB; ++cb) acc[cb] = (f4){0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
-            for (int kc = 0; kc < C::HP; ++kc) {
+                for (int r = 0; r < 4; ++r) top[(size_t)(32 * l + 16 * a + 4 * g + r) * NB + col] = tv[a][r] - Wp[a][r];
+        // The next panel's coupled rows (a reload of these after the last).
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tv[a][r] = top[(size_t)(32 * l1 + 16 * a + 4 * g + r) * NB + col];
+        // X -= V_l W'.
+        {
+            double ws2, winv2;
+            pow2_scale(column_max<8>(&Wp[0][0]), ws2, winv2);
+            double wv[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) wv[e] = Wp[e >> 2][e & 3];
+            Parts<PREC> Bw;
+            split8_f32<PREC>(wv, ws2, Bw);
+            const double uw = winv2 * vinv;
+#pragma unroll
+            for (int rbw = 0; rbw < C::RBW; ++rbw) {
+                const int rb = h * C::RBW + rbw;
                 Parts<PREC> Av;
-                load_parts<PREC>(Av, img + (size_t)(C::HP * h + kc) * L::PANEL + L::VTX_SZ + ((2 * w + jj) * P) * 64 + lane);
 #pragma unroll
-                for (int cb = 0; cb < C::NCB; ++cb) {
-                    Parts<PREC> Bw;
-                    load_parts_lds<PREC>(Bw, WSm + ((kc * C::NCB + cb) * P) * 64 + lane);
-                    acc[cb] += split_product<PREC>(Av, Bw);
-                }
+                for (int q = 0; q < P; ++q) Av.p[q] = from_u4<PREC>(lv[L::VW + (rb * P + q) * 64 + lane]);
+                const f4 d = split_product<PREC>(Av, Bw);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) x[rbw][r] = x[rbw][r] - (double)d[r] * uw;
             }
-#pragma unroll
-            for (int cb = 0; cb < C::NCB; ++cb)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) x[jj][cb][r] -= (double)acc[cb][r] * wpi[cb];
         }
-        // No barrier: the next block's first writes (X images, W column
-        // maxima) go to memory every wave finished reading before the
-        // barriers above.
+        // Region B of the next panel once every wave is done with V W, then
+        // the prefetch of region A of the one after.
+        __syncthreads();
+        vs_store<NB, L::BSIZE>(lv + L::VW, SB);
+        const int l2 = l + 2 < NPAN ? l + 2 : NPAN - 1;
+        vs_load<NB, L::ASIZE>(SA, vs0 + (size_t)l2 * L::SIZE);
+        __syncthreads();
     }
 #pragma unroll
-    for (int jj = 0; jj < 2; ++jj)
+    for (int rb = 0; rb < C::RBW; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < C::NCB; ++cb)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) X[(size_t)(32 * w + 16 * jj + 4 * g + r) * NB + col0 + 16 * cb + n] = x[jj][cb][r];
+        for (int r = 0; r < 4; ++r) X[(size_t)(row0 + 16 * rb + 4 * g + r) * NB + col] = x[rb][r];
 }
 
 }  // namespace tq

@@ -22,59 +22,22 @@ struct MatDev {
 };
 
 // LARFB / SSRFB strip tasks per tile: 32-column strips in FP64; in the split
-// modes the 64-column strips of the split update.
+// modes the column-block width of the split SSRFB (64 columns for nb 128 and
+// 256, 32 for nb 64).
 __host__ __device__ constexpr int strips_per_tile(int nb, int prec)
 {
-    return prec == 0 ? nb / 32 : nb / 64;
+    return prec == 0 ? nb / 32 : (nb >= 128 ? nb / 64 : nb / 32);
 }
 
-// Geometry of the split update for tile size NB (ib = 32).
-template <int NB>
-struct SxCfg {
-    static constexpr int NW = NB / 32;              // waves of the workgroup
-    static constexpr int NP = NB / 32;              // inner panels of a tile
-    static constexpr int NCH = NB / 32;             // 32-row chunks of a tile (= NW)
-    static constexpr int NRB = NB / 16;             // 16-row blocks of a tile
-    static constexpr int HP = NP < 4 ? NP : 4;      // inner panels per reflector block ("half")
-    static constexpr int NH = NP / HP;              // reflector blocks per tile
-    static constexpr int HRB = 2 * HP;              // 16-row blocks of W per block
-    static constexpr int RPW = HRB / NW;            // W row blocks per wave
-    static constexpr int NCB = 4;                   // 16-column blocks per strip
-    static constexpr int WSX = 16 * NCB;            // strip width
-    static constexpr int NSX = NB / WSX;            // strips per tile
-    static constexpr int NPAIR = HP * (HP - 1) / 2; // panel pairs (l < m) of a block
-    static constexpr int NTB = HP * (HP + 1) / 2;   // 32 x 32 blocks of T_h's upper triangle
-    static_assert(NB % 64 == 0 && RPW >= 1 && HRB % NW == 0, "split update geometry");
-};
-
-// Split images of one TS tile, in 16-byte vectors: per inner panel the V^T
-// images [chunk c][block a][part][lane] and the V images [row block][part]
-// [lane]; per reflector block h the T_h^T images [row block rb][chunk kc]
-// [part][lane] (kc <= rb / 2 used) and HRB inverse scales (doubles).
-template <int NB, int P>
-struct SxLayout {
-    using C = SxCfg<NB>;
-    static constexpr int VTX_SZ = C::NCH * 2 * P * 64;
-    static constexpr int VW_SZ = C::NRB * P * 64;
-    static constexpr int PANEL = VTX_SZ + VW_SZ;
-    static constexpr int TH_IMG = C::HRB * C::HP * P * 64;
-    static constexpr int TH_SC = 8;                 // 16 doubles
-    static constexpr int HALF = TH_IMG + TH_SC;
-    static constexpr int TILE = C::NP * PANEL + C::NH * HALF;
-    static_assert(C::HRB <= 16, "scales fit");
-};
-
 // Bytes of the split images of one matrix (p x q tiles, kmax steps): one
-// SxLayout::TILE block of 16-byte vectors per TS tile (k, i), laid out like
-// T by (k p + i).  parts: 3 for BF16 x3, 2 for the other splits.
+// block of 16-byte vectors per TS tile (k, i) and inner panel, holding V^T X
+// and V W images of V (nb / 32 * 2 + nb / 16 vectors per lane and part), the
+// T^T W images of T (2 per lane and part) and one header vector; laid out
+// like T, by (k p + i).  parts: 3 for BF16 x3, 2 for the other splits.
 inline size_t vsplit_bytes(int p, int kmax, int nb, int ib, int parts)
 {
-    (void)ib;
-    size_t tile = 0;
-    if (nb == 64) tile = parts == 3 ? SxLayout<64, 3>::TILE : SxLayout<64, 2>::TILE;
-    else if (nb == 128) tile = parts == 3 ? SxLayout<128, 3>::TILE : SxLayout<128, 2>::TILE;
-    else tile = parts == 3 ? SxLayout<256, 3>::TILE : SxLayout<256, 2>::TILE;
-    return (size_t)kmax * p * tile * 16;
+    const size_t vec = (size_t)(((nb / 32) * 2 + nb / 16 + 2) * parts * 64 + 1 + 7) / 8 * 8;
+    return (size_t)kmax * p * (nb / ib) * vec * 16;
 }
 
 // Words of one trace event: type, k, i, j, strip, worker, then the device

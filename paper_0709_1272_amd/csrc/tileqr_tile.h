@@ -109,9 +109,6 @@ struct alignas(16) Smem {
     double Tl[IB * IB];              // T of the current inner panel
     double tau[IB];
     double sc[2][2];                 // tau of the broadcast reflector
-    // Room the split-precision update (tileqr_cols.h) needs beyond the
-    // above when it reuses this memory as raw bytes (nb = 64 and 128).
-    double xtra[NB == 128 ? 1280 : 2];
     static_assert(C::NSLOT * IB * WS >= 2 * NB, "the broadcast buffers fit in the slots");
 };
 
@@ -1118,15 +1115,10 @@ __device__ __forceinline__ void tsqrt_panel(Smem<NB, IB> &sm, const MatDev &M, i
     build_t<NB, IB>(sm, 0, Ti + l * IB * IB);
     __syncthreads();
     // Split modes: the split images of V and T for the SSRFB tasks.
-    if constexpr (PREC != PREC_FP64)
-        write_vsplit<NB, IB, PREC>(sm, sx_tile<NB, PREC>(M, k, i) + (size_t)l * SxLayout<NB, Narrow<PREC>::NPART>::PANEL);
-    if (trailing) {
-        panel_trailing<NB, IB, true, PREC>(sm, tik, tkk, c0, chain);
-        __syncthreads();
-    }
-    // After the last panel, the reflector-block T_h images of the split update.
-    if constexpr (PREC != PREC_FP64)
-        if (l == C::NPAN - 1) build_th<NB, IB, PREC>(sm, M, k, i);
+    if constexpr (PREC != PREC_FP64) write_vsplit<NB, IB, PREC>(sm, vsplit_ptr<NB, IB, PREC>(M, k, i, l));
+    if (!trailing) return;
+    panel_trailing<NB, IB, true, PREC>(sm, tik, tkk, c0, chain);
+    __syncthreads();
 }
 
 // DTSQRT(R_kk, A_ik) -> (R_kk, V_ik, T_ik): the inner panels in order.
@@ -1266,7 +1258,7 @@ __device__ __forceinline__ void task_ssrfb(Smem<NB, IB> &sm, const MatDev &M, in
         apply_ts_strip<NB, IB, true, PREC>(sm, tile_ptr(M, NB, i, k), tblock_ptr(M, NB, IB, k, i), tile_ptr(M, NB, k, j),
                                            NB, tile_ptr(M, NB, i, j), NB, s * WS);
     else
-        task_ssrfb_mx<NB, IB, PREC>(sm, M, k, i, j, s);
+        task_ssrfb_cols<NB, IB, PREC>(sm, M, k, i, j, s);
 }
 
 // PUPD(k, i, l, s): one strip of a panel task's trailing update as a task of
