@@ -115,3 +115,14 @@ def test_automatic_blocking():
     for m, n in ((1, 1), (300, 7000), (100000, 64)):
         nb, ib = tq.choose_blocking(m, n)
         assert tq.blocking_supported(nb, ib)
+
+
+def test_cli_arguments():
+    # The driver's argument checks run before it touches a device.
+    from paper_0709_1272_amd import cli
+    with pytest.raises(SystemExit):
+        cli.main(["qr", "--n", "8"])
+    with pytest.raises(SystemExit):
+        cli.main(["solve", "--n", "8", "--precision", "fp8"])
+    with pytest.raises(SystemExit):
+        cli.main(["solve"])

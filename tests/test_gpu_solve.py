@@ -156,3 +156,17 @@ def test_two_streams_async_match_sync(tq):
         for s in range(2):
             assert torch.equal(work[s], ref[s][0]), (rep, s)
             assert torch.equal(Ts[s], ref[s][1]), (rep, s)
+
+
+def test_cli_driver(tq, capsys):
+    # The command-line driver runs the library on seeded inputs and prints
+    # one JSON line; a split solve reaches the backward-error target.
+    import json
+    from paper_0709_1272_amd import cli
+    assert cli.main(["factor", "--m", "700", "--n", "300", "--nb", "64", "--ib", "16", "--repeat", "2"]) == 0
+    out = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert out["m"] == 700 and out["n"] == 300 and len(out["runs"]) == 2
+    assert out["copy_bytes"] == 700 * 300 * 8
+    assert cli.main(["solve", "--n", "512", "--nrhs", "3", "--precision", "bf16x3", "--nb", "128"]) == 0
+    out = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert out["runs"][0]["eta"] <= 1e-14 and out["runs"][0]["iterations"] >= 1
