@@ -351,12 +351,16 @@ def main():
     ms_total_dev = sum(s["ms_total"] for _, s in steps) / len(steps)
     value = flops / (ms_per_step * 1e-3) / 1e12
 
-    # Roofline of the dominant kernel (the split-precision factorisation
-    # worker): bound by HBM at nb 256 (the split products' intensity b/4 = 64
-    # flop/B lies below the narrow MFMA ridge), algorithmic bytes 16 nb^2
-    # sum_k (p-k)^2 per launch.
+    # Roofline of the dominant kernel, the BF16X3 factorisation worker.  Its
+    # six kept BF16 products per FP64 product put the narrow-MFMA ridge at
+    # 2.5 PFLOP/s / 6 / 8 TB/s = 52 FP64 flops per byte, below the tiled
+    # update's intensity b/4 = 64 at nb 256: the kernel is bound by the BF16
+    # MFMA rate (113 ms for 6 x 4.69e13 flops, against 93 ms to move the
+    # algorithmic bytes 16 nb^2 sum_k (p-k)^2 at 8 TB/s).
     alg_bytes = ssrfb_bytes(N, N, NB)
-    achieved = alg_bytes / (worker_ms * 1e-3) / 1e9
+    mfma_flops = 6.0 * flops
+    achieved = mfma_flops / (worker_ms * 1e-3) / 1e12
+    hbm_achieved = alg_bytes / (worker_ms * 1e-3) / 1e9
     traffic = measured_traffic("k_worker_ls32768_bf16x3.md")
     out = {
         "metric": "QR TFLOP/s (2mn²−2n³/3): FP64 vs BF16-split+IR at equal 1e-14 backward err",
@@ -383,15 +387,17 @@ def main():
         "bf16x3": {"ms_device_mean": round(ms_total_dev, 3), "eta_inf_check": eta_check,
                    "steps": [s for _, s in steps]},
         "input": {"generation_s": round(gen_s, 2), "checksum_sum_A": checksum},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / BF16_PEAK_TFLOPS, 4), "traffic": traffic,
                      "kernel": f"k_worker<{NB},{IB},3,false> (BF16X3 split)",
-                     "algorithmic": f"{alg_bytes:.4e} bytes per launch (16 nb^2 sum_k (p-k)(q-k))",
+                     "algorithmic": f"6 x {flops:.4e} BF16 MFMA flops per launch (six kept products per FP64 "
+                                    f"product, LAPACK count)",
                      "kernel_ms": round(worker_ms, 3),
-                     "mfma_reading": {"achieved": round(6 * flops / (worker_ms * 1e-3) / 1e12, 2),
-                                      "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                                      "frac": round(6 * flops / (worker_ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 4),
-                                      "note": "6 kept BF16 products per FP64 product, LAPACK flop count"},
+                     "hbm_reading": {"achieved": round(hbm_achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": round(hbm_achieved / HBM_PEAK_GBS, 4),
+                                     "algorithmic": f"{alg_bytes:.4e} bytes per launch (16 nb^2 sum_k (p-k)(q-k))",
+                                     "traffic_frac": (round(traffic / (worker_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                                      if traffic else None)},
                      "fp64_equivalent_tflops": round(flops / (worker_ms * 1e-3) / 1e12, 3)},
     }
     if "fp16x2_ls" in extras:
