@@ -117,6 +117,10 @@ typedef struct {
                              tile is then a task of its own); 0 = automatic
                              (one matrix with at most 32 tile steps: nb / ib,
                              otherwise 1)                                           */
+    int64_t apply_group;  /* inner panels per workgroup when tileqr_solve_ls applies
+                             Q or Q^T: 1, 2, 4 or 8, dividing nb / ib; 0 =
+                             automatic (larger for matrices with many tile steps
+                             per row block).  The result does not depend on it */
 } tileqr_opts;
 
 /* Blocking and schedule of a factorisation, as chosen by tileqr_tune. */

@@ -773,8 +773,8 @@ namespace {
 
 // Q^T or Q on row blocks `rows` (leading dimension ldt) with the factor
 // already in W->tiles.  W->prog must hold min(p, q) nb/ib flags (PROG_STRIDE apart).
-hipError_t apply_rows(Workspace *W, int nb, int ib, int p, int q, const double *T, double *rows, int ldt, bool trans,
-                      hipStream_t st)
+hipError_t apply_rows(Workspace *W, int nb, int ib, int p, int q, const double *T, double *rows, int ldt, int ncol,
+                      bool trans, hipStream_t st, int group = 0)
 {
     ApplyDev D;
     D.M.tiles = (double *)W->tiles.ptr;
@@ -786,7 +786,9 @@ hipError_t apply_rows(Workspace *W, int nb, int ib, int p, int q, const double *
     D.B = rows;
     D.ldb = ldt;
     D.nstrip = ldt / kStripWidth;
+    D.ncol = ncol;
     D.kmax = std::min(p, q);
+    D.group = group;
     D.prog = (int32_t *)W->prog.ptr;
     D.status = (int32_t *)W->status.ptr;
     D.spin_limit = (int64_t)1 << 26;
@@ -825,7 +827,7 @@ int apply_common(bool trans, int64_t m, int64_t n, int64_t nrhs, const double *A
     TQ_HIP(hipMemsetAsync(W->status.ptr, 0, sizeof(int), st));
     TQ_HIP(launch_cm2tile(A, lda, m, n, (double *)W->tiles.ptr, (int)nb, p, q, (int *)W->status.ptr, st));
     TQ_HIP(launch_cm2rows(B, ldb, m, nrhs, (double *)W->rows.ptr, (int64_t)p * nb, ldt, st));
-    TQ_HIP(apply_rows(W, (int)nb, (int)ib, p, q, T, (double *)W->rows.ptr, ldt, trans, st));
+    TQ_HIP(apply_rows(W, (int)nb, (int)ib, p, q, T, (double *)W->rows.ptr, ldt, (int)nrhs, trans, st));
     TQ_HIP(launch_rows2cm(B, ldb, m, nrhs, (double *)W->rows.ptr, ldt, st));
     return check_status(W, (int *)W->status.ptr, st);
 }
@@ -857,6 +859,7 @@ struct SolveCtx {
     const double *A;
     int64_t lda, m, n;
     int nrhs, ldt, nb, ib, p, q;
+    int group;       // inner panels per workgroup of the Q applications (0: automatic)
     double *buf[SNUM];
     double *T;
     double *part;
@@ -932,7 +935,9 @@ int beta_fact_probe(SolveCtx &c, double normA, uint64_t seed, double *out)
     D.B = V;
     D.ldb = c.ldt;
     D.nstrip = c.ldt / kStripWidth;
+    D.ncol = NPROBE;
     D.kmax = std::min(c.p, c.q);
+    D.group = c.group;
     D.prog = (int32_t *)W->prog.ptr;
     D.status = (int32_t *)W->status.ptr;
     D.spin_limit = (int64_t)1 << 26;
@@ -976,6 +981,9 @@ extern "C" int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double 
     if (nb == 0 || ib == 0) tileqr_choose_blocking(m, n, o.precision, &nb, &ib);
     if (!tileqr_blocking_supported(nb, ib)) return TILEQR_EUNSUPPORTED;
     if (!panel_tasks_ok(o.panel_tasks, nb, ib)) return -10;
+    if (o.apply_group != 0 && (o.apply_group > 8 || (o.apply_group & (o.apply_group - 1)) != 0 ||
+                               (nb / ib) % o.apply_group != 0))
+        return -10;
     if (!precision_supported(o.precision, ib)) return TILEQR_EUNSUPPORTED;
 
     std::lock_guard<std::mutex> lock(g_mu);
@@ -1014,6 +1022,7 @@ extern "C" int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double 
     c.ib = (int)ib;
     c.p = p;
     c.q = q;
+    c.group = (int)o.apply_group;
     for (int i = 0; i < SNUM; ++i) c.buf[i] = (double *)W->solve.ptr + i * slot;
     c.T = (double *)W->tws.ptr;
     c.part = (double *)W->part.ptr;
@@ -1056,7 +1065,7 @@ extern "C" int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double 
 
     // x0 = R^{-1} (Q^T b)(0:n),  r0 = b - A x0.
     TQ_HIP(launch_axpy_rows(c.buf[SB], c.buf[SX], ldt, m, c.nrhs, 2, st));
-    TQ_HIP(apply_rows(W, c.nb, c.ib, p, q, c.T, c.buf[SX], ldt, true, st));
+    TQ_HIP(apply_rows(W, c.nb, c.ib, p, q, c.T, c.buf[SX], ldt, c.nrhs, true, st, c.group));
     TQ_HIP(launch_trsm(c.nb, (double *)W->tiles.ptr, p, n, c.buf[SX], ldt, true, (int *)W->tflags.ptr, tflags_cap,
                        dstatus, spin, st));
     // zero the rows n.. of x (they held (Q^T b)(n:m))
@@ -1093,7 +1102,7 @@ extern "C" int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double 
             // least-squares residual is zero): dx = R^{-1} Q^T (b - A x), with
             // the residual b - A x that eta_of left in buf[SS].
             TQ_HIP(launch_axpy_rows(c.buf[SS], F, ldt, m, c.nrhs, 2, st));
-            TQ_HIP(apply_rows(W, c.nb, c.ib, p, q, c.T, F, ldt, true, st));
+            TQ_HIP(apply_rows(W, c.nb, c.ib, p, q, c.T, F, ldt, c.nrhs, true, st, c.group));
             TQ_HIP(launch_trsm(c.nb, (double *)W->tiles.ptr, p, n, F, ldt, true, (int *)W->tflags.ptr, tflags_cap,
                                dstatus, spin, st));
             TQ_HIP(launch_axpy_rows(F, c.buf[SX], ldt, n, c.nrhs, 1, st));
@@ -1107,7 +1116,7 @@ extern "C" int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double 
             TQ_HIP(launch_gemv_n(A, lda, m, n, c.buf[SX], ldt, c.nrhs, -1.0, 1.0, F, c.part, part_cap, st));
             TQ_HIP(launch_gemv_t(A, lda, m, n, c.buf[SR], ldt, c.nrhs, -1.0, 0.0, G, c.part, part_cap, st));
             // [f1; f2] = Q^T f ;  d1 = R^{-T} g ;  dx = R^{-1} (f1 - d1) ;  dr = Q [d1; f2]
-            TQ_HIP(apply_rows(W, c.nb, c.ib, p, q, c.T, F, ldt, true, st));
+            TQ_HIP(apply_rows(W, c.nb, c.ib, p, q, c.T, F, ldt, c.nrhs, true, st, c.group));
             TQ_HIP(launch_trsm(c.nb, (double *)W->tiles.ptr, p, n, G, ldt, false, (int *)W->tflags.ptr, tflags_cap,
                                dstatus, spin, st));
             double *DX = c.buf[SS];
@@ -1119,7 +1128,7 @@ extern "C" int tileqr_solve_ls(int64_t m, int64_t n, int64_t nrhs, const double 
                                dstatus, spin, st));
             TQ_HIP(launch_axpy_rows(DX, c.buf[SX], ldt, n, c.nrhs, 1, st));
             TQ_HIP(launch_axpy_rows(G, F, ldt, n, c.nrhs, 2, st));             // F = [d1; f2]
-            TQ_HIP(apply_rows(W, c.nb, c.ib, p, q, c.T, F, ldt, false, st));
+            TQ_HIP(apply_rows(W, c.nb, c.ib, p, q, c.T, F, ldt, c.nrhs, false, st, c.group));
             TQ_HIP(launch_axpy_rows(F, c.buf[SR], ldt, m, c.nrhs, 1, st));
         }
         if ((rc = eta_of(c, normA, normAinf, normb, square, eta_ls, eta_inf))) return rc;

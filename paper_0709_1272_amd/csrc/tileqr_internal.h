@@ -84,7 +84,9 @@ struct ApplyDev {
     double *B;                // p row blocks of nb x ldb, row-major
     int32_t ldb;              // a multiple of the strip width
     int32_t nstrip;           // ldb / strip width
+    int32_t ncol;             // columns that hold right-hand sides (the rest of ldb is zero padding)
     int32_t kmax;             // tile steps of the factorisation
+    int32_t group = 0;        // inner panels per workgroup (0: chosen from the shape)
     int32_t *prog;            // [kmax * (nb / ib) * PROG_STRIDE] progress flags, one per 256 bytes
     int32_t *status;
     int64_t spin_limit;

@@ -47,53 +47,67 @@ __global__ void k_sched_seed(SchedDev S)
 // the strip width).  Q^T applies, for k = 0, 1, ..: Q_kk^T to block k, then
 // Q_ik^T to blocks (k, i) for i = k+1, k+2, .. (the order in which the
 // factorisation applied them to A); Q applies the transposes in reverse.
-// Each tile reflector is the product of its nb/ib inner panels, and the
-// work is spread over (step, panel) pairs: workgroup (k, l) applies inner
-// panel l of every reflector of step k, row block after row block.  Panel l
-// of the TS reflector (k, i) touches only rows [l ib, (l+1) ib) of block k
-// and all of block i, so workgroup (k, l) on block i waits only for panel
-// l-1 (TRANS; l+1 for Q) of the same step to have finished block i, and the
-// first panel of a step for the previous step (in the product's order) to
-// have finished it: a wavefront over (row block, panel) instead of a chain
-// of whole tiles.  Progress flags (the last block done) sit PROG_STRIDE
-// words apart in D.prog, one per (step, panel).  A workgroup waits only for
-// lower-numbered ones, which were dispatched first, so the waits make
-// progress; every wait is bounded.
+// Each tile reflector is the product of its nb/ib inner panels, taken in
+// groups of D.group consecutive panels, and the work is spread over (step,
+// group) pairs: workgroup (k, g) applies the panels of group g of every
+// reflector of step k, row block after row block.  Panel l of the TS
+// reflector (k, i) touches only rows [l ib, (l+1) ib) of block k and all of
+// block i, so workgroup (k, g) on block i waits only for group g-1 (TRANS;
+// g+1 for Q) of the same step to have finished block i, and the first group
+// of a step for the previous step (in the product's order) to have finished
+// it: a wavefront over (row block, group) instead of a chain of whole tiles.
+// Larger groups mean fewer links in the wavefront and fewer waits per panel,
+// at the price of more work per link; the host picks the size.  A strip of
+// a block stays in registers across the group's panels.  Every panel is applied with the same operands
+// and in the same order whatever the grouping, so the result does not depend
+// on it.  Progress flags (the last block done) sit PROG_STRIDE words apart in
+// D.prog, one per (step, group).  A workgroup waits only for lower-numbered
+// ones, which were dispatched first, so the waits make progress; every wait
+// is bounded.
 template <int NB, int IB, bool TRANS>
 __global__ __launch_bounds__(2 * NB) void k_apply(ApplyDev D)
 {
     __shared__ Smem<NB, IB> sm;
     __shared__ int s_abort;
-    constexpr int NP = Cfg<NB, IB>::NPAN;
+    using C = Cfg<NB, IB>;
+    constexpr int NP = C::NPAN;
     const int tid = threadIdx.x;
-    const int kmax = D.kmax, p = D.M.p;
-    const int sidx = (int)blockIdx.x / NP, pidx = (int)blockIdx.x % NP;
+    const int kmax = D.kmax, p = D.M.p, G = D.group, NG = NP / G;
+    const int sidx = (int)blockIdx.x / NG, gidx = (int)blockIdx.x % NG;
     const int k = TRANS ? sidx : kmax - 1 - sidx;
-    const int l = TRANS ? pidx : NP - 1 - pidx;
+    const int grp = TRANS ? gidx : NG - 1 - gidx;
+    // Panels of the group in the order they are applied: ascending for Q^T,
+    // descending for Q.
+    auto panel_of = [&](int j) { return TRANS ? grp * G + j : grp * G + G - 1 - j; };
     if (*D.status != 0) return;   // input rejected (non-finite factor)
     const gdouble *tkk = tile_ptr(D.M, NB, k, k);
     gdouble *Bk = (gdouble *)(D.B + (size_t)k * NB * D.ldb);
-    // The first panel of a step (l = 0 for Q^T, nb/ib - 1 for Q) follows the
-    // last panel of the previous step in the product; the others follow the
-    // neighbouring panel of the same step.
-    const bool first = pidx == 0;
+    // The first group of a step (in the product's order) follows the last
+    // group of the previous step; the others follow the neighbouring group of
+    // the same step.
+    const bool first = gidx == 0;
     const int *pred = nullptr;
-    if (!first) pred = &D.prog[(k * NP + (TRANS ? l - 1 : l + 1)) * PROG_STRIDE];
-    else if (TRANS ? k > 0 : k + 1 < kmax) pred = &D.prog[((TRANS ? k - 1 : k + 1) * NP + (TRANS ? NP - 1 : 0)) * PROG_STRIDE];
+    if (!first) pred = &D.prog[(k * NG + (TRANS ? grp - 1 : grp + 1)) * PROG_STRIDE];
+    else if (TRANS ? k > 0 : k + 1 < kmax) pred = &D.prog[((TRANS ? k - 1 : k + 1) * NG + (TRANS ? NG - 1 : 0)) * PROG_STRIDE];
     const int nrow = p - k;   // blocks k .. p-1
     // Q^T: k, k+1, .., p-1.   Q: p-1, .., k+1, then k.
     auto row_of = [&](int qq) { return TRANS ? k + qq : (qq + 1 < nrow ? p - 1 - qq : k); };
-    // The panel of the first block is loaded before the first wait, and each
-    // later one while the previous block is applied (the factor is final).
-    Stage<NB, IB> S;
-    {
-        const int r = row_of(0);
+    auto stage = [&](Stage<NB, IB> &S, int qq, int j) {
+        const int r = row_of(qq), l = panel_of(j);
         apply_panel_stage<NB, IB>(S, r == k ? tkk : tile_ptr(D.M, NB, r, k), tblock_ptr(D.M, NB, IB, k, r), l, r == k);
-    }
+    };
+    // Panels are staged one ahead: the first before the first wait, each
+    // later one while the previous panel is applied (the factor is final).
+    Stage<NB, IB> S;
+    stage(S, 0, 0);
+    // Rows of block k the group may change: the diagonal panels from the
+    // group's lowest one on; rows above it belong to other groups.
+    const int rlo_diag = grp * G * IB;
     for (int q = 0; q < nrow; ++q) {
         const int r = row_of(q);
+        const bool diag = r == k;
         // Block k under Q never sees step k+1 (which starts at block k+1).
-        const bool wait = pred != nullptr && !(first && !TRANS && r == k);
+        const bool wait = pred != nullptr && !(first && !TRANS && diag);
         if (tid == 0) {
             int abort = 0;
             if (wait) {
@@ -120,25 +134,42 @@ __global__ __launch_bounds__(2 * NB) void k_apply(ApplyDev D)
         __syncthreads();
         if (s_abort) return;
         gdouble *Br = (gdouble *)(D.B + (size_t)r * NB * D.ldb);
+        gdouble *x = diag ? Bk : Br;
+        const bool last_row = q + 1 == nrow;
 #pragma unroll 1
         for (int st = 0; st < D.nstrip; ++st) {
-            if (r == k)
-                apply_one_panel<NB, IB, TRANS>(sm, S, l, true, nullptr, 0, Bk, D.ldb, st * WS);
-            else
-                apply_one_panel<NB, IB, TRANS>(sm, S, l, false, Bk, D.ldb, Br, D.ldb, st * WS);
+            const int col0 = st * WS;
+            // Column blocks of the strip that hold right-hand sides.
+            const int cbn = min(CB, (D.ncol - col0 + 15) / 16);
+            Strip<NB, IB> X;
+            load_strip<NB, IB>(X, x, D.ldb, col0, cbn);
+#pragma unroll 1
+            for (int j = 0; j < G; ++j) {
+                const int l = panel_of(j), c0 = l * IB;
+                gdouble *tp = diag ? nullptr : Bk + (size_t)c0 * D.ldb + col0;
+                double tv[C::EPT] = {};
+                if (!diag) load_top<NB, IB>(tv, tp, D.ldb, 16 * cbn);
+                stage_store_rows<NB, IB>(sm, S, diag ? c0 : 0, diag, c0);
+                // Stage the next panel: the group's next one, else the first
+                // one for the next strip or row (after the very last, reload).
+                int qn = q, jn = j + 1;
+                if (jn == G) {
+                    jn = 0;
+                    if (st + 1 == D.nstrip) {
+                        if (last_row) jn = G - 1;
+                        else qn = q + 1;
+                    }
+                }
+                stage(S, qn, jn);
+                apply_panel<NB, IB, TRANS, true>(sm, X, diag ? c0 : 0, tp, D.ldb, cbn, tv);
+            }
+            store_strip<NB, IB>(X, x, D.ldb, col0, cbn, diag ? rlo_diag : 0);
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __syncthreads();
         if (tid == 0) {
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __hip_atomic_store(&D.prog[(k * NP + l) * PROG_STRIDE], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        // Prefetch the next block's panel once this block is published
-        // (after the last block a reload of this one).
-        {
-            const int rn = row_of(q + 1 < nrow ? q + 1 : q);
-            apply_panel_stage<NB, IB>(S, rn == k ? tkk : tile_ptr(D.M, NB, rn, k), tblock_ptr(D.M, NB, IB, k, rn), l,
-                                      rn == k);
+            __hip_atomic_store(&D.prog[(k * NG + grp) * PROG_STRIDE], r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
 }
@@ -371,10 +402,23 @@ hipError_t launch_factor_serial(int nb, int ib, int prec, const MatDev &M, const
 #undef TQ_CALL
 }
 
-template <int NB, int IB>
-static hipError_t apply_impl(const ApplyDev &D, bool trans, hipStream_t st)
+// Panels per workgroup of k_apply.  The wavefront has about kmax np / G + p
+// links of a cost that grows with G, so few row blocks per step (square
+// matrices) favour larger groups and many (tall ones) single panels; a group
+// size is a power of two dividing np.
+int apply_group(int np, int kmax, int p)
 {
-    const int nflag = D.kmax * Cfg<NB, IB>::NPAN;
+    int g = 1;
+    while (2 * g <= np && 2 * g <= 8 && (int64_t)3 * kmax * np >= (int64_t)p * (2 * g) * (2 * g)) g *= 2;
+    return g;
+}
+
+template <int NB, int IB>
+static hipError_t apply_impl(ApplyDev D, bool trans, hipStream_t st)
+{
+    constexpr int NP = Cfg<NB, IB>::NPAN;
+    if (D.group < 1 || NP % D.group != 0) D.group = apply_group(NP, D.kmax, D.M.p);
+    const int nflag = D.kmax * (NP / D.group);
     hipLaunchKernelGGL(k_apply_init, dim3(1), dim3(256), 0, st, D.prog, nflag, D.M.p, trans ? 1 : 0);
     if (trans)
         hipLaunchKernelGGL((k_apply<NB, IB, true>), dim3(nflag), dim3(Cfg<NB, IB>::NT), 0, st, D);

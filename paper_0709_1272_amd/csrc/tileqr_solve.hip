@@ -97,6 +97,15 @@ __global__ __launch_bounds__(256) void k_trsm(const double *tiles, int p, int nr
         }
     }
 
+    // This block's right-hand sides, read before the first wait (only this
+    // workgroup writes them, with the solution, at the end).
+    double *Cr = C + (size_t)r * RB * ldt;
+    double crv[2][4];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) crv[cb][e] = Cr[(size_t)(16 * w + 4 * e + g) * ldt + s0 + 16 * cb + ln];
+
     d4 acc[2] = {};   // element e: row 16 w + 4 e + g, column 16 cb + ln
     const int nc = upper ? nrb - 1 - r : r;
     for (int u = 0; u < nc; ++u) {
@@ -151,14 +160,10 @@ __global__ __launch_bounds__(256) void k_trsm(const double *tiles, int p, int nr
     }
 
     // Y = C_r - accumulated products, in Xs.
-    double *Cr = C + (size_t)r * RB * ldt;
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb)
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int row = 16 * w + 4 * e + g, col = 16 * cb + ln;
-            Xs[row][col] = Cr[(size_t)row * ldt + s0 + col] - acc[cb][e];
-        }
+        for (int e = 0; e < 4; ++e) Xs[16 * w + 4 * e + g][16 * cb + ln] = crv[cb][e] - acc[cb][e];
     __syncthreads();
 
     // Substitution with op(R)_rr: lane (cl, part) of wave w holds rows

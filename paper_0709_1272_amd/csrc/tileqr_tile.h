@@ -371,7 +371,10 @@ __device__ __forceinline__ void store_top(const Smem<NB, IB> &sm, const double (
 // tile (the R rows the TS form also updates), row stride ldtop; tv holds
 // that block as load_top read it.
 // Three workgroup barriers; the products V^T X, T^T W and V W run on MFMA.
-template <int NB, int IB, bool TRANS = true>
+// With SKIP the column blocks from cbn on (which the caller neither loaded
+// nor stores) are left out of the products; every output column depends
+// only on its own input column, so the others come out the same.
+template <int NB, int IB, bool TRANS = true, bool SKIP = false>
 __device__ __forceinline__ void apply_panel(Smem<NB, IB> &sm, Strip<NB, IB> &X, int rlo, gdouble *top, int ldtop, int cbn,
                                             const double (&tv)[Cfg<NB, IB>::EPT])
 {
@@ -379,6 +382,7 @@ __device__ __forceinline__ void apply_panel(Smem<NB, IB> &sm, Strip<NB, IB> &X, 
     const int tid = threadIdx.x, w = wave_id();
     const int n = lane_id() & 15, g = lane_id() >> 4, rowbase = w * 32;
     const int ncol = cbn * 16;
+    auto live = [&](int cb) { return !SKIP || cb < cbn; };
 
     // W partial over this wave's rows.
     d4 Wacc[C::IBB][CB];
@@ -396,7 +400,8 @@ __device__ __forceinline__ void apply_panel(Smem<NB, IB> &sm, Strip<NB, IB> &X, 
             for (int a = 0; a < C::IBB; ++a) {
                 const double va = vrow[a * 16];
 #pragma unroll
-                for (int cb = 0; cb < CB; ++cb) Wacc[a][cb] = mfma(va, X.v[rb][cb][r], Wacc[a][cb]);
+                for (int cb = 0; cb < CB; ++cb)
+                    if (live(cb)) Wacc[a][cb] = mfma(va, X.v[rb][cb][r], Wacc[a][cb]);
             }
         }
     }
@@ -412,6 +417,7 @@ __device__ __forceinline__ void apply_panel(Smem<NB, IB> &sm, Strip<NB, IB> &X, 
     // T^T W: one 16 x 16 output block per wave.
     for (int blk = w; blk < C::IBB * CB; blk += C::NW) {
         const int a = blk / CB, cb = blk % CB;
+        if (!live(cb)) continue;
         d4 acc = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int kc = 0; kc < IB / 4; ++kc)
@@ -431,6 +437,7 @@ __device__ __forceinline__ void apply_panel(Smem<NB, IB> &sm, Strip<NB, IB> &X, 
             const double va = sm.P[(rowbase + rb * 16 + n) * C::LDP + 4 * kc + g];
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) {
+                if (!live(cb)) continue;
                 const double wb = -sm.Wb[(4 * kc + g) * WS + cb * 16 + n];
                 X.v[rb][cb] = mfma(va, wb, X.v[rb][cb]);
             }

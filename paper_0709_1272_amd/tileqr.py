@@ -31,7 +31,8 @@ class Opts(ctypes.Structure):
                 ("max_iter", ctypes.c_int), ("tol", ctypes.c_double), ("stream", ctypes.c_void_p),
                 ("flags", ctypes.c_uint), ("seed", ctypes.c_uint64), ("spin_limit", ctypes.c_int64),
                 ("workers", ctypes.c_int64), ("drop_edge", ctypes.c_int64),
-                ("panel_workers", ctypes.c_int64), ("panel_tasks", ctypes.c_int64)]
+                ("panel_workers", ctypes.c_int64), ("panel_tasks", ctypes.c_int64),
+                ("apply_group", ctypes.c_int64)]
 
 
 class Tuning(ctypes.Structure):

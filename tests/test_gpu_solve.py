@@ -170,3 +170,33 @@ def test_cli_driver(tq, capsys):
     assert cli.main(["solve", "--n", "512", "--nrhs", "3", "--precision", "bf16x3", "--nb", "128"]) == 0
     out = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
     assert out["runs"][0]["eta"] <= 1e-14 and out["runs"][0]["iterations"] >= 1
+
+
+@pytest.mark.parametrize("m,n,nb,ib,nrhs,groups", [(1000, 300, 64, 16, 3, (1, 2, 4)),
+                                                   (777, 777, 128, 16, 40, (1, 2, 4, 8)),
+                                                   (1536, 1024, 256, 32, 16, (1, 2, 4, 8))])
+def test_apply_group_does_not_change_bits(tq, m, n, nb, ib, nrhs, groups):
+    # The Q applications take groups of consecutive inner panels per
+    # workgroup; each panel is applied with the same operands in the same
+    # order whatever the grouping, so the solution is bitwise the same.
+    A, b, _ = synth.svd_matrix(31, m, n, 1e4, nrhs=nrhs)
+    ref = None
+    for g in (0,) + tuple(groups):
+        rc, x, info = solve(tq, A, b, nb=nb, ib=ib, apply_group=g, max_iter=2)
+        assert rc in (tq.OK, tq.ENOCONV)
+        if ref is None:
+            ref = x
+        else:
+            assert np.array_equal(x, ref), f"apply_group {g}"
+    xo, _ = oracle.lstsq(A, b)
+    assert np.linalg.norm(ref - xo) <= 1e-6 * np.linalg.norm(xo)
+
+
+def test_apply_group_rejected(tq):
+    A = synth.uniform(3, 256, 128)
+    b = A @ np.ones(128)
+    for g in (3, 16, -1):
+        rc, _, _ = solve(tq, A, b, nb=64, ib=16, apply_group=g)
+        assert rc == -10, g
+    rc, _, _ = solve(tq, A, b, nb=64, ib=32, apply_group=4)   # nb / ib = 2
+    assert rc == -10
