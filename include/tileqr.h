@@ -348,14 +348,45 @@ int tileqr_solve_ls_batched(int64_t batch, const int64_t *m, const int64_t *n,
  * splits of the workgroups between the panel and update roles, one untimed
  * warm-up run and then `trials` timed runs each (best time counts).  The
  * fastest choice is written to *best and
- * remembered for this multiset of shapes and precision for the rest of the
- * process: tileqr_factor_batched with nb = ib = NULL and tileqr_solve_ls /
- * tileqr_choose_blocking with automatic blocking use it.  Allocates scratch
- * device memory for the trial matrices (freed before returning).
+ * remembered in the tuner's table, keyed by the device's architecture and
+ * compute-unit count, the precision and the multiset of shapes, for the rest
+ * of the process (or longer, with tileqr_tune_save): tileqr_factor_batched
+ * with nb = ib = NULL and tileqr_solve_ls / tileqr_choose_blocking with
+ * automatic blocking use it, for exactly these shapes and, failing that, for
+ * shapes of the same size class: the same precision and the same ceil(log2)
+ * of the batch size, of the flop-weighted typical min(m, n) and of the
+ * largest m and n (the paper tunes b and s per problem size, Section 5).
+ * Allocates scratch device memory for the trial matrices (freed before
+ * returning).
  * Errors: -1 batch, -2 m, -3 n, -4 precision, -5 trials, -6 best.
  */
 int tileqr_tune(int64_t batch, const int64_t *m, const int64_t *n, int precision, int trials,
                 tileqr_tuning *best);
+
+/*
+ * The tuner's table on disk: tileqr_tune_save writes every entry (of any
+ * device kind) to the text file `path`, one line each; tileqr_tune_load adds
+ * the entries of such a file to the table (replacing entries with the same
+ * device kind and shapes).  Host only; no device is needed.  Return the
+ * number of entries written / read, or -1 (path NULL), -2 (the file cannot
+ * be opened or written), -3 (tileqr_tune_load: a malformed line; nothing is
+ * loaded).
+ */
+int64_t tileqr_tune_save(const char *path);
+int64_t tileqr_tune_load(const char *path);
+
+/*
+ * Query the table as the automatic blocking does, for a device of
+ * architecture `arch` (e.g. "gfx950") with `cu` compute units: 1 and *out
+ * set if an entry for exactly these shapes or for their size class exists,
+ * else 0.  Host only.  Errors: -1 arch, -3 batch, -4 m, -5 n, -6 precision,
+ * -7 out.
+ */
+int tileqr_tune_lookup(const char *arch, int cu, int64_t batch, const int64_t *m, const int64_t *n,
+                       int precision, tileqr_tuning *out);
+
+/* Empty the tuner's table. */
+void tileqr_tune_clear(void);
 
 /* Operation counts.  tileqr_flops_lapack: 2mn^2 - 2n^3/3 (m >= n; the
  * mirror formula for m < n), the count the paper reports rates with

@@ -97,15 +97,8 @@ Workspace *g_last_traced = nullptr;
 
 std::vector<TuneEntry> *tuned_entries(bool create)
 {
-    static std::vector<std::pair<int, std::vector<TuneEntry>>> per_device;
-    int dev = 0;
-    if (per_device.empty() && !create) return nullptr;
-    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
-    for (auto &e : per_device)
-        if (e.first == dev) return &e.second;
-    if (!create) return nullptr;
-    per_device.push_back({dev, {}});
-    return &per_device.back().second;
+    static std::vector<TuneEntry> table;
+    return (table.empty() && !create) ? nullptr : &table;
 }
 
 }  // namespace tq

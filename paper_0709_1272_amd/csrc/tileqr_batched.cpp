@@ -6,7 +6,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
 #include <vector>
 
 #include "../../include/tileqr.h"
@@ -27,13 +31,80 @@ struct Group {
     int workers = 0;
 };
 
-const tileqr_tuning *find_tuned(const std::vector<int64_t> &key)
+// ceil(log2(x)) for x >= 1, else 0.
+int64_t clog2(int64_t x)
+{
+    int64_t b = 0;
+    while (b < 62 && ((int64_t)1 << b) < x) ++b;
+    return b;
+}
+
+// Size class of a shape key (precision, batch, (m, n) pairs): precision,
+// ceil(log2) of the batch size, of the flop-weighted typical min(m, n), and
+// of the largest m and n.  Shapes in one class get the same blocking from a
+// tuned entry when no entry has exactly their shapes.
+std::vector<int64_t> tune_bucket(const std::vector<int64_t> &key)
+{
+    const int64_t batch = key.size() >= 2 ? key[1] : 0;
+    double wsum = 0.0, ksum = 0.0;
+    int64_t mmax = 0, nmax = 0;
+    for (int64_t i = 0; i < batch && 3 + 2 * i < (int64_t)key.size(); ++i) {
+        const int64_t m = key[2 + 2 * i], n = key[3 + 2 * i];
+        const double f = std::max(1.0, tileqr_flops_lapack(std::max(m, n), std::min(m, n)));
+        wsum += f;
+        ksum += f * (double)std::min(m, n);
+        mmax = std::max(mmax, m);
+        nmax = std::max(nmax, n);
+    }
+    const int64_t kt = wsum > 0.0 ? (int64_t)(ksum / wsum + 0.5) : 0;
+    return {key.empty() ? 0 : key[0], clog2(batch), clog2(kt), clog2(mmax), clog2(nmax)};
+}
+
+// Architecture name and compute-unit count of the current device (cached
+// per device), false without a device.
+bool device_signature(std::string &arch, int &cu)
+{
+    static std::vector<std::pair<int, std::pair<std::string, int>>> seen;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    for (auto &e : seen)
+        if (e.first == dev) {
+            arch = e.second.first;
+            cu = e.second.second;
+            return true;
+        }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
+    std::string a = prop.gcnArchName;
+    const size_t colon = a.find(':');
+    if (colon != std::string::npos) a.resize(colon);
+    seen.push_back({dev, {a, prop.multiProcessorCount}});
+    arch = a;
+    cu = prop.multiProcessorCount;
+    return true;
+}
+
+// The entry for exactly these shapes on this kind of device, else one of the
+// same size class (the most recently added).
+const tileqr_tuning *lookup_tuned(const std::string &arch, int cu, const std::vector<int64_t> &key)
 {
     const std::vector<TuneEntry> *tab = tuned_entries(false);
     if (!tab) return nullptr;
     for (const auto &e : *tab)
-        if (e.key == key) return &e.best;
+        if (e.arch == arch && e.cu == cu && e.key == key) return &e.best;
+    const std::vector<int64_t> bucket = tune_bucket(key);
+    for (auto it = tab->rbegin(); it != tab->rend(); ++it)
+        if (it->arch == arch && it->cu == cu && it->bucket == bucket) return &it->best;
     return nullptr;
+}
+
+const tileqr_tuning *find_tuned(const std::vector<int64_t> &key)
+{
+    if (!tuned_entries(false)) return nullptr;   // no HIP call while nothing is tuned
+    std::string arch;
+    int cu = 0;
+    if (!device_signature(arch, cu)) return nullptr;
+    return lookup_tuned(arch, cu, key);
 }
 
 std::vector<int64_t> shape_key(int64_t batch, const int64_t *m, const int64_t *n, int precision)
@@ -459,18 +530,127 @@ extern "C" int tileqr_tune(int64_t batch, const int64_t *m, const int64_t *n, in
     Abuf.release();
     Tbuf.release();
     if (rc) return rc;
+    std::string arch;
+    int cu = 0;
+    if (!device_signature(arch, cu)) return hip_fail(hipErrorNoDevice, "device properties");
     const std::vector<int64_t> key = shape_key(batch, m, n, precision);
     std::vector<TuneEntry> *tab = tuned_entries(true);
-    if (!tab) return hip_fail(hipErrorNoDevice, "tuner table");
-    bool found = false;
-    for (auto &e : *tab)
-        if (e.key == key) {
-            e.best = top;
-            found = true;
+    for (auto it = tab->begin(); it != tab->end(); ++it)
+        if (it->arch == arch && it->cu == cu && it->key == key) {
+            tab->erase(it);
+            break;
         }
-    if (!found) tab->push_back(TuneEntry{key, top});
+    TuneEntry e;
+    e.arch = arch;
+    e.cu = cu;
+    e.key = key;
+    e.bucket = tune_bucket(key);
+    e.best = top;
+    tab->push_back(e);
     *best = top;
     return TILEQR_OK;
+}
+
+// ------------------------------------------------------- tuner table files
+//
+// One entry per line, whitespace-separated:
+//   tileqr-tune-1 <arch> <cu> <nb> <ib> <panel_workers> <workers> <ms> <key length> <key...>
+// The size class is recomputed from the key on loading.
+
+extern "C" int64_t tileqr_tune_save(const char *path)
+{
+    if (!path) return -1;
+    std::lock_guard<std::mutex> lock(g_mu);
+    FILE *f = std::fopen(path, "w");
+    if (!f) return -2;
+    int64_t count = 0;
+    bool ok = true;
+    if (const std::vector<TuneEntry> *tab = tuned_entries(false))
+        for (const auto &e : *tab) {
+            ok = ok && std::fprintf(f, "tileqr-tune-1 %s %d %lld %lld %lld %lld %.17g %zu", e.arch.c_str(), e.cu,
+                                    (long long)e.best.nb, (long long)e.best.ib, (long long)e.best.panel_workers,
+                                    (long long)e.best.workers, e.best.ms, e.key.size()) > 0;
+            for (int64_t v : e.key) ok = ok && std::fprintf(f, " %lld", (long long)v) > 0;
+            ok = ok && std::fputc('\n', f) != EOF;
+            ++count;
+        }
+    ok = std::fclose(f) == 0 && ok;
+    return ok ? count : -2;
+}
+
+extern "C" int64_t tileqr_tune_load(const char *path)
+{
+    if (!path) return -1;
+    std::ifstream in(path);
+    if (!in) return -2;
+    std::vector<TuneEntry> got;
+    std::string line;
+    while (std::getline(in, line)) {
+        if (line.find_first_not_of(" \t\r") == std::string::npos) continue;
+        std::istringstream ls(line);
+        std::string tag;
+        TuneEntry e;
+        size_t klen = 0;
+        long long nb = 0, ib = 0, pw = 0, wk = 0;
+        if (!(ls >> tag >> e.arch >> e.cu >> nb >> ib >> pw >> wk >> e.best.ms >> klen) || tag != "tileqr-tune-1" ||
+            klen < 4 || klen > ((size_t)1 << 24))
+            return -3;
+        e.key.resize(klen);
+        for (auto &v : e.key) {
+            long long x;
+            if (!(ls >> x)) return -3;
+            v = x;
+        }
+        std::string extra;
+        if (ls >> extra) return -3;
+        // The key is (precision, batch, then batch (m, n) pairs), and the
+        // blocking one the library supports.
+        if (e.key[0] < TILEQR_FP64 || e.key[0] > TILEQR_BF16X3 || e.key[1] < 1 ||
+            klen != (size_t)(2 + 2 * e.key[1]) || !tileqr_blocking_supported(nb, ib) ||
+            !precision_supported((int)e.key[0], ib) || pw < 0 || wk < 0 || e.cu <= 0)
+            return -3;
+        for (size_t i = 2; i < klen; ++i)
+            if (e.key[i] < 0) return -3;
+        e.best.nb = nb;
+        e.best.ib = ib;
+        e.best.panel_workers = pw;
+        e.best.workers = wk;
+        e.bucket = tune_bucket(e.key);
+        got.push_back(std::move(e));
+    }
+    std::lock_guard<std::mutex> lock(g_mu);
+    std::vector<TuneEntry> *tab = tuned_entries(true);
+    for (auto &e : got) {
+        for (auto it = tab->begin(); it != tab->end(); ++it)
+            if (it->arch == e.arch && it->cu == e.cu && it->key == e.key) {
+                tab->erase(it);
+                break;
+            }
+        tab->push_back(std::move(e));
+    }
+    return (int64_t)got.size();
+}
+
+extern "C" int tileqr_tune_lookup(const char *arch, int cu, int64_t batch, const int64_t *m, const int64_t *n,
+                                  int precision, tileqr_tuning *out)
+{
+    if (!arch) return -1;
+    if (batch < 1) return -3;
+    if (!m) return -4;
+    if (!n) return -5;
+    if (precision < TILEQR_FP64 || precision > TILEQR_BF16X3) return -6;
+    if (!out) return -7;
+    std::lock_guard<std::mutex> lock(g_mu);
+    const tileqr_tuning *t = lookup_tuned(arch, cu, shape_key(batch, m, n, precision));
+    if (!t) return 0;
+    *out = *t;
+    return 1;
+}
+
+extern "C" void tileqr_tune_clear(void)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    if (std::vector<TuneEntry> *tab = tuned_entries(false)) tab->clear();
 }
 
 extern "C" int tileqr_solve_ls_batched(int64_t batch, const int64_t *m, const int64_t *n, const double *const *A,

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "../../include/tileqr.h"
@@ -53,9 +54,13 @@ struct SchedBufs {
     void release();
 };
 
-// Best blocking and schedule found by tileqr_tune for a set of shapes.
+// Best blocking and schedule found by tileqr_tune for a set of shapes, on a
+// device of architecture `arch` with `cu` compute units.
 struct TuneEntry {
-    std::vector<int64_t> key;   // precision, batch, then (m, n) sorted
+    std::string arch;
+    int cu = 0;
+    std::vector<int64_t> key;      // precision, batch, then (m, n) sorted
+    std::vector<int64_t> bucket;   // size class of the key (tune_bucket)
     tileqr_tuning best;
 };
 
@@ -93,8 +98,8 @@ Workspace *workspace(hipStream_t stream);
 // Workspaces of the last synchronous timed call and of the last traced call.
 extern Workspace *g_last_timed;
 extern Workspace *g_last_traced;
-// The tuner's entries for the current device; with create == false,
-// nullptr if there are none (and no HIP call is made before the first).
+// The tuner's table (entries made by tileqr_tune or loaded from a file, for
+// any device); with create == false, nullptr while it is empty.
 std::vector<TuneEntry> *tuned_entries(bool create);
 // tileqr_choose_blocking for callers that hold g_mu.
 void choose_blocking_held(int64_t m, int64_t n, int precision, int64_t *nb, int64_t *ib);

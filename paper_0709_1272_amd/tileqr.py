@@ -74,6 +74,10 @@ _SIGS = {
                                        ctypes.POINTER(_vp), ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(BatchInfo)]),
     "tileqr_tune": (_int, [_i64, _I64P, _I64P, _int, _int, ctypes.POINTER(Tuning)]),
+    "tileqr_tune_save": (_i64, [ctypes.c_char_p]),
+    "tileqr_tune_load": (_i64, [ctypes.c_char_p]),
+    "tileqr_tune_lookup": (_int, [ctypes.c_char_p, _int, _i64, _I64P, _I64P, _int, ctypes.POINTER(Tuning)]),
+    "tileqr_tune_clear": (None, []),
     "tileqr_flops_lapack": (_dbl, [_i64, _i64]),
     "tileqr_flops_tiled": (_dbl, [_i64, _i64, _i64, _i64]),
     "tileqr_dag_counts": (_i64, [_i64, _i64, _i64, _i64, _I64P]),
@@ -184,6 +188,38 @@ def tune(ms, ns, precision=FP64, trials=2):
     t = Tuning()
     check(_L.tileqr_tune(b, arr(ms), arr(ns), precision, trials, ctypes.byref(t)), "tileqr_tune")
     return t
+
+
+def tune_save(path):
+    """Write the tuner's table to a text file; returns the entry count."""
+    r = _L.tileqr_tune_save(os.fsencode(path))
+    if r < 0:
+        raise OSError(f"tileqr_tune_save({path!r}) returned {r}")
+    return r
+
+
+def tune_load(path):
+    """Add the entries of a file written by tune_save; returns their count."""
+    r = _L.tileqr_tune_load(os.fsencode(path))
+    if r < 0:
+        raise OSError(f"tileqr_tune_load({path!r}) returned {r}")
+    return r
+
+
+def tune_lookup(arch, cu, ms, ns, precision=FP64):
+    """The tuned entry the automatic blocking would use on a device of this
+    architecture and CU count (exact shapes, else the size class), or None."""
+    b = len(ms)
+    arr = lambda vals: (ctypes.c_int64 * b)(*[int(v) for v in vals])
+    t = Tuning()
+    r = _L.tileqr_tune_lookup(arch.encode(), cu, b, arr(ms), arr(ns), precision, ctypes.byref(t))
+    if r < 0:
+        raise ValueError(f"tileqr_tune_lookup: argument {-r}")
+    return t if r == 1 else None
+
+
+def tune_clear():
+    _L.tileqr_tune_clear()
 
 
 def flops_lapack(m, n):

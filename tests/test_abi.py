@@ -126,3 +126,106 @@ def test_cli_arguments():
         cli.main(["solve", "--n", "8", "--precision", "fp8"])
     with pytest.raises(SystemExit):
         cli.main(["solve"])
+
+
+def _tune_line(arch, cu, nb, ib, pw, prec, shapes):
+    key = [prec, len(shapes)] + [v for mn in sorted(shapes) for v in mn]
+    return f"tileqr-tune-1 {arch} {cu} {nb} {ib} {pw} 0 1.5 {len(key)} " + " ".join(map(str, key))
+
+
+def test_tune_table_file_exact_and_size_class(tmp_path):
+    # The tuner's table survives the process through a text file and serves
+    # shapes of the same size class (ceil log2 of the batch, of the typical
+    # min(m, n) and of the largest m and n) when no entry has exactly theirs.
+    tq = _tq()
+    tq.tune_clear()
+    try:
+        f = tmp_path / "tune.txt"
+        f.write_text("\n".join([
+            _tune_line("gfx950", 256, 256, 32, 0, tq.FP64, [(8192, 8192)]),
+            _tune_line("gfx950", 256, 128, 16, 32, tq.FP64, [(700, 300), (500, 500), (64, 40)]),
+            _tune_line("gfx942", 304, 64, 16, 0, tq.FP64, [(8192, 8192)]),
+            _tune_line("gfx950", 256, 128, 32, 0, tq.BF16X3, [(8192, 8192)]),
+        ]) + "\n")
+        assert tq.tune_load(str(f)) == 4
+        t = tq.tune_lookup("gfx950", 256, [8192], [8192])
+        assert (t.nb, t.ib, t.panel_workers) == (256, 32, 0)
+        t = tq.tune_lookup("gfx950", 256, [8000], [7000])        # same class as 8192^2
+        assert (t.nb, t.ib) == (256, 32)
+        assert tq.tune_lookup("gfx950", 256, [4000], [4000]) is None   # next class down
+        t = tq.tune_lookup("gfx942", 304, [8192], [8192])
+        assert (t.nb, t.ib) == (64, 16)
+        assert tq.tune_lookup("gfx950", 128, [8192], [8192]) is None   # other CU count
+        t = tq.tune_lookup("gfx950", 256, [8192], [8192], tq.BF16X3)
+        assert (t.nb, t.ib) == (128, 32)
+        assert tq.tune_lookup("gfx950", 256, [8192], [8192], tq.FP16X2) is None
+        t = tq.tune_lookup("gfx950", 256, [64, 500, 700], [40, 500, 300])   # the batch, any order
+        assert (t.nb, t.ib, t.panel_workers) == (128, 16, 32)
+        t = tq.tune_lookup("gfx950", 256, [60, 480, 690], [40, 490, 300])   # same class
+        assert (t.nb, t.ib) == (128, 16)
+        assert tq.tune_lookup("gfx950", 256, [700] * 9, [300] * 9) is None  # batch of 9: 4 > 2
+        # Save, clear, load back: the same answers.
+        g = tmp_path / "saved.txt"
+        assert tq.tune_save(str(g)) == 4
+        tq.tune_clear()
+        assert tq.tune_lookup("gfx950", 256, [8192], [8192]) is None
+        assert tq.tune_load(str(g)) == 4
+        t = tq.tune_lookup("gfx950", 256, [8000], [7000])
+        assert (t.nb, t.ib) == (256, 32)
+        # Loading an entry with the same device kind and shapes replaces it.
+        h = tmp_path / "newer.txt"
+        h.write_text(_tune_line("gfx950", 256, 128, 32, 0, tq.FP64, [(8192, 8192)]) + "\n")
+        assert tq.tune_load(str(h)) == 1
+        assert tq.tune_save(str(g)) == 4
+        t = tq.tune_lookup("gfx950", 256, [8192], [8192])
+        assert (t.nb, t.ib) == (128, 32)
+    finally:
+        tq.tune_clear()
+
+
+@pytest.mark.parametrize("line", [
+    "tileqr-tune-2 gfx950 256 256 32 0 0 1.0 4 0 1 64 64",          # unknown version
+    "tileqr-tune-1 gfx950 256 96 32 0 0 1.0 4 0 1 64 64",           # unsupported nb
+    "tileqr-tune-1 gfx950 256 256 16 0 0 1.0 4 3 1 64 64",          # split precision with ib 16
+    "tileqr-tune-1 gfx950 256 256 32 0 0 1.0 6 0 1 64 64 64 64",    # key longer than its batch
+    "tileqr-tune-1 gfx950 256 256 32 0 0 1.0 4 0 1 64",             # key cut short
+    "tileqr-tune-1 gfx950 256 256 32 0 0 1.0 4 0 1 64 64 7",        # trailing token
+    "tileqr-tune-1 gfx950 0 256 32 0 0 1.0 4 0 1 64 64",            # no compute units
+    "tileqr-tune-1 gfx950 256 256 32 0 0 1.0 4 0 1 -64 64",         # negative size
+])
+def test_tune_table_file_rejects_malformed_lines(tmp_path, line):
+    tq = _tq()
+    tq.tune_clear()
+    try:
+        f = tmp_path / "bad.txt"
+        f.write_text(_tune_line("gfx950", 256, 256, 32, 0, tq.FP64, [(8192, 8192)]) + "\n" + line + "\n")
+        with pytest.raises(OSError):
+            tq.tune_load(str(f))
+        assert tq.tune_lookup("gfx950", 256, [8192], [8192]) is None   # nothing loaded
+        with pytest.raises(OSError):
+            tq.tune_load(str(tmp_path / "missing.txt"))
+    finally:
+        tq.tune_clear()
+
+
+def test_trace_export_format(tmp_path):
+    # Chrome trace-event JSON from trace tuples (type, k, i, j, strip,
+    # worker, t_pop, t_start, t_body_end, t_end): per task a body slice and,
+    # when they take time, the acquire and the release slices.
+    import json
+    from paper_0709_1272_amd import trace
+    ev = [(0, 0, 0, 0, 1, 0, 100, 110, 200, 210),
+          (3, 0, 2, 1, 3, (1 << 16) | 5, 150, 150, 400, 420),
+          (4, 0, 1, 2, 6, (1 << 16) | 7, 300, 305, 350, 350)]
+    n = trace.write_chrome_json(str(tmp_path / "t.json"), ev, 1e8)   # 10 ns per tick
+    data = json.loads((tmp_path / "t.json").read_text())["traceEvents"]
+    assert n == len(data)
+    bodies = [d for d in data if d["ph"] == "X" and d.get("cat") != "fence"]
+    assert [d["name"] for d in bodies] == ["GEQRT(0,0) panel 1", "SSRFB(0,2,1) strip 3", "PUPD(0,1) panel 2 strip 6"]
+    assert bodies[0]["ts"] == pytest.approx(0.1) and bodies[0]["dur"] == pytest.approx(0.9)
+    assert bodies[1]["ts"] == pytest.approx(0.5) and bodies[1]["dur"] == pytest.approx(2.5)
+    fences = [d for d in data if d.get("cat") == "fence"]
+    assert len(fences) == 4   # acquire + release of the first, release of the second, acquire of the third
+    names = {d["args"]["name"] for d in data if d["ph"] == "M" and d["name"] == "thread_name"}
+    assert names == {"panel wg 0", "update wg 5", "update wg 7"}
+    assert trace.chrome_events([], 1e8) == []

@@ -222,6 +222,29 @@ def test_tuner_picks_a_supported_blocking_and_is_used(tq):
     assert tq.choose_blocking(1500, 700) == (t1.nb, t1.ib)
 
 
+def test_tuned_entry_serves_its_size_class_and_persists(tq, tmp_path):
+    # A tuned single shape also sets the blocking of shapes in its size class;
+    # the table goes to a file and back, keyed by the device's kind.
+    import torch
+    t1 = tq.tune([1500], [700], tq.FP64, trials=1)
+    assert tq.choose_blocking(1500, 700) == (t1.nb, t1.ib)
+    assert tq.choose_blocking(1600, 600) == (t1.nb, t1.ib)       # same size class
+    f = tmp_path / "tune.txt"
+    assert tq.tune_save(str(f)) >= 1
+    props = torch.cuda.get_device_properties(0)
+    arch = props.gcnArchName.split(":")[0]
+    assert arch in f.read_text()
+    tq.tune_clear()
+    try:
+        assert tq.choose_blocking(1500, 700) == (128, 16)        # the untuned default
+        assert tq.tune_load(str(f)) >= 1
+        assert tq.choose_blocking(1500, 700) == (t1.nb, t1.ib)
+        t = tq.tune_lookup(arch, props.multi_processor_count, [1500], [700])
+        assert t is not None and (t.nb, t.ib) == (t1.nb, t1.ib)
+    finally:
+        tq.tune_clear()
+
+
 def test_full_batched_config_sampled(tq):
     # 4000 matrices, m ~ U{32..768}, n ~ U{16..m}, N(0, 1), seed 0; one call.
     mats = synth.batch_matrices(0)[2]

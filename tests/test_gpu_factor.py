@@ -225,3 +225,24 @@ def test_full_size_8192_sampled(tq):
             r = R[:, a] @ R[:, b]
             tol = 1e-13 * np.linalg.norm(A[:, a]) * np.linalg.norm(A[:, b])
             assert abs(g - r) <= tol, (a, b, g, r)
+
+
+def test_trace_covers_every_task(tq, tmp_path):
+    # With TILEQR_FLAG_TRACE every task of the DAG leaves one event with
+    # ordered timestamps, and the export writes a loadable trace file.
+    import json
+    from paper_0709_1272_amd import trace
+    A = synth.uniform(5, 1024, 768)
+    At = tq.to_device(A)
+    T = torch.empty(tq.t_size(1024, 768, 128, 32), dtype=torch.float64, device="cuda")
+    o = tq.opts(flags=tq.FLAG_TRACE, panel_tasks=4)
+    tq.check(tq.factor(1024, 768, At.data_ptr(), 1024, 128, 32, T.data_ptr(), o), "factor")
+    events, hz = tq.trace()
+    total, _ = tq.dag_counts(8, 6, 4, 4)
+    assert len(events) == total and hz > 0
+    for ev in events:
+        assert ev[6] <= ev[7] <= ev[8] <= ev[9], ev
+    assert sorted({ev[0] for ev in events}) == [0, 1, 2, 3, 4]
+    n = trace.write_chrome_json(str(tmp_path / "qr.json"), events, hz)
+    assert n >= len(events)
+    assert len(json.loads((tmp_path / "qr.json").read_text())["traceEvents"]) == n
