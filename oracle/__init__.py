@@ -1,12 +1,14 @@
-"""Oracle for the tiled Householder QR: TEST INFRASTRUCTURE ONLY.
+"""Oracles for the tiled Householder QR and the tiled Cholesky factorisation:
+TEST INFRASTRUCTURE ONLY.
 
 Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  The library never does, and nothing here imports the
 library: the two share no code.
 
 ``oracle.c`` holds the arithmetic (unblocked Householder QR, application of
-Q and Q^T, back substitution, least squares).  This module marshals numpy
-arrays into it.  The error measures used to assess a factorisation or a
+Q and Q^T, back substitution, least squares), ``cholesky.c`` the plain
+column-by-column Cholesky factorisation and its solve.  This module marshals
+numpy arrays into them.  The error measures used to assess a factorisation or a
 solution (``r_diff``, ``beta_fact``, ``beta_orth``, ``eta_inf``, ``eta_ls``)
 are defined in ``metrics.py`` and re-exported here.
 """
@@ -164,6 +166,66 @@ def thin_q(F, tau):
 
 def oracle_beta_fact(A, F, tau):
     return default().beta_fact(A, F, tau)
+
+
+# ----------------------------------------------------------------- Cholesky
+
+class CholOracle:
+    """The C Cholesky oracle (cholesky.c) from one shared library (the
+    default build, or a mutant the tests compile)."""
+
+    def __init__(self, path=None):
+        if path is None:
+            path = _build.CHOL_LIB
+            if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.CHOL_SRC):
+                _build.build(force=False)
+        L = ctypes.CDLL(path)
+        i64, dp, ci = ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.c_int
+        L.oracle_potrf_lower.argtypes = [i64, dp, i64]
+        L.oracle_potrf_lower.restype = ci
+        L.oracle_potrs_lower.argtypes = [i64, i64, dp, i64, dp, i64]
+        L.oracle_potrs_lower.restype = ci
+        self.L = L
+
+    def potrf(self, A):
+        """(L, info): the Cholesky factor of the lower triangle of A (L lower
+        triangular, zeros above) and 0; or, when the leading minor of order
+        info > 0 is not positive definite, the partial result and info."""
+        F = _fortran(A)
+        n = F.shape[0]
+        info = self.L.oracle_potrf_lower(n, _ptr(F), max(n, 1))
+        if info < 0:
+            raise ValueError(f"oracle_potrf_lower info={info}")
+        return np.tril(F), info
+
+    def potrs(self, Lf, B):
+        """X with L L^T X = B for the factor of potrf."""
+        F = _fortran(Lf)
+        n = F.shape[0]
+        vec = B.ndim == 1
+        X = _fortran(B.reshape(n, -1) if vec else B)
+        info = self.L.oracle_potrs_lower(n, X.shape[1], _ptr(F), max(n, 1), _ptr(X), max(n, 1))
+        if info != 0:
+            raise ValueError(f"oracle_potrs_lower info={info}")
+        return X[:, 0] if vec else X
+
+
+_chol = None
+
+
+def chol_default():
+    global _chol
+    if _chol is None:
+        _chol = CholOracle()
+    return _chol
+
+
+def potrf(A):
+    return chol_default().potrf(A)
+
+
+def potrs(Lf, B):
+    return chol_default().potrs(Lf, B)
 
 
 # ----------------------------------------------------------------- metrics
