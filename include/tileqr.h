@@ -54,7 +54,8 @@ typedef enum {
     TILEQR_ETIMEOUT = 4,    /* scheduler watchdog: no task became ready in time     */
     TILEQR_ENOMEM = 5,      /* workspace allocation failed                          */
     TILEQR_EUNSUPPORTED = 6,/* a valid but unsupported combination (see nb/ib rules)*/
-    TILEQR_ESINGULAR = 7    /* R has an exact zero on its diagonal (solve only)     */
+    TILEQR_ESINGULAR = 7,   /* R has an exact zero on its diagonal (solve only)     */
+    TILEQR_ENOTSPD = 8      /* tilechol: a leading minor is not positive definite   */
 } tileqr_status;
 
 /* Arithmetic of the block-reflector products: LARFB, SSRFB and the updates

@@ -25,6 +25,7 @@ UNITS = [("tileqr_kernels.hip", [], "tileqr_kernels"),
          ("tileqr_peak.hip", [], "tileqr_peak"),
          ("tileqr_noalloc.hip", [], "tileqr_noalloc"),
          ("tileqr_lsbatch.hip", [], "tileqr_lsbatch"),
+         ("tilechol.hip", [], "tilechol"),
          ("tileqr_api.cpp", [], "tileqr_api"),
          ("tileqr_batched.cpp", [], "tileqr_batched")]
 SOURCES = sorted({u[0] for u in UNITS})

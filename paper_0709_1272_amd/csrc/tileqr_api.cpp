@@ -712,6 +712,7 @@ extern "C" const char *tileqr_status_string(int s)
     case TILEQR_ENOMEM: return "out of device memory";
     case TILEQR_EUNSUPPORTED: return "unsupported blocking";
     case TILEQR_ESINGULAR: return "singular triangular factor";
+    case TILEQR_ENOTSPD: return "matrix not positive definite";
     default: return "unknown status";
     }
 }

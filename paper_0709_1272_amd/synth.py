@@ -24,6 +24,10 @@ experiments draw entries with randn):
                    entries N(0, 1)                           (batched QR)
 * ``batch_ls``     the same matrices, then one consistent right-hand side
                    each, b_i = A_i x_i with x_i ~ N(0, 1)    (batched least squares)
+* ``spd_matrix``   A = U diag(s) U^T, symmetric positive definite with
+                   eigenvalues log-spaced from 1 to 1/kappa  (Cholesky)
+* ``spd_matrix_device``  the same spectrum with the structured orthogonal U of
+                   ``svd_matrix_device``, built on the GPU   (large Cholesky)
 """
 import numpy as np
 
@@ -147,6 +151,43 @@ def svd_matrix_haar_device(seed, m, n, kappa, nrhs=1, noise=1e-6, device="cuda")
     X = torch.randn((nrhs, n), generator=g, device=device, dtype=torch.float64)
     Bt = X @ At + noise * torch.randn((nrhs, m), generator=g, device=device, dtype=torch.float64)
     return At.contiguous(), Bt.contiguous(), X.contiguous()
+
+
+def spd_matrix(seed, n, kappa=1e3):
+    """Symmetric positive definite n x n: A = U diag(s) U^T with U the
+    orthogonal factor of a Gaussian matrix and s = logspace(0, -log10 kappa, n);
+    exactly symmetric (the mean of A and A^T), column-major."""
+    rng = np.random.default_rng(seed)
+    U = _orthonormal_columns(rng, n, n)
+    s = np.logspace(0.0, -np.log10(kappa), n)
+    A = (U * s[None, :]) @ U.T
+    return np.asfortranarray((A + A.T) / 2.0)
+
+
+def spd_matrix_device(seed, n, kappa=1e6, device="cuda"):
+    """Symmetric positive definite n x n on `device` (n a power of two):
+    A = U diag(s) U^T with U = H D1 P1 H D2 (H the normalised Walsh-Hadamard
+    matrix, D random signs, P a random permutation) and
+    s = logspace(0, -log10 kappa, n); returned as a contiguous (n, n) tensor
+    (A is symmetric, so row- and column-major agree), exactly symmetric."""
+    import torch
+    assert n & (n - 1) == 0, "n must be a power of two"
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    sign = lambda: torch.randint(0, 2, (n,), generator=g, device=device, dtype=torch.int64).to(torch.float64) * 2 - 1
+    d1, d2 = sign(), sign()
+    p1 = torch.randperm(n, generator=g, device=device)
+    s = torch.logspace(0.0, -float(torch.log10(torch.tensor(kappa))), n, dtype=torch.float64, device=device)
+    # M = U diag(sqrt(s)), then A = M M^T.
+    M = torch.diag(torch.sqrt(s) * d2)          # D2 S^(1/2)
+    M = _hadamard(M, 0)                         # H D2 S^(1/2)
+    M = M[p1]                                   # P1 H D2 S^(1/2)
+    M = M * d1[:, None]                         # D1 P1 H D2 S^(1/2)
+    M = _hadamard(M, 0)                         # U S^(1/2)
+    A = M @ M.t()
+    del M
+    A = (A + A.t()) * 0.5
+    return A.contiguous()
 
 
 def batch_sizes(seed, count=4000, m_lo=32, m_hi=768, n_lo=16):

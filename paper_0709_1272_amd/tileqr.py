@@ -21,7 +21,7 @@ if not os.path.exists(LIB_PATH):
 
 _L = ctypes.CDLL(LIB_PATH)
 
-OK, EHIP, ENONFINITE, ENOCONV, ETIMEOUT, ENOMEM, EUNSUPPORTED, ESINGULAR = range(8)
+OK, EHIP, ENONFINITE, ENOCONV, ETIMEOUT, ENOMEM, EUNSUPPORTED, ESINGULAR, ENOTSPD = range(9)
 FP64, BF16X2, FP16X2, BF16X3 = range(4)
 FLAG_ASYNC, FLAG_SERIAL, FLAG_TRACE, FLAG_SHUFFLE, FLAG_TIMING, FLAG_NO_GRAPH, FLAG_CHECK = 1, 2, 4, 8, 16, 32, 64
 

@@ -229,3 +229,45 @@ def test_trace_export_format(tmp_path):
     names = {d["args"]["name"] for d in data if d["ph"] == "M" and d["name"] == "thread_name"}
     assert names == {"panel wg 0", "update wg 5", "update wg 7"}
     assert trace.chrome_events([], 1e8) == []
+
+
+def test_tilechol_exports_match_header():
+    _tq()
+    from paper_0709_1272_amd import tilechol
+    text = open(os.path.join(ROOT, "include", "tilechol.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    declared = sorted(set(re.findall(r"\b(tilechol_[a-z_0-9]+)\s*\(", text)))
+    assert declared and sorted(tilechol.EXPORTS) == declared
+    for name in declared:
+        assert hasattr(tilechol._L, name), name
+
+
+def test_tilechol_dag_counts_and_selfcheck():
+    # Algorithm 1 on a p x p tile grid: p POTF2, p(p-1)/2 TRSM and
+    # (p-1)p(p+1)/6 GSMM (k < j <= i); the scheduler's in-degrees match its
+    # successor lists and random topological orders respect every tile's
+    # order of writes in Algorithm 1.
+    _tq()
+    from paper_0709_1272_amd import tilechol
+    for p in (1, 2, 3, 4, 7, 16):
+        total, c = tilechol.dag_counts(p)
+        brute = [p, sum(1 for k in range(p) for i in range(k + 1, p)),
+                 sum(1 for k in range(p) for i in range(k + 1, p) for j in range(k + 1, i + 1))]
+        assert c == brute and total == sum(brute), p
+        assert tilechol.dag_selfcheck(p, trials=4, seed=p) == 0, p
+    assert tilechol.dag_selfcheck(0) == -1 and tilechol.dag_selfcheck(65) == -1
+
+
+def test_tilechol_argument_checks_need_no_device():
+    tq = _tq()
+    from paper_0709_1272_amd import tilechol
+    info = tilechol.CholInfo()
+    assert tilechol.factor(-1, 0, 1) == -1
+    assert tilechol.factor(4, 0, 4) == -2
+    assert tilechol.factor(4, 1 << 20, 3) == -3
+    assert tilechol.factor(4, 1 << 20, 4, 256) == -4
+    assert tilechol.factor(4, 1 << 20, 4, 32) == -4
+    assert tilechol.factor(4, 1 << 20, 4, 64, tq.opts(precision=7)) == -5
+    assert tilechol.factor(4, 1 << 20, 4, 64, tq.opts(precision=tq.BF16X3), info) == tq.EUNSUPPORTED
+    assert tilechol.factor(0, 0, 1, 0, None, info) == tq.OK and info.nb == 64
+    assert tq.status_string(tq.ENOTSPD) == "matrix not positive definite"
