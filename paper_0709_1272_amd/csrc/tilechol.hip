@@ -166,17 +166,22 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Row strides of the LDS arrays: two doubles of padding, so that the 16
+// rows x 4 columns an MFMA operand load reads (lane n + 16 g: row n, column
+// g) fall in distinct banks in each half-wave (bank pair 4 n + 2 g).
+constexpr int LDX(int cols) { return cols + 2; }
+
 template <int NB>
 struct SmemF {
-    double X[NB][NB + 1];      // the tile being factored or solved
+    double X[NB][LDX(NB)];     // the tile being factored or solved
     double Lb[PW][PW + 1];     // TRSM: the diagonal block of L_kk of the panel
     int fail;
 };
 
 template <int NB>
 struct SmemG {
-    double A[2][NB][KC + 1];   // L_ik, columns [kc, kc + KC)
-    double B[2][NB][KC + 1];   // L_jk, same columns
+    double A[2][NB][LDX(KC)];  // L_ik, columns [kc, kc + KC)
+    double B[2][NB][LDX(KC)];  // L_jk, same columns
 };
 
 template <int NB>
@@ -275,7 +280,7 @@ __device__ void task_potf2(SmemF<NB> &sm, double *T, int k, int32_t *status, int
         }
         __syncthreads();
         if (sm.fail) return;
-        solve_rows<NB>(sm, &sm.X[c0][c0], NB + 1, c0 + PW, c0);
+        solve_rows<NB>(sm, &sm.X[c0][c0], LDX(NB), c0 + PW, c0);
         __syncthreads();
     }
     for (int e = tid; e < NB * NB; e += NT) {
