@@ -47,7 +47,7 @@ KAPPA = 1e6
 NB, IB = 256, 32
 TOL = 1e-14
 CPU_SAMPLE_N = 2048
-EXTRAS = ("fp16x2_ls", "qr8192", "tall_ls", "batched", "mfma_peak")
+EXTRAS = ("fp16x2_ls", "qr8192", "tall_ls", "batched", "cholesky", "mfma_peak")
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 # Sources the worker kernels are compiled from: a traffic figure in a profile
 # is valid only for the build whose hash it records.
@@ -56,15 +56,18 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_0709_1272_amd", "csrc", f)
                          "tileqr_internal.h")]
 
 
-def kernel_hash():
+CHOL_SRCS = [os.path.join(ROOT, "paper_0709_1272_amd", "csrc", "tilechol.hip")]
+
+
+def kernel_hash(srcs=None):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SRCS:
+    for f in (KERNEL_SRCS if srcs is None else srcs):
         h.update(open(f, "rb").read())
     return h.hexdigest()
 
 
-def measured_traffic(profile):
+def measured_traffic(profile, srcs=None):
     """HBM bytes per launch of a worker kernel from a committed rocprofv3
     counter summary (FETCH_SIZE + WRITE_SIZE, each scaled by what the counter
     reads for a plain copy of known size), or None when the kernel sources
@@ -74,7 +77,7 @@ def measured_traffic(profile):
         text = open(os.path.join(PROFILE_DIR, profile)).read()
     except OSError:
         return None
-    if kernel_hash() not in text:
+    if kernel_hash(srcs) not in text:
         return None
     m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+-]+)", text)
     return float(m.group(1)) if m else None
@@ -190,6 +193,35 @@ def qr8192(tq, torch, dev, st):
             "worker_ms": round(wk, 4), "worker_frac_fp64_peak": round(flops / (wk * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
             "traffic_bytes_per_launch": measured_traffic("k_worker_qr8192_fp64.md"),
             "algorithmic_bytes": ssrfb_bytes(m, n, NB)}
+
+
+def cholesky(tq, torch, dev, st):
+    """Tiled Cholesky (Algorithm 1) of one 32768 x 32768 SPD matrix with
+    eigenvalues log-spaced from 1 to 1e-6, nb 128, FP64."""
+    from paper_0709_1272_amd import synth, tilechol as tc
+    n, nb = 32768, 128
+    A0 = synth.spd_matrix_device(0, n, 1e6, device=dev)
+    A = torch.empty_like(A0)
+    res = []
+    for r in range(4):
+        A.copy_(A0)
+        info = tc.CholInfo()
+        tq.check(tc.factor(n, A.data_ptr(), n, nb, tq.opts(stream=st.cuda_stream, flags=tq.FLAG_TIMING), info),
+                 "tilechol_factor")
+        if r:
+            res.append((info.ms_factor, info.ms_worker))
+    del A, A0
+    torch.cuda.empty_cache()
+    ms = sum(r[0] for r in res) / len(res)
+    wk = sum(r[1] for r in res) / len(res)
+    p = n // nb
+    return {"workload": f"tiled Cholesky (Algorithm 1) of one {n}x{n} SPD matrix, U diag(s) U^T with s log-spaced "
+                        f"to 1e-6 (Walsh-Hadamard U, seed 0), nb {nb}, FP64",
+            "ms": round(ms, 3), "tflops": round(tc.flops(n) / (ms * 1e-3) / 1e12, 4),
+            "worker_ms": round(wk, 3),
+            "worker_frac_fp64_peak": round(tc.flops(n) / (wk * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+            "traffic_bytes_per_launch": measured_traffic("k_chol_worker_chol32768_fp64.md", CHOL_SRCS),
+            "algorithmic_bytes": 16.0 * nb * nb * sum(m * (m + 1) // 2 for m in range(1, p))}
 
 
 def tall_ls(tq, torch, dev, st):
@@ -420,6 +452,8 @@ def main():
         torch.cuda.empty_cache()
     if "batched" in extras:
         out["batched"] = batched(tq, torch, dev, st)
+    if "cholesky" in extras:
+        out["cholesky"] = cholesky(tq, torch, dev, st)
     if "mfma_peak" in extras:
         out["mfma_peak"] = {"fp64": round(tq.mfma_peak(0), 2), "bf16": round(tq.mfma_peak(1), 2),
                             "fp16": round(tq.mfma_peak(2), 2), "unit": "TFLOP/s",
