@@ -7,7 +7,9 @@ library: the two share no code.
 
 ``oracle.c`` holds the arithmetic (unblocked Householder QR, application of
 Q and Q^T, back substitution, least squares), ``cholesky.c`` the plain
-column-by-column Cholesky factorisation and its solve.  This module marshals
+column-by-column Cholesky factorisation and its solve, ``lu.c`` the tiled LU
+factorisation with tiled pairwise pivoting (Algorithm 3's steps) and its
+solve.  This module marshals
 numpy arrays into them.  The error measures used to assess a factorisation or a
 solution (``r_diff``, ``beta_fact``, ``beta_orth``, ``eta_inf``, ``eta_ls``)
 are defined in ``metrics.py`` and re-exported here.
@@ -226,6 +228,72 @@ def potrf(A):
 
 def potrs(Lf, B):
     return chol_default().potrs(Lf, B)
+
+
+# ------------------------------------------------------------------- LU
+
+class LUOracle:
+    """The C tiled-LU oracle (lu.c) from one shared library (the default
+    build, or a mutant the tests compile)."""
+
+    def __init__(self, path=None):
+        if path is None:
+            path = _build.LU_LIB
+            if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.LU_SRC):
+                _build.build(force=False)
+        L = ctypes.CDLL(path)
+        i64, dp, ci = ctypes.c_int64, ctypes.POINTER(ctypes.c_double), ctypes.c_int
+        ip = ctypes.POINTER(ctypes.c_int32)
+        L.oracle_tile_lu.argtypes = [i64, i64, i64, dp, i64, dp, ip]
+        L.oracle_tile_lu.restype = ci
+        L.oracle_tile_lu_solve.argtypes = [i64, i64, i64, dp, i64, dp, ip, i64, dp, i64]
+        L.oracle_tile_lu_solve.restype = ci
+        self.L = L
+
+    def tile_lu(self, A, b, s):
+        """Algorithm 3 on A (n x n, n = p b): (F, Lup, piv, info) with F the
+        factored matrix (U above, L_kk and the TSTRF multipliers below), Lup
+        (p, p, s, b) and piv (p, p, b) indexed [k][i], info 0 or the 1-based
+        column that had no nonzero pivot."""
+        F = _fortran(A)
+        n = F.shape[0]
+        p = n // b if b else 0
+        Lup = np.zeros((max(p, 1), max(p, 1), s, b))
+        piv = np.zeros((max(p, 1), max(p, 1), b), dtype=np.int32)
+        info = self.L.oracle_tile_lu(n, b, s, _ptr(F), max(n, 1), _ptr(Lup),
+                                     piv.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        if info < 0:
+            raise ValueError(f"oracle_tile_lu info={info}")
+        return F, Lup, piv, info
+
+    def tile_lu_solve(self, F, Lup, piv, b, s, B):
+        n = F.shape[0]
+        vec = B.ndim == 1
+        X = _fortran(B.reshape(n, -1) if vec else B)
+        info = self.L.oracle_tile_lu_solve(n, b, s, _ptr(_fortran(F)), max(n, 1), _ptr(np.ascontiguousarray(Lup)),
+                                           np.ascontiguousarray(piv).ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                           X.shape[1], _ptr(X), max(n, 1))
+        if info != 0:
+            raise ValueError(f"oracle_tile_lu_solve info={info}")
+        return X[:, 0] if vec else X
+
+
+_lu = None
+
+
+def lu_default():
+    global _lu
+    if _lu is None:
+        _lu = LUOracle()
+    return _lu
+
+
+def tile_lu(A, b, s):
+    return lu_default().tile_lu(A, b, s)
+
+
+def tile_lu_solve(F, Lup, piv, b, s, B):
+    return lu_default().tile_lu_solve(F, Lup, piv, b, s, B)
 
 
 # ----------------------------------------------------------------- metrics

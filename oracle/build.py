@@ -13,6 +13,9 @@ LIB = os.path.join(HERE, "liboracle.so")
 # alone).
 CHOL_SRC = os.path.join(HERE, "cholesky.c")
 CHOL_LIB = os.path.join(HERE, "liboracle_chol.so")
+# The tiled LU oracle likewise.
+LU_SRC = os.path.join(HERE, "lu.c")
+LU_LIB = os.path.join(HERE, "liboracle_lu.so")
 
 
 def _compile(src, lib):
@@ -24,7 +27,7 @@ def _compile(src, lib):
 
 
 def build(force: bool = True) -> str:
-    for src, lib in ((SRC, LIB), (CHOL_SRC, CHOL_LIB)):
+    for src, lib in ((SRC, LIB), (CHOL_SRC, CHOL_LIB), (LU_SRC, LU_LIB)):
         if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
             _compile(src, lib)
     return LIB
