@@ -26,6 +26,7 @@ UNITS = [("tileqr_kernels.hip", [], "tileqr_kernels"),
          ("tileqr_noalloc.hip", [], "tileqr_noalloc"),
          ("tileqr_lsbatch.hip", [], "tileqr_lsbatch"),
          ("tilechol.hip", [], "tilechol"),
+         ("tilelu.hip", [], "tilelu"),
          ("tileqr_api.cpp", [], "tileqr_api"),
          ("tileqr_batched.cpp", [], "tileqr_batched")]
 SOURCES = sorted({u[0] for u in UNITS})
