@@ -4,12 +4,14 @@ synthetic matrix through the C-ABI, printing one JSON line.
     python -m paper_0709_1272_amd.cli factor --m 8192 --n 8192
     python -m paper_0709_1272_amd.cli solve --n 32768 --nrhs 16 --precision bf16x3
     python -m paper_0709_1272_amd.cli cholesky --n 32768 --nb 128
+    python -m paper_0709_1272_amd.cli lu --n 8192 --nb 64 --ib 16
 
 `factor` takes entries uniform(-1, 1); `solve` takes the Hadamard SVD
 construction of a square matrix (n a power of two) with singular values
 logspace(0, -log10 kappa, n) and B = A X + 1e-6 N(0, 1); `cholesky` the
 symmetric positive definite U diag(s) U^T of the same construction (tiled
-Cholesky, tilechol_factor).  Neither input needs
+Cholesky, tilechol_factor); `lu` entries N(0, 1) (tiled LU with pairwise
+pivoting, tilelu_factor).  Neither input needs
 a dense LAPACK routine on the device, so the driver also runs under hardware
 counter collection.  Before the first call the input is copied once on the
 device with a plain device-to-device copy of `copy_bytes` bytes, a kernel of
@@ -27,7 +29,7 @@ PRECISIONS = {"fp64": 0, "bf16x2": 1, "fp16x2": 2, "bf16x3": 3}
 
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_0709_1272_amd.cli")
-    ap.add_argument("op", choices=("factor", "solve", "cholesky"))
+    ap.add_argument("op", choices=("factor", "solve", "cholesky", "lu"))
     ap.add_argument("--m", type=int, default=None, help="rows (factor only; default n)")
     ap.add_argument("--n", type=int, required=True)
     ap.add_argument("--nrhs", type=int, default=1)
@@ -68,6 +70,27 @@ def main(argv=None):
         torch.cuda.synchronize()
         out["copy_bytes"] = A.numel() * A.element_size()
         out["flops"] = tc.flops(n)
+        print(json.dumps(out), flush=True)
+        return 0
+    if args.op == "lu":
+        from . import tilelu as tl
+        g = torch.Generator(device=dev)
+        g.manual_seed(args.seed)
+        A0 = torch.randn((n, n), generator=g, device=dev, dtype=torch.float64)
+        A = torch.empty_like(A0)
+        ib = args.ib if args.ib in (16, 32) else 16
+        Lup = torch.zeros(tl.lup_size(n, 64, ib), dtype=torch.float64, device=dev)
+        piv = torch.zeros(tl.piv_size(n, 64), dtype=torch.int32, device=dev)
+        out.update(nb=64, ib=ib, precision="fp64")
+        for _ in range(args.repeat):
+            A.copy_(A0)
+            info = tl.LUInfo()
+            tq.check(tl.factor(n, A.data_ptr(), n, 64, ib, Lup.data_ptr(), piv.data_ptr(),
+                               tq.opts(stream=st.cuda_stream, flags=tq.FLAG_TIMING), info), "tilelu_factor")
+            out["runs"].append({"ms_total": round(info.ms_factor, 3), "ms_worker": round(info.ms_worker, 3)})
+        torch.cuda.synchronize()
+        out["copy_bytes"] = A.numel() * A.element_size()
+        out["flops"] = tl.flops(n)
         print(json.dumps(out), flush=True)
         return 0
     if args.op == "factor":

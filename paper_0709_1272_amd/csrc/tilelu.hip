@@ -236,7 +236,18 @@ __device__ __forceinline__ void fail_column(const Sched &S, int col)
     __hip_atomic_fetch_min(S.minor, col + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// GETRF(k): partial pivoting of the diagonal tile, column by column.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// GETRF(k): partial pivoting of the diagonal tile, column by column on wave
+// 0 (the tile has as many rows as the wave has lanes): the pivot by a
+// wave-wide reduction, the exchange with one lane per column, the
+// multipliers and the rank-1 update with one lane per row.  Only wave-level
+// ordering between the phases; the other waves wait at the end.
 __device__ void task_getrf(Smem &sm, const Sched &S, int k)
 {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -244,40 +255,35 @@ __device__ void task_getrf(Smem &sm, const Sched &S, int k)
     load_tile(sm.X, T);
     if (tid == 0) sm.fail = 0;
     __syncthreads();
-    for (int j = 0; j < NB; ++j) {
-        if (w == 0) {
-            // Rows j .. NB-1, one per lane (NB == 64).
+    if (w == 0) {
+        for (int j = 0; j < NB; ++j) {
             double v = lane >= j ? fabs(sm.X[lane][j]) : -1.0;
             int idx = lane;
             wave_argmax(v, idx);
-            if (lane == 0) {
-                sm.pick = idx;
-                sm.piv[j] = idx;
-                if (v == 0.0) {
+            if (v == 0.0) {
+                if (lane == 0) {
                     sm.fail = 1;
                     fail_column(S, k * NB + j);
                 }
+                break;
             }
+            if (lane == 0) sm.piv[j] = idx;
+            if (idx != j) {
+                const double a = sm.X[j][lane], b = sm.X[idx][lane];
+                sm.X[j][lane] = b;
+                sm.X[idx][lane] = a;
+            }
+            wave_sync();
+            if (lane > j) {
+                const double l = sm.X[lane][j] / sm.X[j][j];
+                sm.X[lane][j] = l;
+                for (int c = j + 1; c < NB; ++c) sm.X[lane][c] = sm.X[lane][c] - l * sm.X[j][c];
+            }
+            wave_sync();
         }
-        __syncthreads();
-        if (sm.fail) return;
-        const int pr = sm.pick;
-        if (pr != j && tid < NB) {
-            const double t = sm.X[j][tid];
-            sm.X[j][tid] = sm.X[pr][tid];
-            sm.X[pr][tid] = t;
-        }
-        __syncthreads();
-        const double d = sm.X[j][j];
-        if (tid > j && tid < NB) sm.X[tid][j] = sm.X[tid][j] / d;
-        __syncthreads();
-        const int m = NB - j - 1;
-        for (int e = tid; e < m * m; e += NT) {
-            const int r = j + 1 + e / m, c = j + 1 + e % m;
-            sm.X[r][c] = sm.X[r][c] - sm.X[r][j] * sm.X[j][c];
-        }
-        __syncthreads();
     }
+    __syncthreads();
+    if (sm.fail) return;
     store_tile(T, sm.X);
     int32_t *pv = S.piv + ((size_t)k * S.p + k) * NB;
     if (tid < NB) pv[tid] = sm.piv[tid];
@@ -337,47 +343,43 @@ __device__ void task_tstrf(Smem &sm, const Sched &S, int k, int i)
     __syncthreads();
     for (int l0 = 0; l0 < NB; l0 += ib) {
         const int l1 = l0 + ib;
-        for (int j = l0; j < l1; ++j) {
-            if (w == 0) {
+        // The panel's columns on wave 0: lane r owns row r of A_ik for the
+        // multipliers and the updates, lane c column c for the exchange.
+        if (w == 0) {
+            for (int j = l0; j < l1; ++j) {
                 double v = fabs(sm.Y[lane][j]);
                 int idx = lane;
                 wave_argmax(v, idx);
-                if (lane == 0) {
-                    const double u = fabs(sm.X[j][j]);
-                    const int pick = v > u ? idx : -1;
-                    sm.pick = pick;
-                    sm.piv[j] = pick >= 0 ? NB + pick : j;
-                    if (!(v > u) && u == 0.0) {
+                const double u = fabs(sm.X[j][j]);
+                const int pick = v > u ? idx : -1;
+                if (pick < 0 && u == 0.0) {
+                    if (lane == 0) {
                         sm.fail = 1;
                         fail_column(S, k * NB + j);
                     }
+                    break;
                 }
-            }
-            __syncthreads();
-            if (sm.fail) return;
-            const int pr = sm.pick;
-            if (pr >= 0 && tid < NB) {
-                const int c = tid;
-                if (c >= j) {
-                    const double t = sm.X[j][c];
-                    sm.X[j][c] = sm.Y[pr][c];
-                    sm.Y[pr][c] = t;
-                } else if (c >= l0) {
-                    sm.Lup[j - l0][c] = sm.Y[pr][c];
-                    sm.Y[pr][c] = 0.0;
+                if (lane == 0) sm.piv[j] = pick >= 0 ? NB + pick : j;
+                if (pick >= 0) {
+                    const int c = lane;
+                    if (c >= j) {
+                        const double t = sm.X[j][c];
+                        sm.X[j][c] = sm.Y[pick][c];
+                        sm.Y[pick][c] = t;
+                    } else if (c >= l0) {
+                        sm.Lup[j - l0][c] = sm.Y[pick][c];
+                        sm.Y[pick][c] = 0.0;
+                    }
                 }
+                wave_sync();
+                const double l = sm.Y[lane][j] / sm.X[j][j];
+                sm.Y[lane][j] = l;
+                for (int c = j + 1; c < l1; ++c) sm.Y[lane][c] = sm.Y[lane][c] - l * sm.X[j][c];
+                wave_sync();
             }
-            __syncthreads();
-            const double d = sm.X[j][j];
-            if (tid < NB) sm.Y[tid][j] = sm.Y[tid][j] / d;
-            __syncthreads();
-            const int m = l1 - j - 1;
-            for (int e = tid; e < NB * m; e += NT) {
-                const int r = e / m, c = j + 1 + e % m;
-                sm.Y[r][c] = sm.Y[r][c] - sm.Y[r][j] * sm.X[j][c];
-            }
-            __syncthreads();
         }
+        __syncthreads();
+        if (sm.fail) return;
         // Columns right of the panel: U's panel rows by L_up (one column per
         // thread), then A_ik by its multipliers.
         if (tid >= l1 && tid < NB) {
