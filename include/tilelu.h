@@ -65,7 +65,8 @@ size_t tilelu_piv_size(int64_t n, int64_t nb);
  * TILEQR_ESINGULAR (a column with no nonzero pivot: info->minor, A left
  * unchanged); TILEQR_ETIMEOUT; TILEQR_EHIP; TILEQR_ENOMEM;
  * TILEQR_EUNSUPPORTED (nb, ib or precision); or -1 n, -2 A, -3 lda, -4 nb,
- * -5 ib, -6 Lup, -7 piv, -8 opts for an invalid argument.
+ * -5 ib, -6 Lup (NULL or not 16-byte aligned), -7 piv, -8 opts for an
+ * invalid argument.
  */
 int tilelu_factor(int64_t n, double *A, int64_t lda, int64_t nb, int64_t ib, double *Lup, int32_t *piv,
                   const tileqr_opts *opts, tilelu_info *info);

@@ -4,22 +4,26 @@
 // GESSM / TSTRF / SSSSM tasks run by a persistent kernel with per-task
 // dependency counters and ready queues in HBM (Section 4).
 //
-// One workgroup of four wave64s runs one task, with its tiles in LDS:
-//   GETRF(k)      partial pivoting column by column: the pivot by a
-//                 wave-wide (magnitude, index) reduction, the exchange of
-//                 whole tile rows, the multipliers and the rank-1 update;
-//   GESSM(k, j)   the exchanges of GETRF, then L_kk^{-1} by forward
-//                 substitution, one column of A_kj per thread;
-//   TSTRF(k, i)   [U_kk; A_ik] by inner panels of ib columns: per column the
-//                 pivot among U_kk's diagonal entry and A_ik's column, the
-//                 exchange of U's row with an A row from the column on (the
+// One workgroup of four wave64s runs one task, with its tiles in LDS (about
+// 74 KiB with ib = 16, so two workgroups share a CU):
+//   GETRF(k)      partial pivoting on one wave, lane r holding tile row r in
+//                 registers: the pivot by a wave-wide maximum, the exchange
+//                 of rows as an exchange of row indices, the pivot row
+//                 broadcast through LDS, the multipliers and rank-1 update;
+//   GESSM(k, j)   one wave, lane c holding column c of A_kj: GETRF's
+//                 exchanges composed into one gather, then L_kk^{-1} by
+//                 forward substitution in registers;
+//   TSTRF(k, i)   [U_kk; A_ik] by inner panels of ib columns: the panel's
+//                 columns on one wave (A's panel rows in registers, U in
+//                 LDS): per column the pivot among U_kk's diagonal entry and
+//                 A_ik's column, the exchange of U's row with an A row (the
 //                 A row's multipliers of the panel's earlier columns moving
-//                 to L_up), the multipliers and the update of the panel's
-//                 later columns; after the panel, the columns right of it:
-//                 U's panel rows by L_up, then A_ik by the multipliers;
-//   SSSSM(k, i, j) panel by panel: the exchanges between A_kj and A_ij rows,
-//                 A_kj's panel rows by L_up, then A_ij -= L_ik A_kj[panel]
-//                 on FP64 MFMA.
+//                 to L_up), the multipliers and the update of the panel;
+//                 then the columns right of it: the exchanges, U's panel
+//                 rows by L_up, and A_ik by its multipliers on FP64 MFMA;
+//   SSSSM(k, i, j) every wave owns 16 columns of A_kj and A_ij: per panel
+//                 the exchanges and L_up on A_kj's panel rows (one lane per
+//                 column), then A_ij -= L_ik A_kj[panel] on FP64 MFMA.
 // Every task's arithmetic is fixed by its inputs (pivot choices included:
 // the reductions take the largest magnitude and, among equal ones, the first
 // candidate), so the DAG result is bitwise the one of Algorithm 3's loop
@@ -190,13 +194,13 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// LDS of one task (about 74 KiB with ib = 16: two workgroups fit a CU).
+template <int IB>
 struct Smem {
-    double X[NB][LD];          // GETRF / GESSM: the tile; TSTRF: U_kk; SSSSM: A_kj
-    double Y[NB][LD];          // GESSM: L_kk; TSTRF: A_ik; SSSSM: A_ij
-    double Z[NB][LD];          // SSSSM: the multipliers L_ik
-    double Lup[32][NB];        // TSTRF / SSSSM: L_up of the tile
+    double X[NB][LD];          // GETRF: the tile; GESSM: A_kj; TSTRF: U_kk; SSSSM: A_kj
+    double Y[NB][LD];          // GETRF: the pivot row; GESSM: L_kk; TSTRF: A_ik; SSSSM: A_ij
+    double Lup[IB][NB];        // TSTRF / SSSSM: L_up of the tile
     int32_t piv[NB];
-    int32_t pick;              // the chosen pivot (-1: U's row)
     int32_t fail;
 };
 
@@ -205,30 +209,69 @@ __device__ __forceinline__ double *tile_at(const Sched &S, int i, int j)
     return S.tiles + ((size_t)j * S.p + i) * (size_t)(NB * NB);
 }
 
+// Whole-tile moves between HBM and LDS, 16-byte accesses: element pair e of
+// the tile is row e / 32, columns 2 (e % 32) and the next.
+__device__ __forceinline__ void load_regs(double2 (&v)[8], const double *T)
+{
+    const double2 *T2 = reinterpret_cast<const double2 *>(T);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) v[s] = T2[threadIdx.x + s * NT];
+}
+__device__ __forceinline__ void regs_to_lds(double (*X)[LD], const double2 (&v)[8])
+{
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const int e = threadIdx.x + s * NT;
+        *reinterpret_cast<double2 *>(&X[e >> 5][2 * (e & 31)]) = v[s];
+    }
+}
 __device__ __forceinline__ void load_tile(double (*X)[LD], const double *T)
 {
-    for (int e = threadIdx.x; e < NB * NB; e += NT) X[e / NB][e % NB] = T[e];
+    double2 v[8];
+    load_regs(v, T);
+    regs_to_lds(X, v);
 }
 __device__ __forceinline__ void store_tile(double *T, const double (*X)[LD])
 {
-    for (int e = threadIdx.x; e < NB * NB; e += NT) T[e] = X[e / NB][e % NB];
-}
-
-// Largest |v| and, among equal magnitudes, the smallest index, over the 64
-// lanes of a wave (lanes with v < 0 take no part).  Every lane gets the
-// result.
-__device__ __forceinline__ void wave_argmax(double &v, int &idx)
-{
+    double2 *T2 = reinterpret_cast<double2 *>(T);
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const double ov = __shfl_xor(v, off, 64);
-        const int oi = __shfl_xor(idx, off, 64);
-        if (ov > v || (ov == v && oi < idx)) {
-            v = ov;
-            idx = oi;
-        }
+    for (int s = 0; s < 8; ++s) {
+        const int e = threadIdx.x + s * NT;
+        T2[e] = *reinterpret_cast<const double2 *>(&X[e >> 5][2 * (e & 31)]);
     }
 }
+
+__device__ __forceinline__ double2 ld2(const double *p) { return *reinterpret_cast<const double2 *>(p); }
+
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// v of lane l (l wave-uniform).
+__device__ __forceinline__ double readlane(double v, int l)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+// The largest v over the 64 lanes, in every lane: the maximum over each row
+// of 16 lanes by DPP (xor 1, xor 2, mirror in 8, mirror in 16), then over
+// the four rows.  Exact: a maximum only selects.
+__device__ __forceinline__ double wave_max(double v)
+{
+    v = fmax(v, dpp<0xB1>(v));
+    v = fmax(v, dpp<0x4E>(v));
+    v = fmax(v, dpp<0x141>(v));
+    v = fmax(v, dpp<0x140>(v));
+    return fmax(fmax(readlane(v, 0), readlane(v, 16)), fmax(readlane(v, 32), readlane(v, 48)));
+}
+
+__device__ __forceinline__ bool uniform(bool b) { return __builtin_amdgcn_readfirstlane(b ? 1 : 0) != 0; }
 
 __device__ __forceinline__ void fail_column(const Sched &S, int col)
 {
@@ -236,6 +279,7 @@ __device__ __forceinline__ void fail_column(const Sched &S, int col)
     __hip_atomic_fetch_min(S.minor, col + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Orders one wavefront's LDS accesses (its lanes exchange data through LDS).
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -243,226 +287,502 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// GETRF(k): partial pivoting of the diagonal tile, column by column on wave
-// 0 (the tile has as many rows as the wave has lanes): the pivot by a
-// wave-wide reduction, the exchange with one lane per column, the
-// multipliers and the rank-1 update with one lane per row.  Only wave-level
-// ordering between the phases; the other waves wait at the end.
-__device__ void task_getrf(Smem &sm, const Sched &S, int k)
+// Left-looking forward substitution with a unit lower triangle of PB rows
+// (PB even), in registers: x_r -= sum_{q < r} l_rq x_q, the terms in
+// increasing q.  lrow(r) points at row r of the triangle in LDS (columns
+// 0 .. r-1 are read, two at a time).
+template <int PB, typename LRow>
+__device__ __forceinline__ void unit_lower_solve(double (&x)[PB], LRow lrow)
 {
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    double *T = tile_at(S, k, k);
-    load_tile(sm.X, T);
-    if (tid == 0) sm.fail = 0;
-    __syncthreads();
-    if (w == 0) {
-        for (int j = 0; j < NB; ++j) {
-            double v = lane >= j ? fabs(sm.X[lane][j]) : -1.0;
-            int idx = lane;
-            wave_argmax(v, idx);
-            if (v == 0.0) {
-                if (lane == 0) {
-                    sm.fail = 1;
-                    fail_column(S, k * NB + j);
-                }
-                break;
-            }
-            if (lane == 0) sm.piv[j] = idx;
-            if (idx != j) {
-                const double a = sm.X[j][lane], b = sm.X[idx][lane];
-                sm.X[j][lane] = b;
-                sm.X[idx][lane] = a;
-            }
-            wave_sync();
-            if (lane > j) {
-                const double l = sm.X[lane][j] / sm.X[j][j];
-                sm.X[lane][j] = l;
-                for (int c = j + 1; c < NB; ++c) sm.X[lane][c] = sm.X[lane][c] - l * sm.X[j][c];
-            }
-            wave_sync();
+#pragma unroll
+    for (int r = 1; r < PB; ++r) {
+        const double *L = lrow(r);
+#pragma unroll
+        for (int q = 0; q < r; q += 2) {
+            const double2 l = ld2(&L[q]);
+            x[r] = x[r] - l.x * x[q];
+            if (q + 1 < r) x[r] = x[r] - l.y * x[q + 1];
         }
     }
+}
+
+// The largest |v| over the wave with its lane (lanes whose candidate index
+// `idx` is smallest among equal magnitudes win; v < 0 takes no part).
+// Returns the magnitude; pl gets the lane, best its index.
+__device__ __forceinline__ double wave_pick(double v, int idx, int &pl, int &best)
+{
+    const double m = wave_max(v);
+    uint64_t mask = __ballot(v == m);
+    pl = mask ? (int)__builtin_ctzll(mask) : 0;
+    best = __builtin_amdgcn_readlane(idx, pl);
+    for (mask &= mask - 1; mask; mask &= mask - 1) {
+        const int L = __builtin_ctzll(mask);
+        const int r = __builtin_amdgcn_readlane(idx, L);
+        if (r < best) {
+            best = r;
+            pl = L;
+        }
+    }
+    return m;
+}
+
+// GETRF(k): partial pivoting of the diagonal tile by panels of 16 columns.
+// Per panel, on wave 0, lane r holding the panel part of tile row r in
+// registers: rows are not moved while the panel is factored (each lane
+// carries the index of the row it currently stands for, so an exchange of
+// rows is an exchange of indices); per column j the pivot is the largest
+// magnitude among rows j.. (on ties the smallest current row index, as a
+// sequential search finds it), the pivot row is broadcast through LDS, rows
+// below it take l = a_rj / u_jj and a_rc - l u_jc over the panel (rows on or
+// above it use l = 0, which leaves them exactly as they are).  Then the panel
+// rows go to their rows, the panel's exchanges are applied to the other
+// columns in order (one lane per column), U12 = L11^{-1} A12 (one lane per
+// column), and A22 -= L21 U12 on FP64 MFMA by the four waves.
+template <int IB>
+__device__ __forceinline__ void task_getrf(Smem<IB> &sm, const Sched &S, int k)
+{
+    constexpr int PB = 16;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, n = lane & 15, g = lane >> 4;
+    double *T = tile_at(S, k, k);
+    load_tile(sm.X, T);
     __syncthreads();
+    double *urow = &sm.Y[0][0];
+#pragma unroll 1
+    for (int l0 = 0; l0 < NB; l0 += PB) {
+        const int l1 = l0 + PB;
+        if (w == 0) {
+            double y[PB];
+#pragma unroll
+            for (int t = 0; t < PB; t += 2) {
+                const double2 v = ld2(&sm.X[lane][l0 + t]);
+                y[t] = v.x;
+                y[t + 1] = v.y;
+            }
+            int row = lane;
+            int pj[PB];
+            bool ok = true;     // wave-uniform
+#pragma unroll
+            for (int t = 0; t < PB; ++t) {
+                pj[t] = l0 + t;
+                if (!ok) continue;
+                const int j = l0 + t;
+                int pl, best;
+                const double m = wave_pick(row >= j ? fabs(y[t]) : -1.0, row, pl, best);
+                if (!uniform(m > 0.0)) {
+                    if (lane == 0) {
+                        sm.fail = 1;
+                        fail_column(S, k * NB + j);
+                    }
+                    ok = false;
+                    continue;
+                }
+                pj[t] = best;
+                if (lane == 0) sm.piv[j] = best;
+                if (row == j) row = best;
+                else if (lane == pl) row = j;
+                if (lane == pl)
+#pragma unroll
+                    for (int q = t & ~1; q < PB; q += 2) *reinterpret_cast<double2 *>(&urow[q]) = make_double2(y[q], y[q + 1]);
+                wave_sync();
+                const double u = readlane(y[t], pl);
+                const double l = row > j ? y[t] / u : 0.0;
+                if (row > j) y[t] = l;
+#pragma unroll
+                for (int q = (t + 1) & ~1; q < PB; q += 2) {
+                    const double2 uq = ld2(&urow[q]);
+                    if (q > t) y[q] = y[q] - l * uq.x;
+                    y[q + 1] = y[q + 1] - l * uq.y;
+                }
+                wave_sync();
+            }
+            if (ok) {
+#pragma unroll
+                for (int t = 0; t < PB; t += 2) *reinterpret_cast<double2 *>(&sm.X[row][l0 + t]) = make_double2(y[t], y[t + 1]);
+                wave_sync();
+                if (lane < l0 || lane >= l1) {
+#pragma unroll
+                    for (int t = 0; t < PB; ++t) {
+                        const int pr = pj[t];
+                        if (pr != l0 + t) {
+                            const double a = sm.X[l0 + t][lane], b = sm.X[pr][lane];
+                            sm.X[l0 + t][lane] = b;
+                            sm.X[pr][lane] = a;
+                        }
+                    }
+                }
+                wave_sync();
+                if (lane >= l1) {
+                    double xr[PB];
+#pragma unroll
+                    for (int t = 0; t < PB; ++t) xr[t] = sm.X[l0 + t][lane];
+                    unit_lower_solve<PB>(xr, [&](int r) { return &sm.X[l0 + r][l0]; });
+#pragma unroll
+                    for (int t = 1; t < PB; ++t) sm.X[l0 + t][lane] = xr[t];
+                }
+            }
+        }
+        __syncthreads();
+        if (sm.fail) break;
+        if (l1 < NB) {
+            const int nbk = (NB - l1) / 16, b0 = l1 / 16;
+            for (int blk = w; blk < nbk * nbk; blk += 4) {
+                const int rb = b0 + blk / nbk, cb = b0 + blk % nbk;
+                d4 acc;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r] = sm.X[16 * rb + 4 * r + g][16 * cb + n];
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    acc = mfma(-sm.X[16 * rb + n][l0 + 4 * g + t], sm.X[l0 + 4 * g + t][16 * cb + n], acc);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sm.X[16 * rb + 4 * r + g][16 * cb + n] = acc[r];
+            }
+            __syncthreads();
+        }
+    }
     if (sm.fail) return;
     store_tile(T, sm.X);
     int32_t *pv = S.piv + ((size_t)k * S.p + k) * NB;
     if (tid < NB) pv[tid] = sm.piv[tid];
 }
 
-// GESSM(k, j): A_kj <- L_kk^{-1} P_kk A_kj.
-__device__ void task_gessm(Smem &sm, const Sched &S, int k, int j)
+// GESSM(k, j): A_kj <- L_kk^{-1} P_kk A_kj.  Every column is transformed on
+// its own, so wave w owns columns 16 w .. 16 w + 15: GETRF's exchanges
+// composed into one gather (lane r of every wave learns which row ends in
+// row r), then forward substitution with the unit lower L_kk by blocks of
+// 16 rows: the diagonal block's triangle in registers (one lane per column,
+// left-looking), the rows below it on FP64 MFMA.
+template <int IB>
+__device__ __forceinline__ void task_gessm(Smem<IB> &sm, const Sched &S, int k, int j)
 {
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, n = lane & 15, g = lane >> 4;
     double *T = tile_at(S, k, j);
-    load_tile(sm.X, T);
-    // L_kk only (the strictly lower part; the TSTRF chain may be rewriting
-    // the upper triangle of the same tile meanwhile).
     const double *Tk = tile_at(S, k, k);
-    for (int e = tid; e < NB * NB; e += NT) {
-        const int r = e / NB, c = e % NB;
-        sm.Y[r][c] = r > c ? Tk[e] : 0.0;
-    }
-    const int32_t *pv = S.piv + ((size_t)k * S.p + k) * NB;
-    if (tid < NB) sm.piv[tid] = pv[tid];
-    __syncthreads();
-    if (tid < NB) {
-        const int c = tid;
-        for (int q = 0; q < NB; ++q) {
-            const int pr = sm.piv[q];
-            if (pr != q) {
-                const double t = sm.X[q][c];
-                sm.X[q][c] = sm.X[pr][c];
-                sm.X[pr][c] = t;
-            }
+    const int pvl = S.piv[((size_t)k * S.p + k) * NB + lane];
+    {
+        double2 a[8], b[8];
+        load_regs(a, T);
+        load_regs(b, Tk);
+        regs_to_lds(sm.X, a);
+        // L_kk only (the strictly lower part; the TSTRF chain may be
+        // rewriting the upper triangle of the same tile meanwhile).
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int e = tid + s * NT, r = e >> 5, c = 2 * (e & 31);
+            b[s].x = r > c ? b[s].x : 0.0;
+            b[s].y = r > c + 1 ? b[s].y : 0.0;
         }
-        for (int r = 1; r < NB; ++r) {
-            double s = sm.X[r][c];
-            for (int q = 0; q < r; ++q) s -= sm.Y[r][q] * sm.X[q][c];
-            sm.X[r][c] = s;
+        regs_to_lds(sm.Y, b);
+    }
+    int src = lane;
+    for (int q = 0; q < NB; ++q) {
+        const int pr = __builtin_amdgcn_readlane(pvl, q);
+        if (pr != q) {
+            const int a = __builtin_amdgcn_readlane(src, q), b = __builtin_amdgcn_readlane(src, pr & (NB - 1));
+            if (lane == q) src = b;
+            if (lane == pr) src = a;
         }
     }
     __syncthreads();
-    store_tile(T, sm.X);
+    const int col = 16 * w + n;
+    {
+        double v[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) v[m] = sm.X[__shfl(src, g + 4 * m, 64) & (NB - 1)][col];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) sm.X[g + 4 * m][col] = v[m];
+    }
+    wave_sync();
+#pragma unroll 1
+    for (int r0 = 0; r0 < NB; r0 += 16) {
+        if (g == 0) {
+            double xr[16];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) xr[t] = sm.X[r0 + t][col];
+            unit_lower_solve<16>(xr, [&](int r) { return &sm.Y[r0 + r][r0]; });
+#pragma unroll
+            for (int t = 1; t < 16; ++t) sm.X[r0 + t][col] = xr[t];
+        }
+        wave_sync();
+        double xb[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) xb[t] = sm.X[r0 + 4 * g + t][col];
+        for (int rb = r0 / 16 + 1; rb < 4; ++rb) {
+            d4 acc;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[r] = sm.X[16 * rb + 4 * r + g][col];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) acc = mfma(-sm.Y[16 * rb + n][r0 + 4 * g + t], xb[t], acc);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sm.X[16 * rb + 4 * r + g][col] = acc[r];
+        }
+        wave_sync();
+    }
+    // This wave's 16 columns: lane -> row lane / 8 + 8 s, columns
+    // 16 w + 2 (lane % 8) and the next.
+    const int rr = lane >> 3, cc = 16 * w + 2 * (lane & 7);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const int r = rr + 8 * s;
+        *reinterpret_cast<double2 *>(&T[r * NB + cc]) = ld2(&sm.X[r][cc]);
+    }
 }
 
-// TSTRF(k, i): [U_kk; A_ik] by inner panels of ib columns.
-__device__ void task_tstrf(Smem &sm, const Sched &S, int k, int i)
+// TSTRF(k, i): [U_kk; A_ik] by inner panels of IB columns.  The panel's
+// columns on wave 0, lane r holding row r of A_ik's panel in registers and
+// U_kk in LDS: per column j, the largest |a_rj| against |u_jj| (U's row on
+// ties, then the first A row); a pivot in A row r exchanges the panel part
+// of U's row j and A's row r from column j on and moves A row r's
+// multipliers of the panel's earlier columns to L_up (U's row holds zeros
+// there); then every A row's multiplier a_rj / u_jj and the update of the
+// panel's later columns.  After the panel, the columns right of it: the
+// panel's exchanges (one lane per column; they only move data, so deferring
+// them past the panel's own columns changes nothing), U's panel rows by the
+// unit lower L_up, then A -= A[:, panel] U[panel, :] on FP64 MFMA by all
+// four waves.
+template <int IB>
+__device__ __forceinline__ void task_tstrf(Smem<IB> &sm, const Sched &S, int k, int i)
 {
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int ib = S.ib;
+    constexpr int KP = IB / 4;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, n = lane & 15, g = lane >> 4;
     double *U = tile_at(S, k, k), *A = tile_at(S, i, k);
-    // U_kk's upper triangle (the strictly lower part, L_kk, stays in memory
-    // untouched); A_ik whole.
-    for (int e = tid; e < NB * NB; e += NT) {
-        const int r = e / NB, c = e % NB;
-        sm.X[r][c] = r <= c ? U[e] : 0.0;
-        sm.Y[r][c] = A[e];
+    {
+        double2 a[8], b[8];
+        load_regs(a, U);
+        load_regs(b, A);
+        // U_kk's upper triangle (the strictly lower part, L_kk, stays in
+        // memory untouched); A_ik whole.
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int e = tid + s * NT, r = e >> 5, c = 2 * (e & 31);
+            a[s].x = r <= c ? a[s].x : 0.0;
+            a[s].y = r <= c + 1 ? a[s].y : 0.0;
+        }
+        regs_to_lds(sm.X, a);
+        regs_to_lds(sm.Y, b);
+        for (int e = tid; e < IB * NB; e += NT) sm.Lup[e / NB][e % NB] = 0.0;
     }
-    for (int e = tid; e < 32 * NB; e += NT) sm.Lup[e / NB][e % NB] = 0.0;
-    if (tid == 0) sm.fail = 0;
     __syncthreads();
-    for (int l0 = 0; l0 < NB; l0 += ib) {
-        const int l1 = l0 + ib;
-        // The panel's columns on wave 0: lane r owns row r of A_ik for the
-        // multipliers and the updates, lane c column c for the exchange.
+#pragma unroll 1
+    for (int l0 = 0; l0 < NB; l0 += IB) {
+        const int l1 = l0 + IB;
         if (w == 0) {
-            for (int j = l0; j < l1; ++j) {
-                double v = fabs(sm.Y[lane][j]);
-                int idx = lane;
-                wave_argmax(v, idx);
-                const double u = fabs(sm.X[j][j]);
-                const int pick = v > u ? idx : -1;
-                if (pick < 0 && u == 0.0) {
+            double y[IB];
+#pragma unroll
+            for (int t = 0; t < IB; t += 2) {
+                const double2 v = ld2(&sm.Y[lane][l0 + t]);
+                y[t] = v.x;
+                y[t + 1] = v.y;
+            }
+            int pj[IB];
+            bool ok = true;     // wave-uniform
+#pragma unroll
+            for (int t = 0; t < IB; ++t) {
+                pj[t] = l0 + t;
+                if (!ok) continue;
+                const int j = l0 + t;
+                int pl, best;
+                const double m = wave_pick(fabs(y[t]), lane, pl, best);
+                const double d = fabs(sm.X[j][j]);
+                const bool pick = uniform(m > d);
+                if (!pick && !uniform(d > 0.0)) {
                     if (lane == 0) {
                         sm.fail = 1;
                         fail_column(S, k * NB + j);
                     }
-                    break;
+                    ok = false;
+                    continue;
                 }
-                if (lane == 0) sm.piv[j] = pick >= 0 ? NB + pick : j;
-                if (pick >= 0) {
-                    const int c = lane;
-                    if (c >= j) {
-                        const double t = sm.X[j][c];
-                        sm.X[j][c] = sm.Y[pick][c];
-                        sm.Y[pick][c] = t;
-                    } else if (c >= l0) {
-                        sm.Lup[j - l0][c] = sm.Y[pick][c];
-                        sm.Y[pick][c] = 0.0;
+                if (!pick) pl = -1;
+                pj[t] = pick ? NB + pl : j;
+                if (lane == 0) sm.piv[j] = pj[t];
+                if (lane == pl) {
+#pragma unroll
+                    for (int q = t; q < IB; ++q) {
+                        const double u = sm.X[j][l0 + q];
+                        sm.X[j][l0 + q] = y[q];
+                        y[q] = u;
+                    }
+#pragma unroll
+                    for (int q = 0; q < t; ++q) {
+                        sm.Lup[t][l0 + q] = y[q];
+                        y[q] = 0.0;
                     }
                 }
                 wave_sync();
-                const double l = sm.Y[lane][j] / sm.X[j][j];
-                sm.Y[lane][j] = l;
-                for (int c = j + 1; c < l1; ++c) sm.Y[lane][c] = sm.Y[lane][c] - l * sm.X[j][c];
-                wave_sync();
+                const double l = y[t] / sm.X[j][j];
+                y[t] = l;
+#pragma unroll
+                for (int q = t + 1; q < IB; ++q) y[q] = y[q] - l * sm.X[j][l0 + q];
+            }
+#pragma unroll
+            for (int t = 0; t < IB; t += 2) *reinterpret_cast<double2 *>(&sm.Y[lane][l0 + t]) = make_double2(y[t], y[t + 1]);
+            wave_sync();
+            // Columns right of the panel, one lane each: the panel's
+            // exchanges in order, then U's panel rows by L_up.
+            if (ok && lane >= l1) {
+                const int c = lane;
+#pragma unroll
+                for (int t = 0; t < IB; ++t) {
+                    const int pq = pj[t];
+                    if (pq >= NB) {
+                        const double u = sm.X[l0 + t][c];
+                        sm.X[l0 + t][c] = sm.Y[pq - NB][c];
+                        sm.Y[pq - NB][c] = u;
+                    }
+                }
+                double xr[IB];
+#pragma unroll
+                for (int t = 0; t < IB; ++t) xr[t] = sm.X[l0 + t][c];
+                unit_lower_solve<IB>(xr, [&](int r) { return &sm.Lup[r][l0]; });
+#pragma unroll
+                for (int t = 1; t < IB; ++t) sm.X[l0 + t][c] = xr[t];
             }
         }
         __syncthreads();
-        if (sm.fail) return;
-        // Columns right of the panel: U's panel rows by L_up (one column per
-        // thread), then A_ik by its multipliers.
-        if (tid >= l1 && tid < NB) {
-            const int c = tid;
-            for (int r = l0; r < l1; ++r) {
-                double s = sm.X[r][c];
-                for (int q = l0; q < r; ++q) s -= sm.Lup[r - l0][q] * sm.X[q][c];
-                sm.X[r][c] = s;
+        if (sm.fail) break;
+        if (l1 < NB) {
+            // A[:, l1:] -= A[:, panel] U[panel, l1:], 16 x 16 blocks over the
+            // waves; k-slot g of step t is panel column KP g + t.
+            const int nblk = 4 * ((NB - l1) / 16);
+            for (int blk = w; blk < nblk; blk += 4) {
+                const int rb = blk & 3, cb = l1 / 16 + (blk >> 2);
+                d4 acc;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[r] = sm.Y[16 * rb + 4 * r + g][16 * cb + n];
+#pragma unroll
+                for (int t = 0; t < KP; ++t)
+                    acc = mfma(-sm.Y[16 * rb + n][l0 + KP * g + t], sm.X[l0 + KP * g + t][16 * cb + n], acc);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sm.Y[16 * rb + 4 * r + g][16 * cb + n] = acc[r];
             }
+            __syncthreads();
         }
-        __syncthreads();
-        const int mc = NB - l1;
-        for (int e = tid; e < NB * mc; e += NT) {
-            const int r = e / mc, c = l1 + e % mc;
-            double s = sm.Y[r][c];
-            for (int q = l0; q < l1; ++q) s -= sm.Y[r][q] * sm.X[q][c];
-            sm.Y[r][c] = s;
-        }
-        __syncthreads();
     }
+    if (sm.fail) return;
     for (int e = tid; e < NB * NB; e += NT) {
         const int r = e / NB, c = e % NB;
         if (r <= c) U[e] = sm.X[r][c];
-        A[e] = sm.Y[r][c];
     }
-    double *lup = S.lup + ((size_t)k * S.p + i) * (size_t)ib * NB;
-    for (int e = tid; e < ib * NB; e += NT) lup[e] = sm.Lup[e / NB][e % NB];
+    store_tile(A, sm.Y);
+    double *lup = S.lup + ((size_t)k * S.p + i) * (size_t)IB * NB;
+    for (int e = tid; e < IB * NB; e += NT) lup[e] = sm.Lup[e / NB][e % NB];
     int32_t *pv = S.piv + ((size_t)k * S.p + i) * NB;
     if (tid < NB) pv[tid] = sm.piv[tid];
 }
 
-// SSSSM(k, i, j): [A_kj; A_ij] <- L_ik^{-1} P_ik [A_kj; A_ij], by panels.
-__device__ void task_ssssm(Smem &sm, const Sched &S, int k, int i, int j)
+// SSSSM(k, i, j): [A_kj; A_ij] <- L_ik^{-1} P_ik [A_kj; A_ij], panel by
+// panel.  Every column is transformed on its own, so wave w owns columns
+// 16 w .. 16 w + 15 of both tiles from the load to the store, with no
+// workgroup barrier after the load: per panel, lanes 0..15 exchange the
+// panel's rows of A_kj with the chosen rows of A_ij (the pivots are read
+// once, one per lane) and apply L_up to them (one lane per column, in
+// registers); then A_ij -= L_ik[:, panel] A_kj[panel, :] on FP64 MFMA, the
+// multipliers read from HBM straight into the operand registers, one panel
+// ahead.  The MFMA's k-slot g of step t is panel column KP g + t, so a
+// lane's operand entries are contiguous.
+template <int IB>
+__device__ __forceinline__ void task_ssssm(Smem<IB> &sm, const Sched &S, int k, int i, int j)
 {
+    constexpr int KP = IB / 4;
+    constexpr int LU2 = IB * NB / 2 / NT;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, n = lane & 15, g = lane >> 4;
-    const int ib = S.ib;
     double *X1 = tile_at(S, k, j), *X2 = tile_at(S, i, j);
-    load_tile(sm.X, X1);
-    load_tile(sm.Y, X2);
-    load_tile(sm.Z, tile_at(S, i, k));
-    const double *lup = S.lup + ((size_t)k * S.p + i) * (size_t)ib * NB;
-    for (int e = tid; e < ib * NB; e += NT) sm.Lup[e / NB][e % NB] = lup[e];
-    const int32_t *pv = S.piv + ((size_t)k * S.p + i) * NB;
-    if (tid < NB) sm.piv[tid] = pv[tid];
+    const double *Z = tile_at(S, i, k);
+    const int pvl = S.piv[((size_t)k * S.p + i) * NB + lane];
+    {
+        double2 a[8], b[8], c[LU2];
+        load_regs(a, X1);
+        load_regs(b, X2);
+        const double2 *lup = reinterpret_cast<const double2 *>(S.lup + ((size_t)k * S.p + i) * (size_t)IB * NB);
+#pragma unroll
+        for (int s = 0; s < LU2; ++s) c[s] = lup[tid + s * NT];
+        regs_to_lds(sm.X, a);
+        regs_to_lds(sm.Y, b);
+#pragma unroll
+        for (int s = 0; s < LU2; ++s) {
+            const int e = tid + s * NT;
+            *reinterpret_cast<double2 *>(&sm.Lup[e / (NB / 2)][2 * (e % (NB / 2))]) = c[s];
+        }
+    }
+    double za[4][KP];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int t = 0; t < KP; t += 2) {
+            const double2 v = ld2(&Z[(16 * rb + n) * NB + KP * g + t]);
+            za[rb][t] = v.x;
+            za[rb][t + 1] = v.y;
+        }
     __syncthreads();
-    for (int l0 = 0; l0 < NB; l0 += ib) {
-        const int l1 = l0 + ib;
-        if (tid < NB) {
-            const int c = tid;
-            for (int q = l0; q < l1; ++q) {
-                const int pq = sm.piv[q];
+    const int col = 16 * w + n;
+#pragma unroll 1
+    for (int l0 = 0; l0 < NB; l0 += IB) {
+        const bool more = l0 + IB < NB;
+        double zb[4][KP];
+        if (more)
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int t = 0; t < KP; t += 2) {
+                    const double2 v = ld2(&Z[(16 * rb + n) * NB + l0 + IB + KP * g + t]);
+                    zb[rb][t] = v.x;
+                    zb[rb][t + 1] = v.y;
+                }
+        if (g == 0) {
+            double xr[IB];
+#pragma unroll
+            for (int t = 0; t < IB; ++t) xr[t] = sm.X[l0 + t][col];
+#pragma unroll
+            for (int t = 0; t < IB; ++t) {
+                const int pq = __builtin_amdgcn_readlane(pvl, l0 + t);
                 if (pq >= NB) {
-                    const double t = sm.X[q][c];
-                    sm.X[q][c] = sm.Y[pq - NB][c];
-                    sm.Y[pq - NB][c] = t;
+                    const int r = (pq - NB) & (NB - 1);
+                    const double tmp = sm.Y[r][col];
+                    sm.Y[r][col] = xr[t];
+                    xr[t] = tmp;
                 }
             }
-            for (int r = l0; r < l1; ++r) {
-                double s = sm.X[r][c];
-                for (int q = l0; q < r; ++q) s -= sm.Lup[r - l0][q] * sm.X[q][c];
-                sm.X[r][c] = s;
-            }
-        }
-        __syncthreads();
-        // A_ij -= L_ik[:, panel] A_kj[panel, :]: 16 blocks of 16 x 16, four
-        // per wave, K = ib in steps of 4.
-        for (int blk = w; blk < 16; blk += 4) {
-            const int rb = blk >> 2, cb = blk & 3;
-            d4 acc;
+            unit_lower_solve<IB>(xr, [&](int r) { return &sm.Lup[r][l0]; });
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc[r] = sm.Y[16 * rb + 4 * r + g][16 * cb + n];
-            for (int ks = l0 / 4; ks < l1 / 4; ++ks)
-                acc = mfma(-sm.Z[16 * rb + n][4 * ks + g], sm.X[4 * ks + g][16 * cb + n], acc);
-#pragma unroll
-            for (int r = 0; r < 4; ++r) sm.Y[16 * rb + 4 * r + g][16 * cb + n] = acc[r];
+            for (int t = 0; t < IB; ++t) sm.X[l0 + t][col] = xr[t];
         }
-        __syncthreads();
+        wave_sync();
+        d4 acc[4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[rb][r] = sm.Y[16 * rb + 4 * r + g][col];
+        double xb[KP];
+#pragma unroll
+        for (int t = 0; t < KP; ++t) xb[t] = sm.X[l0 + KP * g + t][col];
+#pragma unroll
+        for (int t = 0; t < KP; ++t)
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) acc[rb] = mfma(-za[rb][t], xb[t], acc[rb]);
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sm.Y[16 * rb + 4 * r + g][col] = acc[rb][r];
+        wave_sync();
+        if (more)
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int t = 0; t < KP; ++t) za[rb][t] = zb[rb][t];
     }
-    store_tile(X1, sm.X);
-    store_tile(X2, sm.Y);
+    // This wave's 16 columns of both tiles: lane -> row lane / 8 + 8 s,
+    // columns 16 w + 2 (lane % 8) and the next.
+    const int rr = lane >> 3, cc = 16 * w + 2 * (lane & 7);
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const int r = rr + 8 * s;
+        *reinterpret_cast<double2 *>(&X1[r * NB + cc]) = ld2(&sm.X[r][cc]);
+        *reinterpret_cast<double2 *>(&X2[r * NB + cc]) = ld2(&sm.Y[r][cc]);
+    }
 }
 
-__device__ __forceinline__ void run_task(Smem &sm, const Sched &S, const LTask &t)
+template <int IB>
+__device__ __forceinline__ void run_task(Smem<IB> &sm, const Sched &S, const LTask &t)
 {
     if (t.type == T_GETRF) task_getrf(sm, S, t.k);
     else if (t.type == T_GESSM) task_gessm(sm, S, t.k, t.j);
@@ -558,9 +878,10 @@ __global__ void k_lu_seed(Sched S)
     }
 }
 
-__global__ __launch_bounds__(NT) void k_lu_worker(Sched S)
+template <int IB>
+__global__ __launch_bounds__(NT, IB == 16 ? 2 : 1) void k_lu_worker(Sched S)
 {
-    __shared__ Smem sm;
+    __shared__ Smem<IB> sm;
     __shared__ int64_t s_id, s_next;
     __shared__ int s_exit;
     const int tid = threadIdx.x;
@@ -669,10 +990,10 @@ __global__ __launch_bounds__(NT) void k_lu_worker(Sched S)
 
 // Algorithm 3 in loop order: GETRF(k), the GESSMs of step k (independent),
 // then for each i in turn TSTRF(k, i) and the SSSSMs of row i (independent).
-template <int TYPE>
-__global__ __launch_bounds__(NT) void k_lu_step(Sched S, int k, int i)
+template <int TYPE, int IB>
+__global__ __launch_bounds__(NT, IB == 16 ? 2 : 1) void k_lu_step(Sched S, int k, int i)
 {
-    __shared__ Smem sm;
+    __shared__ Smem<IB> sm;
     if (*S.status != 0) return;
     if (threadIdx.x == 0) sm.fail = 0;
     __syncthreads();
@@ -743,22 +1064,33 @@ __global__ void k_lu_status_init(int32_t *status, int32_t *minor)
     }
 }
 
+template <int IB>
 hipError_t launch_run(const Sched &S, bool serial, int workers, hipStream_t st)
 {
     if (serial) {
         for (int k = 0; k < S.p; ++k) {
             const int nt = S.p - k - 1;
-            hipLaunchKernelGGL((k_lu_step<T_GETRF>), dim3(1), dim3(NT), 0, st, S, k, k);
-            if (nt > 0) hipLaunchKernelGGL((k_lu_step<T_GESSM>), dim3(nt), dim3(NT), 0, st, S, k, k);
+            hipLaunchKernelGGL((k_lu_step<T_GETRF, IB>), dim3(1), dim3(NT), 0, st, S, k, k);
+            if (nt > 0) hipLaunchKernelGGL((k_lu_step<T_GESSM, IB>), dim3(nt), dim3(NT), 0, st, S, k, k);
             for (int i = k + 1; i < S.p; ++i) {
-                hipLaunchKernelGGL((k_lu_step<T_TSTRF>), dim3(1), dim3(NT), 0, st, S, k, i);
-                hipLaunchKernelGGL((k_lu_step<T_SSSSM>), dim3(nt), dim3(NT), 0, st, S, k, i);
+                hipLaunchKernelGGL((k_lu_step<T_TSTRF, IB>), dim3(1), dim3(NT), 0, st, S, k, i);
+                hipLaunchKernelGGL((k_lu_step<T_SSSSM, IB>), dim3(nt), dim3(NT), 0, st, S, k, i);
             }
         }
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(k_lu_worker, dim3(workers), dim3(NT), 0, st, S);
+    hipLaunchKernelGGL((k_lu_worker<IB>), dim3(workers), dim3(NT), 0, st, S);
     return hipGetLastError();
+}
+
+// Workgroups of the persistent kernel that fit the device at once.
+template <int IB>
+int resident_workers(int num_cu)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_lu_worker<IB>, NT, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    return std::max(1, num_cu) * per_cu;
 }
 
 }  // namespace tl
@@ -894,7 +1226,7 @@ extern "C" int tilelu_factor(int64_t n, double *A, int64_t lda, int64_t nb, int6
     if (lda < std::max<int64_t>(1, n)) return -3;
     if (nb <= 0) return -4;
     if (ib <= 0 || nb % ib != 0) return -5;
-    if (n > 0 && !Lup) return -6;
+    if (n > 0 && (!Lup || ((uintptr_t)Lup & 15))) return -6;
     if (n > 0 && !piv) return -7;
     tileqr_opts o;
     tileqr_opts_default(&o);
@@ -958,7 +1290,7 @@ extern "C" int tilelu_factor(int64_t n, double *A, int64_t lda, int64_t nb, int6
     S.shuffle = (o.flags & TILEQR_FLAG_SHUFFLE) ? 1 : 0;
     S.seed = o.seed;
     int workers = (int)o.workers;
-    if (workers <= 0) workers = std::max(1, W->num_cu);
+    if (workers <= 0) workers = ib == 16 ? tl::resident_workers<16>(W->num_cu) : tl::resident_workers<32>(W->num_cu);
 
     hipLaunchKernelGGL(tl::k_lu_status_init, dim3(1), dim3(64), 0, st, S.status, S.minor);
     if (timing) TQ_HIP(hipEventRecord(W->ev[0], st));
@@ -973,7 +1305,7 @@ extern "C" int tilelu_factor(int64_t n, double *A, int64_t lda, int64_t nb, int6
     }
     TQ_HIP(hipGetLastError());
     if (timing) TQ_HIP(hipEventRecord(W->ev[1], st));
-    hipError_t e = tl::launch_run(S, serial, workers, st);
+    hipError_t e = ib == 16 ? tl::launch_run<16>(S, serial, workers, st) : tl::launch_run<32>(S, serial, workers, st);
     if (e != hipSuccess) return hip_fail(e, "tilelu worker");
     if (timing) TQ_HIP(hipEventRecord(W->ev[2], st));
     hipLaunchKernelGGL(tl::k_lu_out, dim3((unsigned)((int64_t)p * p)), dim3(256), 0, st, A, lda, n, S.tiles, p,

@@ -126,6 +126,8 @@ def test_nonfinite_and_arguments(tq, tl):
     assert tl.factor(4, 0, 4, 64, 16, d.data_ptr(), pv.data_ptr()) == -2
     assert tl.factor(4, d.data_ptr(), 3, 64, 16, d.data_ptr(), pv.data_ptr()) == -3
     assert tl.factor(4, d.data_ptr(), 4, 64, 24, d.data_ptr(), pv.data_ptr()) == -5
+    assert tl.factor(4, d.data_ptr(), 4, 64, 16, 0, pv.data_ptr()) == -6
+    assert tl.factor(4, d.data_ptr(), 4, 64, 16, d.data_ptr() + 8, pv.data_ptr()) == -6   # not 16-byte aligned
     assert tl.factor(4, d.data_ptr(), 4, 128, 16, d.data_ptr(), pv.data_ptr()) == tq.EUNSUPPORTED
     assert tl.factor(4, d.data_ptr(), 4, 64, 8, d.data_ptr(), pv.data_ptr()) == tq.EUNSUPPORTED
     assert tl.lup_size(100, 64, 16) == 2 * 2 * 16 * 64 and tl.piv_size(100, 64) == 2 * 2 * 64
