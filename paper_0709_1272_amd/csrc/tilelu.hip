@@ -54,6 +54,7 @@ enum { ST_NONFINITE = 1, ST_TIMEOUT = 2, ST_SINGULAR = 4 };
 struct Sched {
     double *tiles;
     double *lup;               // p * p * ib * NB
+    double *linv;              // p * p * ib * NB: per tile (i, k), the inverse of each panel's L_up triangle
     int32_t *piv;              // p * p * NB
     int32_t p, ib;
     int32_t *counters;
@@ -209,19 +210,65 @@ __device__ __forceinline__ double *tile_at(const Sched &S, int i, int j)
     return S.tiles + ((size_t)j * S.p + i) * (size_t)(NB * NB);
 }
 
+// Accesses to the data the tasks hand to each other (tiles, L_up, pivots):
+// relaxed atomics at agent scope, i.e. loads and stores coherent across the
+// XCDs' L2 caches on their own.  A task's results are published by waiting
+// for its stores to complete before the dependency counters are touched, and
+// its inputs are read with such loads after the task was taken, so no
+// task needs a whole-cache write-back or invalidate (which an agent-scope
+// release or acquire fence performs).
+__device__ __forceinline__ double gld(const double *p)
+{
+    return __longlong_as_double((long long)__hip_atomic_load(reinterpret_cast<const unsigned long long *>(p),
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ double2 gld2(const double *p) { return make_double2(gld(p), gld(p + 1)); }
+__device__ __forceinline__ int gldi(const int32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gst(double *p, double v)
+{
+    __hip_atomic_store(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gst2(double *p, double2 v)
+{
+    gst(p, v.x);
+    gst(p + 1, v.y);
+}
+__device__ __forceinline__ void gsti(int32_t *p, int32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Waits until this wave's stores have completed (are visible at agent
+// scope); also a compiler barrier for memory accesses.
+__device__ __forceinline__ void stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// The thread's index, opaque to the optimiser: addresses derived from it are
+// formed inside each task instead of being hoisted out of the persistent
+// loop, where the four task bodies would keep all of them live at once.
+__device__ __forceinline__ int opaque_tid()
+{
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 // Whole-tile moves between HBM and LDS, 16-byte accesses: element pair e of
 // the tile is row e / 32, columns 2 (e % 32) and the next.
 __device__ __forceinline__ void load_regs(double2 (&v)[8], const double *T)
 {
-    const double2 *T2 = reinterpret_cast<const double2 *>(T);
+    const int tid = opaque_tid();
 #pragma unroll
-    for (int s = 0; s < 8; ++s) v[s] = T2[threadIdx.x + s * NT];
+    for (int s = 0; s < 8; ++s) v[s] = gld2(&T[2 * (tid + s * NT)]);
 }
 __device__ __forceinline__ void regs_to_lds(double (*X)[LD], const double2 (&v)[8])
 {
+    const int tid = opaque_tid();
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
-        const int e = threadIdx.x + s * NT;
+        const int e = tid + s * NT;
         *reinterpret_cast<double2 *>(&X[e >> 5][2 * (e & 31)]) = v[s];
     }
 }
@@ -233,11 +280,11 @@ __device__ __forceinline__ void load_tile(double (*X)[LD], const double *T)
 }
 __device__ __forceinline__ void store_tile(double *T, const double (*X)[LD])
 {
-    double2 *T2 = reinterpret_cast<double2 *>(T);
+    const int tid = opaque_tid();
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
-        const int e = threadIdx.x + s * NT;
-        T2[e] = *reinterpret_cast<const double2 *>(&X[e >> 5][2 * (e & 31)]);
+        const int e = tid + s * NT;
+        gst2(&T[2 * e], *reinterpret_cast<const double2 *>(&X[e >> 5][2 * (e & 31)]));
     }
 }
 
@@ -342,7 +389,7 @@ template <int IB>
 __device__ __forceinline__ void task_getrf(Smem<IB> &sm, const Sched &S, int k)
 {
     constexpr int PB = 16;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, n = lane & 15, g = lane >> 4;
+    const int tid = opaque_tid(), lane = tid & 63, w = tid >> 6, n = lane & 15, g = lane >> 4;
     double *T = tile_at(S, k, k);
     load_tile(sm.X, T);
     __syncthreads();
@@ -442,7 +489,7 @@ __device__ __forceinline__ void task_getrf(Smem<IB> &sm, const Sched &S, int k)
     if (sm.fail) return;
     store_tile(T, sm.X);
     int32_t *pv = S.piv + ((size_t)k * S.p + k) * NB;
-    if (tid < NB) pv[tid] = sm.piv[tid];
+    if (tid < NB) gsti(&pv[tid], sm.piv[tid]);
 }
 
 // GESSM(k, j): A_kj <- L_kk^{-1} P_kk A_kj.  Every column is transformed on
@@ -454,10 +501,10 @@ __device__ __forceinline__ void task_getrf(Smem<IB> &sm, const Sched &S, int k)
 template <int IB>
 __device__ __forceinline__ void task_gessm(Smem<IB> &sm, const Sched &S, int k, int j)
 {
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, n = lane & 15, g = lane >> 4;
+    const int tid = opaque_tid(), lane = tid & 63, w = tid >> 6, n = lane & 15, g = lane >> 4;
     double *T = tile_at(S, k, j);
     const double *Tk = tile_at(S, k, k);
-    const int pvl = S.piv[((size_t)k * S.p + k) * NB + lane];
+    const int pvl = gldi(&S.piv[((size_t)k * S.p + k) * NB + lane]);
     {
         double2 a[8], b[8];
         load_regs(a, T);
@@ -523,7 +570,7 @@ __device__ __forceinline__ void task_gessm(Smem<IB> &sm, const Sched &S, int k, 
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
         const int r = rr + 8 * s;
-        *reinterpret_cast<double2 *>(&T[r * NB + cc]) = ld2(&sm.X[r][cc]);
+        gst2(&T[r * NB + cc], ld2(&sm.X[r][cc]));
     }
 }
 
@@ -543,7 +590,7 @@ template <int IB>
 __device__ __forceinline__ void task_tstrf(Smem<IB> &sm, const Sched &S, int k, int i)
 {
     constexpr int KP = IB / 4;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, n = lane & 15, g = lane >> 4;
+    const int tid = opaque_tid(), lane = tid & 63, w = tid >> 6, n = lane & 15, g = lane >> 4;
     double *U = tile_at(S, k, k), *A = tile_at(S, i, k);
     {
         double2 a[8], b[8];
@@ -640,6 +687,17 @@ __device__ __forceinline__ void task_tstrf(Smem<IB> &sm, const Sched &S, int k, 
         }
         __syncthreads();
         if (sm.fail) break;
+        if (w == 1 && lane < IB) {
+            // Column `lane` of the inverse of the panel's unit lower L_up
+            // (for SSSSM, which applies it as a product on MFMA).
+            double x[IB];
+#pragma unroll
+            for (int r = 0; r < IB; ++r) x[r] = r == lane ? 1.0 : 0.0;
+            unit_lower_solve<IB>(x, [&](int r) { return &sm.Lup[r][l0]; });
+            double *li = S.linv + ((size_t)k * S.p + i) * (size_t)IB * NB + (size_t)l0 * IB;
+#pragma unroll
+            for (int r = 0; r < IB; ++r) gst(&li[r * IB + lane], x[r]);
+        }
         if (l1 < NB) {
             // A[:, l1:] -= A[:, panel] U[panel, l1:], 16 x 16 blocks over the
             // waves; k-slot g of step t is panel column KP g + t.
@@ -661,124 +719,148 @@ __device__ __forceinline__ void task_tstrf(Smem<IB> &sm, const Sched &S, int k, 
     if (sm.fail) return;
     for (int e = tid; e < NB * NB; e += NT) {
         const int r = e / NB, c = e % NB;
-        if (r <= c) U[e] = sm.X[r][c];
+        if (r <= c) gst(&U[e], sm.X[r][c]);
     }
     store_tile(A, sm.Y);
     double *lup = S.lup + ((size_t)k * S.p + i) * (size_t)IB * NB;
-    for (int e = tid; e < IB * NB; e += NT) lup[e] = sm.Lup[e / NB][e % NB];
+    for (int e = tid; e < IB * NB; e += NT) gst(&lup[e], sm.Lup[e / NB][e % NB]);
     int32_t *pv = S.piv + ((size_t)k * S.p + i) * NB;
-    if (tid < NB) pv[tid] = sm.piv[tid];
+    if (tid < NB) gsti(&pv[tid], sm.piv[tid]);
 }
 
 // SSSSM(k, i, j): [A_kj; A_ij] <- L_ik^{-1} P_ik [A_kj; A_ij], panel by
-// panel.  Every column is transformed on its own, so wave w owns columns
-// 16 w .. 16 w + 15 of both tiles from the load to the store, with no
-// workgroup barrier after the load: per panel, lanes 0..15 exchange the
-// panel's rows of A_kj with the chosen rows of A_ij (the pivots are read
-// once, one per lane) and apply L_up to them (one lane per column, in
-// registers); then A_ij -= L_ik[:, panel] A_kj[panel, :] on FP64 MFMA, the
-// multipliers read from HBM straight into the operand registers, one panel
-// ahead.  The MFMA's k-slot g of step t is panel column KP g + t, so a
-// lane's operand entries are contiguous.
+// panel, in two phases with a workgroup barrier after each:
+//   by columns (wave w owns columns 16 w .. 16 w + 15): lanes 0..15 exchange
+//     the panel's rows of A_kj with the chosen rows of A_ij (the pivots read
+//     once, one per lane; all reads then all writes when the panel's rows of
+//     A_ij are distinct, else one exchange after the other); then
+//     A_kj[panel] <- L_up^{-1} A_kj[panel] on FP64 MFMA (the inverse TSTRF
+//     formed);
+//   by rows (wave w owns rows 16 w .. 16 w + 15 of A_ij):
+//     A_ij -= L_ik[:, panel] A_kj[panel] on FP64 MFMA, each wave reading
+//     only its 16 rows of L_ik from HBM, into registers, one panel ahead.
 template <int IB>
 __device__ __forceinline__ void task_ssssm(Smem<IB> &sm, const Sched &S, int k, int i, int j)
 {
-    constexpr int KP = IB / 4;
-    constexpr int LU2 = IB * NB / 2 / NT;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, n = lane & 15, g = lane >> 4;
+    constexpr int NH = IB / 16;        // 16-row blocks of a panel
+    constexpr int KS = IB / 4;         // MFMA steps over a panel
+    const int tid = opaque_tid(), lane = tid & 63, w = tid >> 6, n = lane & 15, g = lane >> 4;
     double *X1 = tile_at(S, k, j), *X2 = tile_at(S, i, j);
     const double *Z = tile_at(S, i, k);
-    const int pvl = S.piv[((size_t)k * S.p + i) * NB + lane];
+    const double *LI = S.linv + ((size_t)k * S.p + i) * (size_t)IB * NB;
+    const int pvl = gldi(&S.piv[((size_t)k * S.p + i) * NB + lane]);
     {
-        double2 a[8], b[8], c[LU2];
+        double2 a[8], b[8];
         load_regs(a, X1);
         load_regs(b, X2);
-        const double2 *lup = reinterpret_cast<const double2 *>(S.lup + ((size_t)k * S.p + i) * (size_t)IB * NB);
-#pragma unroll
-        for (int s = 0; s < LU2; ++s) c[s] = lup[tid + s * NT];
         regs_to_lds(sm.X, a);
         regs_to_lds(sm.Y, b);
-#pragma unroll
-        for (int s = 0; s < LU2; ++s) {
-            const int e = tid + s * NT;
-            *reinterpret_cast<double2 *>(&sm.Lup[e / (NB / 2)][2 * (e % (NB / 2))]) = c[s];
-        }
     }
-    double za[4][KP];
+    // Panel operands: li[h][t] = L_up^{-1}[16 h + n][KS g + t] and
+    // zw[t] = L_ik[16 w + n][l0 + KS g + t] (k-slot g of step t is panel row
+    // KS g + t in both products).
+    double li[NH][KS], zw[KS];
+    auto fetch = [&](int l0, double (&li_)[NH][KS], double (&zw_)[KS]) {
+        const double *L = LI + (size_t)l0 * IB;
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+        for (int h = 0; h < NH; ++h)
 #pragma unroll
-        for (int t = 0; t < KP; t += 2) {
-            const double2 v = ld2(&Z[(16 * rb + n) * NB + KP * g + t]);
-            za[rb][t] = v.x;
-            za[rb][t + 1] = v.y;
-        }
+            for (int t = 0; t < KS; ++t) li_[h][t] = gld(&L[(16 * h + n) * IB + KS * g + t]);
+#pragma unroll
+        for (int t = 0; t < KS; ++t) zw_[t] = gld(&Z[(16 * w + n) * NB + l0 + KS * g + t]);
+    };
+    fetch(0, li, zw);
     __syncthreads();
     const int col = 16 * w + n;
 #pragma unroll 1
     for (int l0 = 0; l0 < NB; l0 += IB) {
         const bool more = l0 + IB < NB;
-        double zb[4][KP];
-        if (more)
-#pragma unroll
-            for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-                for (int t = 0; t < KP; t += 2) {
-                    const double2 v = ld2(&Z[(16 * rb + n) * NB + l0 + IB + KP * g + t]);
-                    zb[rb][t] = v.x;
-                    zb[rb][t + 1] = v.y;
-                }
+        double lin[NH][KS], zwn[KS];
+        if (more) fetch(l0 + IB, lin, zwn);
         if (g == 0) {
-            double xr[IB];
-#pragma unroll
-            for (int t = 0; t < IB; ++t) xr[t] = sm.X[l0 + t][col];
+            int rt[IB];
+            uint64_t seen = 0;
+            bool dup = false;
 #pragma unroll
             for (int t = 0; t < IB; ++t) {
                 const int pq = __builtin_amdgcn_readlane(pvl, l0 + t);
-                if (pq >= NB) {
-                    const int r = (pq - NB) & (NB - 1);
-                    const double tmp = sm.Y[r][col];
-                    sm.Y[r][col] = xr[t];
-                    xr[t] = tmp;
+                rt[t] = pq >= NB ? (pq - NB) & (NB - 1) : -1;
+                if (rt[t] >= 0) {
+                    dup = dup || ((seen >> rt[t]) & 1);
+                    seen |= 1ull << rt[t];
                 }
             }
-            unit_lower_solve<IB>(xr, [&](int r) { return &sm.Lup[r][l0]; });
+            if (!dup) {
 #pragma unroll
-            for (int t = 0; t < IB; ++t) sm.X[l0 + t][col] = xr[t];
+                for (int t0 = 0; t0 < IB; t0 += 8) {
+                    double xv[8], yv[8];
+#pragma unroll
+                    for (int t = 0; t < 8; ++t)
+                        if (rt[t0 + t] >= 0) {
+                            xv[t] = sm.X[l0 + t0 + t][col];
+                            yv[t] = sm.Y[rt[t0 + t]][col];
+                        }
+#pragma unroll
+                    for (int t = 0; t < 8; ++t)
+                        if (rt[t0 + t] >= 0) {
+                            sm.X[l0 + t0 + t][col] = yv[t];
+                            sm.Y[rt[t0 + t]][col] = xv[t];
+                        }
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < IB; ++t)
+                    if (rt[t] >= 0) {
+                        const double x = sm.X[l0 + t][col], y = sm.Y[rt[t]][col];
+                        sm.X[l0 + t][col] = y;
+                        sm.Y[rt[t]][col] = x;
+                    }
+            }
         }
         wave_sync();
-        d4 acc[4];
+        {
+            double xb[KS];
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+            for (int t = 0; t < KS; ++t) xb[t] = sm.X[l0 + KS * g + t][col];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) acc[rb][r] = sm.Y[16 * rb + 4 * r + g][col];
-        double xb[KP];
+            for (int h = 0; h < NH; ++h) {
+                d4 ax = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int t = 0; t < KP; ++t) xb[t] = sm.X[l0 + KP * g + t][col];
+                for (int t = 0; t < KS; ++t) ax = mfma(li[h][t], xb[t], ax);
 #pragma unroll
-        for (int t = 0; t < KP; ++t)
+                for (int r = 0; r < 4; ++r) sm.X[l0 + 16 * h + 4 * r + g][col] = ax[r];
+            }
+        }
+        __syncthreads();
+        {
+            double xb[4][KS];
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) acc[rb] = mfma(-za[rb][t], xb[t], acc[rb]);
+            for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+                for (int t = 0; t < KS; ++t) xb[cb][t] = sm.X[l0 + KS * g + t][16 * cb + n];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) sm.Y[16 * rb + 4 * r + g][col] = acc[rb][r];
-        wave_sync();
-        if (more)
+            for (int cb = 0; cb < 4; ++cb) {
+                d4 acc;
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb)
+                for (int r = 0; r < 4; ++r) acc[r] = sm.Y[16 * w + 4 * r + g][16 * cb + n];
 #pragma unroll
-                for (int t = 0; t < KP; ++t) za[rb][t] = zb[rb][t];
+                for (int t = 0; t < KS; ++t) acc = mfma(-zw[t], xb[cb][t], acc);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sm.Y[16 * w + 4 * r + g][16 * cb + n] = acc[r];
+            }
+        }
+        __syncthreads();
+        if (more) {
+#pragma unroll
+            for (int h = 0; h < NH; ++h)
+#pragma unroll
+                for (int t = 0; t < KS; ++t) li[h][t] = lin[h][t];
+#pragma unroll
+            for (int t = 0; t < KS; ++t) zw[t] = zwn[t];
+        }
     }
-    // This wave's 16 columns of both tiles: lane -> row lane / 8 + 8 s,
-    // columns 16 w + 2 (lane % 8) and the next.
-    const int rr = lane >> 3, cc = 16 * w + 2 * (lane & 7);
-#pragma unroll
-    for (int s = 0; s < 8; ++s) {
-        const int r = rr + 8 * s;
-        *reinterpret_cast<double2 *>(&X1[r * NB + cc]) = ld2(&sm.X[r][cc]);
-        *reinterpret_cast<double2 *>(&X2[r * NB + cc]) = ld2(&sm.Y[r][cc]);
-    }
+    store_tile(X1, sm.X);
+    store_tile(X2, sm.Y);
 }
 
 template <int IB>
@@ -801,7 +883,7 @@ __device__ __forceinline__ void push(const Sched &S, int q, int64_t id)
 {
     const uint32_t slot = __hip_atomic_fetch_add(&S.qctl[(NQ + q) * QSTRIDE], 1u, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&S.qslot[S.qoff[q] + slot], (int32_t)(id + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&S.qslot[S.qoff[q] + slot], (int32_t)(id + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ __forceinline__ int64_t pop(const Sched &S, int q)
@@ -945,19 +1027,21 @@ __global__ __launch_bounds__(NT, IB == 16 ? 2 : 1) void k_lu_worker(Sched S)
         }
         __syncthreads();
         if (s_exit) break;
+        // The task's inputs are read with agent-coherent loads (gld): no
+        // acquire fence (it would invalidate the whole L2 of this XCD).
         const int64_t id = s_id;
-        if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        __syncthreads();
         const LTask t = decode(S.p, id);
         if (tid == 0) sm.fail = 0;
         __syncthreads();
         run_task(sm, S, t);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        // Every wave's agent-coherent stores complete before any counter of
+        // a successor moves (in place of a release fence, which would write
+        // back the whole L2 of this XCD).
+        stores_done();
         __syncthreads();
         if (tid < 64) {
             // A task that found no pivot releases nothing: the workers stop on
             // the status.
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const bool failed = sm.fail != 0;
             const int ns = failed ? 0 : nsucc(S.p, t);
             bool kept = false;
@@ -967,7 +1051,7 @@ __global__ __launch_bounds__(NT, IB == 16 ? 2 : 1) void k_lu_worker(Sched S)
                 int64_t sid = -1;
                 if (nn < ns) {
                     sid = succ(S.p, t, nn);
-                    const int32_t old = __hip_atomic_fetch_add(&S.counters[sid], -1, __ATOMIC_ACQUIRE,
+                    const int32_t old = __hip_atomic_fetch_add(&S.counters[sid], -1, __ATOMIC_RELAXED,
                                                                __HIP_MEMORY_SCOPE_AGENT);
                     ready = old == 1;
                 }
@@ -1262,6 +1346,7 @@ extern "C" int tilelu_factor(int64_t n, double *A, int64_t lda, int64_t nb, int6
     for (int q = 0; q < tl::NQ; ++q) off[q + 1] = off[q] + std::max<int64_t>(cap[q], 1);
     int rc;
     if ((rc = W->tiles.ensure((size_t)p * p * nb * nb * sizeof(double)))) return rc;
+    if ((rc = W->luinv.ensure((size_t)p * p * ib * nb * sizeof(double)))) return rc;
     if ((rc = W->status.ensure(256))) return rc;
     if ((rc = W->sched.counters.ensure((size_t)nid * sizeof(int32_t)))) return rc;
     if ((rc = W->sched.qslot.ensure((size_t)off[tl::NQ] * sizeof(int32_t)))) return rc;
@@ -1273,6 +1358,7 @@ extern "C" int tilelu_factor(int64_t n, double *A, int64_t lda, int64_t nb, int6
     tl::Sched S;
     S.tiles = (double *)W->tiles.ptr;
     S.lup = Lup;
+    S.linv = (double *)W->luinv.ptr;
     S.piv = piv;
     S.p = p;
     S.ib = (int)ib;

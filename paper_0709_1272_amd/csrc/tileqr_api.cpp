@@ -743,6 +743,7 @@ extern "C" int tileqr_finalize(void)
             w->status.release();
             w->trace.release();
             w->misc.release();
+            w->luinv.release();
             w->rows.release();
             w->prog.release();
             w->tws.release();
