@@ -159,6 +159,36 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Accesses to the tiles the tasks hand to each other: relaxed atomics at
+// agent scope, i.e. loads and stores coherent across the XCDs' L2 caches on
+// their own.  A task's results are published by waiting for its stores to
+// complete before the dependency counters move, and its inputs are read with
+// such loads after the task was taken, so no task needs the whole-cache
+// write-back or invalidate of an agent-scope release or acquire fence.
+__device__ __forceinline__ double gld(const double *p)
+{
+    return __longlong_as_double((long long)__hip_atomic_load(reinterpret_cast<const unsigned long long *>(p),
+                                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ void gst(double *p, double v)
+{
+    __hip_atomic_store(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Waits until this wave's stores have completed (are visible at agent
+// scope); also a compiler barrier for memory accesses.
+__device__ __forceinline__ void stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// The thread's index, opaque to the optimiser: addresses derived from it are
+// formed inside each task instead of being hoisted out of the persistent
+// loop, where the three task bodies would keep all of them live at once.
+__device__ __forceinline__ int opaque_tid()
+{
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -202,7 +232,7 @@ __device__ __forceinline__ double *tile_at(const Sched &S, int i, int j)
 template <int NB>
 __device__ __forceinline__ void solve_rows(SmemF<NB> &sm, const double *Lbb, int ld, int r0, int c0)
 {
-    const int r = r0 + (int)threadIdx.x;
+    const int r = r0 + opaque_tid();
     if (r >= NB) return;
     double x[PW];
 #pragma unroll
@@ -225,10 +255,10 @@ __device__ __forceinline__ void solve_rows(SmemF<NB> &sm, const double *Lbb, int
 template <int NB>
 __device__ void task_potf2(SmemF<NB> &sm, double *T, int k, int32_t *status, int32_t *minor)
 {
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, n = lane & 15, g = lane >> 4;
+    const int tid = opaque_tid(), w = tid >> 6, lane = tid & 63, n = lane & 15, g = lane >> 4;
     for (int e = tid; e < NB * NB; e += NT) {
         const int r = e / NB, c = e % NB;
-        sm.X[r][c] = r >= c ? T[e] : 0.0;
+        sm.X[r][c] = r >= c ? gld(&T[e]) : 0.0;
     }
     if (tid == 0) sm.fail = 0;
     __syncthreads();
@@ -285,7 +315,7 @@ __device__ void task_potf2(SmemF<NB> &sm, double *T, int k, int32_t *status, int
     }
     for (int e = tid; e < NB * NB; e += NT) {
         const int r = e / NB, c = e % NB;
-        if (r >= c) T[e] = sm.X[r][c];
+        if (r >= c) gst(&T[e], sm.X[r][c]);
     }
 }
 
@@ -295,7 +325,7 @@ __device__ void task_potf2(SmemF<NB> &sm, double *T, int k, int32_t *status, int
 template <int NB, int C0>
 __device__ __forceinline__ void trsm_panel(SmemF<NB> &sm, const double *Tk)
 {
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, n = lane & 15, g = lane >> 4;
+    const int tid = opaque_tid(), w = tid >> 6, lane = tid & 63, n = lane & 15, g = lane >> 4;
     if constexpr (C0 > 0) {
         constexpr int NRB = NB / 16, KS = C0 / 4;
         for (int blk = w; blk < NRB * 2; blk += 4) {
@@ -303,7 +333,7 @@ __device__ __forceinline__ void trsm_panel(SmemF<NB> &sm, const double *Tk)
             const double *lrow = Tk + (size_t)(C0 + 16 * cb + n) * NB + g;
             double lv[KS];
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) lv[ks] = lrow[4 * ks];
+            for (int ks = 0; ks < KS; ++ks) lv[ks] = gld(&lrow[4 * ks]);
             d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) acc = mfma(sm.X[16 * rb + n][4 * ks + g], lv[ks], acc);
@@ -313,7 +343,7 @@ __device__ __forceinline__ void trsm_panel(SmemF<NB> &sm, const double *Tk)
     }
     for (int e = tid; e < PW * PW; e += NT) {
         const int r = e / PW, c = e % PW;
-        sm.Lb[r][c] = r >= c ? Tk[(size_t)(C0 + r) * NB + C0 + c] : 0.0;
+        sm.Lb[r][c] = r >= c ? gld(&Tk[(size_t)(C0 + r) * NB + C0 + c]) : 0.0;
     }
     __syncthreads();
     solve_rows<NB>(sm, &sm.Lb[0][0], PW + 1, 0, C0);
@@ -334,11 +364,11 @@ __device__ __forceinline__ void trsm_panels(SmemF<NB> &sm, const double *Tk)
 template <int NB>
 __device__ void task_trsm(SmemF<NB> &sm, double *Ti, const double *Tk)
 {
-    const int tid = threadIdx.x;
-    for (int e = tid; e < NB * NB; e += NT) sm.X[e / NB][e % NB] = Ti[e];
+    const int tid = opaque_tid();
+    for (int e = tid; e < NB * NB; e += NT) sm.X[e / NB][e % NB] = gld(&Ti[e]);
     __syncthreads();
     trsm_panels<NB, 0>(sm, Tk);
-    for (int e = tid; e < NB * NB; e += NT) Ti[e] = sm.X[e / NB][e % NB];
+    for (int e = tid; e < NB * NB; e += NT) gst(&Ti[e], sm.X[e / NB][e % NB]);
 }
 
 // GSMM(k, i, j): C <- C - Li Lj^T (C, Li, Lj row-major NB x NB tiles); with
@@ -348,7 +378,7 @@ template <int NB>
 __device__ void task_gsmm(SmemG<NB> &sm, double *C, const double *Li, const double *Lj, bool diag)
 {
     constexpr int H = NB / 2, BW = H / 16, NCH = NB / KC, PER = NB * KC / NT;
-    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, n = lane & 15, g = lane >> 4;
+    const int tid = opaque_tid(), w = tid >> 6, lane = tid & 63, n = lane & 15, g = lane >> 4;
     const int wr = w >> 1, wc = w & 1;
     const bool active = !diag || wr >= wc;
     auto live = [&](int a, int bb) { return !diag || wr > wc || a >= bb; };
@@ -360,15 +390,15 @@ __device__ void task_gsmm(SmemG<NB> &sm, double *C, const double *Li, const doub
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 acc[a][bb][r] = (active && live(a, bb))
-                                    ? C[(size_t)(wr * H + 16 * a + 4 * r + g) * NB + wc * H + 16 * bb + n]
+                                    ? gld(&C[(size_t)(wr * H + 16 * a + 4 * r + g) * NB + wc * H + 16 * bb + n])
                                     : 0.0;
     double ra[PER], rb[PER];
     auto load_chunk = [&](int kc) {
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int e = tid + u * NT, row = e / KC, col = e % KC;
-            ra[u] = Li[(size_t)row * NB + kc + col];
-            rb[u] = Lj[(size_t)row * NB + kc + col];
+            ra[u] = gld(&Li[(size_t)row * NB + kc + col]);
+            rb[u] = gld(&Lj[(size_t)row * NB + kc + col]);
         }
     };
     auto store_chunk = [&](int buf) {
@@ -413,7 +443,7 @@ __device__ void task_gsmm(SmemG<NB> &sm, double *C, const double *Li, const doub
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = wr * H + 16 * a + 4 * r + g, col = wc * H + 16 * bb + n;
-                if (!diag || row >= col) C[(size_t)row * NB + col] = acc[a][bb][r];
+                if (!diag || row >= col) gst(&C[(size_t)row * NB + col], acc[a][bb][r]);
             }
         }
 }
@@ -437,7 +467,7 @@ __device__ __forceinline__ void push(const Sched &S, int q, int64_t id)
 {
     const uint32_t slot = __hip_atomic_fetch_add(&S.qctl[(NQ + q) * QSTRIDE], 1u, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&S.qslot[S.qoff[q] + slot], (int32_t)(id + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&S.qslot[S.qoff[q] + slot], (int32_t)(id + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Non-blocking pop: -1 when the queue holds nothing claimable now.
@@ -585,16 +615,18 @@ __global__ __launch_bounds__(NT) void k_chol_worker(Sched S)
         }
         __syncthreads();
         if (s_exit) break;
+        // The task's inputs are read with agent-coherent loads (gld): no
+        // acquire fence (it would invalidate the whole L2 of this XCD).
         const int64_t id = s_id;
-        if (tid < 64) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        __syncthreads();
         const CTask t = decode(S.p, id);
         run_task<NB>(sm, S, t);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        // Every wave's agent-coherent stores complete before any counter of
+        // a successor moves (in place of a release fence, which would write
+        // back the whole L2 of this XCD).
+        stores_done();
         __syncthreads();
         if (tid < 64) {
             // A failed POTF2 releases nothing: the workers stop on the status.
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const bool failed = t.type == T_POTF2 && sm.f.fail;
             const int ns = failed ? 0 : nsucc(S.p, t);
             bool kept = false;
@@ -604,7 +636,7 @@ __global__ __launch_bounds__(NT) void k_chol_worker(Sched S)
                 int64_t sid = -1;
                 if (nn < ns) {
                     sid = succ(S.p, t, nn);
-                    const int32_t old = __hip_atomic_fetch_add(&S.counters[sid], -1, __ATOMIC_ACQUIRE,
+                    const int32_t old = __hip_atomic_fetch_add(&S.counters[sid], -1, __ATOMIC_RELAXED,
                                                                __HIP_MEMORY_SCOPE_AGENT);
                     ready = old == 1;
                 }
