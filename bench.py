@@ -47,7 +47,7 @@ KAPPA = 1e6
 NB, IB = 256, 32
 TOL = 1e-14
 CPU_SAMPLE_N = 2048
-EXTRAS = ("fp16x2_ls", "qr8192", "tall_ls", "batched", "cholesky", "mfma_peak")
+EXTRAS = ("fp16x2_ls", "qr8192", "tall_ls", "batched", "cholesky", "lu", "mfma_peak")
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 # Sources the worker kernels are compiled from: a traffic figure in a profile
 # is valid only for the build whose hash it records.
@@ -57,6 +57,7 @@ KERNEL_SRCS = [os.path.join(ROOT, "paper_0709_1272_amd", "csrc", f)
 
 
 CHOL_SRCS = [os.path.join(ROOT, "paper_0709_1272_amd", "csrc", "tilechol.hip")]
+LU_SRCS = [os.path.join(ROOT, "paper_0709_1272_amd", "csrc", "tilelu.hip")]
 
 
 def kernel_hash(srcs=None):
@@ -222,6 +223,39 @@ def cholesky(tq, torch, dev, st):
             "worker_frac_fp64_peak": round(tc.flops(n) / (wk * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
             "traffic_bytes_per_launch": measured_traffic("k_chol_worker_chol32768_fp64.md", CHOL_SRCS),
             "algorithmic_bytes": 16.0 * nb * nb * sum(m * (m + 1) // 2 for m in range(1, p))}
+
+
+def lu(tq, torch, dev, st):
+    """Tiled LU with tiled pairwise pivoting (Algorithm 3) of one 16384 x 16384
+    matrix with N(0, 1) entries, nb 64, ib 16, FP64."""
+    from paper_0709_1272_amd import tilelu as tl
+    n, nb, ib = 16384, 64, 16
+    g = torch.Generator(device=dev)
+    g.manual_seed(0)
+    A0 = torch.randn((n, n), generator=g, device=dev, dtype=torch.float64)
+    A = torch.empty_like(A0)
+    Lup = torch.zeros(tl.lup_size(n, nb, ib), dtype=torch.float64, device=dev)
+    piv = torch.zeros(tl.piv_size(n, nb), dtype=torch.int32, device=dev)
+    res = []
+    for r in range(4):
+        A.copy_(A0)
+        info = tl.LUInfo()
+        tq.check(tl.factor(n, A.data_ptr(), n, nb, ib, Lup.data_ptr(), piv.data_ptr(),
+                           tq.opts(stream=st.cuda_stream, flags=tq.FLAG_TIMING), info), "tilelu_factor")
+        if r:
+            res.append((info.ms_factor, info.ms_worker))
+    del A, A0, Lup, piv
+    torch.cuda.empty_cache()
+    ms = sum(r[0] for r in res) / len(res)
+    wk = sum(r[1] for r in res) / len(res)
+    p = n // nb
+    return {"workload": f"tiled LU with tiled pairwise pivoting (Algorithm 3) of one {n}x{n} matrix, N(0,1) entries "
+                        f"(torch generator on the device, seed 0), nb {nb}, ib {ib}, FP64",
+            "ms": round(ms, 3), "tflops": round(tl.flops(n) / (ms * 1e-3) / 1e12, 4),
+            "worker_ms": round(wk, 3),
+            "worker_frac_fp64_peak": round(tl.flops(n) / (wk * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+            "traffic_bytes_per_launch": measured_traffic("k_lu_worker_lu16384_fp64.md", LU_SRCS),
+            "algorithmic_bytes": 16.0 * nb * nb * sum(m * m for m in range(1, p))}
 
 
 def tall_ls(tq, torch, dev, st):
@@ -454,6 +488,8 @@ def main():
         out["batched"] = batched(tq, torch, dev, st)
     if "cholesky" in extras:
         out["cholesky"] = cholesky(tq, torch, dev, st)
+    if "lu" in extras:
+        out["lu"] = lu(tq, torch, dev, st)
     if "mfma_peak" in extras:
         out["mfma_peak"] = {"fp64": round(tq.mfma_peak(0), 2), "bf16": round(tq.mfma_peak(1), 2),
                             "fp16": round(tq.mfma_peak(2), 2), "unit": "TFLOP/s",
