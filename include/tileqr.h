@@ -299,6 +299,49 @@ int tileqr_factor_batched(int64_t batch, const int64_t *m, const int64_t *n,
                           double *const *A, const int64_t *lda, const int64_t *nb,
                           const int64_t *ib, double *const *T, const tileqr_opts *opts);
 
+/*
+ * Tree reduction of the panels of a tall matrix (m >= n), an extension of
+ * Section 3.2.1's Algorithm 2, whose flat chain of TSQRT makes the panel of
+ * every step a chain of ceil(m / nb) tasks.  The rows are cut into `leaves`
+ * row blocks of h rows (h the largest multiple of nb with leaves * h <= m;
+ * the last block takes the rest; every block needs at least max(n, nb)
+ * rows); each block is factored by Algorithm 2 (all blocks in one
+ * tileqr_factor_batched launch, one task per inner panel unless
+ * opts->panel_tasks says otherwise, a quarter of the CUs on the panels
+ * unless opts->panel_workers says otherwise), then the blocks' triangles R
+ * are merged level by level, up to four at a time, by the QR of the stack
+ * [R_1; ...; R_k] (kn x n) with the same tile kernels (the merges of a level
+ * in one batched launch; a lone block passes up unchanged).
+ *   A (m x n, lda >= m): on return R in the upper triangle of rows 0..n-1;
+ *     below the diagonal of every block's first rows its reflectors (the
+ *     other blocks' first n rows hold their own R, used by the merges).
+ *   F (device, tileqr_tree_size doubles): the blocks' T factors, then every
+ *     merge's stacked matrix (leading dimension kn) and T.
+ *   opts: FP64 only; stream (the call returns with its work done); the
+ *     scheduler options apply to the batched launches.
+ * Q^T B and Q B (B m x nrhs, ldb >= m) follow the same order: each block's
+ * Q^T on its rows, then each merge's on the first n rows of its blocks (the
+ * leftmost block of a merged group carries the group).  (Q^T B)(0:n) is
+ * in B's first n rows, as with tileqr_apply_qt.
+ * tileqr_solve_ls_tree: X (n x nrhs, ldx >= n) = R^{-1} (Q^T B)(0:n), the
+ * FP64 least-squares solution, from copies of A and B; *ms (may be NULL)
+ * gets the device time of the call.
+ * tileqr_tree_size returns 0 for impossible arguments.  Errors as
+ * tileqr_factor_ex; -7 leaves (a block would be too short) for the factor,
+ * -8 for the applies, -12 for the solve; TILEQR_EUNSUPPORTED for a split
+ * precision, TILEQR_FLAG_SERIAL or TILEQR_FLAG_TRACE.
+ */
+size_t tileqr_tree_size(int64_t m, int64_t n, int64_t nb, int64_t ib, int64_t leaves);
+int tileqr_factor_tree(int64_t m, int64_t n, double *A, int64_t lda, int64_t nb, int64_t ib, int64_t leaves,
+                       double *F, const tileqr_opts *opts);
+int tileqr_apply_qt_tree(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, int64_t nb, int64_t ib,
+                         int64_t leaves, const double *F, double *B, int64_t ldb);
+int tileqr_apply_q_tree(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, int64_t nb, int64_t ib,
+                        int64_t leaves, const double *F, double *B, int64_t ldb);
+int tileqr_solve_ls_tree(int64_t m, int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B,
+                         int64_t ldb, double *X, int64_t ldx, int64_t nb, int64_t ib, int64_t leaves,
+                         const tileqr_opts *opts, double *ms);
+
 /* Outcome of a tileqr_solve_ls_batched call. */
 typedef struct {
     int64_t converged;      /* matrices whose backward error reached tol         */

@@ -25,6 +25,7 @@ UNITS = [("tileqr_kernels.hip", [], "tileqr_kernels"),
          ("tileqr_peak.hip", [], "tileqr_peak"),
          ("tileqr_noalloc.hip", [], "tileqr_noalloc"),
          ("tileqr_lsbatch.hip", [], "tileqr_lsbatch"),
+         ("tileqr_tree.hip", [], "tileqr_tree"),
          ("tilechol.hip", [], "tilechol"),
          ("tilelu.hip", [], "tilelu"),
          ("tileqr_api.cpp", [], "tileqr_api"),

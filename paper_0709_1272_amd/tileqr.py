@@ -68,6 +68,12 @@ _SIGS = {
     "tileqr_apply_q": (_int, [_i64, _i64, _i64, _vp, _i64, _i64, _i64, _vp, _vp, _i64]),
     "tileqr_solve_ls": (_int, [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
                                ctypes.POINTER(Opts), ctypes.POINTER(Info)]),
+    "tileqr_tree_size": (ctypes.c_size_t, [_i64, _i64, _i64, _i64, _i64]),
+    "tileqr_factor_tree": (_int, [_i64, _i64, _vp, _i64, _i64, _i64, _i64, _vp, ctypes.POINTER(Opts)]),
+    "tileqr_apply_qt_tree": (_int, [_i64, _i64, _i64, _vp, _i64, _i64, _i64, _i64, _vp, _vp, _i64]),
+    "tileqr_apply_q_tree": (_int, [_i64, _i64, _i64, _vp, _i64, _i64, _i64, _i64, _vp, _vp, _i64]),
+    "tileqr_solve_ls_tree": (_int, [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _i64, _i64, _i64,
+                                    ctypes.POINTER(Opts), ctypes.POINTER(ctypes.c_double)]),
     "tileqr_factor_batched": (_int, [_i64, _I64P, _I64P, ctypes.POINTER(_vp), _I64P, _I64P, _I64P,
                                      ctypes.POINTER(_vp), ctypes.POINTER(Opts)]),
     "tileqr_solve_ls_batched": (_int, [_i64, _I64P, _I64P, ctypes.POINTER(_vp), _I64P, ctypes.POINTER(_vp),
@@ -157,6 +163,29 @@ def apply_q(m, n, nrhs, A, lda, nb, ib, T, B, ldb):
 def solve_ls(m, n, nrhs, A, lda, B, ldb, X, ldx, o=None, info=None):
     return _L.tileqr_solve_ls(m, n, nrhs, A, lda, B, ldb, X, ldx, _ptr_opts(o),
                               ctypes.byref(info) if info is not None else None)
+
+
+def tree_size(m, n, nb, ib, leaves):
+    return int(_L.tileqr_tree_size(m, n, nb, ib, leaves))
+
+
+def factor_tree(m, n, A, lda, nb, ib, leaves, F, o=None):
+    return _L.tileqr_factor_tree(m, n, A, lda, nb, ib, leaves, F, _ptr_opts(o))
+
+
+def apply_qt_tree(m, n, nrhs, A, lda, nb, ib, leaves, F, B, ldb):
+    return _L.tileqr_apply_qt_tree(m, n, nrhs, A, lda, nb, ib, leaves, F, B, ldb)
+
+
+def apply_q_tree(m, n, nrhs, A, lda, nb, ib, leaves, F, B, ldb):
+    return _L.tileqr_apply_q_tree(m, n, nrhs, A, lda, nb, ib, leaves, F, B, ldb)
+
+
+def solve_ls_tree(m, n, nrhs, A, lda, B, ldb, X, ldx, nb, ib, leaves, o=None):
+    """Returns (status, device milliseconds of the call)."""
+    ms = ctypes.c_double(0.0)
+    rc = _L.tileqr_solve_ls_tree(m, n, nrhs, A, lda, B, ldb, X, ldx, nb, ib, leaves, _ptr_opts(o), ctypes.byref(ms))
+    return rc, ms.value
 
 
 def solve_ls_batched(ms, ns, A_ptrs, ldas, b_ptrs, x_ptrs, o=None, info=None):

@@ -288,3 +288,31 @@ def test_tilelu_exports_counts_selfcheck():
         assert c == brute and total == sum(brute), p
         assert tilelu.dag_selfcheck(p, trials=4, seed=p) == 0, p
     assert tilelu.lup_size(0, 64, 16) == 0 and tilelu.lup_size(64, 32, 16) == 0
+
+
+def test_tree_size_and_arguments():
+    # The tree's storage: every leaf's T (leaves of h rows, h the largest
+    # multiple of nb with leaves * h <= m, the last leaf the rest), then per
+    # merge (up to four children) a stacked kn x n matrix and its T; argument
+    # checks before any device work.
+    tq = _tq()
+    m, n, nb, ib, L = 5000, 300, 64, 16, 3
+    h = (m // L) // nb * nb
+    rows = [h, h, m - 2 * h]
+    want = sum(tq.t_size(r, n, nb, ib) for r in rows) + 3 * n * n + tq.t_size(3 * n, n, nb, ib)
+    assert tq.tree_size(m, n, nb, ib, L) == want
+    # Six leaves: a merge of four and one of two, then a merge of those two.
+    m, n, L = 6000, 100, 6
+    h = (m // L) // nb * nb
+    rows = [h] * 5 + [m - 5 * h]
+    want = (sum(tq.t_size(r, n, nb, ib) for r in rows) + 4 * n * n + tq.t_size(4 * n, n, nb, ib)
+            + 2 * (2 * n * n + tq.t_size(2 * n, n, nb, ib)))
+    assert tq.tree_size(m, n, nb, ib, L) == want
+    assert tq.tree_size(m, n, nb, ib, 1) == tq.t_size(m, n, nb, ib)
+    assert tq.tree_size(1000, 300, 64, 16, 4) == 0           # leaves of 192 rows < n
+    assert tq.tree_size(1000, 2000, 64, 16, 1) == 0          # not tall
+    assert tq.factor_tree(-1, 1, 8, 1, 64, 16, 1, 8, None) == -1
+    assert tq.factor_tree(10, 20, 8, 10, 64, 16, 1, 8, None) == -2
+    assert tq.factor_tree(1000, 300, 8, 1000, 64, 16, 4, 8, None) == -7
+    assert tq.factor_tree(1000, 300, 8, 1000, 64, 16, 2, 0, None) == -8
+    assert tq.apply_qt_tree(1000, 300, 1, 8, 1000, 64, 16, 4, 8, 8, 1000) == -8
