@@ -279,6 +279,38 @@ def tall_ls(tq, torch, dev, st):
             row[name]["tflops"] = round(flops / (info.ms_total * 1e-3) / 1e12, 4)
         for name in ("fp16x2", "bf16x3", "bf16x2"):
             row[name]["speedup_vs_fp64"] = round(row["fp64"]["ms_total"] / row[name]["ms_total"], 3)
+        # The tree reduction of the panels (4 row-block leaves, one merge),
+        # FP64, one solve without refinement; its backward error recomputed
+        # here with torch.
+        best = None
+        for _ in range(3):
+            rc, ms = tq.solve_ls_tree(m, n, 1, At.data_ptr(), m, Bt.data_ptr(), m, Xt.data_ptr(), n, 256, 32, 4,
+                                      tq.opts(stream=st.cuda_stream))
+            tq.check(rc, "tileqr_solve_ls_tree")
+            best = ms if best is None else min(best, ms)
+        A_, x_, b_ = At.t(), Xt.t(), Bt.t()
+        r_ = b_ - A_ @ x_
+        nA = torch.linalg.norm(A_)
+        eta = float(torch.linalg.norm(A_.t() @ r_) / (nA * (nA * torch.linalg.norm(x_) + torch.linalg.norm(b_))))
+        row["fp64_tree4"] = {"ms_total": round(best, 3), "tflops": round(flops / (best * 1e-3) / 1e12, 4),
+                             "eta_ls": eta, "speedup_vs_fp64": round(row["fp64"]["ms_total"] / best, 3)}
+        if kappa == 1e6:
+            fac = {}
+            for leaves in (1, 4):
+                F = torch.zeros(tq.tree_size(m, n, 256, 32, leaves), dtype=torch.float64, device=dev)
+                t = []
+                for _ in range(3):
+                    Ac = At.clone()
+                    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    s0.record(st)
+                    tq.check(tq.factor_tree(m, n, Ac.data_ptr(), m, 256, 32, leaves, F.data_ptr(),
+                                            tq.opts(stream=st.cuda_stream)), "tileqr_factor_tree")
+                    s1.record(st)
+                    torch.cuda.synchronize()
+                    t.append(s0.elapsed_time(s1))
+                fac[f"leaves_{leaves}_ms"] = round(min(t), 3)
+                del F, Ac
+            out["factor_tree_vs_flat"] = fac
         out[f"kappa_{kappa:.0e}"] = row
         del At, Bt, Xt
     return out
