@@ -203,6 +203,7 @@ struct Smem {
     double Lup[IB][NB];        // TSTRF / SSSSM: L_up of the tile
     int32_t piv[NB];
     int32_t fail;
+    int32_t chain;             // SSSSM: A_kj stays here for SSSSM(k, i+1, j), run next by this workgroup
 };
 
 __device__ __forceinline__ double *tile_at(const Sched &S, int i, int j)
@@ -739,8 +740,14 @@ __device__ __forceinline__ void task_tstrf(Smem<IB> &sm, const Sched &S, int k, 
 //   by rows (wave w owns rows 16 w .. 16 w + 15 of A_ij):
 //     A_ij -= L_ik[:, panel] A_kj[panel] on FP64 MFMA, each wave reading
 //     only its 16 rows of L_ik from HBM, into registers, one panel ahead.
+// Chaining: A_kj passes down the column, SSSSM(k, i, j) to SSSSM(k, i+1, j).
+// When the latter waits only for this task (its counter reads 1: TSTRF(k, i+1)
+// and the previous step's update of tile (i+1, j) are done, and no other task
+// can make it ready), this workgroup runs it next with A_kj still in LDS
+// (have_x), so A_kj is neither stored nor loaded in between.
 template <int IB>
-__device__ __forceinline__ void task_ssssm(Smem<IB> &sm, const Sched &S, int k, int i, int j)
+__device__ __forceinline__ void task_ssssm(Smem<IB> &sm, const Sched &S, int k, int i, int j, bool have_x,
+                                           bool may_chain)
 {
     constexpr int NH = IB / 16;        // 16-row blocks of a panel
     constexpr int KS = IB / 4;         // MFMA steps over a panel
@@ -750,10 +757,13 @@ __device__ __forceinline__ void task_ssssm(Smem<IB> &sm, const Sched &S, int k, 
     const double *LI = S.linv + ((size_t)k * S.p + i) * (size_t)IB * NB;
     const int pvl = gldi(&S.piv[((size_t)k * S.p + i) * NB + lane]);
     {
-        double2 a[8], b[8];
-        load_regs(a, X1);
+        double2 b[8];
         load_regs(b, X2);
-        regs_to_lds(sm.X, a);
+        if (!have_x) {
+            double2 a[8];
+            load_regs(a, X1);
+            regs_to_lds(sm.X, a);
+        }
         regs_to_lds(sm.Y, b);
     }
     // Panel operands: li[h][t] = L_up^{-1}[16 h + n][KS g + t] and
@@ -859,17 +869,21 @@ __device__ __forceinline__ void task_ssssm(Smem<IB> &sm, const Sched &S, int k, 
             for (int t = 0; t < KS; ++t) zw[t] = zwn[t];
         }
     }
-    store_tile(X1, sm.X);
+    if (tid == 0)
+        sm.chain = may_chain && i + 1 < S.p && gldi(&S.counters[id_ssssm(S.p, k, i + 1, j)]) == 1 ? 1 : 0;
+    __syncthreads();
+    if (!sm.chain) store_tile(X1, sm.X);
     store_tile(X2, sm.Y);
 }
 
 template <int IB>
-__device__ __forceinline__ void run_task(Smem<IB> &sm, const Sched &S, const LTask &t)
+__device__ __forceinline__ void run_task(Smem<IB> &sm, const Sched &S, const LTask &t, bool have_x = false,
+                                         bool may_chain = false)
 {
     if (t.type == T_GETRF) task_getrf(sm, S, t.k);
     else if (t.type == T_GESSM) task_gessm(sm, S, t.k, t.j);
     else if (t.type == T_TSTRF) task_tstrf(sm, S, t.k, t.i);
-    else task_ssssm(sm, S, t.k, t.i, t.j);
+    else task_ssssm(sm, S, t.k, t.i, t.j, have_x, may_chain);
 }
 
 // ------------------------------------------------------------- scheduler
@@ -964,18 +978,24 @@ template <int IB>
 __global__ __launch_bounds__(NT, IB == 16 ? 2 : 1) void k_lu_worker(Sched S)
 {
     __shared__ Smem<IB> sm;
-    __shared__ int64_t s_id, s_next;
+    __shared__ int64_t s_id, s_next, s_chain;   // s_chain: the chained SSSSM's id, else -1
     __shared__ int s_exit;
     const int tid = threadIdx.x;
     const int xcd = xcd_id();
     uint64_t rng = mix64(S.seed ^ (0x9e3779b97f4a7c15ULL * (blockIdx.x + 1)));
-    if (tid == 0) s_next = -1;
+    if (tid == 0) {
+        s_next = -1;
+        s_chain = -1;
+    }
     for (;;) {
         if (tid == 0) {
             int64_t id = s_next;
             int ex = 0;
             s_next = -1;
-            if (id >= 0) {
+            // A chained SSSSM (its A_kj in LDS) runs now, whatever else is
+            // ready; any other kept task yields to a ready one of a higher
+            // level.
+            if (id >= 0 && id != s_chain) {
                 const int lv = level_of(decode(S.p, id));
                 if (lv > 0) {
                     const int64_t hi = pop_upto(S, lv - 1, xcd, false, 0);
@@ -1031,9 +1051,15 @@ __global__ __launch_bounds__(NT, IB == 16 ? 2 : 1) void k_lu_worker(Sched S)
         // acquire fence (it would invalidate the whole L2 of this XCD).
         const int64_t id = s_id;
         const LTask t = decode(S.p, id);
-        if (tid == 0) sm.fail = 0;
+        const bool have_x = id == s_chain;
         __syncthreads();
-        run_task(sm, S, t);
+        if (tid == 0) {
+            sm.fail = 0;
+            sm.chain = 0;
+            s_chain = -1;
+        }
+        __syncthreads();
+        run_task(sm, S, t, have_x, true);
         // Every wave's agent-coherent stores complete before any counter of
         // a successor moves (in place of a release fence, which would write
         // back the whole L2 of this XCD).
@@ -1043,6 +1069,7 @@ __global__ __launch_bounds__(NT, IB == 16 ? 2 : 1) void k_lu_worker(Sched S)
             // A task that found no pivot releases nothing: the workers stop on
             // the status.
             const bool failed = sm.fail != 0;
+            const bool chain = t.type == T_SSSSM && sm.chain != 0;
             const int ns = failed ? 0 : nsucc(S.p, t);
             bool kept = false;
             for (int base = 0; base < ns; base += 64) {
@@ -1058,7 +1085,9 @@ __global__ __launch_bounds__(NT, IB == 16 ? 2 : 1) void k_lu_worker(Sched S)
                 const uint64_t mask = __ballot(ready);
                 int keeper = -1;
                 if (!kept && mask != 0) {
-                    keeper = __builtin_ctzll(mask);
+                    // A chain keeps SSSSM(k, i+1, j), successor 1 of an
+                    // SSSSM, which this task's decrement made ready.
+                    keeper = chain ? 1 : __builtin_ctzll(mask);
                     kept = true;
                 }
                 if (ready) {
@@ -1066,7 +1095,10 @@ __global__ __launch_bounds__(NT, IB == 16 ? 2 : 1) void k_lu_worker(Sched S)
                     else push(S, queue_of(decode(S.p, sid)), sid);
                 }
             }
-            if (tid == 0 && !failed) __hip_atomic_fetch_add(S.done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (tid == 0) {
+                s_chain = chain ? id_ssssm(S.p, t.k, t.i + 1, t.j) : -1;
+                if (!failed) __hip_atomic_fetch_add(S.done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
         __syncthreads();
     }
