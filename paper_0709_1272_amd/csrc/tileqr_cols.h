@@ -134,7 +134,7 @@ __device__ __forceinline__ void write_vsplit(const Smem<NB, IB> &sm, gu4 *dst)
     // |v| <= 1 for every reflector entry (|alpha - beta| >= |x_i|): a fixed
     // scale keeps the FP16 parts out of the subnormal range.
     constexpr double VS = PREC == PREC_FP16X2 ? 4096.0 : 1.0;
-    const int tid = threadIdx.x, lane = lane_id(), n = lane & 15, g = lane >> 4;
+    const int tid = tidx(), lane = lane_id(), n = lane & 15, g = lane >> 4;
     // V^T X images: chunk c, block a, lane (n, g), element e = V[32c + 16(e/4) + 4g + e%4][16a + n].
     constexpr int NVTX = (NB / 32) * 2 * 64;
 #pragma unroll
@@ -216,7 +216,7 @@ __device__ __forceinline__ void vs_load(VsStage<NB, COUNT> &S, const gu4 *src)
 {
 #pragma unroll
     for (int u = 0; u < VsStage<NB, COUNT>::SPT; ++u) {
-        const int e = threadIdx.x + u * VsStage<NB, COUNT>::NT;
+        const int e = tidx() + u * VsStage<NB, COUNT>::NT;
         S.v[u] = src[e < COUNT ? e : COUNT - 1];
     }
 }
@@ -226,7 +226,7 @@ __device__ __forceinline__ void vs_store(u4 *lv, const VsStage<NB, COUNT> &S)
 {
 #pragma unroll
     for (int u = 0; u < VsStage<NB, COUNT>::SPT; ++u) {
-        const int e = threadIdx.x + u * VsStage<NB, COUNT>::NT;
+        const int e = tidx() + u * VsStage<NB, COUNT>::NT;
         if (e < COUNT) lv[e] = S.v[u];
     }
 }

@@ -3,6 +3,7 @@
 // value of TQ_PREC (1 BF16 x2, 2 FP16 x2, 3 BF16 x3), always with ib = 32.
 // Reflectors and T are formed in FP64; the block-reflector products (in
 // LARFB, SSRFB and the trailing updates inside GEQRT / TSQRT) are split.
+#define TQ_OPAQUE_TID 1
 #include "tileqr_tile.h"
 
 #ifndef TQ_PREC

@@ -114,8 +114,25 @@ struct alignas(16) Smem {
 
 // ------------------------------------------------------------------ helpers
 
-__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
-__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+// The thread's index.  A unit that defines TQ_OPAQUE_TID to 1 makes it opaque
+// to the optimiser, so that addresses derived from it are formed inside each
+// task instead of being hoisted out of the persistent loop, where the task
+// bodies of every role would keep all of them live at once.  The split units
+// need that: their update tasks hold a 128 x 16 FP64 block per wave, and the
+// hoisted addresses on top of it spill.  The FP64 units keep the index
+// transparent: their hoisted addresses fit, and forming them per task is the
+// slower of the two there.
+#ifndef TQ_OPAQUE_TID
+#define TQ_OPAQUE_TID 0
+#endif
+__device__ __forceinline__ int tidx()
+{
+    int t = threadIdx.x;
+    if constexpr (TQ_OPAQUE_TID != 0) asm volatile("" : "+v"(t));
+    return t;
+}
+__device__ __forceinline__ int lane_id() { return tidx() & 63; }
+__device__ __forceinline__ int wave_id() { return tidx() >> 6; }
 
 __device__ __forceinline__ gdouble *tile_ptr(const MatDev &M, int nb, int i, int j)
 {
@@ -141,13 +158,13 @@ __device__ __forceinline__ void stage_load(Stage<NB, IB> &S, const gdouble *tile
     constexpr int H = IB / 2, TE = IB * IB / 2;
 #pragma unroll
     for (int u = 0; u < C::VPT; ++u) {
-        const int e = threadIdx.x + u * C::NT, r = e / H, c2 = e % H;
+        const int e = tidx() + u * C::NT, r = e / H, c2 = e % H;
         const v2d x = *reinterpret_cast<const gv2d *>(tile + (size_t)r * NB + c0 + 2 * c2);
         S.v[u] = r >= r0 ? x : v2d{0.0, 0.0};
     }
 #pragma unroll
     for (int u = 0; u < C::TPT; ++u) {
-        const int e = threadIdx.x + u * C::NT;
+        const int e = tidx() + u * C::NT;
         if constexpr (HAS_T) {
             const v2d t = reinterpret_cast<const gv2d *>(Tg)[e < TE ? e : TE - 1];
             S.t[u] = e < TE ? t : v2d{0.0, 0.0};
@@ -167,7 +184,7 @@ __device__ __forceinline__ void stage_store(Smem<NB, IB> &sm, const Stage<NB, IB
     constexpr int H = IB / 2;
 #pragma unroll
     for (int u = 0; u < C::VPT; ++u) {
-        const int e = threadIdx.x + u * C::NT, r = e / H, c = 2 * (e % H);
+        const int e = tidx() + u * C::NT, r = e / H, c = 2 * (e % H);
         if (r < r0) continue;
         double a = S.v[u].x, b = S.v[u].y;
         if (unit) {
@@ -179,7 +196,7 @@ __device__ __forceinline__ void stage_store(Smem<NB, IB> &sm, const Stage<NB, IB
     }
 #pragma unroll
     for (int u = 0; u < C::TPT; ++u) {
-        const int e = threadIdx.x + u * C::NT;
+        const int e = tidx() + u * C::NT;
         if (e < IB * IB / 2) reinterpret_cast<v2d *>(sm.Tl)[e] = S.t[u];
     }
 }
@@ -212,7 +229,7 @@ __device__ __forceinline__ void stage_load_rows(Stage<NB, IB> &S, const gdouble 
     }
 #pragma unroll
     for (int u = 0; u < C::TPT; ++u) {
-        const int e = threadIdx.x + u * C::NT;
+        const int e = tidx() + u * C::NT;
         const v2d t = reinterpret_cast<const gv2d *>(Tg)[e < TE ? e : TE - 1];
         S.t[u] = e < TE ? t : v2d{0.0, 0.0};
     }
@@ -238,7 +255,7 @@ __device__ __forceinline__ void stage_store_rows(Smem<NB, IB> &sm, const Stage<N
     }
 #pragma unroll
     for (int u = 0; u < C::TPT; ++u) {
-        const int e = threadIdx.x + u * C::NT;
+        const int e = tidx() + u * C::NT;
         if (e < IB * IB / 2) reinterpret_cast<v2d *>(sm.Tl)[e] = S.t[u];
     }
     // The wave reads these rows next: keep the compiler from moving its
@@ -343,7 +360,7 @@ __device__ __forceinline__ void load_top(double (&tv)[(Cfg<NB, IB>::EPT)], const
     using C = Cfg<NB, IB>;
 #pragma unroll
     for (int u = 0; u < C::EPT; ++u) {
-        const int e = threadIdx.x + u * C::NT, kr = e / WS, c = e % WS;
+        const int e = tidx() + u * C::NT, kr = e / WS, c = e % WS;
         tv[u] = (top != nullptr && c < ncol) ? top[(size_t)kr * ldtop + c] : 0.0;
     }
 }
@@ -357,7 +374,7 @@ __device__ __forceinline__ void store_top(const Smem<NB, IB> &sm, const double (
     using C = Cfg<NB, IB>;
 #pragma unroll
     for (int u = 0; u < C::EPT; ++u) {
-        const int e = threadIdx.x + u * C::NT, kr = e / WS, c = e % WS;
+        const int e = tidx() + u * C::NT, kr = e / WS, c = e % WS;
         if (c < ncol) top[(size_t)kr * ldtop + c] = tv[u] - sm.Wb[e];
     }
 }
@@ -379,7 +396,7 @@ __device__ __forceinline__ void apply_panel(Smem<NB, IB> &sm, Strip<NB, IB> &X, 
                                             const double (&tv)[Cfg<NB, IB>::EPT])
 {
     using C = Cfg<NB, IB>;
-    const int tid = threadIdx.x, w = wave_id();
+    const int tid = tidx(), w = wave_id();
     const int n = lane_id() & 15, g = lane_id() >> 4, rowbase = w * 32;
     const int ncol = cbn * 16;
     auto live = [&](int cb) { return !SKIP || cb < cbn; };
@@ -561,7 +578,7 @@ __device__ __forceinline__ void apply_panel_mx(Smem<NB, IB> &sm, Strip<NB, IB> &
     // it only for FP16, whose low parts would otherwise go subnormal.
     constexpr bool SCALED = true;
     constexpr double VSCALE = PREC == PREC_FP16X2 ? 4096.0 : 1.0;
-    const int tid = threadIdx.x, w = wave_id();
+    const int tid = tidx(), w = wave_id();
     const int n = lane_id() & 15, g = lane_id() >> 4, rowbase = w * 32;
     const bool active = rowbase >= rlo;
 
@@ -764,7 +781,7 @@ __device__ __forceinline__ void panel_factor(Smem<NB, IB> &sm, int c0)
     // the slots i RG < ib can lie on or above a column's diagonal and need
     // a per-row test; TSQRT's tile rows are all below its head.
     constexpr int NHEAD = TS ? 0 : (IB + RG - 1) / RG;
-    const int tid = threadIdx.x, c = tid / RG, rg = tid % RG;
+    const int tid = tidx(), c = tid / RG, rg = tid % RG;
     const int rbase = TS ? 0 : c0;
     double pr[RPT];
 #pragma unroll
@@ -897,7 +914,7 @@ template <int NB, int IB>
 __device__ __forceinline__ void build_t(Smem<NB, IB> &sm, int rlo, gdouble *Tg)
 {
     using C = Cfg<NB, IB>;
-    const int tid = threadIdx.x, w = wave_id();
+    const int tid = tidx(), w = wave_id();
     const int n = lane_id() & 15, g = lane_id() >> 4, rowbase = w * 32;
     d4 G[C::IBB][C::IBB];
 #pragma unroll
@@ -1042,7 +1059,7 @@ __device__ __forceinline__ void geqrt_panel(Smem<NB, IB> &sm, const MatDev &M, i
     constexpr int H = IB / 2;
 #pragma unroll
     for (int u = 0; u < C::VPT; ++u) {
-        const int e = threadIdx.x + u * C::NT, r = e / H, cc = 2 * (e % H);
+        const int e = tidx() + u * C::NT, r = e / H, cc = 2 * (e % H);
         if (r < c0) continue;
         v2d v = *reinterpret_cast<v2d *>(&sm.P[r * C::LDP + cc]);
         *reinterpret_cast<gv2d *>(tkk + (size_t)r * NB + c0 + cc) = v;
@@ -1098,24 +1115,24 @@ __device__ __forceinline__ void tsqrt_panel(Smem<NB, IB> &sm, const MatDev &M, i
         double tri[TRI];
 #pragma unroll
         for (int u = 0; u < TRI; ++u) {
-            const int e = min((int)threadIdx.x + u * C::NT, IB * IB - 1);
+            const int e = min(tidx() + u * C::NT, IB * IB - 1);
             tri[u] = tkk[(size_t)(c0 + e / IB) * NB + c0 + e % IB];
         }
 #pragma unroll
         for (int u = 0; u < TRI; ++u) {
-            const int e = threadIdx.x + u * C::NT, r = e / IB, c = e % IB;
+            const int e = tidx() + u * C::NT, r = e / IB, c = e % IB;
             if (e < IB * IB) sm.P[(NB + r) * C::LDP + c] = r <= c ? tri[u] : 0.0;
         }
     }
     __syncthreads();
     panel_factor<NB, IB, true>(sm, c0);
-    for (int e = threadIdx.x; e < IB * IB; e += C::NT) {
+    for (int e = tidx(); e < IB * IB; e += C::NT) {
         const int r = e / IB, c = e % IB;
         if (r <= c) tkk[(size_t)(c0 + r) * NB + c0 + c] = sm.P[(NB + r) * C::LDP + c];
     }
 #pragma unroll
     for (int u = 0; u < C::VPT; ++u) {
-        const int e = threadIdx.x + u * C::NT, r = e / H, cc = 2 * (e % H);
+        const int e = tidx() + u * C::NT, r = e / H, cc = 2 * (e % H);
         *reinterpret_cast<gv2d *>(tik + (size_t)r * NB + c0 + cc) =
             *reinterpret_cast<v2d *>(&sm.P[r * C::LDP + cc]);
     }
@@ -1451,7 +1468,7 @@ __device__ __forceinline__ void worker_loop(Smem<NB, IB> &sm, const SchedDev &S)
     __shared__ int s_next_queue;
     __shared__ int s_exit;
     __shared__ uint64_t s_tpop, s_trun;
-    const int tid = threadIdx.x;
+    const int tid = tidx();
     uint64_t rng = mix64(S.seed ^ (0x9e3779b97f4a7c15ULL * (blockIdx.x + 1)));
     const int xcd = xcd_id();
     // Idle polling goes to a few memory lines that every worker shares, so
