@@ -212,7 +212,13 @@ template <int NB>
 struct SmemG {
     double A[2][NB][LDX(KC)];  // L_ik, columns [kc, kc + KC)
     double B[2][NB][LDX(KC)];  // L_jk, same columns
+    int chain;                 // C kept in registers for the next update of the tile
 };
+
+// The update tile of a GSMM in accumulator layout: wave w (row half w / 2,
+// column half w % 2) holds a quarter of C in 16 x 16 blocks.
+template <int NB>
+using CAcc = d4[NB / 32][NB / 32];
 
 template <int NB>
 union Smem {
@@ -374,24 +380,32 @@ __device__ void task_trsm(SmemF<NB> &sm, double *Ti, const double *Tk)
 // GSMM(k, i, j): C <- C - Li Lj^T (C, Li, Lj row-major NB x NB tiles); with
 // diag (i == j) only the blocks on or below the diagonal, and of those only
 // the entries on or below it are stored.
+// Chaining: with have_c, C is already in acc (the previous update of the same
+// tile kept it) and is not loaded.  With next_ctr (the counter of the next
+// update of the tile, GSMM(k+1, i, j)) reading 1 at the end, this task is
+// the last one that update waits for: C stays in acc for it, is not stored,
+// and sm.chain says so (the caller then runs that update next on this
+// workgroup).  The arithmetic is the same either way.
 template <int NB>
-__device__ void task_gsmm(SmemG<NB> &sm, double *C, const double *Li, const double *Lj, bool diag)
+__device__ __forceinline__ void task_gsmm(SmemG<NB> &sm, CAcc<NB> &acc, double *C, const double *Li, const double *Lj,
+                                          bool diag, bool have_c, const int32_t *next_ctr)
 {
     constexpr int H = NB / 2, BW = H / 16, NCH = NB / KC, PER = NB * KC / NT;
     const int tid = opaque_tid(), w = tid >> 6, lane = tid & 63, n = lane & 15, g = lane >> 4;
     const int wr = w >> 1, wc = w & 1;
     const bool active = !diag || wr >= wc;
     auto live = [&](int a, int bb) { return !diag || wr > wc || a >= bb; };
-    d4 acc[BW][BW];
+    if (!have_c) {
 #pragma unroll
-    for (int a = 0; a < BW; ++a)
+        for (int a = 0; a < BW; ++a)
 #pragma unroll
-        for (int bb = 0; bb < BW; ++bb)
+            for (int bb = 0; bb < BW; ++bb)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                acc[a][bb][r] = (active && live(a, bb))
-                                    ? gld(&C[(size_t)(wr * H + 16 * a + 4 * r + g) * NB + wc * H + 16 * bb + n])
-                                    : 0.0;
+                for (int r = 0; r < 4; ++r)
+                    acc[a][bb][r] = (active && live(a, bb))
+                                        ? gld(&C[(size_t)(wr * H + 16 * a + 4 * r + g) * NB + wc * H + 16 * bb + n])
+                                        : 0.0;
+    }
     double ra[PER], rb[PER];
     auto load_chunk = [&](int kc) {
 #pragma unroll
@@ -434,7 +448,13 @@ __device__ void task_gsmm(SmemG<NB> &sm, double *C, const double *Li, const doub
         if (ch + 1 < NCH) store_chunk(buf ^ 1);
         __syncthreads();
     }
-    if (!active) return;
+    if (tid == 0)
+        sm.chain = next_ctr != nullptr &&
+                           __hip_atomic_load(next_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1
+                       ? 1
+                       : 0;
+    __syncthreads();
+    if (sm.chain || !active) return;
 #pragma unroll
     for (int a = 0; a < BW; ++a)
 #pragma unroll
@@ -448,12 +468,21 @@ __device__ void task_gsmm(SmemG<NB> &sm, double *C, const double *Li, const doub
         }
 }
 
+// With may_chain, a GSMM whose next update of the same tile is another GSMM
+// may keep C in acc for it (task_gsmm); have_c says acc holds C already.
 template <int NB>
-__device__ __forceinline__ void run_task(Smem<NB> &sm, const Sched &S, const CTask &t)
+__device__ __forceinline__ void run_task(Smem<NB> &sm, const Sched &S, const CTask &t, CAcc<NB> &acc, bool have_c,
+                                         bool may_chain)
 {
-    if (t.type == T_POTF2) task_potf2<NB>(sm.f, tile_at(S, t.k, t.k), t.k, S.status, S.minor);
-    else if (t.type == T_TRSM) task_trsm<NB>(sm.f, tile_at(S, t.i, t.k), tile_at(S, t.k, t.k));
-    else task_gsmm<NB>(sm.g, tile_at(S, t.i, t.j), tile_at(S, t.i, t.k), tile_at(S, t.j, t.k), t.i == t.j);
+    if (t.type == T_POTF2) {
+        task_potf2<NB>(sm.f, tile_at(S, t.k, t.k), t.k, S.status, S.minor);
+    } else if (t.type == T_TRSM) {
+        task_trsm<NB>(sm.f, tile_at(S, t.i, t.k), tile_at(S, t.k, t.k));
+    } else {
+        const int32_t *next = may_chain && t.j > t.k + 1 ? &S.counters[id_gsmm(S.p, t.k + 1, t.i, t.j)] : nullptr;
+        task_gsmm<NB>(sm.g, acc, tile_at(S, t.i, t.j), tile_at(S, t.i, t.k), tile_at(S, t.j, t.k), t.i == t.j, have_c,
+                      next);
+    }
 }
 
 // ------------------------------------------------------------- scheduler
@@ -551,19 +580,26 @@ template <int NB>
 __global__ __launch_bounds__(NT) void k_chol_worker(Sched S)
 {
     __shared__ Smem<NB> sm;
-    __shared__ int64_t s_id, s_next;
+    __shared__ int64_t s_id, s_next, s_chain;
     __shared__ int s_exit;
     const int tid = threadIdx.x;
     const int xcd = xcd_id();
     uint64_t rng = mix64(S.seed ^ (0x9e3779b97f4a7c15ULL * (blockIdx.x + 1)));
-    if (tid == 0) s_next = -1;
+    // The update tile a chained GSMM hands to the next update of its tile.
+    CAcc<NB> acc;
+    if (tid == 0) {
+        s_next = -1;
+        s_chain = -1;
+    }
     for (;;) {
         if (tid == 0) {
             int64_t id = s_next;
             int ex = 0;
             s_next = -1;
-            if (id >= 0) {
-                // A kept successor yields to a queued task of a higher level.
+            if (id >= 0 && id != s_chain) {
+                // A kept successor yields to a queued task of a higher level
+                // (not a chained update: its tile is in this workgroup's
+                // registers only).
                 const int lv = level_of(decode(S.p, id));
                 if (lv > 0) {
                     const int64_t hi = pop_upto(S, lv - 1, xcd, false, 0);
@@ -619,7 +655,7 @@ __global__ __launch_bounds__(NT) void k_chol_worker(Sched S)
         // acquire fence (it would invalidate the whole L2 of this XCD).
         const int64_t id = s_id;
         const CTask t = decode(S.p, id);
-        run_task<NB>(sm, S, t);
+        run_task<NB>(sm, S, t, acc, id == s_chain, true);
         // Every wave's agent-coherent stores complete before any counter of
         // a successor moves (in place of a release fence, which would write
         // back the whole L2 of this XCD).
@@ -628,6 +664,7 @@ __global__ __launch_bounds__(NT) void k_chol_worker(Sched S)
         if (tid < 64) {
             // A failed POTF2 releases nothing: the workers stop on the status.
             const bool failed = t.type == T_POTF2 && sm.f.fail;
+            const bool chained = t.type == T_GSMM && sm.g.chain;
             const int ns = failed ? 0 : nsucc(S.p, t);
             bool kept = false;
             for (int base = 0; base < ns; base += 64) {
@@ -651,6 +688,10 @@ __global__ __launch_bounds__(NT) void k_chol_worker(Sched S)
                     else push(S, queue_of(decode(S.p, sid)), sid);
                 }
             }
+            // A chained GSMM's one successor read 1 before this task's
+            // decrement, so it is ready now and kept (it is the next update
+            // of the same tile, whose C is in acc).
+            if (tid == 0) s_chain = chained ? s_next : -1;
             if (tid == 0 && !failed) __hip_atomic_fetch_add(S.done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
@@ -677,7 +718,8 @@ __global__ __launch_bounds__(NT) void k_chol_step(Sched S, int k)
         t.i = i;
         t.j = k + 1 + (int)r;
     }
-    run_task<NB>(sm, S, t);
+    CAcc<NB> acc;
+    run_task<NB>(sm, S, t, acc, false, false);
 }
 
 // ---------------------------------------------------------------- layout
