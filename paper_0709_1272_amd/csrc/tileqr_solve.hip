@@ -537,6 +537,9 @@ __global__ __launch_bounds__(2 * NB) void k_trmm(const double *tiles, int p, int
                                        },
                                        [&](int e, double v) { Rc[e / 32][e % 32] = v; });
             __syncthreads();
+            // Unrolled by 8 only: fully unrolled, the compiler hoists all 32
+            // steps' LDS reads ahead of the products and spills.
+#pragma unroll 8
             for (int kk = 0; kk < 32; ++kk) {
                 double a[4], b[4];
 #pragma unroll
