@@ -756,16 +756,15 @@ __device__ __forceinline__ void task_ssssm(Smem<IB> &sm, const Sched &S, int k, 
     const double *Z = tile_at(S, i, k);
     const double *LI = S.linv + ((size_t)k * S.p + i) * (size_t)IB * NB;
     const int pvl = gldi(&S.piv[((size_t)k * S.p + i) * NB + lane]);
-    {
-        double2 b[8];
-        load_regs(b, X2);
-        if (!have_x) {
-            double2 a[8];
-            load_regs(a, X1);
-            regs_to_lds(sm.X, a);
-        }
-        regs_to_lds(sm.Y, b);
-    }
+    // A_ij stays in registers for the whole task: wave w holds rows
+    // 16 w .. 16 w + 15 in the MFMA accumulator layout, yv[cb][r] = row
+    // 16 w + 4 r + g, column 16 cb + n.  A_kj is in LDS (sm.X).
+    d4 yv[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) yv[cb][r] = gld(&X2[(size_t)(16 * w + 4 * r + g) * NB + 16 * cb + n]);
+    if (!have_x) load_tile(sm.X, X1);
     // Panel operands: li[h][t] = L_up^{-1}[16 h + n][KS g + t] and
     // zw[t] = L_ik[16 w + n][l0 + KS g + t] (k-slot g of step t is panel row
     // KS g + t in both products).
@@ -787,47 +786,29 @@ __device__ __forceinline__ void task_ssssm(Smem<IB> &sm, const Sched &S, int k, 
         const bool more = l0 + IB < NB;
         double lin[NH][KS], zwn[KS];
         if (more) fetch(l0 + IB, lin, zwn);
-        if (g == 0) {
-            int rt[IB];
-            uint64_t seen = 0;
-            bool dup = false;
+        // TSTRF's row exchanges, in their order: row l0 + t of A_kj with row
+        // rt of A_ij.  The wave holding row rt swaps it with the LDS row; each
+        // A_kj row is touched by one step only, and the steps that touch one
+        // A_ij row run in order on the wave that holds it.
 #pragma unroll
-            for (int t = 0; t < IB; ++t) {
-                const int pq = __builtin_amdgcn_readlane(pvl, l0 + t);
-                rt[t] = pq >= NB ? (pq - NB) & (NB - 1) : -1;
-                if (rt[t] >= 0) {
-                    dup = dup || ((seen >> rt[t]) & 1);
-                    seen |= 1ull << rt[t];
-                }
-            }
-            if (!dup) {
+        for (int t = 0; t < IB; ++t) {
+            const int pq = __builtin_amdgcn_readlane(pvl, l0 + t);
+            if (pq < NB) continue;
+            const int rt = (pq - NB) & (NB - 1);
+            if (w != rt >> 4 || g != (rt & 3)) continue;
+            const int r = (rt & 15) >> 2;
 #pragma unroll
-                for (int t0 = 0; t0 < IB; t0 += 8) {
-                    double xv[8], yv[8];
-#pragma unroll
-                    for (int t = 0; t < 8; ++t)
-                        if (rt[t0 + t] >= 0) {
-                            xv[t] = sm.X[l0 + t0 + t][col];
-                            yv[t] = sm.Y[rt[t0 + t]][col];
-                        }
-#pragma unroll
-                    for (int t = 0; t < 8; ++t)
-                        if (rt[t0 + t] >= 0) {
-                            sm.X[l0 + t0 + t][col] = yv[t];
-                            sm.Y[rt[t0 + t]][col] = xv[t];
-                        }
-                }
-            } else {
-#pragma unroll
-                for (int t = 0; t < IB; ++t)
-                    if (rt[t] >= 0) {
-                        const double x = sm.X[l0 + t][col], y = sm.Y[rt[t]][col];
-                        sm.X[l0 + t][col] = y;
-                        sm.Y[rt[t]][col] = x;
-                    }
+            for (int cb = 0; cb < 4; ++cb) {
+                const double x = sm.X[l0 + t][16 * cb + n];
+                double y;
+                if (r == 0) { y = yv[cb][0]; yv[cb][0] = x; }
+                else if (r == 1) { y = yv[cb][1]; yv[cb][1] = x; }
+                else if (r == 2) { y = yv[cb][2]; yv[cb][2] = x; }
+                else { y = yv[cb][3]; yv[cb][3] = x; }
+                sm.X[l0 + t][16 * cb + n] = y;
             }
         }
-        wave_sync();
+        __syncthreads();
         {
             double xb[KS];
 #pragma unroll
@@ -842,6 +823,8 @@ __device__ __forceinline__ void task_ssssm(Smem<IB> &sm, const Sched &S, int k, 
             }
         }
         __syncthreads();
+        // A_ij -= L_ik[:, panel] X_P.  The next panel's exchanges and product
+        // touch other rows of A_kj, so no barrier follows.
         {
             double xb[4][KS];
 #pragma unroll
@@ -849,17 +832,10 @@ __device__ __forceinline__ void task_ssssm(Smem<IB> &sm, const Sched &S, int k, 
 #pragma unroll
                 for (int t = 0; t < KS; ++t) xb[cb][t] = sm.X[l0 + KS * g + t][16 * cb + n];
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb) {
-                d4 acc;
+            for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) acc[r] = sm.Y[16 * w + 4 * r + g][16 * cb + n];
-#pragma unroll
-                for (int t = 0; t < KS; ++t) acc = mfma(-zw[t], xb[cb][t], acc);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) sm.Y[16 * w + 4 * r + g][16 * cb + n] = acc[r];
-            }
+                for (int t = 0; t < KS; ++t) yv[cb] = mfma(-zw[t], xb[cb][t], yv[cb]);
         }
-        __syncthreads();
         if (more) {
 #pragma unroll
             for (int h = 0; h < NH; ++h)
@@ -873,7 +849,10 @@ __device__ __forceinline__ void task_ssssm(Smem<IB> &sm, const Sched &S, int k, 
         sm.chain = may_chain && i + 1 < S.p && gldi(&S.counters[id_ssssm(S.p, k, i + 1, j)]) == 1 ? 1 : 0;
     __syncthreads();
     if (!sm.chain) store_tile(X1, sm.X);
-    store_tile(X2, sm.Y);
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) gst(&X2[(size_t)(16 * w + 4 * r + g) * NB + 16 * cb + n], yv[cb][r]);
 }
 
 template <int IB>
