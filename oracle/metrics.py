@@ -1,7 +1,7 @@
 """Error measures of the oracle: TEST INFRASTRUCTURE ONLY.
 
 Plain numpy, FP64, one definition per function, no blocking or reordering.
-They judge a factorisation or a solution, whichever path produced it:
+They measure a factorisation or a solution, whichever path produced it:
 
 * ``r_diff``     ||D_t R_t - D_r R_r||_F / ||R_r||_F with D = diag(sign R_jj)
                  and sign(0) = +1.  R of a full-rank matrix is unique up to
