@@ -62,6 +62,26 @@ typedef struct {
 int tilechol_factor(int64_t n, double *A, int64_t lda, int64_t nb, const tileqr_opts *opts,
                     tilechol_info *info);
 
+/*
+ * X with A X = B, from the factor tilechol_factor left in L (the lower
+ * triangle of the n x n column-major array L, leading dimension
+ * ldl >= max(1, n); its strict upper triangle is not read): the forward
+ * solve L Y = B, then the back solve L^T X = Y -- the use of the factor
+ * L L^T = A of Section 3.1 (LAPACK's DPOTRS).  B (n x nrhs, leading
+ * dimension ldb >= max(1, n)) is overwritten with X.  Both solves run on
+ * FP64 MFMA by 64-row blocks over nb x nb tiles of L^T (nb 64 or 128, or 0 to
+ * choose as tilechol_factor does; any nb works with any factor).
+ * opts (may be NULL): precision must be TILEQR_FP64 (else
+ * TILEQR_EUNSUPPORTED); stream orders the call; TILEQR_FLAG_ASYNC returns
+ * without waiting (status unchecked); spin_limit as for tileqr_factor_ex.
+ * Returns TILEQR_OK; TILEQR_ESINGULAR (an exact zero on the diagonal of L;
+ * B then holds no solution); TILEQR_ETIMEOUT; TILEQR_EHIP; TILEQR_ENOMEM; or
+ * -1 n, -2 nrhs, -3 L, -4 ldl, -5 B, -6 ldb, -7 nb, -8 opts for an invalid
+ * argument (nothing touched).
+ */
+int tilechol_solve(int64_t n, int64_t nrhs, const double *L, int64_t ldl, double *B, int64_t ldb, int64_t nb,
+                   const tileqr_opts *opts);
+
 /* Tasks of Algorithm 1 on a p x p tile grid (host only): returns the total
  * and, if counts != NULL, writes {POTF2, TRSM, GSMM} counts. */
 int64_t tilechol_dag_counts(int64_t p, int64_t *counts);

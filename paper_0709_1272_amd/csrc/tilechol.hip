@@ -803,6 +803,23 @@ __global__ void k_chol_status_init(int32_t *status, int32_t *minor)
     }
 }
 
+// R = L^T in the tile layout of the QR's triangular solves (row-major nb x nb
+// tiles, tile (i, j) at tiles + (j p + i) nb^2), tiles i <= j only:
+// R[r][c] = L[c][r] for r <= c < n, else 0.  L is the column-major factor,
+// its lower triangle read; consecutive threads read consecutive rows of one
+// column of L.
+__global__ __launch_bounds__(256) void k_chol_lt(const double *L, int64_t ldl, int64_t n, double *tiles, int nb, int p)
+{
+    const int64_t nb2 = (int64_t)nb * nb, total = (int64_t)p * p * nb2;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = e / nb2, w = e % nb2;
+        const int i = (int)(t % p), j = (int)(t / p);
+        if (i > j) continue;
+        const int64_t r = (int64_t)i * nb + w / nb, c = (int64_t)j * nb + w % nb;
+        tiles[e] = (r <= c && c < n) ? L[c + r * ldl] : 0.0;
+    }
+}
+
 // ------------------------------------------------------------------ host
 
 int64_t count_tasks(int64_t p, int64_t *counts)
@@ -1048,5 +1065,59 @@ extern "C" int tilechol_factor(int64_t n, double *A, int64_t lda, int64_t nb, co
         return TILEQR_ENOTSPD;
     }
     if (status & ST_TIMEOUT) return TILEQR_ETIMEOUT;
+    return TILEQR_OK;
+}
+
+extern "C" int tilechol_solve(int64_t n, int64_t nrhs, const double *L, int64_t ldl, double *B, int64_t ldb,
+                              int64_t nb, const tileqr_opts *opts)
+{
+    if (n < 0 || n > (int64_t)INT_MAX / 2) return -1;
+    if (nrhs < 0 || nrhs > (int64_t)INT_MAX / 2) return -2;
+    if (n > 0 && !L) return -3;
+    if (ldl < std::max<int64_t>(1, n)) return -4;
+    if (n > 0 && nrhs > 0 && !B) return -5;
+    if (ldb < std::max<int64_t>(1, n)) return -6;
+    if (nb != 0 && nb != 64 && nb != 128) return -7;
+    tileqr_opts o;
+    tileqr_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.precision < TILEQR_FP64 || o.precision > TILEQR_BF16X3) return -8;
+    if (o.precision != TILEQR_FP64) return TILEQR_EUNSUPPORTED;
+    if (nb == 0) nb = n <= 512 ? 64 : 128;
+    if (n == 0 || nrhs == 0) return TILEQR_OK;
+
+    std::lock_guard<std::mutex> lock(g_mu);
+    hipStream_t st = (hipStream_t)o.stream;
+    Workspace *W = workspace(st);
+    if (!W) return hip_fail(hipErrorNoDevice, "workspace");
+    const int p = (int)cdiv(n, nb);
+    const int ldt = (int)cdiv(nrhs, 32) * 32;
+    const int64_t rows = (int64_t)p * nb;
+    const int64_t flags_cap = trsm_flags_needed(n, ldt);
+    int rc;
+    if ((rc = W->tiles.ensure((size_t)p * p * nb * nb * sizeof(double)))) return rc;
+    if ((rc = W->rows.ensure((size_t)rows * ldt * sizeof(double)))) return rc;
+    if ((rc = W->tflags.ensure((size_t)flags_cap * sizeof(int32_t)))) return rc;
+    if ((rc = W->status.ensure(256))) return rc;
+    double *tiles = (double *)W->tiles.ptr, *Bt = (double *)W->rows.ptr;
+    int32_t *status = (int32_t *)W->status.ptr;
+    const int64_t spin = o.spin_limit > 0 ? o.spin_limit : (int64_t)1 << 24;
+
+    hipLaunchKernelGGL(k_chol_status_init, dim3(1), dim3(64), 0, st, status, status + 32);
+    const int64_t total = (int64_t)p * p * nb * nb;
+    hipLaunchKernelGGL(k_chol_lt, dim3((unsigned)std::min<int64_t>(8192, (total + 255) / 256)), dim3(256), 0, st, L,
+                       ldl, n, tiles, (int)nb, p);
+    TQ_HIP(hipGetLastError());
+    TQ_HIP(launch_cm2rows(B, ldb, n, nrhs, Bt, rows, ldt, st));
+    // L Y = B is R^T Y = B, then L^T X = Y is R X = Y.
+    TQ_HIP(launch_trsm((int)nb, tiles, p, n, Bt, ldt, false, (int *)W->tflags.ptr, flags_cap, status, spin, st));
+    TQ_HIP(launch_trsm((int)nb, tiles, p, n, Bt, ldt, true, (int *)W->tflags.ptr, flags_cap, status, spin, st));
+    TQ_HIP(launch_rows2cm(B, ldb, n, nrhs, Bt, ldt, st));
+    if (o.flags & TILEQR_FLAG_ASYNC) return TILEQR_OK;
+    TQ_HIP(hipMemcpyAsync(W->host_small, status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    TQ_HIP(hipStreamSynchronize(st));
+    const int32_t s0 = *(const int32_t *)W->host_small;
+    if (s0 & STATUS_SINGULAR) return TILEQR_ESINGULAR;
+    if (s0 & STATUS_TIMEOUT) return TILEQR_ETIMEOUT;
     return TILEQR_OK;
 }

@@ -18,6 +18,8 @@ _i64 = ctypes.c_int64
 _SIGS = {
     "tilechol_factor": (ctypes.c_int, [_i64, ctypes.c_void_p, _i64, _i64, ctypes.POINTER(_tq.Opts),
                                        ctypes.POINTER(CholInfo)]),
+    "tilechol_solve": (ctypes.c_int, [_i64, _i64, ctypes.c_void_p, _i64, ctypes.c_void_p, _i64, _i64,
+                                      ctypes.POINTER(_tq.Opts)]),
     "tilechol_dag_counts": (_i64, [_i64, ctypes.POINTER(_i64)]),
     "tilechol_dag_selfcheck": (ctypes.c_int, [_i64, _i64, ctypes.c_uint64]),
 }
@@ -33,6 +35,11 @@ def factor(n, A, lda, nb=0, o=None, info=None):
     """tilechol_factor on a device pointer; returns the status."""
     return _L.tilechol_factor(n, A, lda, nb, ctypes.byref(o) if o is not None else None,
                               ctypes.byref(info) if info is not None else None)
+
+
+def solve(n, nrhs, L, ldl, B, ldb, nb=0, o=None):
+    """tilechol_solve on device pointers (B overwritten with X); returns the status."""
+    return _L.tilechol_solve(n, nrhs, L, ldl, B, ldb, nb, ctypes.byref(o) if o is not None else None)
 
 
 def dag_counts(p):

@@ -175,3 +175,113 @@ def test_full_size_sampled(tq, tc, n):
     est = float(torch.linalg.norm(AZ - W) / k ** 0.5 / torch.linalg.norm(A))
     print(f"n={n}: ||A - L L^T||_F / ||A||_F estimate {est:.2e}")
     assert est <= 1e-14
+
+
+def solve_on_device(tq, tc, F, B, nb=0, ldl=None, ldb=None, **opt):
+    """tilechol_solve with the factored array F (host) and right-hand sides B;
+    returns (status, X)."""
+    n, nrhs = B.shape
+    ldl = ldl or n
+    ldb = ldb or n
+    Fp = np.zeros((ldl, n))
+    Fp[:n] = F
+    Bp = np.zeros((ldb, nrhs))
+    Bp[:n] = B
+    Lt = tq.to_device(Fp)
+    Bt = tq.to_device(Bp)
+    rc = tc.solve(n, nrhs, Lt.data_ptr(), ldl, Bt.data_ptr(), ldb, nb, tq.opts(**opt))
+    torch.cuda.synchronize()
+    Xp = tq.to_host(Bt)
+    assert np.array_equal(Xp[n:], Bp[n:])          # rows beyond n untouched
+    return rc, Xp[:n]
+
+
+@pytest.mark.parametrize("n,nrhs,nb,kappa", [(64, 1, 64, 1e2), (100, 3, 64, 1e3), (333, 40, 64, 1e4),
+                                             (517, 33, 128, 1e6), (1024, 64, 128, 1e3), (2000, 5, 128, 1e6),
+                                             (300, 70, 128, 1e2)])
+def test_solve_vs_oracle(tq, tc, n, nrhs, nb, kappa):
+    # X from tilechol_solve with the GPU factor against the oracle's forward
+    # and back substitution (oracle_potrs_lower) with the same L: normwise
+    # within c n u kappa (both solve the same triangles, in other orders);
+    # and the backward error ||A X - B||_F / (||A||_F ||X||_F).
+    A = synth.spd_matrix(n + 17, n, kappa)
+    rc, F, _ = factor(tq, tc, A, nb)
+    assert rc == tq.OK
+    B = np.random.default_rng(n + nrhs).standard_normal((n, nrhs))
+    rc, X = solve_on_device(tq, tc, F, B, nb)
+    assert rc == tq.OK
+    Xo = oracle.potrs(np.tril(F), B)
+    err = np.linalg.norm(X - Xo) / np.linalg.norm(Xo)
+    bwd = np.linalg.norm(A @ X - B) / (np.linalg.norm(A) * np.linalg.norm(X))
+    print(f"n={n} nrhs={nrhs} nb={nb} kappa={kappa:.0e}: |X - X_oracle|/|X| = {err:.2e}, backward {bwd:.2e}")
+    assert err <= 8 * n * EPS * kappa
+    assert bwd <= 1e-14
+
+
+def test_solve_tile_size_and_leading_dimensions(tq, tc):
+    # Any tile size with any factor; leading dimensions above n.
+    n, nrhs = 450, 9
+    A = synth.spd_matrix(21, n, 1e4)
+    rc, F, _ = factor(tq, tc, A, 128)
+    assert rc == tq.OK
+    B = np.random.default_rng(5).standard_normal((n, nrhs))
+    rc1, X1 = solve_on_device(tq, tc, F, B, 64)
+    rc2, X2 = solve_on_device(tq, tc, F, B, 128, ldl=n + 13, ldb=n + 3)
+    rc3, X3 = solve_on_device(tq, tc, F, B, 0)
+    assert rc1 == rc2 == rc3 == tq.OK
+    Xo = oracle.potrs(np.tril(F), B)
+    for X in (X1, X2, X3):
+        assert np.linalg.norm(X - Xo) <= 8 * n * EPS * 1e4 * np.linalg.norm(Xo)
+    assert np.array_equal(X3, X1)                   # n <= 512 chooses nb 64
+
+
+def test_solve_zero_diagonal_and_arguments(tq, tc):
+    n = 200
+    A = synth.spd_matrix(22, n, 10.0)
+    rc, F, _ = factor(tq, tc, A, 64)
+    assert rc == tq.OK
+    F0 = F.copy()
+    F0[130, 130] = 0.0
+    rc, _ = solve_on_device(tq, tc, F0, np.ones((n, 2)), 64)
+    assert rc == tq.ESINGULAR
+    Lt = tq.to_device(F)
+    Bt = tq.to_device(np.ones((n, 2)))
+    L, B = Lt.data_ptr(), Bt.data_ptr()
+    assert tc.solve(-1, 2, L, n, B, n) == -1
+    assert tc.solve(n, -1, L, n, B, n) == -2
+    assert tc.solve(n, 2, 0, n, B, n) == -3
+    assert tc.solve(n, 2, L, n - 1, B, n) == -4
+    assert tc.solve(n, 2, L, n, 0, n) == -5
+    assert tc.solve(n, 2, L, n, B, n - 1) == -6
+    assert tc.solve(n, 2, L, n, B, n, 96) == -7
+    assert tc.solve(n, 2, L, n, B, n, 0, tq.opts(precision=9)) == -8
+    assert tc.solve(n, 2, L, n, B, n, 0, tq.opts(precision=tq.BF16X3)) == tq.EUNSUPPORTED
+    assert tc.solve(0, 2, 0, 1, 0, 1) == tq.OK
+    assert tc.solve(n, 0, L, n, 0, n) == tq.OK
+    torch.cuda.synchronize()
+    assert np.array_equal(tq.to_host(Bt), np.ones((n, 2)))    # nothing touched
+
+
+def test_solve_full_size(tq, tc):
+    # 16384^2, 16 right-hand sides: the backward error of X, with the
+    # products summed with compensation on the device.
+    from gpu_probes import compensated_matmul
+    n, nrhs = 16384, 16
+    A = synth.spd_matrix_device(3, n, 1e6, device="cuda")      # symmetric: rows = columns
+    Lt = A.clone()
+    info = tc.CholInfo()
+    assert tc.factor(n, Lt.data_ptr(), n, 128, tq.opts(), info) == tq.OK
+    g = torch.Generator(device="cuda")
+    g.manual_seed(9)
+    Bt = torch.randn((nrhs, n), generator=g, device="cuda", dtype=torch.float64)   # B column-major
+    Xt = Bt.clone()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    rc = tc.solve(n, nrhs, Lt.data_ptr(), n, Xt.data_ptr(), n, 128, tq.opts())
+    e1.record()
+    torch.cuda.synchronize()
+    assert rc == tq.OK
+    AX = compensated_matmul(Xt, A)                   # (A X)^T, A symmetric
+    bwd = float(torch.linalg.norm(AX - Bt) / (torch.linalg.norm(A) * torch.linalg.norm(Xt)))
+    print(f"n={n} nrhs={nrhs}: solve {e0.elapsed_time(e1):.2f} ms, backward error {bwd:.2e}")
+    assert bwd <= 1e-14
