@@ -71,6 +71,40 @@ size_t tilelu_piv_size(int64_t n, int64_t nb);
 int tilelu_factor(int64_t n, double *A, int64_t lda, int64_t nb, int64_t ib, double *Lup, int32_t *piv,
                   const tileqr_opts *opts, tilelu_info *info);
 
+typedef struct {
+    int iterations;       /* refinement corrections applied                      */
+    int converged;        /* 1 if the backward error reached tol                 */
+    double eta;           /* the returned X's largest (over the columns)
+                             ||b - A x||_inf / (||A||_inf ||x||_inf)             */
+    int64_t minor;        /* TILEQR_ESINGULAR from the factorisation: as in
+                             tilelu_info                                        */
+} tilelu_solve_info;
+
+/*
+ * X with A X = B for the n x n column-major A (lda >= max(1, n), not
+ * modified) and 1 <= nrhs <= 64 right-hand sides B (ldb >= max(1, n)): the
+ * tiled LU of Algorithm 3 with tiled pairwise pivoting (nb 64, inner panels
+ * ib 16 or 32, 0 choosing 16) computed into the library's workspace, the
+ * factor's transformations applied to B in the factorisation's order
+ * (GESSM(k) on row block k, then SSSSM(k, i) on row blocks k and i), the back
+ * solve with U, then classical refinement with FP64 residuals: Section 3.2.4
+ * notes that tiled pairwise pivoting is not guaranteed stable and advises
+ * checking the backward error ||b - A x||_inf / (||A||_inf ||x||_inf) and
+ * refining.  Refinement stops at opts->tol (default 1e-14) for every column,
+ * after opts->max_iter corrections (<= 64), or after two corrections that
+ * fail to halve the error; the best iterate goes to X (ldx >= max(1, n)).
+ * opts (may be NULL): precision must be TILEQR_FP64 and TILEQR_FLAG_ASYNC is
+ * not accepted (TILEQR_EUNSUPPORTED: the refinement decides on the host);
+ * stream, workers, spin_limit, TILEQR_FLAG_SERIAL / _SHUFFLE as for
+ * tilelu_factor.  info (may be NULL): host memory.
+ * Returns TILEQR_OK; TILEQR_ENOCONV (best iterate in X); TILEQR_ESINGULAR;
+ * TILEQR_ENONFINITE; TILEQR_ETIMEOUT; TILEQR_EHIP; TILEQR_ENOMEM; or -1 n,
+ * -2 nrhs, -3 A, -4 lda, -5 B, -6 ldb, -7 X, -8 ldx, -9 ib, -10 opts for an
+ * invalid argument (nothing written).
+ */
+int tilelu_solve(int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B, int64_t ldb, double *X,
+                 int64_t ldx, int64_t ib, const tileqr_opts *opts, tilelu_solve_info *info);
+
 /* Tasks of Algorithm 3 on a p x p tile grid (host only): the total, and
  * {GETRF, GESSM, TSTRF, SSSSM} counts if counts != NULL. */
 int64_t tilelu_dag_counts(int64_t p, int64_t *counts);

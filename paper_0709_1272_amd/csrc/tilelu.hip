@@ -1102,6 +1102,34 @@ __global__ __launch_bounds__(NT, IB == 16 ? 2 : 1) void k_lu_step(Sched S, int k
     run_task(sm, S, t);
 }
 
+// Algorithm 3's transformations of a finished factor applied to tile column
+// j (right-hand sides, j = p: the tile array has that extra column), in the
+// factorisation's order: GESSM(k, j), then SSSSM(k, i, j) for i = k+1 ..
+// p-1, step after step, on one workgroup.  Each task stores its tiles and
+// the next reads them back once those stores have completed.
+template <int IB>
+__global__ __launch_bounds__(NT, 1) void k_lu_forward(Sched S, int j)
+{
+    __shared__ Smem<IB> sm;
+    for (int k = 0; k < S.p; ++k) {
+        task_gessm<IB>(sm, S, k, j);
+        stores_done();
+        __syncthreads();
+        for (int i = k + 1; i < S.p; ++i) {
+            task_ssssm<IB>(sm, S, k, i, j, false, false);
+            stores_done();
+            __syncthreads();
+        }
+    }
+}
+
+hipError_t launch_forward(const Sched &S, int j, hipStream_t st)
+{
+    if (S.ib == 16) hipLaunchKernelGGL((k_lu_forward<16>), dim3(1), dim3(NT), 0, st, S, j);
+    else hipLaunchKernelGGL((k_lu_forward<32>), dim3(1), dim3(NT), 0, st, S, j);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- layout
 
 // Column-major n x n A -> tiles (row-major inside); beyond n the diagonal
@@ -1313,31 +1341,16 @@ extern "C" int tilelu_dag_selfcheck(int64_t p64, int64_t trials, uint64_t seed)
     return 0;
 }
 
-extern "C" int tilelu_factor(int64_t n, double *A, int64_t lda, int64_t nb, int64_t ib, double *Lup, int32_t *piv,
-                             const tileqr_opts *opts, tilelu_info *info)
-{
-    if (n < 0 || n > (int64_t)INT_MAX / 2) return -1;
-    if (n > 0 && !A) return -2;
-    if (lda < std::max<int64_t>(1, n)) return -3;
-    if (nb <= 0) return -4;
-    if (ib <= 0 || nb % ib != 0) return -5;
-    if (n > 0 && (!Lup || ((uintptr_t)Lup & 15))) return -6;
-    if (n > 0 && !piv) return -7;
-    tileqr_opts o;
-    tileqr_opts_default(&o);
-    if (opts) o = *opts;
-    if (o.precision < TILEQR_FP64 || o.precision > TILEQR_BF16X3) return -8;
-    if (info) {
-        info->minor = 0;
-        info->ms_factor = info->ms_worker = 0.0;
-    }
-    if (nb != tl::NB || (ib != 16 && ib != 32) || o.precision != TILEQR_FP64) return TILEQR_EUNSUPPORTED;
-    if (n == 0) return TILEQR_OK;
+namespace {
 
-    std::lock_guard<std::mutex> lock(g_mu);
-    hipStream_t st = (hipStream_t)o.stream;
-    Workspace *W = workspace(st);
-    if (!W) return hip_fail(hipErrorNoDevice, "workspace");
+// The factorisation of the column-major n x n matrix A into W's tiles (with
+// `extra` further tile columns allocated after the p x p grid, which the
+// factorisation does not touch): scheduler set-up, layout in, workers.  On
+// return S describes the factor; the status words are not read back.  With
+// `timing`, W->ev[0..2] are recorded around the layout and the workers.
+int lu_run(Workspace *W, const double *A, int64_t lda, int64_t n, int64_t nb, int64_t ib, int extra, double *Lup,
+           int32_t *piv, const tileqr_opts &o, bool timing, hipStream_t st, tl::Sched &S)
+{
     const int p = (int)cdiv(n, nb);
     int64_t cnt[4];
     const int64_t total = tl::count_tasks(p, cnt);
@@ -1356,17 +1369,15 @@ extern "C" int tilelu_factor(int64_t n, double *A, int64_t lda, int64_t nb, int6
     off[0] = 0;
     for (int q = 0; q < tl::NQ; ++q) off[q + 1] = off[q] + std::max<int64_t>(cap[q], 1);
     int rc;
-    if ((rc = W->tiles.ensure((size_t)p * p * nb * nb * sizeof(double)))) return rc;
+    if ((rc = W->tiles.ensure((size_t)p * (p + extra) * nb * nb * sizeof(double)))) return rc;
     if ((rc = W->luinv.ensure((size_t)p * p * ib * nb * sizeof(double)))) return rc;
     if ((rc = W->status.ensure(256))) return rc;
     if ((rc = W->sched.counters.ensure((size_t)nid * sizeof(int32_t)))) return rc;
     if ((rc = W->sched.qslot.ensure((size_t)off[tl::NQ] * sizeof(int32_t)))) return rc;
     if ((rc = W->sched.qctl.ensure((size_t)(2 * tl::NQ * tl::QSTRIDE + 64) * sizeof(uint32_t)))) return rc;
-    const bool timing = (o.flags & TILEQR_FLAG_TIMING) && !(o.flags & TILEQR_FLAG_ASYNC) && info;
     if (timing && !W->ev[0])
         for (auto &e : W->ev) TQ_HIP(hipEventCreate(&e));
 
-    tl::Sched S;
     S.tiles = (double *)W->tiles.ptr;
     S.lup = Lup;
     S.linv = (double *)W->luinv.ptr;
@@ -1402,8 +1413,43 @@ extern "C" int tilelu_factor(int64_t n, double *A, int64_t lda, int64_t nb, int6
     }
     TQ_HIP(hipGetLastError());
     if (timing) TQ_HIP(hipEventRecord(W->ev[1], st));
-    hipError_t e = ib == 16 ? tl::launch_run<16>(S, serial, workers, st) : tl::launch_run<32>(S, serial, workers, st);
+    const hipError_t e = ib == 16 ? tl::launch_run<16>(S, serial, workers, st) : tl::launch_run<32>(S, serial, workers, st);
     if (e != hipSuccess) return hip_fail(e, "tilelu worker");
+    return 0;
+}
+
+}  // namespace
+
+extern "C" int tilelu_factor(int64_t n, double *A, int64_t lda, int64_t nb, int64_t ib, double *Lup, int32_t *piv,
+                             const tileqr_opts *opts, tilelu_info *info)
+{
+    if (n < 0 || n > (int64_t)INT_MAX / 2) return -1;
+    if (n > 0 && !A) return -2;
+    if (lda < std::max<int64_t>(1, n)) return -3;
+    if (nb <= 0) return -4;
+    if (ib <= 0 || nb % ib != 0) return -5;
+    if (n > 0 && (!Lup || ((uintptr_t)Lup & 15))) return -6;
+    if (n > 0 && !piv) return -7;
+    tileqr_opts o;
+    tileqr_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.precision < TILEQR_FP64 || o.precision > TILEQR_BF16X3) return -8;
+    if (info) {
+        info->minor = 0;
+        info->ms_factor = info->ms_worker = 0.0;
+    }
+    if (nb != tl::NB || (ib != 16 && ib != 32) || o.precision != TILEQR_FP64) return TILEQR_EUNSUPPORTED;
+    if (n == 0) return TILEQR_OK;
+
+    std::lock_guard<std::mutex> lock(g_mu);
+    hipStream_t st = (hipStream_t)o.stream;
+    Workspace *W = workspace(st);
+    if (!W) return hip_fail(hipErrorNoDevice, "workspace");
+    const bool timing = (o.flags & TILEQR_FLAG_TIMING) && !(o.flags & TILEQR_FLAG_ASYNC) && info;
+    tl::Sched S;
+    int rc;
+    if ((rc = lu_run(W, A, lda, n, nb, ib, 0, Lup, piv, o, timing, st, S))) return rc;
+    const int p = S.p;
     if (timing) TQ_HIP(hipEventRecord(W->ev[2], st));
     hipLaunchKernelGGL(tl::k_lu_out, dim3((unsigned)((int64_t)p * p)), dim3(256), 0, st, A, lda, n, S.tiles, p,
                        S.status);
@@ -1428,4 +1474,133 @@ extern "C" int tilelu_factor(int64_t n, double *A, int64_t lda, int64_t nb, int6
     }
     if (status & tl::ST_TIMEOUT) return TILEQR_ETIMEOUT;
     return TILEQR_OK;
+}
+
+extern "C" int tilelu_solve(int64_t n, int64_t nrhs, const double *A, int64_t lda, const double *B, int64_t ldb,
+                            double *X, int64_t ldx, int64_t ib, const tileqr_opts *opts, tilelu_solve_info *info)
+{
+    if (n < 0 || n > (int64_t)INT_MAX / 2) return -1;
+    if (nrhs < 0 || nrhs > tl::NB) return -2;
+    if (n > 0 && !A) return -3;
+    if (lda < std::max<int64_t>(1, n)) return -4;
+    if (n > 0 && nrhs > 0 && !B) return -5;
+    if (ldb < std::max<int64_t>(1, n)) return -6;
+    if (n > 0 && nrhs > 0 && !X) return -7;
+    if (ldx < std::max<int64_t>(1, n)) return -8;
+    if (ib != 0 && ib != 16 && ib != 32) return -9;
+    tileqr_opts o;
+    tileqr_opts_default(&o);
+    if (opts) o = *opts;
+    if (o.precision < TILEQR_FP64 || o.precision > TILEQR_BF16X3 || o.max_iter < 0 || o.max_iter > 64) return -10;
+    if (info) {
+        info->iterations = 0;
+        info->converged = 0;
+        info->eta = 0.0;
+        info->minor = 0;
+    }
+    if (o.precision != TILEQR_FP64 || (o.flags & TILEQR_FLAG_ASYNC)) return TILEQR_EUNSUPPORTED;
+    if (ib == 0) ib = 16;
+    if (n == 0 || nrhs == 0) {
+        if (info) info->converged = 1;
+        return TILEQR_OK;
+    }
+    const double tol = o.tol > 0.0 ? o.tol : 1e-14;
+
+    std::lock_guard<std::mutex> lock(g_mu);
+    hipStream_t st = (hipStream_t)o.stream;
+    Workspace *W = workspace(st);
+    if (!W) return hip_fail(hipErrorNoDevice, "workspace");
+    const int64_t nb = tl::NB;
+    const int p = (int)cdiv(n, nb);
+    const int ldt = (int)nb;   // the right-hand sides' tile column: row blocks of nb rows, nb wide
+    const size_t slot = (size_t)p * nb * nb;
+    const int64_t part_cap = std::max<int64_t>(n * 32 * 16, 1 << 20);
+    constexpr int64_t SMALL = 1024, SMALL_CAP = (int64_t)COLSQ_BLOCKS * 64;
+    const int64_t flags_cap = trsm_flags_needed(n, ldt);
+    int rc;
+    if ((rc = W->lulup.ensure(tilelu_lup_size(n, nb, ib) * sizeof(double)))) return rc;
+    if ((rc = W->lupiv.ensure(tilelu_piv_size(n, nb) * sizeof(int32_t)))) return rc;
+    if ((rc = W->solve.ensure(3 * slot * sizeof(double)))) return rc;
+    if ((rc = W->part.ensure((size_t)part_cap * sizeof(double)))) return rc;
+    if ((rc = W->misc.ensure((size_t)(SMALL + SMALL_CAP) * sizeof(double)))) return rc;
+    if ((rc = W->tflags.ensure((size_t)flags_cap * sizeof(int32_t)))) return rc;
+
+    tl::Sched S;
+    if ((rc = lu_run(W, A, lda, n, nb, ib, 1, (double *)W->lulup.ptr, (int32_t *)W->lupiv.ptr, o, false, st, S)))
+        return rc;
+    int32_t *tst = S.status + 48;   // the triangular solves' status word (STATUS_* bits)
+    TQ_HIP(hipMemsetAsync(tst, 0, sizeof(int32_t), st));
+    TQ_HIP(hipMemcpyAsync(W->host_small, S.status, 33 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    TQ_HIP(hipStreamSynchronize(st));
+    {
+        const int32_t *hs = (const int32_t *)W->host_small;
+        if (hs[0] & tl::ST_NONFINITE) return TILEQR_ENONFINITE;
+        if (hs[0] & tl::ST_SINGULAR) {
+            if (info) info->minor = hs[32];
+            return TILEQR_ESINGULAR;
+        }
+        if (hs[0] & tl::ST_TIMEOUT) return TILEQR_ETIMEOUT;
+    }
+    double *Bc = S.tiles + (size_t)p * p * nb * nb;   // tile column p
+    double *Xr = (double *)W->solve.ptr, *Rr = Xr + slot, *Xb = Rr + slot;
+    double *small = (double *)W->misc.ptr, *part = (double *)W->part.ptr;
+    // Bc <- A^{-1} Bc: the factor's transformations, then U.
+    auto solve_bc = [&]() -> hipError_t {
+        hipError_t e = tl::launch_forward(S, p, st);
+        if (e != hipSuccess) return e;
+        return launch_trsm((int)nb, S.tiles, p, n, Bc, ldt, true, (int *)W->tflags.ptr, flags_cap, tst, S.spin_limit,
+                           st);
+    };
+    TQ_HIP(launch_norm_inf(A, lda, n, n, part, part_cap, small, st));
+    TQ_HIP(launch_cm2rows(B, ldb, n, nrhs, Bc, (int64_t)p * nb, ldt, st));
+    TQ_HIP(solve_bc());
+    TQ_HIP(hipMemcpyAsync(Xr, Bc, slot * sizeof(double), hipMemcpyDeviceToDevice, st));
+    // Classical refinement in FP64 (Section 3.2.4's check of the backward
+    // error, then corrections through the factor) until the largest
+    // ||b - A x||_inf / (||A||_inf ||x||_inf) over the columns is <= tol,
+    // max_iter corrections, or two corrections that fail to halve it; the
+    // best iterate is returned.
+    double best = INFINITY, prev = INFINITY;
+    int it = 0, stall = 0;
+    bool conv = false;
+    for (;;) {
+        TQ_HIP(launch_cm2rows(B, ldb, n, nrhs, Rr, (int64_t)p * nb, ldt, st));
+        TQ_HIP(launch_gemv_n(A, lda, n, n, Xr, ldt, (int)nrhs, -1.0, 1.0, Rr, part, part_cap, st));
+        TQ_HIP(launch_colmax(Rr, ldt, n, (int)nrhs, small + SMALL, SMALL_CAP, small + 256, st));
+        TQ_HIP(launch_colmax(Xr, ldt, n, (int)nrhs, small + SMALL, SMALL_CAP, small + 320, st));
+        TQ_HIP(hipMemcpyAsync(W->host_small, small, 384 * sizeof(double), hipMemcpyDeviceToHost, st));
+        TQ_HIP(hipMemcpyAsync(W->host_status, tst, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        TQ_HIP(hipStreamSynchronize(st));
+        if (*W->host_status & STATUS_SINGULAR) return TILEQR_ESINGULAR;
+        if (*W->host_status & STATUS_TIMEOUT) return TILEQR_ETIMEOUT;
+        const double *hs = W->host_small, normA = hs[0];
+        double eta = 0.0;
+        for (int c = 0; c < nrhs; ++c) {
+            const double r = hs[256 + c], d = normA * hs[320 + c];
+            eta = std::max(eta, d > 0.0 ? r / d : (r > 0.0 ? INFINITY : 0.0));
+        }
+        if (eta < best) {
+            best = eta;
+            TQ_HIP(hipMemcpyAsync(Xb, Xr, slot * sizeof(double), hipMemcpyDeviceToDevice, st));
+        }
+        if (eta <= tol) {
+            conv = true;
+            break;
+        }
+        stall = eta > 0.5 * prev ? stall + 1 : 0;
+        prev = eta;
+        if (it >= o.max_iter || stall >= 2) break;
+        ++it;
+        TQ_HIP(hipMemcpyAsync(Bc, Rr, slot * sizeof(double), hipMemcpyDeviceToDevice, st));
+        TQ_HIP(solve_bc());
+        TQ_HIP(launch_axpy_rows(Bc, Xr, ldt, n, (int)nrhs, 1, st));
+    }
+    TQ_HIP(launch_rows2cm(X, ldx, n, nrhs, Xb, ldt, st));
+    TQ_HIP(hipStreamSynchronize(st));
+    if (info) {
+        info->iterations = it;
+        info->converged = conv ? 1 : 0;
+        info->eta = best;
+    }
+    return conv ? TILEQR_OK : TILEQR_ENOCONV;
 }

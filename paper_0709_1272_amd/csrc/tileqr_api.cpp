@@ -744,6 +744,8 @@ extern "C" int tileqr_finalize(void)
             w->trace.release();
             w->misc.release();
             w->luinv.release();
+            w->lulup.release();
+            w->lupiv.release();
             w->rows.release();
             w->prog.release();
             w->tws.release();

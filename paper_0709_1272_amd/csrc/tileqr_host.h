@@ -73,6 +73,7 @@ struct Workspace {
     DevBuf tiles, status, trace, misc, rows, prog, tws, solve, part, tflags;
     DevBuf vsplit;                        // split images of V and T (split modes)
     DevBuf luinv;                         // tiled LU: the inverses of the L_up triangles
+    DevBuf lulup, lupiv;                  // tiled LU solve: its own L_up and pivots
     SchedBufs sched;                      // single-matrix calls
     // Batched calls keep their own buffers so that a captured graph stays
     // valid across single-matrix calls.

@@ -13,12 +13,19 @@ class LUInfo(ctypes.Structure):
     _fields_ = [("minor", ctypes.c_int64), ("ms_factor", ctypes.c_double), ("ms_worker", ctypes.c_double)]
 
 
+class LUSolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int), ("eta", ctypes.c_double),
+                ("minor", ctypes.c_int64)]
+
+
 _i64 = ctypes.c_int64
 _SIGS = {
     "tilelu_lup_size": (ctypes.c_size_t, [_i64, _i64, _i64]),
     "tilelu_piv_size": (ctypes.c_size_t, [_i64, _i64]),
     "tilelu_factor": (ctypes.c_int, [_i64, ctypes.c_void_p, _i64, _i64, _i64, ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.POINTER(_tq.Opts), ctypes.POINTER(LUInfo)]),
+    "tilelu_solve": (ctypes.c_int, [_i64, _i64, ctypes.c_void_p, _i64, ctypes.c_void_p, _i64, ctypes.c_void_p, _i64,
+                                    _i64, ctypes.POINTER(_tq.Opts), ctypes.POINTER(LUSolveInfo)]),
     "tilelu_dag_counts": (_i64, [_i64, ctypes.POINTER(_i64)]),
     "tilelu_dag_selfcheck": (ctypes.c_int, [_i64, _i64, ctypes.c_uint64]),
 }
@@ -28,6 +35,12 @@ for _name, (_res, _args) in _SIGS.items():
     _f.argtypes = _args
 
 EXPORTS = sorted(_SIGS)
+
+
+def solve(n, nrhs, A, lda, B, ldb, X, ldx, ib=0, o=None, info=None):
+    """tilelu_solve on device pointers; returns the status."""
+    return _L.tilelu_solve(n, nrhs, A, lda, B, ldb, X, ldx, ib, ctypes.byref(o) if o is not None else None,
+                           ctypes.byref(info) if info is not None else None)
 
 
 def lup_size(n, nb, ib):

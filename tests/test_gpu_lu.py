@@ -153,3 +153,116 @@ def test_full_size_backward_error(tq, tl, n):
     eta = eta_inf(A, xs, b)
     print(f"n={n}: eta_inf {eta:.2e}")
     assert eta <= 4 * n * EPS
+
+
+def lu_solve_gpu(tq, tl, A, B, ib=16, **opt):
+    n, nrhs = B.shape
+    At = tq.to_device(A)
+    Bt = tq.to_device(B)
+    Xt = torch.zeros_like(Bt)
+    info = tl.LUSolveInfo()
+    rc = tl.solve(n, nrhs, At.data_ptr(), n, Bt.data_ptr(), n, Xt.data_ptr(), n, ib, tq.opts(**opt), info)
+    torch.cuda.synchronize()
+    return rc, tq.to_host(Xt, n), info, tq.to_host(At, n), tq.to_host(Bt, n)
+
+
+@pytest.mark.parametrize("n,nrhs,ib", [(64, 1, 16), (100, 3, 16), (256, 5, 32), (333, 33, 16), (640, 64, 32),
+                                       (1024, 8, 16)])
+def test_solve_vs_oracle(tq, tl, n, nrhs, ib):
+    # tilelu_solve (factor, the factor's transformations on B, U, FP64
+    # refinement) against the oracle's Algorithm 3 and its unrefined solve,
+    # and against the exact solution of B = A X: the backward error
+    # ||b - A x||_inf / (||A||_inf ||x||_inf) of every column at the
+    # library's tolerance, the error in X within that of the oracle's
+    # solution or c n u kappa; A and B untouched.
+    A = synth.normal(n + 5, n, n)
+    Xtrue = np.random.default_rng(n + nrhs).standard_normal((n, nrhs))
+    B = A @ Xtrue
+    rc, X, info, A2, B2 = lu_solve_gpu(tq, tl, A, B, ib)
+    assert rc == tq.OK and info.converged == 1, (rc, info.iterations, info.eta)
+    assert np.array_equal(A2, A) and np.array_equal(B2, B)
+    Ap = padded(A)
+    Fo, Lupo, pivo, oinfo = oracle.tile_lu(Ap, NB, ib)
+    assert oinfo == 0
+    Bp = np.zeros((Ap.shape[0], nrhs))
+    Bp[:n] = B
+    Xo = oracle.tile_lu_solve(Fo, Lupo, pivo, NB, ib, Bp)[:n]
+    eta = max(eta_inf(A, X[:, c], B[:, c]) for c in range(nrhs))
+    eta_o = max(eta_inf(A, Xo[:, c], B[:, c]) for c in range(nrhs))
+    err = np.linalg.norm(X - Xtrue) / np.linalg.norm(Xtrue)
+    err_o = np.linalg.norm(Xo - Xtrue) / np.linalg.norm(Xtrue)
+    kappa = np.linalg.cond(A)
+    print(f"n={n} nrhs={nrhs} ib={ib}: {info.iterations} corrections, eta {eta:.2e} (library {info.eta:.2e}; "
+          f"oracle unrefined {eta_o:.2e}), |X - X_true|/|X_true| {err:.2e} (oracle {err_o:.2e}), kappa {kappa:.1e}")
+    assert info.eta <= 1e-14
+    assert eta <= 2e-14
+    assert err <= max(4 * err_o, 16 * n * EPS * kappa)
+
+
+def test_solve_refinement_steps_and_best_iterate(tq, tl):
+    # An unreachable tolerance: the refinement runs (at most max_iter
+    # corrections, or stops when two fail to halve the error), reports
+    # TILEQR_ENOCONV and returns its best iterate, still at FP64 accuracy.
+    n, nrhs = 512, 4
+    A = synth.normal(77, n, n)
+    Xtrue = np.random.default_rng(3).standard_normal((n, nrhs))
+    B = A @ Xtrue
+    rc, X, info, _, _ = lu_solve_gpu(tq, tl, A, B, 16, tol=1e-30, max_iter=3)
+    assert rc == tq.ENOCONV and info.converged == 0
+    assert 1 <= info.iterations <= 3
+    eta = max(eta_inf(A, X[:, c], B[:, c]) for c in range(nrhs))
+    print(f"{info.iterations} corrections, best eta {info.eta:.2e} (numpy residual {eta:.2e})")
+    assert info.eta <= 1e-14 and eta <= 2e-14
+
+
+def test_solve_singular_and_arguments(tq, tl):
+    n = 256
+    A = synth.normal(78, n, n)
+    A[:, 70] = 0.0
+    rc, _, info, _, _ = lu_solve_gpu(tq, tl, A, np.ones((n, 2)))
+    assert rc == tq.ESINGULAR and info.minor == 71
+    A = synth.normal(79, n, n)
+    At = tq.to_device(A)
+    Bt = tq.to_device(np.ones((n, 2)))
+    Xt = torch.full((2, n), 7.0, dtype=torch.float64, device="cuda")
+    a, b, x = At.data_ptr(), Bt.data_ptr(), Xt.data_ptr()
+    assert tl.solve(-1, 2, a, n, b, n, x, n) == -1
+    assert tl.solve(n, 65, a, n, b, n, x, n) == -2
+    assert tl.solve(n, 2, 0, n, b, n, x, n) == -3
+    assert tl.solve(n, 2, a, n - 1, b, n, x, n) == -4
+    assert tl.solve(n, 2, a, n, 0, n, x, n) == -5
+    assert tl.solve(n, 2, a, n, b, n - 1, x, n) == -6
+    assert tl.solve(n, 2, a, n, b, n, 0, n) == -7
+    assert tl.solve(n, 2, a, n, b, n, x, n - 1) == -8
+    assert tl.solve(n, 2, a, n, b, n, x, n, 8) == -9
+    assert tl.solve(n, 2, a, n, b, n, x, n, 16, tq.opts(max_iter=65)) == -10
+    assert tl.solve(n, 2, a, n, b, n, x, n, 16, tq.opts(precision=tq.BF16X3)) == tq.EUNSUPPORTED
+    assert tl.solve(n, 2, a, n, b, n, x, n, 16, tq.opts(flags=tq.FLAG_ASYNC)) == tq.EUNSUPPORTED
+    assert tl.solve(0, 2, 0, 1, 0, 1, 0, 1) == tq.OK
+    assert tl.solve(n, 0, a, n, 0, n, 0, n) == tq.OK
+    torch.cuda.synchronize()
+    assert np.array_equal(tq.to_host(Xt), np.full((n, 2), 7.0))    # nothing written
+
+
+def test_solve_full_size(tq, tl):
+    # 4096^2 with 16 right-hand sides: the backward error of every column.
+    n, nrhs = 4096, 16
+    A = synth.normal(80, n, n)
+    Xtrue = np.random.default_rng(4).standard_normal((n, nrhs))
+    B = A @ Xtrue
+    At = tq.to_device(A)
+    Bt = tq.to_device(B)
+    Xt = torch.zeros_like(Bt)
+    info = tl.LUSolveInfo()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    rc = tl.solve(n, nrhs, At.data_ptr(), n, Bt.data_ptr(), n, Xt.data_ptr(), n, 16, tq.opts(), info)
+    e1.record()
+    torch.cuda.synchronize()
+    assert rc == tq.OK, (rc, info.iterations, info.eta)
+    X = tq.to_host(Xt, n)
+    eta = max(eta_inf(A, X[:, c], B[:, c]) for c in range(nrhs))
+    err = np.linalg.norm(X - Xtrue) / np.linalg.norm(Xtrue)
+    print(f"n={n} nrhs={nrhs}: {e0.elapsed_time(e1):.1f} ms, {info.iterations} corrections, eta {eta:.2e} "
+          f"(library {info.eta:.2e}), |X - X_true|/|X_true| {err:.2e}")
+    assert eta <= 2e-14 and info.eta <= 1e-14
