@@ -1123,10 +1123,69 @@ __global__ __launch_bounds__(NT, 1) void k_lu_forward(Sched S, int j)
     }
 }
 
-hipError_t launch_forward(const Sched &S, int j, hipStream_t st)
+// The same tasks as a (step, row) wavefront: workgroup k runs step k --
+// GESSM(k, j), then SSSSM(k, i, j) for i = k+1 .. p-1 -- and publishes in
+// prog[k] the last row it has finished (after its stores have completed).
+// Before touching row i (row k for GESSM) it waits for step k-1 to have
+// finished that row, the last writer of that tile before it.  A workgroup
+// waits only for lower-numbered ones, which are dispatched first, and every
+// wait is bounded (ST_TIMEOUT).  Each tile sees the same operations in the
+// same order as under k_lu_forward, so the result is bitwise the same.
+constexpr int PSTRIDE = 64;   // ints between progress words
+
+template <int IB>
+__global__ __launch_bounds__(NT, IB == 16 ? 2 : 1) void k_lu_forward_wave(Sched S, int j, int *prog)
 {
-    if (S.ib == 16) hipLaunchKernelGGL((k_lu_forward<16>), dim3(1), dim3(NT), 0, st, S, j);
-    else hipLaunchKernelGGL((k_lu_forward<32>), dim3(1), dim3(NT), 0, st, S, j);
+    __shared__ Smem<IB> sm;
+    __shared__ int s_abort;
+    const int k = (int)blockIdx.x;
+    auto wait_row = [&](int i) -> bool {
+        if (k == 0) return true;
+        if (threadIdx.x == 0) {
+            int abort = 0;
+            int64_t spins = 0;
+            while (__hip_atomic_load(&prog[(k - 1) * PSTRIDE], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < i) {
+                if ((__hip_atomic_load(S.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & ST_TIMEOUT) ||
+                    ++spins > S.spin_limit) {
+                    __hip_atomic_fetch_or(S.status, ST_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    abort = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            s_abort = abort;
+        }
+        __syncthreads();
+        return s_abort == 0;
+    };
+    auto publish = [&](int i) {
+        stores_done();
+        __syncthreads();
+        if (threadIdx.x == 0) __hip_atomic_store(&prog[k * PSTRIDE], i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    if (!wait_row(k)) return;
+    task_gessm<IB>(sm, S, k, j);
+    publish(k);
+    for (int i = k + 1; i < S.p; ++i) {
+        if (!wait_row(i)) return;
+        task_ssssm<IB>(sm, S, k, i, j, false, false);
+        publish(i);
+    }
+}
+
+// The factor's transformations on tile column j: the wavefront (prog holds
+// p * PSTRIDE ints), or with `serial` the one-workgroup order.
+hipError_t launch_forward(const Sched &S, int j, int *prog, bool serial, hipStream_t st)
+{
+    if (serial) {
+        if (S.ib == 16) hipLaunchKernelGGL((k_lu_forward<16>), dim3(1), dim3(NT), 0, st, S, j);
+        else hipLaunchKernelGGL((k_lu_forward<32>), dim3(1), dim3(NT), 0, st, S, j);
+        return hipGetLastError();
+    }
+    hipError_t e = hipMemsetAsync(prog, 0xff, (size_t)S.p * PSTRIDE * sizeof(int), st);   // every word -1
+    if (e != hipSuccess) return e;
+    if (S.ib == 16) hipLaunchKernelGGL((k_lu_forward_wave<16>), dim3(S.p), dim3(NT), 0, st, S, j, prog);
+    else hipLaunchKernelGGL((k_lu_forward_wave<32>), dim3(S.p), dim3(NT), 0, st, S, j, prog);
     return hipGetLastError();
 }
 
@@ -1524,6 +1583,8 @@ extern "C" int tilelu_solve(int64_t n, int64_t nrhs, const double *A, int64_t ld
     if ((rc = W->part.ensure((size_t)part_cap * sizeof(double)))) return rc;
     if ((rc = W->misc.ensure((size_t)(SMALL + SMALL_CAP) * sizeof(double)))) return rc;
     if ((rc = W->tflags.ensure((size_t)flags_cap * sizeof(int32_t)))) return rc;
+    if ((rc = W->prog.ensure((size_t)p * tl::PSTRIDE * sizeof(int32_t)))) return rc;
+    const bool serial = (o.flags & TILEQR_FLAG_SERIAL) != 0;
 
     tl::Sched S;
     if ((rc = lu_run(W, A, lda, n, nb, ib, 1, (double *)W->lulup.ptr, (int32_t *)W->lupiv.ptr, o, false, st, S)))
@@ -1546,7 +1607,7 @@ extern "C" int tilelu_solve(int64_t n, int64_t nrhs, const double *A, int64_t ld
     double *small = (double *)W->misc.ptr, *part = (double *)W->part.ptr;
     // Bc <- A^{-1} Bc: the factor's transformations, then U.
     auto solve_bc = [&]() -> hipError_t {
-        hipError_t e = tl::launch_forward(S, p, st);
+        hipError_t e = tl::launch_forward(S, p, (int *)W->prog.ptr, serial, st);
         if (e != hipSuccess) return e;
         return launch_trsm((int)nb, S.tiles, p, n, Bc, ldt, true, (int *)W->tflags.ptr, flags_cap, tst, S.spin_limit,
                            st);
@@ -1570,9 +1631,10 @@ extern "C" int tilelu_solve(int64_t n, int64_t nrhs, const double *A, int64_t ld
         TQ_HIP(launch_colmax(Xr, ldt, n, (int)nrhs, small + SMALL, SMALL_CAP, small + 320, st));
         TQ_HIP(hipMemcpyAsync(W->host_small, small, 384 * sizeof(double), hipMemcpyDeviceToHost, st));
         TQ_HIP(hipMemcpyAsync(W->host_status, tst, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        TQ_HIP(hipMemcpyAsync(W->host_status + 1, S.status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
         TQ_HIP(hipStreamSynchronize(st));
         if (*W->host_status & STATUS_SINGULAR) return TILEQR_ESINGULAR;
-        if (*W->host_status & STATUS_TIMEOUT) return TILEQR_ETIMEOUT;
+        if ((*W->host_status & STATUS_TIMEOUT) || (W->host_status[1] & tl::ST_TIMEOUT)) return TILEQR_ETIMEOUT;
         const double *hs = W->host_small, normA = hs[0];
         double eta = 0.0;
         for (int c = 0; c < nrhs; ++c) {

@@ -266,3 +266,17 @@ def test_solve_full_size(tq, tl):
     print(f"n={n} nrhs={nrhs}: {e0.elapsed_time(e1):.1f} ms, {info.iterations} corrections, eta {eta:.2e} "
           f"(library {info.eta:.2e}), |X - X_true|/|X_true| {err:.2e}")
     assert eta <= 2e-14 and info.eta <= 1e-14
+
+
+@pytest.mark.parametrize("n,nrhs,ib", [(700, 6, 16), (448, 64, 32)])
+def test_solve_wavefront_bitwise_equals_serial_order(tq, tl, n, nrhs, ib):
+    # The forward pass as a (step, row) wavefront of workgroups gives the
+    # bits of the one-workgroup pass in Algorithm 3's order (TILEQR_FLAG_SERIAL,
+    # which also factors in that order: the factor is bitwise the same).
+    A = synth.normal(81 + n, n, n)
+    B = np.random.default_rng(n).standard_normal((n, nrhs))
+    rc1, X1, info1, _, _ = lu_solve_gpu(tq, tl, A, B, ib)
+    rc2, X2, info2, _, _ = lu_solve_gpu(tq, tl, A, B, ib, flags=tq.FLAG_SERIAL)
+    assert rc1 == rc2 == tq.OK
+    assert info1.iterations == info2.iterations
+    assert np.array_equal(X1, X2)
