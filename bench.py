@@ -211,7 +211,24 @@ def cholesky(tq, torch, dev, st):
                  "tilechol_factor")
         if r:
             res.append((info.ms_factor, info.ms_worker))
-    del A, A0
+    # The solve with that factor: 16 right-hand sides, HIP events on the stream.
+    nrhs = 16
+    g = torch.Generator(device=dev)
+    g.manual_seed(1)
+    B = torch.randn((nrhs, n), generator=g, device=dev, dtype=torch.float64)   # column-major n x 16
+    X = torch.empty_like(B)
+    solve_ms = []
+    for r in range(3):
+        X.copy_(B)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        rc = tc.solve(n, nrhs, A.data_ptr(), n, X.data_ptr(), n, nb, tq.opts(stream=st.cuda_stream))
+        e1.record(st)
+        torch.cuda.synchronize()
+        tq.check(rc, "tilechol_solve")
+        if r:
+            solve_ms.append(e0.elapsed_time(e1))
+    del A, A0, B, X
     torch.cuda.empty_cache()
     ms = sum(r[0] for r in res) / len(res)
     wk = sum(r[1] for r in res) / len(res)
@@ -222,7 +239,9 @@ def cholesky(tq, torch, dev, st):
             "worker_ms": round(wk, 3),
             "worker_frac_fp64_peak": round(tc.flops(n) / (wk * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
             "traffic_bytes_per_launch": measured_traffic("k_chol_worker_chol32768_fp64.md", CHOL_SRCS),
-            "algorithmic_bytes": 16.0 * nb * nb * sum(m * (m + 1) // 2 for m in range(1, p))}
+            "algorithmic_bytes": 16.0 * nb * nb * sum(m * (m + 1) // 2 for m in range(1, p)),
+            "solve": {"workload": f"tilechol_solve with that factor, {nrhs} right-hand sides N(0,1), seed 1",
+                      "ms": round(min(solve_ms), 3)}}
 
 
 def lu(tq, torch, dev, st):
@@ -244,7 +263,28 @@ def lu(tq, torch, dev, st):
                            tq.opts(stream=st.cuda_stream, flags=tq.FLAG_TIMING), info), "tilelu_factor")
         if r:
             res.append((info.ms_factor, info.ms_worker))
-    del A, A0, Lup, piv
+    del A, Lup, piv
+    # A X = B with refinement (factorisation, the factor's transformations on
+    # B, U, FP64 residuals): 16 right-hand sides, B = A X_true.
+    nrhs = 16
+    Xtrue = torch.randn((nrhs, n), generator=g, device=dev, dtype=torch.float64)
+    B = (Xtrue @ A0).contiguous()          # (A X_true)^T: A0 holds A column-major, i.e. the tensor A0 is A^T
+    X = torch.empty_like(B)
+    sol = None
+    for r in range(2):
+        sinfo = tl.LUSolveInfo()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        rc = tl.solve(n, nrhs, A0.data_ptr(), n, B.data_ptr(), n, X.data_ptr(), n, ib, tq.opts(stream=st.cuda_stream),
+                      sinfo)
+        e1.record(st)
+        torch.cuda.synchronize()
+        tq.check(rc, "tilelu_solve")
+        if r:
+            sol = {"workload": f"tilelu_solve of that matrix, {nrhs} right-hand sides B = A X_true with X_true N(0,1)",
+                   "ms": round(e0.elapsed_time(e1), 3), "iterations": sinfo.iterations, "eta_inf": sinfo.eta,
+                   "rel_err_x": float(torch.linalg.norm(X - Xtrue) / torch.linalg.norm(Xtrue))}
+    del A0, B, X, Xtrue
     torch.cuda.empty_cache()
     ms = sum(r[0] for r in res) / len(res)
     wk = sum(r[1] for r in res) / len(res)
@@ -255,7 +295,8 @@ def lu(tq, torch, dev, st):
             "worker_ms": round(wk, 3),
             "worker_frac_fp64_peak": round(tl.flops(n) / (wk * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
             "traffic_bytes_per_launch": measured_traffic("k_lu_worker_lu16384_fp64.md", LU_SRCS),
-            "algorithmic_bytes": 16.0 * nb * nb * sum(m * m for m in range(1, p))}
+            "algorithmic_bytes": 16.0 * nb * nb * sum(m * m for m in range(1, p)),
+            "solve": sol}
 
 
 def tall_ls(tq, torch, dev, st):
