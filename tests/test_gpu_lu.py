@@ -7,7 +7,10 @@ factor (U, L_kk, the TSTRF multipliers) and L_up normwise within a bound from
 the arithmetic (n^2 u), and the GPU factor is used by the oracle's solve,
 whose backward error is held to the order of the oracle's own factor's.  Every order of the DAG gives the same bits
 as Algorithm 3's loop order; a column with no pivot is reported with its
-index.
+index.  tilelu_solve (the factor's transformations on B, U, FP64
+refinement) is checked against the oracle's Algorithm 3 and solve and
+against the exact solution, by its backward error in every column, its
+refinement path, and the bits of its wavefront against the serial order.
 """
 import numpy as np
 import pytest
