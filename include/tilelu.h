@@ -82,7 +82,7 @@ typedef struct {
 
 /*
  * X with A X = B for the n x n column-major A (lda >= max(1, n), not
- * modified) and 1 <= nrhs <= 64 right-hand sides B (ldb >= max(1, n)): the
+ * modified) and nrhs >= 0 right-hand sides B (ldb >= max(1, n)): the
  * tiled LU of Algorithm 3 with tiled pairwise pivoting (nb 64, inner panels
  * ib 16 or 32, 0 choosing 16) computed into the library's workspace, the
  * factor's transformations applied to B in the factorisation's order
@@ -90,9 +90,11 @@ typedef struct {
  * solve with U, then classical refinement with FP64 residuals: Section 3.2.4
  * notes that tiled pairwise pivoting is not guaranteed stable and advises
  * checking the backward error ||b - A x||_inf / (||A||_inf ||x||_inf) and
- * refining.  Refinement stops at opts->tol (default 1e-14) for every column,
- * after opts->max_iter corrections (<= 64), or after two corrections that
- * fail to halve the error; the best iterate goes to X (ldx >= max(1, n)).
+ * refining.  The right-hand sides are taken 64 columns at a time, each
+ * block with its own refinement, which stops at opts->tol (default 1e-14)
+ * for every column, after opts->max_iter corrections (<= 64), or after two
+ * corrections that fail to halve the error; the best iterate goes to X
+ * (ldx >= max(1, n)).
  * opts (may be NULL): precision must be TILEQR_FP64 and TILEQR_FLAG_ASYNC is
  * not accepted (TILEQR_EUNSUPPORTED: the refinement decides on the host);
  * stream, workers, spin_limit, TILEQR_FLAG_SERIAL / _SHUFFLE as for

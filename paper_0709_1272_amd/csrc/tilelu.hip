@@ -1539,7 +1539,7 @@ extern "C" int tilelu_solve(int64_t n, int64_t nrhs, const double *A, int64_t ld
                             double *X, int64_t ldx, int64_t ib, const tileqr_opts *opts, tilelu_solve_info *info)
 {
     if (n < 0 || n > (int64_t)INT_MAX / 2) return -1;
-    if (nrhs < 0 || nrhs > tl::NB) return -2;
+    if (nrhs < 0 || nrhs > (int64_t)INT_MAX / 2) return -2;
     if (n > 0 && !A) return -3;
     if (lda < std::max<int64_t>(1, n)) return -4;
     if (n > 0 && nrhs > 0 && !B) return -5;
@@ -1613,56 +1613,70 @@ extern "C" int tilelu_solve(int64_t n, int64_t nrhs, const double *A, int64_t ld
                            st);
     };
     TQ_HIP(launch_norm_inf(A, lda, n, n, part, part_cap, small, st));
-    TQ_HIP(launch_cm2rows(B, ldb, n, nrhs, Bc, (int64_t)p * nb, ldt, st));
-    TQ_HIP(solve_bc());
-    TQ_HIP(hipMemcpyAsync(Xr, Bc, slot * sizeof(double), hipMemcpyDeviceToDevice, st));
-    // Classical refinement in FP64 (Section 3.2.4's check of the backward
-    // error, then corrections through the factor) until the largest
-    // ||b - A x||_inf / (||A||_inf ||x||_inf) over the columns is <= tol,
-    // max_iter corrections, or two corrections that fail to halve it; the
-    // best iterate is returned.
-    double best = INFINITY, prev = INFINITY;
-    int it = 0, stall = 0;
-    bool conv = false;
-    for (;;) {
-        TQ_HIP(launch_cm2rows(B, ldb, n, nrhs, Rr, (int64_t)p * nb, ldt, st));
-        TQ_HIP(launch_gemv_n(A, lda, n, n, Xr, ldt, (int)nrhs, -1.0, 1.0, Rr, part, part_cap, st));
-        TQ_HIP(launch_colmax(Rr, ldt, n, (int)nrhs, small + SMALL, SMALL_CAP, small + 256, st));
-        TQ_HIP(launch_colmax(Xr, ldt, n, (int)nrhs, small + SMALL, SMALL_CAP, small + 320, st));
-        TQ_HIP(hipMemcpyAsync(W->host_small, small, 384 * sizeof(double), hipMemcpyDeviceToHost, st));
-        TQ_HIP(hipMemcpyAsync(W->host_status, tst, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        TQ_HIP(hipMemcpyAsync(W->host_status + 1, S.status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        TQ_HIP(hipStreamSynchronize(st));
-        if (*W->host_status & STATUS_SINGULAR) return TILEQR_ESINGULAR;
-        if ((*W->host_status & STATUS_TIMEOUT) || (W->host_status[1] & tl::ST_TIMEOUT)) return TILEQR_ETIMEOUT;
-        const double *hs = W->host_small, normA = hs[0];
-        double eta = 0.0;
-        for (int c = 0; c < nrhs; ++c) {
-            const double r = hs[256 + c], d = normA * hs[320 + c];
-            eta = std::max(eta, d > 0.0 ? r / d : (r > 0.0 ? INFINITY : 0.0));
-        }
-        if (eta < best) {
-            best = eta;
-            TQ_HIP(hipMemcpyAsync(Xb, Xr, slot * sizeof(double), hipMemcpyDeviceToDevice, st));
-        }
-        if (eta <= tol) {
-            conv = true;
-            break;
-        }
-        stall = eta > 0.5 * prev ? stall + 1 : 0;
-        prev = eta;
-        if (it >= o.max_iter || stall >= 2) break;
-        ++it;
-        TQ_HIP(hipMemcpyAsync(Bc, Rr, slot * sizeof(double), hipMemcpyDeviceToDevice, st));
+    int max_it = 0;
+    double max_eta = 0.0;
+    bool all_conv = true;
+    // One block of at most 64 right-hand sides (columns Bb of B, Xo of X).
+    auto solve_block = [&](const double *Bb, double *Xo, int nr) -> int {
+        TQ_HIP(launch_cm2rows(Bb, ldb, n, nr, Bc, (int64_t)p * nb, ldt, st));
         TQ_HIP(solve_bc());
-        TQ_HIP(launch_axpy_rows(Bc, Xr, ldt, n, (int)nrhs, 1, st));
+        TQ_HIP(hipMemcpyAsync(Xr, Bc, slot * sizeof(double), hipMemcpyDeviceToDevice, st));
+        // Classical refinement in FP64 (Section 3.2.4's check of the backward
+        // error, then corrections through the factor) until the largest
+        // ||b - A x||_inf / (||A||_inf ||x||_inf) over the columns is <= tol,
+        // max_iter corrections, or two corrections that fail to halve it; the
+        // best iterate is returned.
+        double best = INFINITY, prev = INFINITY;
+        int it = 0, stall = 0;
+        bool conv = false;
+        for (;;) {
+            TQ_HIP(launch_cm2rows(Bb, ldb, n, nr, Rr, (int64_t)p * nb, ldt, st));
+            TQ_HIP(launch_gemv_n(A, lda, n, n, Xr, ldt, nr, -1.0, 1.0, Rr, part, part_cap, st));
+            TQ_HIP(launch_colmax(Rr, ldt, n, nr, small + SMALL, SMALL_CAP, small + 256, st));
+            TQ_HIP(launch_colmax(Xr, ldt, n, nr, small + SMALL, SMALL_CAP, small + 320, st));
+            TQ_HIP(hipMemcpyAsync(W->host_small, small, 384 * sizeof(double), hipMemcpyDeviceToHost, st));
+            TQ_HIP(hipMemcpyAsync(W->host_status, tst, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            TQ_HIP(hipMemcpyAsync(W->host_status + 1, S.status, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            TQ_HIP(hipStreamSynchronize(st));
+            if (*W->host_status & STATUS_SINGULAR) return TILEQR_ESINGULAR;
+            if ((*W->host_status & STATUS_TIMEOUT) || (W->host_status[1] & tl::ST_TIMEOUT)) return TILEQR_ETIMEOUT;
+            const double *hs = W->host_small, normA = hs[0];
+            double eta = 0.0;
+            for (int c = 0; c < nr; ++c) {
+                const double r = hs[256 + c], d = normA * hs[320 + c];
+                eta = std::max(eta, d > 0.0 ? r / d : (r > 0.0 ? INFINITY : 0.0));
+            }
+            if (eta < best) {
+                best = eta;
+                TQ_HIP(hipMemcpyAsync(Xb, Xr, slot * sizeof(double), hipMemcpyDeviceToDevice, st));
+            }
+            if (eta <= tol) {
+                conv = true;
+                break;
+            }
+            stall = eta > 0.5 * prev ? stall + 1 : 0;
+            prev = eta;
+            if (it >= o.max_iter || stall >= 2) break;
+            ++it;
+            TQ_HIP(hipMemcpyAsync(Bc, Rr, slot * sizeof(double), hipMemcpyDeviceToDevice, st));
+            TQ_HIP(solve_bc());
+            TQ_HIP(launch_axpy_rows(Bc, Xr, ldt, n, nr, 1, st));
+        }
+        TQ_HIP(launch_rows2cm(Xo, ldx, n, nr, Xb, ldt, st));
+        max_it = std::max(max_it, it);
+        max_eta = std::max(max_eta, best);
+        all_conv = all_conv && conv;
+        return TILEQR_OK;
+    };
+    for (int64_t c0 = 0; c0 < nrhs; c0 += nb) {
+        const int nr = (int)std::min<int64_t>(nb, nrhs - c0);
+        if ((rc = solve_block(B + (size_t)c0 * ldb, X + (size_t)c0 * ldx, nr)) != TILEQR_OK) return rc;
     }
-    TQ_HIP(launch_rows2cm(X, ldx, n, nrhs, Xb, ldt, st));
     TQ_HIP(hipStreamSynchronize(st));
     if (info) {
-        info->iterations = it;
-        info->converged = conv ? 1 : 0;
-        info->eta = best;
+        info->iterations = max_it;
+        info->converged = all_conv ? 1 : 0;
+        info->eta = max_eta;
     }
-    return conv ? TILEQR_OK : TILEQR_ENOCONV;
+    return all_conv ? TILEQR_OK : TILEQR_ENOCONV;
 }

@@ -170,7 +170,7 @@ def lu_solve_gpu(tq, tl, A, B, ib=16, **opt):
 
 
 @pytest.mark.parametrize("n,nrhs,ib", [(64, 1, 16), (100, 3, 16), (256, 5, 32), (333, 33, 16), (640, 64, 32),
-                                       (1024, 8, 16)])
+                                       (1024, 8, 16), (300, 100, 16)])
 def test_solve_vs_oracle(tq, tl, n, nrhs, ib):
     # tilelu_solve (factor, the factor's transformations on B, U, FP64
     # refinement) against the oracle's Algorithm 3 and its unrefined solve,
@@ -230,7 +230,7 @@ def test_solve_singular_and_arguments(tq, tl):
     Xt = torch.full((2, n), 7.0, dtype=torch.float64, device="cuda")
     a, b, x = At.data_ptr(), Bt.data_ptr(), Xt.data_ptr()
     assert tl.solve(-1, 2, a, n, b, n, x, n) == -1
-    assert tl.solve(n, 65, a, n, b, n, x, n) == -2
+    assert tl.solve(n, -1, a, n, b, n, x, n) == -2
     assert tl.solve(n, 2, 0, n, b, n, x, n) == -3
     assert tl.solve(n, 2, a, n - 1, b, n, x, n) == -4
     assert tl.solve(n, 2, a, n, 0, n, x, n) == -5
